@@ -1,0 +1,234 @@
+/*
+ * sg.h -- C-ABI of the MI355X (gfx950) spin-glass local-search library.
+ *
+ * The library minimises the hyper-Ising energy of García & Markov
+ * ("High-performance Energy Minimization in Spin-glasses with Applications
+ * to Adiabatic Quantum Computing"), Sec. II eq. (1) extended by Sec. VI
+ * eq. (5) to couplings over three spins:
+ *
+ *   E(s) = - sum_{edges (i,j)} J_ij s_i s_j - sum_i h_i s_i
+ *          - sum_{triples (i,j,k)} K_ijk s_i s_j s_k ,     s_i in {-1,+1}
+ *
+ * with every undirected edge and every triple counted once, by single-spin
+ * moves (Sec. IV): the move of spin i changes the energy by
+ * dE_i = 2 s_i f_i, f_i = h_i + sum_j J_ij s_j + sum_(j,k) K_ijk s_j s_k
+ * (its gain, in the paper's words, is -dE_i).  Moves are applied in
+ * colour-ordered parallel sweeps: the spins are split into colour classes of
+ * a proper colouring of the primal graph (edges plus the three pairs of each
+ * triple), colours are visited in ascending order and all spins of one
+ * colour are decided and flipped at once.  Because no energy term holds two
+ * spins of one colour, this equals visiting the spins of the colour one at a
+ * time, so every result is that of a sequential descent.  Random starts are
+ * uniform (Sec. IV); a run stops when a sweep flips nothing (the stopping
+ * rule of Sec. IV, Fig. 3) or after a fixed number of sweeps; independent
+ * restarts keep the best (Sec. IV, Sec. V).
+ *
+ * Randomness: Philox4x32-10 (Salmon et al., SC'11), key = seed (low word,
+ * high word), counter = (external spin index, sweep index or 0xFFFFFFFF for
+ * the start, instance_id, restart); bit 0 of output word 0 is used.  The
+ * sweep index is the replica's absolute sweep count, so splitting a run over
+ * several sg_run_sweeps calls gives the same result as one call.
+ *
+ * All arithmetic is integer: couplings, fields and hyper-couplings are
+ * int32 at this boundary, energies and counters int64; every result is
+ * exact and reproducible bit for bit.
+ *
+ * Memory: the library allocates no device memory.  The caller provides one
+ * device buffer of sg_workspace_bytes() bytes (for example a torch uint8
+ * tensor) and a HIP stream; every kernel runs on that stream.  Host arrays
+ * passed in are copied; host output buffers are written before return.
+ * A handle is not thread-safe.  All functions return an sg_status; on error
+ * sg_last_error() holds a message (thread-local).
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sg_status;
+enum {
+    SG_OK = 0,
+    SG_ENOTCONV = 1,   /* warning: until_converged and some replica hit the sweep cap */
+    SG_EINVAL = -1,    /* invalid argument or instance (message says which) */
+    SG_ERANGE = -2,    /* a value or size outside what the kernels represent */
+    SG_ENOMEM = -3,    /* workspace smaller than sg_workspace_bytes(), or host allocation failed */
+    SG_EDEVICE = -4,   /* a HIP call failed (message holds the HIP error string) */
+    SG_ESTATE = -5     /* call out of order (run or read before bind / init) */
+};
+
+/* Acceptance rule of a move with energy change dE. */
+enum {
+    SG_RULE_GREEDY = 0,      /* flip iff dE < 0 */
+    SG_RULE_GREEDY_TIE = 1   /* also flip when dE == 0 and the sweep's RNG bit is 1 */
+};
+
+/* Execution schedules.  Every schedule computes the same result bit for bit;
+ * they differ only in how the sweeps are mapped onto the GPU. */
+enum {
+    SG_SCHED_AUTO = -1,        /* pick per instance from the tuned table */
+    SG_SCHED_PHASE = 0,        /* one kernel launch per colour phase per instance */
+    SG_SCHED_GRAPH = 1,        /* SG_SCHED_PHASE captured in HIP graphs of several sweeps */
+    SG_SCHED_PERSISTENT = 2,   /* one cooperative launch; grid barrier between phases */
+    SG_SCHED_LATTICE = 3,      /* lattice instances: LDS-resident tiles, neighbour flags */
+    SG_SCHED_BLOCK = 4,        /* one workgroup per instance, structure and replicas in LDS */
+    SG_SCHED_QUEUE = 5         /* persistent batched: work queue of uneven instances */
+};
+
+typedef struct sg_ctx* sg_handle;
+
+/* One instance.  Arrays are host memory owned by the caller and copied by
+ * sg_load_instance.
+ *   n            number of spins, >= 1
+ *   m, ei, ej, J undirected couplings (ei[k], ej[k], J[k]); ei != ej, no pair
+ *                twice (in either orientation), indices in [0, n)
+ *   h            n fields, or NULL for all zero
+ *   t, tri, K    3-spin hyper-couplings: tri[3k..3k+2] three distinct spins,
+ *                no set of three twice, coefficient K[k]
+ *   colour       n colours forming a proper colouring of the primal graph,
+ *                or NULL: first-fit colouring over increasing spin index
+ *                (spin i takes the smallest colour not used by a primal
+ *                neighbour j < i)
+ *   dims         lattice hint: {Lx, Ly, Lz} of a periodic hypercubic lattice
+ *                with row-major site index (x slowest) and the +axis bond of
+ *                every site, or {Lx, Ly, 0} in 2-D; all zero = general
+ *                graph.  When given, the edge list must be exactly that
+ *                lattice (checked) and SG_SCHED_LATTICE becomes available.
+ *   instance_id  RNG key word of the instance; keep it stable across
+ *                batching and serving to reproduce results
+ *   restarts     independent replicas of this instance, >= 1
+ * Limits (SG_ERANGE beyond): n < 2^24; |J|, |h|, |K| <= 127; for every
+ * spin |h_i| + sum|J_ij| + sum|K| < 2^23. */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int32_t* ei;
+    const int32_t* ej;
+    const int32_t* J;
+    const int32_t* h;
+    int64_t t;
+    const int32_t* tri;
+    const int32_t* K;
+    const int32_t* colour;
+    int32_t dims[3];
+    uint32_t instance_id;
+    int32_t restarts;
+} sg_instance_desc;
+
+/* Parameters of one sg_run_sweeps call.
+ *   seed             Philox key
+ *   rule             SG_RULE_*
+ *   max_sweeps       sweeps this call may perform per replica (>= 0)
+ *   until_converged  1: a replica stops after its first sweep with no flip
+ *                    (that sweep counts) and stays frozen until it is
+ *                    restarted; 0: exactly max_sweeps sweeps per replica
+ *   schedule         SG_SCHED_*; a schedule the instance cannot use gives
+ *                    SG_EINVAL */
+typedef struct {
+    uint64_t seed;
+    int32_t rule;
+    int32_t max_sweeps;
+    int32_t until_converged;
+    int32_t schedule;
+} sg_run_params;
+
+/* Totals of one sg_run_sweeps call over all replicas of the handle.
+ *   attempts       sum over replicas of (sweeps performed) x n
+ *   flips          moves applied
+ *   sweeps_max     most sweeps performed by one replica
+ *   n_unconverged  replicas not converged at return (until_converged only)
+ *   kernel_ms      device time of the call's sweep kernels (HIP events) */
+typedef struct {
+    int64_t attempts;
+    int64_t flips;
+    int64_t sweeps_max;
+    int32_t n_unconverged;
+    int32_t schedule_used;
+    double kernel_ms;
+} sg_run_stats;
+
+/* Per-instance facts after loading. */
+typedef struct {
+    int32_t n;
+    int32_t colours;       /* number of colour classes */
+    int64_t m;
+    int64_t t;
+    int32_t restarts;
+    int32_t lattice;       /* 1 if the lattice hint was accepted */
+    int64_t replica_base;  /* index of replica 0 of this instance in handle order */
+} sg_instance_info;
+
+/* Validate and pack `count` instances into one handle (a batch when
+ * count > 1).  Host-only: needs no GPU.  Errors: SG_EINVAL (message names the
+ * instance and the problem), SG_ERANGE, SG_ENOMEM. */
+sg_status sg_load_instance(const sg_instance_desc* descs, int32_t count, sg_handle* out);
+
+/* Device bytes the handle needs: packed coupling structure, spins of every
+ * replica, per-replica counters and scratch.  Host-only. */
+sg_status sg_workspace_bytes(sg_handle h, uint64_t* bytes);
+
+/* Facts about instance `inst` (colour count, replica offset, ...); the
+ * colouring actually used is written to colour_out (n entries, external
+ * order) when not NULL.  Host-only. */
+sg_status sg_instance_info_get(sg_handle h, int32_t inst, sg_instance_info* info,
+                               int32_t* colour_out);
+
+/* Bind caller-owned device memory (>= sg_workspace_bytes, 256-byte aligned)
+ * and a HIP stream (hipStream_t, NULL = default stream) to the handle, and
+ * upload the coupling structure.  The memory must stay allocated while the
+ * handle uses it; binding again moves the handle (state is not kept).
+ * Errors: SG_ENOMEM if too small, SG_EINVAL if misaligned, SG_EDEVICE. */
+sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
+
+/* Draw the random start of every replica (Sec. IV: uniform), compute its
+ * energy, reset sweeps, flips and converged.  Errors: SG_ESTATE before bind. */
+sg_status sg_init_spins(sg_handle h, uint64_t seed);
+
+/* Set replica r of instance inst to host spins s (n int8 values, each +1 or
+ * -1, external order) and reset its counters.  Errors: SG_EINVAL for a value
+ * other than +-1 or an index out of range; SG_ESTATE before bind. */
+sg_status sg_set_spins(sg_handle h, int32_t inst, int32_t r, const int8_t* s);
+
+/* Run colour-ordered sweeps on every replica that is not frozen (enqueued
+ * on the bound stream; returns after the stream has finished them).
+ * stats may be NULL.  Returns SG_ENOTCONV when until_converged and a
+ * replica hit max_sweeps.  Errors: SG_ESTATE before sg_init_spins or
+ * sg_set_spins of every replica, SG_EINVAL for bad parameters or a schedule
+ * the handle cannot use. */
+sg_status sg_run_sweeps(sg_handle h, const sg_run_params* p, sg_run_stats* stats);
+
+/* Energies of all replicas in handle order (sum over instances of
+ * restarts entries).  recompute = 0: the tracked energy (start energy plus
+ * the dE of every applied move); recompute = 1: a fresh evaluation of the
+ * energy from the current spins. */
+sg_status sg_energy(sg_handle h, int64_t* E, int32_t recompute);
+
+/* Per-replica counters in handle order (any pointer may be NULL): sweeps
+ * performed since the last start, moves applied, converged flag. */
+sg_status sg_replica_counters(sg_handle h, int64_t* sweeps, int64_t* flips, int8_t* converged);
+
+/* Spins of replica r of instance inst, n int8 values in external order. */
+sg_status sg_spins_out(sg_handle h, int32_t inst, int32_t r, int8_t* s);
+
+/* Multi-start result per instance (Sec. IV: keep the best start): lowest
+ * tracked energy over its restarts, lowest restart index on ties.  E_best and
+ * r_best have one entry per instance; either may be NULL. */
+sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
+
+/* Release the handle (not the caller's device memory).  NULL is allowed. */
+sg_status sg_free(sg_handle h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* sg_last_error(void);
+
+/* Library version string. */
+const char* sg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

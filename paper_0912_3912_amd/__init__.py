@@ -1,0 +1,287 @@
+"""MI355X-native colour-ordered single-spin-flip descent for hyper-Ising
+spin glasses (García & Markov, Sec. II eq. (1), Sec. IV, Sec. VI eq. (5)).
+
+This module is a thin ctypes binding of the C-ABI in ``include/sg.h``; every
+step of the method runs in the HIP kernels of ``libsg.so``.  PyTorch provides
+the device workspace (a uint8 tensor) and the HIP stream.  There is no CPU
+fallback: if the library or a GPU is missing the calls raise.
+
+Typical use::
+
+    import paper_0912_3912_amd as sg
+    h = sg.load_instance([inst])            # anything with n, ei, ej, J, h, tri, K, ...
+    h.bind()                                # torch workspace on cuda:0, current stream
+    h.init_spins(seed=7)
+    stats = h.run_sweeps(seed=7, rule=sg.GREEDY, max_sweeps=1000)
+    E = h.energy()
+    s = h.spins_out(0, 0)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "GREEDY", "GREEDY_TIE", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "SCHED_PERSISTENT",
+    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SGError", "Handle", "load_instance",
+    "run_sweeps", "energy", "spins_out", "library_path", "lib",
+]
+
+SG_OK, SG_ENOTCONV, SG_EINVAL, SG_ERANGE, SG_ENOMEM, SG_EDEVICE, SG_ESTATE = 0, 1, -1, -2, -3, -4, -5
+GREEDY, GREEDY_TIE = 0, 1
+SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_PERSISTENT, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE = (
+    -1, 0, 1, 2, 3, 4, 5)
+_STATUS = {SG_EINVAL: "SG_EINVAL", SG_ERANGE: "SG_ERANGE", SG_ENOMEM: "SG_ENOMEM",
+           SG_EDEVICE: "SG_EDEVICE", SG_ESTATE: "SG_ESTATE", SG_ENOTCONV: "SG_ENOTCONV"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libsg.so")
+
+
+class SGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("ei", ctypes.c_void_p), ("ej", ctypes.c_void_p), ("J", ctypes.c_void_p),
+                ("h", ctypes.c_void_p), ("t", ctypes.c_int64), ("tri", ctypes.c_void_p),
+                ("K", ctypes.c_void_p), ("colour", ctypes.c_void_p), ("dims", ctypes.c_int32 * 3),
+                ("instance_id", ctypes.c_uint32), ("restarts", ctypes.c_int32)]
+
+
+class RunParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("rule", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("until_converged", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_int64), ("flips", ctypes.c_int64), ("sweeps_max", ctypes.c_int64),
+                ("n_unconverged", ctypes.c_int32), ("schedule_used", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class InstanceInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("colours", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("t", ctypes.c_int64), ("restarts", ctypes.c_int32), ("lattice", ctypes.c_int32),
+                ("replica_base", ctypes.c_int64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported C-ABI function
+_P = ctypes.c_void_p
+SIGNATURES = [
+    ("sg_load_instance", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    ("sg_workspace_bytes", ctypes.c_int32, [_P, _P]),
+    ("sg_instance_info_get", ctypes.c_int32, [_P, ctypes.c_int32, _P, _P]),
+    ("sg_bind", ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
+    ("sg_init_spins", ctypes.c_int32, [_P, ctypes.c_uint64]),
+    ("sg_set_spins", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    ("sg_run_sweeps", ctypes.c_int32, [_P, _P, _P]),
+    ("sg_energy", ctypes.c_int32, [_P, _P, ctypes.c_int32]),
+    ("sg_replica_counters", ctypes.c_int32, [_P, _P, _P, _P]),
+    ("sg_spins_out", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    ("sg_best", ctypes.c_int32, [_P, _P, _P]),
+    ("sg_free", ctypes.c_int32, [_P]),
+    ("sg_last_error", ctypes.c_char_p, []),
+    ("sg_version", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """Load libsg.so (raises if it was not built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                              "or python paper_0912_3912_amd/_build.py")
+        L = ctypes.CDLL(path)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status < 0:
+        raise SGError(status, lib().sg_last_error().decode())
+    return status
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Handle:
+    """One loaded batch of instances (the C handle plus the arrays it keeps
+    alive).  Instances are duck-typed: attributes n, ei, ej, J and optionally
+    h, tri, K, colour, dims, instance_id, restarts."""
+
+    def __init__(self, instances: Sequence, lattice_dims: Optional[Sequence] = None):
+        self._keep = []
+        descs = (InstanceDesc * len(instances))()
+        self.sizes = []
+        self.restarts = []
+        for k, inst in enumerate(instances):
+            d = descs[k]
+            n = int(inst.n)
+            ei, ej, J = _i32(inst.ei), _i32(inst.ej), _i32(inst.J)
+            h = getattr(inst, "h", None)
+            h = None if h is None else _i32(h)
+            tri = getattr(inst, "tri", None)
+            tri = np.zeros(0, np.int32) if tri is None else _i32(tri).reshape(-1)
+            K = getattr(inst, "K", None)
+            K = np.zeros(0, np.int32) if K is None else _i32(K)
+            col = getattr(inst, "colour", None)
+            col = None if col is None else _i32(col)
+            self._keep += [ei, ej, J, h, tri, K, col]
+            d.n = n
+            d.m = ei.shape[0]
+            d.ei, d.ej, d.J, d.h = _ptr(ei), _ptr(ej), _ptr(J), _ptr(h)
+            d.t = tri.shape[0] // 3
+            d.tri, d.K, d.colour = _ptr(tri), _ptr(K), _ptr(col)
+            dims = None
+            if lattice_dims is not None:
+                dims = lattice_dims[k]
+            elif getattr(inst, "dims", None) is not None:
+                dims = inst.dims
+            if dims is not None:
+                dd = list(dims) + [0] * (3 - len(dims))
+                d.dims[0], d.dims[1], d.dims[2] = int(dd[0]), int(dd[1]), int(dd[2])
+            d.instance_id = int(getattr(inst, "instance_id", 0)) & 0xFFFFFFFF
+            d.restarts = int(getattr(inst, "restarts", 1))
+            self.sizes.append(n)
+            self.restarts.append(d.restarts)
+        self._h = ctypes.c_void_p()
+        _check(lib().sg_load_instance(descs, len(instances), ctypes.byref(self._h)))
+        self._keep = None  # the library copied the arrays
+        self.workspace = None
+        self.total_replicas = int(sum(self.restarts))
+
+    # ------------------------------------------------------------------ host-only
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().sg_workspace_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def info(self, inst: int = 0) -> dict:
+        inf = InstanceInfo()
+        col = np.zeros(self.sizes[inst], np.int32)
+        _check(lib().sg_instance_info_get(self._h, inst, ctypes.byref(inf), _ptr(col)))
+        d = {k: getattr(inf, k) for k, _ in InstanceInfo._fields_}
+        d["colour"] = col
+        return d
+
+    # ------------------------------------------------------------------ device
+    def bind(self, workspace=None, stream=None, device=None):
+        """Bind a torch uint8 device tensor (allocated here when None) and a
+        torch stream (the current stream when None)."""
+        import torch
+        if workspace is None:
+            dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+            workspace = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(workspace.device)
+        self.workspace = workspace
+        self.stream = stream
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().sg_bind(self._h, ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel() * workspace.element_size(), ctypes.c_void_p(sp)))
+        return self
+
+    def bind_raw(self, dev_ptr: int, nbytes: int, stream_ptr: int = 0):
+        _check(lib().sg_bind(self._h, ctypes.c_void_p(dev_ptr), nbytes, ctypes.c_void_p(stream_ptr)))
+        return self
+
+    def init_spins(self, seed: int):
+        _check(lib().sg_init_spins(self._h, seed & 0xFFFFFFFFFFFFFFFF))
+
+    def set_spins(self, inst: int, r: int, s):
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        if s.shape[0] != self.sizes[inst]:
+            raise ValueError("wrong spin count")
+        _check(lib().sg_set_spins(self._h, inst, r, _ptr(s)))
+
+    def run_sweeps(self, seed: int, rule: int = GREEDY, max_sweeps: int = 10000,
+                   until_converged: bool = True, schedule: int = SCHED_AUTO) -> dict:
+        p = RunParams(seed & 0xFFFFFFFFFFFFFFFF, rule, max_sweeps, int(until_converged), schedule)
+        st = RunStats()
+        status = _check(lib().sg_run_sweeps(self._h, ctypes.byref(p), ctypes.byref(st)))
+        d = st.as_dict()
+        d["status"] = status
+        return d
+
+    def energy(self, recompute: bool = False) -> np.ndarray:
+        E = np.zeros(self.total_replicas, np.int64)
+        _check(lib().sg_energy(self._h, _ptr(E), int(recompute)))
+        return E
+
+    def counters(self):
+        sw = np.zeros(self.total_replicas, np.int64)
+        fl = np.zeros(self.total_replicas, np.int64)
+        cv = np.zeros(self.total_replicas, np.int8)
+        _check(lib().sg_replica_counters(self._h, _ptr(sw), _ptr(fl), _ptr(cv)))
+        return sw, fl, cv
+
+    def spins_out(self, inst: int, r: int) -> np.ndarray:
+        s = np.zeros(self.sizes[inst], np.int8)
+        _check(lib().sg_spins_out(self._h, inst, r, _ptr(s)))
+        return s
+
+    def best(self):
+        ni = len(self.sizes)
+        E = np.zeros(ni, np.int64)
+        r = np.zeros(ni, np.int32)
+        _check(lib().sg_best(self._h, _ptr(E), _ptr(r)))
+        return E, r
+
+    def free(self):
+        if self._h:
+            lib().sg_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# module-level names matching the C-ABI calls -------------------------------
+
+
+def load_instance(instances, lattice_dims=None) -> Handle:
+    if not isinstance(instances, (list, tuple)):
+        instances = [instances]
+    return Handle(instances, lattice_dims)
+
+
+def run_sweeps(handle: Handle, **kw) -> dict:
+    return handle.run_sweeps(**kw)
+
+
+def energy(handle: Handle, recompute: bool = False) -> np.ndarray:
+    return handle.energy(recompute)
+
+
+def spins_out(handle: Handle, inst: int, r: int) -> np.ndarray:
+    return handle.spins_out(inst, r)

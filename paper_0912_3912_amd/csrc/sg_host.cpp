@@ -1,0 +1,790 @@
+// sg_host.cpp -- host core and C-ABI of the spin-glass local-search library.
+//
+// Instance ingest (validation, colouring, colour-major relabel, sliced
+// coupling layout, workspace layout), the run driver that enqueues the HIP
+// kernels of sg_kernels.hip on the caller's stream, and readout.  The
+// semantics of every entry point are documented in include/sg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+#include "sg_launch.h"
+#include "sg_layout.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sg_status fail(sg_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+sg_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(SG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SG_HIP(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+inline uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+constexpr int32_t kMaxN = (1 << 24) - 1;
+constexpr int32_t kMaxCoef = 127;
+constexpr int64_t kMaxField = (1 << 23) - 1;
+constexpr int32_t kMaxRestarts = 65535;
+
+struct HostInst {
+    int32_t n = 0;
+    int64_t m = 0, t = 0;
+    int32_t C = 0;
+    uint32_t id = 0;
+    int32_t R = 1;
+    int32_t lattice = 0;
+    int32_t dims[3] = {0, 0, 0};
+    std::vector<int32_t> colour;       // external order
+    std::vector<uint32_t> ext_of;      // internal -> external
+    std::vector<int32_t> colour_slice; // C+1 slice offsets
+    std::vector<sg::Slice> slices;
+    std::vector<uint32_t> nbr, ta, tb;
+    std::vector<int8_t> h;             // internal order
+    int32_t nslots = 1;                // phase-kernel blocks per colour (max over colours)
+    int64_t rep_base = 0;
+    // workspace offsets (bytes)
+    uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0;
+    uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
+};
+
+}  // namespace
+
+struct sg_ctx {
+    std::vector<HostInst> insts;
+    int64_t total_reps = 0;
+    uint64_t bytes = 0;
+    uint64_t off_reps = 0, off_stats = 0, off_flag = 0, off_eout = 0, off_slots = 0;
+    uint64_t off_best_E = 0, off_best_r = 0, off_rep_base = 0, off_restarts = 0;
+    uint8_t* dev = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    std::vector<uint8_t> started;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    template <class T>
+    T* at(uint64_t off) const { return reinterpret_cast<T*>(dev + off); }
+
+    sg::InstDev view(const HostInst& q) const
+    {
+        sg::InstDev I;
+        I.nbr = at<uint32_t>(q.off_nbr);
+        I.ta = at<uint32_t>(q.off_ta);
+        I.tb = at<uint32_t>(q.off_tb);
+        I.h = at<int8_t>(q.off_h);
+        I.ext = at<uint32_t>(q.off_ext);
+        I.slices = at<sg::Slice>(q.off_slices);
+        I.n = q.n;
+        I.nslices = (int32_t)q.slices.size();
+        I.instance_id = q.id;
+        I.has_tri = q.t > 0 ? 1 : 0;
+        return I;
+    }
+    sg::RepState* reps() const { return at<sg::RepState>(off_reps); }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// ingest
+
+struct Primal {  // primal adjacency (edges plus triple pairs), for colouring
+    std::vector<int64_t> start;
+    std::vector<int32_t> adj;
+};
+
+Primal build_primal(const sg_instance_desc& d)
+{
+    Primal P;
+    const int32_t n = d.n;
+    P.start.assign((size_t)n + 1, 0);
+    for (int64_t k = 0; k < d.m; ++k) {
+        P.start[d.ei[k] + 1]++;
+        P.start[d.ej[k] + 1]++;
+    }
+    for (int64_t k = 0; k < d.t; ++k)
+        for (int q = 0; q < 3; ++q) P.start[d.tri[3 * k + q] + 1] += 2;
+    for (int32_t i = 0; i < n; ++i) P.start[i + 1] += P.start[i];
+    P.adj.resize((size_t)P.start[n]);
+    std::vector<int64_t> fill(P.start.begin(), P.start.end() - 1);
+    for (int64_t k = 0; k < d.m; ++k) {
+        P.adj[fill[d.ei[k]]++] = d.ej[k];
+        P.adj[fill[d.ej[k]]++] = d.ei[k];
+    }
+    for (int64_t k = 0; k < d.t; ++k) {
+        const int32_t a = d.tri[3 * k], b = d.tri[3 * k + 1], c = d.tri[3 * k + 2];
+        P.adj[fill[a]++] = b; P.adj[fill[a]++] = c;
+        P.adj[fill[b]++] = a; P.adj[fill[b]++] = c;
+        P.adj[fill[c]++] = a; P.adj[fill[c]++] = b;
+    }
+    return P;
+}
+
+// First-fit: spin i takes the smallest colour unused by primal neighbours j < i.
+int32_t first_fit(const Primal& P, int32_t n, std::vector<int32_t>& colour)
+{
+    colour.assign((size_t)n, 0);
+    std::vector<int32_t> seen;  // seen[c] == i + 1 when colour c is taken by a lower neighbour of i
+    int32_t ncol = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t q = P.start[i]; q < P.start[i + 1]; ++q) {
+            const int32_t j = P.adj[q];
+            if (j < i) {
+                const int32_t c = colour[j];
+                if ((size_t)c >= seen.size()) seen.resize((size_t)c + 1, 0);
+                seen[c] = i + 1;
+            }
+        }
+        int32_t c = 0;
+        while ((size_t)c < seen.size() && seen[c] == i + 1) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+sg_status validate(const sg_instance_desc& d, int idx)
+{
+    if (d.n < 1) return fail(SG_EINVAL, "instance %d: n must be >= 1", idx);
+    if (d.n > kMaxN) return fail(SG_ERANGE, "instance %d: n = %d exceeds %d", idx, d.n, kMaxN);
+    if (d.m < 0 || d.t < 0) return fail(SG_EINVAL, "instance %d: negative edge or triple count", idx);
+    if (d.m > 0 && (!d.ei || !d.ej || !d.J)) return fail(SG_EINVAL, "instance %d: edge arrays missing", idx);
+    if (d.t > 0 && (!d.tri || !d.K)) return fail(SG_EINVAL, "instance %d: triple arrays missing", idx);
+    if (d.restarts < 1) return fail(SG_EINVAL, "instance %d: restarts must be >= 1", idx);
+    if (d.restarts > kMaxRestarts)
+        return fail(SG_ERANGE, "instance %d: restarts = %d exceeds %d", idx, d.restarts, kMaxRestarts);
+    const int64_t n = d.n;
+    std::vector<uint64_t> keys((size_t)d.m);
+    std::vector<int64_t> field((size_t)n, 0);
+    for (int64_t k = 0; k < d.m; ++k) {
+        const int64_t a = d.ei[k], b = d.ej[k];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return fail(SG_EINVAL, "instance %d: edge %lld has a spin index out of range", idx, (long long)k);
+        if (a == b) return fail(SG_EINVAL, "instance %d: edge %lld is a self-loop on spin %lld", idx, (long long)k,
+                                (long long)a);
+        if (d.J[k] < -kMaxCoef || d.J[k] > kMaxCoef)
+            return fail(SG_ERANGE, "instance %d: |J| of edge %lld exceeds %d", idx, (long long)k, kMaxCoef);
+        keys[k] = (uint64_t)std::min(a, b) * (uint64_t)n + (uint64_t)std::max(a, b);
+        field[a] += std::abs(d.J[k]);
+        field[b] += std::abs(d.J[k]);
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t k = 1; k < keys.size(); ++k)
+        if (keys[k] == keys[k - 1])
+            return fail(SG_EINVAL, "instance %d: edge (%llu,%llu) given twice", idx,
+                        (unsigned long long)(keys[k] / n), (unsigned long long)(keys[k] % n));
+    std::vector<std::array<int32_t, 3>> tk((size_t)d.t);
+    for (int64_t k = 0; k < d.t; ++k) {
+        std::array<int32_t, 3> v = {d.tri[3 * k], d.tri[3 * k + 1], d.tri[3 * k + 2]};
+        for (int q = 0; q < 3; ++q)
+            if (v[q] < 0 || v[q] >= n)
+                return fail(SG_EINVAL, "instance %d: triple %lld has a spin index out of range", idx, (long long)k);
+        if (v[0] == v[1] || v[0] == v[2] || v[1] == v[2])
+            return fail(SG_EINVAL, "instance %d: triple %lld repeats a spin", idx, (long long)k);
+        if (d.K[k] < -kMaxCoef || d.K[k] > kMaxCoef)
+            return fail(SG_ERANGE, "instance %d: |K| of triple %lld exceeds %d", idx, (long long)k, kMaxCoef);
+        std::sort(v.begin(), v.end());
+        tk[k] = v;
+        for (int q = 0; q < 3; ++q) field[v[q]] += std::abs(d.K[k]);
+    }
+    std::sort(tk.begin(), tk.end());
+    for (size_t k = 1; k < tk.size(); ++k)
+        if (tk[k] == tk[k - 1])
+            return fail(SG_EINVAL, "instance %d: triple (%d,%d,%d) given twice", idx, tk[k][0], tk[k][1], tk[k][2]);
+    for (int64_t i = 0; i < n; ++i) {
+        if (d.h) {
+            if (d.h[i] < -kMaxCoef || d.h[i] > kMaxCoef)
+                return fail(SG_ERANGE, "instance %d: |h| of spin %lld exceeds %d", idx, (long long)i, kMaxCoef);
+            field[i] += std::abs(d.h[i]);
+        }
+        if (field[i] > kMaxField)
+            return fail(SG_ERANGE, "instance %d: spin %lld has |h|+sum|J|+sum|K| = %lld > %lld", idx, (long long)i,
+                        (long long)field[i], (long long)kMaxField);
+    }
+    return SG_OK;
+}
+
+sg_status check_lattice(const sg_instance_desc& d, int idx)
+{
+    const int dim = d.dims[2] ? 3 : 2;
+    int64_t L[3] = {d.dims[0], d.dims[1], dim == 3 ? d.dims[2] : 1};
+    for (int a = 0; a < dim; ++a)
+        if (L[a] < 3) return fail(SG_EINVAL, "instance %d: lattice extent %lld < 3", idx, (long long)L[a]);
+    if (L[0] * L[1] * L[2] != d.n)
+        return fail(SG_EINVAL, "instance %d: lattice dims do not multiply to n", idx);
+    if (d.m != (int64_t)dim * d.n)
+        return fail(SG_EINVAL, "instance %d: a periodic %d-D lattice has %lld bonds, got %lld", idx, dim,
+                    (long long)dim * d.n, (long long)d.m);
+    for (int64_t k = 0; k < d.m; ++k) {
+        int64_t a = d.ei[k], b = d.ej[k];
+        int64_t ca[3] = {a / (L[1] * L[2]), (a / L[2]) % L[1], a % L[2]};
+        int64_t cb[3] = {b / (L[1] * L[2]), (b / L[2]) % L[1], b % L[2]};
+        int diff = 0, ok = 1;
+        for (int q = 0; q < 3; ++q) {
+            if (ca[q] == cb[q]) continue;
+            ++diff;
+            const int64_t dd = (cb[q] - ca[q] + L[q]) % L[q];
+            if (dd != 1 && dd != L[q] - 1) ok = 0;
+        }
+        if (diff != 1 || !ok)
+            return fail(SG_EINVAL, "instance %d: edge %lld (%lld,%lld) is not a lattice bond", idx, (long long)k,
+                        (long long)a, (long long)b);
+    }
+    return SG_OK;
+}
+
+sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
+{
+    sg_status st = validate(d, idx);
+    if (st != SG_OK) return st;
+    q.n = d.n;
+    q.m = d.m;
+    q.t = d.t;
+    q.id = d.instance_id;
+    q.R = d.restarts;
+    if (d.dims[0] || d.dims[1] || d.dims[2]) {
+        st = check_lattice(d, idx);
+        if (st != SG_OK) return st;
+        q.lattice = 1;
+        for (int a = 0; a < 3; ++a) q.dims[a] = d.dims[a];
+    }
+    const int32_t n = d.n;
+    Primal P = build_primal(d);
+    if (d.colour) {
+        q.colour.assign(d.colour, d.colour + n);
+        int32_t mx = -1;
+        for (int32_t i = 0; i < n; ++i) {
+            if (q.colour[i] < 0) return fail(SG_EINVAL, "instance %d: colour of spin %d is negative", idx, i);
+            mx = std::max(mx, q.colour[i]);
+        }
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t k = P.start[i]; k < P.start[i + 1]; ++k)
+                if (q.colour[P.adj[k]] == q.colour[i])
+                    return fail(SG_EINVAL, "instance %d: colouring is not proper (spins %d and %d share colour %d)",
+                                idx, i, P.adj[k], q.colour[i]);
+        q.C = mx + 1;
+    } else {
+        q.C = first_fit(P, n, q.colour);
+    }
+    if (q.C > 65535) return fail(SG_ERANGE, "instance %d: %d colours", idx, q.C);
+
+    // incidence counts
+    std::vector<int32_t> deg((size_t)n, 0), tdeg((size_t)n, 0);
+    for (int64_t k = 0; k < d.m; ++k) {
+        deg[d.ei[k]]++;
+        deg[d.ej[k]]++;
+    }
+    for (int64_t k = 0; k < 3 * d.t; ++k) tdeg[d.tri[k]]++;
+    for (int32_t i = 0; i < n; ++i) {
+        if (deg[i] > 65535) return fail(SG_ERANGE, "instance %d: spin %d has %d couplings", idx, i, deg[i]);
+        if (tdeg[i] > 255) return fail(SG_ERANGE, "instance %d: spin %d is in %d triples (max 255)", idx, i, tdeg[i]);
+    }
+    // colour-major relabel, decreasing incidence inside a colour, stable
+    q.ext_of.resize((size_t)n);
+    std::iota(q.ext_of.begin(), q.ext_of.end(), 0u);
+    std::stable_sort(q.ext_of.begin(), q.ext_of.end(), [&](uint32_t a, uint32_t b) {
+        if (q.colour[a] != q.colour[b]) return q.colour[a] < q.colour[b];
+        if (deg[a] != deg[b]) return deg[a] > deg[b];
+        return tdeg[a] > tdeg[b];
+    });
+    std::vector<uint32_t> int_of((size_t)n);
+    for (int32_t i = 0; i < n; ++i) int_of[q.ext_of[i]] = (uint32_t)i;
+
+    // incidence lists in internal numbering
+    std::vector<int64_t> es((size_t)n + 1, 0), ts((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        es[int_of[i] + 1] = deg[i];
+        ts[int_of[i] + 1] = tdeg[i];
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        es[i + 1] += es[i];
+        ts[i + 1] += ts[i];
+    }
+    std::vector<uint32_t> ew((size_t)es[n]), twa((size_t)ts[n]), twb((size_t)ts[n]);
+    {
+        std::vector<int64_t> fe(es.begin(), es.end() - 1), ft(ts.begin(), ts.end() - 1);
+        for (int64_t k = 0; k < d.m; ++k) {
+            const uint32_t a = int_of[d.ei[k]], b = int_of[d.ej[k]];
+            const uint32_t jb = (uint32_t)(uint8_t)(int8_t)d.J[k];
+            ew[fe[a]++] = (b << 8) | jb;
+            ew[fe[b]++] = (a << 8) | jb;
+        }
+        for (int64_t k = 0; k < d.t; ++k) {
+            const uint32_t v[3] = {int_of[d.tri[3 * k]], int_of[d.tri[3 * k + 1]], int_of[d.tri[3 * k + 2]]};
+            const uint32_t kb = (uint32_t)(uint8_t)(int8_t)d.K[k];
+            for (int s = 0; s < 3; ++s) {
+                const uint32_t o1 = v[(s + 1) % 3], o2 = v[(s + 2) % 3];
+                twa[ft[v[s]]] = (std::min(o1, o2) << 8) | kb;
+                twb[ft[v[s]]++] = std::max(o1, o2);
+            }
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            std::sort(ew.begin() + es[i], ew.begin() + es[i + 1]);
+            // order triple entries of a row by partner (pairs sorted together)
+            std::vector<std::pair<uint32_t, uint32_t>> tmp;
+            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) tmp.emplace_back(twa[k], twb[k]);
+            std::sort(tmp.begin(), tmp.end());
+            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
+                twa[k] = tmp[k - ts[i]].first;
+                twb[k] = tmp[k - ts[i]].second;
+            }
+        }
+    }
+    // fields
+    q.h.assign((size_t)n, 0);
+    if (d.h)
+        for (int32_t i = 0; i < n; ++i) q.h[int_of[i]] = (int8_t)d.h[i];
+
+    // sliced layout, colour by colour
+    std::vector<int32_t> cstart((size_t)q.C + 1, 0);
+    for (int32_t i = 0; i < n; ++i) cstart[q.colour[i] + 1]++;
+    for (int32_t c = 0; c < q.C; ++c) cstart[c + 1] += cstart[c];
+    q.colour_slice.assign((size_t)q.C + 1, 0);
+    uint64_t ebase = 0, tbase = 0;
+    int32_t maxblocks = 1;
+    for (int32_t c = 0; c < q.C; ++c) {
+        q.colour_slice[c] = (int32_t)q.slices.size();
+        for (int32_t r0 = cstart[c]; r0 < cstart[c + 1]; r0 += sg::kSlice) {
+            const int32_t rows = std::min(sg::kSlice, cstart[c + 1] - r0);
+            int32_t w = 0, tw = 0;
+            for (int32_t l = 0; l < rows; ++l) {
+                w = std::max<int32_t>(w, (int32_t)(es[r0 + l + 1] - es[r0 + l]));
+                tw = std::max<int32_t>(tw, (int32_t)(ts[r0 + l + 1] - ts[r0 + l]));
+            }
+            sg::Slice S;
+            S.row0 = (uint32_t)r0;
+            S.ebase = (uint32_t)ebase;
+            S.tbase = (uint32_t)tbase;
+            S.ew = (uint16_t)w;
+            S.tw = (uint8_t)tw;
+            S.rows = (uint8_t)rows;
+            q.slices.push_back(S);
+            ebase += (uint64_t)w * sg::kSlice;
+            tbase += (uint64_t)tw * sg::kSlice;
+            if (ebase > 0xFFFFFFFFull || tbase > 0xFFFFFFFFull)
+                return fail(SG_ERANGE, "instance %d: coupling layout exceeds 2^32 words", idx);
+        }
+        const int32_t ns = (int32_t)q.slices.size() - q.colour_slice[c];
+        maxblocks = std::max(maxblocks, (ns + sg::kPhaseWaves - 1) / sg::kPhaseWaves);
+    }
+    q.colour_slice[q.C] = (int32_t)q.slices.size();
+    q.nslots = maxblocks;
+    q.nbr.assign((size_t)std::max<uint64_t>(ebase, 1), 0u);
+    q.ta.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
+    q.tb.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
+    for (const sg::Slice& S : q.slices) {
+        for (int32_t l = 0; l < S.rows; ++l) {
+            const int32_t i = (int32_t)S.row0 + l;
+            for (int64_t k = es[i]; k < es[i + 1]; ++k) q.nbr[S.ebase + (k - es[i]) * sg::kSlice + l] = ew[k];
+            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
+                q.ta[S.tbase + (k - ts[i]) * sg::kSlice + l] = twa[k];
+                q.tb[S.tbase + (k - ts[i]) * sg::kSlice + l] = twb[k];
+            }
+        }
+    }
+    return SG_OK;
+}
+
+void layout(sg_ctx* H)
+{
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(bytes, 1));
+        return o;
+    };
+    int64_t max_slots = 1;
+    for (HostInst& q : H->insts) {
+        q.off_nbr = take(q.nbr.size() * 4);
+        q.off_ta = take(q.ta.size() * 4);
+        q.off_tb = take(q.tb.size() * 4);
+        q.off_h = take((uint64_t)q.n);
+        q.off_ext = take((uint64_t)q.n * 4);
+        q.off_slices = take(q.slices.size() * sizeof(sg::Slice));
+        q.spin_stride = align_up((uint64_t)q.n);
+        q.off_spins = take(q.spin_stride * (uint64_t)q.R);
+        q.off_acc = take((uint64_t)q.R * q.nslots * 16);
+        max_slots = std::max<int64_t>(max_slots, (int64_t)q.R * q.nslots);
+    }
+    H->off_reps = take((uint64_t)H->total_reps * sizeof(sg::RepState));
+    H->off_stats = take(sizeof(sg::CallStats));
+    H->off_flag = take(64);
+    H->off_eout = take((uint64_t)H->total_reps * 8);
+    H->off_slots = take((uint64_t)max_slots * 8);
+    const uint64_t ni = H->insts.size();
+    H->off_best_E = take(ni * 8);
+    H->off_best_r = take(ni * 4);
+    H->off_rep_base = take(ni * 8);
+    H->off_restarts = take(ni * 4);
+    H->bytes = off;
+}
+
+sg_status need_bound(sg_handle H)
+{
+    if (!H) return fail(SG_EINVAL, "null handle");
+    if (!H->bound) return fail(SG_ESTATE, "handle is not bound to device memory (call sg_bind)");
+    return SG_OK;
+}
+
+sg_status check_inst(sg_handle H, int32_t inst, int32_t r)
+{
+    if (inst < 0 || inst >= (int32_t)H->insts.size())
+        return fail(SG_EINVAL, "instance index %d out of range [0,%zu)", inst, H->insts.size());
+    if (r < 0 || r >= H->insts[inst].R)
+        return fail(SG_EINVAL, "restart %d out of range [0,%d)", r, H->insts[inst].R);
+    return SG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// run driver: one kernel launch per colour phase, instance by instance
+
+sg_status run_phase_schedule(sg_handle H, const sg_run_params* p)
+{
+    hipStream_t st = H->stream;
+    sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
+    uint32_t* flag = H->at<uint32_t>(H->off_flag);
+    for (const HostInst& q : H->insts) {
+        const sg::InstDev I = H->view(q);
+        sg::RepState* rs = H->reps() + q.rep_base;
+        int8_t* spins = H->at<int8_t>(q.off_spins);
+        int64_t* acc = H->at<int64_t>(q.off_acc);
+        SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.nslots * 2, st), "begin kernel");
+        int T = 0;
+        auto sweeps = [&](int from, int to) -> sg_status {
+            for (int t = from; t < to; ++t)
+                for (int32_t c = 0; c < q.C; ++c) {
+                    const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
+                    SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.nslots, s0, ns, t,
+                                            p->seed, p->rule, p->until_converged, st),
+                           "phase kernel");
+                }
+            return SG_OK;
+        };
+        if (!p->until_converged) {
+            sg_status e = sweeps(0, p->max_sweeps);
+            if (e != SG_OK) return e;
+            T = p->max_sweeps;
+        } else {
+            int seg = 2;
+            uint32_t hflag = 0;
+            while (T < p->max_sweeps) {
+                const int k = std::min(seg, p->max_sweeps - T);
+                sg_status e = sweeps(T, T + k);
+                if (e != SG_OK) return e;
+                T += k;
+                if (T >= p->max_sweeps) break;
+                SG_HIP(sg::launch_fill_u32(flag, 1, 0u, st), "fill kernel");
+                SG_HIP(sg::launch_any_active(rs, q.R, T, flag, st), "activity kernel");
+                SG_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
+                SG_HIP(hipStreamSynchronize(st), "stream sync");
+                if (!hflag) break;
+                seg = std::min(seg * 2, 64);
+            }
+        }
+        SG_HIP(sg::launch_end(rs, q.R, acc, q.nslots, T, p->until_converged, q.n, cs, st), "end kernel");
+    }
+    return SG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_err.c_str(); }
+
+const char* sg_version(void) { return "sg 0.1 (gfx950)"; }
+
+sg_status sg_load_instance(const sg_instance_desc* descs, int32_t count, sg_handle* out)
+{
+    g_err.clear();
+    if (!descs || !out || count < 1) return fail(SG_EINVAL, "sg_load_instance: need descs, out and count >= 1");
+    *out = nullptr;
+    sg_ctx* H = new (std::nothrow) sg_ctx;
+    if (!H) return fail(SG_ENOMEM, "out of host memory");
+    try {
+        H->insts.resize((size_t)count);
+        for (int32_t k = 0; k < count; ++k) {
+            sg_status st = ingest(descs[k], k, H->insts[k]);
+            if (st != SG_OK) {
+                delete H;
+                return st;
+            }
+            H->insts[k].rep_base = H->total_reps;
+            H->total_reps += H->insts[k].R;
+        }
+        layout(H);
+        H->started.assign((size_t)H->total_reps, 0);
+    } catch (const std::bad_alloc&) {
+        delete H;
+        return fail(SG_ENOMEM, "out of host memory while packing instances");
+    }
+    *out = H;
+    return SG_OK;
+}
+
+sg_status sg_workspace_bytes(sg_handle H, uint64_t* bytes)
+{
+    if (!H || !bytes) return fail(SG_EINVAL, "sg_workspace_bytes: null argument");
+    *bytes = H->bytes;
+    return SG_OK;
+}
+
+sg_status sg_instance_info_get(sg_handle H, int32_t inst, sg_instance_info* info, int32_t* colour_out)
+{
+    if (!H) return fail(SG_EINVAL, "null handle");
+    if (inst < 0 || inst >= (int32_t)H->insts.size()) return fail(SG_EINVAL, "instance index %d out of range", inst);
+    const HostInst& q = H->insts[inst];
+    if (info) {
+        info->n = q.n;
+        info->colours = q.C;
+        info->m = q.m;
+        info->t = q.t;
+        info->restarts = q.R;
+        info->lattice = q.lattice;
+        info->replica_base = q.rep_base;
+    }
+    if (colour_out) std::memcpy(colour_out, q.colour.data(), sizeof(int32_t) * (size_t)q.n);
+    return SG_OK;
+}
+
+sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
+{
+    if (!H) return fail(SG_EINVAL, "null handle");
+    if (!dev_ptr) return fail(SG_EINVAL, "sg_bind: null device pointer");
+    if ((uintptr_t)dev_ptr % kAlign) return fail(SG_EINVAL, "sg_bind: device pointer not 256-byte aligned");
+    if (bytes < H->bytes)
+        return fail(SG_ENOMEM, "sg_bind: workspace of %llu bytes, need %llu", (unsigned long long)bytes,
+                    (unsigned long long)H->bytes);
+    H->dev = (uint8_t*)dev_ptr;
+    H->stream = (hipStream_t)hip_stream;
+    H->bound = false;
+    std::fill(H->started.begin(), H->started.end(), 0);
+    hipStream_t st = H->stream;
+    for (const HostInst& q : H->insts) {
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_nbr, q.nbr.data(), q.nbr.size() * 4, hipMemcpyHostToDevice, st),
+               "upload couplings");
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_ta, q.ta.data(), q.ta.size() * 4, hipMemcpyHostToDevice, st),
+               "upload triples");
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_tb, q.tb.data(), q.tb.size() * 4, hipMemcpyHostToDevice, st),
+               "upload triples");
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_h, q.h.data(), (size_t)q.n, hipMemcpyHostToDevice, st), "upload fields");
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_ext, q.ext_of.data(), (size_t)q.n * 4, hipMemcpyHostToDevice, st),
+               "upload index map");
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_slices, q.slices.data(), q.slices.size() * sizeof(sg::Slice),
+                              hipMemcpyHostToDevice, st),
+               "upload slices");
+    }
+    std::vector<int64_t> rb(H->insts.size());
+    std::vector<int32_t> rr(H->insts.size());
+    for (size_t k = 0; k < H->insts.size(); ++k) {
+        rb[k] = H->insts[k].rep_base;
+        rr[k] = H->insts[k].R;
+    }
+    SG_HIP(hipMemcpyAsync(H->dev + H->off_rep_base, rb.data(), rb.size() * 8, hipMemcpyHostToDevice, st), "upload");
+    SG_HIP(hipMemcpyAsync(H->dev + H->off_restarts, rr.data(), rr.size() * 4, hipMemcpyHostToDevice, st), "upload");
+    SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
+    if (!H->ev0) SG_HIP(hipEventCreate(&H->ev0), "event create");
+    if (!H->ev1) SG_HIP(hipEventCreate(&H->ev1), "event create");
+    H->bound = true;
+    return SG_OK;
+}
+
+sg_status sg_init_spins(sg_handle H, uint64_t seed)
+{
+    sg_status s = need_bound(H);
+    if (s != SG_OK) return s;
+    hipStream_t st = H->stream;
+    for (const HostInst& q : H->insts) {
+        const sg::InstDev I = H->view(q);
+        sg::RepState* rs = H->reps() + q.rep_base;
+        SG_HIP(sg::launch_init(I, H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, rs, q.R, seed, st),
+               "init kernel");
+        SG_HIP(sg::launch_energy(I, H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
+                                 H->at<int64_t>(H->off_slots), q.nslots, rs, nullptr, st),
+               "energy kernel");
+    }
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    std::fill(H->started.begin(), H->started.end(), 1);
+    return SG_OK;
+}
+
+sg_status sg_set_spins(sg_handle H, int32_t inst, int32_t r, const int8_t* s)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    if ((e = check_inst(H, inst, r)) != SG_OK) return e;
+    if (!s) return fail(SG_EINVAL, "sg_set_spins: null spins");
+    const HostInst& q = H->insts[inst];
+    std::vector<int8_t> tmp((size_t)q.n);
+    for (int32_t i = 0; i < q.n; ++i) {
+        const int8_t v = s[q.ext_of[i]];
+        if (v != 1 && v != -1) return fail(SG_EINVAL, "sg_set_spins: spin %u is %d, not +1 or -1", q.ext_of[i], v);
+        tmp[i] = v;
+    }
+    hipStream_t st = H->stream;
+    int8_t* dst = H->at<int8_t>(q.off_spins) + (uint64_t)r * q.spin_stride;
+    sg::RepState z{};
+    sg::RepState* rs = H->reps() + q.rep_base + r;
+    SG_HIP(hipMemcpyAsync(dst, tmp.data(), (size_t)q.n, hipMemcpyHostToDevice, st), "spin upload");
+    SG_HIP(hipMemcpyAsync(rs, &z, sizeof z, hipMemcpyHostToDevice, st), "state upload");
+    SG_HIP(sg::launch_energy(H->view(q), dst, (int64_t)q.spin_stride, 1, H->at<int64_t>(H->off_slots), q.nslots, rs,
+                             nullptr, st),
+           "energy kernel");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    H->started[(size_t)(q.rep_base + r)] = 1;
+    return SG_OK;
+}
+
+sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    if (!p) return fail(SG_EINVAL, "sg_run_sweeps: null params");
+    if (p->rule != SG_RULE_GREEDY && p->rule != SG_RULE_GREEDY_TIE) return fail(SG_EINVAL, "unknown rule %d", p->rule);
+    if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
+    for (uint8_t v : H->started)
+        if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
+    int sched = p->schedule;
+    if (sched == SG_SCHED_AUTO) sched = SG_SCHED_PHASE;
+    if (sched != SG_SCHED_PHASE) return fail(SG_EINVAL, "schedule %d is not available for this handle", sched);
+    hipStream_t st = H->stream;
+    SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
+    SG_HIP(hipEventRecord(H->ev0, st), "event record");
+    e = run_phase_schedule(H, p);
+    if (e != SG_OK) return e;
+    SG_HIP(hipEventRecord(H->ev1, st), "event record");
+    sg::CallStats cs;
+    SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    float ms = 0.f;
+    SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
+    if (stats) {
+        stats->attempts = (int64_t)cs.attempts;
+        stats->flips = (int64_t)cs.flips;
+        stats->sweeps_max = (int64_t)cs.sweeps_max;
+        stats->n_unconverged = (int32_t)cs.unconverged;
+        stats->schedule_used = sched;
+        stats->kernel_ms = ms;
+    }
+    if (p->until_converged && cs.unconverged) {
+        fail(SG_ENOTCONV, "%llu replicas did not converge within %d sweeps", (unsigned long long)cs.unconverged,
+             p->max_sweeps);
+        return SG_ENOTCONV;
+    }
+    return SG_OK;
+}
+
+sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    if (!E) return fail(SG_EINVAL, "sg_energy: null output");
+    hipStream_t st = H->stream;
+    if (recompute) {
+        int64_t* eout = H->at<int64_t>(H->off_eout);
+        for (const HostInst& q : H->insts)
+            SG_HIP(sg::launch_energy(H->view(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
+                                     H->at<int64_t>(H->off_slots), q.nslots, nullptr, eout + q.rep_base, st),
+                   "energy kernel");
+        SG_HIP(hipMemcpyAsync(E, eout, (size_t)H->total_reps * 8, hipMemcpyDeviceToHost, st), "energy copy");
+        SG_HIP(hipStreamSynchronize(st), "stream sync");
+        return SG_OK;
+    }
+    std::vector<sg::RepState> rs((size_t)H->total_reps);
+    SG_HIP(hipMemcpyAsync(rs.data(), H->reps(), rs.size() * sizeof(sg::RepState), hipMemcpyDeviceToHost, st),
+           "state copy");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    for (size_t k = 0; k < rs.size(); ++k) E[k] = rs[k].E;
+    return SG_OK;
+}
+
+sg_status sg_replica_counters(sg_handle H, int64_t* sweeps, int64_t* flips, int8_t* converged)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    std::vector<sg::RepState> rs((size_t)H->total_reps);
+    SG_HIP(hipMemcpyAsync(rs.data(), H->reps(), rs.size() * sizeof(sg::RepState), hipMemcpyDeviceToHost, H->stream),
+           "state copy");
+    SG_HIP(hipStreamSynchronize(H->stream), "stream sync");
+    for (size_t k = 0; k < rs.size(); ++k) {
+        if (sweeps) sweeps[k] = rs[k].sweeps;
+        if (flips) flips[k] = rs[k].flips;
+        if (converged) converged[k] = (int8_t)rs[k].converged;
+    }
+    return SG_OK;
+}
+
+sg_status sg_spins_out(sg_handle H, int32_t inst, int32_t r, int8_t* s)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    if ((e = check_inst(H, inst, r)) != SG_OK) return e;
+    if (!s) return fail(SG_EINVAL, "sg_spins_out: null output");
+    const HostInst& q = H->insts[inst];
+    std::vector<int8_t> tmp((size_t)q.n);
+    SG_HIP(hipMemcpyAsync(tmp.data(), H->at<int8_t>(q.off_spins) + (uint64_t)r * q.spin_stride, (size_t)q.n,
+                          hipMemcpyDeviceToHost, H->stream),
+           "spin copy");
+    SG_HIP(hipStreamSynchronize(H->stream), "stream sync");
+    for (int32_t i = 0; i < q.n; ++i) s[q.ext_of[i]] = tmp[i];
+    return SG_OK;
+}
+
+sg_status sg_best(sg_handle H, int64_t* E_best, int32_t* r_best)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    const int ni = (int)H->insts.size();
+    hipStream_t st = H->stream;
+    SG_HIP(sg::launch_best(H->reps(), H->at<int64_t>(H->off_rep_base), H->at<int32_t>(H->off_restarts), ni,
+                           H->at<int64_t>(H->off_best_E), H->at<int32_t>(H->off_best_r), st),
+           "best kernel");
+    std::vector<int64_t> eb((size_t)ni);
+    std::vector<int32_t> rb((size_t)ni);
+    SG_HIP(hipMemcpyAsync(eb.data(), H->at<int64_t>(H->off_best_E), (size_t)ni * 8, hipMemcpyDeviceToHost, st), "copy");
+    SG_HIP(hipMemcpyAsync(rb.data(), H->at<int32_t>(H->off_best_r), (size_t)ni * 4, hipMemcpyDeviceToHost, st), "copy");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    if (E_best) std::memcpy(E_best, eb.data(), (size_t)ni * 8);
+    if (r_best) std::memcpy(r_best, rb.data(), (size_t)ni * 4);
+    return SG_OK;
+}
+
+sg_status sg_free(sg_handle H)
+{
+    if (!H) return SG_OK;
+    if (H->ev0) (void)hipEventDestroy(H->ev0);
+    if (H->ev1) (void)hipEventDestroy(H->ev1);
+    delete H;
+    return SG_OK;
+}
+
+}  // extern "C"

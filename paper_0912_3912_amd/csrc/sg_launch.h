@@ -1,0 +1,26 @@
+// sg_launch.h -- launchers of the library's HIP kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_layout.h"
+
+namespace sg {
+
+hipError_t launch_fill_u32(void* p, uint64_t count, uint32_t v, hipStream_t st);
+hipError_t launch_init(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, uint64_t seed,
+                       hipStream_t st);
+// Energy of every replica of one instance into rs[r].E (out == NULL) or out[r].
+hipError_t launch_energy(const InstDev& I, const int8_t* spins, int64_t stride, int R, int64_t* slots,
+                         int nslots, RepState* rs, int64_t* out, hipStream_t st);
+hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStream_t st);
+hipError_t launch_phase(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, int64_t* acc,
+                        int nslots, int slice0, int nslice_c, int t_rel, uint64_t seed, int rule,
+                        int until_conv, hipStream_t st);
+hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T, int until_conv, int64_t n,
+                      CallStats* cs, hipStream_t st);
+hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, hipStream_t st);
+hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_t* restarts, int ninst,
+                       int64_t* Eb, int32_t* rb, hipStream_t st);
+
+}  // namespace sg

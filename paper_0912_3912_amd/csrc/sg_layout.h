@@ -1,0 +1,76 @@
+// sg_layout.h -- packed device layout shared by the library's host code and
+// its HIP kernels (internal; not part of the C-ABI).
+//
+// One instance is stored colour-major: spins are relabelled so that each
+// colour class occupies a contiguous range of internal indices, and inside a
+// class spins are ordered by decreasing incidence count (stable, so equal
+// counts keep increasing external index).  Couplings are stored in sliced
+// ELLPACK form with slices of 64 rows, one row per lane of a wavefront: the
+// k-th coupling of the row in lane l of a slice sits at
+// ebase + k*64 + l, so one coupling step of a wavefront reads 256
+// contiguous bytes.  Each coupling is one 32-bit word (partner << 8 | J & 255)
+// with the partner's internal index in the top 24 bits and J as int8 in the
+// low byte.  A 3-spin hyper-coupling (i, a, b; K) is stored in the row of
+// each of its three members as two words (a << 8 | K & 255) and b.  Padding
+// words are zero (partner 0, coefficient 0) and contribute nothing.
+#pragma once
+#include <stdint.h>
+
+namespace sg {
+
+constexpr int kSlice = 64;        // rows per slice (one wavefront)
+constexpr int kPhaseWaves = 4;    // wavefronts per block of the phase kernels
+constexpr int kPhaseThreads = kSlice * kPhaseWaves;
+
+struct Slice {          // 16 bytes
+    uint32_t row0;      // internal index of the spin in lane 0
+    uint32_t ebase;     // word offset of the slice's first coupling
+    uint32_t tbase;     // word offset of the slice's first hyper-coupling
+    uint16_t ew;        // coupling words per row in this slice
+    uint8_t tw;         // hyper-couplings per row in this slice
+    uint8_t rows;       // valid rows (1..64)
+};
+static_assert(sizeof(Slice) == 16, "Slice must be 16 bytes");
+
+// Device view of one instance (pointers into the caller's workspace).
+struct InstDev {
+    const uint32_t* nbr;     // coupling words
+    const uint32_t* ta;      // hyper-coupling words (a << 8 | K)
+    const uint32_t* tb;      // hyper-coupling partner b
+    const int8_t* h;         // field per internal index
+    const uint32_t* ext;     // internal -> external index (RNG counter word 0)
+    const Slice* slices;     // all slices, colour by colour
+    int32_t n;
+    int32_t nslices;
+    uint32_t instance_id;
+    int32_t has_tri;
+};
+
+// Per-replica state, 32 bytes.
+struct RepState {
+    int64_t E;          // tracked energy
+    int64_t flips;      // moves applied since the start
+    int64_t sweeps;     // sweeps performed since the start (absolute sweep index of the next sweep)
+    int32_t lastflip;   // within a call: 1 + relative index of the last sweep that flipped
+    int32_t converged;  // 1 once a sweep flipped nothing under until_converged
+};
+static_assert(sizeof(RepState) == 32, "RepState must be 32 bytes");
+
+// Per-call totals written by the end-of-call kernel.
+struct CallStats {
+    unsigned long long attempts;
+    unsigned long long flips;
+    unsigned long long sweeps_max;
+    unsigned long long unconverged;
+};
+
+// Lattice (implicit neighbour) layout for the LDS tile schedule.
+struct LatticeDev {
+    const int8_t* jb;        // per site: J of the +x, +y, +z bond (3 bytes per site, site-major)
+    const int8_t* h;         // per site field, external (site) order
+    int32_t L[3];            // extents, x slowest; L[2] == 1 in 2-D... see host code
+    int32_t d;               // 2 or 3
+    int32_t c0;              // colour of site 0 (0 or 1)
+};
+
+}  // namespace sg

@@ -1,0 +1,129 @@
+"""GPU parity: the HIP library (through its C-ABI) against the CPU oracle,
+bit-exact on spins, tracked and recomputed int64 energies, sweep and flip
+counts and converged flags of every replica."""
+import numpy as np
+import pytest
+
+import instances as gen
+import oracle
+from parity import compare, expected_stats, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+GREEDY, TIE = 0, 1
+
+
+def _check(insts, seed, rule, max_sweeps, until_converged, schedule=-1, runs=None, lattice_dims=None):
+    log(f"case: {[i.name for i in insts][:4]} seed={seed} rule={rule} sweeps={runs or max_sweeps} "
+        f"until_converged={until_converged} schedule={schedule}")
+    h, stats = gpu_run(insts, seed, rule, max_sweeps, until_converged, schedule, runs, lattice_dims)
+    states = [oracle_run(i, seed, rule, max_sweeps, until_converged, runs) for i in insts]
+    compare(h, insts, states)
+    if runs is None:
+        att, fl = expected_stats(insts, [None] * len(insts), states)
+        assert stats[0]["attempts"] == att
+        assert stats[0]["flips"] == fl
+    h.free()
+    return states
+
+
+def test_square16_64_starts(gpu):
+    """16x16 periodic +-J lattice, 64 starts, GREEDY until converged."""
+    _check([gen.cfg1_square16()], seed=7, rule=GREEDY, max_sweeps=10000, until_converged=True)
+
+
+def test_square4_against_exhaustive(gpu):
+    inst = gen.cfg1_square4().replace(restarts=64)
+    e_gs, _, _ = oracle.brute_force(inst)
+    _check([inst], seed=7, rule=GREEDY, max_sweeps=10000, until_converged=True)
+    import paper_0912_3912_amd as sg
+    h = sg.load_instance([inst]).bind()
+    h.init_spins(7)
+    h.run_sweeps(seed=7)
+    Eb, rb = h.best()
+    assert Eb[0] >= e_gs
+    E = h.energy()
+    assert Eb[0] == E.min() and rb[0] == int(np.argmin(E))
+
+
+@pytest.mark.parametrize("rule,uc,sweeps", [(TIE, False, 40), (GREEDY, True, 1000), (TIE, True, 60)])
+def test_cubic20(gpu, rule, uc, sweeps):
+    inst = gen.cfg2_cubic100(L=20).replace(restarts=3)
+    _check([inst], seed=7, rule=rule, max_sweeps=sweeps, until_converged=uc)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 129, 1000])
+@pytest.mark.parametrize("rule", [GREEDY, TIE])
+def test_ragged_random_with_triples(gpu, n, rule):
+    inst = gen.random_small(n, seed=n, p_edge=min(1.0, 8.0 / max(n, 1)), n_triples=n // 2,
+                            j_range=(-15, 15), h_range=(-7, 7), k_range=(-7, 7)).replace(restarts=5)
+    _check([inst], seed=n + 1, rule=rule, max_sweeps=25, until_converged=(rule == GREEDY))
+
+
+@pytest.mark.parametrize("rule", [GREEDY, TIE])
+def test_chimera_with_triples(gpu, rule):
+    inst = gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)
+    _check([inst], seed=11, rule=rule, max_sweeps=30, until_converged=(rule == GREEDY))
+
+
+def test_batch_of_mixed_instances(gpu):
+    insts = [gen.chimera(8, 8, seed=s, instance_id=s, restarts=3) for s in range(3)]
+    insts += [gen.erdos_renyi_triples(n, seed=n, instance_id=100 + n) for n in (100, 517, 3000)]
+    insts += [gen.random_regular3(1000, seed=4, instance_id=7)]
+    _check(insts, seed=5, rule=GREEDY, max_sweeps=10000, until_converged=True)
+
+
+@pytest.mark.parametrize("rule,uc", [(GREEDY, True), (TIE, False), (TIE, True)])
+def test_resume_exact(gpu, rule, uc):
+    inst = gen.lattice((10, 10, 10), seed=3, h_range=(-2, 2), restarts=3)
+    _check([inst], seed=8, rule=rule, max_sweeps=0, until_converged=uc, runs=[5, 7, 0, 3])
+
+
+def test_factor21_all_starts_via_set_spins(gpu):
+    import itertools
+    import paper_0912_3912_amd as sg
+    from test_oracle_pins import factor21_instance
+    inst, N, const, _ = factor21_instance()
+    inst = inst.replace(restarts=8)
+    h = sg.load_instance([inst]).bind()
+    for r, S in enumerate(itertools.product([1, -1], repeat=3)):
+        h.set_spins(0, r, np.array(S, np.int8))
+    h.run_sweeps(seed=1)
+    E = h.energy()
+    assert np.all(E == -const)
+    for r in range(8):
+        assert list(h.spins_out(0, r)) == [-1, -1, -1]
+
+
+def test_lattice_hint_and_explicit_colouring(gpu):
+    inst = gen.lattice((8, 6, 4), seed=9, h_range=(-2, 2), restarts=2)
+    _check([inst], seed=3, rule=TIE, max_sweeps=12, until_converged=False, lattice_dims=[(8, 6, 4)])
+
+
+def test_errors(gpu):
+    import paper_0912_3912_amd as sg
+    h = sg.load_instance([gen.cfg1_square16()])
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1)
+    assert e.value.status == sg.SG_ESTATE
+    h.bind()
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1)
+    assert e.value.status == sg.SG_ESTATE
+    h.init_spins(1)
+    with pytest.raises(sg.SGError) as e:
+        h.set_spins(0, 0, np.zeros(256, np.int8))
+    assert e.value.status == sg.SG_EINVAL
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1, rule=5)
+    assert e.value.status == sg.SG_EINVAL
+    st = h.run_sweeps(seed=1, max_sweeps=1)
+    assert st["status"] == sg.SG_ENOTCONV and st["n_unconverged"] == 64
+
+
+def test_cubic100_full_1000_sweeps(gpu):
+    """The 10^6-spin workload at full size: 1000 GREEDY_TIE sweeps from one
+    random start, compared with the oracle (spins, energies, flips)."""
+    inst = gen.cfg2_cubic100()
+    _check([inst], seed=7, rule=TIE, max_sweeps=1000, until_converged=False,
+           lattice_dims=[(100, 100, 100)])
