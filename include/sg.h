@@ -157,7 +157,7 @@ typedef struct {
     int64_t m;
     int64_t t;
     int32_t restarts;
-    int32_t lattice;       /* 1 if the lattice hint was accepted */
+    int32_t lattice;       /* 1 if the lattice schedule can run this instance */
     int64_t replica_base;  /* index of replica 0 of this instance in handle order */
 } sg_instance_info;
 
@@ -217,6 +217,18 @@ sg_status sg_spins_out(sg_handle h, int32_t inst, int32_t r, int8_t* s);
  * tracked energy over its restarts, lowest restart index on ties.  E_best and
  * r_best have one entry per instance; either may be NULL. */
 sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
+
+/* Tuning knobs of the schedules; results never depend on them.
+ *   "lattice_k"          colour phases between halo exchanges of the lattice
+ *                        tile schedule (1..16, default 4)
+ *   "lattice_max_tiles"  cap on tiles per replica (0 = as many as fit)
+ *   "lattice_wg_max_n"   largest lattice run with one workgroup per replica
+ * Unknown key or value out of range: SG_EINVAL. */
+sg_status sg_tune(sg_handle h, const char* key, int64_t value);
+
+/* Read a knob, or one of "last_tiles" (Px*10^6 + Py*10^3 + Pz of the last
+ * lattice tile launch), "last_tile_k", "total_replicas", "instances". */
+sg_status sg_query(sg_handle h, const char* key, int64_t* value);
 
 /* Release the handle (not the caller's device memory).  NULL is allowed. */
 sg_status sg_free(sg_handle h);

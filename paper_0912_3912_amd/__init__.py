@@ -94,6 +94,8 @@ SIGNATURES = [
     ("sg_replica_counters", ctypes.c_int32, [_P, _P, _P, _P]),
     ("sg_spins_out", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("sg_best", ctypes.c_int32, [_P, _P, _P]),
+    ("sg_tune", ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
+    ("sg_query", ctypes.c_int32, [_P, ctypes.c_char_p, _P]),
     ("sg_free", ctypes.c_int32, [_P]),
     ("sg_last_error", ctypes.c_char_p, []),
     ("sg_version", ctypes.c_char_p, []),
@@ -253,6 +255,15 @@ class Handle:
         r = np.zeros(ni, np.int32)
         _check(lib().sg_best(self._h, _ptr(E), _ptr(r)))
         return E, r
+
+    def tune(self, key: str, value: int):
+        _check(lib().sg_tune(self._h, key.encode(), int(value)))
+        return self
+
+    def query(self, key: str) -> int:
+        v = ctypes.c_int64()
+        _check(lib().sg_query(self._h, key.encode(), ctypes.byref(v)))
+        return int(v.value)
 
     def free(self):
         if self._h:

@@ -52,6 +52,7 @@ constexpr int32_t kMaxN = (1 << 24) - 1;
 constexpr int32_t kMaxCoef = 127;
 constexpr int64_t kMaxField = (1 << 23) - 1;
 constexpr int32_t kMaxRestarts = 65535;
+constexpr int32_t kMaxLatticeTiles = 1024;
 
 struct HostInst {
     int32_t n = 0;
@@ -68,7 +69,15 @@ struct HostInst {
     std::vector<uint32_t> nbr, ta, tb;
     std::vector<int8_t> h;             // internal order
     int32_t nslots = 1;                // phase-kernel blocks per colour (max over colours)
+    int32_t acc_slots = 1;             // accumulator slots per replica (max over schedules)
     int64_t rep_base = 0;
+    // lattice schedule (implicit neighbours)
+    int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
+    int32_t lat_L[3] = {0, 0, 0};      // (x, y, z) extents, z fastest; 2-D: (1, Lx, Ly)
+    int32_t lat_D = 0;
+    int32_t lat_c0 = 0;
+    std::vector<uint64_t> lat_rec;     // per-site coupling record
+    uint64_t off_lat_rec = 0, off_lat_g = 0, off_lat_flags = 0;
     // workspace offsets (bytes)
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
@@ -81,12 +90,17 @@ struct sg_ctx {
     int64_t total_reps = 0;
     uint64_t bytes = 0;
     uint64_t off_reps = 0, off_stats = 0, off_flag = 0, off_eout = 0, off_slots = 0;
-    uint64_t off_best_E = 0, off_best_r = 0, off_rep_base = 0, off_restarts = 0;
+    uint64_t off_best_E = 0, off_best_r = 0, off_rep_base = 0, off_restarts = 0, off_err = 0;
+    // tuning knobs (sg_tune)
+    int32_t lattice_k = 4;             // phases per halo exchange of the lattice tile schedule
+    int32_t lattice_max_tiles = 0;     // 0 = as many as fit co-resident
+    int32_t lattice_wg_max_n = 150000; // largest lattice run as one workgroup per replica
     uint8_t* dev = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false;
     std::vector<uint8_t> started;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int32_t last_tiles[4] = {0, 0, 0, 0};  // tiling of the last lattice tile launch
 
     template <class T>
     T* at(uint64_t off) const { return reinterpret_cast<T*>(dev + off); }
@@ -107,6 +121,18 @@ struct sg_ctx {
         return I;
     }
     sg::RepState* reps() const { return at<sg::RepState>(off_reps); }
+
+    sg::LatticeDev lat_view(const HostInst& q) const
+    {
+        sg::LatticeDev L;
+        L.rec = at<uint64_t>(q.off_lat_rec);
+        for (int a = 0; a < 3; ++a) L.L[a] = q.lat_L[a];
+        L.D = q.lat_D;
+        L.c0 = q.lat_c0;
+        L.n = q.n;
+        L.instance_id = q.id;
+        return L;
+    }
 };
 
 namespace {
@@ -259,6 +285,52 @@ sg_status check_lattice(const sg_instance_desc& d, int idx)
     return SG_OK;
 }
 
+// Lattice records for the implicit-neighbour schedules.  Accepted only when
+// every extent is even, the colouring is the checkerboard and the
+// colour-major relabel put site g at internal index colour(g)*n/2 + g/2 (true
+// for the uniform-degree lattice); otherwise those schedules stay off.
+void build_lattice(const sg_instance_desc& d, HostInst& q, const std::vector<uint32_t>& int_of)
+{
+    const int dim = d.dims[2] ? 3 : 2;
+    int32_t L[3];
+    if (dim == 3) {
+        L[0] = d.dims[0]; L[1] = d.dims[1]; L[2] = d.dims[2];
+    } else {
+        L[0] = 1; L[1] = d.dims[0]; L[2] = d.dims[1];
+    }
+    for (int a = 3 - dim; a < 3; ++a)
+        if (L[a] % 2) return;
+    const int32_t n = d.n;
+    const int32_t c0 = q.colour[0];
+    if (c0 != 0 && c0 != 1) return;
+    for (int32_t g = 0; g < n; ++g) {
+        const int32_t x = g / (L[1] * L[2]), y = (g / L[2]) % L[1], z = g % L[2];
+        const int32_t col = (x + y + z + c0) & 1;
+        if (q.colour[g] != col) return;
+        if (int_of[g] != (uint32_t)(col * (n / 2) + g / 2)) return;
+    }
+    q.lat_rec.assign((size_t)n, 0);
+    for (int64_t k = 0; k < d.m; ++k) {
+        const int32_t a = d.ei[k], b = d.ej[k];
+        const int32_t ca[3] = {a / (L[1] * L[2]), (a / L[2]) % L[1], a % L[2]};
+        const int32_t cb[3] = {b / (L[1] * L[2]), (b / L[2]) % L[1], b % L[2]};
+        int ax = 0;
+        while (ax < 3 && ca[ax] == cb[ax]) ++ax;
+        const bool b_is_plus = cb[ax] == (ca[ax] + 1) % L[ax];
+        const int32_t lo = b_is_plus ? a : b, hi = b_is_plus ? b : a;  // hi = lo + e_ax
+        const uint64_t jv = (uint64_t)(uint8_t)(int8_t)d.J[k];
+        q.lat_rec[lo] |= jv << (8 * (2 * ax));
+        q.lat_rec[hi] |= jv << (8 * (2 * ax + 1));
+    }
+    if (d.h)
+        for (int32_t g = 0; g < n; ++g) q.lat_rec[g] |= (uint64_t)(uint8_t)(int8_t)d.h[g] << 48;
+    for (int a = 0; a < 3; ++a) q.lat_L[a] = L[a];
+    q.lat_D = dim;
+    q.lat_c0 = c0;
+    q.lat_ok = 1;
+    q.acc_slots = std::max(q.acc_slots, kMaxLatticeTiles);
+}
+
 sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
 {
     sg_status st = validate(d, idx);
@@ -395,6 +467,7 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     }
     q.colour_slice[q.C] = (int32_t)q.slices.size();
     q.nslots = maxblocks;
+    q.acc_slots = maxblocks;
     q.nbr.assign((size_t)std::max<uint64_t>(ebase, 1), 0u);
     q.ta.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
     q.tb.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
@@ -408,6 +481,7 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
             }
         }
     }
+    if (q.lattice && q.t == 0) build_lattice(d, q, int_of);
     return SG_OK;
 }
 
@@ -429,12 +503,18 @@ void layout(sg_ctx* H)
         q.off_slices = take(q.slices.size() * sizeof(sg::Slice));
         q.spin_stride = align_up((uint64_t)q.n);
         q.off_spins = take(q.spin_stride * (uint64_t)q.R);
-        q.off_acc = take((uint64_t)q.R * q.nslots * 16);
+        q.off_acc = take((uint64_t)q.R * q.acc_slots * 16);
+        if (q.lat_ok) {
+            q.off_lat_rec = take((uint64_t)q.n * 8);
+            q.off_lat_g = take((uint64_t)q.n * q.R * 2);
+            q.off_lat_flags = take((uint64_t)kMaxLatticeTiles * q.R * 4);
+        }
         max_slots = std::max<int64_t>(max_slots, (int64_t)q.R * q.nslots);
     }
     H->off_reps = take((uint64_t)H->total_reps * sizeof(sg::RepState));
     H->off_stats = take(sizeof(sg::CallStats));
     H->off_flag = take(64);
+    H->off_err = take(64);
     H->off_eout = take((uint64_t)H->total_reps * 8);
     H->off_slots = take((uint64_t)max_slots * 8);
     const uint64_t ni = H->insts.size();
@@ -474,13 +554,13 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p)
         sg::RepState* rs = H->reps() + q.rep_base;
         int8_t* spins = H->at<int8_t>(q.off_spins);
         int64_t* acc = H->at<int64_t>(q.off_acc);
-        SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.nslots * 2, st), "begin kernel");
+        SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
         int T = 0;
         auto sweeps = [&](int from, int to) -> sg_status {
             for (int t = from; t < to; ++t)
                 for (int32_t c = 0; c < q.C; ++c) {
                     const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
-                    SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.nslots, s0, ns, t,
+                    SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, t,
                                             p->seed, p->rule, p->until_converged, st),
                            "phase kernel");
                 }
@@ -507,9 +587,122 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p)
                 seg = std::min(seg * 2, 64);
             }
         }
-        SG_HIP(sg::launch_end(rs, q.R, acc, q.nslots, T, p->until_converged, q.n, cs, st), "end kernel");
+        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st), "end kernel");
     }
     return SG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lattice schedules: whole lattice per workgroup, or co-resident tiles
+
+bool lattice_wg_fits(const sg_ctx* H, const HostInst& q) { return q.n <= H->lattice_wg_max_n; }
+
+// Largest tiling whose boxes fit LDS and whose workgroups are co-resident:
+// minimise the largest box (work per workgroup per phase).
+bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
+{
+    const int k = std::max(1, H->lattice_k);
+    int cap_limit = kMaxLatticeTiles;
+    if (H->lattice_max_tiles > 0) cap_limit = std::min(cap_limit, H->lattice_max_tiles);
+    std::vector<std::pair<size_t, int>> cap_cache;  // LDS bytes -> co-resident workgroups
+    auto cap_for = [&](const sg::TileGeom& g) {
+        const size_t lds = sg::lattice_tiles_lds(g, q.lat_L, q.lat_D);
+        for (auto& c : cap_cache)
+            if (c.first == lds) return c.second;
+        const int c = sg::lattice_tiles_max_blocks(g, q.lat_L, q.lat_D);
+        cap_cache.emplace_back(lds, c);
+        return c;
+    };
+    bool found = false;
+    int64_t bestV = INT64_MAX;
+    int bestT = 0;
+    const int a0 = q.lat_D == 2 ? 1 : 0;
+    for (int p0 = 1; p0 <= (a0 ? 1 : q.lat_L[0] / k); ++p0)
+        for (int p1 = 1; p1 <= q.lat_L[1] / k; ++p1)
+            for (int p2 = 1; p2 <= q.lat_L[2] / k; ++p2) {
+                const int T = p0 * p1 * p2;
+                if (T > cap_limit) break;
+                sg::TileGeom g{};
+                g.P[0] = p0; g.P[1] = p1; g.P[2] = p2; g.k = k;
+                int64_t V = 1;
+                for (int a = 0; a < 3; ++a)
+                    V *= (q.lat_L[a] + g.P[a] - 1) / g.P[a] + ((a < a0) ? 0 : 2 * k);
+                if (!(V < bestV || (V == bestV && T < bestT))) continue;
+                if (sg::lattice_tiles_ns(g, q.lat_L, q.lat_D) == 0) continue;
+                if ((int64_t)T * q.R > cap_for(g)) continue;
+                bestV = V;
+                bestT = T;
+                tg = g;
+                found = true;
+            }
+    return found;
+}
+
+sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p)
+{
+    hipStream_t st = H->stream;
+    sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
+    uint32_t* err = H->at<uint32_t>(H->off_err);
+    for (const HostInst& q : H->insts) {
+        sg::RepState* rs = H->reps() + q.rep_base;
+        int8_t* spins = H->at<int8_t>(q.off_spins);
+        int64_t* acc = H->at<int64_t>(q.off_acc);
+        const sg::LatticeDev Lt = H->lat_view(q);
+        SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
+        const int T = p->max_sweeps;
+        if (T > 0) {
+            if (lattice_wg_fits(H, q)) {
+                SG_HIP(sg::launch_lattice_wg(Lt, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, T, p->seed,
+                                             p->rule, p->until_converged, st),
+                       "lattice workgroup kernel");
+            } else {
+                sg::TileGeom tg{};
+                if (!choose_tiling(H, q, tg))
+                    return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0], q.lat_L[1],
+                                q.lat_L[2]);
+                uint32_t* flags = H->at<uint32_t>(q.off_lat_flags);
+                SG_HIP(sg::launch_fill_u32(flags, (uint64_t)kMaxLatticeTiles * q.R, 0u, st), "fill kernel");
+                SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
+                int8_t* G0 = H->at<int8_t>(q.off_lat_g);
+                int8_t* G1 = G0 + (uint64_t)q.n * q.R;
+                SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs, q.R,
+                                                acc, q.acc_slots, T, p->seed, p->rule, st),
+                       "lattice tile kernel");
+                uint32_t herr = 0;
+                SG_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st), "error flag copy");
+                SG_HIP(hipStreamSynchronize(st), "stream sync");
+                if (herr) return fail(SG_EDEVICE, "lattice tile kernel: a neighbour wait timed out");
+                H->last_tiles[0] = tg.P[0];
+                H->last_tiles[1] = tg.P[1];
+                H->last_tiles[2] = tg.P[2];
+                H->last_tiles[3] = tg.k;
+            }
+        }
+        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st), "end kernel");
+    }
+    return SG_OK;
+}
+
+// Schedule a handle can use, or -1.
+int resolve_schedule(const sg_ctx* H, const sg_run_params* p)
+{
+    int sched = p->schedule;
+    bool all_lat = true, all_lat_wg = true;
+    for (const HostInst& q : H->insts) {
+        all_lat = all_lat && q.lat_ok;
+        all_lat_wg = all_lat_wg && q.lat_ok && lattice_wg_fits(H, q);
+    }
+    if (sched == SG_SCHED_AUTO) {
+        if (all_lat && (all_lat_wg || !p->until_converged)) return SG_SCHED_LATTICE;
+        return SG_SCHED_PHASE;
+    }
+    if (sched == SG_SCHED_PHASE) return sched;
+    if (sched == SG_SCHED_LATTICE) {
+        if (!all_lat) return -1;
+        if (p->until_converged && !all_lat_wg) return -1;
+        return sched;
+    }
+    return -1;
 }
 
 }  // namespace
@@ -569,7 +762,7 @@ sg_status sg_instance_info_get(sg_handle H, int32_t inst, sg_instance_info* info
         info->m = q.m;
         info->t = q.t;
         info->restarts = q.R;
-        info->lattice = q.lattice;
+        info->lattice = q.lat_ok;
         info->replica_base = q.rep_base;
     }
     if (colour_out) std::memcpy(colour_out, q.colour.data(), sizeof(int32_t) * (size_t)q.n);
@@ -602,6 +795,10 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
         SG_HIP(hipMemcpyAsync(H->dev + q.off_slices, q.slices.data(), q.slices.size() * sizeof(sg::Slice),
                               hipMemcpyHostToDevice, st),
                "upload slices");
+        if (q.lat_ok)
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_lat_rec, q.lat_rec.data(), q.lat_rec.size() * 8,
+                                  hipMemcpyHostToDevice, st),
+                   "upload lattice records");
     }
     std::vector<int64_t> rb(H->insts.size());
     std::vector<int32_t> rr(H->insts.size());
@@ -673,13 +870,17 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
     for (uint8_t v : H->started)
         if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
-    int sched = p->schedule;
-    if (sched == SG_SCHED_AUTO) sched = SG_SCHED_PHASE;
-    if (sched != SG_SCHED_PHASE) return fail(SG_EINVAL, "schedule %d is not available for this handle", sched);
+    const int sched = resolve_schedule(H, p);
+    if (sched < 0)
+        return fail(SG_EINVAL, "schedule %d is not available for this handle (rule %d, until_converged %d)",
+                    p->schedule, p->rule, p->until_converged);
     hipStream_t st = H->stream;
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
-    e = run_phase_schedule(H, p);
+    switch (sched) {
+    case SG_SCHED_LATTICE: e = run_lattice_schedule(H, p); break;
+    default: e = run_phase_schedule(H, p); break;
+    }
     if (e != SG_OK) return e;
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
     sg::CallStats cs;
@@ -775,6 +976,40 @@ sg_status sg_best(sg_handle H, int64_t* E_best, int32_t* r_best)
     SG_HIP(hipStreamSynchronize(st), "stream sync");
     if (E_best) std::memcpy(E_best, eb.data(), (size_t)ni * 8);
     if (r_best) std::memcpy(r_best, rb.data(), (size_t)ni * 4);
+    return SG_OK;
+}
+
+sg_status sg_tune(sg_handle H, const char* key, int64_t value)
+{
+    if (!H || !key) return fail(SG_EINVAL, "sg_tune: null argument");
+    const std::string k(key);
+    if (k == "lattice_k") {
+        if (value < 1 || value > 16) return fail(SG_EINVAL, "lattice_k must be in [1,16]");
+        H->lattice_k = (int32_t)value;
+    } else if (k == "lattice_max_tiles") {
+        if (value < 0 || value > kMaxLatticeTiles) return fail(SG_EINVAL, "lattice_max_tiles out of range");
+        H->lattice_max_tiles = (int32_t)value;
+    } else if (k == "lattice_wg_max_n") {
+        if (value < 0 || value > 150000) return fail(SG_EINVAL, "lattice_wg_max_n must be in [0,150000]");
+        H->lattice_wg_max_n = (int32_t)value;
+    } else {
+        return fail(SG_EINVAL, "sg_tune: unknown key '%s'", key);
+    }
+    return SG_OK;
+}
+
+sg_status sg_query(sg_handle H, const char* key, int64_t* value)
+{
+    if (!H || !key || !value) return fail(SG_EINVAL, "sg_query: null argument");
+    const std::string k(key);
+    if (k == "lattice_k") *value = H->lattice_k;
+    else if (k == "lattice_max_tiles") *value = H->lattice_max_tiles;
+    else if (k == "lattice_wg_max_n") *value = H->lattice_wg_max_n;
+    else if (k == "last_tiles") *value = (int64_t)H->last_tiles[0] * 1000000 + H->last_tiles[1] * 1000 + H->last_tiles[2];
+    else if (k == "last_tile_k") *value = H->last_tiles[3];
+    else if (k == "total_replicas") *value = H->total_reps;
+    else if (k == "instances") *value = (int64_t)H->insts.size();
+    else return fail(SG_EINVAL, "sg_query: unknown key '%s'", key);
     return SG_OK;
 }
 

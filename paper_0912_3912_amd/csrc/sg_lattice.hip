@@ -1,0 +1,549 @@
+// sg_lattice.hip -- colour-ordered sweeps on periodic 2-D/3-D lattices with
+// implicit neighbours, LDS-resident.
+//
+// Sites are addressed (x, y, z) with z fastest (a 2-D lattice is stored as
+// 1 x Lx x Ly and has no x bonds); all extents are even so the colouring is
+// the checkerboard colour(g) = (x + y + z + c0) mod 2, identical to the
+// colour-major relabel of the general path (internal index of site g =
+// colour(g) * n/2 + g/2).  Each site carries one 64-bit record: the
+// couplings to its +x, -x, +y, -y, +z, -z neighbours and its field, as int8.
+//
+// k_lattice_tiles: one workgroup per tile of the lattice (one launch for the
+// whole run, all workgroups co-resident).  A workgroup keeps its tile plus a
+// halo of width k in LDS and advances k colour phases between exchanges;
+// after phase q of an epoch only sites at least q+1 layers inside the box are
+// still exact (each update needs its six neighbours from the previous
+// phase), so after k phases exactly the tile interior is exact.  It then
+// publishes its interior, signals an epoch flag, waits for the flags of its
+// (up to 26) neighbouring tiles and reads its new halo.  The exchange buffer
+// alternates between two copies by epoch parity, which removes the
+// write-after-read hazard between neighbours one epoch apart.  Every wait is
+// bounded: on time-out the kernel records an error and every workgroup exits.
+//
+// k_lattice_wg: the whole lattice of one replica in one workgroup (small
+// lattices, many replicas); supports the per-replica stopping rule exactly.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_launch.h"
+#include "sg_layout.h"
+
+namespace sg {
+
+__device__ __forceinline__ uint32_t lat_philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t p0lo = c0 * 0xD2511F53u;
+        const uint32_t p0hi = __umulhi(c0, 0xD2511F53u);
+        const uint32_t p1lo = c2 * 0xCD9E8D57u;
+        const uint32_t p1hi = __umulhi(c2, 0xCD9E8D57u);
+        c0 = p1hi ^ c1 ^ k0;
+        c1 = p1lo;
+        c2 = p0hi ^ c3 ^ k1;
+        c3 = p0lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0;
+}
+
+__device__ __forceinline__ int lat_rng_bit(uint64_t seed, uint32_t site, uint32_t sweep, uint32_t id, uint32_t r)
+{
+    return (int)(lat_philox_word0(site, sweep, id, r, (uint32_t)seed, (uint32_t)(seed >> 32)) & 1u);
+}
+
+__device__ __forceinline__ int jb(uint64_t rec, int k) { return (int)(int8_t)(rec >> (8 * k)); }
+
+// Exact floor(a / d) for a * d < 2^32 with m = floor(2^32 / d) + 1 (then
+// a*m / 2^32 - a/d < a/2^32 < 1/d, so the floor is unchanged); d = 1 is
+// encoded as m = 0.
+__device__ __forceinline__ uint32_t fdiv(uint32_t a, uint32_t m) { return m ? __umulhi(a, m) : a; }
+__host__ __device__ __forceinline__ uint32_t fdiv_magic(uint32_t d)
+{
+    return d <= 1 ? 0u : (uint32_t)((0x100000000ull / d) + 1);
+}
+
+__device__ __forceinline__ int wrapi(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+constexpr int kLatThreads = 1024;
+constexpr int kLatWaves = kLatThreads / 64;
+
+// Per-thread site list entry: box index (bits 0..19), halo depth (bits
+// 20..27: distance to the nearest box face over the axes that have a halo),
+// valid flag (bit 28).
+constexpr int kSiteValid = 1 << 28;
+__device__ __forceinline__ int site_b(int pk) { return pk & 0xFFFFF; }
+__device__ __forceinline__ int site_depth(int pk) { return (pk >> 20) & 0xFF; }
+
+template <int D, bool TIE, int NS>
+__global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, TileGeom tg, int8_t* __restrict__ canon,
+                                                               int64_t stride, int8_t* __restrict__ G0,
+                                                               int8_t* __restrict__ G1, uint32_t* __restrict__ flags,
+                                                               uint32_t* __restrict__ err, RepState* __restrict__ rs,
+                                                               int64_t* __restrict__ acc, int nslots, int T,
+                                                               uint64_t seed)
+{
+    extern __shared__ uint64_t lds64[];
+    const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
+    const int tile = blockIdx.x % ntiles;
+    const int r = blockIdx.x / ntiles;
+    const int tid = threadIdx.x;
+    const int L0 = Lt.L[0], L1 = Lt.L[1], L2 = Lt.L[2];
+    const int n = Lt.n, half = n / 2;
+    const int k = tg.k;
+    int tc[3];
+    tc[0] = tile / (tg.P[1] * tg.P[2]);
+    tc[1] = (tile / tg.P[2]) % tg.P[1];
+    tc[2] = tile % tg.P[2];
+    int X[3], hk[3], B[3], o[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int La = Lt.L[a];
+        const int st = (int)((int64_t)tc[a] * La / tg.P[a]);
+        X[a] = (int)((int64_t)(tc[a] + 1) * La / tg.P[a]) - st;
+        hk[a] = (D == 2 && a == 0) ? 0 : k;
+        B[a] = X[a] + 2 * hk[a];
+        o[a] = st - hk[a];
+    }
+    const int par0 = (((o[0] % 2) + (o[1] % 2) + (o[2] % 2) + Lt.c0) % 2 + 2) % 2;
+    const int V = B[0] * B[1] * B[2];
+    uint64_t* rec = lds64;                                  // V coupling records
+    uint16_t* tieq = reinterpret_cast<uint16_t*>(lds64 + V);  // tie queue: box index | interior << 15
+    int8_t* s = reinterpret_cast<int8_t*>(tieq + ((V / 2 + 1 + 3) & ~3));  // V spins
+    __shared__ int ntie;
+    int8_t* cs = canon + (int64_t)r * stride;
+    int8_t* g0 = G0 + (int64_t)r * n;
+    int8_t* g1 = G1 + (int64_t)r * n;
+    uint32_t* fl = flags + (int64_t)r * ntiles;
+    const uint32_t base = (uint32_t)rs[r].sweeps;
+
+    // ---- per-thread site lists, one per colour (computed once)
+    const int W = (B[2] + 1) >> 1;
+    const int rows = B[0] * B[1];
+    const uint32_t mW = fdiv_magic((uint32_t)W), mB1 = fdiv_magic((uint32_t)B[1]);
+    const uint32_t mB2 = fdiv_magic((uint32_t)B[2]);
+    // global site of box index b
+    auto gsite = [&](int b) -> int {
+        const int q = (int)fdiv((uint32_t)b, mB2);
+        const int z = b - q * B[2];
+        const int x = (int)fdiv((uint32_t)q, mB1);
+        const int y = q - x * B[1];
+        return (wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1)) * L2 + wrapi(o[2] + z, L2);
+    };
+    int pk0[NS], pk1[NS];
+    auto build = [&](int c, int (&pk)[NS]) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int i = tid + u * kLatThreads;
+            pk[u] = 0;
+            if (i < rows * W) {
+                const int row = (int)fdiv((uint32_t)i, mW);
+                const int j = i - row * W;
+                const int x = (int)fdiv((uint32_t)row, mB1);
+                const int y = row - x * B[1];
+                const int z = ((c - par0 - x - y) & 1) + 2 * j;
+                if (z < B[2]) {
+                    int dep = 255;
+                    if (hk[0]) dep = min(dep, min(x, B[0] - 1 - x));
+                    dep = min(dep, min(y, B[1] - 1 - y));
+                    dep = min(dep, min(z, B[2] - 1 - z));
+                    const int g = (wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1)) * L2 + wrapi(o[2] + z, L2);
+                    pk[u] = (row * B[2] + z) | (dep << 20) | kSiteValid;
+                    rec[row * B[2] + z] = Lt.rec[g];
+                }
+            }
+        }
+    };
+    build(0, pk0);
+    build(1, pk1);
+    if (tid == 0) ntie = 0;
+    // initial spins (internal order: colour * n/2 + g/2)
+    {
+        int8_t v0[NS], v1[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            v0[u] = (pk0[u] & kSiteValid) ? cs[(gsite(site_b(pk0[u])) >> 1)] : 0;
+            v1[u] = (pk1[u] & kSiteValid) ? cs[half + (gsite(site_b(pk1[u])) >> 1)] : 0;
+        }
+        // colour of the list's sites is the list index (c = 0: first half of the internal order)
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            if (pk0[u] & kSiteValid) s[site_b(pk0[u])] = v0[u];
+            if (pk1[u] & kSiteValid) s[site_b(pk1[u])] = v1[u];
+        }
+    }
+    __syncthreads();
+
+    const int BZ = B[2], BYZ = B[1] * B[2];
+    const int P_total = 2 * T;
+    long long dE = 0;
+    int nflip = 0;
+    bool failed = false;
+
+    // Moves with dE == 0 under GREEDY_TIE need an RNG draw; they are queued
+    // and drawn after the pass over the colour, compacted over all lanes.
+    auto phase = [&](const int (&pk)[NS], int q) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            int p = pk[u];
+            // Opaque per phase: stops the compiler from hoisting every site's
+            // addresses out of the phase loop and keeping them all live.
+            asm volatile("" : "+v"(p));
+            if ((p & kSiteValid) && site_depth(p) > q) {
+                const int b = site_b(p);
+                const uint64_t c = rec[b];
+                int f = jb(c, 6) + jb(c, 2) * s[b + BZ] + jb(c, 3) * s[b - BZ] + jb(c, 4) * s[b + 1] +
+                        jb(c, 5) * s[b - 1];
+                if (D == 3) f += jb(c, 0) * s[b + BYZ] + jb(c, 1) * s[b - BYZ];
+                const int si = s[b];
+                const int d = 2 * si * f;
+                const bool flip = d < 0;
+                if (TIE && d == 0) {
+                    const int slot = atomicAdd(&ntie, 1);
+                    tieq[slot] = (uint16_t)(b | ((site_depth(p) >= k) << 15));
+                }
+                if (flip) {
+                    s[b] = (int8_t)(-si);
+                    if (site_depth(p) >= k) {
+                        dE += d;
+                        ++nflip;
+                    }
+                }
+            }
+            // keep one site's loads live at a time (the unrolled list would
+            // otherwise be scheduled all at once and spill)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    for (int e = 0; e * k < P_total; ++e) {
+        const int nq = min(k, P_total - e * k);
+        for (int q = 0; q < nq; ++q) {
+            const int p = e * k + q;
+            const uint32_t sweep = base + (uint32_t)(p >> 1);
+            if (p & 1) phase(pk1, q);
+            else phase(pk0, q);
+            if (TIE) {
+                __syncthreads();
+                const int nt = ntie;
+                for (int i = tid; i < nt; i += kLatThreads) {
+                    const int e2 = tieq[i];
+                    const int b = e2 & 0x7FFF;
+                    if (lat_rng_bit(seed, (uint32_t)gsite(b), sweep, Lt.instance_id, (uint32_t)r)) {
+                        s[b] = (int8_t)(-s[b]);
+                        nflip += e2 >> 15;
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) ntie = 0;
+            }
+            __syncthreads();
+        }
+        // ---- exchange: publish the interior, signal, wait for neighbours, read the halo
+        int8_t* gw = (e & 1) ? g1 : g0;
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            if ((pk0[u] & kSiteValid) && site_depth(pk0[u]) >= k)
+                __hip_atomic_store(gw + gsite(site_b(pk0[u])), s[site_b(pk0[u])], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if ((pk1[u] & kSiteValid) && site_depth(pk1[u]) >= k)
+                __hip_atomic_store(gw + gsite(site_b(pk1[u])), s[site_b(pk1[u])], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(fl + tile, (uint32_t)(e + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid < 27) {
+            const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+            const bool used = !(dx == 0 && dy == 0 && dz == 0) && !(D == 2 && dx != 0);
+            if (used) {
+                const int nx = (tc[0] + dx + tg.P[0]) % tg.P[0];
+                const int ny = (tc[1] + dy + tg.P[1]) % tg.P[1];
+                const int nz = (tc[2] + dz + tg.P[2]) % tg.P[2];
+                const int nb = (nx * tg.P[1] + ny) * tg.P[2] + nz;
+                uint32_t spins_left = 1u << 26;
+                while (__hip_atomic_load(fl + nb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)(e + 1)) {
+                    if (--spins_left == 0 ||
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        failed = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        failed = __syncthreads_or(failed);
+        if (failed) break;
+        if ((e + 1) * k < P_total) {
+            int8_t v0[NS], v1[NS];
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                v0[u] = ((pk0[u] & kSiteValid) && site_depth(pk0[u]) < k)
+                            ? __hip_atomic_load(gw + gsite(site_b(pk0[u])), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : (int8_t)0;
+                v1[u] = ((pk1[u] & kSiteValid) && site_depth(pk1[u]) < k)
+                            ? __hip_atomic_load(gw + gsite(site_b(pk1[u])), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : (int8_t)0;
+            }
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                if ((pk0[u] & kSiteValid) && site_depth(pk0[u]) < k) s[site_b(pk0[u])] = v0[u];
+                if ((pk1[u] & kSiteValid) && site_depth(pk1[u]) < k) s[site_b(pk1[u])] = v1[u];
+            }
+            __syncthreads();
+        }
+    }
+    // write the interior back in internal order and fold the counters
+    if (!failed) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            if ((pk0[u] & kSiteValid) && site_depth(pk0[u]) >= k) cs[gsite(site_b(pk0[u])) >> 1] = s[site_b(pk0[u])];
+            if ((pk1[u] & kSiteValid) && site_depth(pk1[u]) >= k)
+                cs[half + (gsite(site_b(pk1[u])) >> 1)] = s[site_b(pk1[u])];
+        }
+    }
+    long long nf = nflip;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        dE += __shfl_xor(dE, off, 64);
+        nf += __shfl_xor(nf, off, 64);
+    }
+    __shared__ long long pd[kLatWaves], pf[kLatWaves];
+    if ((tid & 63) == 0) {
+        pd[tid >> 6] = dE;
+        pf[tid >> 6] = nf;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long a = 0, b2 = 0;
+        for (int w = 0; w < kLatWaves; ++w) {
+            a += pd[w];
+            b2 += pf[w];
+        }
+        int64_t* ap = acc + 2 * ((int64_t)r * nslots + tile);
+        ap[0] += a;
+        ap[1] += b2;
+    }
+}
+
+// Whole lattice of replica r = blockIdx.x in one workgroup (spins in LDS,
+// records read through the cache).  until_conv: stop after the first sweep
+// without flips, recording lastflip as the per-phase kernels do.
+template <int D, bool TIE>
+__global__ __launch_bounds__(kLatThreads) void k_lattice_wg(LatticeDev Lt, int8_t* __restrict__ canon, int64_t stride,
+                                                            RepState* __restrict__ rs, int64_t* __restrict__ acc,
+                                                            int nslots, int T, uint64_t seed, int until_conv)
+{
+    extern __shared__ uint64_t lds64[];
+    int8_t* s = reinterpret_cast<int8_t*>(lds64);
+    const int r = blockIdx.x;
+    RepState* stp = rs + r;
+    if (stp->converged) return;
+    const int tid = threadIdx.x;
+    const int L0 = Lt.L[0], L1 = Lt.L[1], L2 = Lt.L[2];
+    const int n = Lt.n, half = n / 2;
+    int8_t* cs = canon + (int64_t)r * stride;
+    // load: site g <- internal index
+    for (int g = tid; g < n; g += kLatThreads) {
+        const int gz = g % L2, gy = (g / L2) % L1, gx = g / (L1 * L2);
+        s[g] = cs[((gx + gy + gz + Lt.c0) & 1) * half + (g >> 1)];
+    }
+    __shared__ int sweep_flips;
+    if (tid == 0) sweep_flips = 0;
+    __syncthreads();
+    const uint32_t base = (uint32_t)stp->sweeps;
+    const uint32_t mL2 = fdiv_magic((uint32_t)L2), mL1 = fdiv_magic((uint32_t)L1);
+    const int hz = L2 >> 1;  // sites of one colour per z row
+    long long dE = 0, nflip = 0;
+    int lastflip = 0;
+    for (int t = 0; t < T; ++t) {
+        int my = 0;
+        for (int c = 0; c < 2; ++c) {
+            const int total = L0 * L1 * hz;
+            for (int id = tid; id < total; id += kLatThreads) {
+                const uint32_t row = fdiv((uint32_t)id, fdiv_magic((uint32_t)hz));
+                const int j = id - (int)row * hz;
+                const int x = (int)fdiv(row, mL1);
+                const int y = (int)row - x * L1;
+                const int z = ((c - Lt.c0 - x - y) & 1) + 2 * j;
+                const int g = (x * L1 + y) * L2 + z;
+                const uint64_t rc = Lt.rec[g];
+                const int yp = y + 1 == L1 ? 0 : y + 1, ym = y == 0 ? L1 - 1 : y - 1;
+                const int zp = z + 1 == L2 ? 0 : z + 1, zm = z == 0 ? L2 - 1 : z - 1;
+                const int rowb = x * L1;
+                int f = jb(rc, 6) + jb(rc, 2) * s[(rowb + yp) * L2 + z] + jb(rc, 3) * s[(rowb + ym) * L2 + z] +
+                        jb(rc, 4) * s[(rowb + y) * L2 + zp] + jb(rc, 5) * s[(rowb + y) * L2 + zm];
+                if (D == 3) {
+                    const int xp = x + 1 == L0 ? 0 : x + 1, xm = x == 0 ? L0 - 1 : x - 1;
+                    f += jb(rc, 0) * s[(xp * L1 + y) * L2 + z] + jb(rc, 1) * s[(xm * L1 + y) * L2 + z];
+                }
+                const int si = s[g];
+                const int d = 2 * si * f;
+                bool flip = d < 0;
+                if (TIE && d == 0) flip = lat_rng_bit(seed, (uint32_t)g, base + t, Lt.instance_id, (uint32_t)r) != 0;
+                if (flip) {
+                    s[g] = (int8_t)(-si);
+                    dE += d;
+                    ++my;
+                }
+            }
+            __syncthreads();
+        }
+        (void)mL2;
+        nflip += my;
+        if (until_conv) {
+            if (my) atomicAdd(&sweep_flips, my);
+            __syncthreads();
+            const int tot = sweep_flips;
+            __syncthreads();
+            if (tid == 0) sweep_flips = 0;
+            if (tot == 0) break;
+            lastflip = t + 1;
+        }
+    }
+    for (int g = tid; g < n; g += kLatThreads) {
+        const int gz = g % L2, gy = (g / L2) % L1, gx = g / (L1 * L2);
+        cs[((gx + gy + gz + Lt.c0) & 1) * half + (g >> 1)] = s[g];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        dE += __shfl_xor(dE, off, 64);
+        nflip += __shfl_xor(nflip, off, 64);
+    }
+    __shared__ long long pd[kLatWaves], pf[kLatWaves];
+    if ((tid & 63) == 0) {
+        pd[tid >> 6] = dE;
+        pf[tid >> 6] = nflip;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long a = 0, b2 = 0;
+        for (int w = 0; w < kLatWaves; ++w) {
+            a += pd[w];
+            b2 += pf[w];
+        }
+        int64_t* ap = acc + 2 * ((int64_t)r * nslots);
+        ap[0] += a;
+        ap[1] += b2;
+        if (until_conv) stp->lastflip = lastflip;
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+// Box extents of the largest tile and the per-colour site-list length per thread.
+static void tile_box(const TileGeom& tg, const int L[3], int D, int B[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const int mx = (L[a] + tg.P[a] - 1) / tg.P[a];
+        B[a] = mx + ((D == 2 && a == 0) ? 0 : 2 * tg.k);
+    }
+}
+
+size_t lattice_tiles_lds(const TileGeom& tg, const int L[3], int D)
+{
+    int B[3];
+    tile_box(tg, L, D, B);
+    const size_t V = (size_t)B[0] * B[1] * B[2];
+    return V * 8 + ((V / 2 + 1 + 3) & ~(size_t)3) * 2 + V;
+}
+
+int lattice_tiles_ns(const TileGeom& tg, const int L[3], int D)
+{
+    int B[3];
+    tile_box(tg, L, D, B);
+    const long long per_colour = (long long)B[0] * B[1] * ((B[2] + 1) / 2);
+    const long long ns = (per_colour + kLatThreads - 1) / kLatThreads;
+    for (int c : {2, 4, 6, 8, 10})
+        if (ns <= c) return c;
+    return 0;
+}
+
+template <int D, bool TIE, int NS>
+static const void* tiles_kernel() { return (const void*)k_lattice_tiles<D, TIE, NS>; }
+
+static const void* pick_tiles_kernel(int D, bool tie, int ns)
+{
+#define SG_NS_CASE(N)                                                                              \
+    case N:                                                                                        \
+        return D == 3 ? (tie ? tiles_kernel<3, true, N>() : tiles_kernel<3, false, N>())           \
+                      : (tie ? tiles_kernel<2, true, N>() : tiles_kernel<2, false, N>());
+    switch (ns) {
+        SG_NS_CASE(2)
+        SG_NS_CASE(4)
+        SG_NS_CASE(6)
+        SG_NS_CASE(8)
+        SG_NS_CASE(10)
+    default: return nullptr;
+    }
+#undef SG_NS_CASE
+}
+
+hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, int8_t* G0,
+                                int8_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
+                                int nslots, int T, uint64_t seed, int rule, hipStream_t st)
+{
+    const int ns = lattice_tiles_ns(tg, Lt.L, Lt.D);
+    const void* kern = pick_tiles_kernel(Lt.D, rule == 1, ns);
+    if (!kern) return hipErrorInvalidValue;
+    const size_t lds = lattice_tiles_lds(tg, Lt.L, Lt.D);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
+    LatticeDev a0 = Lt;
+    TileGeom a1 = tg;
+    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &flags, &err, &rs, &acc, &nslots, &T, &seed};
+    return hipLaunchCooperativeKernel(kern, dim3(ntiles * R), dim3(kLatThreads), args, (unsigned)lds, st);
+}
+
+// Co-resident workgroups of the tile kernel with this tiling, or 0 when it
+// cannot launch.  A failed probe leaves no error behind for later calls.
+int lattice_tiles_max_blocks(const TileGeom& tg, const int L[3], int D)
+{
+    const int ns = lattice_tiles_ns(tg, L, D);
+    const void* kern = pick_tiles_kernel(D, true, ns);
+    if (!kern) return 0;
+    const size_t lds = lattice_tiles_lds(tg, L, D);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kLatThreads, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
+                             int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st)
+{
+    const size_t lds = ((size_t)Lt.n + 7) / 8 * 8;
+    const bool tie = rule == 1;
+    const void* kern;
+    if (Lt.D == 3) kern = tie ? (const void*)k_lattice_wg<3, true> : (const void*)k_lattice_wg<3, false>;
+    else kern = tie ? (const void*)k_lattice_wg<2, true> : (const void*)k_lattice_wg<2, false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (Lt.D == 3) {
+        if (tie)
+            hipLaunchKernelGGL((k_lattice_wg<3, true>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs, acc,
+                               nslots, T, seed, until_conv);
+        else
+            hipLaunchKernelGGL((k_lattice_wg<3, false>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs,
+                               acc, nslots, T, seed, until_conv);
+    } else {
+        if (tie)
+            hipLaunchKernelGGL((k_lattice_wg<2, true>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs, acc,
+                               nslots, T, seed, until_conv);
+        else
+            hipLaunchKernelGGL((k_lattice_wg<2, false>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs,
+                               acc, nslots, T, seed, until_conv);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -23,4 +23,14 @@ hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, h
 hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_t* restarts, int ninst,
                        int64_t* Eb, int32_t* rb, hipStream_t st);
 
+// lattice schedules (sg_lattice.hip)
+size_t lattice_tiles_lds(const TileGeom& tg, const int L[3], int D);
+int lattice_tiles_ns(const TileGeom& tg, const int L[3], int D);  // 0 if the box is too large
+int lattice_tiles_max_blocks(const TileGeom& tg, const int L[3], int D);
+hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, int8_t* G0,
+                                int8_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
+                                int nslots, int T, uint64_t seed, int rule, hipStream_t st);
+hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
+                             int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
+
 }  // namespace sg

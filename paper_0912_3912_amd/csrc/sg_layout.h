@@ -64,13 +64,21 @@ struct CallStats {
     unsigned long long unconverged;
 };
 
-// Lattice (implicit neighbour) layout for the LDS tile schedule.
+// Lattice (implicit neighbour) layout for the LDS tile schedules.  Sites are
+// (x, y, z), z fastest; 2-D lattices use L[0] = 1.  One 64-bit record per
+// site: bytes 0..5 = J to the +x, -x, +y, -y, +z, -z neighbour, byte 6 = h.
 struct LatticeDev {
-    const int8_t* jb;        // per site: J of the +x, +y, +z bond (3 bytes per site, site-major)
-    const int8_t* h;         // per site field, external (site) order
-    int32_t L[3];            // extents, x slowest; L[2] == 1 in 2-D... see host code
-    int32_t d;               // 2 or 3
-    int32_t c0;              // colour of site 0 (0 or 1)
+    const uint64_t* rec;     // n records, site order
+    int32_t L[3];
+    int32_t D;               // 2 or 3
+    int32_t c0;              // colour of site 0
+    int32_t n;
+    uint32_t instance_id;
+};
+
+struct TileGeom {
+    int32_t P[3];            // tiles per axis
+    int32_t k;               // colour phases per halo exchange (= halo width)
 };
 
 }  // namespace sg

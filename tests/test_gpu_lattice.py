@@ -1,0 +1,99 @@
+"""GPU parity of the lattice schedules (implicit neighbours, LDS-resident):
+the whole-lattice workgroup mode and the co-resident tile mode with halo
+exchanges every k colour phases, against the CPU oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import instances as gen
+from parity import compare, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+GREEDY, TIE = 0, 1
+SCHED_LATTICE = 3
+
+
+def _run(insts, dims, seed, rule, sweeps, uc, tune=None, runs=None):
+    import paper_0912_3912_amd as sg
+    log(f"lattice case: {[i.name for i in insts]} rule={rule} sweeps={runs or sweeps} uc={uc} tune={tune}")
+    h = sg.load_instance(insts, lattice_dims=dims)
+    for k, v in (tune or {}).items():
+        h.tune(k, v)
+    h.bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=rule, max_sweeps=ms, until_converged=uc, schedule=SCHED_LATTICE)
+             for ms in (runs or [sweeps])]
+    assert all(s["schedule_used"] == SCHED_LATTICE for s in stats)
+    states = [oracle_run(i, seed, rule, sweeps, uc, runs) for i in insts]
+    compare(h, insts, states)
+    return h, stats
+
+
+def test_square16_workgroup_mode(gpu):
+    inst = gen.cfg1_square16()
+    _run([inst], [(16, 16)], 7, GREEDY, 10000, True)
+
+
+@pytest.mark.parametrize("rule,uc", [(GREEDY, True), (TIE, False), (TIE, True)])
+def test_cubic_workgroup_mode(gpu, rule, uc):
+    inst = gen.lattice((12, 10, 8), seed=5, h_range=(-2, 2), restarts=5)
+    _run([inst], [(12, 10, 8)], 3, rule, 40, uc)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("rule", [GREEDY, TIE])
+def test_cubic_tile_mode_halo_widths(gpu, k, rule):
+    inst = gen.lattice((20, 16, 24), seed=k, h_range=(-2, 2), restarts=2)
+    h, _ = _run([inst], [(20, 16, 24)], 11, rule, 17, False,
+                tune={"lattice_wg_max_n": 0, "lattice_k": k})
+    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')}")
+    assert h.query("last_tile_k") == k
+
+
+@pytest.mark.parametrize("max_tiles", [1, 2, 3, 8, 27])
+def test_cubic_tile_mode_tilings(gpu, max_tiles):
+    """Few tiles: periodic self-neighbours (one or two tiles along an axis)
+    and uneven tile extents."""
+    inst = gen.lattice((14, 18, 10), seed=2, h_range=(-2, 2))
+    h, _ = _run([inst], [(14, 18, 10)], 5, TIE, 9, False,
+                tune={"lattice_wg_max_n": 0, "lattice_k": 3, "lattice_max_tiles": max_tiles})
+    log(f"tiles={h.query('last_tiles')}")
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_square_tile_mode(gpu, k):
+    inst = gen.lattice((64, 48), seed=3, h_range=(-1, 1), j_values=(-2, -1, 1, 2), restarts=2)
+    _run([inst], [(64, 48)], 9, TIE, 13, False, tune={"lattice_wg_max_n": 0, "lattice_k": k})
+
+
+def test_tile_mode_resume(gpu):
+    inst = gen.lattice((16, 16, 16), seed=8, h_range=(-2, 2))
+    _run([inst], [(16, 16, 16)], 4, TIE, 0, False, tune={"lattice_wg_max_n": 0, "lattice_k": 4},
+         runs=[3, 5, 1, 0, 6])
+
+
+def test_tile_mode_refuses_until_converged(gpu):
+    import paper_0912_3912_amd as sg
+    inst = gen.lattice((16, 16, 16), seed=8, h_range=(-2, 2))
+    h = sg.load_instance([inst], lattice_dims=[(16, 16, 16)]).tune("lattice_wg_max_n", 0).bind()
+    h.init_spins(1)
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1, until_converged=True, schedule=SCHED_LATTICE)
+    assert e.value.status == sg.SG_EINVAL
+    # AUTO falls back to a schedule that supports the stopping rule
+    st = h.run_sweeps(seed=1, until_converged=True)
+    assert st["schedule_used"] != SCHED_LATTICE
+
+
+def test_mixed_lattice_batch(gpu):
+    insts = [gen.lattice((8, 8), seed=1, restarts=3, instance_id=1),
+             gen.lattice((6, 6, 6), seed=2, h_range=(-2, 2), restarts=2, instance_id=2)]
+    _run(insts, [(8, 8), (6, 6, 6)], 21, GREEDY, 100, True)
+
+
+def test_cubic100_full_tile_mode(gpu):
+    """The 10^6-spin workload in the launch configuration the benchmark
+    times (tile mode, default tiling), 1000 GREEDY_TIE sweeps."""
+    inst = gen.cfg2_cubic100()
+    h, st = _run([inst], [(100, 100, 100)], 7, TIE, 1000, False)
+    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')} kernel_ms={st[0]['kernel_ms']:.2f}")
