@@ -223,11 +223,22 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        tile schedule (1..16, default 4)
  *   "lattice_max_tiles"  cap on tiles per replica (0 = as many as fit)
  *   "lattice_wg_max_n"   largest lattice run with one workgroup per replica
+ *   "block_rg"           restarts per workgroup of the block schedule
+ *                        (64, 128, 256; 0 = largest that fits LDS)
+ *   "block_min_restarts" SG_SCHED_AUTO uses the block schedule for instances
+ *                        with at least this many restarts (default 32)
+ *   "queue_wave_max_n"   queue items with at most this many spins run one per
+ *                        wavefront, larger ones on a whole workgroup (4096)
+ *   "queue_grid"         workgroups of the persistent queue launch (0 = all
+ *                        that fit co-resident)
+ *   "queue_min_items"    SG_SCHED_AUTO uses the queue schedule when the
+ *                        handle has at least this many queue items (32)
  * Unknown key or value out of range: SG_EINVAL. */
 sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 
 /* Read a knob, or one of "last_tiles" (Px*10^6 + Py*10^3 + Pz of the last
- * lattice tile launch), "last_tile_k", "total_replicas", "instances". */
+ * lattice tile launch), "last_tile_k", "last_queue_grid", "total_replicas",
+ * "instances". */
 sg_status sg_query(sg_handle h, const char* key, int64_t* value);
 
 /* Release the handle (not the caller's device memory).  NULL is allowed. */

@@ -1,0 +1,467 @@
+// sg_batch.hip -- batched schedules: many instances and restarts of uneven
+// size in one launch, each replica run to its own stopping point.
+//
+// k_block (one workgroup per instance and group of restarts): the
+// instance's sliced couplings, its fields and the spins of up to 256
+// restarts sit in LDS.  Spins are stored [spin][restart], so the 64 lanes of
+// a wavefront are 64 restarts of one spin: coupling reads are uniform across
+// the wavefront (LDS broadcast) and spin reads are 64 consecutive bytes.
+//
+// k_queue (persistent): workgroups take (instance, restart) items from a
+// queue sorted by decreasing size.  Large items run on the whole workgroup
+// (rows of the sliced layout on lanes, couplings streamed from memory, spins
+// in LDS); small items run one per wavefront in a private LDS window, 16 at
+// a time.
+//
+// Both update the replica state and the call totals themselves and follow
+// the stopping rule of the per-phase kernels exactly: with until_converged a
+// replica stops after its first sweep without a flip (that sweep counts).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_launch.h"
+#include "sg_layout.h"
+
+namespace sg {
+
+__device__ __forceinline__ uint32_t bat_philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                     uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t p0lo = c0 * 0xD2511F53u;
+        const uint32_t p0hi = __umulhi(c0, 0xD2511F53u);
+        const uint32_t p1lo = c2 * 0xCD9E8D57u;
+        const uint32_t p1hi = __umulhi(c2, 0xCD9E8D57u);
+        c0 = p1hi ^ c1 ^ k0;
+        c1 = p1lo;
+        c2 = p0hi ^ c3 ^ k1;
+        c3 = p0lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0;
+}
+
+__device__ __forceinline__ int bat_rng_bit(uint64_t seed, uint32_t spin, uint32_t sweep, uint32_t id, uint32_t r)
+{
+    return (int)(bat_philox_word0(spin, sweep, id, r, (uint32_t)seed, (uint32_t)(seed >> 32)) & 1u);
+}
+
+__device__ __forceinline__ int bat_j(uint32_t w) { return (int)(int8_t)(w & 0xffu); }
+
+constexpr int kBatThreads = 1024;
+constexpr int kBatWaves = kBatThreads / 64;
+
+// ---------------------------------------------------------------------------
+// k_block
+
+template <bool TIE>
+__global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict__ tab, const int32_t* __restrict__ ctab,
+                                                       const BlockItem* __restrict__ items, RepState* __restrict__ rs,
+                                                       CallStats* __restrict__ cs, int RG, int T, uint64_t seed,
+                                                       int until_conv)
+{
+    extern __shared__ uint64_t lds64[];
+    const BlockItem it = items[blockIdx.x];
+    const InstTab& Q = tab[it.inst];
+    const InstDev& I = Q.I;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = I.n;
+    const int r0 = it.r0, nr = it.nr;  // restarts [r0, r0 + nr) of the instance
+    const int G = RG / 64;             // replica groups of 64 lanes
+    const int S = kBatWaves / G;       // spin subsets
+    const int g = wave % G, ss = wave / G;
+    const int r_loc = g * 64 + lane;
+    const bool has_r = r_loc < nr;
+    const int r = r0 + r_loc;
+
+    // LDS layout: couplings | triple words a | triple words b | slices | h | colour table | spins [n][RG]
+    const int ew = Q.nbr_words, tw = Q.tri_words, nsl = I.nslices, C = Q.C;
+    uint32_t* l_nbr = reinterpret_cast<uint32_t*>(lds64);
+    uint32_t* l_ta = l_nbr + ew;
+    uint32_t* l_tb = l_ta + tw;
+    Slice* l_sl = reinterpret_cast<Slice*>(l_tb + tw + ((ew + 2 * tw) & 3 ? 4 - ((ew + 2 * tw) & 3) : 0));
+    int8_t* l_h = reinterpret_cast<int8_t*>(l_sl + nsl);
+    int32_t* l_cs = reinterpret_cast<int32_t*>(l_h + ((n + 3) & ~3));
+    int8_t* l_s = reinterpret_cast<int8_t*>(l_cs + C + 1);
+    __shared__ int sw_flips[256];
+    __shared__ int n_active;
+
+    for (int k = tid; k < ew; k += kBatThreads) l_nbr[k] = I.nbr[k];
+    if (I.has_tri)
+        for (int k = tid; k < tw; k += kBatThreads) {
+            l_ta[k] = I.ta[k];
+            l_tb[k] = I.tb[k];
+        }
+    for (int k = tid; k < nsl; k += kBatThreads) l_sl[k] = I.slices[k];
+    for (int k = tid; k < n; k += kBatThreads) l_h[k] = I.h[k];
+    for (int k = tid; k <= C; k += kBatThreads) l_cs[k] = ctab[Q.ctab_off + k];
+    // spins: global [r][i] -> LDS [i][r]
+    for (int k = tid; k < n * RG; k += kBatThreads) {
+        const int rr = k / n, i = k - rr * n;
+        l_s[i * RG + rr] = rr < nr ? Q.spins[(int64_t)(r0 + rr) * Q.spin_stride + i] : (int8_t)1;
+    }
+    // per-replica state held by the lanes of the first spin subset
+    bool active = false;
+    uint32_t base = 0;
+    if (has_r) {
+        active = !rs[Q.rep_base + r].converged;
+        base = (uint32_t)rs[Q.rep_base + r].sweeps;
+    }
+    if (tid == 0) n_active = 0;
+    if (tid < 256) sw_flips[tid] = 0;
+    __syncthreads();
+    if (ss == 0 && active) atomicAdd(&n_active, 1);
+    __syncthreads();
+
+    long long dE = 0;
+    int nflip = 0, performed = 0, lastflip = 0;
+    bool frozen_before = has_r && !active;
+    for (int t = 0; t < T && n_active > 0; ++t) {
+        int my = 0;
+        for (int c = 0; c < C; ++c) {
+            const int s_lo = l_cs[c], s_hi = l_cs[c + 1];
+            for (int sl = s_lo; sl < s_hi; ++sl) {
+                const Slice Sl = l_sl[sl];
+                for (int l = ss; l < Sl.rows; l += S) {
+                    const int i = Sl.row0 + l;
+                    int f = l_h[i];
+                    const uint32_t* pw = l_nbr + Sl.ebase + l;
+                    for (int kk = 0; kk < Sl.ew; ++kk) {
+                        const uint32_t w = pw[kk * kSlice];
+                        f += bat_j(w) * l_s[(w >> 8) * RG + r_loc];
+                    }
+                    if (I.has_tri) {
+                        const uint32_t* pa = l_ta + Sl.tbase + l;
+                        const uint32_t* pb = l_tb + Sl.tbase + l;
+                        for (int kk = 0; kk < Sl.tw; ++kk) {
+                            const uint32_t wa = pa[kk * kSlice];
+                            const uint32_t b = pb[kk * kSlice];
+                            f += bat_j(wa) * l_s[(wa >> 8) * RG + r_loc] * l_s[b * RG + r_loc];
+                        }
+                    }
+                    const int si = l_s[i * RG + r_loc];
+                    const int d = 2 * si * f;
+                    bool flip = d < 0;
+                    if (TIE && d == 0 && active)
+                        flip = bat_rng_bit(seed, I.ext[i], base + t, I.instance_id, (uint32_t)r) != 0;
+                    if (flip && active) {
+                        l_s[i * RG + r_loc] = (int8_t)(-si);
+                        dE += d;
+                        ++my;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // sweep totals per replica over the spin subsets
+        if (my) atomicAdd(&sw_flips[r_loc], my);
+        nflip += my;
+        __syncthreads();
+        if (active) {
+            performed = t + 1;
+            const int tot = sw_flips[r_loc];
+            if (tot) lastflip = t + 1;
+            if (until_conv && tot == 0) {
+                active = false;
+                if (ss == 0) atomicSub(&n_active, 1);
+            }
+        }
+        __syncthreads();
+        if (tid < 256) sw_flips[tid] = 0;
+        __syncthreads();
+    }
+    // fold dE and flips of the spin subsets into subset 0's lanes
+    __shared__ long long red_d[256];
+    __shared__ int red_f[256];
+    if (ss == 0 && tid < 256) {
+        red_d[r_loc] = 0;
+        red_f[r_loc] = 0;
+    }
+    __syncthreads();
+    if (dE) atomicAdd((unsigned long long*)&red_d[r_loc], (unsigned long long)dE);
+    if (nflip) atomicAdd(&red_f[r_loc], nflip);
+    __syncthreads();
+    // spins back: LDS [i][r] -> global [r][i]
+    for (int k = tid; k < n * nr; k += kBatThreads) {
+        const int rr = k / n, i = k - rr * n;
+        Q.spins[(int64_t)(r0 + rr) * Q.spin_stride + i] = l_s[i * RG + rr];
+    }
+    if (ss == 0 && has_r && !frozen_before) {
+        RepState* st = rs + Q.rep_base + r;
+        const long long de = red_d[r_loc];
+        const int nf = red_f[r_loc];
+        st->E += de;
+        st->flips += nf;
+        st->sweeps += performed;
+        st->lastflip = lastflip;
+        const bool conv = until_conv && lastflip < performed;
+        if (conv) st->converged = 1;
+        atomicAdd(&cs->attempts, (unsigned long long)performed * (unsigned long long)n);
+        atomicAdd(&cs->flips, (unsigned long long)nf);
+        atomicMax(&cs->sweeps_max, (unsigned long long)performed);
+        if (until_conv && !conv) atomicAdd(&cs->unconverged, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_queue
+
+// One colour phase of one replica on `nw` wavefronts (wave index w among
+// them): lane = row of a slice, couplings from memory, spins in LDS.
+template <bool TIE>
+__device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __restrict__ slices, int s_lo, int s_hi,
+                                            int8_t* __restrict__ sp, int w, int nw, int lane, uint32_t sweep,
+                                            uint64_t seed, uint32_t r, long long& dE, int& my)
+{
+    for (int sl = s_lo + w; sl < s_hi; sl += nw) {
+        const Slice S = slices[sl];
+        if (lane < S.rows) {
+            const int i = S.row0 + lane;
+            int f = I.h[i];
+            const uint32_t* p = I.nbr + S.ebase + lane;
+            int k = 0;
+            for (; k + 4 <= S.ew; k += 4) {
+                const uint32_t w0 = p[(k + 0) * kSlice], w1 = p[(k + 1) * kSlice];
+                const uint32_t w2 = p[(k + 2) * kSlice], w3 = p[(k + 3) * kSlice];
+                f += bat_j(w0) * sp[w0 >> 8] + bat_j(w1) * sp[w1 >> 8] + bat_j(w2) * sp[w2 >> 8] +
+                     bat_j(w3) * sp[w3 >> 8];
+            }
+            for (; k < S.ew; ++k) {
+                const uint32_t w1 = p[k * kSlice];
+                f += bat_j(w1) * sp[w1 >> 8];
+            }
+            if (I.has_tri) {
+                const uint32_t* pa = I.ta + S.tbase + lane;
+                const uint32_t* pb = I.tb + S.tbase + lane;
+                for (int q = 0; q < S.tw; ++q) {
+                    const uint32_t wa = pa[q * kSlice];
+                    f += bat_j(wa) * sp[wa >> 8] * sp[pb[q * kSlice]];
+                }
+            }
+            const int si = sp[i];
+            const int d = 2 * si * f;
+            bool flip = d < 0;
+            if (TIE && d == 0) flip = bat_rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
+            if (flip) {
+                sp[i] = (int8_t)(-si);
+                dE += d;
+                ++my;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void queue_finish(const InstTab& Q, int r, long long dE, int nflip, int performed,
+                                             int lastflip, int T, int until_conv, RepState* __restrict__ rs,
+                                             CallStats* __restrict__ cs)
+{
+    RepState* st = rs + Q.rep_base + r;
+    st->E += dE;
+    st->flips += nflip;
+    st->sweeps += performed;
+    st->lastflip = lastflip;
+    const bool conv = until_conv && lastflip < performed;
+    if (conv) st->converged = 1;
+    atomicAdd(&cs->attempts, (unsigned long long)performed * (unsigned long long)Q.I.n);
+    atomicAdd(&cs->flips, (unsigned long long)nflip);
+    atomicMax(&cs->sweeps_max, (unsigned long long)performed);
+    if (until_conv && !conv) atomicAdd(&cs->unconverged, 1ull);
+}
+
+template <bool TIE>
+__global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict__ tab, const int32_t* __restrict__ ctab,
+                                                       const QueueItem* __restrict__ items, int n_big, int n_items,
+                                                       uint32_t* __restrict__ counters, int wave_lds,
+                                                       RepState* __restrict__ rs, CallStats* __restrict__ cs, int T,
+                                                       uint64_t seed, int until_conv)
+{
+    extern __shared__ uint64_t lds64[];
+    int8_t* lds = reinterpret_cast<int8_t*>(lds64);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ int s_item;
+    __shared__ int s_flips;
+    // ---- large items: the whole workgroup on one replica
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        const int q = s_item;
+        __syncthreads();
+        if (q >= n_big) break;
+        const QueueItem it = items[q];
+        const InstTab& Q = tab[it.inst];
+        const InstDev& I = Q.I;
+        int8_t* gsp = Q.spins + (int64_t)it.r * Q.spin_stride;
+        const RepState* st0 = rs + Q.rep_base + it.r;
+        const bool frozen = st0->converged != 0;
+        if (frozen) continue;
+        const uint32_t base = (uint32_t)st0->sweeps;
+        for (int k = tid; k < I.n; k += kBatThreads) lds[k] = gsp[k];
+        if (tid == 0) s_flips = 0;
+        __syncthreads();
+        long long dE = 0;
+        int nflip = 0, performed = 0, lastflip = 0;
+        for (int t = 0; t < T; ++t) {
+            int my = 0;
+            for (int c = 0; c < Q.C; ++c) {
+                queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], lds, wave, kBatWaves,
+                                 lane, base + t, seed, (uint32_t)it.r, dE, my);
+                __syncthreads();
+            }
+            nflip += my;
+            performed = t + 1;
+            int wsum = my;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+            if (lane == 0 && wsum) atomicAdd(&s_flips, wsum);
+            __syncthreads();
+            const int tot = s_flips;
+            __syncthreads();
+            if (tid == 0) s_flips = 0;
+            if (tot) lastflip = t + 1;
+            if (until_conv && tot == 0) break;
+        }
+        for (int k = tid; k < I.n; k += kBatThreads) gsp[k] = lds[k];
+        // fold the workgroup's dE and flips
+        long long wd = dE;
+        int wf = nflip;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            wd += __shfl_xor(wd, off, 64);
+            wf += __shfl_xor(wf, off, 64);
+        }
+        __shared__ long long pd[kBatWaves];
+        __shared__ int pf[kBatWaves];
+        if (lane == 0) {
+            pd[wave] = wd;
+            pf[wave] = wf;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            long long a = 0;
+            int b = 0;
+            for (int w = 0; w < kBatWaves; ++w) {
+                a += pd[w];
+                b += pf[w];
+            }
+            queue_finish(Q, it.r, a, b, performed, lastflip, T, until_conv, rs, cs);
+        }
+        __syncthreads();
+    }
+    // ---- small items: one wavefront per replica, 16 at a time
+    int8_t* wl = lds + wave * wave_lds;
+    for (;;) {
+        if (tid == 0) s_item = n_big + (int)atomicAdd(&counters[1], (unsigned)kBatWaves);
+        __syncthreads();
+        const int q0 = s_item;
+        __syncthreads();
+        if (q0 >= n_items) break;
+        const int q = q0 + wave;
+        if (q < n_items) {
+            const QueueItem it = items[q];
+            const InstTab& Q = tab[it.inst];
+            const InstDev& I = Q.I;
+            int8_t* gsp = Q.spins + (int64_t)it.r * Q.spin_stride;
+            const RepState* st0 = rs + Q.rep_base + it.r;
+            if (!st0->converged) {
+                const uint32_t base = (uint32_t)st0->sweeps;
+                for (int k = lane; k < I.n; k += 64) wl[k] = gsp[k];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                long long dE = 0;
+                int nflip = 0, performed = 0, lastflip = 0;
+                for (int t = 0; t < T; ++t) {
+                    int my = 0;
+                    for (int c = 0; c < Q.C; ++c) {
+                        queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], wl, 0, 1, lane,
+                                         base + t, seed, (uint32_t)it.r, dE, my);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    nflip += my;
+                    performed = t + 1;
+                    int tot = my;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+                    if (tot) lastflip = t + 1;
+                    if (until_conv && tot == 0) break;
+                }
+                for (int k = lane; k < I.n; k += 64) gsp[k] = wl[k];
+                long long wd = dE;
+                int wf = nflip;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    wd += __shfl_xor(wd, off, 64);
+                    wf += __shfl_xor(wf, off, 64);
+                }
+                if (lane == 0) queue_finish(Q, it.r, wd, wf, performed, lastflip, T, until_conv, rs, cs);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, int RG)
+{
+    size_t b = (size_t)nbr_words * 4 + (size_t)tri_words * 8;
+    b = (b + 15) / 16 * 16;
+    b += (size_t)nslices * sizeof(Slice);
+    b += (size_t)((n + 3) & ~3);
+    b += (size_t)(C + 1) * 4;
+    b += (size_t)n * RG;
+    return (b + 15) / 16 * 16;
+}
+
+hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem* items, int n_items, size_t lds,
+                        RepState* rs, CallStats* cs, int RG, int T, uint64_t seed, int rule, int until_conv,
+                        hipStream_t st)
+{
+    const void* kern = rule == 1 ? (const void*)k_block<true> : (const void*)k_block<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (rule == 1)
+        hipLaunchKernelGGL(k_block<true>, dim3(n_items), dim3(kBatThreads), lds, st, tab, ctab, items, rs, cs, RG, T,
+                           seed, until_conv);
+    else
+        hipLaunchKernelGGL(k_block<false>, dim3(n_items), dim3(kBatThreads), lds, st, tab, ctab, items, rs, cs, RG, T,
+                           seed, until_conv);
+    return hipGetLastError();
+}
+
+int queue_max_blocks(size_t lds)
+{
+    const void* kern = (const void*)k_queue<true>;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatThreads, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
+                        uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
+                        uint64_t seed, int rule, int until_conv, hipStream_t st)
+{
+    const void* kern = rule == 1 ? (const void*)k_queue<true> : (const void*)k_queue<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (rule == 1)
+        hipLaunchKernelGGL(k_queue<true>, dim3(grid), dim3(kBatThreads), lds, st, tab, ctab, items, n_big, n_items,
+                           counters, wave_lds, rs, cs, T, seed, until_conv);
+    else
+        hipLaunchKernelGGL(k_queue<false>, dim3(grid), dim3(kBatThreads), lds, st, tab, ctab, items, n_big, n_items,
+                           counters, wave_lds, rs, cs, T, seed, until_conv);
+    return hipGetLastError();
+}
+
+}  // namespace sg

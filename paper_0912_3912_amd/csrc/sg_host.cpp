@@ -95,12 +95,22 @@ struct sg_ctx {
     int32_t lattice_k = 4;             // phases per halo exchange of the lattice tile schedule
     int32_t lattice_max_tiles = 0;     // 0 = as many as fit co-resident
     int32_t lattice_wg_max_n = 150000; // largest lattice run as one workgroup per replica
+    int32_t block_rg = 0;              // restarts per block workgroup (0 = largest that fits)
+    int32_t block_min_restarts = 32;   // AUTO uses the block schedule from this many restarts
+    int32_t queue_wave_max_n = 4096;   // queue items up to this size run one per wavefront
+    int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
+    int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
+    uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
+    int64_t n_block_item_cap = 0, ctab_len = 0;
+    std::vector<sg::BlockItem> h_bitems;
+    std::vector<sg::QueueItem> h_qitems;
     uint8_t* dev = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false;
     std::vector<uint8_t> started;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t last_tiles[4] = {0, 0, 0, 0};  // tiling of the last lattice tile launch
+    int32_t last_queue_grid = 0;
 
     template <class T>
     T* at(uint64_t off) const { return reinterpret_cast<T*>(dev + off); }
@@ -518,6 +528,17 @@ void layout(sg_ctx* H)
     H->off_eout = take((uint64_t)H->total_reps * 8);
     H->off_slots = take((uint64_t)max_slots * 8);
     const uint64_t ni = H->insts.size();
+    H->n_block_item_cap = 0;
+    H->ctab_len = 0;
+    for (const HostInst& q : H->insts) {
+        H->n_block_item_cap += (q.R + 63) / 64;
+        H->ctab_len += q.C + 1;
+    }
+    H->off_tab = take(ni * sizeof(sg::InstTab));
+    H->off_ctab = take((uint64_t)H->ctab_len * 4);
+    H->off_bitems = take((uint64_t)H->n_block_item_cap * sizeof(sg::BlockItem));
+    H->off_qitems = take((uint64_t)H->total_reps * sizeof(sg::QueueItem));
+    H->off_qcnt = take(64);
     H->off_best_E = take(ni * 8);
     H->off_best_r = take(ni * 4);
     H->off_rep_base = take(ni * 8);
@@ -544,12 +565,13 @@ sg_status check_inst(sg_handle H, int32_t inst, int32_t r)
 // ---------------------------------------------------------------------------
 // run driver: one kernel launch per colour phase, instance by instance
 
-sg_status run_phase_schedule(sg_handle H, const sg_run_params* p)
+sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
 {
     hipStream_t st = H->stream;
     sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
     uint32_t* flag = H->at<uint32_t>(H->off_flag);
-    for (const HostInst& q : H->insts) {
+    for (int qi : which) {
+        const HostInst& q = H->insts[qi];
         const sg::InstDev I = H->view(q);
         sg::RepState* rs = H->reps() + q.rep_base;
         int8_t* spins = H->at<int8_t>(q.off_spins);
@@ -638,12 +660,13 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
     return found;
 }
 
-sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p)
+sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
 {
     hipStream_t st = H->stream;
     sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
     uint32_t* err = H->at<uint32_t>(H->off_err);
-    for (const HostInst& q : H->insts) {
+    for (int qi : which) {
+        const HostInst& q = H->insts[qi];
         sg::RepState* rs = H->reps() + q.rep_base;
         int8_t* spins = H->at<int8_t>(q.off_spins);
         int64_t* acc = H->at<int64_t>(q.off_acc);
@@ -683,26 +706,154 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p)
     return SG_OK;
 }
 
-// Schedule a handle can use, or -1.
-int resolve_schedule(const sg_ctx* H, const sg_run_params* p)
+// ---------------------------------------------------------------------------
+// batched schedules
+
+constexpr size_t kLdsBudget = 160 * 1024 - 6 * 1024;  // dynamic LDS left beside the kernels' static arrays
+constexpr int32_t kQueueMaxN = 150000;                  // largest item of the queue schedule (spins in LDS)
+
+// Restarts per block workgroup for instance q (0 if the block schedule cannot hold it).
+int block_rg_for(const sg_ctx* H, const HostInst& q)
 {
-    int sched = p->schedule;
-    bool all_lat = true, all_lat_wg = true;
-    for (const HostInst& q : H->insts) {
-        all_lat = all_lat && q.lat_ok;
-        all_lat_wg = all_lat_wg && q.lat_ok && lattice_wg_fits(H, q);
+    const int want = H->block_rg ? H->block_rg : std::min(256, (q.R + 63) / 64 * 64);
+    for (int rg = want; rg >= 64; rg -= 64) {
+        if (H->block_rg && rg != H->block_rg) break;
+        if (rg != 64 && rg != 128 && rg != 192 && rg != 256) continue;
+        if (16 % (rg / 64)) continue;
+        const size_t lds = sg::block_lds_bytes(q.n, (int)q.nbr.size(), (int)q.ta.size(), (int)q.slices.size(), q.C, rg);
+        if (lds <= kLdsBudget) return rg;
     }
-    if (sched == SG_SCHED_AUTO) {
-        if (all_lat && (all_lat_wg || !p->until_converged)) return SG_SCHED_LATTICE;
-        return SG_SCHED_PHASE;
+    return 0;
+}
+
+sg_status run_block_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
+{
+    if (which.empty()) return SG_OK;
+    hipStream_t st = H->stream;
+    // one launch per distinct restart-group size (the kernel takes it as a parameter)
+    std::vector<int> rgs;
+    for (int qi : which) {
+        const int rg = block_rg_for(H, H->insts[qi]);
+        if (std::find(rgs.begin(), rgs.end(), rg) == rgs.end()) rgs.push_back(rg);
     }
-    if (sched == SG_SCHED_PHASE) return sched;
-    if (sched == SG_SCHED_LATTICE) {
-        if (!all_lat) return -1;
-        if (p->until_converged && !all_lat_wg) return -1;
-        return sched;
+    uint64_t item_off = 0;
+    for (int rg : rgs) {
+        H->h_bitems.clear();
+        size_t lds = 0;
+        for (int qi : which) {
+            const HostInst& q = H->insts[qi];
+            if (block_rg_for(H, q) != rg) continue;
+            for (int r0 = 0; r0 < q.R; r0 += rg) {
+                sg::BlockItem it{};
+                it.inst = qi;
+                it.r0 = r0;
+                it.nr = std::min(rg, q.R - r0);
+                H->h_bitems.push_back(it);
+            }
+            lds = std::max(lds, sg::block_lds_bytes(q.n, (int)q.nbr.size(), (int)q.ta.size(), (int)q.slices.size(),
+                                                    q.C, rg));
+        }
+        sg::BlockItem* dit = H->at<sg::BlockItem>(H->off_bitems) + item_off;
+        SG_HIP(hipMemcpyAsync(dit, H->h_bitems.data(), H->h_bitems.size() * sizeof(sg::BlockItem),
+                              hipMemcpyHostToDevice, st),
+               "upload block items");
+        SG_HIP(sg::launch_block(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
+                                (int)H->h_bitems.size(), lds, H->reps(), H->at<sg::CallStats>(H->off_stats), rg,
+                                p->max_sweeps, p->seed, p->rule, p->until_converged, st),
+               "block kernel");
+        SG_HIP(hipStreamSynchronize(st), "stream sync");  // the host item list is reused
+        item_off += H->h_bitems.size();
     }
-    return -1;
+    return SG_OK;
+}
+
+sg_status run_queue_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
+{
+    if (which.empty()) return SG_OK;
+    hipStream_t st = H->stream;
+    // items sorted by decreasing size (longest first), large items before wavefront items
+    H->h_qitems.clear();
+    int nmax_big = 0, nmax_small = 0;
+    for (int qi : which)
+        for (int r = 0; r < H->insts[qi].R; ++r) H->h_qitems.push_back(sg::QueueItem{qi, r});
+    std::stable_sort(H->h_qitems.begin(), H->h_qitems.end(), [&](const sg::QueueItem& a, const sg::QueueItem& b) {
+        return H->insts[a.inst].n > H->insts[b.inst].n;
+    });
+    int n_big = 0;
+    for (const sg::QueueItem& it : H->h_qitems) {
+        const int n = H->insts[it.inst].n;
+        if (n > H->queue_wave_max_n) {
+            ++n_big;
+            nmax_big = std::max(nmax_big, n);
+        } else {
+            nmax_small = std::max(nmax_small, n);
+        }
+    }
+    const int wave_lds = (nmax_small + 15) / 16 * 16;
+    size_t lds = std::max<size_t>((size_t)nmax_big, (size_t)wave_lds * 16);
+    lds = std::max<size_t>((lds + 15) / 16 * 16, 16);
+    if (lds > kLdsBudget) return fail(SG_EINVAL, "queue schedule: an item needs %zu bytes of LDS", lds);
+    int grid = H->queue_grid;
+    if (grid <= 0) grid = sg::queue_max_blocks(lds);
+    if (grid <= 0) grid = 256;
+    grid = std::min<int>(grid, (int)H->h_qitems.size());
+    uint32_t* cnt = H->at<uint32_t>(H->off_qcnt);
+    SG_HIP(sg::launch_fill_u32(cnt, 2, 0u, st), "fill kernel");
+    sg::QueueItem* dit = H->at<sg::QueueItem>(H->off_qitems);
+    SG_HIP(hipMemcpyAsync(dit, H->h_qitems.data(), H->h_qitems.size() * sizeof(sg::QueueItem), hipMemcpyHostToDevice,
+                          st),
+           "upload queue items");
+    SG_HIP(sg::launch_queue(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit, n_big,
+                            (int)H->h_qitems.size(), cnt, wave_lds, lds, grid, H->reps(),
+                            H->at<sg::CallStats>(H->off_stats), p->max_sweeps, p->seed, p->rule, p->until_converged,
+                            st),
+           "queue kernel");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");  // the host item list is reused
+    H->last_queue_grid = grid;
+    return SG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedule choice
+
+bool can_lattice(const sg_ctx* H, const HostInst& q, const sg_run_params* p)
+{
+    return q.lat_ok && (lattice_wg_fits(H, q) || !p->until_converged);
+}
+bool can_block(const sg_ctx* H, const HostInst& q) { return block_rg_for(H, q) > 0; }
+bool can_queue(const HostInst& q) { return q.n <= kQueueMaxN; }
+
+// Per-instance schedule, or -1 when the requested schedule cannot run some instance.
+int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& out)
+{
+    out.assign(H->insts.size(), SG_SCHED_PHASE);
+    const int req = p->schedule;
+    int64_t queue_items = 0;
+    for (const HostInst& q : H->insts)
+        if (!q.lat_ok && can_queue(q) && !(q.R >= H->block_min_restarts && can_block(H, q))) queue_items += q.R;
+    for (size_t k = 0; k < H->insts.size(); ++k) {
+        const HostInst& q = H->insts[k];
+        int s;
+        switch (req) {
+        case SG_SCHED_AUTO:
+            if (can_lattice(H, q, p)) s = SG_SCHED_LATTICE;
+            else if (q.R >= H->block_min_restarts && can_block(H, q)) s = SG_SCHED_BLOCK;
+            else if (can_queue(q) && queue_items >= H->queue_min_items) s = SG_SCHED_QUEUE;
+            else s = SG_SCHED_PHASE;
+            break;
+        case SG_SCHED_PHASE: s = SG_SCHED_PHASE; break;
+        case SG_SCHED_LATTICE: s = can_lattice(H, q, p) ? SG_SCHED_LATTICE : -1; break;
+        case SG_SCHED_BLOCK: s = can_block(H, q) ? SG_SCHED_BLOCK : -1; break;
+        case SG_SCHED_QUEUE: s = can_queue(q) ? SG_SCHED_QUEUE : -1; break;
+        default: s = -1;
+        }
+        if (s < 0) return -1;
+        out[k] = s;
+    }
+    int first = out.empty() ? SG_SCHED_PHASE : out[0];
+    for (int s : out)
+        if (s != first) return SG_SCHED_AUTO;  // mixed
+    return first;
 }
 
 }  // namespace
@@ -808,6 +959,30 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
     }
     SG_HIP(hipMemcpyAsync(H->dev + H->off_rep_base, rb.data(), rb.size() * 8, hipMemcpyHostToDevice, st), "upload");
     SG_HIP(hipMemcpyAsync(H->dev + H->off_restarts, rr.data(), rr.size() * 4, hipMemcpyHostToDevice, st), "upload");
+    {
+        std::vector<sg::InstTab> tab(H->insts.size());
+        std::vector<int32_t> ctab;
+        ctab.reserve((size_t)H->ctab_len);
+        for (size_t k = 0; k < H->insts.size(); ++k) {
+            const HostInst& q = H->insts[k];
+            sg::InstTab& T = tab[k];
+            T.I = H->view(q);
+            T.spins = H->at<int8_t>(q.off_spins);
+            T.spin_stride = (int64_t)q.spin_stride;
+            T.rep_base = q.rep_base;
+            T.C = q.C;
+            T.ctab_off = (int32_t)ctab.size();
+            T.nbr_words = (int32_t)q.nbr.size();
+            T.tri_words = (int32_t)q.ta.size();
+            for (int32_t c = 0; c <= q.C; ++c) ctab.push_back(q.colour_slice[c]);
+        }
+        SG_HIP(hipMemcpyAsync(H->dev + H->off_tab, tab.data(), tab.size() * sizeof(sg::InstTab), hipMemcpyHostToDevice,
+                              st),
+               "upload instance table");
+        SG_HIP(hipMemcpyAsync(H->dev + H->off_ctab, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st),
+               "upload colour table");
+        SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
+    }
     SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
     if (!H->ev0) SG_HIP(hipEventCreate(&H->ev0), "event create");
     if (!H->ev1) SG_HIP(hipEventCreate(&H->ev1), "event create");
@@ -870,18 +1045,27 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
     for (uint8_t v : H->started)
         if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
-    const int sched = resolve_schedule(H, p);
-    if (sched < 0)
+    std::vector<int> assign;
+    const int sched = assign_schedules(H, p, assign);
+    if (sched < 0 && p->schedule != SG_SCHED_AUTO)
         return fail(SG_EINVAL, "schedule %d is not available for this handle (rule %d, until_converged %d)",
                     p->schedule, p->rule, p->until_converged);
     hipStream_t st = H->stream;
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
-    switch (sched) {
-    case SG_SCHED_LATTICE: e = run_lattice_schedule(H, p); break;
-    default: e = run_phase_schedule(H, p); break;
+    for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_PHASE}) {
+        std::vector<int> which;
+        for (size_t k = 0; k < assign.size(); ++k)
+            if (assign[k] == kind) which.push_back((int)k);
+        if (which.empty()) continue;
+        switch (kind) {
+        case SG_SCHED_LATTICE: e = run_lattice_schedule(H, p, which); break;
+        case SG_SCHED_BLOCK: e = run_block_schedule(H, p, which); break;
+        case SG_SCHED_QUEUE: e = run_queue_schedule(H, p, which); break;
+        default: e = run_phase_schedule(H, p, which); break;
+        }
+        if (e != SG_OK) return e;
     }
-    if (e != SG_OK) return e;
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
     sg::CallStats cs;
     SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
@@ -992,6 +1176,22 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "lattice_wg_max_n") {
         if (value < 0 || value > 150000) return fail(SG_EINVAL, "lattice_wg_max_n must be in [0,150000]");
         H->lattice_wg_max_n = (int32_t)value;
+    } else if (k == "block_rg") {
+        if (value != 0 && value != 64 && value != 128 && value != 256)
+            return fail(SG_EINVAL, "block_rg must be 0, 64, 128 or 256");
+        H->block_rg = (int32_t)value;
+    } else if (k == "block_min_restarts") {
+        if (value < 1) return fail(SG_EINVAL, "block_min_restarts must be >= 1");
+        H->block_min_restarts = (int32_t)std::min<int64_t>(value, INT32_MAX);
+    } else if (k == "queue_wave_max_n") {
+        if (value < 0 || value > 9000) return fail(SG_EINVAL, "queue_wave_max_n must be in [0,9000]");
+        H->queue_wave_max_n = (int32_t)value;
+    } else if (k == "queue_grid") {
+        if (value < 0 || value > 65535) return fail(SG_EINVAL, "queue_grid must be in [0,65535]");
+        H->queue_grid = (int32_t)value;
+    } else if (k == "queue_min_items") {
+        if (value < 1) return fail(SG_EINVAL, "queue_min_items must be >= 1");
+        H->queue_min_items = (int32_t)std::min<int64_t>(value, INT32_MAX);
     } else {
         return fail(SG_EINVAL, "sg_tune: unknown key '%s'", key);
     }
@@ -1005,6 +1205,12 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     if (k == "lattice_k") *value = H->lattice_k;
     else if (k == "lattice_max_tiles") *value = H->lattice_max_tiles;
     else if (k == "lattice_wg_max_n") *value = H->lattice_wg_max_n;
+    else if (k == "block_rg") *value = H->block_rg;
+    else if (k == "block_min_restarts") *value = H->block_min_restarts;
+    else if (k == "queue_wave_max_n") *value = H->queue_wave_max_n;
+    else if (k == "queue_grid") *value = H->queue_grid;
+    else if (k == "queue_min_items") *value = H->queue_min_items;
+    else if (k == "last_queue_grid") *value = H->last_queue_grid;
     else if (k == "last_tiles") *value = (int64_t)H->last_tiles[0] * 1000000 + H->last_tiles[1] * 1000 + H->last_tiles[2];
     else if (k == "last_tile_k") *value = H->last_tiles[3];
     else if (k == "total_replicas") *value = H->total_reps;

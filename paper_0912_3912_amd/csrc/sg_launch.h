@@ -33,4 +33,14 @@ hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
                              int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
 
+// batched schedules (sg_batch.hip)
+size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, int RG);
+hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem* items, int n_items, size_t lds,
+                        RepState* rs, CallStats* cs, int RG, int T, uint64_t seed, int rule, int until_conv,
+                        hipStream_t st);
+int queue_max_blocks(size_t lds);
+hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
+                        uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
+                        uint64_t seed, int rule, int until_conv, hipStream_t st);
+
 }  // namespace sg

@@ -81,4 +81,28 @@ struct TileGeom {
     int32_t k;               // colour phases per halo exchange (= halo width)
 };
 
+// Device table entry of one instance for the batched schedules.
+struct InstTab {
+    InstDev I;
+    int8_t* spins;           // replica 0's spins (internal order)
+    int64_t spin_stride;     // bytes between replicas
+    int64_t rep_base;        // index of replica 0 in the handle's replica array
+    int32_t C;               // colours
+    int32_t ctab_off;        // offset of the instance's C+1 colour slice starts in the colour table
+    int32_t nbr_words;       // coupling words of the sliced layout
+    int32_t tri_words;       // hyper-coupling words (each of ta, tb)
+};
+
+struct BlockItem {           // k_block: restarts [r0, r0 + nr) of instance inst
+    int32_t inst;
+    int32_t r0;
+    int32_t nr;
+    int32_t pad;
+};
+
+struct QueueItem {           // k_queue: restart r of instance inst
+    int32_t inst;
+    int32_t r;
+};
+
 }  // namespace sg

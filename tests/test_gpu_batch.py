@@ -1,0 +1,129 @@
+"""GPU parity of the batched schedules (one launch over many instances and
+restarts): the block schedule (restarts of an instance on the lanes of a
+workgroup, everything in LDS), the persistent queue schedule (uneven
+instances, workgroup or wavefront per item) and mixed handles under
+SG_SCHED_AUTO, all bit-exact against the CPU oracle."""
+import numpy as np
+import pytest
+
+import instances as gen
+from parity import compare, expected_stats, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+GREEDY, TIE = 0, 1
+SCHED_AUTO, SCHED_PHASE, SCHED_BLOCK, SCHED_QUEUE = -1, 0, 4, 5
+
+
+def _run(insts, seed, rule, sweeps, uc, schedule, tune=None, runs=None, expect_sched=None, dims=None):
+    import paper_0912_3912_amd as sg
+    log(f"batch case: {len(insts)} instances ({insts[0].name}..) rule={rule} sweeps={runs or sweeps} uc={uc} "
+        f"schedule={schedule} tune={tune}")
+    h = sg.load_instance(insts, lattice_dims=dims)
+    for k, v in (tune or {}).items():
+        h.tune(k, v)
+    h.bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=rule, max_sweeps=ms, until_converged=uc, schedule=schedule)
+             for ms in (runs or [sweeps])]
+    if expect_sched is not None:
+        assert stats[0]["schedule_used"] == expect_sched, stats[0]
+    states = [oracle_run(i, seed, rule, sweeps, uc, runs, threads=8) for i in insts]
+    compare(h, insts, states)
+    if runs is None:
+        att, fl = expected_stats(insts, [None] * len(insts), states)
+        assert stats[0]["attempts"] == att and stats[0]["flips"] == fl
+        if uc:
+            assert stats[0]["n_unconverged"] == sum(int((s.converged == 0).sum()) for s in states)
+    return h, stats
+
+
+def chimera_batch(count, restarts, seed=3):
+    return gen.cfg3_chimera_batch(count=count, restarts=restarts, seed=seed)
+
+
+@pytest.mark.parametrize("rg", [0, 64, 128, 256])
+def test_block_chimera_restart_groups(gpu, rg):
+    import paper_0912_3912_amd as sg
+    insts = chimera_batch(6, 256)
+    try:
+        _run(insts, 7, GREEDY, 10000, True, SCHED_BLOCK, tune={"block_rg": rg}, expect_sched=SCHED_BLOCK)
+    except sg.SGError as e:
+        # 256 restarts of a 512-spin instance plus its padded couplings exceed LDS
+        assert rg == 256 and e.status == sg.SG_EINVAL, e
+
+
+@pytest.mark.parametrize("R", [1, 33, 64, 100, 200])
+def test_block_ragged_restart_counts(gpu, R):
+    insts = chimera_batch(3, R, seed=R)
+    _run(insts, 5, GREEDY, 10000, True, SCHED_BLOCK)
+
+
+@pytest.mark.parametrize("rule,uc", [(TIE, False), (TIE, True)])
+def test_block_tie_rule(gpu, rule, uc):
+    insts = chimera_batch(4, 96) + [gen.lattice((8, 8), seed=1, restarts=64, instance_id=999)]
+    _run(insts, 9, rule, 25, uc, SCHED_BLOCK)
+
+
+def test_block_resume(gpu):
+    insts = chimera_batch(3, 80)
+    _run(insts, 4, TIE, 0, True, SCHED_BLOCK, runs=[2, 3, 0, 40])
+
+
+def test_block_random_small_with_triples(gpu):
+    insts = [gen.random_small(n, seed=n, p_edge=min(1.0, 8.0 / n), n_triples=n // 2, j_range=(-15, 15),
+                              h_range=(-7, 7), k_range=(-7, 7), instance_id=n, restarts=70)
+             for n in (3, 50, 300, 700)]
+    _run(insts, 2, GREEDY, 10000, True, SCHED_BLOCK)
+
+
+@pytest.mark.parametrize("wave_max", [0, 1000, 4096, 9000])
+def test_queue_uneven_er(gpu, wave_max):
+    sizes = [100, 150, 300, 800, 1500, 4096, 4097, 6000, 9000, 12000, 30000]
+    insts = gen.cfg4_uneven_batch(count=len(sizes), sizes=np.array(sizes))
+    _run(insts, 3, GREEDY, 10000, True, SCHED_QUEUE, tune={"queue_wave_max_n": wave_max},
+         expect_sched=SCHED_QUEUE)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 0])
+def test_queue_grid_sizes(gpu, grid):
+    insts = gen.cfg4_uneven_batch(count=40, seed=11)
+    insts = [i for i in insts if i.n <= 20000]
+    _run(insts, 6, GREEDY, 10000, True, SCHED_QUEUE, tune={"queue_grid": grid})
+
+
+@pytest.mark.parametrize("rule,uc", [(TIE, False), (TIE, True), (GREEDY, False)])
+def test_queue_rules_and_restarts(gpu, rule, uc):
+    insts = [gen.erdos_renyi_triples(n, seed=n, instance_id=n, restarts=3) for n in (120, 2000, 7000)]
+    insts += [gen.random_regular3(5000, seed=1, instance_id=5), gen.chimera(8, 8, seed=2, instance_id=6)]
+    _run(insts, 8, rule, 20, uc, SCHED_QUEUE)
+
+
+def test_queue_resume(gpu):
+    insts = [gen.erdos_renyi_triples(n, seed=n, instance_id=n) for n in (300, 5000, 10000)]
+    _run(insts, 1, GREEDY, 0, True, SCHED_QUEUE, runs=[1, 2, 0, 100])
+
+
+def test_auto_mixed_handle(gpu):
+    """AUTO assigns lattice, block, queue and per-phase schedules per
+    instance inside one call; the results match the oracle replica by replica."""
+    insts = [gen.lattice((8, 8), seed=1, restarts=4, instance_id=1),
+             gen.chimera(4, 4, seed=2, restarts=64, instance_id=2)]
+    insts += [gen.erdos_renyi_triples(n, seed=n, instance_id=100 + k) for k, n in enumerate(range(200, 6200, 150))]
+    insts += [gen.erdos_renyi_triples(200000, seed=9, instance_id=7)]
+    dims = [(8, 8), None] + [None] * (len(insts) - 2)
+    h, st = _run(insts, 12, GREEDY, 10000, True, SCHED_AUTO, dims=dims)
+    assert st[0]["schedule_used"] == SCHED_AUTO  # mixed
+
+
+def test_chimera_4096x256_reduced(gpu):
+    """The batched Chimera workload at 64 of its 4096 instances (all 256
+    restarts each), AUTO schedule."""
+    insts = chimera_batch(64, 256)
+    _run(insts, 7, GREEDY, 10000, True, SCHED_AUTO, expect_sched=SCHED_BLOCK)
+
+
+def test_uneven_er_reduced(gpu):
+    """The uneven Erdos-Renyi workload at 60 of its 2000 instances."""
+    insts = gen.cfg4_uneven_batch(count=60, seed=4)
+    _run(insts, 7, GREEDY, 10000, True, SCHED_AUTO, expect_sched=SCHED_QUEUE)
