@@ -1,14 +1,23 @@
-"""Benchmark: spin-flip attempts per second of the colour-ordered descent on
-one MI355X, with the roofline position of the dominant kernel and the CPU
-oracle timed on the host beside it.
+"""Benchmark: spin-flip attempts per second of colour-ordered single-spin-flip
+descent on one MI355X, the roofline position of the dominant kernel, the
+plain per-phase method on the same GPU, and the CPU oracle timed beside it.
 
-Default workload: the 10^6-spin periodic 100^3 +-J lattice with fields
-h in {-2..2}, checkerboard colouring, one random start, GREEDY_TIE for
-exactly 1000 sweeps (10^9 attempts).  One step = random start + start
-energy + 1000 sweeps + best-of-restarts + energy readout, all on the GPU,
-with the coupling structure already resident in HBM.
+Workloads (--workload):
+  cubic100     (default) 10^6-spin periodic 100^3 +-J lattice, h in {-2..2},
+               checkerboard, one random start, GREEDY_TIE for exactly 1000
+               sweeps (10^9 attempts).  Step = random start + start energy +
+               1000 sweeps + best-of-restarts, all on the GPU, couplings
+               already resident in HBM.
+  square16     16x16 periodic +-J lattice, h = 0, 64 starts, GREEDY until
+               converged.
+  chimera4096  4096 Chimera-like 8x8-cell instances with hyper-couplings,
+               256 restarts each, GREEDY until converged, one batched launch.
+  er2000       2000 Erdos-Renyi instances, n log-uniform in [100, 1e5], mean
+               degree 6, n/2 triples, GREEDY until converged, one launch.
+The default run also measures the Chimera batch against per-instance
+per-phase launches (the plain method) and reports the speedup.
 
-Prints one JSON line (rank 0).  Only one GPU is supported.
+Prints one JSON line.  Only one GPU is supported.
 """
 from __future__ import annotations
 
@@ -22,25 +31,215 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+# Plain (non-packed) int32 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3 T lane-ops/s (the published 157.3 TFLOP/s fp32 vector figure
+# counts an FMA as two operations and packed fp32 as two lanes).
+PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+GREEDY, TIE = 0, 1
+SCHED_AUTO, SCHED_PHASE = -1, 0
+KERNEL_NAME = {0: "k_phase", 3: "k_lattice_tiles", 4: "k_block", 5: "k_queue"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_attempt(kind: str, deg: int = 6, tau: float = 0.0) -> float:
-    """Algorithmic bytes one attempt must move in the layout the kernel reads.
+def int_ops_per_attempt(deg: float, tau: float = 0.0) -> float:
+    """Algorithmic integer operations of one attempt: a multiply and an add
+    per coupling, two multiplies and an add per hyper-coupling, the field
+    add, dE = 2 s f (two multiplies) and the decision compare."""
+    return 2.0 * deg + 3.0 * tau + 1 + 2 + 1
 
-    sliced-CSR: deg coupling words of 4 bytes (24-bit partner | int8 J),
-      2*tau hyper-coupling words of 4 bytes, 1 byte field, 1 byte own spin
-      read + 1 byte write, 1 byte of the other colours' spins (each read once
-      per phase: cache-reuse lower bound); slice metadata (16 B per 64 rows)
-      is below 1 byte.
-    """
-    if kind == "sell":
-        return 4.0 * deg + 8.0 * tau + 1 + 2 + 1
-    raise ValueError(kind)
+
+def sell_bytes_per_attempt(deg: float, tau: float = 0.0, spins_in_lds: bool = False) -> float:
+    """Algorithmic HBM bytes of one attempt in the sliced coupling layout:
+    deg 4-byte coupling words, 2 tau 4-byte hyper-coupling words, the 1-byte
+    field, and (spins in memory) the own spin read and written plus one byte
+    of the other colours' spins (read once per phase, cache-reuse bound)."""
+    b = 4.0 * deg + 8.0 * tau + 1
+    if not spins_in_lds:
+        b += 2 + 1
+    return b
+
+
+def timed(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    outs = [fn() for _ in range(steps)]
+    sync()
+    return (time.perf_counter() - t0) / steps, outs
+
+
+def run_cubic(args, sg, gen, torch):
+    L = args.L
+    inst = gen.cfg2_cubic100(L=L)
+    n = inst.n
+    h = sg.load_instance([inst], lattice_dims=[(L, L, L)]).bind()
+    ws_mb = h.workspace_bytes() / 1e6
+    log(f"cubic{L}: n={n} m={inst.m} workspace={ws_mb:.1f} MB sweeps={args.sweeps}")
+
+    def step(schedule=args.schedule):
+        h.init_spins(args.seed)
+        st = h.run_sweeps(seed=args.seed, rule=TIE, max_sweeps=args.sweeps, until_converged=False,
+                          schedule=schedule)
+        h.best()
+        st["hot_ns"] = h.query("hot_ns")
+        st["hot_launches"] = h.query("hot_launches")
+        return st
+
+    dt, outs = timed(step, args.steps, args.warmup, torch.cuda.synchronize)
+    attempts = n * args.sweeps
+    assert all(o["attempts"] == attempts for o in outs)
+    value = attempts / dt
+    sched = outs[-1]["schedule_used"]
+    hot_us = sum(o["hot_ns"] for o in outs) / len(outs) / 1e3
+    launches = outs[-1]["hot_launches"]
+    E = int(h.energy()[0])
+    log(f"timed {args.steps} steps: {dt * 1e3:.3f} ms/step, hot kernel {hot_us:.1f} us over {launches} launch(es), "
+        f"schedule {sched}, E={E}")
+
+    # the plain method: one launch per colour phase, same workload, same GPU
+    plain_ms, _ = timed(lambda: step(SCHED_PHASE), 1, 1, torch.cuda.synchronize)
+    plain_ms *= 1e3
+    log(f"plain per-phase method: {plain_ms:.3f} ms/step")
+
+    ops = int_ops_per_attempt(6)
+    per_launch_s = hot_us / 1e6 / max(launches, 1)
+    achieved = ops * attempts / max(launches, 1) / per_launch_s / 1e12
+    bpa = sell_bytes_per_attempt(6)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 2), "unit": "TOP/s",
+                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": None,
+                "kernel": KERNEL_NAME.get(sched, str(sched)), "ops_per_attempt": ops,
+                "attempts_per_launch": attempts // max(launches, 1), "launches_per_step": launches,
+                "avg_launch_us": round(hot_us / max(launches, 1), 2),
+                "hbm_equiv": {"bytes_per_attempt": bpa, "GB/s": round(bpa * value / 1e9, 1),
+                              "frac": round(bpa * value / 1e9 / PEAK_HBM_GBS, 4),
+                              "note": "bytes a streaming sliced-CSR sweep moves per attempt, at this attempt rate"}}
+    cpu = None
+    if args.cpu_sweeps > 0:
+        import oracle
+        t1 = time.perf_counter()
+        oracle.run(inst, seed=args.seed, rule=oracle.GREEDY_TIE, max_sweeps=args.cpu_sweeps, until_converged=False,
+                   threads=1)
+        ct = time.perf_counter() - t1
+        cpu = {"value": n * args.cpu_sweeps / ct, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+               "sample": f"cubic{L}, 1 start, {args.cpu_sweeps} of the step's {args.sweeps} GREEDY_TIE sweeps "
+                         f"({n * args.cpu_sweeps:.3g} attempts in {ct:.1f} s, one replica so one core)"}
+        log(f"cpu oracle: {cpu['value']:.3e} attempts/s over {ct:.1f} s")
+    out = {
+        "metric": "spin-flip attempts/s (10^6-spin 3-D +-J lattice, 1000 sweeps)",
+        "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8 spins/couplings, int32 fields, int64 energy", "data": "synthetic",
+        "config": {"workload": f"cubic{L}_pmJ_h2_tie_{args.sweeps}sweeps", "n_spins": n, "bonds": inst.m,
+                   "sweeps": args.sweeps, "restarts": 1, "rule": "GREEDY_TIE", "schedule": sched,
+                   "tiles": h.query("last_tiles"), "halo_k": h.query("last_tile_k"), "energy": E,
+                   "workspace_mb": round(ws_mb, 1)},
+        "plain_method": {"ms_per_step": round(plain_ms, 3), "attempts_per_s": attempts / plain_ms * 1e3,
+                         "speedup": round(plain_ms / (dt * 1e3), 3)},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    h.free()
+    return out
+
+
+def run_chimera(args, sg, gen, torch, count=4096, sample=16):
+    insts = gen.cfg3_chimera_batch(count=count, restarts=256)
+    t0 = time.perf_counter()
+    h = sg.load_instance(insts).bind()
+    log(f"chimera{count}x256: ingest {time.perf_counter() - t0:.1f} s, workspace {h.workspace_bytes() / 1e6:.0f} MB")
+    n = insts[0].n
+    deg = 2 * insts[0].m / n
+    tau = 3 * insts[0].t / n
+
+    def step(schedule=SCHED_AUTO, hh=h):
+        hh.init_spins(args.seed)
+        st = hh.run_sweeps(seed=args.seed, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=schedule)
+        hh.best()
+        st["hot_ns"] = hh.query("hot_ns")
+        st["hot_launches"] = hh.query("hot_launches")
+        return st
+
+    dt, outs = timed(step, args.batch_steps, 1, torch.cuda.synchronize)
+    st = outs[-1]
+    attempts = st["attempts"]
+    hot_us = st["hot_ns"] / 1e3
+    log(f"batched: {dt * 1e3:.2f} ms/step, {attempts:.3g} attempts, sweeps_max {st['sweeps_max']}, "
+        f"schedule {st['schedule_used']}, hot {hot_us:.0f} us")
+    h.free()
+    # per-instance baseline: the plain per-phase method on a sample, one instance at a time
+    hs = sg.load_instance(insts[:sample]).bind()
+    dts, outs_s = timed(lambda: step(SCHED_PHASE, hs), 1, 1, torch.cuda.synchronize)
+    extrap = dts * count / sample
+    log(f"per-instance per-phase: {dts * 1e3:.1f} ms for {sample} instances -> {extrap * 1e3:.0f} ms extrapolated")
+    hs.free()
+    ops = int_ops_per_attempt(deg, tau)
+    ach = ops * attempts / (hot_us / 1e6) / 1e12
+    return {"workload": f"chimera{count}x256_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
+            "attempts": attempts, "schedule": st["schedule_used"],
+            "per_instance_ms": round(extrap * 1e3, 2), "per_instance_sample": sample,
+            "per_instance_extrapolated": True, "speedup": round(extrap / dt, 2),
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(PEAK_INT_TOPS, 2),
+                         "unit": "TOP/s", "frac": round(ach / PEAK_INT_TOPS, 4), "kernel": "k_block",
+                         "ops_per_attempt": round(ops, 2)}}
+
+
+def run_er(args, sg, gen, torch, count=2000):
+    t0 = time.perf_counter()
+    insts = gen.cfg4_uneven_batch(count=count)
+    log(f"er{count}: generated in {time.perf_counter() - t0:.1f} s, sum n = {sum(i.n for i in insts)}")
+    t0 = time.perf_counter()
+    h = sg.load_instance(insts).bind()
+    log(f"er{count}: ingest {time.perf_counter() - t0:.1f} s, workspace {h.workspace_bytes() / 1e6:.0f} MB")
+
+    def step(schedule=SCHED_AUTO):
+        h.init_spins(args.seed)
+        st = h.run_sweeps(seed=args.seed, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=schedule)
+        h.best()
+        st["hot_ns"] = h.query("hot_ns")
+        return st
+
+    dt, outs = timed(step, args.batch_steps, 1, torch.cuda.synchronize)
+    st = outs[-1]
+    dtp, outp = timed(lambda: step(SCHED_PHASE), 1, 0, torch.cuda.synchronize)
+    attempts = st["attempts"]
+    assert outp[-1]["attempts"] == attempts
+    hot_us = st["hot_ns"] / 1e3
+    ntot = sum(i.n for i in insts)
+    deg = sum(2 * i.m for i in insts) / ntot
+    tau = sum(3 * i.t for i in insts) / ntot
+    bpa = sell_bytes_per_attempt(deg, tau, spins_in_lds=True)
+    ach = bpa * attempts / (hot_us / 1e6) / 1e9
+    log(f"batched {dt * 1e3:.2f} ms, per-instance per-phase {dtp * 1e3:.1f} ms, speedup {dtp / dt:.2f}")
+    h.free()
+    return {"workload": f"er{count}_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
+            "attempts": attempts, "schedule": st["schedule_used"], "per_instance_ms": round(dtp * 1e3, 2),
+            "per_instance_extrapolated": False, "speedup": round(dtp / dt, 2),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": "k_queue",
+                         "bytes_per_attempt": round(bpa, 2)}}
+
+
+def run_square(args, sg, gen, torch):
+    inst = gen.cfg1_square16()
+    h = sg.load_instance([inst], lattice_dims=[(16, 16)]).bind()
+
+    def step(schedule=SCHED_AUTO):
+        h.init_spins(args.seed)
+        st = h.run_sweeps(seed=args.seed, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=schedule)
+        h.best()
+        return st
+
+    dt, outs = timed(step, args.steps, args.warmup, torch.cuda.synchronize)
+    dtp, _ = timed(lambda: step(SCHED_PHASE), 3, 1, torch.cuda.synchronize)
+    st = outs[-1]
+    return {"workload": "square16_64starts_greedy", "attempts_per_s": st["attempts"] / dt,
+            "us_per_solve": dt * 1e6, "attempts": st["attempts"], "schedule": st["schedule_used"],
+            "per_phase_us_per_solve": dtp * 1e6, "speedup": round(dtp / dt, 2)}
 
 
 def main():
@@ -48,95 +247,41 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cubic100",
+                    choices=["cubic100", "square16", "chimera4096", "er2000"])
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--L", type=int, default=100)
-    ap.add_argument("--schedule", type=int, default=-1)
+    ap.add_argument("--schedule", type=int, default=SCHED_AUTO)
     ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--cpu-sweeps", type=int, default=500,
-                    help="sweeps of the oracle CPU-baseline sample (0 = skip)")
-    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=1000,
+                    help="sweeps of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true", help="skip the Chimera batch in the default run")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: multi-GPU runs are not supported by this build",
-              file=sys.stderr)
+        print("bench.py runs on exactly one GPU; multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import instances as gen
     import paper_0912_3912_amd as sg
 
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    L = args.L
-    inst = gen.cfg2_cubic100(L=L)
-    n = inst.n
-    h = sg.load_instance([inst], lattice_dims=[(L, L, L)]).bind()
-    ws_mb = h.workspace_bytes() / 1e6
-    log(f"workload cubic{L}: n={n} m={inst.m} workspace={ws_mb:.1f} MB sweeps={args.sweeps}")
-
-    def step():
-        h.init_spins(args.seed)
-        st = h.run_sweeps(seed=args.seed, rule=sg.GREEDY_TIE, max_sweeps=args.sweeps,
-                          until_converged=False, schedule=args.schedule)
-        h.best()
-        return st
-
-    for w in range(args.warmup):
-        st = step()
-        log(f"warmup {w}: kernel_ms={st['kernel_ms']:.3f} schedule={st['schedule_used']}")
-    torch.cuda.synchronize()
-    kms = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        st = step()
-        kms.append(st["kernel_ms"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    attempts = n * args.sweeps
-    value = attempts * args.steps / dt
-    ms_step = dt / args.steps * 1e3
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, sweep kernels {np.mean(kms):.3f} ms")
-    E = int(h.energy()[0])
-
-    # roofline of the dominant kernel (the sweep kernels of this step)
-    bpa = bytes_per_attempt("sell", deg=6)
-    sched = st["schedule_used"]
-    launches = args.sweeps * 2 if sched in (0, 1) else 1
-    kernel_ms = float(np.mean(kms))
-    per_launch_s = kernel_ms / 1e3 / launches
-    achieved = bpa * attempts / launches / per_launch_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": {0: "k_phase", 1: "k_phase (graph)", 2: "k_persistent", 3: "k_lattice"}.get(sched, str(sched)),
-                "bytes_per_attempt": bpa, "launches_per_step": launches,
-                "avg_launch_us": round(per_launch_s * 1e6, 3)}
-
-    cpu = None
-    if args.cpu_sweeps > 0:
-        import oracle
-        t1 = time.perf_counter()
-        ref, _ = oracle.run(inst, seed=args.seed, rule=oracle.GREEDY_TIE, max_sweeps=args.cpu_sweeps,
-                            until_converged=False, threads=1)
-        ct = time.perf_counter() - t1
-        cpu = {"value": n * args.cpu_sweeps / ct, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-               "sample": f"cubic{L}, 1 start, first {args.cpu_sweeps} of {args.sweeps} GREEDY_TIE sweeps "
-                         f"({n * args.cpu_sweeps:.3g} attempts, {ct:.1f} s)"}
-        log(f"cpu oracle: {cpu['value']:.3e} attempts/s over {ct:.1f} s")
-
-    out = {
-        "metric": "spin-flip attempts/s (1M-spin 3-D +-J lattice, 1000 sweeps)",
-        "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int8/int32 (int64 energy)",
-        "data": "synthetic", "config": {"workload": f"cubic{L}_pmJ_h2_tie_{args.sweeps}sweeps",
-                                        "n_spins": n, "bonds": inst.m, "sweeps": args.sweeps,
-                                        "restarts": 1, "rule": "GREEDY_TIE", "schedule": sched,
-                                        "energy": E, "workspace_mb": round(ws_mb, 1)},
-        "roofline": roofline, "cpu_baseline": cpu,
-    }
+    torch.cuda.set_device(0)
+    if args.workload == "cubic100":
+        out = run_cubic(args, sg, gen, torch)
+        if not args.no_batched:
+            out["batched"] = run_chimera(args, sg, gen, torch)
+    else:
+        fn = {"square16": run_square, "chimera4096": run_chimera, "er2000": run_er}[args.workload]
+        r = fn(args, sg, gen, torch)
+        out = {"metric": f"spin-flip attempts/s ({r['workload']})", "value": r["attempts_per_s"],
+               "unit": "attempts/s", "n_gpus": 1, "steps": args.batch_steps, "warmup": 1,
+               "ms_per_step": r.get("ms_per_step", r.get("us_per_solve", 0) / 1e3), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "int8/int32, int64 energy", "data": "synthetic",
+               "config": {"workload": r["workload"]}, "roofline": r.get("roofline"), "cpu_baseline": None,
+               "detail": r}
     print(json.dumps(out), flush=True)
 
 

@@ -238,7 +238,10 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 
 /* Read a knob, or one of "last_tiles" (Px*10^6 + Py*10^3 + Pz of the last
  * lattice tile launch), "last_tile_k", "last_queue_grid", "total_replicas",
- * "instances". */
+ * "instances", "hot_ns" / "hot_launches" (device time, from HIP events on the
+ * bound stream, of the last sg_run_sweeps call's sweep kernel launches: the
+ * single launch of the lattice, block or queue schedule, or the span of the
+ * per-phase launches, and how many launches that span holds). */
 sg_status sg_query(sg_handle h, const char* key, int64_t* value);
 
 /* Release the handle (not the caller's device memory).  NULL is allowed. */

@@ -19,6 +19,7 @@ exact, using +-1 and bounded integer ranges.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional, Sequence
 
@@ -141,7 +142,20 @@ def lattice(dims: Sequence[int], periodic=True, seed=0, j_values=(-1, 1),
                     name=name or "lattice" + "x".join(map(str, dims)))
 
 
+@functools.lru_cache(maxsize=16)
+def _chimera_edges_cached(rows, cols):
+    n, ei, ej = _chimera_edges_build(rows, cols)
+    ei.setflags(write=False)
+    ej.setflags(write=False)
+    return n, ei, ej
+
+
 def chimera_edges(rows=8, cols=8):
+    """Chimera-like grid of K4,4 cells (see _chimera_edges_build)."""
+    return _chimera_edges_cached(int(rows), int(cols))
+
+
+def _chimera_edges_build(rows=8, cols=8):
     """Chimera-like grid of K4,4 cells, open boundary.
 
     Spin index = ((r*cols + c)*8 + side*4 + k).  Inside a cell every side-0
@@ -183,6 +197,7 @@ def chimera(rows=8, cols=8, seed=0, j_range=(-15, 15), h_range=(-7, 7),
     """
     rng = _rng(seed)
     n, ei, ej = chimera_edges(rows, cols)
+    ei, ej = ei.copy(), ej.copy()
     jv = np.array([v for v in range(j_range[0], j_range[1] + 1) if v != 0], np.int32)
     J = jv[rng.integers(0, len(jv), size=ei.shape[0])]
     h = rng.integers(h_range[0], h_range[1] + 1, size=n).astype(np.int32)

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sg_launch.h"
 #include "sg_layout.h"
 
@@ -405,7 +407,98 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// batched start and energy: one block of 256 threads per replica listed in
+// `reps` (handle replica indices); rep_inst maps a replica to its instance.
+
+__global__ __launch_bounds__(256) void k_init_batch(const InstTab* __restrict__ tab, const int32_t* __restrict__ rep_inst,
+                                                    const int64_t* __restrict__ reps, RepState* __restrict__ rs,
+                                                    uint64_t seed)
+{
+    const int64_t g = reps[blockIdx.x];
+    const InstTab& Q = tab[rep_inst[g]];
+    const uint32_t r = (uint32_t)(g - Q.rep_base);
+    int8_t* sp = Q.spins + (int64_t)r * Q.spin_stride;
+    for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x)
+        sp[i] = (int8_t)(bat_rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
+    if (threadIdx.x == 0) {
+        RepState z;
+        z.E = 0; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
+        rs[g] = z;
+    }
+}
+
+// Energy of Sec. II eq. (1) / Sec. VI eq. (5), each edge and triple counted
+// at its smallest internal index; writes rs[g].E (out == NULL) or out[g].
+__global__ __launch_bounds__(256) void k_energy_batch(const InstTab* __restrict__ tab,
+                                                      const int32_t* __restrict__ rep_inst,
+                                                      const int64_t* __restrict__ reps, RepState* __restrict__ rs,
+                                                      int64_t* __restrict__ out)
+{
+    const int64_t g = reps[blockIdx.x];
+    const InstTab& Q = tab[rep_inst[g]];
+    const InstDev& I = Q.I;
+    const int r = (int)(g - Q.rep_base);
+    const int8_t* s = Q.spins + (int64_t)r * Q.spin_stride;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    long long acc = 0;
+    for (int sl = wave; sl < I.nslices; sl += 4) {
+        const Slice S = I.slices[sl];
+        if (lane < S.rows) {
+            const int i = S.row0 + lane;
+            const int si = s[i];
+            int e = I.h[i] * si;
+            const uint32_t* p = I.nbr + S.ebase + lane;
+            for (int k = 0; k < S.ew; ++k) {
+                const uint32_t w = p[k * kSlice];
+                const int j = (int)(w >> 8);
+                if (j > i) e += bat_j(w) * si * s[j];
+            }
+            if (I.has_tri) {
+                const uint32_t* pa = I.ta + S.tbase + lane;
+                const uint32_t* pb = I.tb + S.tbase + lane;
+                for (int k = 0; k < S.tw; ++k) {
+                    const uint32_t wa = pa[k * kSlice];
+                    const int a = (int)(wa >> 8), b = (int)pb[k * kSlice];
+                    if (a > i && b > i) e += bat_j(wa) * si * s[a] * s[b];
+                }
+            }
+            acc += e;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ long long part[4];
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = -(part[0] + part[1] + part[2] + part[3]);
+        if (out) out[g] = t;
+        else rs[g].E = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
+
+hipError_t launch_init_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
+                             RepState* rs, uint64_t seed, hipStream_t st)
+{
+    for (int64_t b0 = 0; b0 < nreps; b0 += (1u << 30)) {
+        const unsigned nb = (unsigned)std::min<int64_t>(nreps - b0, 1u << 30);
+        hipLaunchKernelGGL(k_init_batch, dim3(nb), dim3(256), 0, st, tab, rep_inst, reps + b0, rs, seed);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
+                               RepState* rs, int64_t* out, hipStream_t st)
+{
+    for (int64_t b0 = 0; b0 < nreps; b0 += (1u << 30)) {
+        const unsigned nb = (unsigned)std::min<int64_t>(nreps - b0, 1u << 30);
+        hipLaunchKernelGGL(k_energy_batch, dim3(nb), dim3(256), 0, st, tab, rep_inst, reps + b0, rs, out);
+    }
+    return hipGetLastError();
+}
 
 size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, int RG)
 {

@@ -53,6 +53,7 @@ constexpr int32_t kMaxCoef = 127;
 constexpr int64_t kMaxField = (1 << 23) - 1;
 constexpr int32_t kMaxRestarts = 65535;
 constexpr int32_t kMaxLatticeTiles = 1024;
+constexpr int32_t kBatchInitMaxN = 65536;  // instances below this size start and evaluate in batched launches
 
 struct HostInst {
     int32_t n = 0;
@@ -77,7 +78,7 @@ struct HostInst {
     int32_t lat_D = 0;
     int32_t lat_c0 = 0;
     std::vector<uint64_t> lat_rec;     // per-site coupling record
-    uint64_t off_lat_rec = 0, off_lat_g = 0, off_lat_flags = 0;
+    uint64_t off_lat_rec = 0, off_lat_g = 0, off_lat_flags = 0, lat_g_bytes = 0;
     // workspace offsets (bytes)
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
@@ -101,6 +102,8 @@ struct sg_ctx {
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
+    uint64_t off_rep_inst = 0, off_small_reps = 0;
+    int64_t n_small_reps = 0;                  // replicas of instances below kBatchInitMaxN
     int64_t n_block_item_cap = 0, ctab_len = 0;
     std::vector<sg::BlockItem> h_bitems;
     std::vector<sg::QueueItem> h_qitems;
@@ -109,6 +112,9 @@ struct sg_ctx {
     bool bound = false;
     std::vector<uint8_t> started;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evh0 = nullptr, evh1 = nullptr;  // around the hot kernel(s) of the last schedule run
+    double hot_us = 0.0;                        // their device time, microseconds
+    int32_t hot_launches = 0;                   // launches inside that interval
     int32_t last_tiles[4] = {0, 0, 0, 0};  // tiling of the last lattice tile launch
     int32_t last_queue_grid = 0;
 
@@ -516,7 +522,9 @@ void layout(sg_ctx* H)
         q.off_acc = take((uint64_t)q.R * q.acc_slots * 16);
         if (q.lat_ok) {
             q.off_lat_rec = take((uint64_t)q.n * 8);
-            q.off_lat_g = take((uint64_t)q.n * q.R * 2);
+            // two copies of one word per interior z-row of every tile (z extent >= 4 sites)
+            q.lat_g_bytes = ((uint64_t)q.n / 4 + 4096) * 4 * 2 * q.R;
+            q.off_lat_g = take(q.lat_g_bytes);
             q.off_lat_flags = take((uint64_t)kMaxLatticeTiles * q.R * 4);
         }
         max_slots = std::max<int64_t>(max_slots, (int64_t)q.R * q.nslots);
@@ -539,6 +547,11 @@ void layout(sg_ctx* H)
     H->off_bitems = take((uint64_t)H->n_block_item_cap * sizeof(sg::BlockItem));
     H->off_qitems = take((uint64_t)H->total_reps * sizeof(sg::QueueItem));
     H->off_qcnt = take(64);
+    H->off_rep_inst = take((uint64_t)H->total_reps * 4);
+    H->n_small_reps = 0;
+    for (const HostInst& q : H->insts)
+        if (q.n < kBatchInitMaxN) H->n_small_reps += q.R;
+    H->off_small_reps = take((uint64_t)H->n_small_reps * 8);
     H->off_best_E = take(ni * 8);
     H->off_best_r = take(ni * 4);
     H->off_rep_base = take(ni * 8);
@@ -577,6 +590,10 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
         int8_t* spins = H->at<int8_t>(q.off_spins);
         int64_t* acc = H->at<int64_t>(q.off_acc);
         SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
+        if (qi == which.front()) {
+            SG_HIP(hipEventRecord(H->evh0, st), "event record");
+            H->hot_launches = 0;
+        }
         int T = 0;
         auto sweeps = [&](int from, int to) -> sg_status {
             for (int t = from; t < to; ++t)
@@ -585,6 +602,7 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
                     SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, t,
                                             p->seed, p->rule, p->until_converged, st),
                            "phase kernel");
+                    H->hot_launches++;
                 }
             return SG_OK;
         };
@@ -609,6 +627,7 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
                 seg = std::min(seg * 2, 64);
             }
         }
+        if (qi == which.back()) SG_HIP(hipEventRecord(H->evh1, st), "event record");
         SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st), "end kernel");
     }
     return SG_OK;
@@ -651,6 +670,9 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
                     V *= (q.lat_L[a] + g.P[a] - 1) / g.P[a] + ((a < a0) ? 0 : 2 * k);
                 if (!(V < bestV || (V == bestV && T < bestT))) continue;
                 if (sg::lattice_tiles_ns(g, q.lat_L, q.lat_D) == 0) continue;
+                if ((q.lat_L[2] + p2 - 1) / p2 > 32) continue;  // an interior z-row is one 32-bit word
+                if (q.lat_L[2] / p2 < 4) continue;               // keeps the exchange within its allocation
+                if ((int64_t)sg::lattice_tiles_words(g, q.lat_L) * 8 * q.R > (int64_t)q.lat_g_bytes) continue;
                 if ((int64_t)T * q.R > cap_for(g)) continue;
                 bestV = V;
                 bestT = T;
@@ -675,9 +697,12 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
         const int T = p->max_sweeps;
         if (T > 0) {
             if (lattice_wg_fits(H, q)) {
+                SG_HIP(hipEventRecord(H->evh0, st), "event record");
                 SG_HIP(sg::launch_lattice_wg(Lt, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, T, p->seed,
                                              p->rule, p->until_converged, st),
                        "lattice workgroup kernel");
+                SG_HIP(hipEventRecord(H->evh1, st), "event record");
+                H->hot_launches = 1;
             } else {
                 sg::TileGeom tg{};
                 if (!choose_tiling(H, q, tg))
@@ -686,11 +711,18 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 uint32_t* flags = H->at<uint32_t>(q.off_lat_flags);
                 SG_HIP(sg::launch_fill_u32(flags, (uint64_t)kMaxLatticeTiles * q.R, 0u, st), "fill kernel");
                 SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
-                int8_t* G0 = H->at<int8_t>(q.off_lat_g);
-                int8_t* G1 = G0 + (uint64_t)q.n * q.R;
+                // exchange words: at most n / (smallest z extent) + one row per tile, per copy
+                const int64_t words = sg::lattice_tiles_words(tg, q.lat_L) * q.R;
+                if ((uint64_t)words * 8 > q.lat_g_bytes)
+                    return fail(SG_ERANGE, "lattice tile exchange needs %lld bytes", (long long)words * 8);
+                uint32_t* G0 = H->at<uint32_t>(q.off_lat_g);
+                uint32_t* G1 = G0 + words;
+                SG_HIP(hipEventRecord(H->evh0, st), "event record");
                 SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs, q.R,
                                                 acc, q.acc_slots, T, p->seed, p->rule, st),
                        "lattice tile kernel");
+                SG_HIP(hipEventRecord(H->evh1, st), "event record");
+                H->hot_launches = 1;
                 uint32_t herr = 0;
                 SG_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st), "error flag copy");
                 SG_HIP(hipStreamSynchronize(st), "stream sync");
@@ -757,10 +789,13 @@ sg_status run_block_schedule(sg_handle H, const sg_run_params* p, const std::vec
         SG_HIP(hipMemcpyAsync(dit, H->h_bitems.data(), H->h_bitems.size() * sizeof(sg::BlockItem),
                               hipMemcpyHostToDevice, st),
                "upload block items");
+        SG_HIP(hipEventRecord(H->evh0, st), "event record");
         SG_HIP(sg::launch_block(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
                                 (int)H->h_bitems.size(), lds, H->reps(), H->at<sg::CallStats>(H->off_stats), rg,
                                 p->max_sweeps, p->seed, p->rule, p->until_converged, st),
                "block kernel");
+        SG_HIP(hipEventRecord(H->evh1, st), "event record");
+        H->hot_launches = 1;
         SG_HIP(hipStreamSynchronize(st), "stream sync");  // the host item list is reused
         item_off += H->h_bitems.size();
     }
@@ -803,11 +838,14 @@ sg_status run_queue_schedule(sg_handle H, const sg_run_params* p, const std::vec
     SG_HIP(hipMemcpyAsync(dit, H->h_qitems.data(), H->h_qitems.size() * sizeof(sg::QueueItem), hipMemcpyHostToDevice,
                           st),
            "upload queue items");
+    SG_HIP(hipEventRecord(H->evh0, st), "event record");
+    H->hot_launches = 1;
     SG_HIP(sg::launch_queue(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit, n_big,
                             (int)H->h_qitems.size(), cnt, wave_lds, lds, grid, H->reps(),
                             H->at<sg::CallStats>(H->off_stats), p->max_sweeps, p->seed, p->rule, p->until_converged,
                             st),
            "queue kernel");
+    SG_HIP(hipEventRecord(H->evh1, st), "event record");
     SG_HIP(hipStreamSynchronize(st), "stream sync");  // the host item list is reused
     H->last_queue_grid = grid;
     return SG_OK;
@@ -981,10 +1019,30 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
                "upload instance table");
         SG_HIP(hipMemcpyAsync(H->dev + H->off_ctab, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st),
                "upload colour table");
+        std::vector<int32_t> rep_inst((size_t)H->total_reps);
+        std::vector<int64_t> small;
+        small.reserve((size_t)H->n_small_reps);
+        for (size_t k = 0; k < H->insts.size(); ++k) {
+            const HostInst& q = H->insts[k];
+            for (int32_t r = 0; r < q.R; ++r) {
+                rep_inst[(size_t)(q.rep_base + r)] = (int32_t)k;
+                if (q.n < kBatchInitMaxN) small.push_back(q.rep_base + r);
+            }
+        }
+        SG_HIP(hipMemcpyAsync(H->dev + H->off_rep_inst, rep_inst.data(), rep_inst.size() * 4, hipMemcpyHostToDevice,
+                              st),
+               "upload replica table");
+        if (!small.empty())
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_small_reps, small.data(), small.size() * 8, hipMemcpyHostToDevice,
+                                  st),
+                   "upload replica list");
+        SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
         SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
     }
     SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
     if (!H->ev0) SG_HIP(hipEventCreate(&H->ev0), "event create");
+    if (!H->evh0) SG_HIP(hipEventCreate(&H->evh0), "event create");
+    if (!H->evh1) SG_HIP(hipEventCreate(&H->evh1), "event create");
     if (!H->ev1) SG_HIP(hipEventCreate(&H->ev1), "event create");
     H->bound = true;
     return SG_OK;
@@ -996,6 +1054,7 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
     if (s != SG_OK) return s;
     hipStream_t st = H->stream;
     for (const HostInst& q : H->insts) {
+        if (q.n < kBatchInitMaxN) continue;
         const sg::InstDev I = H->view(q);
         sg::RepState* rs = H->reps() + q.rep_base;
         SG_HIP(sg::launch_init(I, H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, rs, q.R, seed, st),
@@ -1003,6 +1062,13 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
         SG_HIP(sg::launch_energy(I, H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
                                  H->at<int64_t>(H->off_slots), q.nslots, rs, nullptr, st),
                "energy kernel");
+    }
+    if (H->n_small_reps) {
+        const sg::InstTab* tab = H->at<sg::InstTab>(H->off_tab);
+        const int32_t* ri = H->at<int32_t>(H->off_rep_inst);
+        const int64_t* sr = H->at<int64_t>(H->off_small_reps);
+        SG_HIP(sg::launch_init_batch(tab, ri, sr, H->n_small_reps, H->reps(), seed, st), "batched init kernel");
+        SG_HIP(sg::launch_energy_batch(tab, ri, sr, H->n_small_reps, H->reps(), nullptr, st), "batched energy kernel");
     }
     SG_HIP(hipStreamSynchronize(st), "stream sync");
     std::fill(H->started.begin(), H->started.end(), 1);
@@ -1053,6 +1119,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     hipStream_t st = H->stream;
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
+    H->hot_launches = 0;
     for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_PHASE}) {
         std::vector<int> which;
         for (size_t k = 0; k < assign.size(); ++k)
@@ -1072,6 +1139,12 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     SG_HIP(hipStreamSynchronize(st), "stream sync");
     float ms = 0.f;
     SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
+    H->hot_us = 0.0;
+    if (H->hot_launches > 0) {
+        float hms = 0.f;
+        if (hipEventElapsedTime(&hms, H->evh0, H->evh1) == hipSuccess) H->hot_us = hms * 1000.0;
+        else (void)hipGetLastError();
+    }
     if (stats) {
         stats->attempts = (int64_t)cs.attempts;
         stats->flips = (int64_t)cs.flips;
@@ -1097,9 +1170,14 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
     if (recompute) {
         int64_t* eout = H->at<int64_t>(H->off_eout);
         for (const HostInst& q : H->insts)
-            SG_HIP(sg::launch_energy(H->view(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
-                                     H->at<int64_t>(H->off_slots), q.nslots, nullptr, eout + q.rep_base, st),
-                   "energy kernel");
+            if (q.n >= kBatchInitMaxN)
+                SG_HIP(sg::launch_energy(H->view(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
+                                         H->at<int64_t>(H->off_slots), q.nslots, nullptr, eout + q.rep_base, st),
+                       "energy kernel");
+        if (H->n_small_reps)
+            SG_HIP(sg::launch_energy_batch(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_rep_inst),
+                                           H->at<int64_t>(H->off_small_reps), H->n_small_reps, nullptr, eout, st),
+                   "batched energy kernel");
         SG_HIP(hipMemcpyAsync(E, eout, (size_t)H->total_reps * 8, hipMemcpyDeviceToHost, st), "energy copy");
         SG_HIP(hipStreamSynchronize(st), "stream sync");
         return SG_OK;
@@ -1211,6 +1289,8 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "queue_grid") *value = H->queue_grid;
     else if (k == "queue_min_items") *value = H->queue_min_items;
     else if (k == "last_queue_grid") *value = H->last_queue_grid;
+    else if (k == "hot_ns") *value = (int64_t)(H->hot_us * 1000.0);
+    else if (k == "hot_launches") *value = H->hot_launches;
     else if (k == "last_tiles") *value = (int64_t)H->last_tiles[0] * 1000000 + H->last_tiles[1] * 1000 + H->last_tiles[2];
     else if (k == "last_tile_k") *value = H->last_tiles[3];
     else if (k == "total_replicas") *value = H->total_reps;
@@ -1224,6 +1304,8 @@ sg_status sg_free(sg_handle H)
     if (!H) return SG_OK;
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
+    if (H->evh0) (void)hipEventDestroy(H->evh0);
+    if (H->evh1) (void)hipEventDestroy(H->evh1);
     delete H;
     return SG_OK;
 }

@@ -14,11 +14,14 @@
 // after phase q of an epoch only sites at least q+1 layers inside the box are
 // still exact (each update needs its six neighbours from the previous
 // phase), so after k phases exactly the tile interior is exact.  It then
-// publishes its interior, signals an epoch flag, waits for the flags of its
-// (up to 26) neighbouring tiles and reads its new halo.  The exchange buffer
-// alternates between two copies by epoch parity, which removes the
-// write-after-read hazard between neighbours one epoch apart.  Every wait is
-// bounded: on time-out the kernel records an error and every workgroup exits.
+// publishes its interior as one 32-bit word per z-row (bit per spin) with
+// coherent stores, waits for them to complete, signals an epoch flag, waits
+// for the flags of its (up to 26) neighbouring tiles and reads its new halo:
+// at most three aligned word loads per box row, all issued at once.  The exchange buffer alternates between two
+// copies by epoch parity, which removes the write-after-read hazard between
+// neighbours one epoch apart.  Each thread's sites are sorted deepest first,
+// so phase q walks only the sites deeper than q.  Every wait is bounded: on
+// time-out the kernel records an error and every workgroup exits.
 //
 // k_lattice_wg: the whole lattice of one replica in one workgroup (small
 // lattices, many replicas); supports the per-replica stopping rule exactly.
@@ -74,13 +77,14 @@ constexpr int kLatWaves = kLatThreads / 64;
 // 20..27: distance to the nearest box face over the axes that have a halo),
 // valid flag (bit 28).
 constexpr int kSiteValid = 1 << 28;
+constexpr int kMaxDepth = 64;
 __device__ __forceinline__ int site_b(int pk) { return pk & 0xFFFFF; }
 __device__ __forceinline__ int site_depth(int pk) { return (pk >> 20) & 0xFF; }
 
 template <int D, bool TIE, int NS>
 __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, TileGeom tg, int8_t* __restrict__ canon,
-                                                               int64_t stride, int8_t* __restrict__ G0,
-                                                               int8_t* __restrict__ G1, uint32_t* __restrict__ flags,
+                                                               int64_t stride, uint32_t* __restrict__ G0,
+                                                               uint32_t* __restrict__ G1, uint32_t* __restrict__ flags,
                                                                uint32_t* __restrict__ err, RepState* __restrict__ rs,
                                                                int64_t* __restrict__ acc, int nslots, int T,
                                                                uint64_t seed)
@@ -97,34 +101,43 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
     tc[0] = tile / (tg.P[1] * tg.P[2]);
     tc[1] = (tile / tg.P[2]) % tg.P[1];
     tc[2] = tile % tg.P[2];
-    int X[3], hk[3], B[3], o[3];
+    int X[3], hk[3], B[3], o[3], st[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int La = Lt.L[a];
-        const int st = (int)((int64_t)tc[a] * La / tg.P[a]);
-        X[a] = (int)((int64_t)(tc[a] + 1) * La / tg.P[a]) - st;
+        st[a] = (int)((int64_t)tc[a] * La / tg.P[a]);
+        X[a] = (int)((int64_t)(tc[a] + 1) * La / tg.P[a]) - st[a];
         hk[a] = (D == 2 && a == 0) ? 0 : k;
         B[a] = X[a] + 2 * hk[a];
-        o[a] = st - hk[a];
+        o[a] = st[a] - hk[a];
     }
     const int par0 = (((o[0] % 2) + (o[1] % 2) + (o[2] % 2) + Lt.c0) % 2 + 2) % 2;
     const int V = B[0] * B[1] * B[2];
-    uint64_t* rec = lds64;                                  // V coupling records
-    uint16_t* tieq = reinterpret_cast<uint16_t*>(lds64 + V);  // tie queue: box index | interior << 15
+    const int nint_all = X[0] * X[1] * X[2];
+    const uint32_t mX1 = fdiv_magic((uint32_t)X[1]), mX2 = fdiv_magic((uint32_t)X[2]);
+    const int nrow_int = X[0] * X[1], nrow_box = B[0] * B[1];
+    // tile extents along an axis: start of tile t is floor(t L / P)
+    auto tstart = [&](int a, int t) -> int { return (int)((int64_t)t * Lt.L[a] / tg.P[a]); };
+    // z-neighbour tiles' extents (periodic)
+    const int tzm = (tc[2] + tg.P[2] - 1) % tg.P[2], tzp = (tc[2] + 1) % tg.P[2];
+    const int Xzm = tstart(2, tzm + 1) - tstart(2, tzm);
+    uint64_t* rec = lds64;                                           // V coupling records
+    uint16_t* tieq = reinterpret_cast<uint16_t*>(lds64 + V);         // tie queue: box index | interior << 15
     int8_t* s = reinterpret_cast<int8_t*>(tieq + ((V / 2 + 1 + 3) & ~3));  // V spins
+    uint32_t* scratch = reinterpret_cast<uint32_t*>(tieq);           // set-up only: sorted site list
     __shared__ int ntie;
+    __shared__ int hist[kMaxDepth], cursor[kMaxDepth];
+    __shared__ int cnt_gt[2][kMaxDepth];  // sites of a colour deeper than d
+    __shared__ int nsites[2];
     int8_t* cs = canon + (int64_t)r * stride;
-    int8_t* g0 = G0 + (int64_t)r * n;
-    int8_t* g1 = G1 + (int64_t)r * n;
+    // exchange words: tile t owns rows_per_tile words, one per interior z-row
+    const int rows_per_tile = ((L0 + tg.P[0] - 1) / tg.P[0]) * ((L1 + tg.P[1] - 1) / tg.P[1]);
+    uint32_t* g0 = G0 + (int64_t)r * ntiles * rows_per_tile;
+    uint32_t* g1 = G1 + (int64_t)r * ntiles * rows_per_tile;
     uint32_t* fl = flags + (int64_t)r * ntiles;
     const uint32_t base = (uint32_t)rs[r].sweeps;
 
-    // ---- per-thread site lists, one per colour (computed once)
-    const int W = (B[2] + 1) >> 1;
-    const int rows = B[0] * B[1];
-    const uint32_t mW = fdiv_magic((uint32_t)W), mB1 = fdiv_magic((uint32_t)B[1]);
-    const uint32_t mB2 = fdiv_magic((uint32_t)B[2]);
-    // global site of box index b
+    const uint32_t mB1 = fdiv_magic((uint32_t)B[1]), mB2 = fdiv_magic((uint32_t)B[2]);
     auto gsite = [&](int b) -> int {
         const int q = (int)fdiv((uint32_t)b, mB2);
         const int z = b - q * B[2];
@@ -132,42 +145,83 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
         const int y = q - x * B[1];
         return (wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1)) * L2 + wrapi(o[2] + z, L2);
     };
+
+    // ---- per-thread site lists, one per colour, deepest sites first (once)
+    const int W = (B[2] + 1) >> 1;
+    const int rows = B[0] * B[1];
+    const uint32_t mW = fdiv_magic((uint32_t)W);
     int pk0[NS], pk1[NS];
     auto build = [&](int c, int (&pk)[NS]) {
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int i = tid + u * kLatThreads;
-            pk[u] = 0;
-            if (i < rows * W) {
-                const int row = (int)fdiv((uint32_t)i, mW);
-                const int j = i - row * W;
-                const int x = (int)fdiv((uint32_t)row, mB1);
-                const int y = row - x * B[1];
-                const int z = ((c - par0 - x - y) & 1) + 2 * j;
-                if (z < B[2]) {
-                    int dep = 255;
-                    if (hk[0]) dep = min(dep, min(x, B[0] - 1 - x));
-                    dep = min(dep, min(y, B[1] - 1 - y));
-                    dep = min(dep, min(z, B[2] - 1 - z));
-                    const int g = (wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1)) * L2 + wrapi(o[2] + z, L2);
-                    pk[u] = (row * B[2] + z) | (dep << 20) | kSiteValid;
-                    rec[row * B[2] + z] = Lt.rec[g];
-                }
+        // enumerate the colour's box sites (row, j) -> (b, depth)
+        auto site = [&](int i, int& b, int& dep) -> bool {
+            const int row = (int)fdiv((uint32_t)i, mW);
+            const int j = i - row * W;
+            const int x = (int)fdiv((uint32_t)row, mB1);
+            const int y = row - x * B[1];
+            const int z = ((c - par0 - x - y) & 1) + 2 * j;
+            if (z >= B[2]) return false;
+            dep = kMaxDepth - 1;
+            if (hk[0]) dep = min(dep, min(x, B[0] - 1 - x));
+            dep = min(dep, min(y, B[1] - 1 - y));
+            dep = min(dep, min(z, B[2] - 1 - z));
+            b = row * B[2] + z;
+            return true;
+        };
+        for (int d = tid; d < kMaxDepth; d += kLatThreads) {
+            hist[d] = 0;
+            cursor[d] = 0;
+        }
+        __syncthreads();
+        for (int i = tid; i < rows * W; i += kLatThreads) {
+            int b, dep;
+            if (site(i, b, dep)) atomicAdd(&hist[dep], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc2 = 0;
+            for (int d = kMaxDepth - 1; d >= 0; --d) {
+                cnt_gt[c][d] = acc2;  // sites deeper than d
+                acc2 += hist[d];
+            }
+            nsites[c] = acc2;
+        }
+        __syncthreads();
+        for (int i = tid; i < rows * W; i += kLatThreads) {
+            int b, dep;
+            if (site(i, b, dep)) {
+                const int pos = cnt_gt[c][dep] + atomicAdd(&cursor[dep], 1);
+                scratch[pos] = (uint32_t)(b | (dep << 20) | kSiteValid);
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int i = u * kLatThreads + tid;
+            pk[u] = i < nsites[c] ? (int)scratch[i] : 0;
+        }
+        __syncthreads();
     };
     build(0, pk0);
     build(1, pk1);
     if (tid == 0) ntie = 0;
-    // initial spins (internal order: colour * n/2 + g/2)
+    // records and initial spins (internal order: colour * n/2 + g/2)
     {
         int8_t v0[NS], v1[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
-            v0[u] = (pk0[u] & kSiteValid) ? cs[(gsite(site_b(pk0[u])) >> 1)] : 0;
-            v1[u] = (pk1[u] & kSiteValid) ? cs[half + (gsite(site_b(pk1[u])) >> 1)] : 0;
+            v0[u] = 0;
+            v1[u] = 0;
+            if (pk0[u] & kSiteValid) {
+                const int g = gsite(site_b(pk0[u]));
+                rec[site_b(pk0[u])] = Lt.rec[g];
+                v0[u] = cs[g >> 1];
+            }
+            if (pk1[u] & kSiteValid) {
+                const int g = gsite(site_b(pk1[u]));
+                rec[site_b(pk1[u])] = Lt.rec[g];
+                v1[u] = cs[half + (g >> 1)];
+            }
         }
-        // colour of the list's sites is the list index (c = 0: first half of the internal order)
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
             if (pk0[u] & kSiteValid) s[site_b(pk0[u])] = v0[u];
@@ -184,14 +238,15 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
 
     // Moves with dE == 0 under GREEDY_TIE need an RNG draw; they are queued
     // and drawn after the pass over the colour, compacted over all lanes.
-    auto phase = [&](const int (&pk)[NS], int q) {
+    auto phase = [&](const int (&pk)[NS], int nact) {
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
+            if (u * kLatThreads >= nact) break;
             int p = pk[u];
             // Opaque per phase: stops the compiler from hoisting every site's
             // addresses out of the phase loop and keeping them all live.
             asm volatile("" : "+v"(p));
-            if ((p & kSiteValid) && site_depth(p) > q) {
+            if (u * kLatThreads + tid < nact) {
                 const int b = site_b(p);
                 const uint64_t c = rec[b];
                 int f = jb(c, 6) + jb(c, 2) * s[b + BZ] + jb(c, 3) * s[b - BZ] + jb(c, 4) * s[b + 1] +
@@ -199,21 +254,19 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
                 if (D == 3) f += jb(c, 0) * s[b + BYZ] + jb(c, 1) * s[b - BYZ];
                 const int si = s[b];
                 const int d = 2 * si * f;
-                const bool flip = d < 0;
+                const bool inner = site_depth(p) >= k;
                 if (TIE && d == 0) {
                     const int slot = atomicAdd(&ntie, 1);
-                    tieq[slot] = (uint16_t)(b | ((site_depth(p) >= k) << 15));
+                    tieq[slot] = (uint16_t)(b | ((int)inner << 15));
                 }
-                if (flip) {
+                if (d < 0) {
                     s[b] = (int8_t)(-si);
-                    if (site_depth(p) >= k) {
+                    if (inner) {
                         dE += d;
                         ++nflip;
                     }
                 }
             }
-            // keep one site's loads live at a time (the unrolled list would
-            // otherwise be scheduled all at once and spill)
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -223,8 +276,9 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
         for (int q = 0; q < nq; ++q) {
             const int p = e * k + q;
             const uint32_t sweep = base + (uint32_t)(p >> 1);
-            if (p & 1) phase(pk1, q);
-            else phase(pk0, q);
+            const int qd = min(q, kMaxDepth - 1);
+            if (p & 1) phase(pk1, cnt_gt[1][qd]);
+            else phase(pk0, cnt_gt[0][qd]);
             if (TIE) {
                 __syncthreads();
                 const int nt = ntie;
@@ -241,20 +295,31 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
             }
             __syncthreads();
         }
-        // ---- exchange: publish the interior, signal, wait for neighbours, read the halo
-        int8_t* gw = (e & 1) ? g1 : g0;
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            if ((pk0[u] & kSiteValid) && site_depth(pk0[u]) >= k)
-                __hip_atomic_store(gw + gsite(site_b(pk0[u])), s[site_b(pk0[u])], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            if ((pk1[u] & kSiteValid) && site_depth(pk1[u]) >= k)
-                __hip_atomic_store(gw + gsite(site_b(pk1[u])), s[site_b(pk1[u])], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        // ---- exchange: publish the interior, signal, wait for the
+        // neighbouring tiles' signals, read the box back.  Both passes walk
+        // contiguous z-runs (lane <-> z) so the uncached byte accesses of a
+        // wavefront coalesce; re-reading the tile's own interior returns what
+        // it just wrote.
+        uint32_t* gw = (e & 1) ? g1 : g0;
+        // one word per interior z-row: bit z set when the spin is -1
+        for (int row = tid; row < nrow_int; row += kLatThreads) {
+            const int x = (int)fdiv((uint32_t)row, mX1);
+            const int y = row - x * X[1];
+            const int b0 = ((x + hk[0]) * B[1] + (y + hk[1])) * B[2] + hk[2];
+            uint32_t w = 0;
+            for (int z = 0; z < X[2]; ++z) w |= (uint32_t)(s[b0 + z] < 0) << z;
+            __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        // Ordering: every exchange word and flag is accessed only with
+        // agent-scope atomics, which gfx950 performs at the coherence point
+        // (no copy in a non-coherent cache).  Each wave waits for its word
+        // stores to complete before the barrier, the flag is stored after it,
+        // and readers issue their word loads only after seeing the flag, so
+        // completion order alone publishes the data.  A release/acquire pair
+        // would add an L2 write-back and invalidate that move nothing here.
         __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(fl + tile, (uint32_t)(e + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(fl + tile, (uint32_t)(e + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (tid < 27) {
             const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
             const bool used = !(dx == 0 && dy == 0 && dz == 0) && !(D == 2 && dx != 0);
@@ -264,7 +329,7 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
                 const int nz = (tc[2] + dz + tg.P[2]) % tg.P[2];
                 const int nb = (nx * tg.P[1] + ny) * tg.P[2] + nz;
                 uint32_t spins_left = 1u << 26;
-                while (__hip_atomic_load(fl + nb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)(e + 1)) {
+                while (__hip_atomic_load(fl + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)(e + 1)) {
                     if (--spins_left == 0 ||
                         __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                         __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -278,31 +343,50 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
         failed = __syncthreads_or(failed);
         if (failed) break;
         if ((e + 1) * k < P_total) {
-            int8_t v0[NS], v1[NS];
-#pragma unroll
-            for (int u = 0; u < NS; ++u) {
-                v0[u] = ((pk0[u] & kSiteValid) && site_depth(pk0[u]) < k)
-                            ? __hip_atomic_load(gw + gsite(site_b(pk0[u])), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : (int8_t)0;
-                v1[u] = ((pk1[u] & kSiteValid) && site_depth(pk1[u]) < k)
-                            ? __hip_atomic_load(gw + gsite(site_b(pk1[u])), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : (int8_t)0;
-            }
-#pragma unroll
-            for (int u = 0; u < NS; ++u) {
-                if ((pk0[u] & kSiteValid) && site_depth(pk0[u]) < k) s[site_b(pk0[u])] = v0[u];
-                if ((pk1[u] & kSiteValid) && site_depth(pk1[u]) < k) s[site_b(pk1[u])] = v1[u];
+            // box rows: the z-caps come from the z-neighbour tiles' rows, the
+            // middle from the tile owning the row (skipped for the own interior)
+            for (int row = tid; row < nrow_box; row += kLatThreads) {
+                const int x = (int)fdiv((uint32_t)row, mB1);
+                const int y = row - x * B[1];
+                const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
+                // owner of a coordinate: t = floor(((g + 1) P - 1) / L)
+                const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
+                const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
+                const int sx = tstart(0, tx), sy = tstart(1, ty);
+                const int X1t = tstart(1, ty + 1) - sy;
+                const int wrow = (gx - sx) * X1t + (gy - sy);
+                const int tb = (tx * tg.P[1] + ty) * tg.P[2];
+                const bool inner_row = x >= hk[0] && x < hk[0] + X[0] && y >= hk[1] && y < hk[1] + X[1];
+                const uint32_t wl = __hip_atomic_load(gw + (int64_t)(tb + tzm) * rows_per_tile + wrow, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t wh = __hip_atomic_load(gw + (int64_t)(tb + tzp) * rows_per_tile + wrow, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t wm = 0;
+                if (!inner_row)
+                    wm = __hip_atomic_load(gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                int8_t* sr = s + row * B[2];
+                for (int z = 0; z < hk[2]; ++z) {
+                    sr[z] = (int8_t)(((wl >> (Xzm - hk[2] + z)) & 1u) ? -1 : 1);
+                    sr[hk[2] + X[2] + z] = (int8_t)(((wh >> z) & 1u) ? -1 : 1);
+                }
+                if (!inner_row)
+                    for (int z = 0; z < X[2]; ++z) sr[hk[2] + z] = (int8_t)(((wm >> z) & 1u) ? -1 : 1);
             }
             __syncthreads();
         }
     }
     // write the interior back in internal order and fold the counters
     if (!failed) {
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            if ((pk0[u] & kSiteValid) && site_depth(pk0[u]) >= k) cs[gsite(site_b(pk0[u])) >> 1] = s[site_b(pk0[u])];
-            if ((pk1[u] & kSiteValid) && site_depth(pk1[u]) >= k)
-                cs[half + (gsite(site_b(pk1[u])) >> 1)] = s[site_b(pk1[u])];
+        for (int i = tid; i < nint_all; i += kLatThreads) {
+            const int row = (int)fdiv((uint32_t)i, mX2);
+            const int z = i - row * X[2];
+            const int x = (int)fdiv((uint32_t)row, mX1);
+            const int y = row - x * X[1];
+            const int b = ((x + hk[0]) * B[1] + (y + hk[1])) * B[2] + (z + hk[2]);
+            const int gx = st[0] + x, gy = st[1] + y, gz = st[2] + z;
+            const int g = (gx * L1 + gy) * L2 + gz;
+            cs[((gx + gy + gz + Lt.c0) & 1) * half + (g >> 1)] = s[b];
         }
     }
     long long nf = nflip;
@@ -451,13 +535,19 @@ size_t lattice_tiles_lds(const TileGeom& tg, const int L[3], int D)
     return V * 8 + ((V / 2 + 1 + 3) & ~(size_t)3) * 2 + V;
 }
 
+int64_t lattice_tiles_words(const TileGeom& tg, const int L[3])
+{
+    const int64_t rows = (int64_t)((L[0] + tg.P[0] - 1) / tg.P[0]) * ((L[1] + tg.P[1] - 1) / tg.P[1]);
+    return rows * tg.P[0] * tg.P[1] * tg.P[2];
+}
+
 int lattice_tiles_ns(const TileGeom& tg, const int L[3], int D)
 {
     int B[3];
     tile_box(tg, L, D, B);
     const long long per_colour = (long long)B[0] * B[1] * ((B[2] + 1) / 2);
     const long long ns = (per_colour + kLatThreads - 1) / kLatThreads;
-    for (int c : {2, 4, 6, 8, 10})
+    for (int c : {2, 3, 4, 5, 6, 7, 8, 10})
         if (ns <= c) return c;
     return 0;
 }
@@ -473,8 +563,11 @@ static const void* pick_tiles_kernel(int D, bool tie, int ns)
                       : (tie ? tiles_kernel<2, true, N>() : tiles_kernel<2, false, N>());
     switch (ns) {
         SG_NS_CASE(2)
+        SG_NS_CASE(3)
         SG_NS_CASE(4)
+        SG_NS_CASE(5)
         SG_NS_CASE(6)
+        SG_NS_CASE(7)
         SG_NS_CASE(8)
         SG_NS_CASE(10)
     default: return nullptr;
@@ -482,9 +575,9 @@ static const void* pick_tiles_kernel(int D, bool tie, int ns)
 #undef SG_NS_CASE
 }
 
-hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, int8_t* G0,
-                                int8_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
-                                int nslots, int T, uint64_t seed, int rule, hipStream_t st)
+hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride,
+                                uint32_t* G0, uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R,
+                                int64_t* acc, int nslots, int T, uint64_t seed, int rule, hipStream_t st)
 {
     const int ns = lattice_tiles_ns(tg, Lt.L, Lt.D);
     const void* kern = pick_tiles_kernel(Lt.D, rule == 1, ns);

@@ -27,9 +27,11 @@ hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_
 size_t lattice_tiles_lds(const TileGeom& tg, const int L[3], int D);
 int lattice_tiles_ns(const TileGeom& tg, const int L[3], int D);  // 0 if the box is too large
 int lattice_tiles_max_blocks(const TileGeom& tg, const int L[3], int D);
-hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, int8_t* G0,
-                                int8_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
-                                int nslots, int T, uint64_t seed, int rule, hipStream_t st);
+hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride,
+                                uint32_t* G0, uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R,
+                                int64_t* acc, int nslots, int T, uint64_t seed, int rule, hipStream_t st);
+// exchange words of one copy for a tiling (per replica)
+int64_t lattice_tiles_words(const TileGeom& tg, const int L[3]);
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
                              int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
 
@@ -39,6 +41,10 @@ hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem
                         RepState* rs, CallStats* cs, int RG, int T, uint64_t seed, int rule, int until_conv,
                         hipStream_t st);
 int queue_max_blocks(size_t lds);
+hipError_t launch_init_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
+                             RepState* rs, uint64_t seed, hipStream_t st);
+hipError_t launch_energy_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
+                               RepState* rs, int64_t* out, hipStream_t st);
 hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
                         uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
                         uint64_t seed, int rule, int until_conv, hipStream_t st);
