@@ -64,6 +64,23 @@ def sell_bytes_per_attempt(deg: float, tau: float = 0.0, spins_in_lds: bool = Fa
     return b
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs (scaled by a plain-copy calibration), or None when the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def timed(fn, steps, warmup, sync):
     for _ in range(warmup):
         fn()
@@ -103,16 +120,20 @@ def run_cubic(args, sg, gen, torch):
         f"schedule {sched}, E={E}")
 
     # the plain method: one launch per colour phase, same workload, same GPU
-    plain_ms, _ = timed(lambda: step(SCHED_PHASE), 1, 1, torch.cuda.synchronize)
-    plain_ms *= 1e3
-    log(f"plain per-phase method: {plain_ms:.3f} ms/step")
+    plain_ms = None
+    if not args.no_plain:
+        plain_ms, _ = timed(lambda: step(SCHED_PHASE), 1, 1, torch.cuda.synchronize)
+        plain_ms *= 1e3
+        log(f"plain per-phase method: {plain_ms:.3f} ms/step")
 
     ops = int_ops_per_attempt(6)
     per_launch_s = hot_us / 1e6 / max(launches, 1)
     achieved = ops * attempts / max(launches, 1) / per_launch_s / 1e12
     bpa = sell_bytes_per_attempt(6)
+    traffic = measured_traffic(KERNEL_NAME.get(sched, "")) if sched == 3 else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 2), "unit": "TOP/s",
-                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": KERNEL_NAME.get(sched, str(sched)), "ops_per_attempt": ops,
                 "attempts_per_launch": attempts // max(launches, 1), "launches_per_step": launches,
                 "avg_launch_us": round(hot_us / max(launches, 1), 2),
@@ -139,8 +160,9 @@ def run_cubic(args, sg, gen, torch):
                    "sweeps": args.sweeps, "restarts": 1, "rule": "GREEDY_TIE", "schedule": sched,
                    "tiles": h.query("last_tiles"), "halo_k": h.query("last_tile_k"), "energy": E,
                    "workspace_mb": round(ws_mb, 1)},
-        "plain_method": {"ms_per_step": round(plain_ms, 3), "attempts_per_s": attempts / plain_ms * 1e3,
-                         "speedup": round(plain_ms / (dt * 1e3), 3)},
+        "plain_method": None if plain_ms is None else {
+            "ms_per_step": round(plain_ms, 3), "attempts_per_s": attempts / plain_ms * 1e3,
+            "speedup": round(plain_ms / (dt * 1e3), 3)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     h.free()
@@ -257,6 +279,9 @@ def main():
                     help="sweeps of the CPU oracle sample (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the Chimera batch in the default run")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-phase comparison run")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only copy MIB mebibytes device-to-device 3 times (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -269,6 +294,15 @@ def main():
     import paper_0912_3912_amd as sg
 
     torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        nb = args.copy_calibrate << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nb, "copies": 3}), flush=True)
+        return
     if args.workload == "cubic100":
         out = run_cubic(args, sg, gen, torch)
         if not args.no_batched:
