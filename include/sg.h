@@ -213,6 +213,11 @@ sg_status sg_replica_counters(sg_handle h, int64_t* sweeps, int64_t* flips, int8
 /* Spins of replica r of instance inst, n int8 values in external order. */
 sg_status sg_spins_out(sg_handle h, int32_t inst, int32_t r, int8_t* s);
 
+/* Spins of restarts r0 .. r0+count-1 of instance inst: count x n int8 values,
+ * restart-major, each in external order.  Errors: SG_EINVAL for a range
+ * outside [0, restarts). */
+sg_status sg_spins_out_batch(sg_handle h, int32_t inst, int32_t r0, int32_t count, int8_t* s);
+
 /* Multi-start result per instance (Sec. IV: keep the best start): lowest
  * tracked energy over its restarts, lowest restart index on ties.  E_best and
  * r_best have one entry per instance; either may be NULL. */

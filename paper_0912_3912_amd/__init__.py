@@ -93,6 +93,7 @@ SIGNATURES = [
     ("sg_energy", ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     ("sg_replica_counters", ctypes.c_int32, [_P, _P, _P, _P]),
     ("sg_spins_out", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    ("sg_spins_out_batch", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]),
     ("sg_best", ctypes.c_int32, [_P, _P, _P]),
     ("sg_tune", ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
     ("sg_query", ctypes.c_int32, [_P, ctypes.c_char_p, _P]),
@@ -247,6 +248,14 @@ class Handle:
     def spins_out(self, inst: int, r: int) -> np.ndarray:
         s = np.zeros(self.sizes[inst], np.int8)
         _check(lib().sg_spins_out(self._h, inst, r, _ptr(s)))
+        return s
+
+    def spins_out_batch(self, inst: int, r0: int = 0, count: Optional[int] = None) -> np.ndarray:
+        """Spins of restarts r0 .. r0+count-1 (all by default), shape (count, n)."""
+        if count is None:
+            count = self.restarts[inst] - r0
+        s = np.zeros((count, self.sizes[inst]), np.int8)
+        _check(lib().sg_spins_out_batch(self._h, inst, r0, count, _ptr(s)))
         return s
 
     def best(self):

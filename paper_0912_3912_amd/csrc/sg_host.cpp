@@ -1222,6 +1222,27 @@ sg_status sg_spins_out(sg_handle H, int32_t inst, int32_t r, int8_t* s)
     return SG_OK;
 }
 
+sg_status sg_spins_out_batch(sg_handle H, int32_t inst, int32_t r0, int32_t count, int8_t* s)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    if (count < 1 || !s) return fail(SG_EINVAL, "sg_spins_out_batch: need count >= 1 and an output");
+    if ((e = check_inst(H, inst, r0)) != SG_OK) return e;
+    if ((e = check_inst(H, inst, r0 + count - 1)) != SG_OK) return e;
+    const HostInst& q = H->insts[inst];
+    std::vector<int8_t> tmp((size_t)q.spin_stride * count);
+    SG_HIP(hipMemcpyAsync(tmp.data(), H->at<int8_t>(q.off_spins) + (uint64_t)r0 * q.spin_stride, tmp.size(),
+                          hipMemcpyDeviceToHost, H->stream),
+           "spin copy");
+    SG_HIP(hipStreamSynchronize(H->stream), "stream sync");
+    for (int32_t r = 0; r < count; ++r) {
+        const int8_t* src = tmp.data() + (size_t)r * q.spin_stride;
+        int8_t* dst = s + (size_t)r * q.n;
+        for (int32_t i = 0; i < q.n; ++i) dst[q.ext_of[i]] = src[i];
+    }
+    return SG_OK;
+}
+
 sg_status sg_best(sg_handle H, int64_t* E_best, int32_t* r_best)
 {
     sg_status e = need_bound(H);

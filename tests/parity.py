@@ -49,18 +49,18 @@ def compare(h, insts, states, check_recompute=True):
     base = 0
     for q, (inst, st) in enumerate(zip(insts, states)):
         R = inst.restarts
-        for r in range(R):
-            s = h.spins_out(q, r)
-            k = base + r
-            if not np.array_equal(s, st.spins[r]):
-                bad = np.nonzero(s != st.spins[r])[0]
-                raise AssertionError(f"instance {q} ({inst.name}) restart {r}: {bad.size} spins differ, "
-                                     f"first at {bad[:8]}")
-            assert E[k] == st.energy[r], (q, r, int(E[k]), int(st.energy[r]))
-            assert Er[k] == st.energy[r], (q, r, int(Er[k]), int(st.energy[r]))
-            assert sw[k] == st.sweeps[r], (q, r, int(sw[k]), int(st.sweeps[r]))
-            assert fl[k] == st.flips[r], (q, r, int(fl[k]), int(st.flips[r]))
-            assert cv[k] == st.converged[r], (q, r, int(cv[k]), int(st.converged[r]))
+        S = h.spins_out_batch(q)
+        if not np.array_equal(S, st.spins):
+            rr, ii = np.nonzero(S != st.spins)
+            raise AssertionError(f"instance {q} ({inst.name}): {rr.size} spins differ, first at restart "
+                                 f"{rr[0]} spin {ii[0]}")
+        sl = slice(base, base + R)
+        for name, got, want in (("energy", E[sl], st.energy), ("recomputed energy", Er[sl], st.energy),
+                                ("sweeps", sw[sl], st.sweeps), ("flips", fl[sl], st.flips),
+                                ("converged", cv[sl], st.converged)):
+            if not np.array_equal(got, want):
+                r = int(np.nonzero(got != want)[0][0])
+                raise AssertionError(f"instance {q} ({inst.name}) restart {r}: {name} {int(got[r])} != {int(want[r])}")
         base += R
 
 

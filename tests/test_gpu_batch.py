@@ -127,3 +127,48 @@ def test_uneven_er_reduced(gpu):
     """The uneven Erdos-Renyi workload at 60 of its 2000 instances."""
     insts = gen.cfg4_uneven_batch(count=60, seed=4)
     _run(insts, 7, GREEDY, 10000, True, SCHED_AUTO, expect_sched=SCHED_QUEUE)
+
+
+def _oracle_many(insts, seed, rule, sweeps, uc, workers=16):
+    """Oracle over many instances, one instance per pool task (the C oracle
+    releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda i: oracle_run(i, seed, rule, sweeps, uc, threads=1 if i.restarts == 1 else 4),
+                           insts))
+
+
+def test_chimera_4096x256_full(gpu):
+    """The batched Chimera workload at full size: 4096 instances x 256
+    restarts (1,048,576 replicas), in the configuration the benchmark times,
+    every replica compared with the oracle."""
+    import paper_0912_3912_amd as sg
+    insts = chimera_batch(4096, 256)
+    log("chimera 4096x256 full: loading")
+    h = sg.load_instance(insts).bind()
+    h.init_spins(7)
+    st = h.run_sweeps(seed=7, rule=GREEDY, max_sweeps=10000, until_converged=True)
+    assert st["schedule_used"] == SCHED_BLOCK
+    log(f"gpu done: {st}")
+    states = _oracle_many(insts, 7, GREEDY, 10000, True, workers=4)
+    log("oracle done")
+    compare(h, insts, states)
+    E, r = h.best()
+    for q in (0, 1, 4095):
+        assert E[q] == states[q].energy.min() and r[q] == int(np.argmin(states[q].energy))
+
+
+def test_uneven_er_2000_full(gpu):
+    """The uneven Erdos-Renyi workload at full size (2000 instances, sum n ~
+    2.9e7), AUTO schedule as benchmarked, every instance compared."""
+    import paper_0912_3912_amd as sg
+    insts = gen.cfg4_uneven_batch()
+    log("er 2000 full: loading")
+    h = sg.load_instance(insts).bind()
+    h.init_spins(7)
+    st = h.run_sweeps(seed=7, rule=GREEDY, max_sweeps=10000, until_converged=True)
+    assert st["schedule_used"] == SCHED_QUEUE
+    log(f"gpu done: {st}")
+    states = _oracle_many(insts, 7, GREEDY, 10000, True)
+    log("oracle done")
+    compare(h, insts, states)
