@@ -14,6 +14,10 @@ Workloads (--workload):
                256 restarts each, GREEDY until converged, one batched launch.
   er2000       2000 Erdos-Renyi instances, n log-uniform in [100, 1e5], mean
                degree 6, n/2 triples, GREEDY until converged, one launch.
+  serving      Poisson arrivals of mixed requests (2-D/3-D +-J lattices,
+               Chimera with hyper-couplings, 3-regular), n log-uniform in
+               [1e3, 1e6], admitted by HBM footprint into a device pool,
+               rate 0.7 x the measured capacity; p50/p99 latency, flips/s.
 The default run also measures the Chimera batch against per-instance
 per-phase launches (the plain method) and reports the speedup.
 
@@ -264,13 +268,50 @@ def run_square(args, sg, gen, torch):
             "per_phase_us_per_solve": dtp * 1e6, "speedup": round(dtp / dt, 2)}
 
 
+def run_serving(args, sg, gen, torch):
+    from paper_0912_3912_amd.serve import Request, Server, summarize
+    count = args.serving_requests
+    t0 = time.perf_counter()
+    reqs, gaps = gen.cfg5_trace(count=count)
+    insts = [gen.serving_instance(f, n, s, i) for (f, n, s, i) in reqs]
+    log(f"serving: {count} requests generated in {time.perf_counter() - t0:.1f} s, "
+        f"sum n = {sum(i.n for i in insts)}")
+    budget = args.serving_budget_mb << 20
+    server = Server(budget_bytes=budget, slots=args.serving_slots, ingest_workers=args.serving_ingest)
+    # capacity: the first requests submitted at once, back to back
+    ncal = min(40, count)
+    cal = [Request(rid=1_000_000 + k, instance=insts[k], seed=args.seed) for k in range(ncal)]
+    t1 = time.perf_counter()
+    server.run_trace(cal, [0.0] * ncal)
+    cap = ncal / (time.perf_counter() - t1)
+    lam = 0.7 * cap
+    log(f"capacity {cap:.1f} req/s -> arrival rate {lam:.1f} req/s")
+    server2 = Server(budget_bytes=budget, slots=args.serving_slots, ingest_workers=args.serving_ingest)
+    server.close()
+    del server
+    requests = [Request(rid=k, instance=inst, seed=args.seed) for k, inst in enumerate(insts)]
+    t2 = time.perf_counter()
+    results = server2.run_trace(requests, gaps, time_scale=1.0 / lam)
+    wall = time.perf_counter() - t2
+    server2.close()
+    summ = summarize(results, wall)
+    summ.update({"capacity_req_per_s": cap, "arrival_rate_req_per_s": lam, "budget_bytes": budget,
+                 "slots": args.serving_slots, "peak_resident_bytes": server2.pool.peak,
+                 "max_resident_requests": max(t[2] for t in server2.timeline)})
+    log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['flips_per_s']:.3g} flips/s")
+    summ["workload"] = f"serving{count}_mixed_greedy"
+    summ["attempts_per_s"] = summ["attempts_per_s"]
+    summ["ms_per_step"] = wall * 1e3
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cubic100",
-                    choices=["cubic100", "square16", "chimera4096", "er2000"])
+                    choices=["cubic100", "square16", "chimera4096", "er2000", "serving"])
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--schedule", type=int, default=SCHED_AUTO)
@@ -280,6 +321,10 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the Chimera batch in the default run")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-phase comparison run")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-budget-mb", type=int, default=4096)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-ingest", type=int, default=8)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device 3 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -308,7 +353,8 @@ def main():
         if not args.no_batched:
             out["batched"] = run_chimera(args, sg, gen, torch)
     else:
-        fn = {"square16": run_square, "chimera4096": run_chimera, "er2000": run_er}[args.workload]
+        fn = {"square16": run_square, "chimera4096": run_chimera, "er2000": run_er,
+              "serving": run_serving}[args.workload]
         r = fn(args, sg, gen, torch)
         out = {"metric": f"spin-flip attempts/s ({r['workload']})", "value": r["attempts_per_s"],
                "unit": "attempts/s", "n_gpus": 1, "steps": args.batch_steps, "warmup": 1,

@@ -1,0 +1,324 @@
+"""Continuous-batching solve server on top of the C-ABI.
+
+Requests (an instance plus run parameters) arrive over time.  Each request is
+ingested on the host (validation, colouring, packing) by a worker pool, then
+waits for admission: it is admitted as soon as a GPU slot is free and the
+device pool has room for its workspace (its HBM footprint), skipping ahead of
+earlier requests that do not fit yet.  An admitted request binds a range of
+the pool and a slot's own HIP stream, draws its starts, runs until converged
+(or its sweep budget) and reads its best restart back; its couplings, fields
+and spins stay resident on the device for the whole solve.  Slots run in
+their own host threads (the C calls release the interpreter lock), so work
+of different requests overlaps on the GPU, and requests that arrive while
+others run are admitted as slots and memory free up.
+
+A result depends only on its request (instance, instance_id, seed, rule,
+budget): never on its slot, its stream, its pool offset or its neighbours.
+"""
+from __future__ import annotations
+
+import bisect
+import dataclasses
+import threading
+import time
+from concurrent.futures import ThreadPoolExecutor
+from typing import Dict, List, Optional
+
+import numpy as np
+
+ALIGN = 256
+
+
+class Pool:
+    """First-fit allocator of aligned byte ranges inside a fixed budget
+    (host bookkeeping only; the device memory is one tensor)."""
+
+    def __init__(self, size: int):
+        self.size = int(size) // ALIGN * ALIGN
+        self.free = [(0, self.size)]  # sorted (offset, length)
+        self.used = 0
+        self.peak = 0
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        need = (int(nbytes) + ALIGN - 1) // ALIGN * ALIGN
+        for k, (off, ln) in enumerate(self.free):
+            if ln >= need:
+                if ln == need:
+                    self.free.pop(k)
+                else:
+                    self.free[k] = (off + need, ln - need)
+                self.used += need
+                self.peak = max(self.peak, self.used)
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int):
+        need = (int(nbytes) + ALIGN - 1) // ALIGN * ALIGN
+        self.used -= need
+        k = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(k, (off, need))
+        # coalesce with neighbours
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+    def largest_free(self) -> int:
+        return max((ln for _, ln in self.free), default=0)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    instance: object
+    seed: int = 7
+    rule: int = 0
+    max_sweeps: int = 10000
+    until_converged: bool = True
+    arrival: float = 0.0          # seconds after the trace start
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    status: str                   # "ok", "notconv", "rejected", "cancelled", "error: ..."
+    energy: Optional[int] = None  # best energy over restarts
+    best_restart: Optional[int] = None
+    spins: Optional[np.ndarray] = None
+    sweeps_max: int = 0
+    flips: int = 0
+    attempts: int = 0
+    footprint: int = 0
+    slot: int = -1
+    arrival: float = 0.0
+    admitted: float = 0.0
+    started: float = 0.0
+    done: float = 0.0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Admission:
+    """Admission policy: the earliest ready request that fits the free pool
+    and a free slot; requests larger than the whole pool are rejected."""
+
+    def __init__(self, pool: Pool, slots: int):
+        self.pool = pool
+        self.free_slots = list(range(slots))
+        self.ready: List[tuple] = []  # (arrival order, rid, footprint)
+
+    def add(self, order: int, rid: int, footprint: int) -> bool:
+        if footprint > self.pool.size:
+            return False
+        bisect.insort(self.ready, (order, rid, footprint))
+        return True
+
+    def cancel(self, rid: int) -> bool:
+        for k, it in enumerate(self.ready):
+            if it[1] == rid:
+                self.ready.pop(k)
+                return True
+        return False
+
+    def next(self):
+        """(rid, slot, offset) of the next admission, or None."""
+        if not self.free_slots:
+            return None
+        for k, (order, rid, fp) in enumerate(self.ready):
+            off = self.pool.alloc(fp)
+            if off is not None:
+                self.ready.pop(k)
+                return rid, self.free_slots.pop(0), off
+        return None
+
+    def finish(self, slot: int, off: int, footprint: int):
+        self.pool.release(off, footprint)
+        self.free_slots.append(slot)
+        self.free_slots.sort()
+
+
+class Server:
+    """Runs requests with continuous admission on one GPU.
+
+    budget_bytes  device pool shared by all resident requests
+    slots         requests resident and running at once (one stream each)
+    ingest_workers host threads that validate and pack arriving instances
+    """
+
+    def __init__(self, budget_bytes: int, slots: int = 4, ingest_workers: int = 4, device: int = 0,
+                 keep_spins: bool = False):
+        import torch
+
+        import paper_0912_3912_amd as sg
+        self.sg = sg
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.pool = Pool(budget_bytes)
+        self.mem = torch.empty(self.pool.size, dtype=torch.uint8, device=self.device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.adm = Admission(self.pool, slots)
+        self.ingest = ThreadPoolExecutor(max_workers=ingest_workers)
+        self.slot_exec = ThreadPoolExecutor(max_workers=slots)
+        self.lock = threading.Condition()
+        self.handles: Dict[int, object] = {}
+        self.requests: Dict[int, Request] = {}
+        self.results: Dict[int, Result] = {}
+        self.order = 0
+        self.t0 = None
+        self.keep_spins = keep_spins
+        self.timeline: List[tuple] = []  # (time, bytes resident, requests resident)
+        self.cancelled = set()
+        self.admitted = set()
+        # Large lattices under a fixed sweep count use the co-resident tile
+        # launch; two such grids must not be resident at once (each could
+        # hold CUs the other needs), so they take turns.
+        self.coop_lock = threading.Lock()
+
+    # ------------------------------------------------------------------ API
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request):
+        """Hand a request to the server (its arrival time is 'now')."""
+        if self.t0 is None:
+            self.t0 = time.perf_counter()
+        req.arrival = self.now()
+        with self.lock:
+            self.requests[req.rid] = req
+            order = self.order
+            self.order += 1
+        self.ingest.submit(self._ingest, req, order)
+
+    def cancel(self, rid: int) -> bool:
+        """Cancel a request that has not been admitted yet.  Returns False
+        when it is already running or finished."""
+        with self.lock:
+            if rid in self.results or rid in self.admitted or rid not in self.requests:
+                return False
+            if self.adm.cancel(rid):  # ingested, waiting for admission
+                h = self.handles.pop(rid, None)
+                if h is not None:
+                    h.free()
+                self._finish_unadmitted(rid, "cancelled")
+                return True
+            self.cancelled.add(rid)  # still ingesting: dropped when the ingest ends
+            return True
+
+    def run_trace(self, requests: List[Request], gaps: List[float], time_scale: float = 1.0):
+        """Submit requests at cumulative gaps (seconds * time_scale), wait
+        for all results and return them in request order."""
+        self.t0 = time.perf_counter()
+        t = 0.0
+        for req, gap in zip(requests, gaps):
+            t += gap * time_scale
+            dt = t - self.now()
+            if dt > 0:
+                time.sleep(dt)
+            self.submit(req)
+        return self.wait([r.rid for r in requests])
+
+    def wait(self, rids, timeout: float = 600.0):
+        end = time.perf_counter() + timeout
+        with self.lock:
+            while any(r not in self.results for r in rids):
+                left = end - time.perf_counter()
+                if left <= 0:
+                    raise TimeoutError("requests still pending")
+                self.lock.wait(timeout=min(left, 1.0))
+            return [self.results[r] for r in rids]
+
+    def close(self):
+        self.ingest.shutdown(wait=True)
+        self.slot_exec.shutdown(wait=True)
+
+    # ------------------------------------------------------------ internals
+    def _finish_unadmitted(self, rid, status):
+        req = self.requests[rid]
+        self.results[rid] = Result(rid=rid, status=status, arrival=req.arrival, done=self.now())
+        self.lock.notify_all()
+
+    def _ingest(self, req: Request, order: int):
+        try:
+            h = self.sg.load_instance([req.instance])
+            fp = h.workspace_bytes()
+        except Exception as e:  # invalid instance
+            with self.lock:
+                self._finish_unadmitted(req.rid, f"error: {e}")
+            return
+        with self.lock:
+            if req.rid in self.cancelled:
+                h.free()
+                self._finish_unadmitted(req.rid, "cancelled")
+                return
+            self.handles[req.rid] = h
+            if not self.adm.add(order, req.rid, fp):
+                h.free()
+                self._finish_unadmitted(req.rid, "rejected")
+                return
+            self._admit_locked()
+
+    def _admit_locked(self):
+        while True:
+            nxt = self.adm.next()
+            if nxt is None:
+                return
+            rid, slot, off = nxt
+            self.admitted.add(rid)
+            self.timeline.append((self.now(), self.pool.used, len(self.streams) - len(self.adm.free_slots)))
+            self.slot_exec.submit(self._run, rid, slot, off)
+
+    def _run(self, rid: int, slot: int, off: int):
+        req = self.requests[rid]
+        h = self.handles.pop(rid)
+        fp = h.workspace_bytes()
+        res = Result(rid=rid, status="ok", footprint=fp, slot=slot, arrival=req.arrival, admitted=self.now())
+        try:
+            st = self.streams[slot]
+            base = self.mem.data_ptr() + off
+            h.bind_raw(base, fp, st.cuda_stream)
+            res.started = self.now()
+            h.init_spins(req.seed)
+            info = h.info(0)
+            coop = info["lattice"] and not req.until_converged and info["n"] > h.query("lattice_wg_max_n")
+            if coop:
+                with self.coop_lock:
+                    stats = h.run_sweeps(seed=req.seed, rule=req.rule, max_sweeps=req.max_sweeps,
+                                         until_converged=req.until_converged)
+            else:
+                stats = h.run_sweeps(seed=req.seed, rule=req.rule, max_sweeps=req.max_sweeps,
+                                     until_converged=req.until_converged)
+            E, r = h.best()
+            res.energy, res.best_restart = int(E[0]), int(r[0])
+            if self.keep_spins:
+                res.spins = h.spins_out(0, int(r[0]))
+            res.sweeps_max, res.flips, res.attempts = stats["sweeps_max"], stats["flips"], stats["attempts"]
+            if stats["status"] == self.sg.SG_ENOTCONV:
+                res.status = "notconv"
+        except Exception as e:
+            res.status = f"error: {e}"
+        finally:
+            h.free()
+        res.done = self.now()
+        with self.lock:
+            self.adm.finish(slot, off, fp)
+            self.results[rid] = res
+            self.timeline.append((self.now(), self.pool.used, len(self.streams) - len(self.adm.free_slots)))
+            self.lock.notify_all()
+            self._admit_locked()
+
+
+def summarize(results: List[Result], wall: float) -> dict:
+    ok = [r for r in results if r.status in ("ok", "notconv")]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    att = sum(r.attempts for r in ok)
+    fl = sum(r.flips for r in ok)
+    return {"requests": len(results), "completed": len(ok),
+            "rejected": sum(r.status == "rejected" for r in results),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "wall_s": wall, "attempts_per_s": att / wall,
+            "flips_per_s": fl / wall, "requests_per_s": len(ok) / wall}
