@@ -72,7 +72,7 @@ enum {
     SG_SCHED_AUTO = -1,        /* pick per instance from the tuned table */
     SG_SCHED_PHASE = 0,        /* one kernel launch per colour phase per instance */
     SG_SCHED_GRAPH = 1,        /* SG_SCHED_PHASE captured in HIP graphs of several sweeps */
-    SG_SCHED_PERSISTENT = 2,   /* one cooperative launch; grid barrier between phases */
+                               /* 2 is reserved */
     SG_SCHED_LATTICE = 3,      /* lattice instances: LDS-resident tiles, neighbour flags */
     SG_SCHED_BLOCK = 4,        /* one workgroup per instance, structure and replicas in LDS */
     SG_SCHED_QUEUE = 5         /* persistent batched: work queue of uneven instances */
@@ -238,6 +238,8 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        that fit co-resident)
  *   "queue_min_items"    SG_SCHED_AUTO uses the queue schedule when the
  *                        handle has at least this many queue items (32)
+ *   "graph_sweeps"       sweeps per captured HIP graph of SG_SCHED_GRAPH
+ *                        (1..1024, default 32)
  * Unknown key or value out of range: SG_EINVAL. */
 sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 

@@ -25,15 +25,14 @@ from typing import Optional, Sequence
 import numpy as np
 
 __all__ = [
-    "GREEDY", "GREEDY_TIE", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "SCHED_PERSISTENT",
+    "GREEDY", "GREEDY_TIE", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH",
     "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SGError", "Handle", "load_instance",
     "run_sweeps", "energy", "spins_out", "library_path", "lib",
 ]
 
 SG_OK, SG_ENOTCONV, SG_EINVAL, SG_ERANGE, SG_ENOMEM, SG_EDEVICE, SG_ESTATE = 0, 1, -1, -2, -3, -4, -5
 GREEDY, GREEDY_TIE = 0, 1
-SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_PERSISTENT, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE = (
-    -1, 0, 1, 2, 3, 4, 5)
+SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE = -1, 0, 1, 3, 4, 5
 _STATUS = {SG_EINVAL: "SG_EINVAL", SG_ERANGE: "SG_ERANGE", SG_ENOMEM: "SG_ENOMEM",
            SG_EDEVICE: "SG_EDEVICE", SG_ESTATE: "SG_ESTATE", SG_ENOTCONV: "SG_ENOTCONV"}
 
@@ -111,6 +110,12 @@ def lib():
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                               "or python paper_0912_3912_amd/_build.py")
+        # PyTorch ships its own HIP and HSA runtimes under the same soname.
+        # Loading torch first makes the dynamic linker resolve the library's
+        # libamdhip64.so.7 to that copy, so the device memory and streams the
+        # binding takes from torch belong to the runtime the library calls;
+        # loaded the other way round, the process would hold two runtimes.
+        import torch  # noqa: F401
         L = ctypes.CDLL(path)
         for name, res, args in SIGNATURES:
             fn = getattr(L, name)

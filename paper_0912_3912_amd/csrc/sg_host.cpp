@@ -101,6 +101,9 @@ struct sg_ctx {
     int32_t queue_wave_max_n = 4096;   // queue items up to this size run one per wavefront
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
+    int32_t graph_sweeps = 32;         // sweeps per captured graph (SG_SCHED_GRAPH)
+    hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
+    uint64_t off_tbase = 0;            // one sweep base per instance (graph replays)
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
     uint64_t off_rep_inst = 0, off_small_reps = 0;
     int64_t n_small_reps = 0;                  // replicas of instances below kBatchInitMaxN
@@ -548,6 +551,7 @@ void layout(sg_ctx* H)
     H->off_qitems = take((uint64_t)H->total_reps * sizeof(sg::QueueItem));
     H->off_qcnt = take(64);
     H->off_rep_inst = take((uint64_t)H->total_reps * 4);
+    H->off_tbase = take((uint64_t)H->insts.size() * 4);
     H->n_small_reps = 0;
     for (const HostInst& q : H->insts)
         if (q.n < kBatchInitMaxN) H->n_small_reps += q.R;
@@ -627,6 +631,103 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
                 seg = std::min(seg * 2, 64);
             }
         }
+        if (qi == which.back()) SG_HIP(hipEventRecord(H->evh1, st), "event record");
+        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st), "end kernel");
+    }
+    return SG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph schedule: the per-phase launches of `seg` sweeps recorded once in a
+// HIP graph (on a private capture stream) and replayed on the bound stream;
+// a last node advances the device sweep base the phase kernels add to their
+// recorded local sweep index.
+
+sg_status run_graph_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
+{
+    hipStream_t st = H->stream;
+    sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
+    uint32_t* flag = H->at<uint32_t>(H->off_flag);
+    if (!H->cap_stream) SG_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking), "stream create");
+    for (int qi : which) {
+        const HostInst& q = H->insts[qi];
+        const sg::InstDev I = H->view(q);
+        sg::RepState* rs = H->reps() + q.rep_base;
+        int8_t* spins = H->at<int8_t>(q.off_spins);
+        int64_t* acc = H->at<int64_t>(q.off_acc);
+        int32_t* tb = H->at<int32_t>(H->off_tbase) + qi;
+        SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
+        SG_HIP(sg::launch_fill_u32(tb, 1, 0u, st), "fill kernel");
+        const int seg = std::max(1, std::min(H->graph_sweeps, p->max_sweeps));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        auto cleanup = [&]() {
+            if (exec) {
+                (void)hipStreamSynchronize(st);  // no replay may still be queued
+                (void)hipGraphExecDestroy(exec);
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+        };
+        if (p->max_sweeps > 0) {
+            SG_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeRelaxed), "graph capture");
+            hipError_t ce = hipSuccess;
+            for (int t = 0; t < seg && ce == hipSuccess; ++t)
+                for (int32_t c = 0; c < q.C && ce == hipSuccess; ++c) {
+                    const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
+                    ce = sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, t,
+                                          p->seed, p->rule, p->until_converged, H->cap_stream, tb);
+                }
+            if (ce == hipSuccess) ce = sg::launch_bump(tb, seg, H->cap_stream);
+            hipError_t ee = hipStreamEndCapture(H->cap_stream, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                cleanup();
+                return hip_fail(ce != hipSuccess ? ce : ee, "graph capture");
+            }
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                cleanup();
+                return hip_fail(ie, "graph instantiate");
+            }
+        }
+        if (qi == which.front()) {
+            SG_HIP(hipEventRecord(H->evh0, st), "event record");
+            H->hot_launches = 0;
+        }
+        int T = 0;
+        bool stopped = false;
+        while (!stopped && T + seg <= p->max_sweeps) {
+            hipError_t le = hipGraphLaunch(exec, st);
+            if (le != hipSuccess) {
+                cleanup();
+                return hip_fail(le, "graph launch");
+            }
+            H->hot_launches += seg * q.C;
+            T += seg;
+            if (p->until_converged && T < p->max_sweeps) {
+                uint32_t hflag = 0;
+                hipError_t e1 = sg::launch_fill_u32(flag, 1, 0u, st);
+                if (e1 == hipSuccess) e1 = sg::launch_any_active(rs, q.R, T, flag, st);
+                if (e1 == hipSuccess) e1 = hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, st);
+                if (e1 == hipSuccess) e1 = hipStreamSynchronize(st);
+                if (e1 != hipSuccess) {
+                    cleanup();
+                    return hip_fail(e1, "activity check");
+                }
+                stopped = hflag == 0;
+            }
+        }
+        cleanup();
+        // fewer than a segment left: plain launches at absolute sweep indices
+        for (; !stopped && T < p->max_sweeps; ++T)
+            for (int32_t c = 0; c < q.C; ++c) {
+                const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
+                SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, T,
+                                        p->seed, p->rule, p->until_converged, st),
+                       "phase kernel");
+                H->hot_launches++;
+            }
         if (qi == which.back()) SG_HIP(hipEventRecord(H->evh1, st), "event record");
         SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st), "end kernel");
     }
@@ -880,6 +981,7 @@ int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& 
             else s = SG_SCHED_PHASE;
             break;
         case SG_SCHED_PHASE: s = SG_SCHED_PHASE; break;
+        case SG_SCHED_GRAPH: s = SG_SCHED_GRAPH; break;
         case SG_SCHED_LATTICE: s = can_lattice(H, q, p) ? SG_SCHED_LATTICE : -1; break;
         case SG_SCHED_BLOCK: s = can_block(H, q) ? SG_SCHED_BLOCK : -1; break;
         case SG_SCHED_QUEUE: s = can_queue(q) ? SG_SCHED_QUEUE : -1; break;
@@ -1120,7 +1222,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
     H->hot_launches = 0;
-    for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_PHASE}) {
+    for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_GRAPH, SG_SCHED_PHASE}) {
         std::vector<int> which;
         for (size_t k = 0; k < assign.size(); ++k)
             if (assign[k] == kind) which.push_back((int)k);
@@ -1129,6 +1231,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
         case SG_SCHED_LATTICE: e = run_lattice_schedule(H, p, which); break;
         case SG_SCHED_BLOCK: e = run_block_schedule(H, p, which); break;
         case SG_SCHED_QUEUE: e = run_queue_schedule(H, p, which); break;
+        case SG_SCHED_GRAPH: e = run_graph_schedule(H, p, which); break;
         default: e = run_phase_schedule(H, p, which); break;
         }
         if (e != SG_OK) return e;
@@ -1288,6 +1391,9 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "queue_grid") {
         if (value < 0 || value > 65535) return fail(SG_EINVAL, "queue_grid must be in [0,65535]");
         H->queue_grid = (int32_t)value;
+    } else if (k == "graph_sweeps") {
+        if (value < 1 || value > 1024) return fail(SG_EINVAL, "graph_sweeps must be in [1,1024]");
+        H->graph_sweeps = (int32_t)value;
     } else if (k == "queue_min_items") {
         if (value < 1) return fail(SG_EINVAL, "queue_min_items must be >= 1");
         H->queue_min_items = (int32_t)std::min<int64_t>(value, INT32_MAX);
@@ -1309,6 +1415,7 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "queue_wave_max_n") *value = H->queue_wave_max_n;
     else if (k == "queue_grid") *value = H->queue_grid;
     else if (k == "queue_min_items") *value = H->queue_min_items;
+    else if (k == "graph_sweeps") *value = H->graph_sweeps;
     else if (k == "last_queue_grid") *value = H->last_queue_grid;
     else if (k == "hot_ns") *value = (int64_t)(H->hot_us * 1000.0);
     else if (k == "hot_launches") *value = H->hot_launches;
@@ -1327,6 +1434,7 @@ sg_status sg_free(sg_handle H)
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     if (H->evh0) (void)hipEventDestroy(H->evh0);
     if (H->evh1) (void)hipEventDestroy(H->evh1);
+    if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
     delete H;
     return SG_OK;
 }

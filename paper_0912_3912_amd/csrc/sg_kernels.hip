@@ -211,13 +211,17 @@ __device__ __forceinline__ int local_field(const InstDev& I, const Slice& S, int
 
 // One colour phase of one instance (the plain method): grid = (ceil(slices_c/4), R),
 // block = 4 wavefronts, wavefront w of block x handles slice slice0 + 4x + w.
+// t_rel = t_local + (*t_base when t_base is not null): graph replays keep the
+// launch arguments fixed and advance the base in device memory.
 template <bool TIE, bool TRI>
 __global__ __launch_bounds__(kPhaseThreads) void k_phase(InstDev I, int8_t* __restrict__ spins,
                                                          int64_t stride, RepState* __restrict__ rs,
                                                          int64_t* __restrict__ acc, int nslots,
-                                                         int slice0, int nslice_c, int t_rel,
+                                                         int slice0, int nslice_c, int t_local,
+                                                         const int32_t* __restrict__ t_base,
                                                          uint64_t seed, int until_conv)
 {
+    const int t_rel = t_local + (t_base ? *t_base : 0);
     const int r = blockIdx.y;
     RepState* st = rs + r;
     if (!replica_active(st, t_rel, until_conv)) return;
@@ -397,22 +401,33 @@ hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStre
 
 hipError_t launch_phase(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, int64_t* acc,
                         int nslots, int slice0, int nslice_c, int t_rel, uint64_t seed, int rule,
-                        int until_conv, hipStream_t st)
+                        int until_conv, hipStream_t st, const int32_t* t_base)
 {
     const dim3 grid((nslice_c + kPhaseWaves - 1) / kPhaseWaves, R);
     const bool tie = rule == 1, tri = I.has_tri != 0;
     if (tie && tri)
         hipLaunchKernelGGL((k_phase<true, true>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, seed, until_conv);
+                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
     else if (tie)
         hipLaunchKernelGGL((k_phase<true, false>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, seed, until_conv);
+                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
     else if (tri)
         hipLaunchKernelGGL((k_phase<false, true>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, seed, until_conv);
+                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
     else
         hipLaunchKernelGGL((k_phase<false, false>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, seed, until_conv);
+                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
+    return hipGetLastError();
+}
+
+__global__ void k_bump(int32_t* __restrict__ t_base, int d)
+{
+    if (threadIdx.x == 0) *t_base += d;
+}
+
+hipError_t launch_bump(int32_t* t_base, int d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, st, t_base, d);
     return hipGetLastError();
 }
 

@@ -14,9 +14,11 @@ hipError_t launch_init(const InstDev& I, int8_t* spins, int64_t stride, RepState
 hipError_t launch_energy(const InstDev& I, const int8_t* spins, int64_t stride, int R, int64_t* slots,
                          int nslots, RepState* rs, int64_t* out, hipStream_t st);
 hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStream_t st);
+// t_rel is relative to *t_base when t_base is not null (graph replays).
 hipError_t launch_phase(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, int64_t* acc,
                         int nslots, int slice0, int nslice_c, int t_rel, uint64_t seed, int rule,
-                        int until_conv, hipStream_t st);
+                        int until_conv, hipStream_t st, const int32_t* t_base = nullptr);
+hipError_t launch_bump(int32_t* t_base, int d, hipStream_t st);
 hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T, int until_conv, int64_t n,
                       CallStats* cs, hipStream_t st);
 hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, hipStream_t st);

@@ -127,3 +127,39 @@ def test_cubic100_full_1000_sweeps(gpu):
     inst = gen.cfg2_cubic100()
     _check([inst], seed=7, rule=TIE, max_sweeps=1000, until_converged=False,
            lattice_dims=[(100, 100, 100)])
+
+
+# ---------------------------------------------------------------------------
+# SG_SCHED_GRAPH: phase launches of a segment of sweeps recorded in a HIP graph
+# and replayed; the sweep index of each replay comes from a device counter.
+
+def _check_graph(insts, seed, rule, uc, runs, graph_sweeps):
+    import paper_0912_3912_amd as sg
+    log(f"case: graph {[i.name for i in insts][:3]} seed={seed} rule={rule} uc={uc} runs={runs} "
+        f"graph_sweeps={graph_sweeps}")
+    h = sg.load_instance(list(insts))
+    h.tune("graph_sweeps", graph_sweeps)
+    h.bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=rule, max_sweeps=ms, until_converged=uc, schedule=sg.SCHED_GRAPH)
+             for ms in runs]
+    assert all(s["schedule_used"] == sg.SCHED_GRAPH for s in stats)
+    states = [oracle_run(i, seed, rule, 0, uc, runs) for i in insts]
+    compare(h, insts, states)
+    if len(runs) == 1:
+        att, fl = expected_stats(insts, [None] * len(insts), states)
+        assert stats[0]["attempts"] == att and stats[0]["flips"] == fl
+    h.free()
+
+
+@pytest.mark.parametrize("graph_sweeps,runs", [(1, [9]), (4, [10]), (32, [70]), (32, [5]), (8, [3, 8, 0, 17])])
+@pytest.mark.parametrize("rule,uc", [(GREEDY, True), (TIE, False), (TIE, True)])
+def test_graph_schedule(gpu, graph_sweeps, runs, rule, uc):
+    inst = gen.erdos_renyi_triples(700, seed=9, instance_id=3, restarts=4)
+    _check_graph([inst], seed=13, rule=rule, uc=uc, runs=runs, graph_sweeps=graph_sweeps)
+
+
+def test_graph_schedule_batch_until_converged(gpu):
+    insts = [gen.chimera(6, 6, seed=s, instance_id=s, restarts=3) for s in range(2)]
+    insts += [gen.lattice((12, 12), seed=2, instance_id=40, restarts=2), gen.random_small(65, seed=1)]
+    _check_graph(insts, seed=21, rule=GREEDY, uc=True, runs=[10000], graph_sweeps=16)
