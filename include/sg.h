@@ -240,11 +240,17 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        handle has at least this many queue items (32)
  *   "graph_sweeps"       sweeps per captured HIP graph of SG_SCHED_GRAPH
  *                        (1..1024, default 32)
+ *   "lattice_msc"        1: tile lattices whose bonds are all +-1 and whose
+ *                        fields satisfy |h| <= 2 with the bit-plane kernel
+ *                        (32 sites of a colour per lane word); 0: byte kernel
+ *   "msc_k"              halo width of the bit-plane kernel (0 = chosen by
+ *                        its cost model, else 1..62)
  * Unknown key or value out of range: SG_EINVAL. */
 sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 
 /* Read a knob, or one of "last_tiles" (Px*10^6 + Py*10^3 + Pz of the last
- * lattice tile launch), "last_tile_k", "last_queue_grid", "total_replicas",
+ * lattice tile launch), "last_tile_k", "last_msc" (1 when that launch used
+ * the bit-plane kernel), "last_queue_grid", "total_replicas",
  * "instances", "hot_ns" / "hot_launches" (device time, from HIP events on the
  * bound stream, of the last sg_run_sweeps call's sweep kernel launches: the
  * single launch of the lattice, block or queue schedule, or the span of the

@@ -21,34 +21,11 @@
 
 #include <algorithm>
 
+#include "sg_device.h"
 #include "sg_launch.h"
 #include "sg_layout.h"
 
 namespace sg {
-
-__device__ __forceinline__ uint32_t bat_philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                                     uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t p0lo = c0 * 0xD2511F53u;
-        const uint32_t p0hi = __umulhi(c0, 0xD2511F53u);
-        const uint32_t p1lo = c2 * 0xCD9E8D57u;
-        const uint32_t p1hi = __umulhi(c2, 0xCD9E8D57u);
-        c0 = p1hi ^ c1 ^ k0;
-        c1 = p1lo;
-        c2 = p0hi ^ c3 ^ k1;
-        c3 = p0lo;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c0;
-}
-
-__device__ __forceinline__ int bat_rng_bit(uint64_t seed, uint32_t spin, uint32_t sweep, uint32_t id, uint32_t r)
-{
-    return (int)(bat_philox_word0(spin, sweep, id, r, (uint32_t)seed, (uint32_t)(seed >> 32)) & 1u);
-}
 
 __device__ __forceinline__ int bat_j(uint32_t w) { return (int)(int8_t)(w & 0xffu); }
 
@@ -147,7 +124,7 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
                     const int d = 2 * si * f;
                     bool flip = d < 0;
                     if (TIE && d == 0 && active)
-                        flip = bat_rng_bit(seed, I.ext[i], base + t, I.instance_id, (uint32_t)r) != 0;
+                        flip = rng_bit(seed, I.ext[i], base + t, I.instance_id, (uint32_t)r) != 0;
                     if (flip && active) {
                         l_s[i * RG + r_loc] = (int8_t)(-si);
                         dE += d;
@@ -245,7 +222,7 @@ __device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __res
             const int si = sp[i];
             const int d = 2 * si * f;
             bool flip = d < 0;
-            if (TIE && d == 0) flip = bat_rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
+            if (TIE && d == 0) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
             if (flip) {
                 sp[i] = (int8_t)(-si);
                 dE += d;
@@ -419,7 +396,7 @@ __global__ __launch_bounds__(256) void k_init_batch(const InstTab* __restrict__ 
     const uint32_t r = (uint32_t)(g - Q.rep_base);
     int8_t* sp = Q.spins + (int64_t)r * Q.spin_stride;
     for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x)
-        sp[i] = (int8_t)(bat_rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
+        sp[i] = (int8_t)(rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
     if (threadIdx.x == 0) {
         RepState z;
         z.E = 0; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;

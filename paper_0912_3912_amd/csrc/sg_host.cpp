@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -53,6 +54,7 @@ constexpr int32_t kMaxCoef = 127;
 constexpr int64_t kMaxField = (1 << 23) - 1;
 constexpr int32_t kMaxRestarts = 65535;
 constexpr int32_t kMaxLatticeTiles = 1024;
+constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kBatchInitMaxN = 65536;  // instances below this size start and evaluate in batched launches
 
 struct HostInst {
@@ -74,6 +76,7 @@ struct HostInst {
     int64_t rep_base = 0;
     // lattice schedule (implicit neighbours)
     int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
+    int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
     int32_t lat_L[3] = {0, 0, 0};      // (x, y, z) extents, z fastest; 2-D: (1, Lx, Ly)
     int32_t lat_D = 0;
     int32_t lat_c0 = 0;
@@ -102,6 +105,9 @@ struct sg_ctx {
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
     int32_t graph_sweeps = 32;         // sweeps per captured graph (SG_SCHED_GRAPH)
+    int32_t lattice_msc = 1;           // use the bit-plane tile kernel where it applies
+    int32_t msc_k = 0;                 // its halo width (0 = chosen by the cost model)
+    int32_t last_msc = 0;              // the last tile launch used the bit-plane kernel
     hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
     uint64_t off_tbase = 0;            // one sweep base per instance (graph replays)
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
@@ -343,6 +349,18 @@ void build_lattice(const sg_instance_desc& d, HostInst& q, const std::vector<uin
     }
     if (d.h)
         for (int32_t g = 0; g < n; ++g) q.lat_rec[g] |= (uint64_t)(uint8_t)(int8_t)d.h[g] << 48;
+    // bit-plane form: every bond of the lattice present with J = +-1, |h| <= 2
+    q.lat_msc = 1;
+    for (int32_t g = 0; g < n && q.lat_msc; ++g) {
+        const uint64_t rc = q.lat_rec[g];
+        for (int ax = 3 - dim; ax < 3; ++ax)
+            for (int side = 0; side < 2; ++side) {
+                const int v = (int)(int8_t)(rc >> (8 * (2 * ax + side)));
+                if (v != 1 && v != -1) q.lat_msc = 0;
+            }
+        const int hv = (int)(int8_t)(rc >> 48);
+        if (hv < -2 || hv > 2) q.lat_msc = 0;
+    }
     for (int a = 0; a < 3; ++a) q.lat_L[a] = L[a];
     q.lat_D = dim;
     q.lat_c0 = c0;
@@ -783,6 +801,64 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
     return found;
 }
 
+// Tiling and halo width of the bit-plane kernel.  Per colour phase a tile
+// costs a fixed latency plus one pass of its lanes over the rows deeper than
+// the phase index, and every k phases an exchange (a fixed latency plus one
+// pass over the box rows); the choice minimises that cost per phase (in
+// microseconds, from measurements of the kernel), subject to LDS,
+// co-residency and the geometry limits of the kernel.
+bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeom& tg)
+{
+    int cap_limit = kMaxLatticeTiles;
+    if (H->lattice_max_tiles > 0) cap_limit = std::min(cap_limit, H->lattice_max_tiles);
+    std::vector<std::pair<size_t, int>> cap_cache;
+    auto cap_for = [&](const sg::TileGeom& g) {
+        const size_t lds = sg::lattice_msc_lds(g, q.lat_L, q.lat_D);
+        for (auto& c : cap_cache)
+            if (c.first == lds) return c.second;
+        const int c = sg::lattice_msc_max_blocks(g, q.lat_L, q.lat_D);
+        cap_cache.emplace_back(lds, c);
+        return c;
+    };
+    const int a0 = q.lat_D == 2 ? 1 : 0;
+    const int k_lo = H->msc_k ? H->msc_k : 1, k_hi = H->msc_k ? H->msc_k : 62;
+    bool found = false;
+    double best = 1e300;
+    int bestT = 0;
+    for (int p0 = 1; p0 <= (a0 ? 1 : q.lat_L[0]) && p0 <= cap_limit; ++p0)
+        for (int p1 = 1; p1 <= q.lat_L[1] && p0 * p1 <= cap_limit; ++p1)
+            for (int p2 = 1; p2 <= q.lat_L[2]; ++p2) {
+                const int T = p0 * p1 * p2;
+                if (T > cap_limit) break;
+                if (q.lat_L[2] / p2 < 4) continue;  // keeps the exchange within its allocation
+                for (int k = k_lo; k <= k_hi; ++k) {
+                    sg::TileGeom g{};
+                    g.P[0] = p0; g.P[1] = p1; g.P[2] = p2; g.k = k;
+                    if (!sg::lattice_msc_geometry_ok(g, q.lat_L, q.lat_D)) continue;
+                    if (sg::lattice_msc_lds(g, q.lat_L, q.lat_D) > kLatLdsBudget) continue;
+                    int B[3];
+                    for (int a = 0; a < 3; ++a)
+                        B[a] = (q.lat_L[a] + g.P[a] - 1) / g.P[a] + ((a < a0) ? 0 : 2 * k);
+                    const double rows = (double)B[0] * B[1];
+                    double cost = 6.0 + 0.4 * std::ceil(rows / 1024.0);
+                    for (int qq = 0; qq < k; ++qq) {
+                        const double ax = a0 ? 1.0 : std::max(0, B[0] - 2 * (qq + 1));
+                        const double ay = std::max(0, B[1] - 2 * (qq + 1));
+                        cost += (tie ? 0.5 : 0.3) + 0.25 * std::ceil(ax * ay / 1024.0);
+                    }
+                    cost /= k;
+                    if (!(cost < best - 1e-9 || (std::fabs(cost - best) <= 1e-9 && T < bestT))) continue;
+                    if ((int64_t)sg::lattice_tiles_words(g, q.lat_L) * 8 * q.R > (int64_t)q.lat_g_bytes) continue;
+                    if ((int64_t)T * q.R > cap_for(g)) continue;
+                    best = cost;
+                    bestT = T;
+                    tg = g;
+                    found = true;
+                }
+            }
+    return found;
+}
+
 sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
 {
     hipStream_t st = H->stream;
@@ -806,7 +882,8 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 H->hot_launches = 1;
             } else {
                 sg::TileGeom tg{};
-                if (!choose_tiling(H, q, tg))
+                const bool msc = q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, p->rule == 1, tg);
+                if (!msc && !choose_tiling(H, q, tg))
                     return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0], q.lat_L[1],
                                 q.lat_L[2]);
                 uint32_t* flags = H->at<uint32_t>(q.off_lat_flags);
@@ -819,9 +896,15 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 uint32_t* G0 = H->at<uint32_t>(q.off_lat_g);
                 uint32_t* G1 = G0 + words;
                 SG_HIP(hipEventRecord(H->evh0, st), "event record");
-                SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs, q.R,
-                                                acc, q.acc_slots, T, p->seed, p->rule, st),
-                       "lattice tile kernel");
+                if (msc)
+                    SG_HIP(sg::launch_lattice_msc(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs, q.R,
+                                                  acc, q.acc_slots, T, p->seed, p->rule, st),
+                           "lattice bit-plane kernel");
+                else
+                    SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs,
+                                                    q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
+                           "lattice tile kernel");
+                H->last_msc = msc ? 1 : 0;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;
                 uint32_t herr = 0;
@@ -1391,6 +1474,12 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "queue_grid") {
         if (value < 0 || value > 65535) return fail(SG_EINVAL, "queue_grid must be in [0,65535]");
         H->queue_grid = (int32_t)value;
+    } else if (k == "lattice_msc") {
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "lattice_msc must be 0 or 1");
+        H->lattice_msc = (int32_t)value;
+    } else if (k == "msc_k") {
+        if (value < 0 || value > 62) return fail(SG_EINVAL, "msc_k must be in [0,62]");
+        H->msc_k = (int32_t)value;
     } else if (k == "graph_sweeps") {
         if (value < 1 || value > 1024) return fail(SG_EINVAL, "graph_sweeps must be in [1,1024]");
         H->graph_sweeps = (int32_t)value;
@@ -1416,6 +1505,9 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "queue_grid") *value = H->queue_grid;
     else if (k == "queue_min_items") *value = H->queue_min_items;
     else if (k == "graph_sweeps") *value = H->graph_sweeps;
+    else if (k == "lattice_msc") *value = H->lattice_msc;
+    else if (k == "msc_k") *value = H->msc_k;
+    else if (k == "last_msc") *value = H->last_msc;
     else if (k == "last_queue_grid") *value = H->last_queue_grid;
     else if (k == "hot_ns") *value = (int64_t)(H->hot_us * 1000.0);
     else if (k == "hot_launches") *value = H->hot_launches;

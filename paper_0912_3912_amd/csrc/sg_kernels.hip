@@ -12,40 +12,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sg_device.h"
 #include "sg_launch.h"
 #include "sg_layout.h"
 
 namespace sg {
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
-// multiplies with the high halves folded into the other two counter words and
-// the key, key advanced by the two Weyl increments after every round.  Only
-// word 0 is needed.
-__device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                                 uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t p0lo = c0 * 0xD2511F53u;
-        const uint32_t p0hi = __umulhi(c0, 0xD2511F53u);
-        const uint32_t p1lo = c2 * 0xCD9E8D57u;
-        const uint32_t p1hi = __umulhi(c2, 0xCD9E8D57u);
-        c0 = p1hi ^ c1 ^ k0;
-        c1 = p1lo;
-        c2 = p0hi ^ c3 ^ k1;
-        c3 = p0lo;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c0;
-}
-
-__device__ __forceinline__ int rng_bit(uint64_t seed, uint32_t spin, uint32_t word1, uint32_t id,
-                                       uint32_t restart)
-{
-    return (int)(philox_word0(spin, word1, id, restart, (uint32_t)seed, (uint32_t)(seed >> 32)) & 1u);
-}
 
 __device__ __forceinline__ int wave_sum_i32(int v)
 {

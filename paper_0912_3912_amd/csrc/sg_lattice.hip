@@ -28,47 +28,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sg_device.h"
 #include "sg_launch.h"
 #include "sg_layout.h"
 
 namespace sg {
 
-__device__ __forceinline__ uint32_t lat_philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                                     uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t p0lo = c0 * 0xD2511F53u;
-        const uint32_t p0hi = __umulhi(c0, 0xD2511F53u);
-        const uint32_t p1lo = c2 * 0xCD9E8D57u;
-        const uint32_t p1hi = __umulhi(c2, 0xCD9E8D57u);
-        c0 = p1hi ^ c1 ^ k0;
-        c1 = p1lo;
-        c2 = p0hi ^ c3 ^ k1;
-        c3 = p0lo;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c0;
-}
-
-__device__ __forceinline__ int lat_rng_bit(uint64_t seed, uint32_t site, uint32_t sweep, uint32_t id, uint32_t r)
-{
-    return (int)(lat_philox_word0(site, sweep, id, r, (uint32_t)seed, (uint32_t)(seed >> 32)) & 1u);
-}
-
 __device__ __forceinline__ int jb(uint64_t rec, int k) { return (int)(int8_t)(rec >> (8 * k)); }
-
-// Exact floor(a / d) for a * d < 2^32 with m = floor(2^32 / d) + 1 (then
-// a*m / 2^32 - a/d < a/2^32 < 1/d, so the floor is unchanged); d = 1 is
-// encoded as m = 0.
-__device__ __forceinline__ uint32_t fdiv(uint32_t a, uint32_t m) { return m ? __umulhi(a, m) : a; }
-__host__ __device__ __forceinline__ uint32_t fdiv_magic(uint32_t d)
-{
-    return d <= 1 ? 0u : (uint32_t)((0x100000000ull / d) + 1);
-}
-
-__device__ __forceinline__ int wrapi(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
 
 constexpr int kLatThreads = 1024;
 constexpr int kLatWaves = kLatThreads / 64;
@@ -285,7 +251,7 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
                 for (int i = tid; i < nt; i += kLatThreads) {
                     const int e2 = tieq[i];
                     const int b = e2 & 0x7FFF;
-                    if (lat_rng_bit(seed, (uint32_t)gsite(b), sweep, Lt.instance_id, (uint32_t)r)) {
+                    if (rng_bit(seed, (uint32_t)gsite(b), sweep, Lt.instance_id, (uint32_t)r)) {
                         s[b] = (int8_t)(-s[b]);
                         nflip += e2 >> 15;
                     }
@@ -467,7 +433,7 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_wg(LatticeDev Lt, int8_
                 const int si = s[g];
                 const int d = 2 * si * f;
                 bool flip = d < 0;
-                if (TIE && d == 0) flip = lat_rng_bit(seed, (uint32_t)g, base + t, Lt.instance_id, (uint32_t)r) != 0;
+                if (TIE && d == 0) flip = rng_bit(seed, (uint32_t)g, base + t, Lt.instance_id, (uint32_t)r) != 0;
                 if (flip) {
                     s[g] = (int8_t)(-si);
                     dE += d;

@@ -34,6 +34,13 @@ hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t
                                 int64_t* acc, int nslots, int T, uint64_t seed, int rule, hipStream_t st);
 // exchange words of one copy for a tiling (per replica)
 int64_t lattice_tiles_words(const TileGeom& tg, const int L[3]);
+// Multi-spin coded tile kernel (lattices with +-1 couplings and |h| <= 2).
+size_t lattice_msc_lds(const TileGeom& tg, const int L[3], int D);
+bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D);
+int lattice_msc_max_blocks(const TileGeom& tg, const int L[3], int D);
+hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint32_t* G0,
+                              uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
+                              int nslots, int T, uint64_t seed, int rule, hipStream_t st);
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
                              int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
 

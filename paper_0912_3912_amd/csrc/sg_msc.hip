@@ -1,0 +1,546 @@
+// sg_msc.hip -- multi-spin coded colour-ordered sweeps on periodic 2-D/3-D
+// lattices whose couplings are all +-1 and whose fields satisfy |h| <= 2,
+// LDS-resident tiles.
+//
+// Same tiling, halo, epoch and exchange protocol as k_lattice_tiles (a tile
+// plus a halo of width k per workgroup, k colour phases between exchanges,
+// bit-packed interior z-rows published with coherent stores and a relaxed
+// epoch flag, bounded waits), but the box is held as bit-planes: every box
+// z-row is split by colour into two 32-bit words (bit j of colour c's word
+// is the site z = 2j + zo, zo = the row's offset for that colour), for the
+// spin (bit set when s = -1), the sign of the +x, +y and +z bond (bit set
+// when J = -1) and three field planes (h > 0, h < 0, |h| = 2).  One lane
+// updates all sites of one colour of one row at once:
+//
+//   a bond (i, d) is unsatisfied when J s_i s_d = -1, i.e. when
+//   bit(s_i) ^ bit(s_d) ^ bit(J < 0) = 1; with U = number of unsatisfied
+//   bonds of i (a bit-sliced sum of 2D one-bit inputs) and g = s_i h_i,
+//   s_i f_i = g + 2D - 2U, so dE_i = 2 s_i f_i = 2g + 4D - 4U
+//   (the move cost of Sec. IV, the field of Sec. II eq. (1)).
+//
+// dE_i < 0 iff U >= D + 1 + (g == 2) - (g < 0); dE_i == 0 iff g is even and
+// U equals that threshold minus one.  Both tests are bit-sliced compares of
+// U against per-site thresholds selected by the g < 0 and g == 2 masks.
+// Under GREEDY_TIE the dE == 0 sites of a wavefront's rows are compacted into
+// the wavefront's own LDS segment and drawn from Philox by all of its lanes
+// right after those rows (only this wavefront touches their words in this
+// phase), so the draws run at full lane occupancy without a workgroup
+// barrier.
+//
+// Neighbours: the +-x and +-y neighbours of a colour-c site are the same bit
+// of the other colour's word in the neighbouring rows (their offset is the
+// same); its -z and +z neighbours are, in the same row's other-colour word,
+// bits j-1 and j (zo = 0) or j and j+1 (zo = 1).  A -d bond is the +d bond of
+// the -d neighbour, read from that neighbour's plane the same way.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_device.h"
+#include "sg_launch.h"
+#include "sg_layout.h"
+
+namespace sg {
+
+constexpr int kMscThreads = 1024;
+constexpr int kMscWaves = kMscThreads / 64;
+constexpr int kWaveTieCap = 128;  // tie entries per wavefront segment (more are drawn in further rounds)
+
+// plane indices (the +x plane exists for 3-D lattices only)
+enum { kPlS = 0, kPlJY = 1, kPlJZ = 2, kPlHP = 3, kPlHN = 4, kPlHA = 5, kPlJX = 6 };
+
+__host__ __device__ constexpr int msc_planes(int D) { return D == 3 ? 7 : 6; }
+
+__device__ __forceinline__ int msc_jb(uint64_t rec, int k) { return (int)(int8_t)(rec >> (8 * k)); }
+
+// bit i of x -> bit 2i (x < 2^16)
+__device__ __forceinline__ uint32_t spread16(uint32_t x)
+{
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+__device__ __forceinline__ uint64_t spread32(uint32_t x)
+{
+    return (uint64_t)spread16(x & 0xFFFFu) | ((uint64_t)spread16(x >> 16) << 32);
+}
+// bit 2i of x -> bit i
+__device__ __forceinline__ uint32_t even16(uint32_t x)
+{
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+__device__ __forceinline__ uint32_t even32(uint64_t v)
+{
+    return even16((uint32_t)v) | (even16((uint32_t)(v >> 32)) << 16);
+}
+// bits lo..hi (inclusive) set; empty when hi < lo; 0 <= lo <= 31
+__device__ __forceinline__ uint32_t bit_range(int lo, int hi)
+{
+    if (hi < lo) return 0u;
+    const uint32_t up = hi >= 31 ? 0xFFFFFFFFu : ((2u << hi) - 1u);
+    return up & ~((1u << lo) - 1u);
+}
+__device__ __forceinline__ uint32_t low_bits(int n) { return n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u); }
+
+// full adder on bit-planes
+__device__ __forceinline__ void fadd(uint32_t a, uint32_t b, uint32_t c, uint32_t& s, uint32_t& cy)
+{
+    const uint32_t t = a ^ b;
+    s = t ^ c;
+    cy = (t & c) | (~t & a);
+}
+
+// U >= t and U == t for U = (u2 u1 u0), 0 <= U <= 6
+template <int t>
+__device__ __forceinline__ uint32_t u_ge(uint32_t u0, uint32_t u1, uint32_t u2)
+{
+    static_assert(t >= 1 && t <= 6, "threshold");
+    if constexpr (t == 1) return u2 | u1 | u0;
+    else if constexpr (t == 2) return u2 | u1;
+    else if constexpr (t == 3) return u2 | (u1 & u0);
+    else if constexpr (t == 4) return u2;
+    else if constexpr (t == 5) return u2 & (u1 | u0);
+    else return u2 & u1;
+}
+template <int t>
+__device__ __forceinline__ uint32_t u_eq(uint32_t u0, uint32_t u1, uint32_t u2)
+{
+    static_assert(t >= 0 && t <= 6, "value");
+    return ((t & 4) ? u2 : ~u2) & ((t & 2) ? u1 : ~u1) & ((t & 1) ? u0 : ~u0);
+}
+
+template <int D, bool TIE>
+__global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, TileGeom tg, int8_t* __restrict__ canon,
+                                                             int64_t stride, uint32_t* __restrict__ G0,
+                                                             uint32_t* __restrict__ G1, uint32_t* __restrict__ flags,
+                                                             uint32_t* __restrict__ err, RepState* __restrict__ rs,
+                                                             int64_t* __restrict__ acc, int nslots, int T,
+                                                             uint64_t seed)
+{
+    constexpr int NPL = msc_planes(D);
+    constexpr int T0 = D + 1;  // flip threshold on U for g in {0, 1}
+    extern __shared__ uint32_t lds32[];
+    const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
+    const int tile = blockIdx.x % ntiles;
+    const int r = blockIdx.x / ntiles;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int L0 = Lt.L[0], L1 = Lt.L[1], L2 = Lt.L[2];
+    const int half = Lt.n / 2;
+    const int k = tg.k;
+    int tc[3];
+    tc[0] = tile / (tg.P[1] * tg.P[2]);
+    tc[1] = (tile / tg.P[2]) % tg.P[1];
+    tc[2] = tile % tg.P[2];
+    int X[3], hk[3], B[3], o[3], st[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int La = Lt.L[a];
+        st[a] = (int)((int64_t)tc[a] * La / tg.P[a]);
+        X[a] = (int)((int64_t)(tc[a] + 1) * La / tg.P[a]) - st[a];
+        hk[a] = (D == 2 && a == 0) ? 0 : k;
+        B[a] = X[a] + 2 * hk[a];
+        o[a] = st[a] - hk[a];
+    }
+    // colour of box site (x, y, z) = (par0 + x + y + z) mod 2
+    const int par0 = (((o[0] % 2) + (o[1] % 2) + (o[2] % 2) + Lt.c0) % 2 + 2) % 2;
+    const int rows = B[0] * B[1];
+    const int nrow_int = X[0] * X[1];
+    const uint32_t mB1 = fdiv_magic((uint32_t)B[1]), mX1 = fdiv_magic((uint32_t)X[1]);
+    auto tstart = [&](int a, int t) -> int { return (int)((int64_t)t * Lt.L[a] / tg.P[a]); };
+    const int tzm = (tc[2] + tg.P[2] - 1) % tg.P[2], tzp = (tc[2] + 1) % tg.P[2];
+    const int Xzm = tstart(2, tzm + 1) - tstart(2, tzm);
+    auto plane = [&](int pl, int c) -> uint32_t* { return lds32 + (pl * 2 + c) * rows; };
+    uint32_t* tieq = lds32 + NPL * 2 * rows;
+    __shared__ uint32_t mag_ay[64];
+    int8_t* cs = canon + (int64_t)r * stride;
+    const int rows_per_tile = ((L0 + tg.P[0] - 1) / tg.P[0]) * ((L1 + tg.P[1] - 1) / tg.P[1]);
+    uint32_t* g0 = G0 + (int64_t)r * ntiles * rows_per_tile;
+    uint32_t* g1 = G1 + (int64_t)r * ntiles * rows_per_tile;
+    uint32_t* fl = flags + (int64_t)r * ntiles;
+    const uint32_t base = (uint32_t)rs[r].sweeps;
+    auto gsite = [&](int x, int y, int z) -> int {
+        return (wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1)) * L2 + wrapi(o[2] + z, L2);
+    };
+
+    if (tid < 64) mag_ay[tid] = fdiv_magic((uint32_t)max(1, B[1] - 2 * (tid + 1)));
+    // ---- bit-planes of the box: one wavefront per box row, lane = z
+    for (int row = wave; row < rows; row += kMscWaves) {
+        const int x = (int)fdiv((uint32_t)row, mB1);
+        const int y = row - x * B[1];
+        const int pr = (par0 + x + y) & 1;  // colour of the even-z sites
+        const int z = lane;
+        bool sneg = false, jx = false, jy = false, jz = false, hp = false, hn = false, ha = false;
+        if (z < B[2]) {
+            const int g = gsite(x, y, z);
+            const uint64_t rc = Lt.rec[g];
+            sneg = cs[((pr + z) & 1) * half + (g >> 1)] < 0;
+            jx = msc_jb(rc, 0) < 0;
+            jy = msc_jb(rc, 2) < 0;
+            jz = msc_jb(rc, 4) < 0;
+            const int hv = msc_jb(rc, 6);
+            hp = hv > 0;
+            hn = hv < 0;
+            ha = hv == 2 || hv == -2;
+        }
+        const uint64_t m[7] = {__ballot(sneg), __ballot(jy), __ballot(jz), __ballot(hp),
+                               __ballot(hn),   __ballot(ha), __ballot(jx)};
+        if (lane < NPL) {
+            uint64_t v = m[0];
+#pragma unroll
+            for (int pl = 1; pl < 7; ++pl)
+                if (lane == pl) v = m[pl];
+            plane(lane, pr)[row] = even32(v);
+            plane(lane, pr ^ 1)[row] = even32(v >> 1);
+        }
+    }
+    __syncthreads();
+
+    const int P_total = 2 * T;
+    long long dE = 0;
+    int nflip = 0;
+    bool failed = false;
+
+    for (int e = 0; e * k < P_total; ++e) {
+        const int nq = min(k, P_total - e * k);
+        for (int q = 0; q < nq; ++q) {
+            const int p = e * k + q;
+            const int c = p & 1;
+            const uint32_t sweep = base + (uint32_t)(p >> 1);
+            const int ax = D == 3 ? B[0] - 2 * (q + 1) : 1;
+            const int ay = B[1] - 2 * (q + 1);
+            const int xlo = D == 3 ? q + 1 : 0, ylo = q + 1;
+            const int nact = (ax > 0 && ay > 0) ? ax * ay : 0;
+            const uint32_t may = mag_ay[q];
+            // sites deeper than q along z, and the tile interior along z, per offset
+            const uint32_t zm0 = bit_range((q + 2) >> 1, (B[2] - 2 - q) >> 1);
+            const uint32_t zm1 = bit_range((q + 1) >> 1, (B[2] - 3 - q) >> 1);
+            const uint32_t im0 = bit_range((hk[2] + 1) >> 1, (hk[2] + X[2] - 1) >> 1);
+            const uint32_t im1 = bit_range(hk[2] >> 1, (hk[2] + X[2] - 2) >> 1);
+            uint32_t* Sc = plane(kPlS, c);
+            const uint32_t* So = plane(kPlS, c ^ 1);
+            const uint32_t* JYc = plane(kPlJY, c);
+            const uint32_t* JYo = plane(kPlJY, c ^ 1);
+            const uint32_t* JZc = plane(kPlJZ, c);
+            const uint32_t* JZo = plane(kPlJZ, c ^ 1);
+            const uint32_t* JXc = plane(kPlJX, c);
+            const uint32_t* JXo = plane(kPlJX, c ^ 1);
+            const uint32_t* HPc = plane(kPlHP, c);
+            const uint32_t* HNc = plane(kPlHN, c);
+            const uint32_t* HAc = plane(kPlHA, c);
+            // wave-uniform trip count: the tie queue is reserved once per wavefront
+            for (int i0 = wave * 64; i0 < nact; i0 += kMscThreads) {
+                const int i = i0 + lane;
+                const bool act = i < nact;
+                const int ii = act ? i : i0;
+                const int qq = (int)fdiv((uint32_t)ii, may);
+                const int x = xlo + qq, y = ylo + ii - qq * ay;
+                const int row = x * B[1] + y;
+                const int zo = (c - par0 - x - y) & 1;
+                const uint32_t s = Sc[row];
+                const uint32_t on = So[row];
+                const uint32_t jzo = JZo[row];
+                const uint32_t szp = zo ? (on >> 1) : on;
+                const uint32_t szm = zo ? on : (on << 1);
+                const uint32_t jzm = zo ? jzo : (jzo << 1);
+                const uint32_t a0 = s ^ So[row + 1] ^ JYc[row];
+                const uint32_t a1 = s ^ So[row - 1] ^ JYo[row - 1];
+                const uint32_t a2 = s ^ szp ^ JZc[row];
+                const uint32_t a3 = s ^ szm ^ jzm;
+                uint32_t u0, u1, u2;
+                if constexpr (D == 3) {
+                    const int BY = B[1];
+                    const uint32_t a4 = s ^ So[row + BY] ^ JXc[row];
+                    const uint32_t a5 = s ^ So[row - BY] ^ JXo[row - BY];
+                    uint32_t s1, c1, s2, c2;
+                    fadd(a0, a1, a2, s1, c1);
+                    fadd(a3, a4, a5, s2, c2);
+                    u0 = s1 ^ s2;
+                    fadd(c1, c2, s1 & s2, u1, u2);
+                } else {
+                    uint32_t s1, c1;
+                    fadd(a0, a1, a2, s1, c1);
+                    u0 = s1 ^ a3;
+                    const uint32_t k0 = s1 & a3;
+                    u1 = c1 ^ k0;
+                    u2 = c1 & k0;
+                }
+                const uint32_t hp = HPc[row], hn = HNc[row], ha = HAc[row];
+                const uint32_t gpos = (hp & ~s) | (hn & s);
+                const uint32_t gneg = (hn & ~s) | (hp & s);
+                const uint32_t gtwo = gpos & ha;  // g == +2
+                const uint32_t gmid = ~(gneg | gtwo);
+                const uint32_t M = act ? (zo ? zm1 : zm0) : 0u;
+                const uint32_t flip = (gneg & u_ge<T0 - 1>(u0, u1, u2)) | (gtwo & u_ge<T0 + 1>(u0, u1, u2)) |
+                                      (gmid & u_ge<T0>(u0, u1, u2));
+                const uint32_t F = flip & M;
+                const bool inner_row = x >= hk[0] && x < hk[0] + X[0] && y >= hk[1] && y < hk[1] + X[1];
+                const uint32_t I = inner_row ? (zo ? im1 : im0) : 0u;
+                const uint32_t FI = F & I;
+                if (FI) {
+                    const int nf = __popc(FI);
+                    const int sg = __popc(FI & gpos) + __popc(FI & gtwo) - __popc(FI & gneg) - __popc(FI & gneg & ha);
+                    const int su = __popc(FI & u0) + 2 * __popc(FI & u1) + 4 * __popc(FI & u2);
+                    dE += 2 * sg + 4 * D * nf - 4 * su;
+                    nflip += nf;
+                }
+                const uint32_t ns = s ^ F;
+                if constexpr (TIE) {
+                    const uint32_t odd = (hp | hn) & ~ha;
+                    const uint32_t tie = ~odd & ((gneg & u_eq<T0 - 2>(u0, u1, u2)) | (gtwo & u_eq<T0>(u0, u1, u2)) |
+                                                 (gmid & u_eq<T0 - 1>(u0, u1, u2)));
+                    const uint32_t Tm = tie & M;
+                    if (ns != s) Sc[row] = ns;
+                    const int cnt = __popc(Tm);
+                    if (__ballot(cnt != 0)) {
+                        // exclusive prefix sum of the lanes' tie counts from one
+                        // ballot per bit of the count
+                        int below = 0, total = 0;
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) {
+                            const uint64_t m = __ballot((cnt >> b) & 1);
+                            below += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))
+                                     << b;
+                            total += __popcll(m) << b;
+                        }
+                        uint32_t* seg = tieq + wave * kWaveTieCap;
+                        for (int rb = 0; rb < total; rb += kWaveTieCap) {
+                            int slot = below;
+                            uint32_t t2 = Tm;
+                            while (t2) {
+                                const int j = __ffs(t2) - 1;
+                                t2 &= t2 - 1;
+                                if (slot >= rb && slot < rb + kWaveTieCap)
+                                    seg[slot - rb] = (uint32_t)row | ((uint32_t)j << 16) | (((I >> j) & 1u) << 21);
+                                ++slot;
+                            }
+                            // LDS operations of one wavefront complete in order: keep
+                            // the compiler from moving the reads above the writes
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                            const int nt = min(total - rb, kWaveTieCap);
+                            if (lane < nt) {
+                                const uint32_t en = seg[lane];
+                                const int trow = (int)(en & 0xFFFFu);
+                                const int j = (int)((en >> 16) & 31u);
+                                const int tx = (int)fdiv((uint32_t)trow, mB1);
+                                const int ty = trow - tx * B[1];
+                                const int tzo = (c - par0 - tx - ty) & 1;
+                                if (rng_bit(seed, (uint32_t)gsite(tx, ty, 2 * j + tzo), sweep, Lt.instance_id,
+                                            (uint32_t)r)) {
+                                    atomicXor(Sc + trow, 1u << j);
+                                    nflip += (int)((en >> 21) & 1u);
+                                }
+                            }
+                            if (lane + 64 < nt) {
+                                const uint32_t en = seg[lane + 64];
+                                const int trow = (int)(en & 0xFFFFu);
+                                const int j = (int)((en >> 16) & 31u);
+                                const int tx = (int)fdiv((uint32_t)trow, mB1);
+                                const int ty = trow - tx * B[1];
+                                const int tzo = (c - par0 - tx - ty) & 1;
+                                if (rng_bit(seed, (uint32_t)gsite(tx, ty, 2 * j + tzo), sweep, Lt.instance_id,
+                                            (uint32_t)r)) {
+                                    atomicXor(Sc + trow, 1u << j);
+                                    nflip += (int)((en >> 21) & 1u);
+                                }
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        }
+                    }
+                } else {
+                    if (ns != s) Sc[row] = ns;
+                }
+            }
+            __syncthreads();
+        }
+        // ---- exchange (protocol of k_lattice_tiles): publish the interior
+        // z-rows, signal, wait for the neighbouring tiles, read the box back
+        uint32_t* gw = (e & 1) ? g1 : g0;
+        for (int row = tid; row < nrow_int; row += kMscThreads) {
+            const int x = (int)fdiv((uint32_t)row, mX1);
+            const int y = row - x * X[1];
+            const int bx = x + hk[0], by = y + hk[1];
+            const int brow = bx * B[1] + by;
+            const int pr = (par0 + bx + by) & 1;
+            const uint64_t v = spread32(plane(kPlS, pr)[brow]) | (spread32(plane(kPlS, pr ^ 1)[brow]) << 1);
+            const uint32_t w = (uint32_t)(v >> hk[2]) & low_bits(X[2]);
+            __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // Ordering: as in k_lattice_tiles, every exchange word and flag is an
+        // agent-scope atomic performed at the coherence point; each wave waits
+        // for its stores before the barrier, the flag follows the barrier and
+        // readers load words only after seeing the flag.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(fl + tile, (uint32_t)(e + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid < 27) {
+            const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+            const bool used = !(dx == 0 && dy == 0 && dz == 0) && !(D == 2 && dx != 0);
+            if (used) {
+                const int nx = (tc[0] + dx + tg.P[0]) % tg.P[0];
+                const int ny = (tc[1] + dy + tg.P[1]) % tg.P[1];
+                const int nz = (tc[2] + dz + tg.P[2]) % tg.P[2];
+                const int nb = (nx * tg.P[1] + ny) * tg.P[2] + nz;
+                uint32_t spins_left = 1u << 26;
+                while (__hip_atomic_load(fl + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)(e + 1)) {
+                    if (--spins_left == 0 ||
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        failed = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        failed = __syncthreads_or(failed);
+        if (failed) break;
+        if ((e + 1) * k < P_total) {
+            for (int row = tid; row < rows; row += kMscThreads) {
+                const int x = (int)fdiv((uint32_t)row, mB1);
+                const int y = row - x * B[1];
+                const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
+                const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
+                const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
+                const int sx = tstart(0, tx), sy = tstart(1, ty);
+                const int X1t = tstart(1, ty + 1) - sy;
+                const int wrow = (gx - sx) * X1t + (gy - sy);
+                const int tb = (tx * tg.P[1] + ty) * tg.P[2];
+                const uint32_t wl = __hip_atomic_load(gw + (int64_t)(tb + tzm) * rows_per_tile + wrow, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t wh = __hip_atomic_load(gw + (int64_t)(tb + tzp) * rows_per_tile + wrow, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t wm = __hip_atomic_load(gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow,
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t v = (uint64_t)((wl >> (Xzm - hk[2])) & low_bits(hk[2])) | ((uint64_t)wm << hk[2]) |
+                                   ((uint64_t)(wh & low_bits(hk[2])) << (hk[2] + X[2]));
+                const int pr = (par0 + x + y) & 1;
+                plane(kPlS, pr)[row] = even32(v);
+                plane(kPlS, pr ^ 1)[row] = even32(v >> 1);
+            }
+            __syncthreads();
+        }
+    }
+    // write the interior back in internal order (one wavefront per row, lane = z)
+    if (!failed) {
+        for (int row = wave; row < nrow_int; row += kMscWaves) {
+            const int x = (int)fdiv((uint32_t)row, mX1);
+            const int y = row - x * X[1];
+            const int bx = x + hk[0], by = y + hk[1];
+            const int brow = bx * B[1] + by;
+            const int z = lane;
+            if (z < X[2]) {
+                const int zb = hk[2] + z;
+                const int c = (par0 + bx + by + zb) & 1;
+                const uint32_t bit = (plane(kPlS, c)[brow] >> (zb >> 1)) & 1u;
+                const int g = gsite(bx, by, zb);
+                cs[c * half + (g >> 1)] = (int8_t)(bit ? -1 : 1);
+            }
+        }
+    }
+    long long nf = nflip;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        dE += __shfl_xor(dE, off, 64);
+        nf += __shfl_xor(nf, off, 64);
+    }
+    __shared__ long long pd[kMscWaves], pf[kMscWaves];
+    if (lane == 0) {
+        pd[wave] = dE;
+        pf[wave] = nf;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long a = 0, b2 = 0;
+        for (int w = 0; w < kMscWaves; ++w) {
+            a += pd[w];
+            b2 += pf[w];
+        }
+        int64_t* ap = acc + 2 * ((int64_t)r * nslots + tile);
+        ap[0] += a;
+        ap[1] += b2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+static void msc_box(const TileGeom& tg, const int L[3], int D, int B[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const int mx = (L[a] + tg.P[a] - 1) / tg.P[a];
+        B[a] = mx + ((D == 2 && a == 0) ? 0 : 2 * tg.k);
+    }
+}
+
+size_t lattice_msc_lds(const TileGeom& tg, const int L[3], int D)
+{
+    int B[3];
+    msc_box(tg, L, D, B);
+    return (size_t)msc_planes(D) * 2 * B[0] * B[1] * 4 + (size_t)kMscWaves * kWaveTieCap * 4;
+}
+
+bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D)
+{
+    int B[3];
+    msc_box(tg, L, D, B);
+    if (tg.k < 1 || tg.k > 62) return false;
+    if (B[2] > 64) return false;                           // a box z-row is two 32-bit colour words
+    if ((L[2] + tg.P[2] - 1) / tg.P[2] > 32) return false;  // an interior z-row is one exchange word
+    if ((int64_t)B[0] * B[1] > 65535) return false;        // tie queue entries hold the row in 16 bits
+    for (int a = (D == 2 ? 1 : 0); a < 3; ++a)
+        if (L[a] / tg.P[a] < tg.k) return false;           // the halo stays within the 26 neighbour tiles
+    return true;
+}
+
+template <int D, bool TIE>
+static const void* msc_kernel() { return (const void*)k_lattice_msc<D, TIE>; }
+
+static const void* pick_msc_kernel(int D, bool tie)
+{
+    return D == 3 ? (tie ? msc_kernel<3, true>() : msc_kernel<3, false>())
+                  : (tie ? msc_kernel<2, true>() : msc_kernel<2, false>());
+}
+
+hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint32_t* G0,
+                              uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
+                              int nslots, int T, uint64_t seed, int rule, hipStream_t st)
+{
+    if (!lattice_msc_geometry_ok(tg, Lt.L, Lt.D)) return hipErrorInvalidValue;
+    const void* kern = pick_msc_kernel(Lt.D, rule == 1);
+    const size_t lds = lattice_msc_lds(tg, Lt.L, Lt.D);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
+    LatticeDev a0 = Lt;
+    TileGeom a1 = tg;
+    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &flags, &err, &rs, &acc, &nslots, &T, &seed};
+    return hipLaunchCooperativeKernel(kern, dim3(ntiles * R), dim3(kMscThreads), args, (unsigned)lds, st);
+}
+
+int lattice_msc_max_blocks(const TileGeom& tg, const int L[3], int D)
+{
+    const void* kern = pick_msc_kernel(D, true);
+    const size_t lds = lattice_msc_lds(tg, L, D);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMscThreads, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+}  // namespace sg

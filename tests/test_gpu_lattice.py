@@ -1,6 +1,8 @@
 """GPU parity of the lattice schedules (implicit neighbours, LDS-resident):
 the whole-lattice workgroup mode and the co-resident tile mode with halo
-exchanges every k colour phases, against the CPU oracle, bit for bit."""
+exchanges every k colour phases, in both its byte-per-spin kernel and its
+bit-plane kernel (lattices with +-1 bonds and |h| <= 2), against the CPU
+oracle, bit for bit."""
 import numpy as np
 import pytest
 
@@ -40,36 +42,83 @@ def test_cubic_workgroup_mode(gpu, rule, uc):
     _run([inst], [(12, 10, 8)], 3, rule, 40, uc)
 
 
+def _tile_tune(kernel, k=None, **extra):
+    t = {"lattice_wg_max_n": 0}
+    if kernel == "byte":
+        t["lattice_msc"] = 0
+        if k is not None:
+            t["lattice_k"] = k
+    elif k is not None:
+        t["msc_k"] = k
+    t.update(extra)
+    return t
+
+
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("rule", [GREEDY, TIE])
-def test_cubic_tile_mode_halo_widths(gpu, k, rule):
+@pytest.mark.parametrize("kernel", ["byte", "msc"])
+def test_cubic_tile_mode_halo_widths(gpu, k, rule, kernel):
     inst = gen.lattice((20, 16, 24), seed=k, h_range=(-2, 2), restarts=2)
-    h, _ = _run([inst], [(20, 16, 24)], 11, rule, 17, False,
-                tune={"lattice_wg_max_n": 0, "lattice_k": k})
-    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')}")
+    h, _ = _run([inst], [(20, 16, 24)], 11, rule, 17, False, tune=_tile_tune(kernel, k))
+    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')} msc={h.query('last_msc')}")
     assert h.query("last_tile_k") == k
+    assert h.query("last_msc") == (kernel == "msc")
+
+
+@pytest.mark.parametrize("k", [6, 8, 11, 16])
+@pytest.mark.parametrize("rule", [GREEDY, TIE])
+def test_cubic_msc_deep_halos(gpu, k, rule):
+    """Deep halos of the bit-plane kernel, a box z-row of up to 64 sites."""
+    inst = gen.lattice((34, 32, 64), seed=k + 40, h_range=(-2, 2), restarts=1)
+    h, _ = _run([inst], [(34, 32, 64)], 17, rule, 2 * k + 3, False, tune=_tile_tune("msc", k))
+    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')}")
+    assert h.query("last_tile_k") == k and h.query("last_msc") == 1
 
 
 @pytest.mark.parametrize("max_tiles", [1, 2, 3, 8, 27])
-def test_cubic_tile_mode_tilings(gpu, max_tiles):
+@pytest.mark.parametrize("kernel", ["byte", "msc"])
+def test_cubic_tile_mode_tilings(gpu, max_tiles, kernel):
     """Few tiles: periodic self-neighbours (one or two tiles along an axis)
     and uneven tile extents."""
     inst = gen.lattice((14, 18, 10), seed=2, h_range=(-2, 2))
-    h, _ = _run([inst], [(14, 18, 10)], 5, TIE, 9, False,
-                tune={"lattice_wg_max_n": 0, "lattice_k": 3, "lattice_max_tiles": max_tiles})
+    h, _ = _run([inst], [(14, 18, 10)], 5, TIE, 9, False, tune=_tile_tune(kernel, 3, lattice_max_tiles=max_tiles))
     log(f"tiles={h.query('last_tiles')}")
+    assert h.query("last_msc") == (kernel == "msc")
 
 
 @pytest.mark.parametrize("k", [1, 4])
 def test_square_tile_mode(gpu, k):
     inst = gen.lattice((64, 48), seed=3, h_range=(-1, 1), j_values=(-2, -1, 1, 2), restarts=2)
-    _run([inst], [(64, 48)], 9, TIE, 13, False, tune={"lattice_wg_max_n": 0, "lattice_k": k})
+    h, _ = _run([inst], [(64, 48)], 9, TIE, 13, False, tune={"lattice_wg_max_n": 0, "lattice_k": k})
+    assert h.query("last_msc") == 0  # |J| = 2 bonds: byte kernel
 
 
-def test_tile_mode_resume(gpu):
+@pytest.mark.parametrize("k", [1, 3, 7, 12])
+@pytest.mark.parametrize("rule", [GREEDY, TIE])
+def test_square_msc(gpu, k, rule):
+    inst = gen.lattice((96, 60), seed=k, h_range=(-2, 2), restarts=3)
+    h, _ = _run([inst], [(96, 60)], 9 + k, rule, 2 * k + 5, False, tune=_tile_tune("msc", k))
+    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')}")
+    assert h.query("last_msc") == 1 and h.query("last_tile_k") == k
+
+
+@pytest.mark.parametrize("kernel", ["byte", "msc"])
+def test_tile_mode_resume(gpu, kernel):
     inst = gen.lattice((16, 16, 16), seed=8, h_range=(-2, 2))
-    _run([inst], [(16, 16, 16)], 4, TIE, 0, False, tune={"lattice_wg_max_n": 0, "lattice_k": 4},
-         runs=[3, 5, 1, 0, 6])
+    _run([inst], [(16, 16, 16)], 4, TIE, 0, False, tune=_tile_tune(kernel, 4), runs=[3, 5, 1, 0, 6])
+
+
+def test_msc_restarts_and_fields(gpu):
+    """h = 0 everywhere (every tie rule branch at g = 0) and several restarts."""
+    inst = gen.lattice((18, 22, 26), seed=3, h_range=(0, 0), restarts=4)
+    h, _ = _run([inst], [(18, 22, 26)], 31, TIE, 11, False, tune=_tile_tune("msc"))
+    assert h.query("last_msc") == 1
+
+
+def test_msc_not_used_when_ineligible(gpu):
+    inst = gen.lattice((16, 16, 16), seed=8, h_range=(-3, 3))
+    h, _ = _run([inst], [(16, 16, 16)], 4, TIE, 5, False, tune=_tile_tune("msc"))
+    assert h.query("last_msc") == 0
 
 
 def test_tile_mode_refuses_until_converged(gpu):
@@ -93,7 +142,16 @@ def test_mixed_lattice_batch(gpu):
 
 def test_cubic100_full_tile_mode(gpu):
     """The 10^6-spin workload in the launch configuration the benchmark
-    times (tile mode, default tiling), 1000 GREEDY_TIE sweeps."""
+    times (tile mode, default tiling and kernel), 1000 GREEDY_TIE sweeps."""
     inst = gen.cfg2_cubic100()
     h, st = _run([inst], [(100, 100, 100)], 7, TIE, 1000, False)
-    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')} kernel_ms={st[0]['kernel_ms']:.2f}")
+    log(f"tiles={h.query('last_tiles')} k={h.query('last_tile_k')} msc={h.query('last_msc')} "
+        f"kernel_ms={st[0]['kernel_ms']:.2f}")
+    assert h.query("last_msc") == 1
+
+
+def test_cubic100_byte_kernel(gpu):
+    """The same workload through the byte-per-spin tile kernel, 200 sweeps."""
+    inst = gen.cfg2_cubic100()
+    h, st = _run([inst], [(100, 100, 100)], 7, TIE, 200, False, tune={"lattice_msc": 0})
+    assert h.query("last_msc") == 0
