@@ -68,19 +68,27 @@ def sell_bytes_per_attempt(deg: float, tau: float = 0.0, spins_in_lds: bool = Fa
     return b
 
 
+def sources_sha256(paths) -> str:
+    """sha256 over the concatenated bytes of the given repository files."""
+    import hashlib
+    d = hashlib.sha256()
+    for p in paths:
+        d.update(open(os.path.join(ROOT, p), "rb").read())
+    return d.hexdigest()
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    runs (scaled by a plain-copy calibration), or None when the kernel's
-    source has changed since the counters were taken."""
-    import hashlib
+    runs (scaled by a plain-copy calibration), or None when a source of the
+    kernel has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+    srcs = rec.get("sources") or [rec["source"]]
+    if not all(os.path.exists(os.path.join(ROOT, p)) for p in srcs) or sources_sha256(srcs) != rec["sha256"]:
         return None
     return rec["bytes_per_launch"]
 
@@ -134,11 +142,14 @@ def run_cubic(args, sg, gen, torch):
     per_launch_s = hot_us / 1e6 / max(launches, 1)
     achieved = ops * attempts / max(launches, 1) / per_launch_s / 1e12
     bpa = sell_bytes_per_attempt(6)
-    traffic = measured_traffic(KERNEL_NAME.get(sched, "")) if sched == 3 else None
+    kname = KERNEL_NAME.get(sched, str(sched))
+    if sched == 3 and h.query("last_msc"):
+        kname = "k_lattice_msc"
+    traffic = measured_traffic(kname) if sched == 3 else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": KERNEL_NAME.get(sched, str(sched)), "ops_per_attempt": ops,
+                "kernel": kname, "ops_per_attempt": ops,
                 "attempts_per_launch": attempts // max(launches, 1), "launches_per_step": launches,
                 "avg_launch_us": round(hot_us / max(launches, 1), 2),
                 "hbm_equiv": {"bytes_per_attempt": bpa, "GB/s": round(bpa * value / 1e9, 1),

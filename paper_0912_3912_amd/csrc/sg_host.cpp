@@ -77,6 +77,10 @@ struct HostInst {
     // lattice schedule (implicit neighbours)
     int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
     int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
+    // last tiling decision and the settings it was made for (rule, knobs)
+    std::array<int32_t, 6> tile_key{{-1, -1, -1, -1, -1, -1}};
+    sg::TileGeom tile_geom{};
+    int32_t tile_msc = 0;
     int32_t lat_L[3] = {0, 0, 0};      // (x, y, z) extents, z fastest; 2-D: (1, Lx, Ly)
     int32_t lat_D = 0;
     int32_t lat_c0 = 0;
@@ -802,10 +806,12 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
 }
 
 // Tiling and halo width of the bit-plane kernel.  Per colour phase a tile
-// costs a fixed latency plus one pass of its lanes over the rows deeper than
-// the phase index, and every k phases an exchange (a fixed latency plus one
-// pass over the box rows); the choice minimises that cost per phase (in
-// microseconds, from measurements of the kernel), subject to LDS,
+// costs a fixed latency plus its lanes' passes over the rows deeper than the
+// phase index (1024 rows per pass; a second pass costs more than the first,
+// it also doubles the wavefronts' tie draws), and every k phases an exchange
+// (a fixed latency plus passes over the box rows).  The constants are
+// microseconds measured for this kernel on the 10^6-spin lattice under both
+// rules; the choice minimises the cost per phase, subject to LDS,
 // co-residency and the geometry limits of the kernel.
 bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeom& tg)
 {
@@ -840,11 +846,14 @@ bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeo
                     for (int a = 0; a < 3; ++a)
                         B[a] = (q.lat_L[a] + g.P[a] - 1) / g.P[a] + ((a < a0) ? 0 : 2 * k);
                     const double rows = (double)B[0] * B[1];
-                    double cost = 6.0 + 0.4 * std::ceil(rows / 1024.0);
+                    const double ex0 = tie ? 7.5 : 4.5, ex1 = tie ? 1.4 : 0.5;
+                    const double ph1 = tie ? 1.3 : 0.55, ph2 = tie ? 1.0 : 0.4;
+                    double cost = ex0 + ex1 * std::ceil(rows / 1024.0);
                     for (int qq = 0; qq < k; ++qq) {
                         const double ax = a0 ? 1.0 : std::max(0, B[0] - 2 * (qq + 1));
                         const double ay = std::max(0, B[1] - 2 * (qq + 1));
-                        cost += (tie ? 0.5 : 0.3) + 0.25 * std::ceil(ax * ay / 1024.0);
+                        const double passes = std::ceil(ax * ay / 1024.0);
+                        cost += 0.3 + ph1 * passes + ph2 * std::max(0.0, passes - 1.0);
                     }
                     cost /= k;
                     if (!(cost < best - 1e-9 || (std::fabs(cost - best) <= 1e-9 && T < bestT))) continue;
@@ -881,11 +890,23 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;
             } else {
-                sg::TileGeom tg{};
-                const bool msc = q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, p->rule == 1, tg);
-                if (!msc && !choose_tiling(H, q, tg))
-                    return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0], q.lat_L[1],
-                                q.lat_L[2]);
+                // the tiling depends only on the instance, the rule and the knobs:
+                // search once per setting
+                HostInst& qm = H->insts[qi];
+                const std::array<int32_t, 6> key{{p->rule, H->lattice_msc, H->msc_k, H->lattice_max_tiles,
+                                                  H->lattice_k, 1}};
+                if (qm.tile_key != key) {
+                    sg::TileGeom g{};
+                    const bool m = q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, p->rule == 1, g);
+                    if (!m && !choose_tiling(H, q, g))
+                        return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0],
+                                    q.lat_L[1], q.lat_L[2]);
+                    qm.tile_key = key;
+                    qm.tile_geom = g;
+                    qm.tile_msc = m ? 1 : 0;
+                }
+                const sg::TileGeom tg = qm.tile_geom;
+                const bool msc = qm.tile_msc != 0;
                 uint32_t* flags = H->at<uint32_t>(q.off_lat_flags);
                 SG_HIP(sg::launch_fill_u32(flags, (uint64_t)kMaxLatticeTiles * q.R, 0u, st), "fill kernel");
                 SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
