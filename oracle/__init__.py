@@ -77,6 +77,9 @@ def _load():
     lib.oracle_philox4x32_10.argtypes = [P, P, P]
     lib.oracle_philox_stream.restype = None
     lib.oracle_philox_stream.argtypes = [u64, u32, u32, u32, u32, i64, P]
+    lib.oracle_fm.restype = ctypes.c_int
+    lib.oracle_fm.argtypes = [i32, i64, P, P, P, P, i64, P, P, u32, i32, u64, i32, i32, i32, P, P, P, P, P,
+                              i32]
     lib.oracle_best.restype = i32
     lib.oracle_best.argtypes = [i32, P, P]
     _lib = lib
@@ -154,6 +157,26 @@ def run(inst, seed: int, rule: int = GREEDY, max_sweeps: int = 10000,
                             _p(state.sweeps), _p(state.flips), _p(state.converged), threads)
     if st < 0:
         raise ValueError(f"oracle_run failed with status {st}")
+    return state, st
+
+
+def fm(inst, seed: int, max_passes: int = 1000, until_converged: bool = True,
+       state: Optional[ReplicaState] = None, threads: int = 0):
+    """The paper's pass-based local search (Sec. IV, Fig. 3) on every restart:
+    max-gain moves (lowest index on equal gains) with locking and
+    hill-climbing, the best state of each pass kept, passes until one brings
+    no improvement.  ``state.sweeps`` counts passes and ``state.flips`` the
+    moves kept.  With ``state`` None the random starts are drawn.  Returns
+    (state, status)."""
+    init = state is None
+    if init:
+        state = ReplicaState(inst.n, inst.restarts)
+    args, _keep = _arrs(inst)
+    st = _load().oracle_fm(*args, inst.instance_id & 0xFFFFFFFF, inst.restarts, seed & 0xFFFFFFFFFFFFFFFF,
+                           max_passes, int(until_converged), int(init), _p(state.spins), _p(state.energy),
+                           _p(state.sweeps), _p(state.flips), _p(state.converged), threads)
+    if st < 0:
+        raise ValueError(f"oracle_fm failed with status {st}")
     return state, st
 
 

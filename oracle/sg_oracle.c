@@ -33,6 +33,8 @@
  *   stop       until_converged: after the first sweep with zero flips (that
  *              sweep counts); otherwise exactly max_sweeps sweeps.  A replica
  *              that converged stays frozen until it is restarted.
+ * It also models the paper's own pass (oracle_fm below): max-gain moves with
+ * locking and hill-climbing, best prefix kept, passes until no improvement.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -541,6 +543,104 @@ int64_t oracle_brute_force(int32_t n, int64_t m, const int32_t* ei, const int32_
     oracle_graph_free(&g);
     if (degeneracy) *degeneracy = deg;
     return best;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The paper's pass-based local search with hill-climbing (Sec. IV, Fig. 3).
+ * A pass starts from the state SP* and its energy.  n times: every unlocked
+ * spin's gain -dE_i is evaluated from the definition (no incremental update),
+ * the unlocked spin of largest gain is moved even when that gain is negative
+ * (lowest spin index among equal gains), and locked; whenever the energy is
+ * strictly below the lowest seen in this pass, the state is remembered.  At the
+ * end of the pass the remembered state becomes SP*.  The search stops after
+ * the first pass that leaves the energy of SP* unchanged (that pass counts).
+ *   passes  cumulative pass count, in/out
+ *   kept    cumulative number of moves kept (the length of each pass's best
+ *           prefix), in/out
+ * Readings: ties go to the lowest index; "energy decreased" is strict and is
+ * measured against the lowest energy seen so far in the pass. */
+static void oracle_fm_replica(const oracle_graph* g, const int32_t* h, int8_t* s, int64_t* E,
+                              int32_t max_passes, int32_t until_converged, int64_t* passes,
+                              int64_t* kept, int8_t* converged, int8_t* locked, int8_t* best)
+{
+    const int32_t n = g->n;
+    if (*converged) return;
+    for (int32_t done = 0; done < max_passes; ++done) {
+        const int64_t E_start = *E;
+        int64_t E_cur = *E, E_low = *E, best_len = 0;
+        memcpy(best, s, (size_t)n);
+        memset(locked, 0, (size_t)n);
+        for (int32_t step = 0; step < n; ++step) {
+            int32_t pick = -1;
+            int64_t pick_gain = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                if (locked[i]) continue;
+                const int64_t gain = -2 * (int64_t)s[i] * oracle_field(g, h, s, i);
+                if (pick < 0 || gain > pick_gain) {
+                    pick = i;
+                    pick_gain = gain;
+                }
+            }
+            s[pick] = (int8_t)-s[pick];
+            locked[pick] = 1;
+            E_cur -= pick_gain;
+            if (E_cur < E_low) {
+                E_low = E_cur;
+                best_len = step + 1;
+                memcpy(best, s, (size_t)n);
+            }
+        }
+        memcpy(s, best, (size_t)n);
+        *E = E_low;
+        *passes += 1;
+        *kept += best_len;
+        if (until_converged && !(E_low < E_start)) {
+            *converged = 1;
+            break;
+        }
+    }
+}
+
+/* The pass-based search on every restart of one instance.  init: draw the
+ * random starts (same start rule as oracle_run) and reset the counters.
+ * spins restarts*n external order in/out; energy out; passes, kept,
+ * converged in/out.  Returns 0; 1 if until_converged and some restart did not
+ * converge within max_passes; negative on bad input. */
+int oracle_fm(int32_t n, int64_t m, const int32_t* ei, const int32_t* ej, const int32_t* J,
+              const int32_t* h, int64_t t, const int32_t* tri, const int32_t* K, uint32_t instance_id,
+              int32_t restarts, uint64_t seed, int32_t max_passes, int32_t until_converged, int32_t init,
+              int8_t* spins, int64_t* energy, int64_t* passes, int64_t* kept, int8_t* converged,
+              int32_t threads)
+{
+    if (n < 1 || restarts < 1 || max_passes < 0) return -1;
+    oracle_graph g;
+    if (oracle_graph_build(&g, n, m, ei, ej, J, t, tri, K) != 0) { oracle_graph_free(&g); return -3; }
+    int notconv = 0;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : notconv)
+#endif
+    for (int32_t r = 0; r < restarts; ++r) {
+        int8_t* s = spins + (int64_t)r * n;
+        int8_t* locked = malloc((size_t)n);
+        int8_t* best = malloc((size_t)n);
+        if (init) {
+            for (int32_t i = 0; i < n; ++i)
+                s[i] = oracle_bit(seed, (uint32_t)i, 0xFFFFFFFFu, instance_id, (uint32_t)r) ? -1 : 1;
+            passes[r] = 0;
+            kept[r] = 0;
+            converged[r] = 0;
+        }
+        int64_t E = oracle_energy(n, m, ei, ej, J, h, t, tri, K, s);
+        oracle_fm_replica(&g, h, s, &E, max_passes, until_converged, &passes[r], &kept[r], &converged[r],
+                          locked, best);
+        energy[r] = E;
+        if (until_converged && !converged[r]) notconv += 1;
+        free(locked);
+        free(best);
+    }
+    oracle_graph_free(&g);
+    return notconv ? 1 : 0;
 }
 
 /* Best restart of one instance: lowest energy, lowest restart index on ties. */
