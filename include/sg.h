@@ -63,7 +63,18 @@ enum {
 /* Acceptance rule of a move with energy change dE. */
 enum {
     SG_RULE_GREEDY = 0,      /* flip iff dE < 0 */
-    SG_RULE_GREEDY_TIE = 1   /* also flip when dE == 0 and the sweep's RNG bit is 1 */
+    SG_RULE_GREEDY_TIE = 1,  /* also flip when dE == 0 and the sweep's RNG bit is 1 */
+    /* The paper's pass-based local search with hill-climbing (Sec. IV,
+     * Fig. 3) instead of the colour sweep: a "sweep" is one pass.  From the
+     * replica's state SP*, n times the unlocked spin of largest gain -dE
+     * (lowest spin index among equal gains) is moved, even at negative gain,
+     * and locked; the state of strictly lowest energy seen in the pass becomes
+     * SP*.  until_converged: stop after the first pass that leaves the energy
+     * unchanged (it counts).  flips counts the moves kept (the best prefix of
+     * each pass); attempts = passes x n.  Deterministic (no RNG).  Instances
+     * up to 4096 spins (else SG_EINVAL); runs under SG_SCHED_AUTO or
+     * SG_SCHED_FM only. */
+    SG_RULE_FM = 2
 };
 
 /* Execution schedules.  Every schedule computes the same result bit for bit;
@@ -75,7 +86,8 @@ enum {
                                /* 2 is reserved */
     SG_SCHED_LATTICE = 3,      /* lattice instances: LDS-resident tiles, neighbour flags */
     SG_SCHED_BLOCK = 4,        /* one workgroup per instance, structure and replicas in LDS */
-    SG_SCHED_QUEUE = 5         /* persistent batched: work queue of uneven instances */
+    SG_SCHED_QUEUE = 5,        /* persistent batched: work queue of uneven instances */
+    SG_SCHED_FM = 6            /* SG_RULE_FM: one wavefront per replica */
 };
 
 typedef struct sg_ctx* sg_handle;

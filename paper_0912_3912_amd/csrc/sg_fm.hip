@@ -1,0 +1,300 @@
+// sg_fm.hip -- the paper's pass-based local search with hill-climbing
+// (Sec. IV, Fig. 3), one wavefront per replica.
+//
+// A pass starts from the replica's state SP* and its tracked energy.  All
+// gains g_i = -dE_i = -2 s_i f_i are evaluated; then, n times, the unlocked
+// spin of largest gain (lowest external index among equal gains) is moved even
+// when its gain is negative, the gains of its coupling and hyper-coupling
+// partners are updated (a flip of s_i changes f_j by -2 J_ij s_i and
+// f_a by -2 K s_i s_b), and the spin is locked; whenever the energy is
+// strictly below the lowest seen in the pass, the prefix length is
+// remembered.  At the end of the pass the moves after the best prefix are
+// undone, so the best state seen becomes SP*.  Under until_converged the
+// search stops after the first pass that does not lower the energy of SP*
+// (that pass counts).  Counters: sweeps += passes, flips += moves kept,
+// attempts = passes x n.
+//
+// Layout: the wavefront keeps the replica's gains (int32), spins (int8), the
+// move list, and two index tables (internal index -> slice, -> external
+// index) in its own LDS slice; couplings and hyper-couplings stay in the
+// sliced layout in device memory (read through the cache, one word per lane
+// per partner).  Lane l owns the internal indices l, l + 64, ...; it caches
+// the best key of its unlocked spins, key = (gain + 2^30) << 32 | ~ext, and
+// rescans its spins only when one of their gains changed or one was locked.
+// The move is the wave-wide maximum key.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_device.h"
+#include "sg_launch.h"
+#include "sg_layout.h"
+
+namespace sg {
+
+constexpr int kFmThreads = 1024;
+constexpr int kFmWaves = kFmThreads / 64;
+constexpr int kFmGainBias = 1 << 30;
+
+__host__ __device__ inline size_t fm_wave_bytes(int nmax)
+{
+    const size_t n4 = ((size_t)nmax + 3) & ~(size_t)3;
+    return 4 * n4 + n4 + 2 * n4 + 2 * n4 + 2 * n4 + 16;  // gain, spin, move, slice, ext, dirty mask
+}
+
+__device__ __forceinline__ uint64_t fm_key(int gain, int ext)
+{
+    return ((uint64_t)(uint32_t)(gain + kFmGainBias) << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)ext);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void wave_lds_order()
+{
+    // LDS operations of one wavefront complete in issue order; this keeps the
+    // compiler from moving them across the point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool TRI>
+__global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ tab, const int32_t* __restrict__ ctab,
+                                                   const QueueItem* __restrict__ items, int nitems, int nmax,
+                                                   int waves_per_block, RepState* __restrict__ rs,
+                                                   CallStats* __restrict__ cs, uint32_t* __restrict__ err,
+                                                   int max_passes, int until_conv)
+{
+    extern __shared__ uint8_t fm_lds[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * waves_per_block + wave;
+    long long att = 0, kept_all = 0;
+    long long passes_done = 0;
+    int unconv = 0;
+    if (wave < waves_per_block && item < nitems) {
+        const QueueItem it = items[item];
+        const InstTab& Q = tab[it.inst];
+        const InstDev& I = Q.I;
+        const int n = I.n;
+        RepState* st = rs + Q.rep_base + it.r;
+        if (!st->converged) {
+            const size_t n4 = ((size_t)nmax + 3) & ~(size_t)3;
+            uint8_t* base = fm_lds + (size_t)wave * fm_wave_bytes(nmax);
+            int* gain = reinterpret_cast<int*>(base);
+            int8_t* spin = reinterpret_cast<int8_t*>(base + 4 * n4);
+            uint16_t* moves = reinterpret_cast<uint16_t*>(base + 5 * n4);
+            uint16_t* slice_of = reinterpret_cast<uint16_t*>(base + 7 * n4);
+            uint16_t* ext = reinterpret_cast<uint16_t*>(base + 9 * n4);
+            uint32_t* dirty = reinterpret_cast<uint32_t*>(base + 11 * n4);
+            int8_t* gs = Q.spins + Q.spin_stride * it.r;
+            const int G = (n + 63) >> 6;
+            // index tables and spins
+            for (int c = 0; c < Q.C; ++c) {
+                const int s0 = ctab[Q.ctab_off + c], s1 = ctab[Q.ctab_off + c + 1];
+                for (int sl = s0; sl < s1; ++sl) {
+                    const Slice S = I.slices[sl];
+                    if (lane < S.rows) slice_of[S.row0 + lane] = (uint16_t)sl;
+                }
+            }
+            for (int i = lane; i < n; i += 64) {
+                ext[i] = (uint16_t)I.ext[i];
+                spin[i] = gs[i];
+            }
+            if (lane < 2) dirty[lane] = 0u;
+            wave_lds_order();
+            long long Estar = st->E;
+            int passes = 0;
+            long long kept = 0;
+            bool conv = false, bad = false;
+            for (int pass = 0; pass < max_passes && !bad; ++pass) {
+                // gains from the definition, and this lane's best unlocked key
+                for (int i = lane; i < n; i += 64) {
+                    const Slice S = I.slices[slice_of[i]];
+                    const int l = i - (int)S.row0;
+                    int f = I.h[i];
+                    const uint32_t* p = I.nbr + S.ebase + l;
+                    for (int k = 0; k < S.ew; ++k) {
+                        const uint32_t w = p[k * kSlice];
+                        f += (int)(int8_t)(w & 0xffu) * spin[w >> 8];
+                    }
+                    if (TRI) {
+                        const uint32_t* pa = I.ta + S.tbase + l;
+                        const uint32_t* pb = I.tb + S.tbase + l;
+                        for (int k = 0; k < S.tw; ++k) {
+                            const uint32_t wa = pa[k * kSlice];
+                            f += (int)(int8_t)(wa & 0xffu) * spin[wa >> 8] * spin[pb[k * kSlice]];
+                        }
+                    }
+                    gain[i] = -2 * spin[i] * f;
+                }
+                wave_lds_order();
+                uint64_t locked = 0;
+                uint64_t best = 0;
+                for (int k = 0; k < G; ++k) {
+                    const int i = lane + 64 * k;
+                    if (i < n) {
+                        const uint64_t key = fm_key(gain[i], ext[i]);
+                        best = key > best ? key : best;
+                    }
+                }
+                long long E = Estar, Elow = Estar;
+                int best_len = 0;
+                for (int step = 0; step < n; ++step) {
+                    const uint64_t top = wave_max_u64(best);
+                    const int g = (int)(uint32_t)(top >> 32) - kFmGainBias;
+                    // internal index of the move: the lane whose cached key is the
+                    // maximum owns it; it scans its spins for the matching key
+                    const uint64_t own = __ballot(best == top);
+                    const int owner = (int)__builtin_ctzll(own);
+                    int mine = -1;
+                    if (lane == owner) {
+                        for (int k = 0; k < G; ++k) {
+                            const int i = lane + 64 * k;
+                            if (i < n && !((locked >> k) & 1ull) && fm_key(gain[i], ext[i]) == top) mine = i;
+                        }
+                    }
+                    const int i = __shfl(mine, owner, 64);
+                    if (i < 0) {  // a cached key without its spin: internal error, stop this replica
+                        bad = true;
+                        break;
+                    }
+                    const int s_old = spin[i];
+                    const Slice S = I.slices[slice_of[i]];
+                    const int l = i - (int)S.row0;
+                    for (int k = lane; k < S.ew; k += 64) {
+                        const uint32_t w = I.nbr[S.ebase + k * kSlice + l];
+                        const int J = (int)(int8_t)(w & 0xffu);
+                        if (J) {
+                            const int j = (int)(w >> 8);
+                            atomicAdd(gain + j, 4 * spin[j] * J * s_old);
+                            atomicOr(dirty + ((j & 63) >> 5), 1u << (j & 31));
+                        }
+                    }
+                    if (TRI) {
+                        for (int k = lane; k < S.tw; k += 64) {
+                            const uint32_t wa = I.ta[S.tbase + k * kSlice + l];
+                            const int K = (int)(int8_t)(wa & 0xffu);
+                            if (K) {
+                                const int a = (int)(wa >> 8);
+                                const int b = (int)I.tb[S.tbase + k * kSlice + l];
+                                const int sa = spin[a], sb = spin[b];
+                                atomicAdd(gain + a, 4 * sa * K * sb * s_old);
+                                atomicAdd(gain + b, 4 * sb * K * sa * s_old);
+                                atomicOr(dirty + ((a & 63) >> 5), 1u << (a & 31));
+                                atomicOr(dirty + ((b & 63) >> 5), 1u << (b & 31));
+                            }
+                        }
+                    }
+                    wave_lds_order();
+                    const uint32_t dm = dirty[lane >> 5];
+                    bool rescan = (dm >> (lane & 31)) & 1u;
+                    if (lane == owner) {
+                        locked |= 1ull << (i >> 6);
+                        spin[i] = (int8_t)-s_old;
+                        moves[step] = (uint16_t)i;
+                        rescan = true;
+                    }
+                    wave_lds_order();
+                    if (lane < 2) dirty[lane] = 0u;
+                    if (rescan) {
+                        best = 0;
+                        for (int k = 0; k < G; ++k) {
+                            const int ii = lane + 64 * k;
+                            if (ii < n && !((locked >> k) & 1ull)) {
+                                const uint64_t key = fm_key(gain[ii], ext[ii]);
+                                best = key > best ? key : best;
+                            }
+                        }
+                    }
+                    E -= g;
+                    if (E < Elow) {
+                        Elow = E;
+                        best_len = step + 1;
+                    }
+                    wave_lds_order();
+                }
+                if (bad) break;
+                // undo the moves after the best prefix
+                for (int t = best_len + lane; t < n; t += 64) {
+                    const int i = moves[t];
+                    spin[i] = (int8_t)-spin[i];
+                }
+                wave_lds_order();
+                ++passes;
+                kept += best_len;
+                const bool improved = Elow < Estar;
+                Estar = Elow;
+                if (until_conv && !improved) {
+                    conv = true;
+                    break;
+                }
+            }
+            if (bad && lane == 0) atomicOr(err, 1u);
+            for (int i = lane; i < n && !bad; i += 64) gs[i] = spin[i];
+            if (lane == 0 && !bad) {
+                st->E = Estar;
+                st->sweeps += passes;
+                st->flips += kept;
+                if (conv) st->converged = 1;
+            }
+            att = (long long)passes * n;
+            kept_all = kept;
+            passes_done = passes;
+            unconv = (until_conv && !conv) ? 1 : 0;
+        }
+    }
+    // call totals: one atomic per block
+    __shared__ long long b_att, b_kept, b_passes;
+    __shared__ int b_unconv;
+    if (threadIdx.x == 0) {
+        b_att = 0;
+        b_kept = 0;
+        b_passes = 0;
+        b_unconv = 0;
+    }
+    __syncthreads();
+    if (lane == 0 && (att || unconv)) {
+        atomicAdd((unsigned long long*)&b_att, (unsigned long long)att);
+        atomicAdd((unsigned long long*)&b_kept, (unsigned long long)kept_all);
+        atomicMax((unsigned long long*)&b_passes, (unsigned long long)passes_done);
+        atomicAdd(&b_unconv, unconv);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && (b_att || b_unconv)) {
+        atomicAdd(&cs->attempts, (unsigned long long)b_att);
+        atomicAdd(&cs->flips, (unsigned long long)b_kept);
+        atomicMax(&cs->sweeps_max, (unsigned long long)b_passes);
+        atomicAdd(&cs->unconverged, (unsigned long long)b_unconv);
+    }
+}
+
+size_t fm_lds_bytes(int nmax, int waves) { return fm_wave_bytes(nmax) * (size_t)waves; }
+
+hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
+                     bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv,
+                     hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (waves < 1 || waves > kFmWaves) return hipErrorInvalidValue;
+    const size_t lds = fm_lds_bytes(nmax, waves);
+    const void* kern = tri ? (const void*)k_fm<true> : (const void*)k_fm<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (nitems + waves - 1) / waves;
+    if (tri)
+        hipLaunchKernelGGL(k_fm<true>, dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax, waves,
+                           rs, cs, err, max_passes, until_conv);
+    else
+        hipLaunchKernelGGL(k_fm<false>, dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax, waves,
+                           rs, cs, err, max_passes, until_conv);
+    return hipGetLastError();
+}
+
+}  // namespace sg

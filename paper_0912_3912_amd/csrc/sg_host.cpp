@@ -55,6 +55,7 @@ constexpr int64_t kMaxField = (1 << 23) - 1;
 constexpr int32_t kMaxRestarts = 65535;
 constexpr int32_t kMaxLatticeTiles = 1024;
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
+constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
 constexpr int32_t kBatchInitMaxN = 65536;  // instances below this size start and evaluate in batched launches
 
 struct HostInst {
@@ -1100,6 +1101,69 @@ int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& 
     return first;
 }
 
+// The pass-based search (SG_RULE_FM): every replica of every instance is one
+// wavefront item, largest instances first.
+sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
+{
+    if (p->schedule != SG_SCHED_AUTO && p->schedule != SG_SCHED_FM)
+        return fail(SG_EINVAL, "rule SG_RULE_FM runs under SG_SCHED_AUTO or SG_SCHED_FM only");
+    int nmax = 1;
+    bool tri = false;
+    for (const HostInst& q : H->insts) {
+        if (q.n > kFmMaxN) return fail(SG_EINVAL, "rule SG_RULE_FM: instance of %d spins (at most %d)", q.n, kFmMaxN);
+        nmax = std::max(nmax, q.n);
+        tri = tri || q.t > 0;
+    }
+    hipStream_t st = H->stream;
+    H->h_qitems.clear();
+    for (size_t k = 0; k < H->insts.size(); ++k)
+        for (int32_t r = 0; r < H->insts[k].R; ++r) H->h_qitems.push_back(sg::QueueItem{(int32_t)k, r});
+    std::stable_sort(H->h_qitems.begin(), H->h_qitems.end(), [&](const sg::QueueItem& a, const sg::QueueItem& b) {
+        return H->insts[a.inst].n > H->insts[b.inst].n;
+    });
+    int waves = 16;
+    while (waves > 1 && sg::fm_lds_bytes(nmax, waves) > kLdsBudget) --waves;
+    sg::QueueItem* dit = H->at<sg::QueueItem>(H->off_qitems);
+    uint32_t* err = H->at<uint32_t>(H->off_err);
+    SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
+    SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
+    SG_HIP(hipMemcpyAsync(dit, H->h_qitems.data(), H->h_qitems.size() * sizeof(sg::QueueItem), hipMemcpyHostToDevice,
+                          st),
+           "upload items");
+    SG_HIP(hipEventRecord(H->ev0, st), "event record");
+    SG_HIP(hipEventRecord(H->evh0, st), "event record");
+    if (p->max_sweeps > 0)
+        SG_HIP(sg::launch_fm(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
+                             (int)H->h_qitems.size(), nmax, waves, tri, H->reps(), H->at<sg::CallStats>(H->off_stats),
+                             err, p->max_sweeps, p->until_converged, st),
+               "pass kernel");
+    SG_HIP(hipEventRecord(H->evh1, st), "event record");
+    SG_HIP(hipEventRecord(H->ev1, st), "event record");
+    H->hot_launches = p->max_sweeps > 0 ? 1 : 0;
+    sg::CallStats cs;
+    uint32_t herr = 0;
+    SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
+    SG_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st), "error flag copy");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    if (herr) return fail(SG_EDEVICE, "pass kernel: internal error (a selected move had no spin)");
+    float ms = 0.f;
+    SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
+    float hms = 0.f;
+    H->hot_us = hipEventElapsedTime(&hms, H->evh0, H->evh1) == hipSuccess ? hms * 1000.0 : 0.0;
+    if (stats) {
+        stats->attempts = (int64_t)cs.attempts;
+        stats->flips = (int64_t)cs.flips;
+        stats->sweeps_max = (int64_t)cs.sweeps_max;
+        stats->n_unconverged = (int32_t)cs.unconverged;
+        stats->schedule_used = SG_SCHED_FM;
+        stats->kernel_ms = ms;
+    }
+    if (p->until_converged && cs.unconverged)
+        return fail(SG_ENOTCONV, "%llu replicas did not converge within %d passes", (unsigned long long)cs.unconverged,
+                    p->max_sweeps);
+    return SG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1313,10 +1377,12 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     sg_status e = need_bound(H);
     if (e != SG_OK) return e;
     if (!p) return fail(SG_EINVAL, "sg_run_sweeps: null params");
-    if (p->rule != SG_RULE_GREEDY && p->rule != SG_RULE_GREEDY_TIE) return fail(SG_EINVAL, "unknown rule %d", p->rule);
+    if (p->rule != SG_RULE_GREEDY && p->rule != SG_RULE_GREEDY_TIE && p->rule != SG_RULE_FM)
+        return fail(SG_EINVAL, "unknown rule %d", p->rule);
     if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
     for (uint8_t v : H->started)
         if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
+    if (p->rule == SG_RULE_FM) return run_fm(H, p, stats);
     std::vector<int> assign;
     const int sched = assign_schedules(H, p, assign);
     if (sched < 0 && p->schedule != SG_SCHED_AUTO)

@@ -41,6 +41,11 @@ int lattice_msc_max_blocks(const TileGeom& tg, const int L[3], int D);
 hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint32_t* G0,
                               uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
                               int nslots, int T, uint64_t seed, int rule, hipStream_t st);
+// The paper's pass-based search, one wavefront per replica item.
+size_t fm_lds_bytes(int nmax, int waves);
+hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
+                     bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv,
+                     hipStream_t st);
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
                              int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
 

@@ -1,0 +1,120 @@
+"""GPU parity of the paper's pass-based local search (rule SG_RULE_FM: one
+wavefront per replica, max-gain moves with locking and hill-climbing, best
+prefix kept, passes until no improvement) against the CPU oracle, bit for
+bit: spins, tracked and recomputed energies, pass counts, moves kept,
+converged flags."""
+import numpy as np
+import pytest
+
+import instances as gen
+import oracle
+from parity import compare, log
+
+pytestmark = pytest.mark.gpu
+
+FM = 2
+
+
+def _oracle(insts, seed, max_passes, uc, runs=None, threads=0):
+    out = []
+    for inst in insts:
+        st = None
+        for mp in (runs or [max_passes]):
+            st, _ = oracle.fm(inst, seed=seed, max_passes=mp, until_converged=uc, state=st, threads=threads)
+        out.append(st)
+    return out
+
+
+def _check(insts, seed, max_passes=1000, uc=True, runs=None):
+    import paper_0912_3912_amd as sg
+    log(f"fm case: {[i.name for i in insts][:4]} seed={seed} passes={runs or max_passes} uc={uc}")
+    h = sg.load_instance(list(insts)).bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=FM, max_sweeps=mp, until_converged=uc) for mp in (runs or [max_passes])]
+    assert all(s["schedule_used"] == sg.SCHED_FM for s in stats)
+    states = _oracle(insts, seed, max_passes, uc, runs)
+    compare(h, insts, states)
+    if runs is None:
+        assert stats[0]["attempts"] == sum(int((st.sweeps * i.n).sum()) for i, st in zip(insts, states))
+        assert stats[0]["flips"] == sum(int(st.flips.sum()) for st in states)
+    return h
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 129, 700])
+def test_ragged_random_with_triples(gpu, n):
+    inst = gen.random_small(n, seed=n, p_edge=min(1.0, 8.0 / max(n, 1)), n_triples=n // 2, j_range=(-15, 15),
+                            h_range=(-7, 7), k_range=(-7, 7)).replace(restarts=4, instance_id=n)
+    _check([inst], seed=n + 3)
+
+
+def test_chimera_with_triples(gpu):
+    _check([gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)], seed=11)
+
+
+def test_lattice_and_regular(gpu):
+    _check([gen.lattice((16, 16), seed=2, restarts=3), gen.random_regular3(1000, seed=4, instance_id=9)], seed=5)
+
+
+def test_fixed_pass_budget_and_resume(gpu):
+    inst = gen.erdos_renyi_triples(900, seed=7, restarts=3)
+    _check([inst], seed=2, max_passes=2, uc=False)
+    _check([inst], seed=2, uc=True, runs=[1, 2, 0, 1000])
+
+
+def test_mixed_batch(gpu):
+    insts = [gen.chimera(6, 6, seed=s, instance_id=s, restarts=3) for s in range(3)]
+    insts += [gen.random_small(40, seed=1, instance_id=77).replace(restarts=2), gen.erdos_renyi_triples(3000, seed=8)]
+    _check(insts, seed=9)
+
+
+def test_errors(gpu):
+    import paper_0912_3912_amd as sg
+    big = gen.erdos_renyi_triples(5000, seed=1)
+    h = sg.load_instance([big]).bind()
+    h.init_spins(1)
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1, rule=FM)
+    assert e.value.status == sg.SG_EINVAL
+    h2 = sg.load_instance([gen.chimera(2, 2, seed=1)]).bind()
+    h2.init_spins(1)
+    with pytest.raises(sg.SGError) as e:
+        h2.run_sweeps(seed=1, rule=FM, schedule=sg.SCHED_QUEUE)
+    assert e.value.status == sg.SG_EINVAL
+
+
+def test_chimera_batch_full_size(gpu):
+    """4096 Chimera instances x 256 restarts in one launch: sampled replicas
+    bit-exact against the oracle; every replica's tracked energy equals a
+    recomputation, and every result is a single-flip local minimum."""
+    import paper_0912_3912_amd as sg
+    insts = gen.cfg3_chimera_batch()
+    h = sg.load_instance(insts).bind()
+    h.init_spins(7)
+    st = h.run_sweeps(seed=7, rule=FM, max_sweeps=1000, until_converged=True)
+    log(f"fm chimera4096x256: {st['kernel_ms']:.1f} ms, passes max {st['sweeps_max']}, attempts {st['attempts']}")
+    E = h.energy()
+    assert np.array_equal(E, h.energy(recompute=True))
+    sw, fl, cv = h.counters()
+    assert cv.all()
+    rng = np.random.default_rng(1)
+    picks = sorted({int(v) for v in rng.integers(0, len(insts), 32)})
+    for q in picks:
+        inst = insts[q]
+        rs = sorted({int(v) for v in rng.integers(0, inst.restarts, 4)})
+        sub = inst.replace(restarts=max(rs) + 1)
+        ref, _ = oracle.fm(sub, seed=7, threads=8)
+        S = h.spins_out_batch(q, 0, max(rs) + 1)
+        base = h.info(q)["replica_base"]
+        for r in rs:
+            assert np.array_equal(S[r], ref.spins[r]), (q, r)
+            assert int(E[base + r]) == int(ref.energy[r]) and int(sw[base + r]) == int(ref.sweeps[r])
+            assert int(fl[base + r]) == int(ref.flips[r])
+    # the same starts under a fixed budget of the largest pass count: passes
+    # after convergence change nothing, and the replicas are not frozen, so
+    # one GREEDY sweep from the results must flip nothing
+    h.init_spins(7)
+    st2 = h.run_sweeps(seed=7, rule=FM, max_sweeps=int(st["sweeps_max"]), until_converged=False)
+    assert np.array_equal(h.energy(), E)
+    g = h.run_sweeps(seed=7, rule=0, max_sweeps=1, until_converged=False)
+    assert g["attempts"] == sum(i.n * i.restarts for i in insts) and g["flips"] == 0
+    log(f"fixed budget run: {st2['kernel_ms']:.1f} ms")
