@@ -87,7 +87,9 @@ enum {
     SG_SCHED_LATTICE = 3,      /* lattice instances: LDS-resident tiles, neighbour flags */
     SG_SCHED_BLOCK = 4,        /* one workgroup per instance, structure and replicas in LDS */
     SG_SCHED_QUEUE = 5,        /* persistent batched: work queue of uneven instances */
-    SG_SCHED_FM = 6            /* SG_RULE_FM: one wavefront per replica */
+    SG_SCHED_FM = 6,           /* SG_RULE_FM: one wavefront per replica */
+    SG_SCHED_FIELDS = 7        /* SG_SCHED_PHASE over local fields kept in the workspace and
+                                  updated by the flips (knob "fields" = 1 before sg_bind) */
 };
 
 typedef struct sg_ctx* sg_handle;
@@ -257,6 +259,12 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        (32 sites of a colour per lane word); 0: byte kernel
  *   "msc_k"              halo width of the bit-plane kernel (0 = chosen by
  *                        its cost model, else 1..62)
+ *   "fields"             1: the workspace also holds each replica's local
+ *                        fields (4 bytes per spin per replica) and
+ *                        SG_SCHED_FIELDS becomes available (SG_SCHED_AUTO
+ *                        then uses it where it would use SG_SCHED_PHASE);
+ *                        changes sg_workspace_bytes, so it must be set
+ *                        before sg_bind (SG_EINVAL after)
  * Unknown key or value out of range: SG_EINVAL. */
 sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 

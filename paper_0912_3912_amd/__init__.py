@@ -26,13 +26,14 @@ import numpy as np
 
 __all__ = [
     "GREEDY", "GREEDY_TIE", "FM", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH",
-    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SGError", "Handle", "load_instance",
+    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SCHED_FIELDS", "SGError", "Handle", "load_instance",
     "run_sweeps", "energy", "spins_out", "library_path", "lib",
 ]
 
 SG_OK, SG_ENOTCONV, SG_EINVAL, SG_ERANGE, SG_ENOMEM, SG_EDEVICE, SG_ESTATE = 0, 1, -1, -2, -3, -4, -5
 GREEDY, GREEDY_TIE, FM = 0, 1, 2
-SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE, SCHED_FM = -1, 0, 1, 3, 4, 5, 6
+SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE, SCHED_FM, SCHED_FIELDS = (
+    -1, 0, 1, 3, 4, 5, 6, 7)
 _STATUS = {SG_EINVAL: "SG_EINVAL", SG_ERANGE: "SG_ERANGE", SG_ENOMEM: "SG_ENOMEM",
            SG_EDEVICE: "SG_EDEVICE", SG_ESTATE: "SG_ESTATE", SG_ENOTCONV: "SG_ENOTCONV"}
 

@@ -90,6 +90,7 @@ struct HostInst {
     // workspace offsets (bytes)
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
+    uint64_t off_fields = 0, field_stride = 0;  // maintained local fields (ints per replica), when enabled
 };
 
 }  // namespace
@@ -113,6 +114,7 @@ struct sg_ctx {
     int32_t lattice_msc = 1;           // use the bit-plane tile kernel where it applies
     int32_t msc_k = 0;                 // its halo width (0 = chosen by the cost model)
     int32_t last_msc = 0;              // the last tile launch used the bit-plane kernel
+    int32_t fields_ws = 0;             // workspace holds local fields per replica (SG_SCHED_FIELDS)
     hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
     uint64_t off_tbase = 0;            // one sweep base per instance (graph replays)
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
@@ -546,6 +548,8 @@ void layout(sg_ctx* H)
         q.spin_stride = align_up((uint64_t)q.n);
         q.off_spins = take(q.spin_stride * (uint64_t)q.R);
         q.off_acc = take((uint64_t)q.R * q.acc_slots * 16);
+        q.field_stride = H->fields_ws ? align_up((uint64_t)q.n * 4) / 4 : 0;
+        q.off_fields = H->fields_ws ? take(q.field_stride * 4 * (uint64_t)q.R) : 0;
         if (q.lat_ok) {
             q.off_lat_rec = take((uint64_t)q.n * 8);
             // two copies of one word per interior z-row of every tile (z extent >= 4 sites)
@@ -605,7 +609,7 @@ sg_status check_inst(sg_handle H, int32_t inst, int32_t r)
 // ---------------------------------------------------------------------------
 // run driver: one kernel launch per colour phase, instance by instance
 
-sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
+sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which, bool inc = false)
 {
     hipStream_t st = H->stream;
     sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
@@ -621,13 +625,16 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
             SG_HIP(hipEventRecord(H->evh0, st), "event record");
             H->hot_launches = 0;
         }
+        int32_t* F = inc ? H->at<int32_t>(q.off_fields) : nullptr;
+        const int64_t fstride = (int64_t)q.field_stride;
+        if (inc) SG_HIP(sg::launch_fields(I, spins, (int64_t)q.spin_stride, q.R, F, fstride, st), "field kernel");
         int T = 0;
         auto sweeps = [&](int from, int to) -> sg_status {
             for (int t = from; t < to; ++t)
                 for (int32_t c = 0; c < q.C; ++c) {
                     const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
                     SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, t,
-                                            p->seed, p->rule, p->until_converged, st),
+                                            p->seed, p->rule, p->until_converged, st, nullptr, F, fstride),
                            "phase kernel");
                     H->hot_launches++;
                 }
@@ -1083,10 +1090,11 @@ int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& 
             if (can_lattice(H, q, p)) s = SG_SCHED_LATTICE;
             else if (q.R >= H->block_min_restarts && can_block(H, q)) s = SG_SCHED_BLOCK;
             else if (can_queue(q) && queue_items >= H->queue_min_items) s = SG_SCHED_QUEUE;
-            else s = SG_SCHED_PHASE;
+            else s = H->fields_ws ? SG_SCHED_FIELDS : SG_SCHED_PHASE;
             break;
         case SG_SCHED_PHASE: s = SG_SCHED_PHASE; break;
         case SG_SCHED_GRAPH: s = SG_SCHED_GRAPH; break;
+        case SG_SCHED_FIELDS: s = H->fields_ws ? SG_SCHED_FIELDS : -1; break;
         case SG_SCHED_LATTICE: s = can_lattice(H, q, p) ? SG_SCHED_LATTICE : -1; break;
         case SG_SCHED_BLOCK: s = can_block(H, q) ? SG_SCHED_BLOCK : -1; break;
         case SG_SCHED_QUEUE: s = can_queue(q) ? SG_SCHED_QUEUE : -1; break;
@@ -1392,7 +1400,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
     H->hot_launches = 0;
-    for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_GRAPH, SG_SCHED_PHASE}) {
+    for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_GRAPH, SG_SCHED_FIELDS, SG_SCHED_PHASE}) {
         std::vector<int> which;
         for (size_t k = 0; k < assign.size(); ++k)
             if (assign[k] == kind) which.push_back((int)k);
@@ -1402,6 +1410,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
         case SG_SCHED_BLOCK: e = run_block_schedule(H, p, which); break;
         case SG_SCHED_QUEUE: e = run_queue_schedule(H, p, which); break;
         case SG_SCHED_GRAPH: e = run_graph_schedule(H, p, which); break;
+        case SG_SCHED_FIELDS: e = run_phase_schedule(H, p, which, true); break;
         default: e = run_phase_schedule(H, p, which); break;
         }
         if (e != SG_OK) return e;
@@ -1567,6 +1576,11 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "msc_k") {
         if (value < 0 || value > 62) return fail(SG_EINVAL, "msc_k must be in [0,62]");
         H->msc_k = (int32_t)value;
+    } else if (k == "fields") {
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "fields must be 0 or 1");
+        if (H->bound) return fail(SG_EINVAL, "fields changes the workspace: set it before sg_bind");
+        H->fields_ws = (int32_t)value;
+        layout(H);
     } else if (k == "graph_sweeps") {
         if (value < 1 || value > 1024) return fail(SG_EINVAL, "graph_sweeps must be in [1,1024]");
         H->graph_sweeps = (int32_t)value;
@@ -1592,6 +1606,7 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "queue_grid") *value = H->queue_grid;
     else if (k == "queue_min_items") *value = H->queue_min_items;
     else if (k == "graph_sweeps") *value = H->graph_sweeps;
+    else if (k == "fields") *value = H->fields_ws;
     else if (k == "lattice_msc") *value = H->lattice_msc;
     else if (k == "msc_k") *value = H->msc_k;
     else if (k == "last_msc") *value = H->last_msc;

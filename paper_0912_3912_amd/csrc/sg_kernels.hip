@@ -180,17 +180,44 @@ __device__ __forceinline__ int local_field(const InstDev& I, const Slice& S, int
     return f;
 }
 
+// Local fields of every spin of every replica (the start of a run over
+// maintained fields): grid = (ceil(nslices/4), R).
+template <bool TRI>
+__global__ __launch_bounds__(kPhaseThreads) void k_fields(InstDev I, const int8_t* __restrict__ spins,
+                                                          int64_t stride, int32_t* __restrict__ fields,
+                                                          int64_t fstride)
+{
+    const int r = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = blockIdx.x * kPhaseWaves + wave;
+    if (sl >= I.nslices) return;
+    const Slice S = I.slices[sl];
+    if (lane < S.rows) {
+        const int i = S.row0 + lane;
+        fields[(int64_t)r * fstride + i] = local_field<TRI>(I, S, lane, i, spins + (int64_t)r * stride);
+    }
+}
+
 // One colour phase of one instance (the plain method): grid = (ceil(slices_c/4), R),
 // block = 4 wavefronts, wavefront w of block x handles slice slice0 + 4x + w.
 // t_rel = t_local + (*t_base when t_base is not null): graph replays keep the
 // launch arguments fixed and advance the base in device memory.
-template <bool TIE, bool TRI>
+//
+// INC (maintained fields, the "only the neighbours' gains change" idea of
+// Sec. IV): f_i is read from the replica's field array instead of being
+// summed over the couplings, and a spin that flips adds the change of its
+// partners' fields, -2 J_ij s_i to f_j and -2 K s_i s_b to f_a for a triple
+// (i, a, b), with integer atomics.  Partners have other colours (proper
+// colouring), so every field read in a phase is exact; a phase with few
+// flips moves a few bytes per spin instead of the coupling stream.
+template <bool TIE, bool TRI, bool INC>
 __global__ __launch_bounds__(kPhaseThreads) void k_phase(InstDev I, int8_t* __restrict__ spins,
                                                          int64_t stride, RepState* __restrict__ rs,
                                                          int64_t* __restrict__ acc, int nslots,
                                                          int slice0, int nslice_c, int t_local,
                                                          const int32_t* __restrict__ t_base,
-                                                         uint64_t seed, int until_conv)
+                                                         uint64_t seed, int until_conv,
+                                                         int32_t* __restrict__ fields, int64_t fstride)
 {
     const int t_rel = t_local + (t_base ? *t_base : 0);
     const int r = blockIdx.y;
@@ -205,7 +232,8 @@ __global__ __launch_bounds__(kPhaseThreads) void k_phase(InstDev I, int8_t* __re
         const Slice S = I.slices[slice0 + sl];
         if (lane < S.rows) {
             const int i = S.row0 + lane;
-            const int f = local_field<TRI>(I, S, lane, i, s);
+            int32_t* F = INC ? fields + (int64_t)r * fstride : nullptr;
+            const int f = INC ? F[i] : local_field<TRI>(I, S, lane, i, s);
             const int si = s[i];
             const int d = 2 * si * f;
             flip = d < 0;
@@ -216,6 +244,27 @@ __global__ __launch_bounds__(kPhaseThreads) void k_phase(InstDev I, int8_t* __re
             if (flip) {
                 s[i] = (int8_t)(-si);
                 dflip = d;
+                if (INC) {
+                    const uint32_t* p = I.nbr + S.ebase + lane;
+                    for (int k = 0; k < S.ew; ++k) {
+                        const uint32_t w = p[k * kSlice];
+                        const int J = coupling_j(w);
+                        if (J) atomicAdd(F + (w >> 8), -2 * J * si);
+                    }
+                    if (TRI) {
+                        const uint32_t* pa = I.ta + S.tbase + lane;
+                        const uint32_t* pb = I.tb + S.tbase + lane;
+                        for (int q = 0; q < S.tw; ++q) {
+                            const uint32_t wa = pa[q * kSlice];
+                            const int K = coupling_j(wa);
+                            if (K) {
+                                const int a = (int)(wa >> 8), b = (int)pb[q * kSlice];
+                                atomicAdd(F + a, -2 * K * si * s[b]);
+                                atomicAdd(F + b, -2 * K * si * s[a]);
+                            }
+                        }
+                    }
+                }
             }
         }
     }
@@ -372,22 +421,36 @@ hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStre
 
 hipError_t launch_phase(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, int64_t* acc,
                         int nslots, int slice0, int nslice_c, int t_rel, uint64_t seed, int rule,
-                        int until_conv, hipStream_t st, const int32_t* t_base)
+                        int until_conv, hipStream_t st, const int32_t* t_base, int32_t* fields, int64_t fstride)
 {
     const dim3 grid((nslice_c + kPhaseWaves - 1) / kPhaseWaves, R);
     const bool tie = rule == 1, tri = I.has_tri != 0;
-    if (tie && tri)
-        hipLaunchKernelGGL((k_phase<true, true>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
-    else if (tie)
-        hipLaunchKernelGGL((k_phase<true, false>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
-    else if (tri)
-        hipLaunchKernelGGL((k_phase<false, true>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
+#define SG_PHASE_LAUNCH(TIE_, TRI_, INC_)                                                                          \
+    hipLaunchKernelGGL((k_phase<TIE_, TRI_, INC_>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,  \
+                       nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv, fields, fstride)
+    if (fields) {
+        if (tie && tri) SG_PHASE_LAUNCH(true, true, true);
+        else if (tie) SG_PHASE_LAUNCH(true, false, true);
+        else if (tri) SG_PHASE_LAUNCH(false, true, true);
+        else SG_PHASE_LAUNCH(false, false, true);
+    } else {
+        if (tie && tri) SG_PHASE_LAUNCH(true, true, false);
+        else if (tie) SG_PHASE_LAUNCH(true, false, false);
+        else if (tri) SG_PHASE_LAUNCH(false, true, false);
+        else SG_PHASE_LAUNCH(false, false, false);
+    }
+#undef SG_PHASE_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const InstDev& I, const int8_t* spins, int64_t stride, int R, int32_t* fields, int64_t fstride,
+                         hipStream_t st)
+{
+    const dim3 grid((I.nslices + kPhaseWaves - 1) / kPhaseWaves, R);
+    if (I.has_tri)
+        hipLaunchKernelGGL((k_fields<true>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, fields, fstride);
     else
-        hipLaunchKernelGGL((k_phase<false, false>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, rs, acc,
-                           nslots, slice0, nslice_c, t_rel, t_base, seed, until_conv);
+        hipLaunchKernelGGL((k_fields<false>), grid, dim3(kPhaseThreads), 0, st, I, spins, stride, fields, fstride);
     return hipGetLastError();
 }
 

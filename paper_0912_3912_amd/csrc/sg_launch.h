@@ -14,10 +14,15 @@ hipError_t launch_init(const InstDev& I, int8_t* spins, int64_t stride, RepState
 hipError_t launch_energy(const InstDev& I, const int8_t* spins, int64_t stride, int R, int64_t* slots,
                          int nslots, RepState* rs, int64_t* out, hipStream_t st);
 hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStream_t st);
-// t_rel is relative to *t_base when t_base is not null (graph replays).
+// t_rel is relative to *t_base when t_base is not null (graph replays);
+// with fields not null the phase reads and maintains the replicas' local
+// fields (fstride ints between replicas) instead of summing the couplings.
 hipError_t launch_phase(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, int64_t* acc,
                         int nslots, int slice0, int nslice_c, int t_rel, uint64_t seed, int rule,
-                        int until_conv, hipStream_t st, const int32_t* t_base = nullptr);
+                        int until_conv, hipStream_t st, const int32_t* t_base = nullptr, int32_t* fields = nullptr,
+                        int64_t fstride = 0);
+hipError_t launch_fields(const InstDev& I, const int8_t* spins, int64_t stride, int R, int32_t* fields, int64_t fstride,
+                         hipStream_t st);
 hipError_t launch_bump(int32_t* t_base, int d, hipStream_t st);
 hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T, int until_conv, int64_t n,
                       CallStats* cs, hipStream_t st);

@@ -163,3 +163,50 @@ def test_graph_schedule_batch_until_converged(gpu):
     insts = [gen.chimera(6, 6, seed=s, instance_id=s, restarts=3) for s in range(2)]
     insts += [gen.lattice((12, 12), seed=2, instance_id=40, restarts=2), gen.random_small(65, seed=1)]
     _check_graph(insts, seed=21, rule=GREEDY, uc=True, runs=[10000], graph_sweeps=16)
+
+
+# ---------------------------------------------------------------------------
+# SG_SCHED_FIELDS: phases over maintained local fields (flips scatter the
+# change of their partners' fields).
+
+def _check_fields(insts, seed, rule, uc, runs):
+    import paper_0912_3912_amd as sg
+    log(f"case: fields {[i.name for i in insts][:3]} seed={seed} rule={rule} uc={uc} runs={runs}")
+    h = sg.load_instance(list(insts)).tune("fields", 1)
+    h.bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=rule, max_sweeps=ms, until_converged=uc, schedule=sg.SCHED_FIELDS)
+             for ms in runs]
+    assert all(s["schedule_used"] == sg.SCHED_FIELDS for s in stats)
+    states = [oracle_run(i, seed, rule, 0, uc, runs) for i in insts]
+    compare(h, insts, states)
+    h.free()
+
+
+@pytest.mark.parametrize("rule,uc", [(GREEDY, True), (TIE, False), (TIE, True)])
+@pytest.mark.parametrize("kind", ["er_triples", "chimera", "ragged"])
+def test_fields_schedule(gpu, rule, uc, kind):
+    inst = {"er_triples": gen.erdos_renyi_triples(3000, seed=5, instance_id=4, restarts=3),
+            "chimera": gen.chimera(8, 8, seed=2, instance_id=8, restarts=4),
+            "ragged": gen.random_small(129, seed=3, p_edge=0.06, n_triples=60, j_range=(-15, 15), h_range=(-7, 7),
+                                       k_range=(-7, 7)).replace(restarts=5)}[kind]
+    runs = [10000] if uc else [7]
+    _check_fields([inst], seed=17, rule=rule, uc=uc, runs=runs)
+
+
+def test_fields_schedule_resume_and_batch(gpu):
+    insts = [gen.erdos_renyi_triples(2000, seed=s, instance_id=s, restarts=2) for s in (1, 2)]
+    insts += [gen.lattice((10, 10, 10), seed=3, h_range=(-2, 2), restarts=2, instance_id=40)]
+    _check_fields(insts, seed=3, rule=TIE, uc=True, runs=[2, 5, 0, 10000])
+
+
+def test_fields_knob_before_bind_only(gpu):
+    import paper_0912_3912_amd as sg
+    h = sg.load_instance([gen.chimera(2, 2, seed=1)]).bind()
+    h.init_spins(1)
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1, schedule=sg.SCHED_FIELDS)  # no fields in this workspace
+    assert e.value.status == sg.SG_EINVAL
+    with pytest.raises(sg.SGError) as e:
+        h.tune("fields", 1)  # would change the bound workspace
+    assert e.value.status == sg.SG_EINVAL

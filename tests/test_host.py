@@ -163,6 +163,19 @@ def test_knobs(sg):
         assert e.value.status == sg.SG_EINVAL
 
 
+def test_fields_knob_changes_the_workspace(sg):
+    inst = gen.erdos_renyi_triples(1000, seed=1, restarts=3)
+    h = sg.load_instance([inst])
+    b0 = h.workspace_bytes()
+    h.tune("fields", 1)
+    assert h.query("fields") == 1
+    assert h.workspace_bytes() >= b0 + 3 * 4 * 1000
+    h.tune("fields", 0)
+    assert h.workspace_bytes() == b0
+    with pytest.raises(sg.SGError):
+        h.tune("fields", 2)
+
+
 def test_calls_before_bind(sg):
     h = sg.load_instance([gen.chimera(2, 2, seed=1)])
     for fn in (lambda: h.run_sweeps(seed=1), lambda: h.energy(), lambda: h.spins_out(0, 0), lambda: h.best(),
