@@ -464,3 +464,58 @@ def cfg5_trace(count=2000, seed=5, n_lo=1e3, n_hi=1e6):
     seeds = rng.integers(0, 2**31 - 1, size=count)
     reqs = [(str(fam[i]), int(n[i]), int(seeds[i]), i) for i in range(count)]
     return reqs, gaps
+
+
+@dataclasses.dataclass
+class DenseInstance:
+    """At most 64 spins; term t is the set of spins in bit mask ``masks[t]``
+    with coefficient ``coefs[t]`` (energy -sum coef prod S)."""
+    n: int
+    masks: np.ndarray
+    coefs: np.ndarray
+    instance_id: int = 0
+    restarts: int = 1
+    name: str = ""
+
+    def replace(self, **kw) -> "DenseInstance":
+        return dataclasses.replace(self, **kw)
+
+
+def random_dense(n: int, nterms: int, max_order: int = 4, coef_range=(-50, 50), seed=0, instance_id=0,
+                 restarts=1, name="") -> DenseInstance:
+    """Distinct random terms of 1..max_order spins with uniform integer coefficients."""
+    rng = _rng(seed)
+    seen = {}
+    tries = 0
+    while len(seen) < nterms and tries < 100 * nterms:
+        tries += 1
+        k = int(rng.integers(1, min(max_order, n) + 1))
+        members = rng.choice(n, size=k, replace=False)
+        m = 0
+        for i in members:
+            m |= 1 << int(i)
+        if m not in seen:
+            seen[m] = int(rng.integers(coef_range[0], coef_range[1] + 1))
+    masks = np.array(list(seen.keys()), dtype=np.uint64)
+    coefs = np.array(list(seen.values()), dtype=np.int64)
+    return DenseInstance(n=n, masks=masks, coefs=coefs, instance_id=instance_id, restarts=restarts,
+                         name=name or f"dense{n}_{len(seen)}")
+
+
+def dense_from_sparse(inst: Instance) -> DenseInstance:
+    """The same energy function written as dense terms (n <= 64): fields as
+    one-spin terms, couplings and triples by their member sets."""
+    masks, coefs = [], []
+    h = inst.h_or_zero()
+    for i in range(inst.n):
+        if h[i]:
+            masks.append(1 << i)
+            coefs.append(int(h[i]))
+    for a, b, j in zip(inst.ei, inst.ej, inst.J):
+        masks.append((1 << int(a)) | (1 << int(b)))
+        coefs.append(int(j))
+    for (a, b, c), k in zip(inst.tri, inst.K):
+        masks.append((1 << int(a)) | (1 << int(b)) | (1 << int(c)))
+        coefs.append(int(k))
+    return DenseInstance(n=inst.n, masks=np.array(masks, dtype=np.uint64), coefs=np.array(coefs, dtype=np.int64),
+                         instance_id=inst.instance_id, restarts=inst.restarts, name=inst.name + "_dense")

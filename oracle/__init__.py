@@ -80,6 +80,14 @@ def _load():
     lib.oracle_fm.restype = ctypes.c_int
     lib.oracle_fm.argtypes = [i32, i64, P, P, P, P, i64, P, P, u32, i32, u64, i32, i32, i32, P, P, P, P, P,
                               i32]
+    lib.oracle_dense_energy.restype = i64
+    lib.oracle_dense_energy.argtypes = [i32, i64, P, P, P]
+    lib.oracle_dense_run.restype = ctypes.c_int
+    lib.oracle_dense_run.argtypes = [i32, i64, P, P, u32, i32, u64, i32, i32, i32, i32, P, P, P, P, P]
+    lib.oracle_dense_fm.restype = ctypes.c_int
+    lib.oracle_dense_fm.argtypes = [i32, i64, P, P, u32, i32, u64, i32, i32, i32, P, P, P, P, P]
+    lib.oracle_dense_brute.restype = i64
+    lib.oracle_dense_brute.argtypes = [i32, i64, P, P, P, P]
     lib.oracle_best.restype = i32
     lib.oracle_best.argtypes = [i32, P, P]
     _lib = lib
@@ -178,6 +186,61 @@ def fm(inst, seed: int, max_passes: int = 1000, until_converged: bool = True,
     if st < 0:
         raise ValueError(f"oracle_fm failed with status {st}")
     return state, st
+
+
+def _dense(d):
+    masks = np.ascontiguousarray(d.masks, np.uint64)
+    coefs = np.ascontiguousarray(d.coefs, np.int64)
+    return masks, coefs
+
+
+def dense_energy(d, s) -> int:
+    """E(s) = -sum_t coef_t prod_{i in t} s_i (Sec. VI eq. (5)) of a dense instance."""
+    masks, coefs = _dense(d)
+    s = np.ascontiguousarray(s, np.int8)
+    return int(_load().oracle_dense_energy(d.n, masks.shape[0], _p(masks), _p(coefs), _p(s)))
+
+
+def dense_run(d, seed, rule=GREEDY, max_sweeps=10000, until_converged=True, state=None):
+    """Colour sweeps on every restart of a dense instance (same rules, start
+    and stopping rule as ``run``).  Returns (state, status)."""
+    init = state is None
+    if init:
+        state = ReplicaState(d.n, d.restarts)
+    masks, coefs = _dense(d)
+    st = _load().oracle_dense_run(d.n, masks.shape[0], _p(masks), _p(coefs), d.instance_id & 0xFFFFFFFF,
+                                  d.restarts, seed & 0xFFFFFFFFFFFFFFFF, rule, max_sweeps, int(until_converged),
+                                  int(init), _p(state.spins), _p(state.energy), _p(state.sweeps),
+                                  _p(state.flips), _p(state.converged))
+    if st < 0:
+        raise ValueError(f"oracle_dense_run failed with status {st}")
+    return state, st
+
+
+def dense_fm(d, seed, max_passes=1000, until_converged=True, state=None):
+    """The pass-based search (as ``fm``) on every restart of a dense instance."""
+    init = state is None
+    if init:
+        state = ReplicaState(d.n, d.restarts)
+    masks, coefs = _dense(d)
+    st = _load().oracle_dense_fm(d.n, masks.shape[0], _p(masks), _p(coefs), d.instance_id & 0xFFFFFFFF,
+                                 d.restarts, seed & 0xFFFFFFFFFFFFFFFF, max_passes, int(until_converged), int(init),
+                                 _p(state.spins), _p(state.energy), _p(state.sweeps), _p(state.flips),
+                                 _p(state.converged))
+    if st < 0:
+        raise ValueError(f"oracle_dense_fm failed with status {st}")
+    return state, st
+
+
+def dense_brute_force(d):
+    """(E_min, one minimising state, number of minimising states), n <= 30."""
+    masks, coefs = _dense(d)
+    best = np.zeros(d.n, np.int8)
+    cnt = np.zeros(1, np.int64)
+    e = _load().oracle_dense_brute(d.n, masks.shape[0], _p(masks), _p(coefs), _p(best), _p(cnt))
+    if e == np.iinfo(np.int64).min:
+        raise ValueError("brute force needs 1 <= n <= 30")
+    return int(e), best, int(cnt[0])
 
 
 def trace(inst, seed, restart=0, rule=GREEDY, max_sweeps=100, until_converged=True,

@@ -37,6 +37,7 @@
  * locking and hill-climbing, best prefix kept, passes until no improvement.
  */
 #include <stdint.h>
+#include <limits.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -641,6 +642,190 @@ int oracle_fm(int32_t n, int64_t m, const int32_t* ei, const int32_t* ej, const 
     }
     oracle_graph_free(&g);
     return notconv ? 1 : 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Dense hyper-Ising instances (Sec. VI eq. (5)): at most 64 spins, every
+ * term a set of spins (bit i of mask[t] = spin i) with an int64 coefficient,
+ * E(s) = -sum_t coef[t] * prod_{i in t} s_i; a one-spin term is a field.
+ * Spins are int8 +-1 in external order.  The colour sweep uses first-fit over
+ * increasing index on the primal graph (two spins adjacent when some term
+ * holds both), colours ascending, spins of a colour ascending. */
+
+static int64_t dense_prod(const int8_t* s, uint64_t m)
+{
+    int64_t p = 1;
+    for (int i = 0; i < 64; ++i)
+        if ((m >> i) & 1u) p *= s[i];
+    return p;
+}
+
+int64_t oracle_dense_energy(int32_t n, int64_t nt, const uint64_t* mask, const int64_t* coef, const int8_t* s)
+{
+    (void)n;
+    int64_t E = 0;
+    for (int64_t t = 0; t < nt; ++t) E -= coef[t] * dense_prod(s, mask[t]);
+    return E;
+}
+
+/* f_i = sum over terms holding i of coef * (product of the other members) */
+static int64_t dense_field(int64_t nt, const uint64_t* mask, const int64_t* coef, const int8_t* s, int32_t i)
+{
+    int64_t f = 0;
+    for (int64_t t = 0; t < nt; ++t)
+        if ((mask[t] >> i) & 1u) f += coef[t] * dense_prod(s, mask[t] & ~((uint64_t)1 << i));
+    return f;
+}
+
+/* spins in sweep order; returns the number of colours */
+static int32_t dense_order(int32_t n, int64_t nt, const uint64_t* mask, int32_t* order)
+{
+    uint64_t adj[64];
+    int32_t col[64];
+    for (int i = 0; i < n; ++i) adj[i] = 0;
+    for (int64_t t = 0; t < nt; ++t)
+        for (int i = 0; i < n; ++i)
+            if ((mask[t] >> i) & 1u) adj[i] |= mask[t] & ~((uint64_t)1 << i);
+    int32_t nc = 0;
+    for (int i = 0; i < n; ++i) {
+        int c = 0;
+        for (;; ++c) {
+            int used = 0;
+            for (int j = 0; j < i; ++j)
+                if (((adj[i] >> j) & 1u) && col[j] == c) used = 1;
+            if (!used) break;
+        }
+        col[i] = c;
+        if (c + 1 > nc) nc = c + 1;
+    }
+    int32_t k = 0;
+    for (int c = 0; c < nc; ++c)
+        for (int i = 0; i < n; ++i)
+            if (col[i] == c) order[k++] = i;
+    return nc;
+}
+
+/* Colour sweeps (rules as oracle_run) on every restart of one dense instance.
+ * init: draw the starts (bit 1 of Philox(seed; i, ~0, id, r) -> -1) and reset
+ * sweeps, flips, converged.  Returns 0, 1 if until_converged and some
+ * restart hit max_sweeps, negative on bad input. */
+int oracle_dense_run(int32_t n, int64_t nt, const uint64_t* mask, const int64_t* coef, uint32_t instance_id,
+                     int32_t restarts, uint64_t seed, int32_t rule, int32_t max_sweeps, int32_t until_converged,
+                     int32_t init, int8_t* spins, int64_t* energy, int64_t* sweeps, int64_t* flips,
+                     int8_t* converged)
+{
+    if (n < 1 || n > 64 || restarts < 1 || max_sweeps < 0) return -1;
+    int32_t order[64];
+    dense_order(n, nt, mask, order);
+    int notconv = 0;
+    for (int32_t r = 0; r < restarts; ++r) {
+        int8_t* s = spins + (int64_t)r * n;
+        if (init) {
+            for (int32_t i = 0; i < n; ++i)
+                s[i] = oracle_bit(seed, (uint32_t)i, 0xFFFFFFFFu, instance_id, (uint32_t)r) ? -1 : 1;
+            sweeps[r] = 0;
+            flips[r] = 0;
+            converged[r] = 0;
+        }
+        int64_t E = oracle_dense_energy(n, nt, mask, coef, s);
+        for (int32_t done = 0; done < max_sweeps && !converged[r]; ++done) {
+            const uint32_t sweep = (uint32_t)sweeps[r];
+            int64_t F = 0;
+            for (int32_t k = 0; k < n; ++k) {
+                const int32_t i = order[k];
+                const int64_t d = 2 * (int64_t)s[i] * dense_field(nt, mask, coef, s, i);
+                if (d < 0 || (rule == 1 && d == 0 && oracle_bit(seed, (uint32_t)i, sweep, instance_id, (uint32_t)r))) {
+                    s[i] = (int8_t)-s[i];
+                    E += d;
+                    ++F;
+                }
+            }
+            sweeps[r] += 1;
+            flips[r] += F;
+            if (until_converged && F == 0) converged[r] = 1;
+        }
+        energy[r] = E;
+        if (until_converged && !converged[r]) notconv = 1;
+    }
+    return notconv;
+}
+
+/* The pass-based search of oracle_fm on a dense instance. */
+int oracle_dense_fm(int32_t n, int64_t nt, const uint64_t* mask, const int64_t* coef, uint32_t instance_id,
+                    int32_t restarts, uint64_t seed, int32_t max_passes, int32_t until_converged, int32_t init,
+                    int8_t* spins, int64_t* energy, int64_t* passes, int64_t* kept, int8_t* converged)
+{
+    if (n < 1 || n > 64 || restarts < 1 || max_passes < 0) return -1;
+    int notconv = 0;
+    for (int32_t r = 0; r < restarts; ++r) {
+        int8_t* s = spins + (int64_t)r * n;
+        int8_t locked[64], best[64];
+        if (init) {
+            for (int32_t i = 0; i < n; ++i)
+                s[i] = oracle_bit(seed, (uint32_t)i, 0xFFFFFFFFu, instance_id, (uint32_t)r) ? -1 : 1;
+            passes[r] = 0;
+            kept[r] = 0;
+            converged[r] = 0;
+        }
+        int64_t E = oracle_dense_energy(n, nt, mask, coef, s);
+        for (int32_t done = 0; done < max_passes && !converged[r]; ++done) {
+            const int64_t E_start = E;
+            int64_t E_cur = E, E_low = E, best_len = 0;
+            memcpy(best, s, (size_t)n);
+            memset(locked, 0, sizeof locked);
+            for (int32_t step = 0; step < n; ++step) {
+                int32_t pick = -1;
+                int64_t pg = 0;
+                for (int32_t i = 0; i < n; ++i) {
+                    if (locked[i]) continue;
+                    const int64_t g = -2 * (int64_t)s[i] * dense_field(nt, mask, coef, s, i);
+                    if (pick < 0 || g > pg) {
+                        pick = i;
+                        pg = g;
+                    }
+                }
+                s[pick] = (int8_t)-s[pick];
+                locked[pick] = 1;
+                E_cur -= pg;
+                if (E_cur < E_low) {
+                    E_low = E_cur;
+                    best_len = step + 1;
+                    memcpy(best, s, (size_t)n);
+                }
+            }
+            memcpy(s, best, (size_t)n);
+            E = E_low;
+            passes[r] += 1;
+            kept[r] += best_len;
+            if (until_converged && !(E_low < E_start)) converged[r] = 1;
+        }
+        energy[r] = E;
+        if (until_converged && !converged[r]) notconv = 1;
+    }
+    return notconv;
+}
+
+/* Exhaustive minimum over all 2^n states (n <= 30): returns E_min, writes one
+ * minimising state and the number of minimising states. */
+int64_t oracle_dense_brute(int32_t n, int64_t nt, const uint64_t* mask, const int64_t* coef, int8_t* best,
+                           int64_t* count)
+{
+    if (n < 1 || n > 30) return INT64_MIN;
+    int8_t s[64];
+    int64_t Emin = INT64_MAX, cnt = 0;
+    for (uint64_t code = 0; code < ((uint64_t)1 << n); ++code) {
+        for (int i = 0; i < n; ++i) s[i] = ((code >> i) & 1u) ? -1 : 1;
+        const int64_t E = oracle_dense_energy(n, nt, mask, coef, s);
+        if (E < Emin) {
+            Emin = E;
+            cnt = 1;
+            memcpy(best, s, (size_t)n);
+        } else if (E == Emin) {
+            ++cnt;
+        }
+    }
+    *count = cnt;
+    return Emin;
 }
 
 /* Best restart of one instance: lowest energy, lowest restart index on ties. */
