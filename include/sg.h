@@ -88,8 +88,9 @@ enum {
     SG_SCHED_BLOCK = 4,        /* one workgroup per instance, structure and replicas in LDS */
     SG_SCHED_QUEUE = 5,        /* persistent batched: work queue of uneven instances */
     SG_SCHED_FM = 6,           /* SG_RULE_FM: one wavefront per replica */
-    SG_SCHED_FIELDS = 7        /* SG_SCHED_PHASE over local fields kept in the workspace and
+    SG_SCHED_FIELDS = 7,       /* SG_SCHED_PHASE over local fields kept in the workspace and
                                   updated by the flips (knob "fields" = 1 before sg_bind) */
+    SG_SCHED_DENSE = 8         /* handles from sg_load_dense: one lane per replica */
 };
 
 typedef struct sg_ctx* sg_handle;
@@ -179,6 +180,39 @@ typedef struct {
  * count > 1).  Host-only: needs no GPU.  Errors: SG_EINVAL (message names the
  * instance and the problem), SG_ERANGE, SG_ENOMEM. */
 sg_status sg_load_instance(const sg_instance_desc* descs, int32_t count, sg_handle* out);
+
+/* Dense hyper-Ising instance (Sec. VI eq. (5)): couplings over any set of
+ * spins, such as the factoring hypergraphs of Sec. VI eqs. (6)-(8), whose
+ * terms reach four spins and whose coefficients exceed the int8 / int32
+ * ranges of sg_instance_desc.  Host arrays, copied by sg_load_dense.
+ *   n            1..64 spins
+ *   nterms       number of terms (>= 0)
+ *   mask         member set of every term: bit i = spin i; non-empty, only
+ *                bits below n, no set twice
+ *   coef         coefficient of every term:
+ *                E(s) = -sum_t coef[t] prod_{i in mask[t]} s_i
+ *                (a one-spin term is a field)
+ *   instance_id, restarts  as in sg_instance_desc
+ * Limit: sum_t |coef[t]| < 2^62 (SG_ERANGE beyond), so energies and gains
+ * are exact int64.  The colour sweep orders spins by the first-fit colouring
+ * of the graph joining any two spins that share a term. */
+typedef struct {
+    int32_t n;
+    int64_t nterms;
+    const uint64_t* mask;
+    const int64_t* coef;
+    uint32_t instance_id;
+    int32_t restarts;
+} sg_dense_desc;
+
+/* Validate and pack `count` dense instances into one handle.  The handle
+ * takes every other call of this interface: sg_init_spins (same start rule),
+ * sg_set_spins, sg_run_sweeps (SG_RULE_GREEDY, SG_RULE_GREEDY_TIE or
+ * SG_RULE_FM under SG_SCHED_AUTO or SG_SCHED_DENSE; the same stopping rule
+ * and counters), sg_energy, sg_replica_counters, sg_spins_out(_batch),
+ * sg_best.  Host-only.  Errors: SG_EINVAL (message names the instance and
+ * the problem), SG_ERANGE, SG_ENOMEM. */
+sg_status sg_load_dense(const sg_dense_desc* descs, int32_t count, sg_handle* out);
 
 /* Device bytes the handle needs: packed coupling structure, spins of every
  * replica, per-replica counters and scratch.  Host-only. */

@@ -26,14 +26,14 @@ import numpy as np
 
 __all__ = [
     "GREEDY", "GREEDY_TIE", "FM", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH",
-    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SCHED_FIELDS", "SGError", "Handle", "load_instance",
+    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SCHED_FIELDS", "SCHED_DENSE", "SGError", "Handle", "load_instance", "load_dense",
     "run_sweeps", "energy", "spins_out", "library_path", "lib",
 ]
 
 SG_OK, SG_ENOTCONV, SG_EINVAL, SG_ERANGE, SG_ENOMEM, SG_EDEVICE, SG_ESTATE = 0, 1, -1, -2, -3, -4, -5
 GREEDY, GREEDY_TIE, FM = 0, 1, 2
-SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE, SCHED_FM, SCHED_FIELDS = (
-    -1, 0, 1, 3, 4, 5, 6, 7)
+SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_LATTICE, SCHED_BLOCK, SCHED_QUEUE, SCHED_FM, SCHED_FIELDS, SCHED_DENSE = (
+    -1, 0, 1, 3, 4, 5, 6, 7, 8)
 _STATUS = {SG_EINVAL: "SG_EINVAL", SG_ERANGE: "SG_ERANGE", SG_ENOMEM: "SG_ENOMEM",
            SG_EDEVICE: "SG_EDEVICE", SG_ESTATE: "SG_ESTATE", SG_ENOTCONV: "SG_ENOTCONV"}
 
@@ -84,6 +84,7 @@ _lib = None
 _P = ctypes.c_void_p
 SIGNATURES = [
     ("sg_load_instance", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    ("sg_load_dense", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("sg_workspace_bytes", ctypes.c_int32, [_P, _P]),
     ("sg_instance_info_get", ctypes.c_int32, [_P, ctypes.c_int32, _P, _P]),
     ("sg_bind", ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
@@ -140,13 +141,23 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+class DenseDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nterms", ctypes.c_int64), ("mask", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p), ("instance_id", ctypes.c_uint32), ("restarts", ctypes.c_int32)]
+
+
 class Handle:
     """One loaded batch of instances (the C handle plus the arrays it keeps
     alive).  Instances are duck-typed: attributes n, ei, ej, J and optionally
-    h, tri, K, colour, dims, instance_id, restarts."""
+    h, tri, K, colour, dims, instance_id, restarts; with ``dense`` they are
+    dense hyper-Ising instances with attributes n, masks, coefs and
+    optionally instance_id, restarts."""
 
-    def __init__(self, instances: Sequence, lattice_dims: Optional[Sequence] = None):
+    def __init__(self, instances: Sequence, lattice_dims: Optional[Sequence] = None, dense: bool = False):
         self._keep = []
+        if dense:
+            self._load_dense(instances)
+            return
         descs = (InstanceDesc * len(instances))()
         self.sizes = []
         self.restarts = []
@@ -183,6 +194,28 @@ class Handle:
         self._h = ctypes.c_void_p()
         _check(lib().sg_load_instance(descs, len(instances), ctypes.byref(self._h)))
         self._keep = None  # the library copied the arrays
+        self.workspace = None
+        self.total_replicas = int(sum(self.restarts))
+
+    def _load_dense(self, instances):
+        descs = (DenseDesc * len(instances))()
+        self.sizes = []
+        self.restarts = []
+        for k, inst in enumerate(instances):
+            d = descs[k]
+            masks = np.ascontiguousarray(inst.masks, dtype=np.uint64)
+            coefs = np.ascontiguousarray(inst.coefs, dtype=np.int64)
+            self._keep += [masks, coefs]
+            d.n = int(inst.n)
+            d.nterms = masks.shape[0]
+            d.mask, d.coef = _ptr(masks), _ptr(coefs)
+            d.instance_id = int(getattr(inst, "instance_id", 0)) & 0xFFFFFFFF
+            d.restarts = int(getattr(inst, "restarts", 1))
+            self.sizes.append(d.n)
+            self.restarts.append(d.restarts)
+        self._h = ctypes.c_void_p()
+        _check(lib().sg_load_dense(descs, len(instances), ctypes.byref(self._h)))
+        self._keep = None
         self.workspace = None
         self.total_replicas = int(sum(self.restarts))
 
@@ -299,6 +332,14 @@ def load_instance(instances, lattice_dims=None) -> Handle:
     if not isinstance(instances, (list, tuple)):
         instances = [instances]
     return Handle(instances, lattice_dims)
+
+
+def load_dense(instances) -> Handle:
+    """Dense hyper-Ising instances (at most 64 spins, couplings over any set of
+    spins, int64 coefficients), e.g. from ``factoring.factoring_instance``."""
+    if not isinstance(instances, (list, tuple)):
+        instances = [instances]
+    return Handle(instances, dense=True)
 
 
 def run_sweeps(handle: Handle, **kw) -> dict:

@@ -91,6 +91,12 @@ struct HostInst {
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
     uint64_t off_fields = 0, field_stride = 0;  // maintained local fields (ints per replica), when enabled
+    // dense hyper-Ising instance (sg_load_dense)
+    int32_t dense = 0;
+    std::vector<int32_t> d_start, d_order;
+    std::vector<uint64_t> d_mask, t_mask;
+    std::vector<int64_t> d_coef, t_coef;
+    uint64_t off_dstart = 0, off_dmask = 0, off_dcoef = 0, off_tmask = 0, off_tcoef = 0, off_dorder = 0;
 };
 
 }  // namespace
@@ -115,6 +121,10 @@ struct sg_ctx {
     int32_t msc_k = 0;                 // its halo width (0 = chosen by the cost model)
     int32_t last_msc = 0;              // the last tile launch used the bit-plane kernel
     int32_t fields_ws = 0;             // workspace holds local fields per replica (SG_SCHED_FIELDS)
+    int32_t dense = 0;                 // a handle of dense hyper-Ising instances
+    uint64_t off_dtab = 0, off_ditems = 0;
+    std::vector<sg::BlockItem> h_ditems;  // (instance, first restart, count <= 64)
+    int32_t dense_nmax = 1;
     hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
     uint64_t off_tbase = 0;            // one sweep base per instance (graph replays)
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
@@ -375,6 +385,83 @@ void build_lattice(const sg_instance_desc& d, HostInst& q, const std::vector<uin
     q.acc_slots = std::max(q.acc_slots, kMaxLatticeTiles);
 }
 
+sg_status ingest_dense(const sg_dense_desc& d, int idx, HostInst& q)
+{
+    if (d.n < 1 || d.n > 64) return fail(SG_EINVAL, "instance %d: n = %d (a dense instance has 1..64 spins)", idx, d.n);
+    if (d.nterms < 0 || (d.nterms > 0 && (!d.mask || !d.coef)))
+        return fail(SG_EINVAL, "instance %d: need mask and coef for %lld terms", idx, (long long)d.nterms);
+    if (d.restarts < 1) return fail(SG_EINVAL, "instance %d: restarts must be >= 1", idx);
+    if (d.restarts > kMaxRestarts) return fail(SG_ERANGE, "instance %d: restarts > %d", idx, kMaxRestarts);
+    const int32_t n = d.n;
+    const uint64_t all = n == 64 ? ~0ull : ((1ull << n) - 1);
+    std::vector<uint64_t> sorted(d.mask, d.mask + d.nterms);
+    std::sort(sorted.begin(), sorted.end());
+    for (int64_t t = 0; t < d.nterms; ++t) {
+        if (!d.mask[t]) return fail(SG_EINVAL, "instance %d: term %lld has no spin", idx, (long long)t);
+        if (d.mask[t] & ~all)
+            return fail(SG_EINVAL, "instance %d: term %lld names a spin >= n", idx, (long long)t);
+        if (t > 0 && sorted[t] == sorted[t - 1])
+            return fail(SG_EINVAL, "instance %d: a set of spins appears twice", idx);
+    }
+    // sum |coef| < 2^62 keeps energies and gains exact in int64
+    unsigned long long acc = 0;
+    for (int64_t t = 0; t < d.nterms; ++t) {
+        const unsigned long long a = d.coef[t] < 0 ? 0ull - (unsigned long long)d.coef[t] : (unsigned long long)d.coef[t];
+        if (a >= (1ull << 62) || acc + a >= (1ull << 62))
+            return fail(SG_ERANGE, "instance %d: sum of |coef| reaches 2^62", idx);
+        acc += a;
+    }
+    q.dense = 1;
+    q.n = n;
+    q.m = 0;
+    q.t = 0;
+    q.id = d.instance_id;
+    q.R = d.restarts;
+    q.t_mask.assign(d.mask, d.mask + d.nterms);
+    q.t_coef.assign(d.coef, d.coef + d.nterms);
+    // per-spin term lists: the other members and the coefficient
+    q.d_start.assign((size_t)n + 1, 0);
+    for (int64_t t = 0; t < d.nterms; ++t)
+        for (int i = 0; i < n; ++i)
+            if ((d.mask[t] >> i) & 1ull) q.d_start[i + 1]++;
+    for (int i = 0; i < n; ++i) q.d_start[i + 1] += q.d_start[i];
+    q.d_mask.assign((size_t)q.d_start[n], 0);
+    q.d_coef.assign((size_t)q.d_start[n], 0);
+    std::vector<int32_t> fill(q.d_start.begin(), q.d_start.end() - 1);
+    for (int64_t t = 0; t < d.nterms; ++t)
+        for (int i = 0; i < n; ++i)
+            if ((d.mask[t] >> i) & 1ull) {
+                q.d_mask[(size_t)fill[i]] = d.mask[t] & ~(1ull << i);
+                q.d_coef[(size_t)fill[i]++] = d.coef[t];
+            }
+    // first-fit colouring over increasing index on the graph of shared terms
+    uint64_t adj[64] = {0};
+    for (int64_t t = 0; t < d.nterms; ++t)
+        for (int i = 0; i < n; ++i)
+            if ((d.mask[t] >> i) & 1ull) adj[i] |= d.mask[t] & ~(1ull << i);
+    q.colour.assign((size_t)n, 0);
+    int32_t C = 0;
+    for (int i = 0; i < n; ++i) {
+        uint64_t used = 0;
+        for (int j = 0; j < i; ++j)
+            if ((adj[i] >> j) & 1ull) used |= 1ull << q.colour[j];
+        int c = 0;
+        while ((used >> c) & 1ull) ++c;
+        q.colour[i] = c;
+        C = std::max(C, c + 1);
+    }
+    q.C = C;
+    q.d_order.clear();
+    for (int c = 0; c < C; ++c)
+        for (int i = 0; i < n; ++i)
+            if (q.colour[i] == c) q.d_order.push_back(i);
+    q.ext_of.resize((size_t)n);
+    for (int i = 0; i < n; ++i) q.ext_of[i] = (uint32_t)i;
+    q.colour_slice.assign((size_t)C + 1, 0);
+    q.h.assign((size_t)n, 0);
+    return SG_OK;
+}
+
 sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
 {
     sg_status st = validate(d, idx);
@@ -550,6 +637,14 @@ void layout(sg_ctx* H)
         q.off_acc = take((uint64_t)q.R * q.acc_slots * 16);
         q.field_stride = H->fields_ws ? align_up((uint64_t)q.n * 4) / 4 : 0;
         q.off_fields = H->fields_ws ? take(q.field_stride * 4 * (uint64_t)q.R) : 0;
+        if (q.dense) {
+            q.off_dstart = take(q.d_start.size() * 4);
+            q.off_dmask = take(q.d_mask.size() * 8);
+            q.off_dcoef = take(q.d_coef.size() * 8);
+            q.off_tmask = take(q.t_mask.size() * 8);
+            q.off_tcoef = take(q.t_coef.size() * 8);
+            q.off_dorder = take(q.d_order.size() * 4);
+        }
         if (q.lat_ok) {
             q.off_lat_rec = take((uint64_t)q.n * 8);
             // two copies of one word per interior z-row of every tile (z extent >= 4 sites)
@@ -581,7 +676,18 @@ void layout(sg_ctx* H)
     H->off_tbase = take((uint64_t)H->insts.size() * 4);
     H->n_small_reps = 0;
     for (const HostInst& q : H->insts)
-        if (q.n < kBatchInitMaxN) H->n_small_reps += q.R;
+        if (q.n < kBatchInitMaxN && !q.dense) H->n_small_reps += q.R;
+    H->h_ditems.clear();
+    H->dense_nmax = 1;
+    for (size_t k = 0; k < H->insts.size(); ++k) {
+        const HostInst& q = H->insts[k];
+        if (!q.dense) continue;
+        H->dense_nmax = std::max(H->dense_nmax, q.n);
+        for (int32_t r0 = 0; r0 < q.R; r0 += 64)
+            H->h_ditems.push_back(sg::BlockItem{(int32_t)k, r0, std::min(64, q.R - r0), 0});
+    }
+    H->off_dtab = take(ni * sizeof(sg::DenseTab));
+    H->off_ditems = take(H->h_ditems.size() * sizeof(sg::BlockItem));
     H->off_small_reps = take((uint64_t)H->n_small_reps * 8);
     H->off_best_E = take(ni * 8);
     H->off_best_r = take(ni * 4);
@@ -1109,6 +1215,44 @@ int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& 
     return first;
 }
 
+// Dense hyper-Ising handles: sweeps or passes, one lane per replica.
+sg_status run_dense(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
+{
+    if (p->schedule != SG_SCHED_AUTO && p->schedule != SG_SCHED_DENSE)
+        return fail(SG_EINVAL, "a dense handle runs under SG_SCHED_AUTO or SG_SCHED_DENSE only");
+    hipStream_t st = H->stream;
+    SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
+    SG_HIP(hipEventRecord(H->ev0, st), "event record");
+    SG_HIP(hipEventRecord(H->evh0, st), "event record");
+    if (p->max_sweeps > 0)
+        SG_HIP(sg::launch_dense_run(H->at<sg::DenseTab>(H->off_dtab), H->at<sg::BlockItem>(H->off_ditems),
+                                    (int)H->h_ditems.size(), H->dense_nmax, H->reps(),
+                                    H->at<sg::CallStats>(H->off_stats), p->rule, p->max_sweeps, p->until_converged,
+                                    p->seed, st),
+               "dense kernel");
+    SG_HIP(hipEventRecord(H->evh1, st), "event record");
+    SG_HIP(hipEventRecord(H->ev1, st), "event record");
+    H->hot_launches = p->max_sweeps > 0 ? 1 : 0;
+    sg::CallStats cs;
+    SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    float ms = 0.f, hms = 0.f;
+    SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
+    H->hot_us = hipEventElapsedTime(&hms, H->evh0, H->evh1) == hipSuccess ? hms * 1000.0 : 0.0;
+    if (stats) {
+        stats->attempts = (int64_t)cs.attempts;
+        stats->flips = (int64_t)cs.flips;
+        stats->sweeps_max = (int64_t)cs.sweeps_max;
+        stats->n_unconverged = (int32_t)cs.unconverged;
+        stats->schedule_used = SG_SCHED_DENSE;
+        stats->kernel_ms = ms;
+    }
+    if (p->until_converged && cs.unconverged)
+        return fail(SG_ENOTCONV, "%llu replicas did not converge within %d %s", (unsigned long long)cs.unconverged,
+                    p->max_sweeps, p->rule == SG_RULE_FM ? "passes" : "sweeps");
+    return SG_OK;
+}
+
 // The pass-based search (SG_RULE_FM): every replica of every instance is one
 // wavefront item, largest instances first.
 sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
@@ -1211,6 +1355,35 @@ sg_status sg_load_instance(const sg_instance_desc* descs, int32_t count, sg_hand
     return SG_OK;
 }
 
+sg_status sg_load_dense(const sg_dense_desc* descs, int32_t count, sg_handle* out)
+{
+    g_err.clear();
+    if (!descs || !out || count < 1) return fail(SG_EINVAL, "sg_load_dense: need descs, out and count >= 1");
+    *out = nullptr;
+    sg_ctx* H = new (std::nothrow) sg_ctx;
+    if (!H) return fail(SG_ENOMEM, "out of host memory");
+    try {
+        H->dense = 1;
+        H->insts.resize((size_t)count);
+        for (int32_t k = 0; k < count; ++k) {
+            sg_status st = ingest_dense(descs[k], k, H->insts[k]);
+            if (st != SG_OK) {
+                delete H;
+                return st;
+            }
+            H->insts[k].rep_base = H->total_reps;
+            H->total_reps += H->insts[k].R;
+        }
+        layout(H);
+        H->started.assign((size_t)H->total_reps, 0);
+    } catch (const std::bad_alloc&) {
+        delete H;
+        return fail(SG_ENOMEM, "out of host memory while packing instances");
+    }
+    *out = H;
+    return SG_OK;
+}
+
 sg_status sg_workspace_bytes(sg_handle H, uint64_t* bytes)
 {
     if (!H || !bytes) return fail(SG_EINVAL, "sg_workspace_bytes: null argument");
@@ -1266,6 +1439,48 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             SG_HIP(hipMemcpyAsync(H->dev + q.off_lat_rec, q.lat_rec.data(), q.lat_rec.size() * 8,
                                   hipMemcpyHostToDevice, st),
                    "upload lattice records");
+        if (q.dense) {
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_dstart, q.d_start.data(), q.d_start.size() * 4, hipMemcpyHostToDevice,
+                                  st),
+                   "upload terms");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_dmask, q.d_mask.data(), q.d_mask.size() * 8, hipMemcpyHostToDevice, st),
+                   "upload terms");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_dcoef, q.d_coef.data(), q.d_coef.size() * 8, hipMemcpyHostToDevice, st),
+                   "upload terms");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_tmask, q.t_mask.data(), q.t_mask.size() * 8, hipMemcpyHostToDevice, st),
+                   "upload terms");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_tcoef, q.t_coef.data(), q.t_coef.size() * 8, hipMemcpyHostToDevice, st),
+                   "upload terms");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_dorder, q.d_order.data(), q.d_order.size() * 4, hipMemcpyHostToDevice,
+                                  st),
+                   "upload sweep order");
+        }
+    }
+    if (H->dense) {
+        std::vector<sg::DenseTab> dt(H->insts.size());
+        for (size_t k = 0; k < H->insts.size(); ++k) {
+            const HostInst& q = H->insts[k];
+            sg::DenseTab& T = dt[k];
+            T.dstart = H->at<int32_t>(q.off_dstart);
+            T.dmask = H->at<uint64_t>(q.off_dmask);
+            T.dcoef = H->at<int64_t>(q.off_dcoef);
+            T.tmask = H->at<uint64_t>(q.off_tmask);
+            T.tcoef = H->at<int64_t>(q.off_tcoef);
+            T.order = H->at<int32_t>(q.off_dorder);
+            T.spins = H->at<int8_t>(q.off_spins);
+            T.spin_stride = (int64_t)q.spin_stride;
+            T.rep_base = q.rep_base;
+            T.n = q.n;
+            T.nterms = (int32_t)q.t_mask.size();
+            T.instance_id = q.id;
+            T.pad = 0;
+        }
+        SG_HIP(hipMemcpyAsync(H->dev + H->off_dtab, dt.data(), dt.size() * sizeof(sg::DenseTab), hipMemcpyHostToDevice,
+                              st),
+               "upload dense table");
+        SG_HIP(hipMemcpyAsync(H->dev + H->off_ditems, H->h_ditems.data(), H->h_ditems.size() * sizeof(sg::BlockItem),
+                              hipMemcpyHostToDevice, st),
+               "upload dense items");
     }
     std::vector<int64_t> rb(H->insts.size());
     std::vector<int32_t> rr(H->insts.size());
@@ -1304,7 +1519,7 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             const HostInst& q = H->insts[k];
             for (int32_t r = 0; r < q.R; ++r) {
                 rep_inst[(size_t)(q.rep_base + r)] = (int32_t)k;
-                if (q.n < kBatchInitMaxN) small.push_back(q.rep_base + r);
+                if (q.n < kBatchInitMaxN && !q.dense) small.push_back(q.rep_base + r);
             }
         }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_rep_inst, rep_inst.data(), rep_inst.size() * 4, hipMemcpyHostToDevice,
@@ -1331,6 +1546,14 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
     sg_status s = need_bound(H);
     if (s != SG_OK) return s;
     hipStream_t st = H->stream;
+    if (H->dense) {
+        SG_HIP(sg::launch_dense_init(H->at<sg::DenseTab>(H->off_dtab), H->at<sg::BlockItem>(H->off_ditems),
+                                     (int)H->h_ditems.size(), H->reps(), seed, st),
+               "dense init kernel");
+        SG_HIP(hipStreamSynchronize(st), "stream sync");
+        std::fill(H->started.begin(), H->started.end(), 1);
+        return SG_OK;
+    }
     for (const HostInst& q : H->insts) {
         if (q.n < kBatchInitMaxN) continue;
         const sg::InstDev I = H->view(q);
@@ -1370,11 +1593,20 @@ sg_status sg_set_spins(sg_handle H, int32_t inst, int32_t r, const int8_t* s)
     int8_t* dst = H->at<int8_t>(q.off_spins) + (uint64_t)r * q.spin_stride;
     sg::RepState z{};
     sg::RepState* rs = H->reps() + q.rep_base + r;
+    if (q.dense) {  // exact energy of the start on the host: E = -sum coef prod s
+        for (size_t t = 0; t < q.t_mask.size(); ++t) {
+            int64_t prod = 1;
+            for (int i = 0; i < q.n; ++i)
+                if ((q.t_mask[t] >> i) & 1ull) prod *= tmp[i];
+            z.E -= q.t_coef[t] * prod;
+        }
+    }
     SG_HIP(hipMemcpyAsync(dst, tmp.data(), (size_t)q.n, hipMemcpyHostToDevice, st), "spin upload");
     SG_HIP(hipMemcpyAsync(rs, &z, sizeof z, hipMemcpyHostToDevice, st), "state upload");
-    SG_HIP(sg::launch_energy(H->view(q), dst, (int64_t)q.spin_stride, 1, H->at<int64_t>(H->off_slots), q.nslots, rs,
-                             nullptr, st),
-           "energy kernel");
+    if (!q.dense)
+        SG_HIP(sg::launch_energy(H->view(q), dst, (int64_t)q.spin_stride, 1, H->at<int64_t>(H->off_slots), q.nslots,
+                                 rs, nullptr, st),
+               "energy kernel");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
     H->started[(size_t)(q.rep_base + r)] = 1;
     return SG_OK;
@@ -1390,6 +1622,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
     for (uint8_t v : H->started)
         if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
+    if (H->dense) return run_dense(H, p, stats);
     if (p->rule == SG_RULE_FM) return run_fm(H, p, stats);
     std::vector<int> assign;
     const int sched = assign_schedules(H, p, assign);
@@ -1451,6 +1684,10 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
     hipStream_t st = H->stream;
     if (recompute) {
         int64_t* eout = H->at<int64_t>(H->off_eout);
+        if (H->dense)
+            SG_HIP(sg::launch_dense_energy(H->at<sg::DenseTab>(H->off_dtab), H->at<sg::BlockItem>(H->off_ditems),
+                                           (int)H->h_ditems.size(), eout, st),
+                   "dense energy kernel");
         for (const HostInst& q : H->insts)
             if (q.n >= kBatchInitMaxN)
                 SG_HIP(sg::launch_energy(H->view(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,

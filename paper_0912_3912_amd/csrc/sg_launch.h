@@ -51,6 +51,13 @@ size_t fm_lds_bytes(int nmax, int waves);
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
                      bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv,
                      hipStream_t st);
+// Dense hyper-Ising instances: one lane per replica; items are (instance,
+// first restart, count <= 64).  rule 0/1: colour sweeps; 2: pass-based search.
+hipError_t launch_dense_init(const DenseTab* tabs, const BlockItem* items, int nitems, RepState* rs, uint64_t seed,
+                             hipStream_t st);
+hipError_t launch_dense_energy(const DenseTab* tabs, const BlockItem* items, int nitems, int64_t* out, hipStream_t st);
+hipError_t launch_dense_run(const DenseTab* tabs, const BlockItem* items, int nitems, int nmax, RepState* rs,
+                            CallStats* cs, int rule, int max_sweeps, int until_conv, uint64_t seed, hipStream_t st);
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
                              int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
 

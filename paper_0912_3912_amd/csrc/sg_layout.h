@@ -105,4 +105,25 @@ struct QueueItem {           // k_queue: restart r of instance inst
     int32_t r;
 };
 
+// Dense hyper-Ising instance (at most 64 spins, couplings over any set of
+// spins, int64 coefficients): terms by spin (the other members and the
+// coefficient of every term holding spin i, entries dstart[i] .. dstart[i+1]),
+// the whole term list, and the sweep order (colours ascending, spins of a
+// colour ascending).  Energy E = -sum_t coef_t prod_{i in t} s_i.
+struct DenseTab {
+    const int32_t* dstart;   // n + 1
+    const uint64_t* dmask;   // other members of the term
+    const int64_t* dcoef;
+    const uint64_t* tmask;   // every term once
+    const int64_t* tcoef;
+    const int32_t* order;    // n spins in sweep order
+    int8_t* spins;           // replica 0, +-1 per spin
+    int64_t spin_stride;
+    int64_t rep_base;
+    int32_t n;
+    int32_t nterms;
+    uint32_t instance_id;
+    int32_t pad;
+};
+
 }  // namespace sg

@@ -190,3 +190,31 @@ def test_free_is_idempotent(sg):
     h.free()
     h.free()
     assert sg.lib().sg_free(None) == 0
+
+
+def test_dense_validation(sg):
+    d = gen.random_dense(10, 20, seed=1)
+    h = sg.load_dense([d])
+    assert h.info(0)["n"] == 10 and h.workspace_bytes() > 0
+    bad = [d.replace(n=65), d.replace(n=0),
+           d.replace(masks=np.append(d.masks, np.uint64(1 << 12)), coefs=np.append(d.coefs, 1)),
+           d.replace(masks=np.append(d.masks, d.masks[0]), coefs=np.append(d.coefs, 1)),
+           d.replace(masks=np.append(d.masks, np.uint64(0)), coefs=np.append(d.coefs, 1)),
+           d.replace(restarts=0)]
+    for b in bad:
+        with pytest.raises(sg.SGError) as e:
+            sg.load_dense([b])
+        assert e.value.status == sg.SG_EINVAL
+    big = d.replace(masks=np.array([1, 2], np.uint64), coefs=np.array([1 << 61, 1 << 61], np.int64))
+    with pytest.raises(sg.SGError) as e:
+        sg.load_dense([big])
+    assert e.value.status == sg.SG_ERANGE
+
+
+def test_dense_colouring_is_first_fit(sg):
+    """The sweep order of a dense instance: first-fit colouring of the graph of
+    shared terms, equal to the sparse ingest's colouring of the same graph."""
+    inst = gen.random_small(30, seed=4, p_edge=0.2, n_triples=6)
+    d = gen.dense_from_sparse(inst)
+    col = sg.load_dense([d]).info(0)["colour"]
+    assert np.array_equal(col, oracle.first_fit_colouring(inst))
