@@ -214,6 +214,27 @@ typedef struct {
  * the problem), SG_ERANGE, SG_ENOMEM. */
 sg_status sg_load_dense(const sg_dense_desc* descs, int32_t count, sg_handle* out);
 
+/* Exact ground state by branch-and-bound (Sec. III) on the host CPU: no GPU
+ * and no handle.  Spins are assigned in breadth-first order of the primal
+ * graph; a partial assignment is pruned when its lower bound (eq. (2) plus
+ * 2|c| for every fully assigned term that is unsatisfied, eqs. (3)-(4)) reaches
+ * the best energy held, or when a spin whose neighbourhood is fully assigned
+ * could be flipped to lower the energy (Lemma 2 with one-spin changes) or to
+ * keep it while holding the value tried second.
+ *   d           one instance (dims, colour and restarts are ignored)
+ *   seed_spins  n spins +-1 (external order) whose energy seeds the bound and
+ *               whose values are tried first, e.g. the best restart of
+ *               sg_run_sweeps; or NULL
+ *   spins_out   n spins: a ground state (the seed when nothing is lower)
+ *   E_out       its energy
+ *   nodes_out   assignments made by the search (may be NULL)
+ *   max_nodes   budget (0 = none); when reached the call returns SG_ENOTCONV
+ *               with the best state found so far, not proven optimal
+ * The search takes exponential time in the worst case: the paper reports
+ * about 100 spins as its practical limit on lattices.  At most 4096 spins. */
+sg_status sg_exact_ground_state(const sg_instance_desc* d, const int8_t* seed_spins, int8_t* spins_out,
+                                int64_t* E_out, int64_t* nodes_out, int64_t max_nodes);
+
 /* Device bytes the handle needs: packed coupling structure, spins of every
  * replica, per-replica counters and scratch.  Host-only. */
 sg_status sg_workspace_bytes(sg_handle h, uint64_t* bytes);

@@ -26,7 +26,8 @@ import numpy as np
 
 __all__ = [
     "GREEDY", "GREEDY_TIE", "FM", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH",
-    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SCHED_FIELDS", "SCHED_DENSE", "SGError", "Handle", "load_instance", "load_dense",
+    "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SCHED_FIELDS", "SCHED_DENSE", "SGError", "Handle",
+    "load_instance", "load_dense", "exact_ground_state",
     "run_sweeps", "energy", "spins_out", "library_path", "lib",
 ]
 
@@ -85,6 +86,7 @@ _P = ctypes.c_void_p
 SIGNATURES = [
     ("sg_load_instance", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("sg_load_dense", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    ("sg_exact_ground_state", ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int64]),
     ("sg_workspace_bytes", ctypes.c_int32, [_P, _P]),
     ("sg_instance_info_get", ctypes.c_int32, [_P, ctypes.c_int32, _P, _P]),
     ("sg_bind", ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
@@ -332,6 +334,35 @@ def load_instance(instances, lattice_dims=None) -> Handle:
     if not isinstance(instances, (list, tuple)):
         instances = [instances]
     return Handle(instances, lattice_dims)
+
+
+def exact_ground_state(inst, seed_spins=None, max_nodes: int = 0):
+    """Exact ground state by branch-and-bound (Sec. III) on the host CPU.
+    Returns (energy, spins, nodes, proven): proven is False when the node
+    budget ran out first (then the state is only the best found)."""
+    h = Handle.__new__(Handle)  # reuse the descriptor marshalling of Handle
+    h._keep = []
+    descs = (InstanceDesc * 1)()
+    d = descs[0]
+    ei, ej, J = _i32(inst.ei), _i32(inst.ej), _i32(inst.J)
+    hv = getattr(inst, "h", None)
+    hv = None if hv is None else _i32(hv)
+    tri = getattr(inst, "tri", None)
+    tri = np.zeros(0, np.int32) if tri is None else _i32(tri).reshape(-1)
+    K = getattr(inst, "K", None)
+    K = np.zeros(0, np.int32) if K is None else _i32(K)
+    d.n, d.m = int(inst.n), ei.shape[0]
+    d.ei, d.ej, d.J, d.h = _ptr(ei), _ptr(ej), _ptr(J), _ptr(hv)
+    d.t, d.tri, d.K = tri.shape[0] // 3, _ptr(tri), _ptr(K)
+    d.restarts = 1
+    seed = None if seed_spins is None else np.ascontiguousarray(seed_spins, dtype=np.int8)
+    out = np.zeros(int(inst.n), np.int8)
+    E = ctypes.c_int64()
+    nodes = ctypes.c_int64()
+    st = lib().sg_exact_ground_state(ctypes.byref(d), _ptr(seed), _ptr(out), ctypes.byref(E), ctypes.byref(nodes),
+                                     int(max_nodes))
+    _check(st)
+    return int(E.value), out, int(nodes.value), st == SG_OK
 
 
 def load_dense(instances) -> Handle:

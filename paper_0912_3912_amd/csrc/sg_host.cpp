@@ -1318,6 +1318,10 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
 
 }  // namespace
 
+// Error reporting and validation for the library's other translation units.
+sg_status sg_internal_fail(sg_status code, const char* msg) { return fail(code, "%s", msg); }
+sg_status sg_internal_validate(const sg_instance_desc* d) { return validate(*d, 0); }
+
 // ---------------------------------------------------------------------------
 // C-ABI
 

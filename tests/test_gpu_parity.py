@@ -210,3 +210,18 @@ def test_fields_knob_before_bind_only(gpu):
     with pytest.raises(sg.SGError) as e:
         h.tune("fields", 1)  # would change the bound workspace
     assert e.value.status == sg.SG_EINVAL
+
+
+def test_gpu_restarts_seed_branch_and_bound(gpu):
+    """The GPU descent's best restart seeds the exact search (Sec. III: a
+    greedy approximation as the initial bound)."""
+    import paper_0912_3912_amd as sg
+    inst = gen.lattice((8, 8), seed=8, h_range=(-1, 1)).replace(restarts=256)
+    h = sg.load_instance([inst]).bind()
+    h.init_spins(5)
+    h.run_sweeps(seed=5, rule=GREEDY)
+    Eb, rb = h.best()
+    seed_state = h.spins_out(0, int(rb[0]))
+    E, s, nodes, proven = sg.exact_ground_state(inst, seed_spins=seed_state)
+    log(f"8x8: GPU best of 256 restarts {int(Eb[0])}, exact {E} after {nodes} nodes")
+    assert proven and E <= int(Eb[0]) and oracle.energy(inst, s) == E
