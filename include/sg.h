@@ -298,7 +298,7 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *   "lattice_max_tiles"  cap on tiles per replica (0 = as many as fit)
  *   "lattice_wg_max_n"   largest lattice run with one workgroup per replica
  *   "block_rg"           restarts per workgroup of the block schedule
- *                        (64, 128, 256; 0 = largest that fits LDS)
+ *                        (64, 128, 256; 0 = 64, the fastest measured)
  *   "block_min_restarts" SG_SCHED_AUTO uses the block schedule for instances
  *                        with at least this many restarts (default 32)
  *   "queue_wave_max_n"   queue items with at most this many spins run one per

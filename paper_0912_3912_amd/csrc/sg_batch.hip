@@ -387,48 +387,24 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
 // batched start and energy: one block of 256 threads per replica listed in
 // `reps` (handle replica indices); rep_inst maps a replica to its instance.
 
-__global__ __launch_bounds__(256) void k_init_batch(const InstTab* __restrict__ tab, const int32_t* __restrict__ rep_inst,
-                                                    const int64_t* __restrict__ reps, RepState* __restrict__ rs,
-                                                    uint64_t seed)
+// Energy of Sec. II eq. (1) / Sec. VI eq. (5) of one replica whose spins are
+// in LDS (sp), each edge and triple counted at its smallest internal index;
+// the block's four wavefronts share the slices; returns the total to thread 0.
+__device__ long long block_energy(const InstDev& I, const int8_t* __restrict__ sp)
 {
-    const int64_t g = reps[blockIdx.x];
-    const InstTab& Q = tab[rep_inst[g]];
-    const uint32_t r = (uint32_t)(g - Q.rep_base);
-    int8_t* sp = Q.spins + (int64_t)r * Q.spin_stride;
-    for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x)
-        sp[i] = (int8_t)(rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
-    if (threadIdx.x == 0) {
-        RepState z;
-        z.E = 0; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
-        rs[g] = z;
-    }
-}
-
-// Energy of Sec. II eq. (1) / Sec. VI eq. (5), each edge and triple counted
-// at its smallest internal index; writes rs[g].E (out == NULL) or out[g].
-__global__ __launch_bounds__(256) void k_energy_batch(const InstTab* __restrict__ tab,
-                                                      const int32_t* __restrict__ rep_inst,
-                                                      const int64_t* __restrict__ reps, RepState* __restrict__ rs,
-                                                      int64_t* __restrict__ out)
-{
-    const int64_t g = reps[blockIdx.x];
-    const InstTab& Q = tab[rep_inst[g]];
-    const InstDev& I = Q.I;
-    const int r = (int)(g - Q.rep_base);
-    const int8_t* s = Q.spins + (int64_t)r * Q.spin_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     long long acc = 0;
     for (int sl = wave; sl < I.nslices; sl += 4) {
         const Slice S = I.slices[sl];
         if (lane < S.rows) {
             const int i = S.row0 + lane;
-            const int si = s[i];
+            const int si = sp[i];
             int e = I.h[i] * si;
             const uint32_t* p = I.nbr + S.ebase + lane;
             for (int k = 0; k < S.ew; ++k) {
                 const uint32_t w = p[k * kSlice];
                 const int j = (int)(w >> 8);
-                if (j > i) e += bat_j(w) * si * s[j];
+                if (j > i) e += bat_j(w) * si * sp[j];
             }
             if (I.has_tri) {
                 const uint32_t* pa = I.ta + S.tbase + lane;
@@ -436,7 +412,7 @@ __global__ __launch_bounds__(256) void k_energy_batch(const InstTab* __restrict_
                 for (int k = 0; k < S.tw; ++k) {
                     const uint32_t wa = pa[k * kSlice];
                     const int a = (int)(wa >> 8), b = (int)pb[k * kSlice];
-                    if (a > i && b > i) e += bat_j(wa) * si * s[a] * s[b];
+                    if (a > i && b > i) e += bat_j(wa) * si * sp[a] * sp[b];
                 }
             }
             acc += e;
@@ -447,32 +423,180 @@ __global__ __launch_bounds__(256) void k_energy_batch(const InstTab* __restrict_
     __shared__ long long part[4];
     if (lane == 0) part[wave] = acc;
     __syncthreads();
+    return -(part[0] + part[1] + part[2] + part[3]);
+}
+
+// Random start of one replica per block (grid over the listed replicas):
+// spins drawn into LDS and stored, then the start energy from LDS; resets
+// the replica state.
+__global__ __launch_bounds__(256) void k_init_batch(const InstTab* __restrict__ tab, const int32_t* __restrict__ rep_inst,
+                                                    const int64_t* __restrict__ reps, RepState* __restrict__ rs,
+                                                    uint64_t seed)
+{
+    extern __shared__ int8_t bsp[];
+    const int64_t g = reps[blockIdx.x];
+    const InstTab& Q = tab[rep_inst[g]];
+    const uint32_t r = (uint32_t)(g - Q.rep_base);
+    int8_t* sp = Q.spins + (int64_t)r * Q.spin_stride;
+    for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x) {
+        const int8_t v = (int8_t)(rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
+        bsp[i] = v;
+        sp[i] = v;
+    }
+    __syncthreads();
+    const long long E = block_energy(Q.I, bsp);
     if (threadIdx.x == 0) {
-        const long long t = -(part[0] + part[1] + part[2] + part[3]);
+        RepState z;
+        z.E = E; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
+        rs[g] = z;
+    }
+}
+
+// Energy of the stored spins of the listed replicas (spins staged in LDS);
+// writes rs[g].E (out == NULL) or out[g].
+__global__ __launch_bounds__(256) void k_energy_batch(const InstTab* __restrict__ tab,
+                                                      const int32_t* __restrict__ rep_inst,
+                                                      const int64_t* __restrict__ reps, RepState* __restrict__ rs,
+                                                      int64_t* __restrict__ out)
+{
+    extern __shared__ int8_t bsp[];
+    const int64_t g = reps[blockIdx.x];
+    const InstTab& Q = tab[rep_inst[g]];
+    const int r = (int)(g - Q.rep_base);
+    const int8_t* s = Q.spins + (int64_t)r * Q.spin_stride;
+    for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x) bsp[i] = s[i];
+    __syncthreads();
+    const long long t = block_energy(Q.I, bsp);
+    if (threadIdx.x == 0) {
         if (out) out[g] = t;
         else rs[g].E = t;
     }
+}
+
+// Start and energy of many replicas of one instance, one lane per replica
+// (items: instance, first restart, count <= 64; one wavefront per item).  A
+// lane keeps its replica's spins bit-packed in its own LDS column (word w at
+// bits[w * 64 + lane], bit set when s = -1, internal order), and the
+// instance's slices and coupling words, the same for every lane, are walked
+// in order with scalar loads.  INIT: draw the start (the Philox start rule)
+// and store it as bytes; else read the stored spins.  Energy of Sec. II
+// eq. (1) / Sec. VI eq. (5), each term at its smallest internal index.
+template <bool INIT>
+__global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__ tab,
+                                                     const BlockItem* __restrict__ items, int nitems, int wmax,
+                                                     RepState* __restrict__ rs, int64_t* __restrict__ out,
+                                                     uint64_t seed)
+{
+    extern __shared__ uint32_t lbits[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + wave;
+    if (item >= nitems) return;
+    const BlockItem it = items[item];
+    const InstTab& Q = tab[it.inst];
+    const InstDev& I = Q.I;
+    const int n = I.n;
+    const int W = (n + 31) >> 5;
+    uint32_t* bits = lbits + (size_t)wave * wmax * 64;
+    const bool mine = lane < it.nr;
+    const int r = it.r0 + (mine ? lane : 0);
+    int8_t* sp = Q.spins + Q.spin_stride * r;
+    for (int w = 0; w < W; ++w) {
+        uint32_t word = 0;
+        for (int q = 0; q < 8; ++q) {
+            const int i0 = w * 32 + 4 * q;
+            if (i0 >= n) break;
+            uint32_t quad;
+            if (INIT) {
+                quad = 0;
+                for (int b = 0; b < 4 && i0 + b < n; ++b) {
+                    const int neg = rng_bit(seed, I.ext[i0 + b], 0xFFFFFFFFu, I.instance_id, (uint32_t)r);
+                    word |= (uint32_t)neg << (4 * q + b);
+                    quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
+                }
+                if (mine) *reinterpret_cast<uint32_t*>(sp + i0) = quad;
+            } else {
+                quad = *reinterpret_cast<const uint32_t*>(sp + i0);
+                for (int b = 0; b < 4 && i0 + b < n; ++b)
+                    word |= (uint32_t)(((quad >> (8 * b)) & 0x80u) != 0) << (4 * q + b);
+            }
+        }
+        bits[w * 64 + lane] = word;
+    }
+    auto spin = [&](int j) -> int { return ((bits[(j >> 5) * 64 + lane] >> (j & 31)) & 1u) ? -1 : 1; };
+    long long acc = 0;
+    for (int sl = 0; sl < I.nslices; ++sl) {
+        const Slice S = I.slices[sl];
+        for (int l = 0; l < S.rows; ++l) {
+            const int i = (int)S.row0 + l;
+            const int si = spin(i);
+            int e = I.h[i] * si;
+            for (int k = 0; k < S.ew; ++k) {
+                const uint32_t w = I.nbr[S.ebase + k * kSlice + l];
+                const int j = (int)(w >> 8);
+                if (j > i) e += bat_j(w) * si * spin(j);
+            }
+            if (I.has_tri) {
+                for (int k = 0; k < S.tw; ++k) {
+                    const uint32_t wa = I.ta[S.tbase + k * kSlice + l];
+                    const int a = (int)(wa >> 8), b = (int)I.tb[S.tbase + k * kSlice + l];
+                    if (a > i && b > i) e += bat_j(wa) * si * spin(a) * spin(b);
+                }
+            }
+            acc += e;
+        }
+    }
+    if (mine) {
+        const int64_t g = Q.rep_base + r;
+        if (INIT) {
+            RepState z;
+            z.E = -acc; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
+            rs[g] = z;
+        } else if (out) {
+            out[g] = -acc;
+        } else {
+            rs[g].E = -acc;
+        }
+    }
+}
+
+hipError_t launch_start_lanes(const InstTab* tab, const BlockItem* items, int nitems, int nmax, bool init,
+                              RepState* rs, int64_t* out, uint64_t seed, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int wmax = (nmax + 31) / 32;
+    const size_t lds = (size_t)4 * wmax * 64 * 4;
+    if (lds > 65536) return hipErrorInvalidValue;
+    const dim3 grid((nitems + 3) / 4);
+    if (init)
+        hipLaunchKernelGGL(k_start_lanes<true>, grid, dim3(256), lds, st, tab, items, nitems, wmax, rs, out, seed);
+    else
+        hipLaunchKernelGGL(k_start_lanes<false>, grid, dim3(256), lds, st, tab, items, nitems, wmax, rs, out, seed);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 
 hipError_t launch_init_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                             RepState* rs, uint64_t seed, hipStream_t st)
+                             int nmax, RepState* rs, uint64_t seed, hipStream_t st)
 {
+    const size_t lds = ((size_t)nmax + 3) & ~(size_t)3;
+    if (lds > 65536) return hipErrorInvalidValue;
     for (int64_t b0 = 0; b0 < nreps; b0 += (1u << 30)) {
         const unsigned nb = (unsigned)std::min<int64_t>(nreps - b0, 1u << 30);
-        hipLaunchKernelGGL(k_init_batch, dim3(nb), dim3(256), 0, st, tab, rep_inst, reps + b0, rs, seed);
+        hipLaunchKernelGGL(k_init_batch, dim3(nb), dim3(256), lds, st, tab, rep_inst, reps + b0, rs, seed);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_energy_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                               RepState* rs, int64_t* out, hipStream_t st)
+                               int nmax, RepState* rs, int64_t* out, hipStream_t st)
 {
+    const size_t lds = ((size_t)nmax + 3) & ~(size_t)3;
+    if (lds > 65536) return hipErrorInvalidValue;
     for (int64_t b0 = 0; b0 < nreps; b0 += (1u << 30)) {
         const unsigned nb = (unsigned)std::min<int64_t>(nreps - b0, 1u << 30);
-        hipLaunchKernelGGL(k_energy_batch, dim3(nb), dim3(256), 0, st, tab, rep_inst, reps + b0, rs, out);
+        hipLaunchKernelGGL(k_energy_batch, dim3(nb), dim3(256), lds, st, tab, rep_inst, reps + b0, rs, out);
     }
     return hipGetLastError();
 }

@@ -56,7 +56,9 @@ constexpr int32_t kMaxRestarts = 65535;
 constexpr int32_t kMaxLatticeTiles = 1024;
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
-constexpr int32_t kBatchInitMaxN = 65536;  // instances below this size start and evaluate in batched launches
+constexpr int32_t kBatchInitMaxN = 65536;
+constexpr int32_t kLaneStartMaxN = 2048;       // lane-per-replica start/energy: instances up to this size ...
+constexpr int32_t kLaneStartMinR = 32;         // ... with at least this many restarts  // instances below this size start and evaluate in batched launches
 
 struct HostInst {
     int32_t n = 0;
@@ -130,6 +132,10 @@ struct sg_ctx {
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
     uint64_t off_rep_inst = 0, off_small_reps = 0;
     int64_t n_small_reps = 0;                  // replicas of instances below kBatchInitMaxN
+    int32_t small_nmax = 1;                    // largest of those instances
+    std::vector<sg::BlockItem> h_litems;       // lane-per-replica start items (instance, r0, count <= 64)
+    int32_t lane_nmax = 1;
+    uint64_t off_litems = 0;
     int64_t n_block_item_cap = 0, ctab_len = 0;
     std::vector<sg::BlockItem> h_bitems;
     std::vector<sg::QueueItem> h_qitems;
@@ -616,6 +622,9 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     return SG_OK;
 }
 
+// Replicas of this instance start (and recompute energies) one lane per replica.
+bool lane_start(const HostInst& q) { return !q.dense && q.n <= kLaneStartMaxN && q.R >= kLaneStartMinR; }
+
 void layout(sg_ctx* H)
 {
     uint64_t off = 0;
@@ -675,8 +684,22 @@ void layout(sg_ctx* H)
     H->off_rep_inst = take((uint64_t)H->total_reps * 4);
     H->off_tbase = take((uint64_t)H->insts.size() * 4);
     H->n_small_reps = 0;
+    H->small_nmax = 1;
     for (const HostInst& q : H->insts)
-        if (q.n < kBatchInitMaxN && !q.dense) H->n_small_reps += q.R;
+        if (q.n < kBatchInitMaxN && !q.dense && !lane_start(q)) {
+            H->n_small_reps += q.R;
+            H->small_nmax = std::max(H->small_nmax, q.n);
+        }
+    H->h_litems.clear();
+    H->lane_nmax = 1;
+    for (size_t k = 0; k < H->insts.size(); ++k) {
+        const HostInst& q = H->insts[k];
+        if (!lane_start(q)) continue;
+        H->lane_nmax = std::max(H->lane_nmax, q.n);
+        for (int32_t r0 = 0; r0 < q.R; r0 += 64)
+            H->h_litems.push_back(sg::BlockItem{(int32_t)k, r0, std::min(64, q.R - r0), 0});
+    }
+    H->off_litems = take(H->h_litems.size() * sizeof(sg::BlockItem));
     H->h_ditems.clear();
     H->dense_nmax = 1;
     for (size_t k = 0; k < H->insts.size(); ++k) {
@@ -1063,10 +1086,13 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
 constexpr size_t kLdsBudget = 160 * 1024 - 6 * 1024;  // dynamic LDS left beside the kernels' static arrays
 constexpr int32_t kQueueMaxN = 150000;                  // largest item of the queue schedule (spins in LDS)
 
-// Restarts per block workgroup for instance q (0 if the block schedule cannot hold it).
+// Restarts per block workgroup for instance q (0 if the block schedule cannot
+// hold it).  Default 64: smaller workgroups fit more per CU and keep one
+// launch for a batch (measured on 4096 Chimera instances x 256 restarts:
+// 9.6 ms at 64, 15.2 ms at 128, 15.8 ms with the largest size that fits).
 int block_rg_for(const sg_ctx* H, const HostInst& q)
 {
-    const int want = H->block_rg ? H->block_rg : std::min(256, (q.R + 63) / 64 * 64);
+    const int want = H->block_rg ? H->block_rg : 64;
     for (int rg = want; rg >= 64; rg -= 64) {
         if (H->block_rg && rg != H->block_rg) break;
         if (rg != 64 && rg != 128 && rg != 192 && rg != 256) continue;
@@ -1523,7 +1549,7 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             const HostInst& q = H->insts[k];
             for (int32_t r = 0; r < q.R; ++r) {
                 rep_inst[(size_t)(q.rep_base + r)] = (int32_t)k;
-                if (q.n < kBatchInitMaxN && !q.dense) small.push_back(q.rep_base + r);
+                if (q.n < kBatchInitMaxN && !q.dense && !lane_start(q)) small.push_back(q.rep_base + r);
             }
         }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_rep_inst, rep_inst.data(), rep_inst.size() * 4, hipMemcpyHostToDevice,
@@ -1533,6 +1559,10 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             SG_HIP(hipMemcpyAsync(H->dev + H->off_small_reps, small.data(), small.size() * 8, hipMemcpyHostToDevice,
                                   st),
                    "upload replica list");
+        if (!H->h_litems.empty())
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_litems, H->h_litems.data(), H->h_litems.size() * sizeof(sg::BlockItem),
+                                  hipMemcpyHostToDevice, st),
+                   "upload start items");
         SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
         SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
     }
@@ -1572,8 +1602,13 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
         const sg::InstTab* tab = H->at<sg::InstTab>(H->off_tab);
         const int32_t* ri = H->at<int32_t>(H->off_rep_inst);
         const int64_t* sr = H->at<int64_t>(H->off_small_reps);
-        SG_HIP(sg::launch_init_batch(tab, ri, sr, H->n_small_reps, H->reps(), seed, st), "batched init kernel");
-        SG_HIP(sg::launch_energy_batch(tab, ri, sr, H->n_small_reps, H->reps(), nullptr, st), "batched energy kernel");
+        SG_HIP(sg::launch_init_batch(tab, ri, sr, H->n_small_reps, H->small_nmax, H->reps(), seed, st),
+               "batched init kernel");
+    }
+    if (!H->h_litems.empty()) {
+        SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
+                                      (int)H->h_litems.size(), H->lane_nmax, true, H->reps(), nullptr, seed, st),
+               "lane start kernel");
     }
     SG_HIP(hipStreamSynchronize(st), "stream sync");
     std::fill(H->started.begin(), H->started.end(), 1);
@@ -1699,7 +1734,12 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
                        "energy kernel");
         if (H->n_small_reps)
             SG_HIP(sg::launch_energy_batch(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_rep_inst),
-                                           H->at<int64_t>(H->off_small_reps), H->n_small_reps, nullptr, eout, st),
+                                           H->at<int64_t>(H->off_small_reps), H->n_small_reps, H->small_nmax, nullptr,
+                                           eout, st),
+                   "batched energy kernel");
+        if (!H->h_litems.empty())
+            SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
+                                          (int)H->h_litems.size(), H->lane_nmax, false, H->reps(), eout, 0, st),
                    "batched energy kernel");
         SG_HIP(hipMemcpyAsync(E, eout, (size_t)H->total_reps * 8, hipMemcpyDeviceToHost, st), "energy copy");
         SG_HIP(hipStreamSynchronize(st), "stream sync");

@@ -67,10 +67,15 @@ hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem
                         RepState* rs, CallStats* cs, int RG, int T, uint64_t seed, int rule, int until_conv,
                         hipStream_t st);
 int queue_max_blocks(size_t lds);
+// Start (init) or energy of many replicas of small instances, one lane per
+// replica; items (instance, first restart, count <= 64), instances of at most
+// 2048 spins.  Without init the energies go to out (or rs when out is null).
+hipError_t launch_start_lanes(const InstTab* tab, const BlockItem* items, int nitems, int nmax, bool init,
+                              RepState* rs, int64_t* out, uint64_t seed, hipStream_t st);
 hipError_t launch_init_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                             RepState* rs, uint64_t seed, hipStream_t st);
+                             int nmax, RepState* rs, uint64_t seed, hipStream_t st);
 hipError_t launch_energy_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                               RepState* rs, int64_t* out, hipStream_t st);
+                               int nmax, RepState* rs, int64_t* out, hipStream_t st);
 hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
                         uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
                         uint64_t seed, int rule, int until_conv, hipStream_t st);
