@@ -302,7 +302,7 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *   "block_min_restarts" SG_SCHED_AUTO uses the block schedule for instances
  *                        with at least this many restarts (default 32)
  *   "queue_wave_max_n"   queue items with at most this many spins run one per
- *                        wavefront, larger ones on a whole workgroup (4096)
+ *                        wavefront, larger ones on a whole workgroup (512)
  *   "queue_grid"         workgroups of the persistent queue launch (0 = all
  *                        that fit co-resident)
  *   "queue_min_items"    SG_SCHED_AUTO uses the queue schedule when the

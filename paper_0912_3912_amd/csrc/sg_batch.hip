@@ -387,24 +387,53 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
 // batched start and energy: one block of 256 threads per replica listed in
 // `reps` (handle replica indices); rep_inst maps a replica to its instance.
 
-// Energy of Sec. II eq. (1) / Sec. VI eq. (5) of one replica whose spins are
-// in LDS (sp), each edge and triple counted at its smallest internal index;
-// the block's four wavefronts share the slices; returns the total to thread 0.
-__device__ long long block_energy(const InstDev& I, const int8_t* __restrict__ sp)
+// Batched start of replicas cut into units of 1024 spins (any instance size,
+// the grid spread over all units): draws the spins of the unit; the unit at
+// spin 0 also resets the replica state (energy 0, summed by the energy units).
+__global__ __launch_bounds__(256) void k_start_units(const InstTab* __restrict__ tab,
+                                                     const StartUnit* __restrict__ units, RepState* __restrict__ rs,
+                                                     uint64_t seed)
 {
+    const StartUnit u = units[blockIdx.x];
+    const InstTab& Q = tab[u.inst];
+    const uint32_t r = (uint32_t)(u.g - Q.rep_base);
+    int8_t* sp = Q.spins + (int64_t)r * Q.spin_stride;
+    const int end = min(Q.I.n, u.off + 1024);
+    for (int i = u.off + threadIdx.x; i < end; i += blockDim.x)
+        sp[i] = (int8_t)(rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
+    if (u.off == 0 && threadIdx.x == 0) {
+        RepState z;
+        z.E = 0; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
+        rs[u.g] = z;
+    }
+}
+
+// Energy of replicas cut into units of four slices: each unit adds its rows'
+// terms (each edge and triple at its smallest internal index) to rs[g].E, or
+// to out[g] (zeroed before), with one int64 atomic.
+__global__ __launch_bounds__(256) void k_energy_units(const InstTab* __restrict__ tab,
+                                                      const StartUnit* __restrict__ units, RepState* __restrict__ rs,
+                                                      int64_t* __restrict__ out)
+{
+    const StartUnit u = units[blockIdx.x];
+    const InstTab& Q = tab[u.inst];
+    const InstDev& I = Q.I;
+    const int r = (int)(u.g - Q.rep_base);
+    const int8_t* s = Q.spins + (int64_t)r * Q.spin_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     long long acc = 0;
-    for (int sl = wave; sl < I.nslices; sl += 4) {
+    const int sl = u.off + wave;
+    if (sl < I.nslices) {
         const Slice S = I.slices[sl];
         if (lane < S.rows) {
             const int i = S.row0 + lane;
-            const int si = sp[i];
+            const int si = s[i];
             int e = I.h[i] * si;
             const uint32_t* p = I.nbr + S.ebase + lane;
             for (int k = 0; k < S.ew; ++k) {
                 const uint32_t w = p[k * kSlice];
                 const int j = (int)(w >> 8);
-                if (j > i) e += bat_j(w) * si * sp[j];
+                if (j > i) e += bat_j(w) * si * s[j];
             }
             if (I.has_tri) {
                 const uint32_t* pa = I.ta + S.tbase + lane;
@@ -412,10 +441,10 @@ __device__ long long block_energy(const InstDev& I, const int8_t* __restrict__ s
                 for (int k = 0; k < S.tw; ++k) {
                     const uint32_t wa = pa[k * kSlice];
                     const int a = (int)(wa >> 8), b = (int)pb[k * kSlice];
-                    if (a > i && b > i) e += bat_j(wa) * si * sp[a] * sp[b];
+                    if (a > i && b > i) e += bat_j(wa) * si * s[a] * s[b];
                 }
             }
-            acc += e;
+            acc = e;
         }
     }
 #pragma unroll
@@ -423,54 +452,26 @@ __device__ long long block_energy(const InstDev& I, const int8_t* __restrict__ s
     __shared__ long long part[4];
     if (lane == 0) part[wave] = acc;
     __syncthreads();
-    return -(part[0] + part[1] + part[2] + part[3]);
-}
-
-// Random start of one replica per block (grid over the listed replicas):
-// spins drawn into LDS and stored, then the start energy from LDS; resets
-// the replica state.
-__global__ __launch_bounds__(256) void k_init_batch(const InstTab* __restrict__ tab, const int32_t* __restrict__ rep_inst,
-                                                    const int64_t* __restrict__ reps, RepState* __restrict__ rs,
-                                                    uint64_t seed)
-{
-    extern __shared__ int8_t bsp[];
-    const int64_t g = reps[blockIdx.x];
-    const InstTab& Q = tab[rep_inst[g]];
-    const uint32_t r = (uint32_t)(g - Q.rep_base);
-    int8_t* sp = Q.spins + (int64_t)r * Q.spin_stride;
-    for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x) {
-        const int8_t v = (int8_t)(rng_bit(seed, Q.I.ext[i], 0xFFFFFFFFu, Q.I.instance_id, r) ? -1 : 1);
-        bsp[i] = v;
-        sp[i] = v;
-    }
-    __syncthreads();
-    const long long E = block_energy(Q.I, bsp);
     if (threadIdx.x == 0) {
-        RepState z;
-        z.E = E; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
-        rs[g] = z;
+        const long long t = -(part[0] + part[1] + part[2] + part[3]);
+        if (t) atomicAdd(reinterpret_cast<unsigned long long*>(out ? out + u.g : &rs[u.g].E), (unsigned long long)t);
     }
 }
 
-// Energy of the stored spins of the listed replicas (spins staged in LDS);
-// writes rs[g].E (out == NULL) or out[g].
-__global__ __launch_bounds__(256) void k_energy_batch(const InstTab* __restrict__ tab,
-                                                      const int32_t* __restrict__ rep_inst,
-                                                      const int64_t* __restrict__ reps, RepState* __restrict__ rs,
-                                                      int64_t* __restrict__ out)
+hipError_t launch_start_units(const InstTab* tab, const StartUnit* start_units, int64_t n_start,
+                              const StartUnit* energy_units, int64_t n_energy, RepState* rs, int64_t* out,
+                              uint64_t seed, bool init, hipStream_t st)
 {
-    extern __shared__ int8_t bsp[];
-    const int64_t g = reps[blockIdx.x];
-    const InstTab& Q = tab[rep_inst[g]];
-    const int r = (int)(g - Q.rep_base);
-    const int8_t* s = Q.spins + (int64_t)r * Q.spin_stride;
-    for (int i = threadIdx.x; i < Q.I.n; i += blockDim.x) bsp[i] = s[i];
-    __syncthreads();
-    const long long t = block_energy(Q.I, bsp);
-    if (threadIdx.x == 0) {
-        if (out) out[g] = t;
-        else rs[g].E = t;
+    if (init)
+        for (int64_t b0 = 0; b0 < n_start; b0 += (1u << 30)) {
+            const unsigned nb = (unsigned)std::min<int64_t>(n_start - b0, 1u << 30);
+            hipLaunchKernelGGL(k_start_units, dim3(nb), dim3(256), 0, st, tab, start_units + b0, rs, seed);
+        }
+    for (int64_t b0 = 0; b0 < n_energy; b0 += (1u << 30)) {
+        const unsigned nb = (unsigned)std::min<int64_t>(n_energy - b0, 1u << 30);
+        hipLaunchKernelGGL(k_energy_units, dim3(nb), dim3(256), 0, st, tab, energy_units + b0, rs, out);
     }
+    return hipGetLastError();
 }
 
 // Start and energy of many replicas of one instance, one lane per replica
@@ -576,30 +577,6 @@ hipError_t launch_start_lanes(const InstTab* tab, const BlockItem* items, int ni
 
 // ---------------------------------------------------------------------------
 // launchers
-
-hipError_t launch_init_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                             int nmax, RepState* rs, uint64_t seed, hipStream_t st)
-{
-    const size_t lds = ((size_t)nmax + 3) & ~(size_t)3;
-    if (lds > 65536) return hipErrorInvalidValue;
-    for (int64_t b0 = 0; b0 < nreps; b0 += (1u << 30)) {
-        const unsigned nb = (unsigned)std::min<int64_t>(nreps - b0, 1u << 30);
-        hipLaunchKernelGGL(k_init_batch, dim3(nb), dim3(256), lds, st, tab, rep_inst, reps + b0, rs, seed);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_energy_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                               int nmax, RepState* rs, int64_t* out, hipStream_t st)
-{
-    const size_t lds = ((size_t)nmax + 3) & ~(size_t)3;
-    if (lds > 65536) return hipErrorInvalidValue;
-    for (int64_t b0 = 0; b0 < nreps; b0 += (1u << 30)) {
-        const unsigned nb = (unsigned)std::min<int64_t>(nreps - b0, 1u << 30);
-        hipLaunchKernelGGL(k_energy_batch, dim3(nb), dim3(256), lds, st, tab, rep_inst, reps + b0, rs, out);
-    }
-    return hipGetLastError();
-}
 
 size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, int RG)
 {

@@ -56,7 +56,6 @@ constexpr int32_t kMaxRestarts = 65535;
 constexpr int32_t kMaxLatticeTiles = 1024;
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
-constexpr int32_t kBatchInitMaxN = 65536;
 constexpr int32_t kLaneStartMaxN = 2048;       // lane-per-replica start/energy: instances up to this size ...
 constexpr int32_t kLaneStartMinR = 32;         // ... with at least this many restarts  // instances below this size start and evaluate in batched launches
 
@@ -115,7 +114,7 @@ struct sg_ctx {
     int32_t lattice_wg_max_n = 150000; // largest lattice run as one workgroup per replica
     int32_t block_rg = 0;              // restarts per block workgroup (0 = largest that fits)
     int32_t block_min_restarts = 32;   // AUTO uses the block schedule from this many restarts
-    int32_t queue_wave_max_n = 4096;   // queue items up to this size run one per wavefront
+    int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
     int32_t graph_sweeps = 32;         // sweeps per captured graph (SG_SCHED_GRAPH)
@@ -130,9 +129,11 @@ struct sg_ctx {
     hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
     uint64_t off_tbase = 0;            // one sweep base per instance (graph replays)
     uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
-    uint64_t off_rep_inst = 0, off_small_reps = 0;
-    int64_t n_small_reps = 0;                  // replicas of instances below kBatchInitMaxN
-    int32_t small_nmax = 1;                    // largest of those instances
+    uint64_t off_rep_inst = 0;
+    // batched start / energy of the replicas not started one lane each: units
+    // of 1024 spins (start) and of four slices (energy)
+    std::vector<sg::StartUnit> h_sunits, h_eunits;
+    uint64_t off_sunits = 0, off_eunits = 0;
     std::vector<sg::BlockItem> h_litems;       // lane-per-replica start items (instance, r0, count <= 64)
     int32_t lane_nmax = 1;
     uint64_t off_litems = 0;
@@ -683,13 +684,20 @@ void layout(sg_ctx* H)
     H->off_qcnt = take(64);
     H->off_rep_inst = take((uint64_t)H->total_reps * 4);
     H->off_tbase = take((uint64_t)H->insts.size() * 4);
-    H->n_small_reps = 0;
-    H->small_nmax = 1;
-    for (const HostInst& q : H->insts)
-        if (q.n < kBatchInitMaxN && !q.dense && !lane_start(q)) {
-            H->n_small_reps += q.R;
-            H->small_nmax = std::max(H->small_nmax, q.n);
+    H->h_sunits.clear();
+    H->h_eunits.clear();
+    for (size_t k = 0; k < H->insts.size(); ++k) {
+        const HostInst& q = H->insts[k];
+        if (q.dense || lane_start(q)) continue;
+        for (int32_t r = 0; r < q.R; ++r) {
+            const int64_t g = q.rep_base + r;
+            for (int32_t i0 = 0; i0 < q.n; i0 += 1024) H->h_sunits.push_back(sg::StartUnit{g, (int32_t)k, i0});
+            for (int32_t s0 = 0; s0 < (int32_t)q.slices.size(); s0 += 4)
+                H->h_eunits.push_back(sg::StartUnit{g, (int32_t)k, s0});
         }
+    }
+    H->off_sunits = take(H->h_sunits.size() * sizeof(sg::StartUnit));
+    H->off_eunits = take(H->h_eunits.size() * sizeof(sg::StartUnit));
     H->h_litems.clear();
     H->lane_nmax = 1;
     for (size_t k = 0; k < H->insts.size(); ++k) {
@@ -711,7 +719,6 @@ void layout(sg_ctx* H)
     }
     H->off_dtab = take(ni * sizeof(sg::DenseTab));
     H->off_ditems = take(H->h_ditems.size() * sizeof(sg::BlockItem));
-    H->off_small_reps = take((uint64_t)H->n_small_reps * 8);
     H->off_best_E = take(ni * 8);
     H->off_best_r = take(ni * 4);
     H->off_rep_base = take(ni * 8);
@@ -1543,27 +1550,25 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
         SG_HIP(hipMemcpyAsync(H->dev + H->off_ctab, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st),
                "upload colour table");
         std::vector<int32_t> rep_inst((size_t)H->total_reps);
-        std::vector<int64_t> small;
-        small.reserve((size_t)H->n_small_reps);
         for (size_t k = 0; k < H->insts.size(); ++k) {
             const HostInst& q = H->insts[k];
-            for (int32_t r = 0; r < q.R; ++r) {
-                rep_inst[(size_t)(q.rep_base + r)] = (int32_t)k;
-                if (q.n < kBatchInitMaxN && !q.dense && !lane_start(q)) small.push_back(q.rep_base + r);
-            }
+            for (int32_t r = 0; r < q.R; ++r) rep_inst[(size_t)(q.rep_base + r)] = (int32_t)k;
         }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_rep_inst, rep_inst.data(), rep_inst.size() * 4, hipMemcpyHostToDevice,
                               st),
                "upload replica table");
-        if (!small.empty())
-            SG_HIP(hipMemcpyAsync(H->dev + H->off_small_reps, small.data(), small.size() * 8, hipMemcpyHostToDevice,
-                                  st),
-                   "upload replica list");
+        if (!H->h_sunits.empty())
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_sunits, H->h_sunits.data(), H->h_sunits.size() * sizeof(sg::StartUnit),
+                                  hipMemcpyHostToDevice, st),
+                   "upload start units");
+        if (!H->h_eunits.empty())
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_eunits, H->h_eunits.data(), H->h_eunits.size() * sizeof(sg::StartUnit),
+                                  hipMemcpyHostToDevice, st),
+                   "upload energy units");
         if (!H->h_litems.empty())
             SG_HIP(hipMemcpyAsync(H->dev + H->off_litems, H->h_litems.data(), H->h_litems.size() * sizeof(sg::BlockItem),
                                   hipMemcpyHostToDevice, st),
                    "upload start items");
-        SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
         SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
     }
     SG_HIP(hipStreamSynchronize(st), "stream sync after upload");
@@ -1588,23 +1593,11 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
         std::fill(H->started.begin(), H->started.end(), 1);
         return SG_OK;
     }
-    for (const HostInst& q : H->insts) {
-        if (q.n < kBatchInitMaxN) continue;
-        const sg::InstDev I = H->view(q);
-        sg::RepState* rs = H->reps() + q.rep_base;
-        SG_HIP(sg::launch_init(I, H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, rs, q.R, seed, st),
-               "init kernel");
-        SG_HIP(sg::launch_energy(I, H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
-                                 H->at<int64_t>(H->off_slots), q.nslots, rs, nullptr, st),
-               "energy kernel");
-    }
-    if (H->n_small_reps) {
-        const sg::InstTab* tab = H->at<sg::InstTab>(H->off_tab);
-        const int32_t* ri = H->at<int32_t>(H->off_rep_inst);
-        const int64_t* sr = H->at<int64_t>(H->off_small_reps);
-        SG_HIP(sg::launch_init_batch(tab, ri, sr, H->n_small_reps, H->small_nmax, H->reps(), seed, st),
-               "batched init kernel");
-    }
+    if (!H->h_sunits.empty())
+        SG_HIP(sg::launch_start_units(H->at<sg::InstTab>(H->off_tab), H->at<sg::StartUnit>(H->off_sunits),
+                                      (int64_t)H->h_sunits.size(), H->at<sg::StartUnit>(H->off_eunits),
+                                      (int64_t)H->h_eunits.size(), H->reps(), nullptr, seed, true, st),
+               "start kernels");
     if (!H->h_litems.empty()) {
         SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
                                       (int)H->h_litems.size(), H->lane_nmax, true, H->reps(), nullptr, seed, st),
@@ -1727,16 +1720,13 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
             SG_HIP(sg::launch_dense_energy(H->at<sg::DenseTab>(H->off_dtab), H->at<sg::BlockItem>(H->off_ditems),
                                            (int)H->h_ditems.size(), eout, st),
                    "dense energy kernel");
-        for (const HostInst& q : H->insts)
-            if (q.n >= kBatchInitMaxN)
-                SG_HIP(sg::launch_energy(H->view(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
-                                         H->at<int64_t>(H->off_slots), q.nslots, nullptr, eout + q.rep_base, st),
-                       "energy kernel");
-        if (H->n_small_reps)
-            SG_HIP(sg::launch_energy_batch(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_rep_inst),
-                                           H->at<int64_t>(H->off_small_reps), H->n_small_reps, H->small_nmax, nullptr,
-                                           eout, st),
-                   "batched energy kernel");
+        if (!H->h_eunits.empty()) {
+            SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(eout), (uint64_t)H->total_reps * 2, 0u, st),
+                   "fill kernel");
+            SG_HIP(sg::launch_start_units(H->at<sg::InstTab>(H->off_tab), nullptr, 0, H->at<sg::StartUnit>(H->off_eunits),
+                                          (int64_t)H->h_eunits.size(), H->reps(), eout, 0, false, st),
+                   "energy kernel");
+        }
         if (!H->h_litems.empty())
             SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
                                           (int)H->h_litems.size(), H->lane_nmax, false, H->reps(), eout, 0, st),

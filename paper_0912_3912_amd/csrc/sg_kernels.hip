@@ -44,24 +44,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t v)
         p[i] = v;
 }
 
-// Random start (Sec. IV): s_i = -1 iff bit 0 of Philox(seed; ext(i), ~0, id, r)
-// is 1.  grid = (ceil(n/256), R).  Also resets the replica counters.
-__global__ void k_init(InstDev I, int8_t* __restrict__ spins, int64_t stride, RepState* __restrict__ rs,
-                       uint64_t seed)
-{
-    const uint32_t r = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < I.n) {
-        const int b = rng_bit(seed, I.ext[i], 0xFFFFFFFFu, I.instance_id, r);
-        spins[r * stride + i] = (int8_t)(b ? -1 : 1);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        RepState z;
-        z.E = 0; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
-        rs[r] = z;
-    }
-}
-
 // Energy, Sec. II eq. (1) / Sec. VI eq. (5): each row i adds
 // h_i s_i + sum_{j > i} J s_i s_j + sum_{i < a, i < b} K s_i s_a s_b, so every
 // edge and triple is counted once (at its smallest internal index).
@@ -392,13 +374,6 @@ hipError_t launch_fill_u32(void* p, uint64_t count, uint32_t v, hipStream_t st)
 {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid1(count, 256, 4096)), dim3(256), 0, st, (uint32_t*)p, count, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_init(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, uint64_t seed,
-                       hipStream_t st)
-{
-    hipLaunchKernelGGL(k_init, dim3(grid1(I.n, 256, 1u << 30), R), dim3(256), 0, st, I, spins, stride, rs, seed);
     return hipGetLastError();
 }
 

@@ -8,8 +8,6 @@
 namespace sg {
 
 hipError_t launch_fill_u32(void* p, uint64_t count, uint32_t v, hipStream_t st);
-hipError_t launch_init(const InstDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, uint64_t seed,
-                       hipStream_t st);
 // Energy of every replica of one instance into rs[r].E (out == NULL) or out[r].
 hipError_t launch_energy(const InstDev& I, const int8_t* spins, int64_t stride, int R, int64_t* slots,
                          int nslots, RepState* rs, int64_t* out, hipStream_t st);
@@ -72,10 +70,12 @@ int queue_max_blocks(size_t lds);
 // 2048 spins.  Without init the energies go to out (or rs when out is null).
 hipError_t launch_start_lanes(const InstTab* tab, const BlockItem* items, int nitems, int nmax, bool init,
                               RepState* rs, int64_t* out, uint64_t seed, hipStream_t st);
-hipError_t launch_init_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                             int nmax, RepState* rs, uint64_t seed, hipStream_t st);
-hipError_t launch_energy_batch(const InstTab* tab, const int32_t* rep_inst, const int64_t* reps, int64_t nreps,
-                               int nmax, RepState* rs, int64_t* out, hipStream_t st);
+// Batched start (init: spins drawn by units of 1024 spins, state reset) and
+// energy (units of four slices, int64 atomics into rs[g].E or into out[g],
+// which must be zero).
+hipError_t launch_start_units(const InstTab* tab, const StartUnit* start_units, int64_t n_start,
+                              const StartUnit* energy_units, int64_t n_energy, RepState* rs, int64_t* out,
+                              uint64_t seed, bool init, hipStream_t st);
 hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
                         uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
                         uint64_t seed, int rule, int until_conv, hipStream_t st);

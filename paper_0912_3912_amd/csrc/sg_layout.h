@@ -100,6 +100,12 @@ struct BlockItem {           // k_block: restarts [r0, r0 + nr) of instance inst
     int32_t pad;
 };
 
+struct StartUnit {           // batched start / energy: a range of replica g
+    int64_t g;               // replica (handle order)
+    int32_t inst;            // its instance
+    int32_t off;             // first spin (start) or first slice (energy)
+};
+
 struct QueueItem {           // k_queue: restart r of instance inst
     int32_t inst;
     int32_t r;
