@@ -46,14 +46,33 @@ __device__ __forceinline__ uint64_t fm_key(int gain, int ext)
     return ((uint64_t)(uint32_t)(gain + kFmGainBias) << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)ext);
 }
 
+// One step of a wave-wide maximum through DPP lane permutations (no LDS
+// traffic): lanes enabled by ROWS take the larger of their value and the
+// permuted one; the others keep theirs.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_max_step(uint64_t v)
+{
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const uint32_t hi2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    const uint64_t w = ((uint64_t)hi2 << 32) | lo2;
+    return w > v ? w : v;
+}
+
+// Maximum over the 64 lanes (every lane active): within quads, half-rows and
+// rows by permutations, then across the four rows by the row broadcasts; lane
+// 63 ends with the maximum, which is read back as a uniform value.
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
+    v = dpp_max_step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_max_step<0x140, 0xF>(v);  // row_mirror
+    v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ void wave_lds_order()
@@ -70,7 +89,7 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                                                    const QueueItem* __restrict__ items, int nitems, int nmax,
                                                    int waves_per_block, RepState* __restrict__ rs,
                                                    CallStats* __restrict__ cs, uint32_t* __restrict__ err,
-                                                   int max_passes, int until_conv)
+                                                   int max_passes, int until_conv, int stage_cap)
 {
     extern __shared__ uint8_t fm_lds[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -78,10 +97,41 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
     long long att = 0, kept_all = 0;
     long long passes_done = 0;
     int unconv = 0;
+    // When every wavefront of the block works on one instance (items are
+    // instance-major), the block stages that instance's slices, coupling and
+    // hyper-coupling words in LDS, so the partner reads of every move stay
+    // on chip.
+    const int first = blockIdx.x * waves_per_block;
+    const int last = min(nitems, first + waves_per_block) - 1;
+    const int inst0 = items[first].inst;
+    const InstTab& Q0 = tab[inst0];
+    const size_t stage_bytes = (size_t)Q0.I.nslices * sizeof(Slice) + (size_t)Q0.nbr_words * 4 +
+                               (TRI ? (size_t)Q0.tri_words * 8 : 0);
+    const bool staged = items[last].inst == inst0 && stage_bytes <= (size_t)stage_cap;
+    InstDev IS = Q0.I;
+    if (staged) {
+        uint8_t* sbase = fm_lds + (size_t)waves_per_block * fm_wave_bytes(nmax);
+        Slice* sl = reinterpret_cast<Slice*>(sbase);
+        uint32_t* nb = reinterpret_cast<uint32_t*>(sl + Q0.I.nslices);
+        uint32_t* ta = nb + Q0.nbr_words;
+        uint32_t* tb = ta + (TRI ? Q0.tri_words : 0);
+        for (int k = threadIdx.x; k < Q0.I.nslices; k += blockDim.x) sl[k] = Q0.I.slices[k];
+        for (int k = threadIdx.x; k < Q0.nbr_words; k += blockDim.x) nb[k] = Q0.I.nbr[k];
+        if (TRI)
+            for (int k = threadIdx.x; k < Q0.tri_words; k += blockDim.x) {
+                ta[k] = Q0.I.ta[k];
+                tb[k] = Q0.I.tb[k];
+            }
+        IS.slices = sl;
+        IS.nbr = nb;
+        IS.ta = ta;
+        IS.tb = tb;
+    }
+    __syncthreads();
     if (wave < waves_per_block && item < nitems) {
         const QueueItem it = items[item];
         const InstTab& Q = tab[it.inst];
-        const InstDev& I = Q.I;
+        const InstDev& I = staged ? IS : Q.I;
         const int n = I.n;
         RepState* st = rs + Q.rep_base + it.r;
         if (!st->converged) {
@@ -137,11 +187,15 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                 wave_lds_order();
                 uint64_t locked = 0;
                 uint64_t best = 0;
+                int besti = -1;
                 for (int k = 0; k < G; ++k) {
                     const int i = lane + 64 * k;
                     if (i < n) {
                         const uint64_t key = fm_key(gain[i], ext[i]);
-                        best = key > best ? key : best;
+                        if (key > best) {
+                            best = key;
+                            besti = i;
+                        }
                     }
                 }
                 long long E = Estar, Elow = Estar;
@@ -149,18 +203,10 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                 for (int step = 0; step < n; ++step) {
                     const uint64_t top = wave_max_u64(best);
                     const int g = (int)(uint32_t)(top >> 32) - kFmGainBias;
-                    // internal index of the move: the lane whose cached key is the
-                    // maximum owns it; it scans its spins for the matching key
+                    // the move: the spin cached by the lane holding the maximum key
                     const uint64_t own = __ballot(best == top);
                     const int owner = (int)__builtin_ctzll(own);
-                    int mine = -1;
-                    if (lane == owner) {
-                        for (int k = 0; k < G; ++k) {
-                            const int i = lane + 64 * k;
-                            if (i < n && !((locked >> k) & 1ull) && fm_key(gain[i], ext[i]) == top) mine = i;
-                        }
-                    }
-                    const int i = __shfl(mine, owner, 64);
+                    const int i = __builtin_amdgcn_readlane(besti, owner);
                     if (i < 0) {  // a cached key without its spin: internal error, stop this replica
                         bad = true;
                         break;
@@ -205,11 +251,15 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                     if (lane < 2) dirty[lane] = 0u;
                     if (rescan) {
                         best = 0;
+                        besti = -1;
                         for (int k = 0; k < G; ++k) {
                             const int ii = lane + 64 * k;
                             if (ii < n && !((locked >> k) & 1ull)) {
                                 const uint64_t key = fm_key(gain[ii], ext[ii]);
-                                best = key > best ? key : best;
+                                if (key > best) {
+                                    best = key;
+                                    besti = ii;
+                                }
                             }
                         }
                     }
@@ -278,22 +328,22 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
 size_t fm_lds_bytes(int nmax, int waves) { return fm_wave_bytes(nmax) * (size_t)waves; }
 
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
-                     bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv,
-                     hipStream_t st)
+                     int stage_cap, bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
+                     int until_conv, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    if (waves < 1 || waves > kFmWaves) return hipErrorInvalidValue;
-    const size_t lds = fm_lds_bytes(nmax, waves);
+    if (waves < 1 || waves > kFmWaves || stage_cap < 0) return hipErrorInvalidValue;
+    const size_t lds = fm_lds_bytes(nmax, waves) + (size_t)stage_cap;
     const void* kern = tri ? (const void*)k_fm<true> : (const void*)k_fm<false>;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int blocks = (nitems + waves - 1) / waves;
     if (tri)
         hipLaunchKernelGGL(k_fm<true>, dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax, waves,
-                           rs, cs, err, max_passes, until_conv);
+                           rs, cs, err, max_passes, until_conv, stage_cap);
     else
         hipLaunchKernelGGL(k_fm<false>, dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax, waves,
-                           rs, cs, err, max_passes, until_conv);
+                           rs, cs, err, max_passes, until_conv, stage_cap);
     return hipGetLastError();
 }
 

@@ -1306,8 +1306,14 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     std::stable_sort(H->h_qitems.begin(), H->h_qitems.end(), [&](const sg::QueueItem& a, const sg::QueueItem& b) {
         return H->insts[a.inst].n > H->insts[b.inst].n;
     });
+    // the wavefronts' slices, plus room to stage one instance's structure
+    size_t stage = 0;
+    for (const HostInst& q : H->insts)
+        stage = std::max(stage, q.slices.size() * sizeof(sg::Slice) + q.nbr.size() * 4 + (tri ? q.ta.size() * 8 : 0));
+    stage = (stage + 15) / 16 * 16;
     int waves = 16;
-    while (waves > 1 && sg::fm_lds_bytes(nmax, waves) > kLdsBudget) --waves;
+    while (waves > 1 && sg::fm_lds_bytes(nmax, waves) + stage > kLdsBudget) --waves;
+    if (sg::fm_lds_bytes(nmax, waves) + stage > kLdsBudget) stage = 0;  // too large to stage: read from memory
     sg::QueueItem* dit = H->at<sg::QueueItem>(H->off_qitems);
     uint32_t* err = H->at<uint32_t>(H->off_err);
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
@@ -1319,7 +1325,8 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     SG_HIP(hipEventRecord(H->evh0, st), "event record");
     if (p->max_sweeps > 0)
         SG_HIP(sg::launch_fm(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
-                             (int)H->h_qitems.size(), nmax, waves, tri, H->reps(), H->at<sg::CallStats>(H->off_stats),
+                             (int)H->h_qitems.size(), nmax, waves, (int)stage, tri, H->reps(),
+                             H->at<sg::CallStats>(H->off_stats),
                              err, p->max_sweeps, p->until_converged, st),
                "pass kernel");
     SG_HIP(hipEventRecord(H->evh1, st), "event record");

@@ -46,9 +46,11 @@ hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* 
                               int nslots, int T, uint64_t seed, int rule, hipStream_t st);
 // The paper's pass-based search, one wavefront per replica item.
 size_t fm_lds_bytes(int nmax, int waves);
+// stage_cap: LDS bytes after the wavefronts' slices in which a block stages
+// its instance's structure when all its items share one instance.
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
-                     bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv,
-                     hipStream_t st);
+                     int stage_cap, bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
+                     int until_conv, hipStream_t st);
 // Dense hyper-Ising instances: one lane per replica; items are (instance,
 // first restart, count <= 64).  rule 0/1: colour sweeps; 2: pass-based search.
 hipError_t launch_dense_init(const DenseTab* tabs, const BlockItem* items, int nitems, RepState* rs, uint64_t seed,
