@@ -216,18 +216,21 @@ def run_chimera(args, sg, gen, torch, count=4096, sample=16):
     log(f"batched: {dt * 1e3:.2f} ms/step, {attempts:.3g} attempts, sweeps_max {st['sweeps_max']}, "
         f"schedule {st['schedule_used']}, hot {hot_us:.0f} us")
     h.free()
-    # per-instance baseline: the plain per-phase method on a sample, one instance at a time
-    hs = sg.load_instance(insts[:sample]).bind()
-    dts, outs_s = timed(lambda: step(SCHED_PHASE, hs), 1, 1, torch.cuda.synchronize)
-    extrap = dts * count / sample
-    log(f"per-instance per-phase: {dts * 1e3:.1f} ms for {sample} instances -> {extrap * 1e3:.0f} ms extrapolated")
-    hs.free()
+    extrap = None
+    if not args.no_plain:
+        # per-instance baseline: the plain per-phase method on a sample, one instance at a time
+        hs = sg.load_instance(insts[:sample]).bind()
+        dts, outs_s = timed(lambda: step(SCHED_PHASE, hs), 1, 1, torch.cuda.synchronize)
+        extrap = dts * count / sample
+        log(f"per-instance per-phase: {dts * 1e3:.1f} ms for {sample} instances -> {extrap * 1e3:.0f} ms "
+            "extrapolated")
+        hs.free()
     ops = int_ops_per_attempt(deg, tau)
     ach = ops * attempts / (hot_us / 1e6) / 1e12
     return {"workload": f"chimera{count}x256_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
             "attempts": attempts, "schedule": st["schedule_used"],
-            "per_instance_ms": round(extrap * 1e3, 2), "per_instance_sample": sample,
-            "per_instance_extrapolated": True, "speedup": round(extrap / dt, 2),
+            "per_instance_ms": None if extrap is None else round(extrap * 1e3, 2), "per_instance_sample": sample,
+            "per_instance_extrapolated": True, "speedup": None if extrap is None else round(extrap / dt, 2),
             "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(PEAK_INT_TOPS, 2),
                          "unit": "TOP/s", "frac": round(ach / PEAK_INT_TOPS, 4), "kernel": "k_block",
                          "ops_per_attempt": round(ops, 2)}}
@@ -356,23 +359,28 @@ def run_er(args, sg, gen, torch, count=2000):
 
     dt, outs = timed(step, args.batch_steps, 1, torch.cuda.synchronize)
     st = outs[-1]
-    dtp, outp = timed(lambda: step(SCHED_PHASE), 1, 0, torch.cuda.synchronize)
     attempts = st["attempts"]
-    assert outp[-1]["attempts"] == attempts
+    dtp = None
+    if not args.no_plain:
+        dtp, outp = timed(lambda: step(SCHED_PHASE), 1, 0, torch.cuda.synchronize)
+        assert outp[-1]["attempts"] == attempts
     hot_us = st["hot_ns"] / 1e3
     ntot = sum(i.n for i in insts)
     deg = sum(2 * i.m for i in insts) / ntot
     tau = sum(3 * i.t for i in insts) / ntot
     bpa = sell_bytes_per_attempt(deg, tau, spins_in_lds=True)
     ach = bpa * attempts / (hot_us / 1e6) / 1e9
-    log(f"batched {dt * 1e3:.2f} ms, per-instance per-phase {dtp * 1e3:.1f} ms, speedup {dtp / dt:.2f}")
+    log(f"batched {dt * 1e3:.2f} ms, hot {hot_us:.0f} us"
+        + ("" if dtp is None else f", per-instance per-phase {dtp * 1e3:.1f} ms, speedup {dtp / dt:.2f}"))
     h.free()
     return {"workload": f"er{count}_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
-            "attempts": attempts, "schedule": st["schedule_used"], "per_instance_ms": round(dtp * 1e3, 2),
-            "per_instance_extrapolated": False, "speedup": round(dtp / dt, 2),
+            "attempts": attempts, "schedule": st["schedule_used"],
+            "per_instance_ms": None if dtp is None else round(dtp * 1e3, 2),
+            "per_instance_extrapolated": False, "speedup": None if dtp is None else round(dtp / dt, 2),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": "k_queue",
-                         "bytes_per_attempt": round(bpa, 2)}}
+                         "bytes_per_attempt": round(bpa, 2), "traffic": measured_traffic("k_queue"),
+                         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}}
 
 
 def run_square(args, sg, gen, torch):
@@ -446,7 +454,8 @@ def main():
                     help="sweeps of the CPU oracle sample (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the Chimera batch in the default run")
-    ap.add_argument("--no-plain", action="store_true", help="skip the per-phase comparison run")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the per-phase comparison runs (the plain method and per-instance baselines)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-budget-mb", type=int, default=4096)
     ap.add_argument("--serving-slots", type=int, default=4)
