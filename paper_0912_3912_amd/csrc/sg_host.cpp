@@ -57,7 +57,8 @@ constexpr int32_t kMaxLatticeTiles = 1024;
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
 constexpr int32_t kLaneStartMaxN = 2048;       // lane-per-replica start/energy: instances up to this size ...
-constexpr int32_t kLaneStartMinR = 32;         // ... with at least this many restarts  // instances below this size start and evaluate in batched launches
+constexpr int32_t kLaneStartMinR = 32;         // ... with at least this many restarts, ...
+constexpr int64_t kLaneStartMinTotal = 16384;  // ... when such replicas fill the chip (64 per wavefront)  // instances below this size start and evaluate in batched launches
 
 struct HostInst {
     int32_t n = 0;
@@ -137,6 +138,7 @@ struct sg_ctx {
     std::vector<sg::BlockItem> h_litems;       // lane-per-replica start items (instance, r0, count <= 64)
     int32_t lane_nmax = 1;
     uint64_t off_litems = 0;
+    bool lanes_on = false;
     int64_t n_block_item_cap = 0, ctab_len = 0;
     std::vector<sg::BlockItem> h_bitems;
     std::vector<sg::QueueItem> h_qitems;
@@ -623,11 +625,18 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     return SG_OK;
 }
 
-// Replicas of this instance start (and recompute energies) one lane per replica.
-bool lane_start(const HostInst& q) { return !q.dense && q.n <= kLaneStartMaxN && q.R >= kLaneStartMinR; }
+// Replicas of this instance may start (and recompute energies) one lane per replica.
+bool lane_start_candidate(const HostInst& q) { return !q.dense && q.n <= kLaneStartMaxN && q.R >= kLaneStartMinR; }
 
 void layout(sg_ctx* H)
 {
+    // the lane path keeps one wavefront per 64 replicas busy with a whole
+    // instance: it pays off only with enough such wavefronts to fill the GPU
+    int64_t lane_reps = 0;
+    for (const HostInst& q : H->insts)
+        if (lane_start_candidate(q)) lane_reps += q.R;
+    H->lanes_on = lane_reps >= kLaneStartMinTotal;
+    auto lane_start = [&](const HostInst& q) { return H->lanes_on && lane_start_candidate(q); };
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         const uint64_t o = off;
