@@ -666,8 +666,9 @@ void layout(sg_ctx* H)
         }
         if (q.lat_ok) {
             q.off_lat_rec = take((uint64_t)q.n * 8);
-            // two copies of one word per interior z-row of every tile (z extent >= 4 sites)
-            q.lat_g_bytes = ((uint64_t)q.n / 4 + 4096) * 4 * 2 * q.R;
+            // two copies of one word per interior z-row of every tile (z extent >= 4 sites);
+            // the bit-plane kernel's words are 8 bytes (epoch tag and bits)
+            q.lat_g_bytes = ((uint64_t)q.n / 4 + 4096) * 8 * 2 * q.R;
             q.off_lat_g = take(q.lat_g_bytes);
             q.off_lat_flags = take((uint64_t)kMaxLatticeTiles * q.R * 4);
         }
@@ -959,13 +960,14 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
 }
 
 // Tiling and halo width of the bit-plane kernel.  Per colour phase a tile
-// costs a fixed latency plus its lanes' passes over the rows deeper than the
-// phase index (1024 rows per pass; a second pass costs more than the first,
-// it also doubles the wavefronts' tie draws), and every k phases an exchange
-// (a fixed latency plus passes over the box rows).  The constants are
-// microseconds measured for this kernel on the 10^6-spin lattice under both
-// rules; the choice minimises the cost per phase, subject to LDS,
-// co-residency and the geometry limits of the kernel.
+// costs a fixed latency plus one step per wavefront that each SIMD runs over
+// the rows deeper than the phase index (64 rows per wavefront, four SIMDs per
+// compute unit; under GREEDY_TIE a step also holds the wavefront's tie draws),
+// and every k phases an exchange (a fixed latency, plus a pass per further
+// 1024 box rows).  The constants are microseconds fitted to the measured time
+// of 1000 sweeps of this kernel on the 10^6-spin lattice over 31 tilings and
+// halo widths under both rules; the choice minimises the cost per phase,
+// subject to LDS, co-residency and the geometry limits of the kernel.
 bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeom& tg)
 {
     int cap_limit = kMaxLatticeTiles;
@@ -999,18 +1001,18 @@ bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeo
                     for (int a = 0; a < 3; ++a)
                         B[a] = (q.lat_L[a] + g.P[a] - 1) / g.P[a] + ((a < a0) ? 0 : 2 * k);
                     const double rows = (double)B[0] * B[1];
-                    const double ex0 = tie ? 7.5 : 4.5, ex1 = tie ? 1.4 : 0.5;
-                    const double ph1 = tie ? 1.3 : 0.55, ph2 = tie ? 1.0 : 0.4;
-                    double cost = ex0 + ex1 * std::ceil(rows / 1024.0);
+                    const double ex0 = tie ? 2.0 : 2.1, ex1 = 0.4;
+                    const double ph0 = tie ? 0.84 : 0.19, ph1 = tie ? 0.49 : 0.28;
+                    double cost = ex0 + ex1 * (std::ceil(rows / 1024.0) - 1.0);
                     for (int qq = 0; qq < k; ++qq) {
                         const double ax = a0 ? 1.0 : std::max(0, B[0] - 2 * (qq + 1));
                         const double ay = std::max(0, B[1] - 2 * (qq + 1));
-                        const double passes = std::ceil(ax * ay / 1024.0);
-                        cost += 0.3 + ph1 * passes + ph2 * std::max(0.0, passes - 1.0);
+                        const double steps = std::ceil(std::ceil(ax * ay / 64.0) / 4.0);
+                        cost += ph0 + ph1 * steps;
                     }
                     cost /= k;
                     if (!(cost < best - 1e-9 || (std::fabs(cost - best) <= 1e-9 && T < bestT))) continue;
-                    if ((int64_t)sg::lattice_tiles_words(g, q.lat_L) * 8 * q.R > (int64_t)q.lat_g_bytes) continue;
+                    if ((int64_t)sg::lattice_tiles_words(g, q.lat_L) * 16 * q.R > (int64_t)q.lat_g_bytes) continue;
                     if ((int64_t)T * q.R > cap_for(g)) continue;
                     best = cost;
                     bestT = T;
@@ -1061,23 +1063,30 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 const sg::TileGeom tg = qm.tile_geom;
                 const bool msc = qm.tile_msc != 0;
                 uint32_t* flags = H->at<uint32_t>(q.off_lat_flags);
-                SG_HIP(sg::launch_fill_u32(flags, (uint64_t)kMaxLatticeTiles * q.R, 0u, st), "fill kernel");
                 SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
                 // exchange words: at most n / (smallest z extent) + one row per tile, per copy
                 const int64_t words = sg::lattice_tiles_words(tg, q.lat_L) * q.R;
-                if ((uint64_t)words * 8 > q.lat_g_bytes)
-                    return fail(SG_ERANGE, "lattice tile exchange needs %lld bytes", (long long)words * 8);
-                uint32_t* G0 = H->at<uint32_t>(q.off_lat_g);
-                uint32_t* G1 = G0 + words;
-                SG_HIP(hipEventRecord(H->evh0, st), "event record");
-                if (msc)
-                    SG_HIP(sg::launch_lattice_msc(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs, q.R,
-                                                  acc, q.acc_slots, T, p->seed, p->rule, st),
+                const uint64_t wbytes = msc ? 8 : 4;
+                if ((uint64_t)words * wbytes * 2 > q.lat_g_bytes)
+                    return fail(SG_ERANGE, "lattice tile exchange needs %lld bytes",
+                                (long long)(words * wbytes * 2));
+                if (msc) {
+                    // tags of this launch's epochs start at 1: clear the tags of earlier launches
+                    uint64_t* G0 = H->at<uint64_t>(q.off_lat_g);
+                    SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(G0), (uint64_t)words * 4, 0u, st),
+                           "fill kernel");
+                    SG_HIP(hipEventRecord(H->evh0, st), "event record");
+                    SG_HIP(sg::launch_lattice_msc(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err, rs,
+                                                  q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
                            "lattice bit-plane kernel");
-                else
-                    SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G1, flags, err, rs,
-                                                    q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
+                } else {
+                    SG_HIP(sg::launch_fill_u32(flags, (uint64_t)kMaxLatticeTiles * q.R, 0u, st), "fill kernel");
+                    uint32_t* G0 = H->at<uint32_t>(q.off_lat_g);
+                    SG_HIP(hipEventRecord(H->evh0, st), "event record");
+                    SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, flags, err,
+                                                    rs, q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
                            "lattice tile kernel");
+                }
                 H->last_msc = msc ? 1 : 0;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;

@@ -41,8 +41,8 @@ int64_t lattice_tiles_words(const TileGeom& tg, const int L[3]);
 size_t lattice_msc_lds(const TileGeom& tg, const int L[3], int D);
 bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D);
 int lattice_msc_max_blocks(const TileGeom& tg, const int L[3], int D);
-hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint32_t* G0,
-                              uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
+hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint64_t* G0,
+                              uint64_t* G1, uint32_t* err, RepState* rs, int R, int64_t* acc,
                               int nslots, int T, uint64_t seed, int rule, hipStream_t st);
 // The paper's pass-based search, one wavefront per replica item.
 size_t fm_lds_bytes(int nmax, int waves);

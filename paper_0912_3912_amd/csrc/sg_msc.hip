@@ -117,9 +117,8 @@ __device__ __forceinline__ uint32_t u_eq(uint32_t u0, uint32_t u1, uint32_t u2)
 
 template <int D, bool TIE>
 __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, TileGeom tg, int8_t* __restrict__ canon,
-                                                             int64_t stride, uint32_t* __restrict__ G0,
-                                                             uint32_t* __restrict__ G1, uint32_t* __restrict__ flags,
-                                                             uint32_t* __restrict__ err, RepState* __restrict__ rs,
+                                                             int64_t stride, uint64_t* __restrict__ G0,
+                                                             uint64_t* __restrict__ G1, uint32_t* __restrict__ err, RepState* __restrict__ rs,
                                                              int64_t* __restrict__ acc, int nslots, int T,
                                                              uint64_t seed)
 {
@@ -161,9 +160,8 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
     __shared__ uint32_t mag_ay[64];
     int8_t* cs = canon + (int64_t)r * stride;
     const int rows_per_tile = ((L0 + tg.P[0] - 1) / tg.P[0]) * ((L1 + tg.P[1] - 1) / tg.P[1]);
-    uint32_t* g0 = G0 + (int64_t)r * ntiles * rows_per_tile;
-    uint32_t* g1 = G1 + (int64_t)r * ntiles * rows_per_tile;
-    uint32_t* fl = flags + (int64_t)r * ntiles;
+    uint64_t* g0 = G0 + (int64_t)r * ntiles * rows_per_tile;
+    uint64_t* g1 = G1 + (int64_t)r * ntiles * rows_per_tile;
     const uint32_t base = (uint32_t)rs[r].sweeps;
     auto gsite = [&](int x, int y, int z) -> int {
         return (wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1)) * L2 + wrapi(o[2] + z, L2);
@@ -364,9 +362,15 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             }
             __syncthreads();
         }
-        // ---- exchange (protocol of k_lattice_tiles): publish the interior
-        // z-rows, signal, wait for the neighbouring tiles, read the box back
-        uint32_t* gw = (e & 1) ? g1 : g0;
+        // ---- exchange: publish the interior z-rows, then read the box back.
+        // Every word travels with the epoch's tag in one 8-byte agent-scope
+        // atomic, so a reader that sees the tag holds the word of this epoch
+        // and no separate flag is needed.  Reuse of a buffer two epochs later
+        // is safe: a tile publishes into it again only after reading words of
+        // the next epoch from every neighbour (the boxes overlap both ways),
+        // and a neighbour publishes those only after it has read this epoch's.
+        uint64_t* gw = (e & 1) ? g1 : g0;
+        const uint64_t tag = (uint64_t)(uint32_t)(e + 1) << 32;
         for (int row = tid; row < nrow_int; row += kMscThreads) {
             const int x = (int)fdiv((uint32_t)row, mX1);
             const int y = row - x * X[1];
@@ -375,62 +379,55 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             const int pr = (par0 + bx + by) & 1;
             const uint64_t v = spread32(plane(kPlS, pr)[brow]) | (spread32(plane(kPlS, pr ^ 1)[brow]) << 1);
             const uint32_t w = (uint32_t)(v >> hk[2]) & low_bits(X[2]);
-            __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, tag | w, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        // Ordering: as in k_lattice_tiles, every exchange word and flag is an
-        // agent-scope atomic performed at the coherence point; each wave waits
-        // for its stores before the barrier, the flag follows the barrier and
-        // readers load words only after seeing the flag.
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(fl + tile, (uint32_t)(e + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (tid < 27) {
-            const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
-            const bool used = !(dx == 0 && dy == 0 && dz == 0) && !(D == 2 && dx != 0);
-            if (used) {
-                const int nx = (tc[0] + dx + tg.P[0]) % tg.P[0];
-                const int ny = (tc[1] + dy + tg.P[1]) % tg.P[1];
-                const int nz = (tc[2] + dz + tg.P[2]) % tg.P[2];
-                const int nb = (nx * tg.P[1] + ny) * tg.P[2] + nz;
-                uint32_t spins_left = 1u << 26;
-                while (__hip_atomic_load(fl + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)(e + 1)) {
-                    if (--spins_left == 0 ||
-                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        failed = true;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+        __syncthreads();  // the reads below overwrite plane rows published above
+        // After the last epoch the words are still awaited, though not used:
+        // then every neighbour has finished reading its box from the spin
+        // array before this tile writes its interior back.
+        const bool last = (e + 1) * k >= P_total;
+        for (int row = tid; row < rows && !failed; row += kMscThreads) {
+            const int x = (int)fdiv((uint32_t)row, mB1);
+            const int y = row - x * B[1];
+            const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
+            const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
+            const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
+            const int sx = tstart(0, tx), sy = tstart(1, ty);
+            const int X1t = tstart(1, ty + 1) - sy;
+            const int wrow = (gx - sx) * X1t + (gy - sy);
+            const int tb = (tx * tg.P[1] + ty) * tg.P[2];
+            uint64_t* al = gw + (int64_t)(tb + tzm) * rows_per_tile + wrow;
+            uint64_t* ah = gw + (int64_t)(tb + tzp) * rows_per_tile + wrow;
+            uint64_t* am = gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow;
+            uint64_t pl = __hip_atomic_load(al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t ph = __hip_atomic_load(ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t pm = __hip_atomic_load(am, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // bounded wait for the three words of this epoch; a timeout here or
+            // in any other tile raises the error flag and ends every workgroup
+            uint32_t left = 1u << 20;
+            while (((pl ^ tag) | (ph ^ tag) | (pm ^ tag)) >> 32) {
+                if (--left == 0 ||
+                    ((left & 63u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    failed = true;
+                    break;
                 }
+                __builtin_amdgcn_s_sleep(2);
+                if ((pl ^ tag) >> 32) pl = __hip_atomic_load(al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((ph ^ tag) >> 32) ph = __hip_atomic_load(ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((pm ^ tag) >> 32) pm = __hip_atomic_load(am, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (failed || last) continue;
+            const uint32_t wl = (uint32_t)pl, wh = (uint32_t)ph, wm = (uint32_t)pm;
+            const uint64_t v = (uint64_t)((wl >> (Xzm - hk[2])) & low_bits(hk[2])) | ((uint64_t)wm << hk[2]) |
+                               ((uint64_t)(wh & low_bits(hk[2])) << (hk[2] + X[2]));
+            const int pr = (par0 + x + y) & 1;
+            plane(kPlS, pr)[row] = even32(v);
+            plane(kPlS, pr ^ 1)[row] = even32(v >> 1);
         }
         failed = __syncthreads_or(failed);
         if (failed) break;
-        if ((e + 1) * k < P_total) {
-            for (int row = tid; row < rows; row += kMscThreads) {
-                const int x = (int)fdiv((uint32_t)row, mB1);
-                const int y = row - x * B[1];
-                const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
-                const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
-                const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
-                const int sx = tstart(0, tx), sy = tstart(1, ty);
-                const int X1t = tstart(1, ty + 1) - sy;
-                const int wrow = (gx - sx) * X1t + (gy - sy);
-                const int tb = (tx * tg.P[1] + ty) * tg.P[2];
-                const uint32_t wl = __hip_atomic_load(gw + (int64_t)(tb + tzm) * rows_per_tile + wrow, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t wh = __hip_atomic_load(gw + (int64_t)(tb + tzp) * rows_per_tile + wrow, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t wm = __hip_atomic_load(gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow,
-                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t v = (uint64_t)((wl >> (Xzm - hk[2])) & low_bits(hk[2])) | ((uint64_t)wm << hk[2]) |
-                                   ((uint64_t)(wh & low_bits(hk[2])) << (hk[2] + X[2]));
-                const int pr = (par0 + x + y) & 1;
-                plane(kPlS, pr)[row] = even32(v);
-                plane(kPlS, pr ^ 1)[row] = even32(v >> 1);
-            }
-            __syncthreads();
-        }
     }
     // write the interior back in internal order (one wavefront per row, lane = z)
     if (!failed) {
@@ -512,8 +509,8 @@ static const void* pick_msc_kernel(int D, bool tie)
                   : (tie ? msc_kernel<2, true>() : msc_kernel<2, false>());
 }
 
-hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint32_t* G0,
-                              uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R, int64_t* acc,
+hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint64_t* G0,
+                              uint64_t* G1, uint32_t* err, RepState* rs, int R, int64_t* acc,
                               int nslots, int T, uint64_t seed, int rule, hipStream_t st)
 {
     if (!lattice_msc_geometry_ok(tg, Lt.L, Lt.D)) return hipErrorInvalidValue;
@@ -524,7 +521,7 @@ hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* 
     const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
     LatticeDev a0 = Lt;
     TileGeom a1 = tg;
-    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &flags, &err, &rs, &acc, &nslots, &T, &seed};
+    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &err, &rs, &acc, &nslots, &T, &seed};
     return hipLaunchCooperativeKernel(kern, dim3(ntiles * R), dim3(kMscThreads), args, (unsigned)lds, st);
 }
 
