@@ -85,10 +85,11 @@ def sources_sha256(paths) -> str:
     return d.hexdigest()
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, geometry=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     runs (scaled by a plain-copy calibration), or None when a source of the
-    kernel has changed since the counters were taken."""
+    kernel has changed since the counters were taken, or when the record names
+    a launch geometry (tiling, halo width) other than this run's."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -97,6 +98,8 @@ def measured_traffic(kernel: str):
         return None
     srcs = rec.get("sources") or [rec["source"]]
     if not all(os.path.exists(os.path.join(ROOT, p)) for p in srcs) or sources_sha256(srcs) != rec["sha256"]:
+        return None
+    if rec.get("geometry") is not None and rec["geometry"] != geometry:
         return None
     return rec["bytes_per_launch"]
 
@@ -153,7 +156,8 @@ def run_cubic(args, sg, gen, torch):
     kname = KERNEL_NAME.get(sched, str(sched))
     if sched == 3 and h.query("last_msc"):
         kname = "k_lattice_msc"
-    traffic = measured_traffic(kname) if sched == 3 else None
+    geometry = {"tiles": h.query("last_tiles"), "halo_k": h.query("last_tile_k")}
+    traffic = measured_traffic(kname, geometry) if sched == 3 else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

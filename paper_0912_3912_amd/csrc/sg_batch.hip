@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
 
 // Batched start of replicas cut into units of 1024 spins (any instance size,
 // the grid spread over all units): draws the spins of the unit; the unit at
-// spin 0 also resets the replica state (energy 0, summed by the energy units).
+// spin 0 also resets the replica state (its energy is then set by k_energy_segs).
 __global__ __launch_bounds__(256) void k_start_units(const InstTab* __restrict__ tab,
                                                      const StartUnit* __restrict__ units, RepState* __restrict__ rs,
                                                      uint64_t seed)
@@ -408,12 +408,13 @@ __global__ __launch_bounds__(256) void k_start_units(const InstTab* __restrict__
     }
 }
 
-// Energy of replicas cut into units of four slices: each unit adds its rows'
-// terms (each edge and triple at its smallest internal index) to rs[g].E, or
-// to out[g] (zeroed before), with one int64 atomic.
+// Energy of replicas cut into units of four slices: each unit sums its rows'
+// terms (each edge and triple at its smallest internal index) into part[unit];
+// k_energy_segs then adds up the units of each replica.  (One atomic per unit
+// on the replica's energy serialised thousands of units of a large instance.)
 __global__ __launch_bounds__(256) void k_energy_units(const InstTab* __restrict__ tab,
-                                                      const StartUnit* __restrict__ units, RepState* __restrict__ rs,
-                                                      int64_t* __restrict__ out)
+                                                      const StartUnit* __restrict__ units, int64_t ubase,
+                                                      int64_t* __restrict__ part_out)
 {
     const StartUnit u = units[blockIdx.x];
     const InstTab& Q = tab[u.inst];
@@ -449,18 +450,43 @@ __global__ __launch_bounds__(256) void k_energy_units(const InstTab* __restrict_
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    __shared__ long long part[4];
-    if (lane == 0) part[wave] = acc;
+    __shared__ long long wpart[4];
+    if (lane == 0) wpart[wave] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const long long t = -(part[0] + part[1] + part[2] + part[3]);
-        if (t) atomicAdd(reinterpret_cast<unsigned long long*>(out ? out + u.g : &rs[u.g].E), (unsigned long long)t);
+    if (threadIdx.x == 0) part_out[ubase + blockIdx.x] = -(wpart[0] + wpart[1] + wpart[2] + wpart[3]);
+}
+
+// Energy of each replica from its units' partial sums, one wavefront per
+// replica: into rs[g].E, or into out[g] when out is given.
+__global__ __launch_bounds__(256) void k_energy_segs(const EnergySeg* __restrict__ segs, int64_t nsegs,
+                                                     const int64_t* __restrict__ part, RepState* __restrict__ rs,
+                                                     int64_t* __restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= nsegs) return;
+    const EnergySeg sg = segs[k];
+    // eight independent loads in flight per lane (a 10^6-spin replica has ~4000 units)
+    long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t* pp = part + sg.u0;
+    int u = lane;
+    for (; u + 7 * 64 < sg.nu; u += 8 * 64) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] += pp[u + j * 64];
+    }
+    for (; u < sg.nu; u += 64) a[0] += pp[u];
+    long long acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) {
+        if (out) out[sg.g] = acc;
+        else rs[sg.g].E = acc;
     }
 }
 
 hipError_t launch_start_units(const InstTab* tab, const StartUnit* start_units, int64_t n_start,
-                              const StartUnit* energy_units, int64_t n_energy, RepState* rs, int64_t* out,
-                              uint64_t seed, bool init, hipStream_t st)
+                              const StartUnit* energy_units, int64_t n_energy, const EnergySeg* segs, int64_t nsegs,
+                              int64_t* part, RepState* rs, int64_t* out, uint64_t seed, bool init, hipStream_t st)
 {
     if (init)
         for (int64_t b0 = 0; b0 < n_start; b0 += (1u << 30)) {
@@ -469,7 +495,12 @@ hipError_t launch_start_units(const InstTab* tab, const StartUnit* start_units, 
         }
     for (int64_t b0 = 0; b0 < n_energy; b0 += (1u << 30)) {
         const unsigned nb = (unsigned)std::min<int64_t>(n_energy - b0, 1u << 30);
-        hipLaunchKernelGGL(k_energy_units, dim3(nb), dim3(256), 0, st, tab, energy_units + b0, rs, out);
+        hipLaunchKernelGGL(k_energy_units, dim3(nb), dim3(256), 0, st, tab, energy_units + b0, b0, part);
+    }
+    for (int64_t k0 = 0; k0 < nsegs; k0 += (int64_t)4 << 30) {
+        const int64_t nk = std::min<int64_t>(nsegs - k0, (int64_t)4 << 30);
+        hipLaunchKernelGGL(k_energy_segs, dim3((unsigned)((nk + 3) / 4)), dim3(256), 0, st, segs + k0, nk, part, rs,
+                           out);
     }
     return hipGetLastError();
 }

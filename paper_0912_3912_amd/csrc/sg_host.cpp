@@ -134,7 +134,8 @@ struct sg_ctx {
     // batched start / energy of the replicas not started one lane each: units
     // of 1024 spins (start) and of four slices (energy)
     std::vector<sg::StartUnit> h_sunits, h_eunits;
-    uint64_t off_sunits = 0, off_eunits = 0;
+    std::vector<sg::EnergySeg> h_esegs;  // the energy units of each replica
+    uint64_t off_sunits = 0, off_eunits = 0, off_esegs = 0, off_eparts = 0;
     std::vector<sg::BlockItem> h_litems;       // lane-per-replica start items (instance, r0, count <= 64)
     int32_t lane_nmax = 1;
     uint64_t off_litems = 0;
@@ -696,18 +697,23 @@ void layout(sg_ctx* H)
     H->off_tbase = take((uint64_t)H->insts.size() * 4);
     H->h_sunits.clear();
     H->h_eunits.clear();
+    H->h_esegs.clear();
     for (size_t k = 0; k < H->insts.size(); ++k) {
         const HostInst& q = H->insts[k];
         if (q.dense || lane_start(q)) continue;
         for (int32_t r = 0; r < q.R; ++r) {
             const int64_t g = q.rep_base + r;
             for (int32_t i0 = 0; i0 < q.n; i0 += 1024) H->h_sunits.push_back(sg::StartUnit{g, (int32_t)k, i0});
+            const int64_t u0 = (int64_t)H->h_eunits.size();
             for (int32_t s0 = 0; s0 < (int32_t)q.slices.size(); s0 += 4)
                 H->h_eunits.push_back(sg::StartUnit{g, (int32_t)k, s0});
+            H->h_esegs.push_back(sg::EnergySeg{g, u0, (int32_t)((int64_t)H->h_eunits.size() - u0), 0});
         }
     }
     H->off_sunits = take(H->h_sunits.size() * sizeof(sg::StartUnit));
     H->off_eunits = take(H->h_eunits.size() * sizeof(sg::StartUnit));
+    H->off_esegs = take(H->h_esegs.size() * sizeof(sg::EnergySeg));
+    H->off_eparts = take(H->h_eunits.size() * 8);
     H->h_litems.clear();
     H->lane_nmax = 1;
     for (size_t k = 0; k < H->insts.size(); ++k) {
@@ -1586,10 +1592,14 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             SG_HIP(hipMemcpyAsync(H->dev + H->off_sunits, H->h_sunits.data(), H->h_sunits.size() * sizeof(sg::StartUnit),
                                   hipMemcpyHostToDevice, st),
                    "upload start units");
-        if (!H->h_eunits.empty())
+        if (!H->h_eunits.empty()) {
             SG_HIP(hipMemcpyAsync(H->dev + H->off_eunits, H->h_eunits.data(), H->h_eunits.size() * sizeof(sg::StartUnit),
                                   hipMemcpyHostToDevice, st),
                    "upload energy units");
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_esegs, H->h_esegs.data(), H->h_esegs.size() * sizeof(sg::EnergySeg),
+                                  hipMemcpyHostToDevice, st),
+                   "upload energy segments");
+        }
         if (!H->h_litems.empty())
             SG_HIP(hipMemcpyAsync(H->dev + H->off_litems, H->h_litems.data(), H->h_litems.size() * sizeof(sg::BlockItem),
                                   hipMemcpyHostToDevice, st),
@@ -1621,7 +1631,9 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
     if (!H->h_sunits.empty())
         SG_HIP(sg::launch_start_units(H->at<sg::InstTab>(H->off_tab), H->at<sg::StartUnit>(H->off_sunits),
                                       (int64_t)H->h_sunits.size(), H->at<sg::StartUnit>(H->off_eunits),
-                                      (int64_t)H->h_eunits.size(), H->reps(), nullptr, seed, true, st),
+                                      (int64_t)H->h_eunits.size(), H->at<sg::EnergySeg>(H->off_esegs),
+                                      (int64_t)H->h_esegs.size(), H->at<int64_t>(H->off_eparts), H->reps(), nullptr,
+                                      seed, true, st),
                "start kernels");
     if (!H->h_litems.empty()) {
         SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
@@ -1749,7 +1761,9 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
             SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(eout), (uint64_t)H->total_reps * 2, 0u, st),
                    "fill kernel");
             SG_HIP(sg::launch_start_units(H->at<sg::InstTab>(H->off_tab), nullptr, 0, H->at<sg::StartUnit>(H->off_eunits),
-                                          (int64_t)H->h_eunits.size(), H->reps(), eout, 0, false, st),
+                                          (int64_t)H->h_eunits.size(), H->at<sg::EnergySeg>(H->off_esegs),
+                                          (int64_t)H->h_esegs.size(), H->at<int64_t>(H->off_eparts), H->reps(), eout,
+                                          0, false, st),
                    "energy kernel");
         }
         if (!H->h_litems.empty())

@@ -73,11 +73,12 @@ int queue_max_blocks(size_t lds);
 hipError_t launch_start_lanes(const InstTab* tab, const BlockItem* items, int nitems, int nmax, bool init,
                               RepState* rs, int64_t* out, uint64_t seed, hipStream_t st);
 // Batched start (init: spins drawn by units of 1024 spins, state reset) and
-// energy (units of four slices, int64 atomics into rs[g].E or into out[g],
-// which must be zero).
+// energy (units of four slices, each summed into part[unit], n_energy
+// entries; then the units of each replica segment added into rs[g].E, or
+// into out[g] when out is given).
 hipError_t launch_start_units(const InstTab* tab, const StartUnit* start_units, int64_t n_start,
-                              const StartUnit* energy_units, int64_t n_energy, RepState* rs, int64_t* out,
-                              uint64_t seed, bool init, hipStream_t st);
+                              const StartUnit* energy_units, int64_t n_energy, const EnergySeg* segs, int64_t nsegs,
+                              int64_t* part, RepState* rs, int64_t* out, uint64_t seed, bool init, hipStream_t st);
 hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
                         uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
                         uint64_t seed, int rule, int until_conv, hipStream_t st);

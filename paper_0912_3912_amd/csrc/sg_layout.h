@@ -106,6 +106,13 @@ struct StartUnit {           // batched start / energy: a range of replica g
     int32_t off;             // first spin (start) or first slice (energy)
 };
 
+struct EnergySeg {           // batched energy: the units of replica g
+    int64_t g;               // replica (handle order)
+    int64_t u0;              // its first energy unit
+    int32_t nu;              // its number of energy units
+    int32_t pad;
+};
+
 struct QueueItem {           // k_queue: restart r of instance inst
     int32_t inst;
     int32_t r;
