@@ -554,28 +554,29 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
         }
         bits[w * 64 + lane] = word;
     }
-    auto spin = [&](int j) -> int { return ((bits[(j >> 5) * 64 + lane] >> (j & 31)) & 1u) ? -1 : 1; };
-    long long acc = 0;
-    for (int sl = 0; sl < I.nslices; ++sl) {
-        const Slice S = I.slices[sl];
-        for (int l = 0; l < S.rows; ++l) {
-            const int i = (int)S.row0 + l;
-            const int si = spin(i);
-            int e = I.h[i] * si;
-            for (int k = 0; k < S.ew; ++k) {
-                const uint32_t w = I.nbr[S.ebase + k * kSlice + l];
-                const int j = (int)(w >> 8);
-                if (j > i) e += bat_j(w) * si * spin(j);
-            }
-            if (I.has_tri) {
-                for (int k = 0; k < S.tw; ++k) {
-                    const uint32_t wa = I.ta[S.tbase + k * kSlice + l];
-                    const int a = (int)(wa >> 8), b = (int)I.tb[S.tbase + k * kSlice + l];
-                    if (a > i && b > i) e += bat_j(wa) * si * spin(a) * spin(b);
-                }
-            }
-            acc += e;
-        }
+    // -E as a sum over the instance's term list (the same for every lane):
+    // a product of spins is +1 or -1 by the parity of their set bits
+    auto bit = [&](uint32_t j) -> uint32_t { return (bits[(j >> 5) * 64 + lane] >> (j & 31u)) & 1u; };
+    auto coef = [](uint32_t w) -> int { return (int)(int8_t)(uint8_t)(w >> 22); };
+    const uint32_t* ET = Q.eterm;
+    int e2 = 0;  // |sum| < 2048 * 128 + 2048^2 / 2 * 128 < 2^31
+#pragma unroll 8
+    for (int t = 0; t < Q.n_eh; ++t) {
+        const uint32_t w = ET[t];
+        e2 += bit(w & 0x7FFu) ? -coef(w) : coef(w);
+    }
+    ET += Q.n_eh;
+#pragma unroll 8
+    for (int t = 0; t < Q.n_ee; ++t) {
+        const uint32_t w = ET[t];
+        e2 += (bit(w & 0x7FFu) ^ bit((w >> 11) & 0x7FFu)) ? -coef(w) : coef(w);
+    }
+    ET += Q.n_ee;
+    long long acc = e2;
+#pragma unroll 4
+    for (int t = 0; t < Q.n_et; ++t) {
+        const uint32_t w = ET[2 * t], b = ET[2 * t + 1];
+        acc += (bit(w & 0x7FFu) ^ bit((w >> 11) & 0x7FFu) ^ bit(b)) ? -coef(w) : coef(w);
     }
     if (mine) {
         const int64_t g = Q.rep_base + r;

@@ -74,6 +74,8 @@ struct HostInst {
     std::vector<sg::Slice> slices;
     std::vector<uint32_t> nbr, ta, tb;
     std::vector<int8_t> h;             // internal order
+    std::vector<uint32_t> eterm;       // energy terms (instances of at most 2048 spins)
+    int32_t n_eh = 0, n_ee = 0, n_et = 0;
     int32_t nslots = 1;                // phase-kernel blocks per colour (max over colours)
     int32_t acc_slots = 1;             // accumulator slots per replica (max over schedules)
     int64_t rep_base = 0;
@@ -90,7 +92,7 @@ struct HostInst {
     std::vector<uint64_t> lat_rec;     // per-site coupling record
     uint64_t off_lat_rec = 0, off_lat_g = 0, off_lat_flags = 0, lat_g_bytes = 0;
     // workspace offsets (bytes)
-    uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0;
+    uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0, off_eterm = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
     uint64_t off_fields = 0, field_stride = 0;  // maintained local fields (ints per replica), when enabled
     // dense hyper-Ising instance (sg_load_dense)
@@ -612,6 +614,29 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     q.nbr.assign((size_t)std::max<uint64_t>(ebase, 1), 0u);
     q.ta.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
     q.tb.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
+    // term list of small instances, for the energy of one replica per lane
+    q.eterm.clear();
+    q.n_eh = q.n_ee = q.n_et = 0;
+    if (n <= kLaneStartMaxN) {
+        for (int32_t i = 0; i < n; ++i)
+            if (q.h[i]) q.eterm.push_back((uint32_t)i | ((uint32_t)(uint8_t)q.h[i] << 22));
+        q.n_eh = (int32_t)q.eterm.size();
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t k = es[i]; k < es[i + 1]; ++k) {
+                const uint32_t j = ew[k] >> 8, Jb = ew[k] & 0xFFu;
+                if ((int32_t)j > i && Jb) q.eterm.push_back((uint32_t)i | (j << 11) | (Jb << 22));
+            }
+        q.n_ee = (int32_t)q.eterm.size() - q.n_eh;
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
+                const uint32_t a = twa[k] >> 8, Kb = twa[k] & 0xFFu, b = twb[k];
+                if ((int32_t)a > i && (int32_t)b > i && Kb) {
+                    q.eterm.push_back((uint32_t)i | (a << 11) | (Kb << 22));
+                    q.eterm.push_back(b);
+                    ++q.n_et;
+                }
+            }
+    }
     for (const sg::Slice& S : q.slices) {
         for (int32_t l = 0; l < S.rows; ++l) {
             const int32_t i = (int32_t)S.row0 + l;
@@ -652,6 +677,7 @@ void layout(sg_ctx* H)
         q.off_h = take((uint64_t)q.n);
         q.off_ext = take((uint64_t)q.n * 4);
         q.off_slices = take(q.slices.size() * sizeof(sg::Slice));
+        q.off_eterm = take(q.eterm.size() * 4);
         q.spin_stride = align_up((uint64_t)q.n);
         q.off_spins = take(q.spin_stride * (uint64_t)q.R);
         q.off_acc = take((uint64_t)q.R * q.acc_slots * 16);
@@ -1498,6 +1524,9 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
         SG_HIP(hipMemcpyAsync(H->dev + q.off_tb, q.tb.data(), q.tb.size() * 4, hipMemcpyHostToDevice, st),
                "upload triples");
         SG_HIP(hipMemcpyAsync(H->dev + q.off_h, q.h.data(), (size_t)q.n, hipMemcpyHostToDevice, st), "upload fields");
+        if (!q.eterm.empty())
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_eterm, q.eterm.data(), q.eterm.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload energy terms");
         SG_HIP(hipMemcpyAsync(H->dev + q.off_ext, q.ext_of.data(), (size_t)q.n * 4, hipMemcpyHostToDevice, st),
                "upload index map");
         SG_HIP(hipMemcpyAsync(H->dev + q.off_slices, q.slices.data(), q.slices.size() * sizeof(sg::Slice),
@@ -1573,6 +1602,11 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             T.ctab_off = (int32_t)ctab.size();
             T.nbr_words = (int32_t)q.nbr.size();
             T.tri_words = (int32_t)q.ta.size();
+            T.eterm = H->at<uint32_t>(q.off_eterm);
+            T.n_eh = q.n_eh;
+            T.n_ee = q.n_ee;
+            T.n_et = q.n_et;
+            T.eterm_pad = 0;
             for (int32_t c = 0; c <= q.C; ++c) ctab.push_back(q.colour_slice[c]);
         }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_tab, tab.data(), tab.size() * sizeof(sg::InstTab), hipMemcpyHostToDevice,

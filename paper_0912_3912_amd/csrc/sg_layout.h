@@ -91,6 +91,12 @@ struct InstTab {
     int32_t ctab_off;        // offset of the instance's C+1 colour slice starts in the colour table
     int32_t nbr_words;       // coupling words of the sliced layout
     int32_t tri_words;       // hyper-coupling words (each of ta, tb)
+    // energy terms of an instance of at most 2048 spins, each at its smallest
+    // internal index i: n_eh fields (i | h << 22), then n_ee couplings
+    // (i | j << 11 | J << 22), then n_et hyper-couplings as word pairs
+    // (i | a << 11 | K << 22, b); coefficients as 8-bit two's complement
+    const uint32_t* eterm;
+    int32_t n_eh, n_ee, n_et, eterm_pad;
 };
 
 struct BlockItem {           // k_block: restarts [r0, r0 + nr) of instance inst
