@@ -67,11 +67,17 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
     __shared__ int sw_flips[256];
     __shared__ int n_active;
 
-    for (int k = tid; k < ew; k += kBatThreads) l_nbr[k] = I.nbr[k];
+    // coupling words staged with the partner's spin offset (j * RG, < 2^19)
+    // in place of j: the lane's spin address is then one add
+    for (int k = tid; k < ew; k += kBatThreads) {
+        const uint32_t w = I.nbr[k];
+        l_nbr[k] = (((w >> 8) * (uint32_t)RG) << 8) | (w & 0xffu);
+    }
     if (I.has_tri)
         for (int k = tid; k < tw; k += kBatThreads) {
-            l_ta[k] = I.ta[k];
-            l_tb[k] = I.tb[k];
+            const uint32_t wa = I.ta[k];
+            l_ta[k] = (((wa >> 8) * (uint32_t)RG) << 8) | (wa & 0xffu);
+            l_tb[k] = I.tb[k] * (uint32_t)RG;
         }
     for (int k = tid; k < nsl; k += kBatThreads) l_sl[k] = I.slices[k];
     for (int k = tid; k < n; k += kBatThreads) l_h[k] = I.h[k];
@@ -107,17 +113,30 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
                     const int i = Sl.row0 + l;
                     int f = l_h[i];
                     const uint32_t* pw = l_nbr + Sl.ebase + l;
-                    for (int kk = 0; kk < Sl.ew; ++kk) {
+                    const int8_t* ls = l_s + r_loc;
+                    // four couplings at a time: their loads are issued together
+                    int kk = 0;
+                    for (; kk + 4 <= Sl.ew; kk += 4) {
+                        uint32_t w[4];
+                        int sj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) w[u] = pw[(kk + u) * kSlice];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) sj[u] = ls[w[u] >> 8];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) f += bat_j(w[u]) * sj[u];
+                    }
+                    for (; kk < Sl.ew; ++kk) {
                         const uint32_t w = pw[kk * kSlice];
-                        f += bat_j(w) * l_s[(w >> 8) * RG + r_loc];
+                        f += bat_j(w) * ls[w >> 8];
                     }
                     if (I.has_tri) {
                         const uint32_t* pa = l_ta + Sl.tbase + l;
                         const uint32_t* pb = l_tb + Sl.tbase + l;
-                        for (int kk = 0; kk < Sl.tw; ++kk) {
-                            const uint32_t wa = pa[kk * kSlice];
-                            const uint32_t b = pb[kk * kSlice];
-                            f += bat_j(wa) * l_s[(wa >> 8) * RG + r_loc] * l_s[b * RG + r_loc];
+                        for (int kk2 = 0; kk2 < Sl.tw; ++kk2) {
+                            const uint32_t wa = pa[kk2 * kSlice];
+                            const uint32_t b = pb[kk2 * kSlice];
+                            f += bat_j(wa) * ls[wa >> 8] * ls[b];
                         }
                     }
                     const int si = l_s[i * RG + r_loc];
