@@ -299,6 +299,10 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *   "lattice_wg_max_n"   largest lattice run with one workgroup per replica
  *   "block_rg"           restarts per workgroup of the block schedule
  *                        (64, 128, 256; 0 = 64, the fastest measured)
+ *   "block_groups"       restarts per workgroup of the block schedule in
+ *                        units of block_rg: its slots take the next restart
+ *                        as replicas stop (0 = up to 4, fewer when the
+ *                        workgroups would not fill the GPU; at most 64)
  *   "block_min_restarts" SG_SCHED_AUTO uses the block schedule for instances
  *                        with at least this many restarts (default 32)
  *   "queue_wave_max_n"   queue items with at most this many spins run one per

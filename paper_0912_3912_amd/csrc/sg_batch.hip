@@ -1,11 +1,14 @@
 // sg_batch.hip -- batched schedules: many instances and restarts of uneven
 // size in one launch, each replica run to its own stopping point.
 //
-// k_block (one workgroup per instance and group of restarts): the
-// instance's sliced couplings, its fields and the spins of up to 256
-// restarts sit in LDS.  Spins are stored [spin][restart], so the 64 lanes of
-// a wavefront are 64 restarts of one spin: coupling reads are uniform across
-// the wavefront (LDS broadcast) and spin reads are 64 consecutive bytes.
+// k_block (one workgroup per instance and range of restarts): the
+// instance's sliced couplings, its fields and the spins of RG (up to 256)
+// restarts sit in LDS.  Spins are stored [spin][slot], so the 64 lanes of a
+// wavefront are 64 restarts of one spin: coupling reads are uniform across
+// the wavefront (LDS broadcast) and spin reads are 64 consecutive bytes.  A
+// slot whose replica stops (converged, or its sweep budget spent) writes it
+// back and takes the next restart of the range, so lanes do not idle while
+// slower restarts of the same instance are still descending.
 //
 // k_queue (persistent): workgroups take (instance, restart) items from a
 // queue sorted by decreasing size.  Large items run on the whole workgroup
@@ -47,15 +50,15 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
     const InstDev& I = Q.I;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = I.n;
-    const int r0 = it.r0, nr = it.nr;  // restarts [r0, r0 + nr) of the instance
+    const int r_end = it.r0 + it.nr;   // restarts [r0, r0 + nr) of the instance, RG at a time
     const int G = RG / 64;             // replica groups of 64 lanes
     const int S = kBatWaves / G;       // spin subsets
     const int g = wave % G, ss = wave / G;
-    const int r_loc = g * 64 + lane;
-    const bool has_r = r_loc < nr;
-    const int r = r0 + r_loc;
+    const int r_loc = g * 64 + lane;   // the lane's replica slot
+    const bool owner = ss == 0;        // one thread per slot keeps its bookkeeping
 
-    // LDS layout: couplings | triple words a | triple words b | slices | h | colour table | spins [n][RG]
+    // LDS layout: couplings | triple words a | triple words b | slices | h | colour table | spins [n][RG] |
+    // per-slot state
     const int ew = Q.nbr_words, tw = Q.tri_words, nsl = I.nslices, C = Q.C;
     uint32_t* l_nbr = reinterpret_cast<uint32_t*>(lds64);
     uint32_t* l_ta = l_nbr + ew;
@@ -64,8 +67,19 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
     int8_t* l_h = reinterpret_cast<int8_t*>(l_sl + nsl);
     int32_t* l_cs = reinterpret_cast<int32_t*>(l_h + ((n + 3) & ~3));
     int8_t* l_s = reinterpret_cast<int8_t*>(l_cs + C + 1);
-    __shared__ int sw_flips[256];
-    __shared__ int n_active;
+    const size_t s_off = (size_t)(l_s - reinterpret_cast<int8_t*>(lds64));
+    long long* sl_dE = reinterpret_cast<long long*>(reinterpret_cast<int8_t*>(lds64) +
+                                                    ((s_off + (size_t)n * RG + 15) & ~(size_t)15));
+    int* sl_r = reinterpret_cast<int*>(sl_dE + RG);  // restart in the slot, -1 when none
+    int* sl_t = sl_r + RG;                           // its sweeps in this call
+    uint32_t* sl_base = reinterpret_cast<uint32_t*>(sl_t + RG);  // its sweep index at the start of the call
+    int* sl_last = reinterpret_cast<int*>(sl_base + RG);         // 1 + its last sweep that flipped
+    int* sl_nf = sl_last + RG;                                   // its flips in this call
+    int* sl_wb = sl_nf + RG;                                     // restart to write back from the slot, or -1
+    int* sl_ld = sl_wb + RG;                                     // restart to load into the slot, or -1
+    int* sw_flips = sl_ld + RG;                                  // flips of the current sweep
+    __shared__ int n_live, next_r;
+    __shared__ unsigned long long b_att, b_flips, b_smax, b_unconv;
 
     // coupling words staged with the partner's spin offset (j * RG, < 2^19)
     // in place of j: the lane's spin address is then one add
@@ -82,28 +96,78 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
     for (int k = tid; k < nsl; k += kBatThreads) l_sl[k] = I.slices[k];
     for (int k = tid; k < n; k += kBatThreads) l_h[k] = I.h[k];
     for (int k = tid; k <= C; k += kBatThreads) l_cs[k] = ctab[Q.ctab_off + k];
-    // spins: global [r][i] -> LDS [i][r]
-    for (int k = tid; k < n * RG; k += kBatThreads) {
-        const int rr = k / n, i = k - rr * n;
-        l_s[i * RG + rr] = rr < nr ? Q.spins[(int64_t)(r0 + rr) * Q.spin_stride + i] : (int8_t)1;
+    if (tid == 0) {
+        n_live = 0;
+        next_r = it.r0;
+        b_att = b_flips = b_smax = b_unconv = 0;
     }
-    // per-replica state held by the lanes of the first spin subset
-    bool active = false;
-    uint32_t base = 0;
-    if (has_r) {
-        active = !rs[Q.rep_base + r].converged;
-        base = (uint32_t)rs[Q.rep_base + r].sweeps;
-    }
-    if (tid == 0) n_active = 0;
-    if (tid < 256) sw_flips[tid] = 0;
-    __syncthreads();
-    if (ss == 0 && active) atomicAdd(&n_active, 1);
+    if (tid < RG) sw_flips[tid] = 0;
     __syncthreads();
 
-    long long dE = 0;
-    int nflip = 0, performed = 0, lastflip = 0;
-    bool frozen_before = has_r && !active;
-    for (int t = 0; t < T && n_active > 0; ++t) {
+    // A replica leaves its slot: state and call totals (slot owner only).
+    auto finalize = [&](int r, int t, int last, long long de, int nf) {
+        RepState* st = rs + Q.rep_base + r;
+        st->E += de;
+        st->flips += nf;
+        st->sweeps += t;
+        st->lastflip = last;
+        const bool conv = until_conv && last < t;
+        if (conv) st->converged = 1;
+        atomicAdd(&b_att, (unsigned long long)t * (unsigned long long)n);
+        atomicAdd(&b_flips, (unsigned long long)nf);
+        atomicMax(&b_smax, (unsigned long long)t);
+        if (until_conv && !conv) atomicAdd(&b_unconv, 1ull);
+    };
+    // The next restart of the item that is not frozen (a replica that had
+    // converged before the call keeps its state and is not counted), or -1.
+    auto advance = [&]() -> int {
+        for (;;) {
+            const int rn = atomicAdd(&next_r, 1);
+            if (rn >= r_end) return -1;
+            const RepState s0 = rs[Q.rep_base + rn];
+            if (s0.converged) continue;
+            if (T <= 0) {
+                finalize(rn, 0, 0, 0, 0);
+                continue;
+            }
+            sl_t[r_loc] = 0;
+            sl_base[r_loc] = (uint32_t)s0.sweeps;
+            sl_last[r_loc] = 0;
+            sl_dE[r_loc] = 0;
+            sl_nf[r_loc] = 0;
+            return rn;
+        }
+    };
+    // Spins of the slot's outgoing and incoming replicas, rows of this subset.
+    auto swap = [&]() {
+        const int wb = sl_wb[r_loc], ld = sl_ld[r_loc];
+        if (wb >= 0) {
+            int8_t* gp = Q.spins + (int64_t)wb * Q.spin_stride;
+            for (int i = ss; i < n; i += S) gp[i] = l_s[i * RG + r_loc];
+        }
+        if (ld >= 0) {
+            const int8_t* gp = Q.spins + (int64_t)ld * Q.spin_stride;
+            for (int i = ss; i < n; i += S) l_s[i * RG + r_loc] = gp[i];
+        }
+    };
+
+    if (owner) {
+        const int rn = advance();
+        sl_r[r_loc] = rn;
+        sl_wb[r_loc] = -1;
+        sl_ld[r_loc] = rn;
+        if (rn >= 0) atomicAdd(&n_live, 1);
+    }
+    __syncthreads();
+    swap();
+    __syncthreads();
+
+    while (n_live > 0) {
+        const int rr = sl_r[r_loc];
+        const bool active = rr >= 0;
+        const uint32_t r = active ? (uint32_t)rr : 0u;
+        const uint32_t sweep = sl_base[r_loc] + (uint32_t)sl_t[r_loc];
+        long long dE = 0;
         int my = 0;
         for (int c = 0; c < C; ++c) {
             const int s_lo = l_cs[c], s_hi = l_cs[c + 1];
@@ -142,8 +206,7 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
                     const int si = l_s[i * RG + r_loc];
                     const int d = 2 * si * f;
                     bool flip = d < 0;
-                    if (TIE && d == 0 && active)
-                        flip = rng_bit(seed, I.ext[i], base + t, I.instance_id, (uint32_t)r) != 0;
+                    if (TIE && d == 0 && active) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
                     if (flip && active) {
                         l_s[i * RG + r_loc] = (int8_t)(-si);
                         dE += d;
@@ -153,53 +216,40 @@ __global__ __launch_bounds__(kBatThreads) void k_block(const InstTab* __restrict
             }
             __syncthreads();
         }
-        // sweep totals per replica over the spin subsets
-        if (my) atomicAdd(&sw_flips[r_loc], my);
-        nflip += my;
+        // the sweep's totals per slot over the spin subsets
+        if (my) {
+            atomicAdd(&sw_flips[r_loc], my);
+            atomicAdd(&sl_nf[r_loc], my);
+        }
+        if (dE) atomicAdd(reinterpret_cast<unsigned long long*>(&sl_dE[r_loc]), (unsigned long long)dE);
         __syncthreads();
-        if (active) {
-            performed = t + 1;
-            const int tot = sw_flips[r_loc];
-            if (tot) lastflip = t + 1;
-            if (until_conv && tot == 0) {
-                active = false;
-                if (ss == 0) atomicSub(&n_active, 1);
+        if (owner) {
+            sl_wb[r_loc] = -1;
+            sl_ld[r_loc] = -1;
+            if (active) {
+                const int t = ++sl_t[r_loc];
+                const int tot = sw_flips[r_loc];
+                sw_flips[r_loc] = 0;
+                if (tot) sl_last[r_loc] = t;
+                if ((until_conv && tot == 0) || t >= T) {
+                    finalize(rr, t, sl_last[r_loc], sl_dE[r_loc], sl_nf[r_loc]);
+                    const int rn = advance();
+                    sl_r[r_loc] = rn;
+                    sl_wb[r_loc] = rr;
+                    sl_ld[r_loc] = rn;
+                    if (rn < 0) atomicSub(&n_live, 1);
+                }
             }
         }
         __syncthreads();
-        if (tid < 256) sw_flips[tid] = 0;
+        swap();
         __syncthreads();
     }
-    // fold dE and flips of the spin subsets into subset 0's lanes
-    __shared__ long long red_d[256];
-    __shared__ int red_f[256];
-    if (ss == 0 && tid < 256) {
-        red_d[r_loc] = 0;
-        red_f[r_loc] = 0;
-    }
-    __syncthreads();
-    if (dE) atomicAdd((unsigned long long*)&red_d[r_loc], (unsigned long long)dE);
-    if (nflip) atomicAdd(&red_f[r_loc], nflip);
-    __syncthreads();
-    // spins back: LDS [i][r] -> global [r][i]
-    for (int k = tid; k < n * nr; k += kBatThreads) {
-        const int rr = k / n, i = k - rr * n;
-        Q.spins[(int64_t)(r0 + rr) * Q.spin_stride + i] = l_s[i * RG + rr];
-    }
-    if (ss == 0 && has_r && !frozen_before) {
-        RepState* st = rs + Q.rep_base + r;
-        const long long de = red_d[r_loc];
-        const int nf = red_f[r_loc];
-        st->E += de;
-        st->flips += nf;
-        st->sweeps += performed;
-        st->lastflip = lastflip;
-        const bool conv = until_conv && lastflip < performed;
-        if (conv) st->converged = 1;
-        atomicAdd(&cs->attempts, (unsigned long long)performed * (unsigned long long)n);
-        atomicAdd(&cs->flips, (unsigned long long)nf);
-        atomicMax(&cs->sweeps_max, (unsigned long long)performed);
-        if (until_conv && !conv) atomicAdd(&cs->unconverged, 1ull);
+    if (tid == 0) {
+        if (b_att) atomicAdd(&cs->attempts, b_att);
+        if (b_flips) atomicAdd(&cs->flips, b_flips);
+        atomicMax(&cs->sweeps_max, b_smax);
+        if (b_unconv) atomicAdd(&cs->unconverged, b_unconv);
     }
 }
 
@@ -637,6 +687,8 @@ size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, 
     b += (size_t)((n + 3) & ~3);
     b += (size_t)(C + 1) * 4;
     b += (size_t)n * RG;
+    b = (b + 15) / 16 * 16;
+    b += (size_t)RG * 40;  // per-slot state
     return (b + 15) / 16 * 16;
 }
 
@@ -654,6 +706,20 @@ hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem
         hipLaunchKernelGGL(k_block<false>, dim3(n_items), dim3(kBatThreads), lds, st, tab, ctab, items, rs, cs, RG, T,
                            seed, until_conv);
     return hipGetLastError();
+}
+
+int block_max_blocks(size_t lds)
+{
+    const void* kern = (const void*)k_block<true>;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatThreads, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
 }
 
 int queue_max_blocks(size_t lds)

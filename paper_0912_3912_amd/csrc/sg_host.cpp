@@ -117,6 +117,7 @@ struct sg_ctx {
     int32_t lattice_wg_max_n = 150000; // largest lattice run as one workgroup per replica
     int32_t block_rg = 0;              // restarts per block workgroup (0 = largest that fits)
     int32_t block_min_restarts = 32;   // AUTO uses the block schedule from this many restarts
+    int32_t block_groups = 0;          // restart groups per block workgroup (0 = auto, up to 4)
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
@@ -1142,6 +1143,7 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
 
 constexpr size_t kLdsBudget = 160 * 1024 - 6 * 1024;  // dynamic LDS left beside the kernels' static arrays
 constexpr int32_t kQueueMaxN = 150000;                  // largest item of the queue schedule (spins in LDS)
+constexpr int32_t kBlockGroupsAuto = 4;                 // most restart groups per block workgroup (auto)
 
 // Restarts per block workgroup for instance q (0 if the block schedule cannot
 // hold it).  Default 64: smaller workgroups fit more per CU and keep one
@@ -1174,18 +1176,32 @@ sg_status run_block_schedule(sg_handle H, const sg_run_params* p, const std::vec
     for (int rg : rgs) {
         H->h_bitems.clear();
         size_t lds = 0;
+        int64_t groups = 0;
         for (int qi : which) {
             const HostInst& q = H->insts[qi];
             if (block_rg_for(H, q) != rg) continue;
-            for (int r0 = 0; r0 < q.R; r0 += rg) {
+            groups += (q.R + rg - 1) / rg;
+            lds = std::max(lds, sg::block_lds_bytes(q.n, (int)q.nbr.size(), (int)q.ta.size(), (int)q.slices.size(),
+                                                    q.C, rg));
+        }
+        // restarts per workgroup: up to block_groups slot-fulls, which its
+        // slots work through as replicas stop, while the workgroups still
+        // fill the GPU
+        int m = H->block_groups;
+        if (m <= 0) {
+            const int cap = std::max(1, sg::block_max_blocks(lds));
+            m = (int)std::max<int64_t>(1, std::min<int64_t>(kBlockGroupsAuto, groups / cap));
+        }
+        for (int qi : which) {
+            const HostInst& q = H->insts[qi];
+            if (block_rg_for(H, q) != rg) continue;
+            for (int r0 = 0; r0 < q.R; r0 += rg * m) {
                 sg::BlockItem it{};
                 it.inst = qi;
                 it.r0 = r0;
-                it.nr = std::min(rg, q.R - r0);
+                it.nr = std::min(rg * m, q.R - r0);
                 H->h_bitems.push_back(it);
             }
-            lds = std::max(lds, sg::block_lds_bytes(q.n, (int)q.nbr.size(), (int)q.ta.size(), (int)q.slices.size(),
-                                                    q.C, rg));
         }
         sg::BlockItem* dit = H->at<sg::BlockItem>(H->off_bitems) + item_off;
         SG_HIP(hipMemcpyAsync(dit, H->h_bitems.data(), H->h_bitems.size() * sizeof(sg::BlockItem),
@@ -1901,6 +1917,9 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "lattice_wg_max_n") {
         if (value < 0 || value > 150000) return fail(SG_EINVAL, "lattice_wg_max_n must be in [0,150000]");
         H->lattice_wg_max_n = (int32_t)value;
+    } else if (k == "block_groups") {
+        if (value < 0 || value > 64) return fail(SG_EINVAL, "block_groups must be in [0, 64]");
+        H->block_groups = (int32_t)value;
     } else if (k == "block_rg") {
         if (value != 0 && value != 64 && value != 128 && value != 256)
             return fail(SG_EINVAL, "block_rg must be 0, 64, 128 or 256");
@@ -1945,6 +1964,7 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "lattice_max_tiles") *value = H->lattice_max_tiles;
     else if (k == "lattice_wg_max_n") *value = H->lattice_wg_max_n;
     else if (k == "block_rg") *value = H->block_rg;
+    else if (k == "block_groups") *value = H->block_groups;
     else if (k == "block_min_restarts") *value = H->block_min_restarts;
     else if (k == "queue_wave_max_n") *value = H->queue_wave_max_n;
     else if (k == "queue_grid") *value = H->queue_grid;

@@ -66,6 +66,8 @@ size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, 
 hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem* items, int n_items, size_t lds,
                         RepState* rs, CallStats* cs, int RG, int T, uint64_t seed, int rule, int until_conv,
                         hipStream_t st);
+// Workgroups of the block kernel with this much LDS that fit the GPU at once.
+int block_max_blocks(size_t lds);
 int queue_max_blocks(size_t lds);
 // Start (init) or energy of many replicas of small instances, one lane per
 // replica; items (instance, first restart, count <= 64), instances of at most

@@ -53,6 +53,17 @@ def test_block_chimera_restart_groups(gpu, rg):
         assert rg == 256 and e.status == sg.SG_EINVAL, e
 
 
+@pytest.mark.parametrize("groups", [1, 2, 3, 64])
+def test_block_restart_refill(gpu, groups):
+    """Slots take the next restart of their workgroup's range as replicas
+    stop: ranges of 1, 2, 3 and 64 slot-fulls with ragged restart counts,
+    both rules, and resumed calls in which converged replicas are frozen
+    (skipped when a slot looks for its next restart)."""
+    insts = chimera_batch(3, 200, seed=groups) + [gen.lattice((8, 8), seed=2, restarts=150, instance_id=77)]
+    _run(insts, 3, GREEDY, 10000, True, SCHED_BLOCK, tune={"block_groups": groups}, expect_sched=SCHED_BLOCK)
+    _run(insts, 3, TIE, 0, True, SCHED_BLOCK, tune={"block_groups": groups}, runs=[4, 0, 30])
+
+
 @pytest.mark.parametrize("R", [1, 33, 64, 100, 200])
 def test_block_ragged_restart_counts(gpu, R):
     insts = chimera_batch(3, R, seed=R)
