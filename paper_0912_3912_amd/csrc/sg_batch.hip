@@ -601,25 +601,34 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
     const bool mine = lane < it.nr;
     const int r = it.r0 + (mine ? lane : 0);
     int8_t* sp = Q.spins + Q.spin_stride * r;
-    for (int w = 0; w < W; ++w) {
+    if (!INIT) {
+        // stored spins: 32 bytes per word in two 16-byte loads (a replica's
+        // spin row is padded past n to a multiple of 256 bytes); the sign bits
+        // of four bytes gather by one multiply (no carries reach bits 28-31)
+        auto signs4 = [](uint32_t x) -> uint32_t { return ((x & 0x80808080u) * 0x00204081u) >> 28; };
+        for (int w = 0; w < W; ++w) {
+            const uint4 a = *reinterpret_cast<const uint4*>(sp + w * 32);
+            const uint4 b = *reinterpret_cast<const uint4*>(sp + w * 32 + 16);
+            uint32_t word = signs4(a.x) | (signs4(a.y) << 4) | (signs4(a.z) << 8) | (signs4(a.w) << 12) |
+                            (signs4(b.x) << 16) | (signs4(b.y) << 20) | (signs4(b.z) << 24) | (signs4(b.w) << 28);
+            const int left = n - w * 32;
+            if (left < 32) word &= (1u << left) - 1u;
+            bits[w * 64 + lane] = word;
+        }
+    }
+    // a drawn start: spins by the start rule, stored as bytes four at a time
+    for (int w = 0; INIT && w < W; ++w) {
         uint32_t word = 0;
         for (int q = 0; q < 8; ++q) {
             const int i0 = w * 32 + 4 * q;
             if (i0 >= n) break;
-            uint32_t quad;
-            if (INIT) {
-                quad = 0;
-                for (int b = 0; b < 4 && i0 + b < n; ++b) {
-                    const int neg = rng_bit(seed, I.ext[i0 + b], 0xFFFFFFFFu, I.instance_id, (uint32_t)r);
-                    word |= (uint32_t)neg << (4 * q + b);
-                    quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
-                }
-                if (mine) *reinterpret_cast<uint32_t*>(sp + i0) = quad;
-            } else {
-                quad = *reinterpret_cast<const uint32_t*>(sp + i0);
-                for (int b = 0; b < 4 && i0 + b < n; ++b)
-                    word |= (uint32_t)(((quad >> (8 * b)) & 0x80u) != 0) << (4 * q + b);
+            uint32_t quad = 0;
+            for (int b = 0; b < 4 && i0 + b < n; ++b) {
+                const int neg = rng_bit(seed, I.ext[i0 + b], 0xFFFFFFFFu, I.instance_id, (uint32_t)r);
+                word |= (uint32_t)neg << (4 * q + b);
+                quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
             }
+            if (mine) *reinterpret_cast<uint32_t*>(sp + i0) = quad;
         }
         bits[w * 64 + lane] = word;
     }

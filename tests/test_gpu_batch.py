@@ -64,6 +64,34 @@ def test_block_restart_refill(gpu, groups):
     _run(insts, 3, TIE, 0, True, SCHED_BLOCK, tune={"block_groups": groups}, runs=[4, 0, 30])
 
 
+@pytest.mark.parametrize("ng", [2, 4, 8, 16])
+def test_block_bits_groups(gpu, ng):
+    """The bit-sliced GREEDY block kernel with at most 2, 4, 8 and 16 groups
+    of 32 restarts per workgroup (instances of 150 to 530 restarts, so several
+    group counts in one call): ragged restart counts (partial groups), refill
+    of finished groups, a fixed sweep budget, and resumed calls with frozen
+    restarts (the 0-sweep call runs on the byte kernel)."""
+    insts = chimera_batch(3, 200, seed=ng) + [gen.lattice((8, 8), seed=2, restarts=150, instance_id=77),
+                                              gen.chimera(4, 4, seed=9, restarts=530, instance_id=78)]
+    h, _ = _run(insts, 3, GREEDY, 10000, True, SCHED_BLOCK, tune={"bits_groups": ng}, expect_sched=SCHED_BLOCK)
+    assert h.query("last_bits") == 1
+    _run(insts, 5, GREEDY, 0, True, SCHED_BLOCK, tune={"bits_groups": ng, "block_groups": 1}, runs=[2, 0, 3, 40])
+    _run(insts, 6, GREEDY, 7, False, SCHED_BLOCK, tune={"bits_groups": ng})
+
+
+def test_block_bits_off_and_mixed(gpu):
+    """block_bits = 0 keeps GREEDY on the byte kernel; an instance with a
+    coupling above 15 in magnitude runs on the byte kernel beside bit-sliced
+    ones in the same call."""
+    big = gen.random_small(60, seed=5, p_edge=0.2, n_triples=10, j_range=(-40, 40), h_range=(-7, 7),
+                           k_range=(-7, 7), instance_id=5, restarts=64)
+    insts = chimera_batch(2, 96) + [big]
+    h, _ = _run(insts, 4, GREEDY, 10000, True, SCHED_BLOCK, tune={"block_bits": 0})
+    assert h.query("last_bits") == 0
+    h, _ = _run(insts, 4, GREEDY, 10000, True, SCHED_BLOCK)
+    assert h.query("last_bits") == 1
+
+
 @pytest.mark.parametrize("R", [1, 33, 64, 100, 200])
 def test_block_ragged_restart_counts(gpu, R):
     insts = chimera_batch(3, R, seed=R)
