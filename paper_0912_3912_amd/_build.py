@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsg.so")
 
-SOURCES = ["sg_host.cpp", "sg_bnb.cpp", "sg_kernels.hip", "sg_lattice.hip", "sg_batch.hip", "sg_msc.hip", "sg_fm.hip", "sg_dense.hip", "sg_bits.hip"]
+SOURCES = ["sg_host.cpp", "sg_bnb.cpp", "sg_kernels.hip", "sg_lattice.hip", "sg_batch.hip", "sg_queue.hip", "sg_msc.hip", "sg_fm.hip", "sg_dense.hip", "sg_bits.hip"]
 HEADERS = ["sg_layout.h", "sg_launch.h", "sg_device.h"]
 
 # Packed-FP32 instructions are disabled for all device code (the path is

@@ -1,0 +1,255 @@
+// sg_queue.hip -- the persistent queue schedule for many instances of uneven
+// size: workgroups take (instance, restart) items from a queue sorted by
+// decreasing size.  Large items run on the whole workgroup (rows of the
+// sliced layout on lanes, couplings streamed from memory, spins in LDS);
+// small items run one per wavefront in a private LDS window, 16 at a time.
+// Each replica runs to its own stopping point, and the replica state and the
+// call totals follow the per-phase kernels exactly: with until_converged a
+// replica stops after its first sweep without a flip (that sweep counts).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "sg_device.h"
+#include "sg_launch.h"
+#include "sg_layout.h"
+
+namespace sg {
+
+__device__ __forceinline__ int bat_j(uint32_t w) { return (int)(int8_t)(w & 0xffu); }
+
+constexpr int kBatThreads = 1024;
+constexpr int kBatWaves = kBatThreads / 64;
+
+// ---------------------------------------------------------------------------
+// k_queue
+
+// One colour phase of one replica on `nw` wavefronts (wave index w among
+// them): lane = row of a slice, couplings from memory, spins in LDS.
+template <bool TIE>
+__device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __restrict__ slices, int s_lo, int s_hi,
+                                            int8_t* __restrict__ sp, int w, int nw, int lane, uint32_t sweep,
+                                            uint64_t seed, uint32_t r, long long& dE, int& my)
+{
+    for (int sl = s_lo + w; sl < s_hi; sl += nw) {
+        const Slice S = slices[sl];
+        if (lane < S.rows) {
+            const int i = S.row0 + lane;
+            int f = I.h[i];
+            const uint32_t* p = I.nbr + S.ebase + lane;
+            int k = 0;
+            for (; k + 4 <= S.ew; k += 4) {
+                const uint32_t w0 = p[(k + 0) * kSlice], w1 = p[(k + 1) * kSlice];
+                const uint32_t w2 = p[(k + 2) * kSlice], w3 = p[(k + 3) * kSlice];
+                f += bat_j(w0) * sp[w0 >> 8] + bat_j(w1) * sp[w1 >> 8] + bat_j(w2) * sp[w2 >> 8] +
+                     bat_j(w3) * sp[w3 >> 8];
+            }
+            for (; k < S.ew; ++k) {
+                const uint32_t w1 = p[k * kSlice];
+                f += bat_j(w1) * sp[w1 >> 8];
+            }
+            if (I.has_tri) {
+                const uint32_t* pa = I.ta + S.tbase + lane;
+                const uint32_t* pb = I.tb + S.tbase + lane;
+                for (int q = 0; q < S.tw; ++q) {
+                    const uint32_t wa = pa[q * kSlice];
+                    f += bat_j(wa) * sp[wa >> 8] * sp[pb[q * kSlice]];
+                }
+            }
+            const int si = sp[i];
+            const int d = 2 * si * f;
+            bool flip = d < 0;
+            if (TIE && d == 0) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
+            if (flip) {
+                sp[i] = (int8_t)(-si);
+                dE += d;
+                ++my;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void queue_finish(const InstTab& Q, int r, long long dE, int nflip, int performed,
+                                             int lastflip, int T, int until_conv, RepState* __restrict__ rs,
+                                             CallStats* __restrict__ cs)
+{
+    RepState* st = rs + Q.rep_base + r;
+    st->E += dE;
+    st->flips += nflip;
+    st->sweeps += performed;
+    st->lastflip = lastflip;
+    const bool conv = until_conv && lastflip < performed;
+    if (conv) st->converged = 1;
+    atomicAdd(&cs->attempts, (unsigned long long)performed * (unsigned long long)Q.I.n);
+    atomicAdd(&cs->flips, (unsigned long long)nflip);
+    atomicMax(&cs->sweeps_max, (unsigned long long)performed);
+    if (until_conv && !conv) atomicAdd(&cs->unconverged, 1ull);
+}
+
+template <bool TIE>
+__global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict__ tab, const int32_t* __restrict__ ctab,
+                                                       const QueueItem* __restrict__ items, int n_big, int n_items,
+                                                       uint32_t* __restrict__ counters, int wave_lds,
+                                                       RepState* __restrict__ rs, CallStats* __restrict__ cs, int T,
+                                                       uint64_t seed, int until_conv)
+{
+    extern __shared__ uint64_t lds64[];
+    int8_t* lds = reinterpret_cast<int8_t*>(lds64);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ int s_item;
+    __shared__ int s_flips;
+    // ---- large items: the whole workgroup on one replica
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        const int q = s_item;
+        __syncthreads();
+        if (q >= n_big) break;
+        const QueueItem it = items[q];
+        const InstTab& Q = tab[it.inst];
+        const InstDev& I = Q.I;
+        int8_t* gsp = Q.spins + (int64_t)it.r * Q.spin_stride;
+        const RepState* st0 = rs + Q.rep_base + it.r;
+        const bool frozen = st0->converged != 0;
+        if (frozen) continue;
+        const uint32_t base = (uint32_t)st0->sweeps;
+        for (int k = tid; k < I.n; k += kBatThreads) lds[k] = gsp[k];
+        if (tid == 0) s_flips = 0;
+        __syncthreads();
+        long long dE = 0;
+        int nflip = 0, performed = 0, lastflip = 0;
+        for (int t = 0; t < T; ++t) {
+            int my = 0;
+            for (int c = 0; c < Q.C; ++c) {
+                queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], lds, wave, kBatWaves,
+                                 lane, base + t, seed, (uint32_t)it.r, dE, my);
+                __syncthreads();
+            }
+            nflip += my;
+            performed = t + 1;
+            int wsum = my;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+            if (lane == 0 && wsum) atomicAdd(&s_flips, wsum);
+            __syncthreads();
+            const int tot = s_flips;
+            __syncthreads();
+            if (tid == 0) s_flips = 0;
+            if (tot) lastflip = t + 1;
+            if (until_conv && tot == 0) break;
+        }
+        for (int k = tid; k < I.n; k += kBatThreads) gsp[k] = lds[k];
+        // fold the workgroup's dE and flips
+        long long wd = dE;
+        int wf = nflip;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            wd += __shfl_xor(wd, off, 64);
+            wf += __shfl_xor(wf, off, 64);
+        }
+        __shared__ long long pd[kBatWaves];
+        __shared__ int pf[kBatWaves];
+        if (lane == 0) {
+            pd[wave] = wd;
+            pf[wave] = wf;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            long long a = 0;
+            int b = 0;
+            for (int w = 0; w < kBatWaves; ++w) {
+                a += pd[w];
+                b += pf[w];
+            }
+            queue_finish(Q, it.r, a, b, performed, lastflip, T, until_conv, rs, cs);
+        }
+        __syncthreads();
+    }
+    // ---- small items: one wavefront per replica, 16 at a time
+    int8_t* wl = lds + wave * wave_lds;
+    for (;;) {
+        if (tid == 0) s_item = n_big + (int)atomicAdd(&counters[1], (unsigned)kBatWaves);
+        __syncthreads();
+        const int q0 = s_item;
+        __syncthreads();
+        if (q0 >= n_items) break;
+        const int q = q0 + wave;
+        if (q < n_items) {
+            const QueueItem it = items[q];
+            const InstTab& Q = tab[it.inst];
+            const InstDev& I = Q.I;
+            int8_t* gsp = Q.spins + (int64_t)it.r * Q.spin_stride;
+            const RepState* st0 = rs + Q.rep_base + it.r;
+            if (!st0->converged) {
+                const uint32_t base = (uint32_t)st0->sweeps;
+                for (int k = lane; k < I.n; k += 64) wl[k] = gsp[k];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                long long dE = 0;
+                int nflip = 0, performed = 0, lastflip = 0;
+                for (int t = 0; t < T; ++t) {
+                    int my = 0;
+                    for (int c = 0; c < Q.C; ++c) {
+                        queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], wl, 0, 1, lane,
+                                         base + t, seed, (uint32_t)it.r, dE, my);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    nflip += my;
+                    performed = t + 1;
+                    int tot = my;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+                    if (tot) lastflip = t + 1;
+                    if (until_conv && tot == 0) break;
+                }
+                for (int k = lane; k < I.n; k += 64) gsp[k] = wl[k];
+                long long wd = dE;
+                int wf = nflip;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    wd += __shfl_xor(wd, off, 64);
+                    wf += __shfl_xor(wf, off, 64);
+                }
+                if (lane == 0) queue_finish(Q, it.r, wd, wf, performed, lastflip, T, until_conv, rs, cs);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+
+int queue_max_blocks(size_t lds)
+{
+    const void* kern = (const void*)k_queue<true>;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatThreads, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+hipError_t launch_queue(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int n_big, int n_items,
+                        uint32_t* counters, int wave_lds, size_t lds, int grid, RepState* rs, CallStats* cs, int T,
+                        uint64_t seed, int rule, int until_conv, hipStream_t st)
+{
+    const void* kern = rule == 1 ? (const void*)k_queue<true> : (const void*)k_queue<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (rule == 1)
+        hipLaunchKernelGGL(k_queue<true>, dim3(grid), dim3(kBatThreads), lds, st, tab, ctab, items, n_big, n_items,
+                           counters, wave_lds, rs, cs, T, seed, until_conv);
+    else
+        hipLaunchKernelGGL(k_queue<false>, dim3(grid), dim3(kBatThreads), lds, st, tab, ctab, items, n_big, n_items,
+                           counters, wave_lds, rs, cs, T, seed, until_conv);
+    return hipGetLastError();
+}
+
+}  // namespace sg
