@@ -293,10 +293,20 @@ __global__ __launch_bounds__(256) void k_energy_units(const InstTab* __restrict_
             const int si = s[i];
             int e = I.h[i] * si;
             const uint32_t* p = I.nbr + S.ebase + lane;
-            for (int k = 0; k < S.ew; ++k) {
-                const uint32_t w = p[k * kSlice];
-                const int j = (int)(w >> 8);
-                if (j > i) e += bat_j(w) * si * s[j];
+            // up to 16 coupling words, then their partners' spins, in flight together
+            constexpr int kPre = 16;
+            uint32_t w[kPre];
+            int sj[kPre];
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) w[k] = k < S.ew ? p[k * kSlice] : 0u;
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) sj[k] = (k < S.ew && (int)(w[k] >> 8) > i) ? s[w[k] >> 8] : 0;
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) e += bat_j(w[k]) * si * sj[k];
+            for (int k = kPre; k < S.ew; ++k) {
+                const uint32_t w1 = p[k * kSlice];
+                const int j = (int)(w1 >> 8);
+                if (j > i) e += bat_j(w1) * si * s[j];
             }
             if (I.has_tri) {
                 const uint32_t* pa = I.ta + S.tbase + lane;

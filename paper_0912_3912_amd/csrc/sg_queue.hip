@@ -26,7 +26,81 @@ constexpr int kBatWaves = kBatThreads / 64;
 // k_queue
 
 // One colour phase of one replica on `nw` wavefronts (wave index w among
-// them): lane = row of a slice, couplings from memory, spins in LDS.
+// them): lane = row of a slice, couplings from memory, spins in LDS.  All
+// coupling and hyper-coupling words of a slice (up to kPreW and kPreT of
+// them, predicated on the slice's widths) are loaded before any is used, so a
+// wavefront keeps a whole slice's loads in flight (measured on 2000 uneven
+// instances: 3.26 ms, against 4.67 ms with four loads at a time and 3.78 ms
+// when loading the next slice while evaluating the current one with fewer
+// words each).
+constexpr int kPreW = 16, kPreT = 8;
+
+struct SliceWords {
+    uint32_t w[kPreW];
+    uint32_t a[kPreT], b[kPreT];
+    int h;
+};
+
+__device__ __forceinline__ void queue_load(const InstDev& I, const Slice& S, int lane, SliceWords& L)
+{
+    const bool row = lane < S.rows;
+    const uint32_t* p = I.nbr + S.ebase + lane;
+#pragma unroll
+    for (int k = 0; k < kPreW; ++k) L.w[k] = (row && k < S.ew) ? p[k * kSlice] : 0u;
+    if (I.has_tri) {
+        const uint32_t* pa = I.ta + S.tbase + lane;
+        const uint32_t* pb = I.tb + S.tbase + lane;
+#pragma unroll
+        for (int q = 0; q < kPreT; ++q) {
+            L.a[q] = (row && q < S.tw) ? pa[q * kSlice] : 0u;
+            L.b[q] = (row && q < S.tw) ? pb[q * kSlice] : 0u;
+        }
+    }
+    L.h = row ? (int)I.h[S.row0 + lane] : 0;
+}
+
+template <bool TIE>
+__device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, const SliceWords& L,
+                                           int8_t* __restrict__ sp, int lane, uint32_t sweep, uint64_t seed,
+                                           uint32_t r, long long& dE, int& my)
+{
+    if (lane >= S.rows) return;
+    const int i = S.row0 + lane;
+    int f = L.h;
+#pragma unroll
+    for (int k = 0; k < kPreW; ++k)
+        if (k < S.ew) f += bat_j(L.w[k]) * sp[L.w[k] >> 8];
+    if (S.ew > kPreW) {
+        const uint32_t* p = I.nbr + S.ebase + lane;
+        for (int k = kPreW; k < S.ew; ++k) {
+            const uint32_t w1 = p[k * kSlice];
+            f += bat_j(w1) * sp[w1 >> 8];
+        }
+    }
+    if (I.has_tri) {
+#pragma unroll
+        for (int q = 0; q < kPreT; ++q)
+            if (q < S.tw) f += bat_j(L.a[q]) * sp[L.a[q] >> 8] * sp[L.b[q]];
+        if (S.tw > kPreT) {
+            const uint32_t* pa = I.ta + S.tbase + lane;
+            const uint32_t* pb = I.tb + S.tbase + lane;
+            for (int q = kPreT; q < S.tw; ++q) {
+                const uint32_t wa = pa[q * kSlice];
+                f += bat_j(wa) * sp[wa >> 8] * sp[pb[q * kSlice]];
+            }
+        }
+    }
+    const int si = sp[i];
+    const int d = 2 * si * f;
+    bool flip = d < 0;
+    if (TIE && d == 0) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
+    if (flip) {
+        sp[i] = (int8_t)(-si);
+        dE += d;
+        ++my;
+    }
+}
+
 template <bool TIE>
 __device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __restrict__ slices, int s_lo, int s_hi,
                                             int8_t* __restrict__ sp, int w, int nw, int lane, uint32_t sweep,
@@ -34,39 +108,9 @@ __device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __res
 {
     for (int sl = s_lo + w; sl < s_hi; sl += nw) {
         const Slice S = slices[sl];
-        if (lane < S.rows) {
-            const int i = S.row0 + lane;
-            int f = I.h[i];
-            const uint32_t* p = I.nbr + S.ebase + lane;
-            int k = 0;
-            for (; k + 4 <= S.ew; k += 4) {
-                const uint32_t w0 = p[(k + 0) * kSlice], w1 = p[(k + 1) * kSlice];
-                const uint32_t w2 = p[(k + 2) * kSlice], w3 = p[(k + 3) * kSlice];
-                f += bat_j(w0) * sp[w0 >> 8] + bat_j(w1) * sp[w1 >> 8] + bat_j(w2) * sp[w2 >> 8] +
-                     bat_j(w3) * sp[w3 >> 8];
-            }
-            for (; k < S.ew; ++k) {
-                const uint32_t w1 = p[k * kSlice];
-                f += bat_j(w1) * sp[w1 >> 8];
-            }
-            if (I.has_tri) {
-                const uint32_t* pa = I.ta + S.tbase + lane;
-                const uint32_t* pb = I.tb + S.tbase + lane;
-                for (int q = 0; q < S.tw; ++q) {
-                    const uint32_t wa = pa[q * kSlice];
-                    f += bat_j(wa) * sp[wa >> 8] * sp[pb[q * kSlice]];
-                }
-            }
-            const int si = sp[i];
-            const int d = 2 * si * f;
-            bool flip = d < 0;
-            if (TIE && d == 0) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
-            if (flip) {
-                sp[i] = (int8_t)(-si);
-                dE += d;
-                ++my;
-            }
-        }
+        SliceWords cur;
+        queue_load(I, S, lane, cur);
+        queue_eval<TIE>(I, S, cur, sp, lane, sweep, seed, r, dE, my);
     }
 }
 
