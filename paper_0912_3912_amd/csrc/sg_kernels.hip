@@ -139,16 +139,19 @@ __device__ __forceinline__ int local_field(const InstDev& I, const Slice& S, int
     int f = I.h[i];
     const uint32_t* p = I.nbr + S.ebase + lane;
     const int ew = S.ew;
-    int k = 0;
-    for (; k + 4 <= ew; k += 4) {
-        const uint32_t w0 = p[(k + 0) * kSlice], w1 = p[(k + 1) * kSlice];
-        const uint32_t w2 = p[(k + 2) * kSlice], w3 = p[(k + 3) * kSlice];
-        f += coupling_j(w0) * s[w0 >> 8] + coupling_j(w1) * s[w1 >> 8] +
-             coupling_j(w2) * s[w2 >> 8] + coupling_j(w3) * s[w3 >> 8];
-    }
-    for (; k < ew; ++k) {
-        const uint32_t w = p[k * kSlice];
-        f += coupling_j(w) * s[w >> 8];
+    // up to 16 coupling words, then their partners' spins, in flight together
+    constexpr int kPre = 16;
+    uint32_t w[kPre];
+    int sj[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) w[k] = k < ew ? p[k * kSlice] : 0u;
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) sj[k] = k < ew ? s[w[k] >> 8] : 0;
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) f += coupling_j(w[k]) * sj[k];
+    for (int k = kPre; k < ew; ++k) {
+        const uint32_t w1 = p[k * kSlice];
+        f += coupling_j(w1) * s[w1 >> 8];
     }
     if (TRI) {
         const uint32_t* pa = I.ta + S.tbase + lane;
