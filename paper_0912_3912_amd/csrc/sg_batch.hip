@@ -393,17 +393,26 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
 {
     extern __shared__ uint32_t lbits[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + wave;
+    // wave-uniform item: its fields are read once into scalar registers (the
+    // spin stores below could otherwise alias them and force reloads)
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave);
     if (item >= nitems) return;
     const BlockItem it = items[item];
     const InstTab& Q = tab[it.inst];
-    const InstDev& I = Q.I;
-    const int n = I.n;
+    const int n = Q.I.n;
+    // external indices through the constant address space: wave-uniform reads of
+    // memory no kernel writes become scalar loads
+    using cu32 = const __attribute__((address_space(4))) uint32_t;
+    cu32* ext = (cu32*)Q.I.ext;
+    const uint32_t iid = Q.I.instance_id;
+    const int64_t stride = Q.spin_stride, rep_base = Q.rep_base;
+    const uint32_t* __restrict__ ET = Q.eterm;
+    const int n_eh = Q.n_eh, n_ee = Q.n_ee, n_et = Q.n_et;
     const int W = (n + 31) >> 5;
     uint32_t* bits = lbits + (size_t)wave * wmax * 64;
     const bool mine = lane < it.nr;
     const int r = it.r0 + (mine ? lane : 0);
-    int8_t* sp = Q.spins + Q.spin_stride * r;
+    int8_t* sp = Q.spins + stride * r;
     if (!INIT) {
         // stored spins: 32 bytes per word in two 16-byte loads (a replica's
         // spin row is padded past n to a multiple of 256 bytes); the sign bits
@@ -426,10 +435,23 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
             const int i0 = w * 32 + 4 * q;
             if (i0 >= n) break;
             uint32_t quad = 0;
-            for (int b = 0; b < 4 && i0 + b < n; ++b) {
-                const int neg = rng_bit(seed, I.ext[i0 + b], 0xFFFFFFFFu, I.instance_id, (uint32_t)r);
-                word |= (uint32_t)neg << (4 * q + b);
-                quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
+            if (i0 + 4 <= n) {
+                // four counters read together, then four independent draws
+                uint32_t e[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) e[b] = ext[i0 + b];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int neg = rng_bit(seed, e[b], 0xFFFFFFFFu, iid, (uint32_t)r);
+                    word |= (uint32_t)neg << (4 * q + b);
+                    quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
+                }
+            } else {
+                for (int b = 0; i0 + b < n; ++b) {
+                    const int neg = rng_bit(seed, ext[i0 + b], 0xFFFFFFFFu, iid, (uint32_t)r);
+                    word |= (uint32_t)neg << (4 * q + b);
+                    quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
+                }
             }
             if (mine) *reinterpret_cast<uint32_t*>(sp + i0) = quad;
         }
@@ -439,28 +461,28 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
     // a product of spins is +1 or -1 by the parity of their set bits
     auto bit = [&](uint32_t j) -> uint32_t { return (bits[(j >> 5) * 64 + lane] >> (j & 31u)) & 1u; };
     auto coef = [](uint32_t w) -> int { return (int)(int8_t)(uint8_t)(w >> 22); };
-    const uint32_t* ET = Q.eterm;
     int e2 = 0;  // |sum| < 2048 * 128 + 2048^2 / 2 * 128 < 2^31
+    const uint32_t* et = ET;
 #pragma unroll 8
-    for (int t = 0; t < Q.n_eh; ++t) {
-        const uint32_t w = ET[t];
+    for (int t = 0; t < n_eh; ++t) {
+        const uint32_t w = et[t];
         e2 += bit(w & 0x7FFu) ? -coef(w) : coef(w);
     }
-    ET += Q.n_eh;
+    et += n_eh;
 #pragma unroll 8
-    for (int t = 0; t < Q.n_ee; ++t) {
-        const uint32_t w = ET[t];
+    for (int t = 0; t < n_ee; ++t) {
+        const uint32_t w = et[t];
         e2 += (bit(w & 0x7FFu) ^ bit((w >> 11) & 0x7FFu)) ? -coef(w) : coef(w);
     }
-    ET += Q.n_ee;
+    et += n_ee;
     long long acc = e2;
 #pragma unroll 4
-    for (int t = 0; t < Q.n_et; ++t) {
-        const uint32_t w = ET[2 * t], b = ET[2 * t + 1];
+    for (int t = 0; t < n_et; ++t) {
+        const uint32_t w = et[2 * t], b = et[2 * t + 1];
         acc += (bit(w & 0x7FFu) ^ bit((w >> 11) & 0x7FFu) ^ bit(b)) ? -coef(w) : coef(w);
     }
     if (mine) {
-        const int64_t g = Q.rep_base + r;
+        const int64_t g = rep_base + r;
         if (INIT) {
             RepState z;
             z.E = -acc; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
