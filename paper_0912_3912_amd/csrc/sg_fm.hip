@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "sg_device.h"
+#include <type_traits>
 #include "sg_launch.h"
 #include "sg_layout.h"
 
@@ -128,10 +129,12 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
         IS.tb = tb;
     }
     __syncthreads();
-    if (wave < waves_per_block && item < nitems) {
-        const QueueItem it = items[item];
-        const InstTab& Q = tab[it.inst];
-        const InstDev& I = staged ? IS : Q.I;
+    // The item body is instantiated once for the staged instance and once
+    // for one read from global memory, so that in the first every slice and
+    // coupling read is known to be an LDS access (a pointer that may be
+    // either compiles to slower generic loads).
+    auto body = [&](auto staged_tag, const InstDev I, const QueueItem it, const InstTab& Q) {
+        (void)staged_tag;
         const int n = I.n;
         RepState* st = rs + Q.rep_base + it.r;
         if (!st->converged) {
@@ -299,6 +302,14 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
             passes_done = passes;
             unconv = (until_conv && !conv) ? 1 : 0;
         }
+    };
+    if (wave < waves_per_block && item < nitems) {
+        const QueueItem it = items[item];
+        const InstTab& Q = tab[it.inst];
+        if (staged)
+            body(std::true_type{}, IS, it, Q);
+        else
+            body(std::false_type{}, Q.I, it, Q);
     }
     // call totals: one atomic per block
     __shared__ long long b_att, b_kept, b_passes;
