@@ -303,6 +303,16 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        units of block_rg: its slots take the next restart
  *                        as replicas stop (0 = up to 4, fewer when the
  *                        workgroups would not fill the GPU; at most 64)
+ *   "block_bits"         1: GREEDY on the block schedule uses the bit-sliced
+ *                        kernel (32 restarts per word) for instances of at
+ *                        most 2048 spins whose coefficients are at most 15
+ *                        in magnitude and sum to at most 255 per spin; 0:
+ *                        always the byte kernel (default 1)
+ *   "bits_groups"        most groups of 32 restarts per bit-sliced workgroup
+ *                        (2, 4, 8, 16; default 8)
+ *   "fm_key32"           1: SG_RULE_FM picks moves on 32-bit keys when every
+ *                        gain is below 2^19 in magnitude; 0: 64-bit keys
+ *                        (default 1)
  *   "block_min_restarts" SG_SCHED_AUTO uses the block schedule for instances
  *                        with at least this many restarts (default 32)
  *   "queue_wave_max_n"   queue items with at most this many spins run one per
@@ -329,7 +339,9 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 
 /* Read a knob, or one of "last_tiles" (Px*10^6 + Py*10^3 + Pz of the last
  * lattice tile launch), "last_tile_k", "last_msc" (1 when that launch used
- * the bit-plane kernel), "last_queue_grid", "total_replicas",
+ * the bit-plane kernel), "last_bits" (1 when the last block-schedule call
+ * used the bit-sliced kernel), "last_key32" (1 when the last SG_RULE_FM call
+ * picked moves on 32-bit keys), "last_queue_grid", "total_replicas",
  * "instances", "hot_ns" / "hot_launches" (device time, from HIP events on the
  * bound stream, of the last sg_run_sweeps call's sweep kernel launches: the
  * single launch of the lattice, block or queue schedule, or the span of the

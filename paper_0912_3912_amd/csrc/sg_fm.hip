@@ -76,6 +76,34 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The same in 32 bits, for instances whose gains satisfy |g| < 2^19 (the
+// host checks 2 max_i sum|c| < 2^19) and whose external indices are below
+// 4096: key = (g + 2^19) << 12 | (4095 - ext), ordered as the 64-bit key.
+constexpr int kFmGainBias32 = 1 << 19;
+
+__device__ __forceinline__ uint32_t fm_key32(int gain, int ext)
+{
+    return ((uint32_t)(gain + kFmGainBias32) << 12) | (uint32_t)(4095 - ext);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_max_step32(uint32_t v)
+{
+    const uint32_t w = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWS, 0xF, false);
+    return w > v ? w : v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    v = dpp_max_step32<0xB1, 0xF>(v);
+    v = dpp_max_step32<0x4E, 0xF>(v);
+    v = dpp_max_step32<0x141, 0xF>(v);
+    v = dpp_max_step32<0x140, 0xF>(v);
+    v = dpp_max_step32<0x142, 0xA>(v);
+    v = dpp_max_step32<0x143, 0xC>(v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ void wave_lds_order()
 {
     // LDS operations of one wavefront complete in issue order; this keeps the
@@ -85,7 +113,7 @@ __device__ __forceinline__ void wave_lds_order()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool TRI>
+template <bool TRI, bool K32>
 __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ tab, const int32_t* __restrict__ ctab,
                                                    const QueueItem* __restrict__ items, int nitems, int nmax,
                                                    int waves_per_block, RepState* __restrict__ rs,
@@ -189,12 +217,17 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                 }
                 wave_lds_order();
                 uint64_t locked = 0;
-                uint64_t best = 0;
+                using Key = std::conditional_t<K32, uint32_t, uint64_t>;
+                auto make_key = [](int gn, int e) -> Key {
+                    if constexpr (K32) return fm_key32(gn, e);
+                    else return fm_key(gn, e);
+                };
+                Key best = 0;
                 int besti = -1;
                 for (int k = 0; k < G; ++k) {
                     const int i = lane + 64 * k;
                     if (i < n) {
-                        const uint64_t key = fm_key(gain[i], ext[i]);
+                        const Key key = make_key(gain[i], ext[i]);
                         if (key > best) {
                             best = key;
                             besti = i;
@@ -204,8 +237,15 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                 long long E = Estar, Elow = Estar;
                 int best_len = 0;
                 for (int step = 0; step < n; ++step) {
-                    const uint64_t top = wave_max_u64(best);
-                    const int g = (int)(uint32_t)(top >> 32) - kFmGainBias;
+                    Key top;
+                    int g;
+                    if constexpr (K32) {
+                        top = wave_max_u32(best);
+                        g = (int)(top >> 12) - kFmGainBias32;
+                    } else {
+                        top = wave_max_u64(best);
+                        g = (int)(uint32_t)(top >> 32) - kFmGainBias;
+                    }
                     // the move: the spin cached by the lane holding the maximum key
                     const uint64_t own = __ballot(best == top);
                     const int owner = (int)__builtin_ctzll(own);
@@ -258,7 +298,7 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                         for (int k = 0; k < G; ++k) {
                             const int ii = lane + 64 * k;
                             if (ii < n && !((locked >> k) & 1ull)) {
-                                const uint64_t key = fm_key(gain[ii], ext[ii]);
+                                const Key key = make_key(gain[ii], ext[ii]);
                                 if (key > best) {
                                     best = key;
                                     besti = ii;
@@ -338,24 +378,37 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
 
 size_t fm_lds_bytes(int nmax, int waves) { return fm_wave_bytes(nmax) * (size_t)waves; }
 
+template <bool TRI, bool K32>
+static hipError_t launch_fm_t(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax,
+                              int waves, int stage_cap, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
+                              int until_conv, hipStream_t st)
+{
+    const size_t lds = fm_lds_bytes(nmax, waves) + (size_t)stage_cap;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fm<TRI, K32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = (nitems + waves - 1) / waves;
+    hipLaunchKernelGGL((k_fm<TRI, K32>), dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax,
+                       waves, rs, cs, err, max_passes, until_conv, stage_cap);
+    return hipGetLastError();
+}
+
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
-                     int stage_cap, bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
-                     int until_conv, hipStream_t st)
+                     int stage_cap, bool tri, bool key32, RepState* rs, CallStats* cs, uint32_t* err,
+                     int max_passes, int until_conv, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
     if (waves < 1 || waves > kFmWaves || stage_cap < 0) return hipErrorInvalidValue;
-    const size_t lds = fm_lds_bytes(nmax, waves) + (size_t)stage_cap;
-    const void* kern = tri ? (const void*)k_fm<true> : (const void*)k_fm<false>;
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    const int blocks = (nitems + waves - 1) / waves;
+    if (key32 && nmax > 4096) return hipErrorInvalidValue;
     if (tri)
-        hipLaunchKernelGGL(k_fm<true>, dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax, waves,
-                           rs, cs, err, max_passes, until_conv, stage_cap);
-    else
-        hipLaunchKernelGGL(k_fm<false>, dim3(blocks), dim3(waves * 64), lds, st, tab, ctab, items, nitems, nmax, waves,
-                           rs, cs, err, max_passes, until_conv, stage_cap);
-    return hipGetLastError();
+        return key32 ? launch_fm_t<true, true>(tab, ctab, items, nitems, nmax, waves, stage_cap, rs, cs, err,
+                                                max_passes, until_conv, st)
+                     : launch_fm_t<true, false>(tab, ctab, items, nitems, nmax, waves, stage_cap, rs, cs, err,
+                                                 max_passes, until_conv, st);
+    return key32 ? launch_fm_t<false, true>(tab, ctab, items, nitems, nmax, waves, stage_cap, rs, cs, err, max_passes,
+                                            until_conv, st)
+                 : launch_fm_t<false, false>(tab, ctab, items, nitems, nmax, waves, stage_cap, rs, cs, err,
+                                             max_passes, until_conv, st);
 }
 
 }  // namespace sg

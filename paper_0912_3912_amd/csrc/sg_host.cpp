@@ -82,6 +82,7 @@ struct HostInst {
     // lattice schedule (implicit neighbours)
     int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
     int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
+    int64_t max_w = 0;                 // largest sum of |coefficients| over one spin's terms
     int32_t bits_ok = 0;               // at most 2048 spins, every |coefficient| <= 15 and per spin
                                        // sum |c| <= 255 (bit-sliced block kernel)
     // last tiling decision and the settings it was made for (rule, knobs)
@@ -122,6 +123,8 @@ struct sg_ctx {
     int32_t block_groups = 0;          // restart groups per block workgroup (0 = auto, up to 4)
     int32_t block_bits = 1;            // GREEDY block schedule in bit-sliced form where it applies
     int32_t bits_groups = 8;           // most groups of 32 restarts per bit-sliced workgroup (2, 4, 8, 16)
+    int32_t fm_key32 = 1;              // FM moves chosen on 32-bit keys where the gains allow
+    int32_t last_key32 = 0;            // the last FM call used 32-bit keys
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
@@ -623,6 +626,13 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     // term list of small instances, for the energy of one replica per lane
     q.eterm.clear();
     q.n_eh = q.n_ee = q.n_et = 0;
+    q.max_w = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t W = std::abs((int32_t)q.h[i]);
+        for (int64_t k = es[i]; k < es[i + 1]; ++k) W += std::abs((int32_t)(int8_t)(ew[k] & 0xFFu));
+        for (int64_t k = ts[i]; k < ts[i + 1]; ++k) W += std::abs((int32_t)(int8_t)(twa[k] & 0xFFu));
+        q.max_w = std::max(q.max_w, W);
+    }
     q.bits_ok = 0;
     if (n <= kLaneStartMaxN) {
         bool ok = true;
@@ -1487,12 +1497,15 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     if (p->schedule != SG_SCHED_AUTO && p->schedule != SG_SCHED_FM)
         return fail(SG_EINVAL, "rule SG_RULE_FM runs under SG_SCHED_AUTO or SG_SCHED_FM only");
     int nmax = 1;
-    bool tri = false;
+    bool tri = false, key32 = true;
     for (const HostInst& q : H->insts) {
         if (q.n > kFmMaxN) return fail(SG_EINVAL, "rule SG_RULE_FM: instance of %d spins (at most %d)", q.n, kFmMaxN);
         nmax = std::max(nmax, q.n);
         tri = tri || q.t > 0;
+        // 32-bit move keys: every gain |2 s f| < 2^19 and external indices below 4096
+        key32 = key32 && 2 * q.max_w < (int64_t)1 << 19 && q.n <= 4096 && H->fm_key32;
     }
+    H->last_key32 = key32 ? 1 : 0;
     hipStream_t st = H->stream;
     H->h_qitems.clear();
     for (size_t k = 0; k < H->insts.size(); ++k)
@@ -1519,7 +1532,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     SG_HIP(hipEventRecord(H->evh0, st), "event record");
     if (p->max_sweeps > 0)
         SG_HIP(sg::launch_fm(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
-                             (int)H->h_qitems.size(), nmax, waves, (int)stage, tri, H->reps(),
+                             (int)H->h_qitems.size(), nmax, waves, (int)stage, tri, key32, H->reps(),
                              H->at<sg::CallStats>(H->off_stats),
                              err, p->max_sweeps, p->until_converged, st),
                "pass kernel");
@@ -2045,6 +2058,9 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "lattice_wg_max_n") {
         if (value < 0 || value > 150000) return fail(SG_EINVAL, "lattice_wg_max_n must be in [0,150000]");
         H->lattice_wg_max_n = (int32_t)value;
+    } else if (k == "fm_key32") {
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "fm_key32 must be 0 or 1");
+        H->fm_key32 = (int32_t)value;
     } else if (k == "block_bits") {
         if (value != 0 && value != 1) return fail(SG_EINVAL, "block_bits must be 0 or 1");
         H->block_bits = (int32_t)value;
@@ -2101,6 +2117,8 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "block_rg") *value = H->block_rg;
     else if (k == "block_groups") *value = H->block_groups;
     else if (k == "block_bits") *value = H->block_bits;
+    else if (k == "fm_key32") *value = H->fm_key32;
+    else if (k == "last_key32") *value = H->last_key32;
     else if (k == "bits_groups") *value = H->bits_groups;
     else if (k == "block_min_restarts") *value = H->block_min_restarts;
     else if (k == "queue_wave_max_n") *value = H->queue_wave_max_n;

@@ -49,7 +49,7 @@ size_t fm_lds_bytes(int nmax, int waves);
 // stage_cap: LDS bytes after the wavefronts' slices in which a block stages
 // its instance's structure when all its items share one instance.
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
-                     int stage_cap, bool tri, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
+                     int stage_cap, bool tri, bool key32, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
                      int until_conv, hipStream_t st);
 // Dense hyper-Ising instances: one lane per replica; items are (instance,
 // first restart, count <= 64).  rule 0/1: colour sweeps; 2: pass-based search.

@@ -25,10 +25,12 @@ def _oracle(insts, seed, max_passes, uc, runs=None, threads=0):
     return out
 
 
-def _check(insts, seed, max_passes=1000, uc=True, runs=None):
+def _check(insts, seed, max_passes=1000, uc=True, runs=None, key32=1):
     import paper_0912_3912_amd as sg
-    log(f"fm case: {[i.name for i in insts][:4]} seed={seed} passes={runs or max_passes} uc={uc}")
-    h = sg.load_instance(list(insts)).bind()
+    log(f"fm case: {[i.name for i in insts][:4]} seed={seed} passes={runs or max_passes} uc={uc} key32={key32}")
+    h = sg.load_instance(list(insts))
+    h.tune("fm_key32", key32)
+    h.bind()
     h.init_spins(seed)
     stats = [h.run_sweeps(seed=seed, rule=FM, max_sweeps=mp, until_converged=uc) for mp in (runs or [max_passes])]
     assert all(s["schedule_used"] == sg.SCHED_FM for s in stats)
@@ -47,8 +49,22 @@ def test_ragged_random_with_triples(gpu, n):
     _check([inst], seed=n + 3)
 
 
-def test_chimera_with_triples(gpu):
-    _check([gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)], seed=11)
+@pytest.mark.parametrize("key32", [1, 0])
+def test_chimera_with_triples(gpu, key32):
+    """Moves chosen on 32-bit keys (the default where the gains allow) and on
+    64-bit keys give the same passes."""
+    h = _check([gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)], seed=11, key32=key32)
+    assert h.query("last_key32") == key32
+
+
+def test_large_coefficients_use_wide_keys(gpu):
+    """A dense instance whose gains may reach 2^19 in magnitude falls back to
+    64-bit keys by itself."""
+    # complete graph of 2100 spins with J = 127: sum |c| per spin >= 127 * 2099 > 2^18
+    inst = gen.random_small(2100, seed=4, p_edge=1.0, n_triples=0, j_range=(127, 127), h_range=(-7, 7),
+                            instance_id=5, restarts=1)
+    h = _check([inst], seed=3, max_passes=1, uc=False)
+    assert h.query("last_key32") == 0
 
 
 def test_lattice_and_regular(gpu):
