@@ -58,6 +58,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Per-attempt HBM bytes of the 3-D lattice sweep in two reference formats:
+# CSR with 4-byte row pointers and column indices and 1-byte couplings
+# (4 + 6 (4 + 1) + 1 (h) + 2 (own spin read and written) + 1 (other colours'
+# spins) = 38 B), and the compact lattice form with implicit indices and
+# 1-byte couplings (6 + 1 + 2 + 1 = 10 B).
+CSR_BYTES_PER_ATTEMPT = 38.0
+COMPACT_BYTES_PER_ATTEMPT = 10.0
+
+
 def int_ops_per_attempt(deg: float, tau: float = 0.0) -> float:
     """Algorithmic integer operations of one attempt: a multiply and an add
     per coupling, two multiplies and an add per hyper-coupling, the field
@@ -166,7 +175,10 @@ def run_cubic(args, sg, gen, torch):
                 "avg_launch_us": round(hot_us / max(launches, 1), 2),
                 "hbm_equiv": {"bytes_per_attempt": bpa, "GB/s": round(bpa * value / 1e9, 1),
                               "frac": round(bpa * value / 1e9 / PEAK_HBM_GBS, 4),
-                              "note": "bytes a streaming sliced-CSR sweep moves per attempt, at this attempt rate"}}
+                              "note": "bytes a streaming sliced-CSR sweep moves per attempt, at this attempt rate",
+                              "models": {name: {"bytes_per_attempt": b, "frac": round(b * value / 1e9 / PEAK_HBM_GBS, 4)}
+                                         for name, b in (("csr_int32_index_int8_J", CSR_BYTES_PER_ATTEMPT),
+                                                         ("compact_lattice", COMPACT_BYTES_PER_ATTEMPT))}}}
     cpu = None
     if args.cpu_sweeps > 0:
         import oracle

@@ -68,6 +68,57 @@ __device__ __forceinline__ void acc_add(uint32_t (&A)[8], uint32_t wt, uint32_t 
     }
 }
 
+// Four weighted masks at once: two 4-bit sums into 5 bits, their sum into 6
+// bits, and that added into the 8-bit counter (fewer carry chains through the
+// upper bits of A than four separate additions).
+__device__ __forceinline__ void acc_add4(uint32_t (&A)[8], const uint32_t (&wt)[4], const uint32_t (&u)[4])
+{
+    uint32_t m[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) m[t][p] = u[t] & (0u - ((wt[t] >> p) & 1u));
+    uint32_t S[2][5];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t* a = m[2 * h];
+        const uint32_t* b = m[2 * h + 1];
+        uint32_t c = a[0] & b[0];
+        S[h][0] = a[0] ^ b[0];
+#pragma unroll
+        for (int p = 1; p < 4; ++p) {
+            S[h][p] = a[p] ^ b[p] ^ c;
+            c = (a[p] & b[p]) | (c & (a[p] ^ b[p]));
+        }
+        S[h][4] = c;
+    }
+    uint32_t T[6];
+    {
+        uint32_t c = S[0][0] & S[1][0];
+        T[0] = S[0][0] ^ S[1][0];
+#pragma unroll
+        for (int p = 1; p < 5; ++p) {
+            T[p] = S[0][p] ^ S[1][p] ^ c;
+            c = (S[0][p] & S[1][p]) | (c & (S[0][p] ^ S[1][p]));
+        }
+        T[5] = c;
+    }
+    uint32_t c = A[0] & T[0];
+    A[0] ^= T[0];
+#pragma unroll
+    for (int p = 1; p < 6; ++p) {
+        const uint32_t a = A[p];
+        A[p] = a ^ T[p] ^ c;
+        c = (a & T[p]) | (c & (a ^ T[p]));
+    }
+#pragma unroll
+    for (int p = 6; p < 8; ++p) {
+        const uint32_t a = A[p];
+        A[p] = a ^ c;
+        c = a & c;
+    }
+}
+
 __device__ __forceinline__ uint32_t wave_or(uint32_t v)
 {
 #pragma unroll
@@ -264,11 +315,14 @@ __global__ __launch_bounds__(kBitsThreads) void k_block_bits(const InstTab* __re
                             for (int u = 0; u < 4; ++u) w[u] = pw[(k + u) * kSlice];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) xj[u] = sp[w[u] >> 8];
+                            uint32_t wt[4], um[4];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int cj = bits_coef(w[u]);
-                                acc_add(A, (uint32_t)abs(cj), xi ^ xj[u] ^ (cj < 0 ? ~0u : 0u));
+                                wt[u] = (uint32_t)abs(cj);
+                                um[u] = xi ^ xj[u] ^ (cj < 0 ? ~0u : 0u);
                             }
+                            acc_add4(A, wt, um);
                         }
                         for (; k < S.ew; ++k) {
                             const uint32_t w = pw[k * kSlice];
