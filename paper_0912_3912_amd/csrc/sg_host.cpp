@@ -93,7 +93,7 @@ struct HostInst {
     int32_t lat_D = 0;
     int32_t lat_c0 = 0;
     std::vector<uint64_t> lat_rec;     // per-site coupling record
-    uint64_t off_lat_rec = 0, off_lat_g = 0, off_lat_flags = 0, lat_g_bytes = 0;
+    uint64_t off_lat_rec = 0, off_lat_g = 0, lat_g_bytes = 0;
     // workspace offsets (bytes)
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0, off_eterm = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
@@ -729,11 +729,11 @@ void layout(sg_ctx* H)
         }
         if (q.lat_ok) {
             q.off_lat_rec = take((uint64_t)q.n * 8);
-            // two copies of one word per interior z-row of every tile (z extent >= 4 sites);
-            // the bit-plane kernel's words are 8 bytes (epoch tag and bits)
+            // two copies of one 8-byte word (epoch tag and bits) per interior z-row of
+            // every tile (z extent >= 4 sites)
             q.lat_g_bytes = ((uint64_t)q.n / 4 + 4096) * 8 * 2 * q.R;
             q.off_lat_g = take(q.lat_g_bytes);
-            q.off_lat_flags = take((uint64_t)kMaxLatticeTiles * q.R * 4);
+
         }
         max_slots = std::max<int64_t>(max_slots, (int64_t)q.R * q.nslots);
     }
@@ -1018,7 +1018,7 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
                 if (sg::lattice_tiles_ns(g, q.lat_L, q.lat_D) == 0) continue;
                 if ((q.lat_L[2] + p2 - 1) / p2 > 32) continue;  // an interior z-row is one 32-bit word
                 if (q.lat_L[2] / p2 < 4) continue;               // keeps the exchange within its allocation
-                if ((int64_t)sg::lattice_tiles_words(g, q.lat_L) * 8 * q.R > (int64_t)q.lat_g_bytes) continue;
+                if ((int64_t)sg::lattice_tiles_words(g, q.lat_L) * 16 * q.R > (int64_t)q.lat_g_bytes) continue;
                 if ((int64_t)T * q.R > cap_for(g)) continue;
                 bestV = V;
                 bestT = T;
@@ -1131,31 +1131,24 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 }
                 const sg::TileGeom tg = qm.tile_geom;
                 const bool msc = qm.tile_msc != 0;
-                uint32_t* flags = H->at<uint32_t>(q.off_lat_flags);
                 SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
-                // exchange words: at most n / (smallest z extent) + one row per tile, per copy
+                // exchange words (8 bytes: epoch tag and bits): at most n / (smallest z
+                // extent) + one row per tile, per copy
                 const int64_t words = sg::lattice_tiles_words(tg, q.lat_L) * q.R;
-                const uint64_t wbytes = msc ? 8 : 4;
-                if ((uint64_t)words * wbytes * 2 > q.lat_g_bytes)
-                    return fail(SG_ERANGE, "lattice tile exchange needs %lld bytes",
-                                (long long)(words * wbytes * 2));
-                if (msc) {
-                    // tags of this launch's epochs start at 1: clear the tags of earlier launches
-                    uint64_t* G0 = H->at<uint64_t>(q.off_lat_g);
-                    SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(G0), (uint64_t)words * 4, 0u, st),
-                           "fill kernel");
-                    SG_HIP(hipEventRecord(H->evh0, st), "event record");
+                if ((uint64_t)words * 16 > q.lat_g_bytes)
+                    return fail(SG_ERANGE, "lattice tile exchange needs %lld bytes", (long long)(words * 16));
+                // tags of this launch's epochs start at 1: clear the tags of earlier launches
+                uint64_t* G0 = H->at<uint64_t>(q.off_lat_g);
+                SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(G0), (uint64_t)words * 4, 0u, st), "fill kernel");
+                SG_HIP(hipEventRecord(H->evh0, st), "event record");
+                if (msc)
                     SG_HIP(sg::launch_lattice_msc(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err, rs,
                                                   q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
                            "lattice bit-plane kernel");
-                } else {
-                    SG_HIP(sg::launch_fill_u32(flags, (uint64_t)kMaxLatticeTiles * q.R, 0u, st), "fill kernel");
-                    uint32_t* G0 = H->at<uint32_t>(q.off_lat_g);
-                    SG_HIP(hipEventRecord(H->evh0, st), "event record");
-                    SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, flags, err,
-                                                    rs, q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
+                else
+                    SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err, rs,
+                                                    q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
                            "lattice tile kernel");
-                }
                 H->last_msc = msc ? 1 : 0;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;

@@ -14,12 +14,13 @@
 // after phase q of an epoch only sites at least q+1 layers inside the box are
 // still exact (each update needs its six neighbours from the previous
 // phase), so after k phases exactly the tile interior is exact.  It then
-// publishes its interior as one 32-bit word per z-row (bit per spin) with
-// coherent stores, waits for them to complete, signals an epoch flag, waits
-// for the flags of its (up to 26) neighbouring tiles and reads its new halo:
-// at most three aligned word loads per box row, all issued at once.  The exchange buffer alternates between two
-// copies by epoch parity, which removes the write-after-read hazard between
-// neighbours one epoch apart.  Each thread's sites are sorted deepest first,
+// publishes its interior as one 32-bit word per z-row (bit per spin), each
+// stored with the epoch's tag in one 8-byte agent-scope atomic, and reads its
+// new halo: at most three word loads per box row, all issued at once and each
+// polled until its tag shows the epoch (no separate flag).  The exchange
+// buffer alternates between two copies by epoch parity; a tile writes a copy
+// again only after reading words of the next epoch from every neighbour, and
+// a neighbour publishes those only after it has read this copy.  Each thread's sites are sorted deepest first,
 // so phase q walks only the sites deeper than q.  Every wait is bounded: on
 // time-out the kernel records an error and every workgroup exits.
 //
@@ -49,8 +50,8 @@ __device__ __forceinline__ int site_depth(int pk) { return (pk >> 20) & 0xFF; }
 
 template <int D, bool TIE, int NS>
 __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, TileGeom tg, int8_t* __restrict__ canon,
-                                                               int64_t stride, uint32_t* __restrict__ G0,
-                                                               uint32_t* __restrict__ G1, uint32_t* __restrict__ flags,
+                                                               int64_t stride, uint64_t* __restrict__ G0,
+                                                               uint64_t* __restrict__ G1,
                                                                uint32_t* __restrict__ err, RepState* __restrict__ rs,
                                                                int64_t* __restrict__ acc, int nslots, int T,
                                                                uint64_t seed)
@@ -98,9 +99,8 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
     int8_t* cs = canon + (int64_t)r * stride;
     // exchange words: tile t owns rows_per_tile words, one per interior z-row
     const int rows_per_tile = ((L0 + tg.P[0] - 1) / tg.P[0]) * ((L1 + tg.P[1] - 1) / tg.P[1]);
-    uint32_t* g0 = G0 + (int64_t)r * ntiles * rows_per_tile;
-    uint32_t* g1 = G1 + (int64_t)r * ntiles * rows_per_tile;
-    uint32_t* fl = flags + (int64_t)r * ntiles;
+    uint64_t* g0 = G0 + (int64_t)r * ntiles * rows_per_tile;
+    uint64_t* g1 = G1 + (int64_t)r * ntiles * rows_per_tile;
     const uint32_t base = (uint32_t)rs[r].sweeps;
 
     const uint32_t mB1 = fdiv_magic((uint32_t)B[1]), mB2 = fdiv_magic((uint32_t)B[2]);
@@ -261,12 +261,15 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
             }
             __syncthreads();
         }
-        // ---- exchange: publish the interior, signal, wait for the
-        // neighbouring tiles' signals, read the box back.  Both passes walk
-        // contiguous z-runs (lane <-> z) so the uncached byte accesses of a
-        // wavefront coalesce; re-reading the tile's own interior returns what
-        // it just wrote.
-        uint32_t* gw = (e & 1) ? g1 : g0;
+        // ---- exchange: publish the interior, then read the box back, every
+        // word with its epoch tag.  Both passes walk contiguous z-runs (lane
+        // <-> z) so a wavefront's byte accesses coalesce.  The reads write
+        // only halo bytes, which the publish does not read, so no barrier
+        // separates them.  After the last epoch the words are still awaited
+        // (not stored): then no neighbour is still reading its box from the
+        // spin array when this tile writes its interior back.
+        uint64_t* gw = (e & 1) ? g1 : g0;
+        const uint64_t tag = (uint64_t)(uint32_t)(e + 1) << 32;
         // one word per interior z-row: bit z set when the spin is -1
         for (int row = tid; row < nrow_int; row += kLatThreads) {
             const int x = (int)fdiv((uint32_t)row, mX1);
@@ -274,73 +277,57 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
             const int b0 = ((x + hk[0]) * B[1] + (y + hk[1])) * B[2] + hk[2];
             uint32_t w = 0;
             for (int z = 0; z < X[2]; ++z) w |= (uint32_t)(s[b0 + z] < 0) << z;
-            __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, tag | w, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        // Ordering: every exchange word and flag is accessed only with
-        // agent-scope atomics, which gfx950 performs at the coherence point
-        // (no copy in a non-coherent cache).  Each wave waits for its word
-        // stores to complete before the barrier, the flag is stored after it,
-        // and readers issue their word loads only after seeing the flag, so
-        // completion order alone publishes the data.  A release/acquire pair
-        // would add an L2 write-back and invalidate that move nothing here.
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(fl + tile, (uint32_t)(e + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (tid < 27) {
-            const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
-            const bool used = !(dx == 0 && dy == 0 && dz == 0) && !(D == 2 && dx != 0);
-            if (used) {
-                const int nx = (tc[0] + dx + tg.P[0]) % tg.P[0];
-                const int ny = (tc[1] + dy + tg.P[1]) % tg.P[1];
-                const int nz = (tc[2] + dz + tg.P[2]) % tg.P[2];
-                const int nb = (nx * tg.P[1] + ny) * tg.P[2] + nz;
-                uint32_t spins_left = 1u << 26;
-                while (__hip_atomic_load(fl + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)(e + 1)) {
-                    if (--spins_left == 0 ||
-                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        failed = true;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+        const bool last = (e + 1) * k >= P_total;
+        // box rows: the z-caps come from the z-neighbour tiles' rows, the
+        // middle from the tile owning the row (skipped for the own interior)
+        for (int row = tid; row < nrow_box && !failed; row += kLatThreads) {
+            const int x = (int)fdiv((uint32_t)row, mB1);
+            const int y = row - x * B[1];
+            const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
+            // owner of a coordinate: t = floor(((g + 1) P - 1) / L)
+            const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
+            const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
+            const int sx = tstart(0, tx), sy = tstart(1, ty);
+            const int X1t = tstart(1, ty + 1) - sy;
+            const int wrow = (gx - sx) * X1t + (gy - sy);
+            const int tb = (tx * tg.P[1] + ty) * tg.P[2];
+            const bool inner_row = x >= hk[0] && x < hk[0] + X[0] && y >= hk[1] && y < hk[1] + X[1];
+            uint64_t* al = gw + (int64_t)(tb + tzm) * rows_per_tile + wrow;
+            uint64_t* ah = gw + (int64_t)(tb + tzp) * rows_per_tile + wrow;
+            uint64_t* am = gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow;
+            uint64_t pl = __hip_atomic_load(al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t ph = __hip_atomic_load(ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t pm = inner_row ? tag : __hip_atomic_load(am, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // bounded wait for this epoch's words; a timeout here or in any
+            // other tile raises the error flag and ends every workgroup
+            uint32_t left = 1u << 20;
+            while (((pl ^ tag) | (ph ^ tag) | (pm ^ tag)) >> 32) {
+                if (--left == 0 ||
+                    ((left & 63u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    failed = true;
+                    break;
                 }
+                __builtin_amdgcn_s_sleep(2);
+                if ((pl ^ tag) >> 32) pl = __hip_atomic_load(al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((ph ^ tag) >> 32) ph = __hip_atomic_load(ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((pm ^ tag) >> 32) pm = __hip_atomic_load(am, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (failed || last) continue;
+            const uint32_t wl = (uint32_t)pl, wh = (uint32_t)ph, wm = (uint32_t)pm;
+            int8_t* sr = s + row * B[2];
+            for (int z = 0; z < hk[2]; ++z) {
+                sr[z] = (int8_t)(((wl >> (Xzm - hk[2] + z)) & 1u) ? -1 : 1);
+                sr[hk[2] + X[2] + z] = (int8_t)(((wh >> z) & 1u) ? -1 : 1);
+            }
+            if (!inner_row)
+                for (int z = 0; z < X[2]; ++z) sr[hk[2] + z] = (int8_t)(((wm >> z) & 1u) ? -1 : 1);
         }
         failed = __syncthreads_or(failed);
         if (failed) break;
-        if ((e + 1) * k < P_total) {
-            // box rows: the z-caps come from the z-neighbour tiles' rows, the
-            // middle from the tile owning the row (skipped for the own interior)
-            for (int row = tid; row < nrow_box; row += kLatThreads) {
-                const int x = (int)fdiv((uint32_t)row, mB1);
-                const int y = row - x * B[1];
-                const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
-                // owner of a coordinate: t = floor(((g + 1) P - 1) / L)
-                const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
-                const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
-                const int sx = tstart(0, tx), sy = tstart(1, ty);
-                const int X1t = tstart(1, ty + 1) - sy;
-                const int wrow = (gx - sx) * X1t + (gy - sy);
-                const int tb = (tx * tg.P[1] + ty) * tg.P[2];
-                const bool inner_row = x >= hk[0] && x < hk[0] + X[0] && y >= hk[1] && y < hk[1] + X[1];
-                const uint32_t wl = __hip_atomic_load(gw + (int64_t)(tb + tzm) * rows_per_tile + wrow, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t wh = __hip_atomic_load(gw + (int64_t)(tb + tzp) * rows_per_tile + wrow, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t wm = 0;
-                if (!inner_row)
-                    wm = __hip_atomic_load(gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                int8_t* sr = s + row * B[2];
-                for (int z = 0; z < hk[2]; ++z) {
-                    sr[z] = (int8_t)(((wl >> (Xzm - hk[2] + z)) & 1u) ? -1 : 1);
-                    sr[hk[2] + X[2] + z] = (int8_t)(((wh >> z) & 1u) ? -1 : 1);
-                }
-                if (!inner_row)
-                    for (int z = 0; z < X[2]; ++z) sr[hk[2] + z] = (int8_t)(((wm >> z) & 1u) ? -1 : 1);
-            }
-            __syncthreads();
-        }
     }
     // write the interior back in internal order and fold the counters
     if (!failed) {
@@ -542,7 +529,7 @@ static const void* pick_tiles_kernel(int D, bool tie, int ns)
 }
 
 hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride,
-                                uint32_t* G0, uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R,
+                                uint64_t* G0, uint64_t* G1, uint32_t* err, RepState* rs, int R,
                                 int64_t* acc, int nslots, int T, uint64_t seed, int rule, hipStream_t st)
 {
     const int ns = lattice_tiles_ns(tg, Lt.L, Lt.D);
@@ -554,7 +541,7 @@ hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t
     const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
     LatticeDev a0 = Lt;
     TileGeom a1 = tg;
-    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &flags, &err, &rs, &acc, &nslots, &T, &seed};
+    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &err, &rs, &acc, &nslots, &T, &seed};
     return hipLaunchCooperativeKernel(kern, dim3(ntiles * R), dim3(kLatThreads), args, (unsigned)lds, st);
 }
 

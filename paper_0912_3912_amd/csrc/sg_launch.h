@@ -33,7 +33,7 @@ size_t lattice_tiles_lds(const TileGeom& tg, const int L[3], int D);
 int lattice_tiles_ns(const TileGeom& tg, const int L[3], int D);  // 0 if the box is too large
 int lattice_tiles_max_blocks(const TileGeom& tg, const int L[3], int D);
 hipError_t launch_lattice_tiles(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride,
-                                uint32_t* G0, uint32_t* G1, uint32_t* flags, uint32_t* err, RepState* rs, int R,
+                                uint64_t* G0, uint64_t* G1, uint32_t* err, RepState* rs, int R,
                                 int64_t* acc, int nslots, int T, uint64_t seed, int rule, hipStream_t st);
 // exchange words of one copy for a tiling (per replica)
 int64_t lattice_tiles_words(const TileGeom& tg, const int L[3]);
