@@ -84,7 +84,7 @@ enum {
     SG_SCHED_PHASE = 0,        /* one kernel launch per colour phase per instance */
     SG_SCHED_GRAPH = 1,        /* SG_SCHED_PHASE captured in HIP graphs of several sweeps */
                                /* 2 is reserved */
-    SG_SCHED_LATTICE = 3,      /* lattice instances: LDS-resident tiles, neighbour flags */
+    SG_SCHED_LATTICE = 3,      /* lattice instances: LDS-resident tiles, halo exchange */
     SG_SCHED_BLOCK = 4,        /* one workgroup per instance, structure and replicas in LDS */
     SG_SCHED_QUEUE = 5,        /* persistent batched: work queue of uneven instances */
     SG_SCHED_FM = 6,           /* SG_RULE_FM: one wavefront per replica */

@@ -4,8 +4,8 @@
 //
 // Same tiling, halo, epoch and exchange protocol as k_lattice_tiles (a tile
 // plus a halo of width k per workgroup, k colour phases between exchanges,
-// bit-packed interior z-rows published with coherent stores and a relaxed
-// epoch flag, bounded waits), but the box is held as bit-planes: every box
+// bit-packed interior z-rows published as coherent 8-byte words that carry
+// their epoch tag, bounded waits), but the box is held as bit-planes: every box
 // z-row is split by colour into two 32-bit words (bit j of colour c's word
 // is the site z = 2j + zo, zo = the row's offset for that colour), for the
 // spin (bit set when s = -1), the sign of the +x, +y and +z bond (bit set
