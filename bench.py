@@ -229,8 +229,7 @@ def run_chimera(args, sg, gen, torch, count=4096, sample=16):
     st = outs[-1]
     attempts = st["attempts"]
     hot_us = st["hot_ns"] / 1e3
-    # the bit-sliced kernel leaves the energies to a recomputation, timed with it
-    kname = "k_block_bits + energy" if h.query("last_bits") else "k_block"
+    kname = "k_block_bits" if h.query("last_bits") else "k_block"
     log(f"batched: {dt * 1e3:.2f} ms/step, {attempts:.3g} attempts, sweeps_max {st['sweeps_max']}, "
         f"schedule {st['schedule_used']}, hot {hot_us:.0f} us")
     h.free()

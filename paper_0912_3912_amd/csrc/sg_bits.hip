@@ -21,8 +21,9 @@
 // restarts have all stopped writes its spins back and takes the next 32
 // restarts of the workgroup's range.  Flip counts per restart are kept as
 // bit-sliced counters per lane and summed over lanes with ballots.  Energies
-// are not tracked here: the host recomputes them from the final spins (the
-// same integer the incremental sum would give).
+// are not tracked incrementally: a finished group computes them from its
+// final spins and the instance's term list (the same integer the incremental
+// sum would give).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -289,6 +290,68 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
         }
     };
 
+    // Energies of the group's 32 restarts from their final spins (Sec. II
+    // eq. (1), Sec. VI eq. (5)): E = -sum c prod s = 2 V - W, with W = sum |c|
+    // over the instance's terms and V the |c|-weighted count of unsatisfied
+    // terms.  The lanes split the term list; each keeps an 8-bit bit-sliced
+    // count (at most 16 terms of weight <= 15) that it folds into a 20-bit one
+    // (sum |c| <= 2048 * 255 < 2^20 for the instances this kernel takes), and
+    // ballots sum the lanes' counts per restart.  Lane b < 32 returns the
+    // energy of restart b.
+    const uint32_t* ET = Q.eterm;
+    const int n_eh = Q.n_eh, n_ee = Q.n_ee, n_et = Q.n_et;
+    auto group_energy = [&]() -> long long {
+        const uint32_t* spg = l_sp + g * n;
+        constexpr int kBW = 20;
+        uint32_t A[8] = {0, 0, 0, 0, 0, 0, 0, 0}, B[kBW];
+#pragma unroll
+        for (int p = 0; p < kBW; ++p) B[p] = 0u;
+        int wsum = 0, pending = 0;
+        auto fold = [&]() {  // B += A, A = 0
+            uint32_t c = 0;
+#pragma unroll
+            for (int p = 0; p < kBW; ++p) {
+                const uint32_t a = p < 8 ? A[p] : 0u, bb = B[p];
+                B[p] = bb ^ a ^ c;
+                c = (bb & a) | (c & (bb ^ a));
+            }
+#pragma unroll
+            for (int p = 0; p < 8; ++p) A[p] = 0u;
+            pending = 0;
+        };
+        auto term = [&](uint32_t w, uint32_t parity) {
+            const int cf = bits_coef(w >> 22);
+            wsum += abs(cf);
+            acc_add(A, (uint32_t)abs(cf), parity ^ (cf < 0 ? ~0u : 0u));
+            if (++pending == 16) fold();
+        };
+        for (int t = lane; t < n_eh; t += 64) {
+            const uint32_t w = ET[t];
+            term(w, spg[w & 0x7FFu]);
+        }
+        for (int t = lane; t < n_ee; t += 64) {
+            const uint32_t w = ET[n_eh + t];
+            term(w, spg[w & 0x7FFu] ^ spg[(w >> 11) & 0x7FFu]);
+        }
+        for (int t = lane; t < n_et; t += 64) {
+            const uint32_t w = ET[n_eh + n_ee + 2 * t], b = ET[n_eh + n_ee + 2 * t + 1];
+            term(w, spg[w & 0x7FFu] ^ spg[(w >> 11) & 0x7FFu] ^ spg[b]);
+        }
+        fold();
+        long long V = 0;
+#pragma unroll
+        for (int p = 0; p < kBW; ++p) {
+            if (__ballot(B[p] != 0u) == 0) continue;
+            for (int b = 0; b < 32; ++b) {
+                const long long v = (long long)__popcll(__ballot((B[p] >> b) & 1u)) << p;
+                if (lane == b) V += v;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+        return 2 * V - (long long)wsum;
+    };
+
     if (wk == 0 && fetch() && lane == 0) atomicAdd(&n_live, 1);
     __syncthreads();
     if (g_load[g]) load_group();
@@ -408,9 +471,11 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
             __syncthreads();
             if (g_fin[g]) {
                 store_group();
+                const long long Eg = group_energy();
                 if (wk == 0 && lane < 32 && ((g_part[g] >> lane) & 1u)) {
                     const int t = r_t[g * 32 + lane], last = r_last[g * 32 + lane], nf = r_flips[g * 32 + lane];
                     RepState* st = rs + Q.rep_base + g_r0[g] + lane;
+                    st->E = Eg;
                     st->flips += nf;
                     st->sweeps += t;
                     st->lastflip = last;

@@ -140,7 +140,7 @@ struct sg_ctx {
     int32_t dense_nmax = 1;
     hipStream_t cap_stream = nullptr;  // private stream used only to record graphs
     uint64_t off_tbase = 0;            // one sweep base per instance (graph replays)
-    uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_beitems = 0, off_qitems = 0, off_qcnt = 0;
+    uint64_t off_tab = 0, off_ctab = 0, off_bitems = 0, off_qitems = 0, off_qcnt = 0;
     uint64_t off_rep_inst = 0;
     // batched start / energy of the replicas not started one lane each: units
     // of 1024 spins (start) and of four slices (energy)
@@ -753,7 +753,6 @@ void layout(sg_ctx* H)
     H->off_tab = take(ni * sizeof(sg::InstTab));
     H->off_ctab = take((uint64_t)H->ctab_len * 4);
     H->off_bitems = take((uint64_t)H->n_block_item_cap * sizeof(sg::BlockItem));
-    H->off_beitems = take((uint64_t)H->n_block_item_cap * sizeof(sg::BlockItem));
     H->off_qitems = take((uint64_t)H->total_reps * sizeof(sg::QueueItem));
     H->off_qcnt = take(64);
     H->off_rep_inst = take((uint64_t)H->total_reps * 4);
@@ -1213,8 +1212,8 @@ size_t bits_lds_for(const sg_ctx* H, const HostInst& q)
 sg_status run_block_bits_ng(sg_handle H, const sg_run_params* p, const std::vector<int>& which, int NG);
 
 // GREEDY on the bit-sliced block kernel: one workgroup per range of restarts
-// (up to four workgroup-fulls of groups of 32, taken in turn as groups stop),
-// then the energies recomputed from the final spins, one replica per lane.
+// (up to four workgroup-fulls of groups of 32, taken in turn as groups stop);
+// a finished group computes its restarts' energies from their final spins.
 sg_status run_block_bits(sg_handle H, const sg_run_params* p, const std::vector<int>& which_all)
 {
     // one launch per group count (a template parameter of the kernel)
@@ -1238,12 +1237,10 @@ sg_status run_block_bits_ng(sg_handle H, const sg_run_params* p, const std::vect
     hipStream_t st = H->stream;
     size_t lds = 0;
     int64_t groups = 0;
-    int nmax = 1;
     for (int qi : which) {
         const HostInst& q = H->insts[qi];
         lds = std::max(lds, bits_lds_for(H, q));
         groups += (q.R + 31) / 32;
-        nmax = std::max(nmax, q.n);
     }
     int m = H->block_groups;
     if (m <= 0) {
@@ -1251,30 +1248,22 @@ sg_status run_block_bits_ng(sg_handle H, const sg_run_params* p, const std::vect
         m = (int)std::max<int64_t>(1, std::min<int64_t>(kBlockGroupsAuto, groups / ((int64_t)NG * cap)));
     }
     H->h_bitems.clear();
-    std::vector<sg::BlockItem> eitems;
     for (int qi : which) {
         const HostInst& q = H->insts[qi];
         for (int r0 = 0; r0 < q.R; r0 += 32 * NG * m)
             H->h_bitems.push_back(sg::BlockItem{qi, r0, std::min(32 * NG * m, q.R - r0), 0});
-        for (int r0 = 0; r0 < q.R; r0 += 64) eitems.push_back(sg::BlockItem{qi, r0, std::min(64, q.R - r0), 0});
     }
-    if ((int64_t)eitems.size() > H->n_block_item_cap || (int64_t)H->h_bitems.size() > H->n_block_item_cap)
+    if ((int64_t)H->h_bitems.size() > H->n_block_item_cap)
         return fail(SG_EINVAL, "block schedule: item list exceeds its allocation");
     sg::BlockItem* dit = H->at<sg::BlockItem>(H->off_bitems);
-    sg::BlockItem* eit = H->at<sg::BlockItem>(H->off_beitems);
     SG_HIP(hipMemcpyAsync(dit, H->h_bitems.data(), H->h_bitems.size() * sizeof(sg::BlockItem), hipMemcpyHostToDevice,
                           st),
            "upload block items");
-    SG_HIP(hipMemcpyAsync(eit, eitems.data(), eitems.size() * sizeof(sg::BlockItem), hipMemcpyHostToDevice, st),
-           "upload energy items");
     SG_HIP(hipEventRecord(H->evh0, st), "event record");
     SG_HIP(sg::launch_block_bits(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
                                  (int)H->h_bitems.size(), lds, H->reps(), H->at<sg::CallStats>(H->off_stats), NG,
                                  p->max_sweeps, p->until_converged, st),
            "bit-sliced block kernel");
-    SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), eit, (int)eitems.size(), nmax, false, H->reps(),
-                                  nullptr, 0, st),
-           "energy kernel");
     SG_HIP(hipEventRecord(H->evh1, st), "event record");
     H->hot_launches = 1;
     H->last_bits = 1;

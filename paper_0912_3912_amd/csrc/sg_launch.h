@@ -67,7 +67,7 @@ hipError_t launch_block(const InstTab* tab, const int32_t* ctab, const BlockItem
                         RepState* rs, CallStats* cs, int RG, int T, uint64_t seed, int rule, int until_conv,
                         hipStream_t st);
 // The block schedule under GREEDY with 32 restarts per LDS word (NG groups of
-// 32 per workgroup); energies are left for a recomputation.
+// 32 per workgroup); a finished group computes its restarts' energies.
 size_t block_bits_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, int NG);
 hipError_t launch_block_bits(const InstTab* tab, const int32_t* ctab, const BlockItem* items, int n_items, size_t lds,
                              RepState* rs, CallStats* cs, int NG, int T, int until_conv, hipStream_t st);
