@@ -310,6 +310,13 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        always the byte kernel (default 1)
  *   "bits_groups"        most groups of 32 restarts per bit-sliced workgroup
  *                        (2, 4, 8, 16; default 8)
+ *   "defer_energy"       1: sg_init_spins leaves out the start energy of
+ *                        instances that SG_SCHED_AUTO would run on the
+ *                        bit-sliced kernel (it computes the energies of the
+ *                        final spins itself); any other reader of the
+ *                        energies (sg_energy, sg_best, another rule or
+ *                        schedule) first computes them.  0: always at the
+ *                        start (default 1; results are the same)
  *   "fm_key32"           1: SG_RULE_FM picks moves on 32-bit keys when every
  *                        gain is below 2^19 in magnitude; 0: 64-bit keys
  *                        (default 1)
@@ -341,7 +348,9 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
  * lattice tile launch), "last_tile_k", "last_msc" (1 when that launch used
  * the bit-plane kernel), "last_bits" (1 when the last block-schedule call
  * used the bit-sliced kernel), "last_key32" (1 when the last SG_RULE_FM call
- * picked moves on 32-bit keys), "last_queue_grid", "total_replicas",
+ * picked moves on 32-bit keys), "energy_pending" (1 while start energies
+ * left out by sg_init_spins are not yet computed), "last_queue_grid",
+ * "total_replicas",
  * "instances", "hot_ns" / "hot_launches" (device time, from HIP events on the
  * bound stream, of the last sg_run_sweeps call's sweep kernel launches: the
  * single launch of the lattice, block or queue schedule, or the span of the

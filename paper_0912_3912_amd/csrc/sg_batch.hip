@@ -384,7 +384,10 @@ hipError_t launch_start_units(const InstTab* tab, const StartUnit* start_units, 
 // instance's slices and coupling words, the same for every lane, are walked
 // in order with scalar loads.  INIT: draw the start (the Philox start rule)
 // and store it as bytes; else read the stored spins.  Energy of Sec. II
-// eq. (1) / Sec. VI eq. (5), each term at its smallest internal index.
+// eq. (1) / Sec. VI eq. (5), each term at its smallest internal index.  An
+// INIT item with a nonzero flag (BlockItem::pad) only draws its start and
+// leaves E at 0: its energy comes later, from the kernel that runs its
+// descent or from an energy pass before anything reads it.
 template <bool INIT>
 __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__ tab,
                                                      const BlockItem* __restrict__ items, int nitems, int wmax,
@@ -456,6 +459,14 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
             if (mine) *reinterpret_cast<uint32_t*>(sp + i0) = quad;
         }
         bits[w * 64 + lane] = word;
+    }
+    if (INIT && it.pad) {
+        if (mine) {
+            RepState z;
+            z.E = 0; z.flips = 0; z.sweeps = 0; z.lastflip = 0; z.converged = 0;
+            rs[rep_base + r] = z;
+        }
+        return;
     }
     // -E as a sum over the instance's term list (the same for every lane):
     // a product of spins is +1 or -1 by the parity of their set bits

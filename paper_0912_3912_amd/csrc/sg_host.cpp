@@ -124,6 +124,7 @@ struct sg_ctx {
     int32_t block_bits = 1;            // GREEDY block schedule in bit-sliced form where it applies
     int32_t bits_groups = 8;           // most groups of 32 restarts per bit-sliced workgroup (2, 4, 8, 16)
     int32_t fm_key32 = 1;              // FM moves chosen on 32-bit keys where the gains allow
+    int32_t defer_energy = 1;          // a drawn start expected on the bit-sliced kernel gets its energy later
     int32_t last_key32 = 0;            // the last FM call used 32-bit keys
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
@@ -158,6 +159,11 @@ struct sg_ctx {
     hipStream_t stream = nullptr;
     bool bound = false;
     std::vector<uint8_t> started;
+    // Start energies left out by the lane start kernel: e_deferred marks the
+    // instances, e_pending is set until a bit-sliced run has written their
+    // energies or an energy pass has computed them.
+    std::vector<uint8_t> e_deferred;
+    bool e_pending = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evh0 = nullptr, evh1 = nullptr;  // around the hot kernel(s) of the last schedule run
     double hot_us = 0.0;                        // their device time, microseconds
@@ -1271,16 +1277,19 @@ sg_status run_block_bits_ng(sg_handle H, const sg_run_params* p, const std::vect
     return SG_OK;
 }
 
+// The block schedule runs this instance on the bit-sliced kernel.
+bool bits_path(const sg_ctx* H, const sg_run_params* p, const HostInst& q)
+{
+    return H->block_bits && p->rule == SG_RULE_GREEDY && p->max_sweeps > 0 && bits_lds_for(H, q) > 0;
+}
+
 sg_status run_block_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which_all)
 {
     if (which_all.empty()) return SG_OK;
     hipStream_t st = H->stream;
     H->last_bits = 0;
     std::vector<int> bits, which;
-    for (int qi : which_all) {
-        const bool b = H->block_bits && p->rule == SG_RULE_GREEDY && p->max_sweeps > 0 && bits_lds_for(H, H->insts[qi]);
-        (b ? bits : which).push_back(qi);
-    }
+    for (int qi : which_all) (bits_path(H, p, H->insts[qi]) ? bits : which).push_back(qi);
     if (!bits.empty()) {
         sg_status e = run_block_bits(H, p, bits);
         if (e != SG_OK) return e;
@@ -1554,6 +1563,28 @@ sg_status sg_internal_validate(const sg_instance_desc* d) { return validate(*d, 
 // ---------------------------------------------------------------------------
 // C-ABI
 
+// A drawn start of this lane-started instance leaves its energy out when
+// SG_SCHED_AUTO would run the instance on the bit-sliced block kernel, which
+// computes the energies of the final spins itself.  A wrong guess costs an
+// energy pass, never a wrong energy.
+bool defer_start_energy(const sg_ctx* H, const HostInst& q)
+{
+    return H->defer_energy && H->block_bits && q.bits_ok && !q.lat_ok && q.R >= H->block_min_restarts &&
+           can_block(H, q) && bits_lds_for(H, q) > 0;
+}
+
+// Compute the left-out start energies (all lane-started replicas; the others
+// have not moved since their start, so theirs are recomputed unchanged).
+sg_status ensure_energy(sg_handle H)
+{
+    if (!H->e_pending) return SG_OK;
+    SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
+                                  (int)H->h_litems.size(), H->lane_nmax, false, H->reps(), nullptr, 0, H->stream),
+           "lane energy kernel");
+    H->e_pending = false;
+    return SG_OK;
+}
+
 extern "C" {
 
 const char* sg_last_error(void) { return g_err.c_str(); }
@@ -1808,7 +1839,21 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
                                       (int64_t)H->h_esegs.size(), H->at<int64_t>(H->off_eparts), H->reps(), nullptr,
                                       seed, true, st),
                "start kernels");
+    H->e_pending = false;
+    H->e_deferred.assign(H->insts.size(), 0);
     if (!H->h_litems.empty()) {
+        bool changed = false;
+        for (sg::BlockItem& it : H->h_litems) {
+            const int32_t d = defer_start_energy(H, H->insts[(size_t)it.inst]) ? 1 : 0;
+            H->e_deferred[(size_t)it.inst] = (uint8_t)d;
+            H->e_pending = H->e_pending || d;
+            changed = changed || it.pad != d;
+            it.pad = d;
+        }
+        if (changed)
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_litems, H->h_litems.data(), H->h_litems.size() * sizeof(sg::BlockItem),
+                                  hipMemcpyHostToDevice, st),
+                   "upload lane items");
         SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
                                       (int)H->h_litems.size(), H->lane_nmax, true, H->reps(), nullptr, seed, st),
                "lane start kernel");
@@ -1865,12 +1910,20 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     for (uint8_t v : H->started)
         if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
     if (H->dense) return run_dense(H, p, stats);
-    if (p->rule == SG_RULE_FM) return run_fm(H, p, stats);
+    if (p->rule == SG_RULE_FM) {
+        if ((e = ensure_energy(H)) != SG_OK) return e;
+        return run_fm(H, p, stats);
+    }
     std::vector<int> assign;
     const int sched = assign_schedules(H, p, assign);
     if (sched < 0 && p->schedule != SG_SCHED_AUTO)
         return fail(SG_EINVAL, "schedule %d is not available for this handle (rule %d, until_converged %d)",
                     p->schedule, p->rule, p->until_converged);
+    // left-out start energies are written by the bit-sliced kernel; any other
+    // kernel continues from them, so they are computed first
+    for (size_t k = 0; H->e_pending && k < assign.size(); ++k)
+        if (H->e_deferred[k] && !(assign[k] == SG_SCHED_BLOCK && bits_path(H, p, H->insts[k])))
+            if ((e = ensure_energy(H)) != SG_OK) return e;
     hipStream_t st = H->stream;
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
@@ -1890,6 +1943,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
         }
         if (e != SG_OK) return e;
     }
+    H->e_pending = false;
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
     sg::CallStats cs;
     SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
@@ -1923,6 +1977,7 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
     sg_status e = need_bound(H);
     if (e != SG_OK) return e;
     if (!E) return fail(SG_EINVAL, "sg_energy: null output");
+    if (!recompute && (e = ensure_energy(H)) != SG_OK) return e;
     hipStream_t st = H->stream;
     if (recompute) {
         int64_t* eout = H->at<int64_t>(H->off_eout);
@@ -2012,6 +2067,7 @@ sg_status sg_best(sg_handle H, int64_t* E_best, int32_t* r_best)
 {
     sg_status e = need_bound(H);
     if (e != SG_OK) return e;
+    if ((e = ensure_energy(H)) != SG_OK) return e;
     const int ni = (int)H->insts.size();
     hipStream_t st = H->stream;
     SG_HIP(sg::launch_best(H->reps(), H->at<int64_t>(H->off_rep_base), H->at<int32_t>(H->off_restarts), ni,
@@ -2043,6 +2099,9 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "fm_key32") {
         if (value != 0 && value != 1) return fail(SG_EINVAL, "fm_key32 must be 0 or 1");
         H->fm_key32 = (int32_t)value;
+    } else if (k == "defer_energy") {
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "defer_energy must be 0 or 1");
+        H->defer_energy = (int32_t)value;
     } else if (k == "block_bits") {
         if (value != 0 && value != 1) return fail(SG_EINVAL, "block_bits must be 0 or 1");
         H->block_bits = (int32_t)value;
@@ -2099,6 +2158,8 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "block_rg") *value = H->block_rg;
     else if (k == "block_groups") *value = H->block_groups;
     else if (k == "block_bits") *value = H->block_bits;
+    else if (k == "defer_energy") *value = H->defer_energy;
+    else if (k == "energy_pending") *value = H->e_pending ? 1 : 0;
     else if (k == "fm_key32") *value = H->fm_key32;
     else if (k == "last_key32") *value = H->last_key32;
     else if (k == "bits_groups") *value = H->bits_groups;

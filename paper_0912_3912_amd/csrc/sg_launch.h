@@ -78,6 +78,7 @@ int queue_max_blocks(size_t lds);
 // Start (init) or energy of many replicas of small instances, one lane per
 // replica; items (instance, first restart, count <= 64), instances of at most
 // 2048 spins.  Without init the energies go to out (or rs when out is null).
+// With init, an item whose pad field is nonzero leaves its replicas' E at 0.
 hipError_t launch_start_lanes(const InstTab* tab, const BlockItem* items, int nitems, int nmax, bool init,
                               RepState* rs, int64_t* out, uint64_t seed, hipStream_t st);
 // Batched start (init: spins drawn by units of 1024 spins, state reset) and

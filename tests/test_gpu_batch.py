@@ -64,6 +64,53 @@ def test_block_restart_refill(gpu, groups):
     _run(insts, 3, TIE, 0, True, SCHED_BLOCK, tune={"block_groups": groups}, runs=[4, 0, 30])
 
 
+def test_deferred_start_energy(gpu):
+    """Start energies that sg_init_spins leaves out for instances bound for the
+    bit-sliced kernel: equal to the oracle's when read right after the start
+    (energy, best), when the bit-sliced kernel writes them, when another rule
+    or a zero-sweep call runs first, and under the pass rule (whose tracked
+    energies continue from them); the same with the deferral switched off."""
+    import paper_0912_3912_amd as sg
+    # enough replicas for the lane start kernel (16384), ragged restart counts
+    insts = [gen.chimera(4, 4, seed=20 + k, restarts=R, instance_id=90 + k)
+             for k, R in enumerate((4096, 4100, 4200, 4000))]
+    seed = 5
+    start = [oracle_run(i, seed, GREEDY, 0, False) for i in insts]
+
+    def handle(defer):
+        h = sg.load_instance(insts).tune("defer_energy", defer).bind()
+        h.init_spins(seed)
+        assert h.query("energy_pending") == defer
+        return h
+
+    for defer in (1, 0):
+        log(f"deferred start energy: defer={defer}")
+        h = handle(defer)
+        Eb, rb = h.best()
+        assert h.query("energy_pending") == 0
+        for q, st in enumerate(start):
+            assert Eb[q] == st.energy.min() and rb[q] == int(np.argmin(st.energy))
+        compare(h, insts, start)
+
+        h = handle(defer)
+        h.run_sweeps(seed=seed, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=SCHED_AUTO)
+        assert h.query("last_bits") == 1 and h.query("energy_pending") == 0
+        compare(h, insts, [oracle_run(i, seed, GREEDY, 10000, True, threads=8) for i in insts])
+
+        h = handle(defer)
+        h.run_sweeps(seed=seed, rule=TIE, max_sweeps=6, until_converged=False, schedule=SCHED_AUTO)
+        compare(h, insts, [oracle_run(i, seed, TIE, 6, False, threads=8) for i in insts])
+
+        h = handle(defer)
+        h.run_sweeps(seed=seed, rule=GREEDY, max_sweeps=0, until_converged=False, schedule=SCHED_AUTO)
+        assert h.query("energy_pending") == 0
+        compare(h, insts, start)
+
+        h = handle(defer)
+        h.run_sweeps(seed=seed, rule=sg.FM, max_sweeps=2, until_converged=False)
+        assert np.array_equal(h.energy(), h.energy(recompute=True))
+
+
 @pytest.mark.parametrize("ng", [2, 4, 8, 16])
 def test_block_bits_groups(gpu, ng):
     """The bit-sliced GREEDY block kernel with at most 2, 4, 8 and 16 groups
