@@ -311,12 +311,16 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *   "bits_groups"        most groups of 32 restarts per bit-sliced workgroup
  *                        (2, 4, 8, 16; default 8)
  *   "defer_energy"       1: sg_init_spins leaves out the start energy of
- *                        instances that SG_SCHED_AUTO would run on the
- *                        bit-sliced kernel (it computes the energies of the
- *                        final spins itself); any other reader of the
- *                        energies (sg_energy, sg_best, another rule or
- *                        schedule) first computes them.  0: always at the
- *                        start (default 1; results are the same)
+ *                        instances that SG_SCHED_AUTO would run on a kernel
+ *                        that computes the energies of the final spins
+ *                        itself: the bit-sliced block kernel, or the queue
+ *                        kernel (from the last sweep of a converged replica;
+ *                        when a replica stops on the sweep cap, the energies
+ *                        are computed after the run).  Any other reader
+ *                        (sg_energy, sg_best, another rule or schedule, a
+ *                        run without until_converged) first computes them.
+ *                        0: always at the start (default 1; results are the
+ *                        same)
  *   "fm_key32"           1: SG_RULE_FM picks moves on 32-bit keys when every
  *                        gain is below 2^19 in magnitude; 0: 64-bit keys
  *                        (default 1)

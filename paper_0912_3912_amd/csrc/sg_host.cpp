@@ -124,7 +124,7 @@ struct sg_ctx {
     int32_t block_bits = 1;            // GREEDY block schedule in bit-sliced form where it applies
     int32_t bits_groups = 8;           // most groups of 32 restarts per bit-sliced workgroup (2, 4, 8, 16)
     int32_t fm_key32 = 1;              // FM moves chosen on 32-bit keys where the gains allow
-    int32_t defer_energy = 1;          // a drawn start expected on the bit-sliced kernel gets its energy later
+    int32_t defer_energy = 1;          // a drawn start whose run computes final energies gets its energy later
     int32_t last_key32 = 0;            // the last FM call used 32-bit keys
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
@@ -159,9 +159,10 @@ struct sg_ctx {
     hipStream_t stream = nullptr;
     bool bound = false;
     std::vector<uint8_t> started;
-    // Start energies left out by the lane start kernel: e_deferred marks the
-    // instances, e_pending is set until a bit-sliced run has written their
-    // energies or an energy pass has computed them.
+    // Start energies left out by sg_init_spins: e_deferred marks the instances
+    // (1: lane start, the bit-sliced kernel writes the energies; 2: unit start,
+    // the queue kernel writes them at convergence), e_pending is set until a
+    // run has written them or an energy pass has computed them.
     std::vector<uint8_t> e_deferred;
     bool e_pending = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1563,24 +1564,57 @@ sg_status sg_internal_validate(const sg_instance_desc* d) { return validate(*d, 
 // ---------------------------------------------------------------------------
 // C-ABI
 
-// A drawn start of this lane-started instance leaves its energy out when
-// SG_SCHED_AUTO would run the instance on the bit-sliced block kernel, which
-// computes the energies of the final spins itself.  A wrong guess costs an
-// energy pass, never a wrong energy.
-bool defer_start_energy(const sg_ctx* H, const HostInst& q)
+// A drawn start leaves its energy out when the kernel that SG_SCHED_AUTO
+// would run next computes the energies of the final spins itself: the
+// bit-sliced block kernel for lane-started instances (always), the queue
+// kernel for the others (at convergence; it is taken only when every
+// unit-started instance would run there).  A wrong guess costs an energy
+// pass, never a wrong energy.
+bool defer_lane_energy(const sg_ctx* H, const HostInst& q)
 {
     return H->defer_energy && H->block_bits && q.bits_ok && !q.lat_ok && q.R >= H->block_min_restarts &&
            can_block(H, q) && bits_lds_for(H, q) > 0;
 }
 
-// Compute the left-out start energies (all lane-started replicas; the others
-// have not moved since their start, so theirs are recomputed unchanged).
+bool defer_unit_energy(const sg_ctx* H)
+{
+    if (!H->defer_energy || H->h_esegs.empty()) return false;
+    int64_t queue_items = 0;
+    for (const HostInst& q : H->insts)
+        if (!q.lat_ok && can_queue(q) && !(q.R >= H->block_min_restarts && can_block(H, q))) queue_items += q.R;
+    for (const HostInst& q : H->insts) {
+        if (q.dense || (H->lanes_on && lane_start_candidate(q))) continue;
+        const bool queue = !q.lat_ok && !(q.R >= H->block_min_restarts && can_block(H, q)) && can_queue(q) &&
+                           queue_items >= H->queue_min_items;
+        if (!queue) return false;
+    }
+    return true;
+}
+
+// The run writes the final energies of a deferred instance itself.
+bool run_writes_energy(const sg_ctx* H, const sg_run_params* p, int kind, int sched, const HostInst& q)
+{
+    if (kind == 1) return sched == SG_SCHED_BLOCK && bits_path(H, p, q);
+    return sched == SG_SCHED_QUEUE && p->until_converged && p->max_sweeps > 0;
+}
+
+// Compute the energies of the current spins of every replica started by the
+// unit and lane kernels (those not left out are recomputed unchanged: this
+// runs only while no sweep has moved them since their start, or right after
+// the run whose final energies it replaces).
 sg_status ensure_energy(sg_handle H)
 {
     if (!H->e_pending) return SG_OK;
-    SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
-                                  (int)H->h_litems.size(), H->lane_nmax, false, H->reps(), nullptr, 0, H->stream),
-           "lane energy kernel");
+    if (!H->h_eunits.empty())
+        SG_HIP(sg::launch_start_units(H->at<sg::InstTab>(H->off_tab), nullptr, 0, H->at<sg::StartUnit>(H->off_eunits),
+                                      (int64_t)H->h_eunits.size(), H->at<sg::EnergySeg>(H->off_esegs),
+                                      (int64_t)H->h_esegs.size(), H->at<int64_t>(H->off_eparts), H->reps(), nullptr, 0,
+                                      false, H->stream),
+               "energy kernel");
+    if (!H->h_litems.empty())
+        SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
+                                      (int)H->h_litems.size(), H->lane_nmax, false, H->reps(), nullptr, 0, H->stream),
+               "lane energy kernel");
     H->e_pending = false;
     return SG_OK;
 }
@@ -1832,19 +1866,27 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
         std::fill(H->started.begin(), H->started.end(), 1);
         return SG_OK;
     }
+    H->e_pending = false;
+    H->e_deferred.assign(H->insts.size(), 0);
+    const bool defer_units = defer_unit_energy(H);
+    if (defer_units) {
+        for (size_t k = 0; k < H->insts.size(); ++k) {
+            const HostInst& q = H->insts[k];
+            if (!q.dense && !(H->lanes_on && lane_start_candidate(q))) H->e_deferred[k] = 2;
+        }
+        H->e_pending = true;
+    }
     if (!H->h_sunits.empty())
         SG_HIP(sg::launch_start_units(H->at<sg::InstTab>(H->off_tab), H->at<sg::StartUnit>(H->off_sunits),
                                       (int64_t)H->h_sunits.size(), H->at<sg::StartUnit>(H->off_eunits),
-                                      (int64_t)H->h_eunits.size(), H->at<sg::EnergySeg>(H->off_esegs),
-                                      (int64_t)H->h_esegs.size(), H->at<int64_t>(H->off_eparts), H->reps(), nullptr,
-                                      seed, true, st),
+                                      defer_units ? 0 : (int64_t)H->h_eunits.size(),
+                                      H->at<sg::EnergySeg>(H->off_esegs), defer_units ? 0 : (int64_t)H->h_esegs.size(),
+                                      H->at<int64_t>(H->off_eparts), H->reps(), nullptr, seed, true, st),
                "start kernels");
-    H->e_pending = false;
-    H->e_deferred.assign(H->insts.size(), 0);
     if (!H->h_litems.empty()) {
         bool changed = false;
         for (sg::BlockItem& it : H->h_litems) {
-            const int32_t d = defer_start_energy(H, H->insts[(size_t)it.inst]) ? 1 : 0;
+            const int32_t d = defer_lane_energy(H, H->insts[(size_t)it.inst]) ? 1 : 0;
             H->e_deferred[(size_t)it.inst] = (uint8_t)d;
             H->e_pending = H->e_pending || d;
             changed = changed || it.pad != d;
@@ -1919,10 +1961,10 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     if (sched < 0 && p->schedule != SG_SCHED_AUTO)
         return fail(SG_EINVAL, "schedule %d is not available for this handle (rule %d, until_converged %d)",
                     p->schedule, p->rule, p->until_converged);
-    // left-out start energies are written by the bit-sliced kernel; any other
-    // kernel continues from them, so they are computed first
+    // left-out start energies are written by the bit-sliced or the queue
+    // kernel; any other kernel continues from them, so they are computed first
     for (size_t k = 0; H->e_pending && k < assign.size(); ++k)
-        if (H->e_deferred[k] && !(assign[k] == SG_SCHED_BLOCK && bits_path(H, p, H->insts[k])))
+        if (H->e_deferred[k] && !run_writes_energy(H, p, H->e_deferred[k], assign[k], H->insts[k]))
             if ((e = ensure_energy(H)) != SG_OK) return e;
     hipStream_t st = H->stream;
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
@@ -1943,11 +1985,21 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
         }
         if (e != SG_OK) return e;
     }
-    H->e_pending = false;
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
     sg::CallStats cs;
     SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
+    if (H->e_pending) {
+        // the queue kernel wrote the energies of the replicas that converged;
+        // if any did not, all are computed from their final spins
+        bool queue_deferred = false;
+        for (uint8_t d : H->e_deferred) queue_deferred = queue_deferred || d == 2;
+        if (queue_deferred && cs.unconverged) {
+            if ((e = ensure_energy(H)) != SG_OK) return e;
+            SG_HIP(hipStreamSynchronize(st), "stream sync");
+        }
+        H->e_pending = false;
+    }
     float ms = 0.f;
     SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
     H->hot_us = 0.0;

@@ -6,6 +6,9 @@
 // Each replica runs to its own stopping point, and the replica state and the
 // call totals follow the per-phase kernels exactly: with until_converged a
 // replica stops after its first sweep without a flip (that sweep counts).
+// A sweep without a flip evaluates every spin on the final configuration, so
+// its fields also give the replica's exact energy, which is then stored
+// instead of the running sum (the start energy is not needed for it).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -59,10 +62,14 @@ __device__ __forceinline__ void queue_load(const InstDev& I, const Slice& S, int
     L.h = row ? (int)I.h[S.row0 + lane] : 0;
 }
 
+// Energy from one sweep's fields: with f1 = h_i + (coupling part) and f the
+// whole field, sum_i s_i (3 h_i + f1_i + 2 f_i) = 6 (sum h s + sum_{i<j} J s s
+// + sum K s s s) = -6 E, each pair counted twice and each triple three times
+// in the fields (Sec. II eq. (1), Sec. VI eq. (5)).
 template <bool TIE>
 __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, const SliceWords& L,
                                            int8_t* __restrict__ sp, int lane, uint32_t sweep, uint64_t seed,
-                                           uint32_t r, long long& dE, int& my)
+                                           uint32_t r, long long& dE, int& my, long long& e6)
 {
     if (lane >= S.rows) return;
     const int i = S.row0 + lane;
@@ -77,6 +84,7 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
             f += bat_j(w1) * sp[w1 >> 8];
         }
     }
+    const int f1 = f;
     if (I.has_tri) {
 #pragma unroll
         for (int q = 0; q < kPreT; ++q)
@@ -91,6 +99,7 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
         }
     }
     const int si = sp[i];
+    e6 += si * (3 * L.h + f1 + 2 * f);
     const int d = 2 * si * f;
     bool flip = d < 0;
     if (TIE && d == 0) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
@@ -104,22 +113,24 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
 template <bool TIE>
 __device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __restrict__ slices, int s_lo, int s_hi,
                                             int8_t* __restrict__ sp, int w, int nw, int lane, uint32_t sweep,
-                                            uint64_t seed, uint32_t r, long long& dE, int& my)
+                                            uint64_t seed, uint32_t r, long long& dE, int& my, long long& e6)
 {
     for (int sl = s_lo + w; sl < s_hi; sl += nw) {
         const Slice S = slices[sl];
         SliceWords cur;
         queue_load(I, S, lane, cur);
-        queue_eval<TIE>(I, S, cur, sp, lane, sweep, seed, r, dE, my);
+        queue_eval<TIE>(I, S, cur, sp, lane, sweep, seed, r, dE, my, e6);
     }
 }
 
-__device__ __forceinline__ void queue_finish(const InstTab& Q, int r, long long dE, int nflip, int performed,
-                                             int lastflip, int T, int until_conv, RepState* __restrict__ rs,
-                                             CallStats* __restrict__ cs)
+// e6: -6 E of the last sweep's fields, exact when that sweep flipped nothing.
+__device__ __forceinline__ void queue_finish(const InstTab& Q, int r, long long dE, long long e6, int nflip,
+                                             int performed, int lastflip, int T, int until_conv,
+                                             RepState* __restrict__ rs, CallStats* __restrict__ cs)
 {
     RepState* st = rs + Q.rep_base + r;
-    st->E += dE;
+    if (performed > 0 && lastflip < performed) st->E = -e6 / 6;
+    else st->E += dE;
     st->flips += nflip;
     st->sweeps += performed;
     st->lastflip = lastflip;
@@ -161,13 +172,14 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
         for (int k = tid; k < I.n; k += kBatThreads) lds[k] = gsp[k];
         if (tid == 0) s_flips = 0;
         __syncthreads();
-        long long dE = 0;
+        long long dE = 0, e6 = 0;
         int nflip = 0, performed = 0, lastflip = 0;
         for (int t = 0; t < T; ++t) {
             int my = 0;
+            e6 = 0;
             for (int c = 0; c < Q.C; ++c) {
                 queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], lds, wave, kBatWaves,
-                                 lane, base + t, seed, (uint32_t)it.r, dE, my);
+                                 lane, base + t, seed, (uint32_t)it.r, dE, my, e6);
                 __syncthreads();
             }
             nflip += my;
@@ -184,29 +196,32 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
             if (until_conv && tot == 0) break;
         }
         for (int k = tid; k < I.n; k += kBatThreads) gsp[k] = lds[k];
-        // fold the workgroup's dE and flips
-        long long wd = dE;
+        // fold the workgroup's dE, energy sum and flips
+        long long wd = dE, we = e6;
         int wf = nflip;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             wd += __shfl_xor(wd, off, 64);
+            we += __shfl_xor(we, off, 64);
             wf += __shfl_xor(wf, off, 64);
         }
-        __shared__ long long pd[kBatWaves];
+        __shared__ long long pd[kBatWaves], pe[kBatWaves];
         __shared__ int pf[kBatWaves];
         if (lane == 0) {
             pd[wave] = wd;
+            pe[wave] = we;
             pf[wave] = wf;
         }
         __syncthreads();
         if (tid == 0) {
-            long long a = 0;
+            long long a = 0, e = 0;
             int b = 0;
             for (int w = 0; w < kBatWaves; ++w) {
                 a += pd[w];
+                e += pe[w];
                 b += pf[w];
             }
-            queue_finish(Q, it.r, a, b, performed, lastflip, T, until_conv, rs, cs);
+            queue_finish(Q, it.r, a, e, b, performed, lastflip, T, until_conv, rs, cs);
         }
         __syncthreads();
     }
@@ -231,13 +246,14 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                long long dE = 0;
+                long long dE = 0, e6 = 0;
                 int nflip = 0, performed = 0, lastflip = 0;
                 for (int t = 0; t < T; ++t) {
                     int my = 0;
+                    e6 = 0;
                     for (int c = 0; c < Q.C; ++c) {
                         queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], wl, 0, 1, lane,
-                                         base + t, seed, (uint32_t)it.r, dE, my);
+                                         base + t, seed, (uint32_t)it.r, dE, my, e6);
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -251,14 +267,15 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
                     if (until_conv && tot == 0) break;
                 }
                 for (int k = lane; k < I.n; k += 64) gsp[k] = wl[k];
-                long long wd = dE;
+                long long wd = dE, we = e6;
                 int wf = nflip;
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) {
                     wd += __shfl_xor(wd, off, 64);
+                    we += __shfl_xor(we, off, 64);
                     wf += __shfl_xor(wf, off, 64);
                 }
-                if (lane == 0) queue_finish(Q, it.r, wd, wf, performed, lastflip, T, until_conv, rs, cs);
+                if (lane == 0) queue_finish(Q, it.r, wd, we, wf, performed, lastflip, T, until_conv, rs, cs);
             }
         }
         __syncthreads();

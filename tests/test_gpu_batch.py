@@ -111,6 +111,35 @@ def test_deferred_start_energy(gpu):
         assert np.array_equal(h.energy(), h.energy(recompute=True))
 
 
+def test_deferred_start_energy_queue(gpu):
+    """Start energies left out for a batch bound for the queue schedule: the
+    queue kernel stores each converged replica's exact energy from its last
+    sweep (which flips nothing), and any other ending computes them from the
+    final spins.  Equal to the oracle's in every case: read right after the
+    start, converged runs under both rules, runs that stop on the sweep cap
+    with and without until_converged; the same with the deferral off."""
+    import paper_0912_3912_amd as sg
+    insts = [i for i in gen.cfg4_uneven_batch(count=48, seed=13) if i.n <= 20000]
+    assert len(insts) >= 32
+    seed = 4
+    start = [oracle_run(i, seed, GREEDY, 0, False) for i in insts]
+
+    def handle(defer):
+        h = sg.load_instance(insts).tune("defer_energy", defer).bind()
+        h.init_spins(seed)
+        assert h.query("energy_pending") == defer
+        return h
+
+    for defer in (1, 0):
+        log(f"deferred start energy, queue: defer={defer}")
+        compare(handle(defer), insts, start)
+        for rule, sweeps, uc in ((GREEDY, 10000, True), (TIE, 30, True), (GREEDY, 2, True), (GREEDY, 3, False)):
+            h = handle(defer)
+            st = h.run_sweeps(seed=seed, rule=rule, max_sweeps=sweeps, until_converged=uc, schedule=SCHED_AUTO)
+            assert st["schedule_used"] == SCHED_QUEUE and h.query("energy_pending") == 0
+            compare(h, insts, [oracle_run(i, seed, rule, sweeps, uc, threads=8) for i in insts])
+
+
 @pytest.mark.parametrize("ng", [2, 4, 8, 16])
 def test_block_bits_groups(gpu, ng):
     """The bit-sliced GREEDY block kernel with at most 2, 4, 8 and 16 groups
