@@ -156,7 +156,8 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
     const int tzm = (tc[2] + tg.P[2] - 1) % tg.P[2], tzp = (tc[2] + 1) % tg.P[2];
     const int Xzm = tstart(2, tzm + 1) - tstart(2, tzm);
     auto plane = [&](int pl, int c) -> uint32_t* { return lds32 + (pl * 2 + c) * rows; };
-    uint32_t* tieq = lds32 + NPL * 2 * rows;
+    // tie queue entries: (box row | z << 16 | interior << 22, global row index)
+    uint2* tieq = reinterpret_cast<uint2*>(lds32 + NPL * 2 * rows);
     __shared__ uint32_t mag_ay[64];
     int8_t* cs = canon + (int64_t)r * stride;
     const int rows_per_tile = ((L0 + tg.P[0] - 1) / tg.P[0]) * ((L1 + tg.P[1] - 1) / tg.P[1]);
@@ -298,25 +299,34 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                     const int cnt = __popc(Tm);
                     if (__ballot(cnt != 0)) {
                         // exclusive prefix sum of the lanes' tie counts from one
-                        // ballot per bit of the count
+                        // ballot per bit of the count (two bits unless some lane
+                        // has more than three ties)
                         int below = 0, total = 0;
-#pragma unroll
-                        for (int b = 0; b < 6; ++b) {
+                        auto count_bit = [&](int b) {
                             const uint64_t m = __ballot((cnt >> b) & 1);
                             below += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))
                                      << b;
                             total += __popcll(m) << b;
+                        };
+                        count_bit(0);
+                        count_bit(1);
+                        if (__ballot(cnt > 3)) {
+#pragma unroll
+                            for (int b = 2; b < 6; ++b) count_bit(b);
                         }
-                        uint32_t* seg = tieq + wave * kWaveTieCap;
+                        uint2* seg = tieq + wave * kWaveTieCap;
+                        const uint32_t gxy = (uint32_t)(wrapi(o[0] + x, L0) * L1 + wrapi(o[1] + y, L1));
                         for (int rb = 0; rb < total; rb += kWaveTieCap) {
-                            int slot = below;
+                            int slot = below - rb;
                             uint32_t t2 = Tm;
                             while (t2) {
                                 const int j = __ffs(t2) - 1;
                                 t2 &= t2 - 1;
-                                if (slot >= rb && slot < rb + kWaveTieCap)
-                                    seg[slot - rb] = (uint32_t)row | ((uint32_t)j << 16) | (((I >> j) & 1u) << 21);
+                                if ((unsigned)slot < (unsigned)kWaveTieCap)
+                                    seg[slot] = make_uint2((uint32_t)row | ((uint32_t)(2 * j + zo) << 16) |
+                                                               (((I >> j) & 1u) << 22),
+                                                           gxy);
                                 ++slot;
                             }
                             // LDS operations of one wavefront complete in order: keep
@@ -325,32 +335,16 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                             __builtin_amdgcn_wave_barrier();
                             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                             const int nt = min(total - rb, kWaveTieCap);
-                            if (lane < nt) {
-                                const uint32_t en = seg[lane];
-                                const int trow = (int)(en & 0xFFFFu);
-                                const int j = (int)((en >> 16) & 31u);
-                                const int tx = (int)fdiv((uint32_t)trow, mB1);
-                                const int ty = trow - tx * B[1];
-                                const int tzo = (c - par0 - tx - ty) & 1;
-                                if (rng_bit(seed, (uint32_t)gsite(tx, ty, 2 * j + tzo), sweep, Lt.instance_id,
-                                            (uint32_t)r)) {
-                                    atomicXor(Sc + trow, 1u << j);
-                                    nflip += (int)((en >> 21) & 1u);
+                            auto draw = [&](const uint2 en) {
+                                const int tz = (int)((en.x >> 16) & 63u);
+                                const uint32_t site = en.y * (uint32_t)L2 + (uint32_t)wrapi(o[2] + tz, L2);
+                                if (rng_bit(seed, site, sweep, Lt.instance_id, (uint32_t)r)) {
+                                    atomicXor(Sc + (en.x & 0xFFFFu), 1u << (tz >> 1));
+                                    nflip += (int)(en.x >> 22);
                                 }
-                            }
-                            if (lane + 64 < nt) {
-                                const uint32_t en = seg[lane + 64];
-                                const int trow = (int)(en & 0xFFFFu);
-                                const int j = (int)((en >> 16) & 31u);
-                                const int tx = (int)fdiv((uint32_t)trow, mB1);
-                                const int ty = trow - tx * B[1];
-                                const int tzo = (c - par0 - tx - ty) & 1;
-                                if (rng_bit(seed, (uint32_t)gsite(tx, ty, 2 * j + tzo), sweep, Lt.instance_id,
-                                            (uint32_t)r)) {
-                                    atomicXor(Sc + trow, 1u << j);
-                                    nflip += (int)((en >> 21) & 1u);
-                                }
-                            }
+                            };
+                            if (lane < nt) draw(seg[lane]);
+                            if (lane + 64 < nt) draw(seg[lane + 64]);
                             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                             __builtin_amdgcn_wave_barrier();
                             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -484,7 +478,7 @@ size_t lattice_msc_lds(const TileGeom& tg, const int L[3], int D)
 {
     int B[3];
     msc_box(tg, L, D, B);
-    return (size_t)msc_planes(D) * 2 * B[0] * B[1] * 4 + (size_t)kMscWaves * kWaveTieCap * 4;
+    return (size_t)msc_planes(D) * 2 * B[0] * B[1] * 4 + (size_t)kMscWaves * kWaveTieCap * 8;
 }
 
 bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D)
