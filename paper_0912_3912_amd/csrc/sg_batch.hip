@@ -431,32 +431,40 @@ __global__ __launch_bounds__(256) void k_start_lanes(const InstTab* __restrict__
             bits[w * 64 + lane] = word;
         }
     }
-    // a drawn start: spins by the start rule, stored as bytes four at a time
+    // a drawn start: spins by the start rule, 32 bytes per word in two 16-byte
+    // stores (bytes past n, inside the row's padding, hold +1)
     for (int w = 0; INIT && w < W; ++w) {
         uint32_t word = 0;
+        uint32_t qv[8];
+#pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int i0 = w * 32 + 4 * q;
-            if (i0 >= n) break;
-            uint32_t quad = 0;
+            uint32_t quad = 0x01010101u;
             if (i0 + 4 <= n) {
                 // four counters read together, then four independent draws
                 uint32_t e[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) e[b] = ext[i0 + b];
+                quad = 0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int neg = rng_bit(seed, e[b], 0xFFFFFFFFu, iid, (uint32_t)r);
                     word |= (uint32_t)neg << (4 * q + b);
                     quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
                 }
-            } else {
+            } else if (i0 < n) {
                 for (int b = 0; i0 + b < n; ++b) {
                     const int neg = rng_bit(seed, ext[i0 + b], 0xFFFFFFFFu, iid, (uint32_t)r);
                     word |= (uint32_t)neg << (4 * q + b);
-                    quad |= (neg ? 0xFFu : 0x01u) << (8 * b);
+                    if (neg) quad ^= 0xFEu << (8 * b);
                 }
             }
-            if (mine) *reinterpret_cast<uint32_t*>(sp + i0) = quad;
+            qv[q] = quad;
+        }
+        if (mine) {
+            uint4* dst = reinterpret_cast<uint4*>(sp + w * 32);
+            dst[0] = make_uint4(qv[0], qv[1], qv[2], qv[3]);
+            dst[1] = make_uint4(qv[4], qv[5], qv[6], qv[7]);
         }
         bits[w * 64 + lane] = word;
     }
