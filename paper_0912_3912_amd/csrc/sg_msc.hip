@@ -155,9 +155,13 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
     auto tstart = [&](int a, int t) -> int { return (int)((int64_t)t * Lt.L[a] / tg.P[a]); };
     const int tzm = (tc[2] + tg.P[2] - 1) % tg.P[2], tzp = (tc[2] + 1) % tg.P[2];
     const int Xzm = tstart(2, tzm + 1) - tstart(2, tzm);
-    auto plane = [&](int pl, int c) -> uint32_t* { return lds32 + (pl * 2 + c) * rows; };
+    // box row layout: RS words per row, word 2 * plane + colour; RS is odd, so
+    // lanes on consecutive rows read distinct banks, and a row's words sit at
+    // constant offsets from one address
+    constexpr int RS = 2 * NPL + 1;
+    auto pw = [&](int pl, int c, int row) -> uint32_t& { return lds32[row * RS + 2 * pl + c]; };
     // tie queue entries: (box row | z << 16 | interior << 22, global row index)
-    uint2* tieq = reinterpret_cast<uint2*>(lds32 + NPL * 2 * rows);
+    uint2* tieq = reinterpret_cast<uint2*>(lds32 + ((RS * rows + 1) & ~1));
     __shared__ uint32_t mag_ay[64];
     int8_t* cs = canon + (int64_t)r * stride;
     const int rows_per_tile = ((L0 + tg.P[0] - 1) / tg.P[0]) * ((L1 + tg.P[1] - 1) / tg.P[1]);
@@ -195,8 +199,8 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
 #pragma unroll
             for (int pl = 1; pl < 7; ++pl)
                 if (lane == pl) v = m[pl];
-            plane(lane, pr)[row] = even32(v);
-            plane(lane, pr ^ 1)[row] = even32(v >> 1);
+            pw(lane, pr, row) = even32(v);
+            pw(lane, pr ^ 1, row) = even32(v >> 1);
         }
     }
     __syncthreads();
@@ -222,17 +226,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             const uint32_t zm1 = bit_range((q + 1) >> 1, (B[2] - 3 - q) >> 1);
             const uint32_t im0 = bit_range((hk[2] + 1) >> 1, (hk[2] + X[2] - 1) >> 1);
             const uint32_t im1 = bit_range(hk[2] >> 1, (hk[2] + X[2] - 2) >> 1);
-            uint32_t* Sc = plane(kPlS, c);
-            const uint32_t* So = plane(kPlS, c ^ 1);
-            const uint32_t* JYc = plane(kPlJY, c);
-            const uint32_t* JYo = plane(kPlJY, c ^ 1);
-            const uint32_t* JZc = plane(kPlJZ, c);
-            const uint32_t* JZo = plane(kPlJZ, c ^ 1);
-            const uint32_t* JXc = plane(kPlJX, c);
-            const uint32_t* JXo = plane(kPlJX, c ^ 1);
-            const uint32_t* HPc = plane(kPlHP, c);
-            const uint32_t* HNc = plane(kPlHN, c);
-            const uint32_t* HAc = plane(kPlHA, c);
+            uint32_t* const Sc = lds32 + c;  // colour-c spin word of box row t: Sc[t * RS]
             // wave-uniform trip count: the tie queue is reserved once per wavefront
             for (int i0 = wave * 64; i0 < nact; i0 += kMscThreads) {
                 const int i = i0 + lane;
@@ -242,21 +236,24 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                 const int x = xlo + qq, y = ylo + ii - qq * ay;
                 const int row = x * B[1] + y;
                 const int zo = (c - par0 - x - y) & 1;
-                const uint32_t s = Sc[row];
-                const uint32_t on = So[row];
-                const uint32_t jzo = JZo[row];
+                // this row's words of colour c and of the other colour
+                uint32_t* const wc = lds32 + row * RS + c;
+                const uint32_t* const wo = lds32 + row * RS + (c ^ 1);
+                const uint32_t s = wc[2 * kPlS];
+                const uint32_t on = wo[2 * kPlS];
+                const uint32_t jzo = wo[2 * kPlJZ];
                 const uint32_t szp = zo ? (on >> 1) : on;
                 const uint32_t szm = zo ? on : (on << 1);
                 const uint32_t jzm = zo ? jzo : (jzo << 1);
-                const uint32_t a0 = s ^ So[row + 1] ^ JYc[row];
-                const uint32_t a1 = s ^ So[row - 1] ^ JYo[row - 1];
-                const uint32_t a2 = s ^ szp ^ JZc[row];
+                const uint32_t a0 = s ^ wo[RS + 2 * kPlS] ^ wc[2 * kPlJY];
+                const uint32_t a1 = s ^ wo[2 * kPlS - RS] ^ wo[2 * kPlJY - RS];
+                const uint32_t a2 = s ^ szp ^ wc[2 * kPlJZ];
                 const uint32_t a3 = s ^ szm ^ jzm;
                 uint32_t u0, u1, u2;
                 if constexpr (D == 3) {
-                    const int BY = B[1];
-                    const uint32_t a4 = s ^ So[row + BY] ^ JXc[row];
-                    const uint32_t a5 = s ^ So[row - BY] ^ JXo[row - BY];
+                    const int BR = B[1] * RS;
+                    const uint32_t a4 = s ^ wo[BR + 2 * kPlS] ^ wc[2 * kPlJX];
+                    const uint32_t a5 = s ^ wo[2 * kPlS - BR] ^ wo[2 * kPlJX - BR];
                     uint32_t s1, c1, s2, c2;
                     fadd(a0, a1, a2, s1, c1);
                     fadd(a3, a4, a5, s2, c2);
@@ -270,7 +267,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                     u1 = c1 ^ k0;
                     u2 = c1 & k0;
                 }
-                const uint32_t hp = HPc[row], hn = HNc[row], ha = HAc[row];
+                const uint32_t hp = wc[2 * kPlHP], hn = wc[2 * kPlHN], ha = wc[2 * kPlHA];
                 const uint32_t gpos = (hp & ~s) | (hn & s);
                 const uint32_t gneg = (hn & ~s) | (hp & s);
                 const uint32_t gtwo = gpos & ha;  // g == +2
@@ -295,7 +292,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                     const uint32_t tie = ~odd & ((gneg & u_eq<T0 - 2>(u0, u1, u2)) | (gtwo & u_eq<T0>(u0, u1, u2)) |
                                                  (gmid & u_eq<T0 - 1>(u0, u1, u2)));
                     const uint32_t Tm = tie & M;
-                    if (ns != s) Sc[row] = ns;
+                    if (ns != s) wc[2 * kPlS] = ns;
                     const int cnt = __popc(Tm);
                     if (__ballot(cnt != 0)) {
                         // exclusive prefix sum of the lanes' tie counts from one
@@ -339,7 +336,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                                 const int tz = (int)((en.x >> 16) & 63u);
                                 const uint32_t site = en.y * (uint32_t)L2 + (uint32_t)wrapi(o[2] + tz, L2);
                                 if (rng_bit(seed, site, sweep, Lt.instance_id, (uint32_t)r)) {
-                                    atomicXor(Sc + (en.x & 0xFFFFu), 1u << (tz >> 1));
+                                    atomicXor(Sc + (en.x & 0xFFFFu) * RS, 1u << (tz >> 1));
                                     nflip += (int)(en.x >> 22);
                                 }
                             };
@@ -351,7 +348,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                         }
                     }
                 } else {
-                    if (ns != s) Sc[row] = ns;
+                    if (ns != s) wc[2 * kPlS] = ns;
                 }
             }
             __syncthreads();
@@ -371,7 +368,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             const int bx = x + hk[0], by = y + hk[1];
             const int brow = bx * B[1] + by;
             const int pr = (par0 + bx + by) & 1;
-            const uint64_t v = spread32(plane(kPlS, pr)[brow]) | (spread32(plane(kPlS, pr ^ 1)[brow]) << 1);
+            const uint64_t v = spread32(pw(kPlS, pr, brow)) | (spread32(pw(kPlS, pr ^ 1, brow)) << 1);
             const uint32_t w = (uint32_t)(v >> hk[2]) & low_bits(X[2]);
             __hip_atomic_store(gw + (int64_t)tile * rows_per_tile + row, tag | w, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -417,8 +414,8 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             const uint64_t v = (uint64_t)((wl >> (Xzm - hk[2])) & low_bits(hk[2])) | ((uint64_t)wm << hk[2]) |
                                ((uint64_t)(wh & low_bits(hk[2])) << (hk[2] + X[2]));
             const int pr = (par0 + x + y) & 1;
-            plane(kPlS, pr)[row] = even32(v);
-            plane(kPlS, pr ^ 1)[row] = even32(v >> 1);
+            pw(kPlS, pr, row) = even32(v);
+            pw(kPlS, pr ^ 1, row) = even32(v >> 1);
         }
         failed = __syncthreads_or(failed);
         if (failed) break;
@@ -434,7 +431,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             if (z < X[2]) {
                 const int zb = hk[2] + z;
                 const int c = (par0 + bx + by + zb) & 1;
-                const uint32_t bit = (plane(kPlS, c)[brow] >> (zb >> 1)) & 1u;
+                const uint32_t bit = (pw(kPlS, c, brow) >> (zb >> 1)) & 1u;
                 const int g = gsite(bx, by, zb);
                 cs[c * half + (g >> 1)] = (int8_t)(bit ? -1 : 1);
             }
@@ -478,7 +475,8 @@ size_t lattice_msc_lds(const TileGeom& tg, const int L[3], int D)
 {
     int B[3];
     msc_box(tg, L, D, B);
-    return (size_t)msc_planes(D) * 2 * B[0] * B[1] * 4 + (size_t)kMscWaves * kWaveTieCap * 8;
+    const size_t words = ((size_t)(2 * msc_planes(D) + 1) * B[0] * B[1] + 1) & ~(size_t)1;
+    return words * 4 + (size_t)kMscWaves * kWaveTieCap * 8;
 }
 
 bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D)
