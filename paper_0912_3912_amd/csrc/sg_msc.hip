@@ -43,6 +43,7 @@ namespace sg {
 
 constexpr int kMscThreads = 1024;
 constexpr int kMscWaves = kMscThreads / 64;
+constexpr int kExRows = 4;  // box rows per thread in the exchange (rows <= kExRows * kMscThreads)
 constexpr int kWaveTieCap = 128;  // tie entries per wavefront segment (more are drawn in further rounds)
 
 // plane indices (the +x plane exists for 3-D lattices only)
@@ -202,6 +203,27 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             pw(lane, pr, row) = even32(v);
             pw(lane, pr ^ 1, row) = even32(v >> 1);
         }
+    }
+    // where each of this thread's box rows (tid + kMscThreads * m) is read
+    // from in the exchange buffers: the owning tile's first word plus the
+    // row's index inside that tile (the same in every epoch, so the divisions
+    // are done once per launch)
+    int32_t exoff[kExRows];
+#pragma unroll
+    for (int m = 0; m < kExRows; ++m) {
+        const int row = tid + m * kMscThreads;
+        exoff[m] = 0;
+        if (row >= rows) continue;
+        const int x = (int)fdiv((uint32_t)row, mB1);
+        const int y = row - x * B[1];
+        const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
+        const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
+        const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
+        const int sx = tstart(0, tx), sy = tstart(1, ty);
+        const int X1t = tstart(1, ty + 1) - sy;
+        const int wrow = (gx - sx) * X1t + (gy - sy);
+        const int tb = (tx * tg.P[1] + ty) * tg.P[2];
+        exoff[m] = tb * rows_per_tile + wrow;
     }
     __syncthreads();
 
@@ -378,19 +400,16 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
         // then every neighbour has finished reading its box from the spin
         // array before this tile writes its interior back.
         const bool last = (e + 1) * k >= P_total;
-        for (int row = tid; row < rows && !failed; row += kMscThreads) {
+#pragma unroll
+        for (int m = 0; m < kExRows; ++m) {
+            const int row = tid + m * kMscThreads;
+            if (row >= rows || failed) continue;
             const int x = (int)fdiv((uint32_t)row, mB1);
             const int y = row - x * B[1];
-            const int gx = wrapi(o[0] + x, L0), gy = wrapi(o[1] + y, L1);
-            const int tx = (int)(((int64_t)(gx + 1) * tg.P[0] - 1) / L0);
-            const int ty = (int)(((int64_t)(gy + 1) * tg.P[1] - 1) / L1);
-            const int sx = tstart(0, tx), sy = tstart(1, ty);
-            const int X1t = tstart(1, ty + 1) - sy;
-            const int wrow = (gx - sx) * X1t + (gy - sy);
-            const int tb = (tx * tg.P[1] + ty) * tg.P[2];
-            uint64_t* al = gw + (int64_t)(tb + tzm) * rows_per_tile + wrow;
-            uint64_t* ah = gw + (int64_t)(tb + tzp) * rows_per_tile + wrow;
-            uint64_t* am = gw + (int64_t)(tb + tc[2]) * rows_per_tile + wrow;
+            uint64_t* const src = gw + exoff[m];
+            uint64_t* al = src + (int64_t)tzm * rows_per_tile;
+            uint64_t* ah = src + (int64_t)tzp * rows_per_tile;
+            uint64_t* am = src + (int64_t)tc[2] * rows_per_tile;
             uint64_t pl = __hip_atomic_load(al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint64_t ph = __hip_atomic_load(ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint64_t pm = __hip_atomic_load(am, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -487,6 +506,7 @@ bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D)
     if (B[2] > 64) return false;                           // a box z-row is two 32-bit colour words
     if ((L[2] + tg.P[2] - 1) / tg.P[2] > 32) return false;  // an interior z-row is one exchange word
     if ((int64_t)B[0] * B[1] > 65535) return false;        // tie queue entries hold the row in 16 bits
+    if ((int64_t)B[0] * B[1] > kExRows * kMscThreads) return false;  // exchange offsets held in registers
     for (int a = (D == 2 ? 1 : 0); a < 3; ++a)
         if (L[a] / tg.P[a] < tg.k) return false;           // the halo stays within the 26 neighbour tiles
     return true;
