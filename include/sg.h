@@ -253,7 +253,9 @@ sg_status sg_instance_info_get(sg_handle h, int32_t inst, sg_instance_info* info
 sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
 
 /* Draw the random start of every replica (Sec. IV: uniform), compute its
- * energy, reset sweeps, flips and converged.  Errors: SG_ESTATE before bind. */
+ * energy (or leave it to the run that follows, see the "defer_energy" knob
+ * of sg_tune), reset sweeps, flips and converged.  Errors: SG_ESTATE before
+ * bind. */
 sg_status sg_init_spins(sg_handle h, uint64_t seed);
 
 /* Set replica r of instance inst to host spins s (n int8 values, each +1 or
