@@ -1719,6 +1719,8 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
     H->stream = (hipStream_t)hip_stream;
     H->bound = false;
     std::fill(H->started.begin(), H->started.end(), 0);
+    H->e_pending = false;
+    H->e_deferred.assign(H->insts.size(), 0);
     hipStream_t st = H->stream;
     for (const HostInst& q : H->insts) {
         SG_HIP(hipMemcpyAsync(H->dev + q.off_nbr, q.nbr.data(), q.nbr.size() * 4, hipMemcpyHostToDevice, st),
