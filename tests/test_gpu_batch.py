@@ -110,6 +110,24 @@ def test_deferred_start_energy(gpu):
         h.run_sweeps(seed=seed, rule=sg.FM, max_sweeps=2, until_converged=False)
         assert np.array_equal(h.energy(), h.energy(recompute=True))
 
+        # the byte block kernel after all (knob changed between start and run)
+        h = handle(defer)
+        h.tune("block_bits", 0)
+        h.run_sweeps(seed=seed, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=SCHED_AUTO)
+        assert h.query("last_bits") == 0
+        compare(h, insts, [oracle_run(i, seed, GREEDY, 10000, True, threads=8) for i in insts])
+
+        # binding again drops the replica state, left-out energies included
+        h = handle(defer)
+        h.bind()
+        assert h.query("energy_pending") == 0
+
+        # a second start with another seed replaces the first
+        h = handle(defer)
+        h.init_spins(seed + 1)
+        h.run_sweeps(seed=seed + 1, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=SCHED_AUTO)
+        compare(h, insts, [oracle_run(i, seed + 1, GREEDY, 10000, True, threads=8) for i in insts])
+
 
 def test_deferred_start_energy_queue(gpu):
     """Start energies left out for a batch bound for the queue schedule: the
