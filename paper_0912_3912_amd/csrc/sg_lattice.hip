@@ -60,6 +60,9 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
     const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
     const int tile = blockIdx.x % ntiles;
     const int r = blockIdx.x / ntiles;
+    // a replica frozen by an earlier call is not swept; all its tiles leave
+    // together, and no other replica waits on them (exchanges are per replica)
+    if (rs[r].converged) return;
     const int tid = threadIdx.x;
     const int L0 = Lt.L[0], L1 = Lt.L[1], L2 = Lt.L[2];
     const int n = Lt.n, half = n / 2;

@@ -108,6 +108,31 @@ def test_tile_mode_resume(gpu, kernel):
     _run([inst], [(16, 16, 16)], 4, TIE, 0, False, tune=_tile_tune(kernel, 4), runs=[3, 5, 1, 0, 6])
 
 
+@pytest.mark.parametrize("kernel", ["byte", "msc"])
+def test_tile_mode_skips_frozen_replicas(gpu, kernel):
+    """Replicas that converged in an earlier call stay frozen: a later
+    fixed-sweep GREEDY_TIE call on the tile schedule (which would flip their
+    ties) leaves them as they are, as the oracle does."""
+    import paper_0912_3912_amd as sg
+    inst = gen.lattice((16, 12, 24), seed=8, h_range=(-2, 2), restarts=6, instance_id=3)
+    seed = 4
+    log(f"lattice case: frozen replicas, {kernel} tile kernel")
+    h = sg.load_instance([inst], lattice_dims=[(16, 12, 24)])
+    for k, v in _tile_tune(kernel, 2).items():
+        h.tune(k, v)
+    h.bind()
+    h.init_spins(seed)
+    # converge a few replicas first (per-phase schedule, a short cap), then
+    # sweep all of them with ties on the tile schedule
+    st = h.run_sweeps(seed=seed, rule=GREEDY, max_sweeps=6, until_converged=True, schedule=0)
+    assert 0 < st["n_unconverged"] < inst.restarts
+    st = h.run_sweeps(seed=seed, rule=TIE, max_sweeps=9, until_converged=False, schedule=SCHED_LATTICE)
+    assert st["schedule_used"] == SCHED_LATTICE and h.query("last_msc") == (1 if kernel == "msc" else 0)
+    s1 = oracle_run(inst, seed, GREEDY, 6, True)
+    s2 = oracle_run(inst, seed, TIE, 9, False, state=s1)
+    compare(h, [inst], [s2])
+
+
 def test_msc_restarts_and_fields(gpu):
     """h = 0 everywhere (every tie rule branch at g = 0) and several restarts."""
     inst = gen.lattice((18, 22, 26), seed=3, h_range=(0, 0), restarts=4)
