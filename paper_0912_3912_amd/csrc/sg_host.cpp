@@ -1111,6 +1111,7 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
         const sg::LatticeDev Lt = H->lat_view(q);
         SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
         const int T = p->max_sweeps;
+        bool absolute = false;  // the bit-plane kernel leaves final energies, not changes
         if (T > 0) {
             if (lattice_wg_fits(H, q)) {
                 SG_HIP(hipEventRecord(H->evh0, st), "event record");
@@ -1156,6 +1157,7 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                                                     q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
                            "lattice tile kernel");
                 H->last_msc = msc ? 1 : 0;
+                absolute = msc;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;
                 uint32_t herr = 0;
@@ -1168,7 +1170,7 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 H->last_tiles[3] = tg.k;
             }
         }
-        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st), "end kernel");
+        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st, absolute), "end kernel");
     }
     return SG_OK;
 }

@@ -285,9 +285,11 @@ __global__ __launch_bounds__(kPhaseThreads) void k_phase(InstDev I, int8_t* __re
 
 // End of a call, one block per replica: fold the per-block accumulators into
 // the replica state, settle the sweep count and the converged flag, add the
-// call totals.  T = sweeps launched in this call.
+// call totals.  T = sweeps launched in this call.  The first accumulator of
+// each slot is an energy change, or with `absolute` the slot's share of the
+// final energy (then it replaces E of every replica not frozen at entry).
 __global__ void k_end(RepState* __restrict__ rs, const int64_t* __restrict__ acc, int nslots, int T,
-                      int until_conv, int64_t n, CallStats* __restrict__ cs)
+                      int until_conv, int64_t n, CallStats* __restrict__ cs, int absolute)
 {
     const int r = blockIdx.x;
     RepState* st = rs + r;
@@ -313,6 +315,7 @@ __global__ void k_end(RepState* __restrict__ rs, const int64_t* __restrict__ acc
     }
     int performed = 0;
     int conv = st->converged;
+    const int frozen = conv;
     if (!conv) {
         if (until_conv) {
             const int L = st->lastflip;
@@ -326,7 +329,8 @@ __global__ void k_end(RepState* __restrict__ rs, const int64_t* __restrict__ acc
             performed = T;
         }
     }
-    st->E += td;
+    if (!absolute) st->E += td;
+    else if (!frozen) st->E = td;
     st->flips += tf;
     st->sweeps += performed;
     st->converged = conv;
@@ -444,10 +448,11 @@ hipError_t launch_bump(int32_t* t_base, int d, hipStream_t st)
 }
 
 hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T, int until_conv, int64_t n,
-                      CallStats* cs, hipStream_t st)
+                      CallStats* cs, hipStream_t st, bool absolute)
 {
     const unsigned threads = nslots <= 64 ? 64 : 256;
-    hipLaunchKernelGGL(k_end, dim3(R), dim3(threads), 0, st, rs, acc, nslots, T, until_conv, n, cs);
+    hipLaunchKernelGGL(k_end, dim3(R), dim3(threads), 0, st, rs, acc, nslots, T, until_conv, n, cs,
+                       absolute ? 1 : 0);
     return hipGetLastError();
 }
 

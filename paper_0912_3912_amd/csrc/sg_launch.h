@@ -22,8 +22,10 @@ hipError_t launch_phase(const InstDev& I, int8_t* spins, int64_t stride, RepStat
 hipError_t launch_fields(const InstDev& I, const int8_t* spins, int64_t stride, int R, int32_t* fields, int64_t fstride,
                          hipStream_t st);
 hipError_t launch_bump(int32_t* t_base, int d, hipStream_t st);
+// Fold a call's per-slot accumulators into the replicas (absolute: the slots
+// hold shares of the final energy instead of energy changes).
 hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T, int until_conv, int64_t n,
-                      CallStats* cs, hipStream_t st);
+                      CallStats* cs, hipStream_t st, bool absolute = false);
 hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, hipStream_t st);
 hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_t* restarts, int ninst,
                        int64_t* Eb, int32_t* rb, hipStream_t st);

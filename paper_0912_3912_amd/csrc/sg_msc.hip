@@ -27,6 +27,12 @@
 // phase), so the draws run at full lane occupancy without a workgroup
 // barrier.
 //
+// Energy: the phases count flips only.  After the last exchange (whose words
+// then fill the whole box) each tile sums the exact energy of its interior:
+// every interior site adds its +x, +y, +z bonds (+1 unsatisfied, -1
+// satisfied) and -s h, so each bond and field of the lattice is counted once
+// (Sec. II eq. (1)); the replica's energy is the sum over its tiles.
+//
 // Neighbours: the +-x and +-y neighbours of a colour-c site are the same bit
 // of the other colour's word in the neighbouring rows (their offset is the
 // same); its -z and +z neighbours are, in the same row's other-colour word,
@@ -231,7 +237,6 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
     __syncthreads();
 
     const int P_total = 2 * T;
-    long long dE = 0;
     int nflip = 0;
     bool failed = false;
 
@@ -304,13 +309,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                 const bool inner_row = x >= hk[0] && x < hk[0] + X[0] && y >= hk[1] && y < hk[1] + X[1];
                 const uint32_t I = inner_row ? (zo ? im1 : im0) : 0u;
                 const uint32_t FI = F & I;
-                if (FI) {
-                    const int nf = __popc(FI);
-                    const int sg = __popc(FI & gpos) + __popc(FI & gtwo) - __popc(FI & gneg) - __popc(FI & gneg & ha);
-                    const int su = __popc(FI & u0) + 2 * __popc(FI & u1) + 4 * __popc(FI & u2);
-                    dE += 2 * sg + 4 * D * nf - 4 * su;
-                    nflip += nf;
-                }
+                nflip += __popc(FI);
                 const uint32_t ns = s ^ F;
                 if constexpr (TIE) {
                     const uint32_t odd = (hp | hn) & ~ha;
@@ -399,10 +398,10 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                                __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();  // the reads below overwrite plane rows published above
-        // After the last epoch the words are still awaited, though not used:
+        // After the last epoch the words are still awaited and written too:
         // then every neighbour has finished reading its box from the spin
-        // array before this tile writes its interior back.
-        const bool last = (e + 1) * k >= P_total;
+        // array before this tile writes its interior back, and the box holds
+        // the final neighbours of every interior site for the energy.
 #pragma unroll
         for (int m = 0; m < kExRows; ++m) {
             const int row = tid + m * kMscThreads;
@@ -431,7 +430,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                 if ((ph ^ tag) >> 32) ph = __hip_atomic_load(ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((pm ^ tag) >> 32) pm = __hip_atomic_load(am, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (failed || last) continue;
+            if (failed) continue;
             const uint32_t wl = (uint32_t)pl, wh = (uint32_t)ph, wm = (uint32_t)pm;
             const uint64_t v = (uint64_t)((wl >> (Xzm - hk[2])) & low_bits(hk[2])) | ((uint64_t)wm << hk[2]) |
                                ((uint64_t)(wh & low_bits(hk[2])) << (hk[2] + X[2]));
@@ -459,15 +458,46 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             }
         }
     }
+    // exact energy of the interior from the final box (thread per interior row)
+    long long eT = 0;
+    if (!failed) {
+        const uint32_t im0 = bit_range((hk[2] + 1) >> 1, (hk[2] + X[2] - 1) >> 1);
+        const uint32_t im1 = bit_range(hk[2] >> 1, (hk[2] + X[2] - 2) >> 1);
+        for (int row = tid; row < nrow_int; row += kMscThreads) {
+            const int x = (int)fdiv((uint32_t)row, mX1);
+            const int y = row - x * X[1];
+            const int bx = x + hk[0], by = y + hk[1];
+            const int brow = bx * B[1] + by;
+            int e = 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int zo = (c - par0 - bx - by) & 1;
+                const uint32_t* const wc = lds32 + brow * RS + c;
+                const uint32_t* const wo = lds32 + brow * RS + (c ^ 1);
+                const uint32_t s = wc[2 * kPlS], on = wo[2 * kPlS];
+                const uint32_t I = zo ? im1 : im0;
+                // unsatisfied +y and +z bonds (and +x in 3-D)
+                int u = __popc((s ^ wo[RS + 2 * kPlS] ^ wc[2 * kPlJY]) & I) +
+                        __popc((s ^ (zo ? (on >> 1) : on) ^ wc[2 * kPlJZ]) & I);
+                if constexpr (D == 3) u += __popc((s ^ wo[B[1] * RS + 2 * kPlS] ^ wc[2 * kPlJX]) & I);
+                const uint32_t hp = wc[2 * kPlHP], hn = wc[2 * kPlHN], ha = wc[2 * kPlHA];
+                const uint32_t gpos = (hp & ~s) | (hn & s);
+                const uint32_t gneg = (hn & ~s) | (hp & s);
+                const int sg = __popc(gpos & I) + __popc(gpos & ha & I) - __popc(gneg & I) - __popc(gneg & ha & I);
+                e += 2 * u - D * __popc(I) - sg;
+            }
+            eT += e;
+        }
+    }
     long long nf = nflip;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        dE += __shfl_xor(dE, off, 64);
+        eT += __shfl_xor(eT, off, 64);
         nf += __shfl_xor(nf, off, 64);
     }
     __shared__ long long pd[kMscWaves], pf[kMscWaves];
     if (lane == 0) {
-        pd[wave] = dE;
+        pd[wave] = eT;
         pf[wave] = nf;
     }
     __syncthreads();
@@ -478,7 +508,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
             b2 += pf[w];
         }
         int64_t* ap = acc + 2 * ((int64_t)r * nslots + tile);
-        ap[0] += a;
+        ap[0] = a;  // the tile's energy (absolute)
         ap[1] += b2;
     }
 }
