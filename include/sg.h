@@ -254,8 +254,8 @@ sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
 
 /* Draw the random start of every replica (Sec. IV: uniform), compute its
  * energy (or leave it to the run that follows, see the "defer_energy" knob
- * of sg_tune), reset sweeps, flips and converged.  Errors: SG_ESTATE before
- * bind. */
+ * of sg_tune), reset sweeps, flips and converged.  Enqueued on the bound
+ * stream (returns without waiting for it).  Errors: SG_ESTATE before bind. */
 sg_status sg_init_spins(sg_handle h, uint64_t seed);
 
 /* Set replica r of instance inst to host spins s (n int8 values, each +1 or
@@ -268,7 +268,9 @@ sg_status sg_set_spins(sg_handle h, int32_t inst, int32_t r, const int8_t* s);
  * stats may be NULL.  Returns SG_ENOTCONV when until_converged and a
  * replica hit max_sweeps.  Errors: SG_ESTATE before sg_init_spins or
  * sg_set_spins of every replica, SG_EINVAL for bad parameters or a schedule
- * the handle cannot use. */
+ * the handle cannot use, SG_EDEVICE for a HIP failure or a lattice tile
+ * kernel whose wait for a neighbour tile timed out (the replica state is then
+ * undefined: start again with sg_init_spins). */
 sg_status sg_run_sweeps(sg_handle h, const sg_run_params* p, sg_run_stats* stats);
 
 /* Energies of all replicas in handle order (sum over instances of

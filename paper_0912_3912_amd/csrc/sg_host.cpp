@@ -165,6 +165,7 @@ struct sg_ctx {
     // run has written them or an energy pass has computed them.
     std::vector<uint8_t> e_deferred;
     bool e_pending = false;
+    bool lat_err_check = false;  // the current call launched tile kernels: read their error flag at its end
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evh0 = nullptr, evh1 = nullptr;  // around the hot kernel(s) of the last schedule run
     double hot_us = 0.0;                        // their device time, microseconds
@@ -1103,6 +1104,10 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
     hipStream_t st = H->stream;
     sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
     uint32_t* err = H->at<uint32_t>(H->off_err);
+    // the tile kernels' error flag: cleared once per call (so a failed wait in
+    // any launch of the call is reported), read with the call totals at its end
+    SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
+    H->lat_err_check = true;
     for (int qi : which) {
         const HostInst& q = H->insts[qi];
         sg::RepState* rs = H->reps() + q.rep_base;
@@ -1138,7 +1143,6 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 }
                 const sg::TileGeom tg = qm.tile_geom;
                 const bool msc = qm.tile_msc != 0;
-                SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
                 // exchange words (8 bytes: epoch tag and bits): at most n / (smallest z
                 // extent) + one row per tile, per copy
                 const int64_t words = sg::lattice_tiles_words(tg, q.lat_L) * q.R;
@@ -1160,10 +1164,6 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 absolute = msc;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;
-                uint32_t herr = 0;
-                SG_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st), "error flag copy");
-                SG_HIP(hipStreamSynchronize(st), "stream sync");
-                if (herr) return fail(SG_EDEVICE, "lattice tile kernel: a neighbour wait timed out");
                 H->last_tiles[0] = tg.P[0];
                 H->last_tiles[1] = tg.P[1];
                 H->last_tiles[2] = tg.P[2];
@@ -1904,7 +1904,7 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
                                       (int)H->h_litems.size(), H->lane_nmax, true, H->reps(), nullptr, seed, st),
                "lane start kernel");
     }
-    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    // enqueued on the bound stream: every later call of the handle is ordered after it
     std::fill(H->started.begin(), H->started.end(), 1);
     return SG_OK;
 }
@@ -1974,6 +1974,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
     H->hot_launches = 0;
+    H->lat_err_check = false;
     for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_GRAPH, SG_SCHED_FIELDS, SG_SCHED_PHASE}) {
         std::vector<int> which;
         for (size_t k = 0; k < assign.size(); ++k)
@@ -1992,7 +1993,13 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
     sg::CallStats cs;
     SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
+    uint32_t herr = 0;
+    if (H->lat_err_check)
+        SG_HIP(hipMemcpyAsync(&herr, H->at<uint32_t>(H->off_err), 4, hipMemcpyDeviceToHost, st), "error flag copy");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
+    if (herr)
+        return fail(SG_EDEVICE, "lattice tile kernel: a neighbour wait timed out (replica state is undefined; "
+                                "start again with sg_init_spins)");
     if (H->e_pending) {
         // the queue kernel wrote the energies of the replicas that converged;
         // if any did not, all are computed from their final spins

@@ -302,6 +302,9 @@ class Server:
         except Exception as e:
             res.status = f"error: {e}"
         finally:
+            # work still queued on the slot's stream (a start whose run then
+            # failed) must end before its pool slice goes to another request
+            self.streams[slot].synchronize()
             h.free()
         res.done = self.now()
         with self.lock:
