@@ -168,9 +168,8 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
     int* r_last = r_t + NG * 32;                                // 1 + its last sweep that flipped
     int* r_flips = r_last + NG * 32;                            // its flips in this call
     __shared__ int g_r0[NG], g_cnt[NG];                         // restarts [g_r0, g_r0 + g_cnt) in the group's bits
-    __shared__ uint32_t g_act[NG], g_part[NG], g_any[NG];       // sweeping; taking part in the call; flipped this sweep
-    __shared__ int g_fin[NG], g_flush[NG], g_load[NG], g_since[NG];
-    __shared__ int n_live, next_r, blk_event, kflush;
+    __shared__ uint32_t g_act[NG], g_part[NG];                  // sweeping; taking part in the call
+    __shared__ int next_r, kflush;
     __shared__ unsigned long long b_att, b_flips, b_smax, b_unconv;
 
     for (int k = tid; k < ew; k += kBitsThreads) l_nbr[k] = I.nbr[k];
@@ -183,15 +182,12 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
     for (int k = tid; k < n; k += kBitsThreads) l_h[k] = I.h[k];
     for (int k = tid; k <= C; k += kBitsThreads) l_cs[k] = ctab[Q.ctab_off + k];
     if (tid == 0) {
-        n_live = 0;
         next_r = it.r0;
-        blk_event = 0;
         b_att = b_flips = b_smax = b_unconv = 0;
     }
     if (tid < NG) {
         g_cnt[tid] = 0;
-        g_act[tid] = g_part[tid] = g_any[tid] = 0u;
-        g_fin[tid] = g_flush[tid] = g_load[tid] = g_since[tid] = 0;
+        g_act[tid] = g_part[tid] = 0u;
     }
     __syncthreads();
     // flip offsets 127 - floor(W_i / 2); rows a lane decides per sweep (bounds the counters)
@@ -211,7 +207,7 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
         kflush = max(1, 255 / max(1, rows));  // sweeps between counter flushes
     }
 
-    // next group of up to 32 restarts with at least one not frozen (lead wavefront of group g)
+    // next group of up to 32 restarts with at least one not frozen (the group's wavefront)
     auto fetch = [&]() {
         for (;;) {
             int r = 0;
@@ -221,7 +217,6 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
                 if (lane == 0) {
                     g_cnt[g] = 0;
                     g_act[g] = g_part[g] = 0u;
-                    g_load[g] = 0;
                 }
                 return false;
             }
@@ -238,9 +233,6 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
                 g_r0[g] = r;
                 g_cnt[g] = cnt;
                 g_act[g] = g_part[g] = act;
-                g_any[g] = 0u;
-                g_since[g] = 0;
-                g_load[g] = 1;
             }
             return true;
         }
@@ -352,156 +344,144 @@ __global__ __launch_bounds__(bits_threads<NG>()) void k_block_bits(const InstTab
         return 2 * V - (long long)wsum;
     };
 
-    if (wk == 0 && fetch() && lane == 0) atomicAdd(&n_live, 1);
-    __syncthreads();
-    if (g_load[g]) load_group();
-    __syncthreads();
+    // Each wavefront runs its own group (one wavefront per group): it sweeps,
+    // keeps its restarts' counters, finishes the group and takes the next
+    // restarts without waiting for the other groups of the workgroup.  Its
+    // LDS writes and later reads by other lanes of the same wavefront are
+    // ordered by wavefront fences (LDS operations of a wavefront complete in
+    // order; the fences keep the compiler from moving them).
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    __syncthreads();  // flip offsets and kflush are read by every wavefront
+    bool have = fetch();
+    wave_sync();
+    if (have) load_group();
+    wave_sync();
 
     uint32_t cnt8[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // this lane's flips per restart of its group, bit-sliced
-    while (n_live > 0) {
-        const uint32_t act = g_act[g];
+    int since = 0;                                 // sweeps since the counters were last flushed
+    uint32_t act = have ? g_act[g] : 0u;
+    while (have) {
         uint32_t any = 0;
         for (int c = 0; c < C; ++c) {
-            if (act) {
-                for (int sl = l_cs[c] + wk; sl < l_cs[c + 1]; sl += WPG) {
-                    const Slice S = l_sl[sl];
-                    if (lane < S.rows) {
-                        const int i = (int)S.row0 + lane;
-                        uint32_t* sp = l_sp + g * n;
-                        const uint32_t xi = sp[i];
-                        const uint32_t K = l_k[i];
-                        uint32_t A[8];
+            for (int sl = l_cs[c]; sl < l_cs[c + 1]; ++sl) {
+                const Slice S = l_sl[sl];
+                if (lane < S.rows) {
+                    const int i = (int)S.row0 + lane;
+                    uint32_t* sp = l_sp + g * n;
+                    const uint32_t xi = sp[i];
+                    const uint32_t K = l_k[i];
+                    uint32_t A[8];
 #pragma unroll
-                        for (int b = 0; b < 8; ++b) A[b] = 0u - ((K >> b) & 1u);
-                        {
-                            const int h = l_h[i];
-                            acc_add(A, (uint32_t)abs(h), xi ^ (h < 0 ? ~0u : 0u));
+                    for (int b = 0; b < 8; ++b) A[b] = 0u - ((K >> b) & 1u);
+                    {
+                        const int h = l_h[i];
+                        acc_add(A, (uint32_t)abs(h), xi ^ (h < 0 ? ~0u : 0u));
+                    }
+                    const uint32_t* pw = l_nbr + S.ebase + lane;
+                    // four couplings at a time: their loads are issued together
+                    int k = 0;
+                    for (; k + 4 <= S.ew; k += 4) {
+                        uint32_t w[4], xj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) w[u] = pw[(k + u) * kSlice];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) xj[u] = sp[w[u] >> 8];
+                        uint32_t wt[4], um[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int cj = bits_coef(w[u]);
+                            wt[u] = (uint32_t)abs(cj);
+                            um[u] = xi ^ xj[u] ^ (cj < 0 ? ~0u : 0u);
                         }
-                        const uint32_t* pw = l_nbr + S.ebase + lane;
-                        // four couplings at a time: their loads are issued together
-                        int k = 0;
-                        for (; k + 4 <= S.ew; k += 4) {
-                            uint32_t w[4], xj[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) w[u] = pw[(k + u) * kSlice];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) xj[u] = sp[w[u] >> 8];
-                            uint32_t wt[4], um[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int cj = bits_coef(w[u]);
-                                wt[u] = (uint32_t)abs(cj);
-                                um[u] = xi ^ xj[u] ^ (cj < 0 ? ~0u : 0u);
-                            }
-                            acc_add4(A, wt, um);
+                        acc_add4(A, wt, um);
+                    }
+                    for (; k < S.ew; ++k) {
+                        const uint32_t w = pw[k * kSlice];
+                        const int cj = bits_coef(w);
+                        acc_add(A, (uint32_t)abs(cj), xi ^ sp[w >> 8] ^ (cj < 0 ? ~0u : 0u));
+                    }
+                    if (I.has_tri) {
+                        const uint32_t* pa = l_ta + S.tbase + lane;
+                        const uint32_t* pb = l_tb + S.tbase + lane;
+                        for (int k = 0; k < S.tw; ++k) {
+                            const uint32_t wa = pa[k * kSlice];
+                            const int ck = bits_coef(wa);
+                            acc_add(A, (uint32_t)abs(ck),
+                                    xi ^ sp[wa >> 8] ^ sp[pb[k * kSlice]] ^ (ck < 0 ? ~0u : 0u));
                         }
-                        for (; k < S.ew; ++k) {
-                            const uint32_t w = pw[k * kSlice];
-                            const int cj = bits_coef(w);
-                            acc_add(A, (uint32_t)abs(cj), xi ^ sp[w >> 8] ^ (cj < 0 ? ~0u : 0u));
-                        }
-                        if (I.has_tri) {
-                            const uint32_t* pa = l_ta + S.tbase + lane;
-                            const uint32_t* pb = l_tb + S.tbase + lane;
-                            for (int k = 0; k < S.tw; ++k) {
-                                const uint32_t wa = pa[k * kSlice];
-                                const int ck = bits_coef(wa);
-                                acc_add(A, (uint32_t)abs(ck),
-                                        xi ^ sp[wa >> 8] ^ sp[pb[k * kSlice]] ^ (ck < 0 ? ~0u : 0u));
-                            }
-                        }
-                        const uint32_t F = A[7] & act;
-                        if (F) {
-                            sp[i] = xi ^ F;
-                            any |= F;
-                            uint32_t carry = F;
+                    }
+                    const uint32_t F = A[7] & act;
+                    if (F) {
+                        sp[i] = xi ^ F;
+                        any |= F;
+                        uint32_t carry = F;
 #pragma unroll
-                            for (int b = 0; b < 8; ++b) {
-                                const uint32_t t = cnt8[b] & carry;
-                                cnt8[b] ^= carry;
-                                carry = t;
-                            }
+                        for (int b = 0; b < 8; ++b) {
+                            const uint32_t t = cnt8[b] & carry;
+                            cnt8[b] ^= carry;
+                            carry = t;
                         }
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
         any = wave_or(any);
-        if (lane == 0 && any) atomicOr(&g_any[g], any);
-        __syncthreads();
-        // per-restart bookkeeping of the sweep (lead wavefront of each group)
-        if (wk == 0 && act) {
-            const uint32_t ga = g_any[g];
-            bool done = false;
-            if (lane < 32 && ((act >> lane) & 1u)) {
-                const int t = ++r_t[g * 32 + lane];
-                const bool flipped = (ga >> lane) & 1u;
-                if (flipped) r_last[g * 32 + lane] = t;
-                done = (until_conv && !flipped) || t >= T;
-            }
-            const uint32_t left = act & ~(uint32_t)__ballot(done);
-            if (lane == 0) {
-                g_act[g] = left;
-                g_any[g] = 0u;
-                g_fin[g] = left == 0u;
-                const int since = g_since[g] + 1;
-                g_flush[g] = (left == 0u || since >= kflush) ? 1 : 0;
-                g_since[g] = g_flush[g] ? 0 : since;
-                g_load[g] = 0;
-                if (g_flush[g]) blk_event = 1;
-            }
+        // per-restart bookkeeping of the sweep
+        bool done = false;
+        if (lane < 32 && ((act >> lane) & 1u)) {
+            const int t = ++r_t[g * 32 + lane];
+            const bool flipped = (any >> lane) & 1u;
+            if (flipped) r_last[g * 32 + lane] = t;
+            done = (until_conv && !flipped) || t >= T;
         }
-        __syncthreads();
-        if (blk_event) {
-            // flip counters of flushing groups: per restart b, sum over lanes of each counter bit
-            if (g_flush[g]) {
-                int mine = 0;
+        act &= ~(uint32_t)__ballot(done);
+        const bool fin = act == 0u;
+        if (fin || ++since >= kflush) {
+            // flip counters: per restart b, sum over lanes of each counter bit
+            since = 0;
+            int mine = 0;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (__ballot(cnt8[k] != 0u) == 0) continue;
-                    for (int b = 0; b < 32; ++b) {
-                        const int v = (int)__popcll(__ballot((cnt8[k] >> b) & 1u)) << k;
-                        if (lane == b) mine += v;
-                    }
-                    cnt8[k] = 0u;
+            for (int k = 0; k < 8; ++k) {
+                if (__ballot(cnt8[k] != 0u) == 0) continue;
+                for (int b = 0; b < 32; ++b) {
+                    const int v = (int)__popcll(__ballot((cnt8[k] >> b) & 1u)) << k;
+                    if (lane == b) mine += v;
                 }
-                if (lane < 32 && mine) atomicAdd(&r_flips[g * 32 + lane], mine);
+                cnt8[k] = 0u;
             }
-            __syncthreads();
-            if (g_fin[g]) {
-                store_group();
-                const long long Eg = group_energy();
-                if (wk == 0 && lane < 32 && ((g_part[g] >> lane) & 1u)) {
-                    const int t = r_t[g * 32 + lane], last = r_last[g * 32 + lane], nf = r_flips[g * 32 + lane];
-                    RepState* st = rs + Q.rep_base + g_r0[g] + lane;
-                    st->E = Eg;
-                    st->flips += nf;
-                    st->sweeps += t;
-                    st->lastflip = last;
-                    const bool conv = until_conv && last < t;
-                    if (conv) st->converged = 1;
-                    atomicAdd(&b_att, (unsigned long long)t * (unsigned long long)n);
-                    atomicAdd(&b_flips, (unsigned long long)nf);
-                    atomicMax(&b_smax, (unsigned long long)t);
-                    if (until_conv && !conv) atomicAdd(&b_unconv, 1ull);
-                }
+            if (lane < 32) r_flips[g * 32 + lane] += mine;
+        }
+        if (fin) {
+            store_group();
+            const long long Eg = group_energy();
+            if (lane < 32 && ((g_part[g] >> lane) & 1u)) {
+                const int t = r_t[g * 32 + lane], last = r_last[g * 32 + lane], nf = r_flips[g * 32 + lane];
+                RepState* st = rs + Q.rep_base + g_r0[g] + lane;
+                st->E = Eg;
+                st->flips += nf;
+                st->sweeps += t;
+                st->lastflip = last;
+                const bool conv = until_conv && last < t;
+                if (conv) st->converged = 1;
+                atomicAdd(&b_att, (unsigned long long)t * (unsigned long long)n);
+                atomicAdd(&b_flips, (unsigned long long)nf);
+                atomicMax(&b_smax, (unsigned long long)t);
+                if (until_conv && !conv) atomicAdd(&b_unconv, 1ull);
             }
-            __syncthreads();
-            if (g_fin[g] && wk == 0) {
-                const bool got = fetch();
-                if (lane == 0) {
-                    g_fin[g] = 0;
-                    g_flush[g] = 0;
-                    if (!got) atomicSub(&n_live, 1);
-                }
-            }
-            __syncthreads();
-            if (g_load[g]) load_group();
-            if (tid == 0) blk_event = 0;
-            __syncthreads();
+            wave_sync();
+            have = fetch();
+            wave_sync();
+            if (have) load_group();
+            wave_sync();
+            act = have ? g_act[g] : 0u;
         }
     }
+    __syncthreads();
     if (tid == 0) {
         if (b_att) atomicAdd(&cs->attempts, b_att);
         if (b_flips) atomicAdd(&cs->flips, b_flips);
