@@ -165,6 +165,7 @@ struct sg_ctx {
     // run has written them or an energy pass has computed them.
     std::vector<uint8_t> e_deferred;
     bool e_pending = false;
+    std::vector<uint8_t> e_written;  // this call's kernels wrote the final energies of the instance
     bool lat_err_check = false;  // the current call launched tile kernels: read their error flag at its end
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evh0 = nullptr, evh1 = nullptr;  // around the hot kernel(s) of the last schedule run
@@ -1162,6 +1163,7 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                            "lattice tile kernel");
                 H->last_msc = msc ? 1 : 0;
                 absolute = msc;
+                if (msc) H->e_written[(size_t)qi] = 1;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;
                 H->last_tiles[0] = tg.P[0];
@@ -1568,14 +1570,21 @@ sg_status sg_internal_validate(const sg_instance_desc* d) { return validate(*d, 
 
 // A drawn start leaves its energy out when the kernel that SG_SCHED_AUTO
 // would run next computes the energies of the final spins itself: the
-// bit-sliced block kernel for lane-started instances (always), the queue
-// kernel for the others (at convergence; it is taken only when every
-// unit-started instance would run there).  A wrong guess costs an energy
-// pass, never a wrong energy.
+// bit-sliced block kernel for lane-started instances (always), for the
+// others the queue kernel (at convergence) or the bit-plane lattice tile
+// kernel (taken only when every unit-started instance would run on one of
+// these two).  A wrong guess costs an energy pass, never a wrong energy.
 bool defer_lane_energy(const sg_ctx* H, const HostInst& q)
 {
     return H->defer_energy && H->block_bits && q.bits_ok && !q.lat_ok && q.R >= H->block_min_restarts &&
            can_block(H, q) && bits_lds_for(H, q) > 0;
+}
+
+// The lattice schedule would run this instance on the bit-plane tile kernel
+// (unless no tiling of it fits, which the run reports through e_written).
+bool lattice_msc_bound(const sg_ctx* H, const HostInst& q)
+{
+    return q.lat_ok && q.lat_msc && H->lattice_msc && !lattice_wg_fits(H, q);
 }
 
 bool defer_unit_energy(const sg_ctx* H)
@@ -1588,7 +1597,7 @@ bool defer_unit_energy(const sg_ctx* H)
         if (q.dense || (H->lanes_on && lane_start_candidate(q))) continue;
         const bool queue = !q.lat_ok && !(q.R >= H->block_min_restarts && can_block(H, q)) && can_queue(q) &&
                            queue_items >= H->queue_min_items;
-        if (!queue) return false;
+        if (!queue && !lattice_msc_bound(H, q)) return false;
     }
     return true;
 }
@@ -1597,6 +1606,7 @@ bool defer_unit_energy(const sg_ctx* H)
 bool run_writes_energy(const sg_ctx* H, const sg_run_params* p, int kind, int sched, const HostInst& q)
 {
     if (kind == 1) return sched == SG_SCHED_BLOCK && bits_path(H, p, q);
+    if (sched == SG_SCHED_LATTICE) return lattice_msc_bound(H, q) && !p->until_converged && p->max_sweeps > 0;
     return sched == SG_SCHED_QUEUE && p->until_converged && p->max_sweeps > 0;
 }
 
@@ -1975,6 +1985,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
     H->hot_launches = 0;
     H->lat_err_check = false;
+    H->e_written.assign(H->insts.size(), 0);
     for (int kind : {SG_SCHED_LATTICE, SG_SCHED_BLOCK, SG_SCHED_QUEUE, SG_SCHED_GRAPH, SG_SCHED_FIELDS, SG_SCHED_PHASE}) {
         std::vector<int> which;
         for (size_t k = 0; k < assign.size(); ++k)
@@ -2001,11 +2012,16 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
         return fail(SG_EDEVICE, "lattice tile kernel: a neighbour wait timed out (replica state is undefined; "
                                 "start again with sg_init_spins)");
     if (H->e_pending) {
-        // the queue kernel wrote the energies of the replicas that converged;
-        // if any did not, all are computed from their final spins
-        bool queue_deferred = false;
-        for (uint8_t d : H->e_deferred) queue_deferred = queue_deferred || d == 2;
-        if (queue_deferred && cs.unconverged) {
+        // the queue kernel wrote the energies of the replicas that converged,
+        // the bit-plane lattice kernel those of its instances; if any replica
+        // is left without, all are computed from their final spins
+        bool missing = false;
+        for (size_t k = 0; k < H->e_deferred.size(); ++k) {
+            if (H->e_deferred[k] != 2) continue;
+            if (assign[k] == SG_SCHED_QUEUE) missing = missing || cs.unconverged != 0;
+            else missing = missing || !H->e_written[k];
+        }
+        if (missing) {
             if ((e = ensure_energy(H)) != SG_OK) return e;
             SG_HIP(hipStreamSynchronize(st), "stream sync");
         }

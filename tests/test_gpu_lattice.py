@@ -133,6 +133,42 @@ def test_tile_mode_skips_frozen_replicas(gpu, kernel):
     compare(h, [inst], [s2])
 
 
+def test_lattice_deferred_start_energy(gpu):
+    """A start bound for the bit-plane tile kernel leaves its energy out (that
+    kernel sums the final energies itself).  Energies equal the oracle's when
+    read right after the start, after a bit-plane run, and after a run that
+    ends up on another kernel (byte tile kernel, or until_converged on the
+    per-phase schedule), each read back after its run."""
+    import paper_0912_3912_amd as sg
+    dims = (16, 12, 24)
+    inst = gen.lattice(dims, seed=9, h_range=(-2, 2), restarts=3, instance_id=5)
+    seed = 6
+
+    def handle(**after):
+        h = sg.load_instance([inst], lattice_dims=[dims])
+        h.tune("lattice_wg_max_n", 0)
+        h.bind()
+        h.init_spins(seed)
+        assert h.query("energy_pending") == 1
+        for k, v in after.items():  # knobs changed between the start and the run
+            h.tune(k, v)
+        return h
+
+    log("lattice case: deferred start energy")
+    h = handle()
+    compare(h, [inst], [oracle_run(inst, seed, GREEDY, 0, False)])
+    for rule, ms, uc, tune, sched, msc in ((TIE, 11, False, {}, SCHED_LATTICE, 1),
+                                           (GREEDY, 7, False, {}, SCHED_LATTICE, 1),
+                                           (TIE, 11, False, {"lattice_msc": 0}, SCHED_LATTICE, 0),
+                                           (GREEDY, 50, True, {}, -1, None)):
+        h = handle(**tune)
+        st = h.run_sweeps(seed=seed, rule=rule, max_sweeps=ms, until_converged=uc, schedule=sched)
+        if msc is not None:
+            assert st["schedule_used"] == SCHED_LATTICE and h.query("last_msc") == msc
+        assert h.query("energy_pending") == 0
+        compare(h, [inst], [oracle_run(inst, seed, rule, ms, uc)])
+
+
 def test_msc_restarts_and_fields(gpu):
     """h = 0 everywhere (every tie rule branch at g = 0) and several restarts."""
     inst = gen.lattice((18, 22, 26), seed=3, h_range=(0, 0), restarts=4)
