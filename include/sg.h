@@ -317,10 +317,11 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *   "defer_energy"       1: sg_init_spins leaves out the start energy of
  *                        instances that SG_SCHED_AUTO would run on a kernel
  *                        that computes the energies of the final spins
- *                        itself: the bit-sliced block kernel, or the queue
- *                        kernel (from the last sweep of a converged replica;
- *                        when a replica stops on the sweep cap, the energies
- *                        are computed after the run).  Any other reader
+ *                        itself: the bit-sliced block kernel, the bit-plane
+ *                        lattice tile kernel, or the queue kernel (from the
+ *                        last sweep of a converged replica).  When a run
+ *                        leaves some replica without (a sweep cap, another
+ *                        kernel), the energies are computed after it.  Any other reader
  *                        (sg_energy, sg_best, another rule or schedule, a
  *                        run without until_converged) first computes them.
  *                        0: always at the start (default 1; results are the
