@@ -326,6 +326,9 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        run without until_converged) first computes them.
  *                        0: always at the start (default 1; results are the
  *                        same)
+ *   "fm_waves"           most wavefronts per SG_RULE_FM workgroup (0 = 16);
+ *                        among the sizes that fit LDS the one with the most
+ *                        wavefronts resident per compute unit is used
  *   "fm_key32"           1: SG_RULE_FM picks moves on 32-bit keys when every
  *                        gain is below 2^19 in magnitude; 0: 64-bit keys
  *                        (default 1)
@@ -357,7 +360,8 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
  * lattice tile launch), "last_tile_k", "last_msc" (1 when that launch used
  * the bit-plane kernel), "last_bits" (1 when the last block-schedule call
  * used the bit-sliced kernel), "last_key32" (1 when the last SG_RULE_FM call
- * picked moves on 32-bit keys), "energy_pending" (1 while start energies
+ * picked moves on 32-bit keys), "last_fm_waves" (its wavefronts per
+ * workgroup), "energy_pending" (1 while start energies
  * left out by sg_init_spins are not yet computed), "last_queue_grid",
  * "total_replicas",
  * "instances", "hot_ns" / "hot_launches" (device time, from HIP events on the

@@ -393,6 +393,25 @@ static hipError_t launch_fm_t(const InstTab* tab, const int32_t* ctab, const Que
     return hipGetLastError();
 }
 
+template <bool TRI, bool K32>
+static int fm_blocks_per_cu(int waves, size_t lds)
+{
+    const void* kern = (const void*)k_fm<TRI, K32>;
+    int per_cu = 0;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves * 64, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu;
+}
+
+int fm_max_blocks_per_cu(int waves, size_t lds, bool tri, bool key32)
+{
+    if (tri) return key32 ? fm_blocks_per_cu<true, true>(waves, lds) : fm_blocks_per_cu<true, false>(waves, lds);
+    return key32 ? fm_blocks_per_cu<false, true>(waves, lds) : fm_blocks_per_cu<false, false>(waves, lds);
+}
+
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
                      int stage_cap, bool tri, bool key32, RepState* rs, CallStats* cs, uint32_t* err,
                      int max_passes, int until_conv, hipStream_t st)

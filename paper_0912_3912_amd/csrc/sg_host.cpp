@@ -124,6 +124,8 @@ struct sg_ctx {
     int32_t block_bits = 1;            // GREEDY block schedule in bit-sliced form where it applies
     int32_t bits_groups = 8;           // most groups of 32 restarts per bit-sliced workgroup (2, 4, 8, 16)
     int32_t fm_key32 = 1;              // FM moves chosen on 32-bit keys where the gains allow
+    int32_t fm_waves = 0;              // most wavefronts per FM workgroup (0 = 16); the most resident are taken
+    int32_t last_fm_waves = 0;         // what the last FM call used
     int32_t defer_energy = 1;          // a drawn start whose run computes final energies gets its energy later
     int32_t last_key32 = 0;            // the last FM call used 32-bit keys
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
@@ -1514,9 +1516,26 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     for (const HostInst& q : H->insts)
         stage = std::max(stage, q.slices.size() * sizeof(sg::Slice) + q.nbr.size() * 4 + (tri ? q.ta.size() * 8 : 0));
     stage = (stage + 15) / 16 * 16;
-    int waves = 16;
-    while (waves > 1 && sg::fm_lds_bytes(nmax, waves) + stage > kLdsBudget) --waves;
-    if (sg::fm_lds_bytes(nmax, waves) + stage > kLdsBudget) stage = 0;  // too large to stage: read from memory
+    // wavefronts per workgroup: the most resident wavefronts per compute unit
+    // (several smaller workgroups can share one), staging the instance where
+    // it fits; among equals the smallest multiple of four (its wavefronts
+    // spread evenly over the four SIMDs; on 4096 Chimera instances x 256
+    // restarts 8 wavefronts took 1.28 s against 1.40 s with 16, the same
+    // 16 resident); fm_waves bounds the count
+    if (sg::fm_lds_bytes(nmax, 1) + stage > kLdsBudget) stage = 0;  // too large to stage: read from memory
+    int waves = 0, resident = -1;
+    for (int w = 16; w >= 1; --w) {
+        if (H->fm_waves && w > H->fm_waves) continue;
+        const size_t lds = sg::fm_lds_bytes(nmax, w) + stage;
+        if (lds > kLdsBudget) continue;
+        const int r = w * sg::fm_max_blocks_per_cu(w, lds, tri, key32);
+        if (r > resident || (r == resident && w % 4 == 0)) {
+            resident = r;
+            waves = w;
+        }
+    }
+    if (waves == 0) return fail(SG_EINVAL, "rule SG_RULE_FM: no workgroup size fits LDS (fm_waves %d)", H->fm_waves);
+    H->last_fm_waves = waves;
     sg::QueueItem* dit = H->at<sg::QueueItem>(H->off_qitems);
     uint32_t* err = H->at<uint32_t>(H->off_err);
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
@@ -2175,6 +2194,9 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "lattice_wg_max_n") {
         if (value < 0 || value > 150000) return fail(SG_EINVAL, "lattice_wg_max_n must be in [0,150000]");
         H->lattice_wg_max_n = (int32_t)value;
+    } else if (k == "fm_waves") {
+        if (value < 0 || value > 16) return fail(SG_EINVAL, "fm_waves must be in [0,16]");
+        H->fm_waves = (int32_t)value;
     } else if (k == "fm_key32") {
         if (value != 0 && value != 1) return fail(SG_EINVAL, "fm_key32 must be 0 or 1");
         H->fm_key32 = (int32_t)value;
@@ -2237,6 +2259,8 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "block_rg") *value = H->block_rg;
     else if (k == "block_groups") *value = H->block_groups;
     else if (k == "block_bits") *value = H->block_bits;
+    else if (k == "fm_waves") *value = H->fm_waves;
+    else if (k == "last_fm_waves") *value = H->last_fm_waves;
     else if (k == "defer_energy") *value = H->defer_energy;
     else if (k == "energy_pending") *value = H->e_pending ? 1 : 0;
     else if (k == "fm_key32") *value = H->fm_key32;

@@ -48,6 +48,9 @@ hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* 
                               int nslots, int T, uint64_t seed, int rule, hipStream_t st);
 // The paper's pass-based search, one wavefront per replica item.
 size_t fm_lds_bytes(int nmax, int waves);
+// Workgroups of `waves` wavefronts of the pass kernel with this much LDS
+// that fit one compute unit at once.
+int fm_max_blocks_per_cu(int waves, size_t lds, bool tri, bool key32);
 // stage_cap: LDS bytes after the wavefronts' slices in which a block stages
 // its instance's structure when all its items share one instance.
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,

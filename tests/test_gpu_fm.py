@@ -25,11 +25,13 @@ def _oracle(insts, seed, max_passes, uc, runs=None, threads=0):
     return out
 
 
-def _check(insts, seed, max_passes=1000, uc=True, runs=None, key32=1):
+def _check(insts, seed, max_passes=1000, uc=True, runs=None, key32=1, waves=0):
     import paper_0912_3912_amd as sg
-    log(f"fm case: {[i.name for i in insts][:4]} seed={seed} passes={runs or max_passes} uc={uc} key32={key32}")
+    log(f"fm case: {[i.name for i in insts][:4]} seed={seed} passes={runs or max_passes} uc={uc} key32={key32} "
+        f"waves={waves}")
     h = sg.load_instance(list(insts))
     h.tune("fm_key32", key32)
+    h.tune("fm_waves", waves)
     h.bind()
     h.init_spins(seed)
     stats = [h.run_sweeps(seed=seed, rule=FM, max_sweeps=mp, until_converged=uc) for mp in (runs or [max_passes])]
@@ -77,10 +79,14 @@ def test_fixed_pass_budget_and_resume(gpu):
     _check([inst], seed=2, uc=True, runs=[1, 2, 0, 1000])
 
 
-def test_mixed_batch(gpu):
+@pytest.mark.parametrize("waves", [0, 1, 3, 8, 16])
+def test_mixed_batch(gpu, waves):
+    """Mixed sizes in one call, for several workgroup sizes (0: chosen by
+    occupancy): blocks that stage one instance and blocks that read several
+    from memory."""
     insts = [gen.chimera(6, 6, seed=s, instance_id=s, restarts=3) for s in range(3)]
     insts += [gen.random_small(40, seed=1, instance_id=77).replace(restarts=2), gen.erdos_renyi_triples(3000, seed=8)]
-    _check(insts, seed=9)
+    _check(insts, seed=9, waves=waves)
 
 
 def test_errors(gpu):

@@ -154,13 +154,13 @@ def test_knobs(sg):
                  ("block_min_restarts", 8), ("queue_wave_max_n", 2048), ("queue_grid", 100),
                  ("queue_min_items", 4), ("graph_sweeps", 64), ("lattice_msc", 0), ("msc_k", 9),
                  ("block_groups", 3), ("block_bits", 0), ("bits_groups", 8), ("fm_key32", 0),
-                 ("defer_energy", 0)]:
+                 ("defer_energy", 0), ("fm_waves", 8)]:
         h.tune(k, v)
         assert h.query(k) == v
     for k, v in [("lattice_k", 0), ("lattice_k", 17), ("block_rg", 100), ("queue_wave_max_n", 20000),
                  ("graph_sweeps", 0), ("graph_sweeps", 1025), ("lattice_msc", 2), ("msc_k", 63),
                  ("block_groups", 65), ("block_groups", -1), ("block_bits", 2), ("bits_groups", 3), ("fm_key32", 2),
-                 ("defer_energy", 2), ("no_such_knob", 1)]:
+                 ("defer_energy", 2), ("fm_waves", 17), ("fm_waves", -1), ("no_such_knob", 1)]:
         with pytest.raises(sg.SGError) as e:
             h.tune(k, v)
         assert e.value.status == sg.SG_EINVAL
