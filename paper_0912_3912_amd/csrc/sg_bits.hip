@@ -15,11 +15,12 @@
 // of magnitude at most 15 (4-bit weights) and W_i <= 255 keep the counter
 // within 8 bits; the host routes other instances to the byte kernel.
 //
-// One wavefront per group of 32 restarts, NG groups per workgroup.  Restarts
-// sweep in groups of 32 in lockstep; a restart that stops
-// (converged, or out of sweeps) is masked out of its group, and a group whose
-// restarts have all stopped writes its spins back and takes the next 32
-// restarts of the workgroup's range.  Flip counts per restart are kept as
+// One wavefront per group of 32 restarts, NG groups per workgroup; each
+// wavefront runs its own groups, without waiting for the others.  The 32
+// restarts of a group sweep in lockstep; a restart that stops (converged, or
+// out of sweeps) is masked out of its group, and a group whose restarts have
+// all stopped writes its spins back and takes the next 32 restarts of the
+// workgroup's range.  Flip counts per restart are kept as
 // bit-sliced counters per lane and summed over lanes with ballots.  Energies
 // are not tracked incrementally: a finished group computes them from its
 // final spins and the instance's term list (the same integer the incremental
