@@ -126,6 +126,8 @@ struct sg_ctx {
     int32_t fm_key32 = 1;              // FM moves chosen on 32-bit keys where the gains allow
     int32_t fm_waves = 0;              // most wavefronts per FM workgroup (0 = 16); the most resident are taken
     int32_t last_fm_waves = 0;         // what the last FM call used
+    std::array<int64_t, 5> fm_key{{-1, -1, -1, -1, -1}};  // setting of the cached FM workgroup size
+    int32_t fm_waves_cached = 0;
     int32_t defer_energy = 1;          // a drawn start whose run computes final energies gets its energy later
     int32_t last_key32 = 0;            // the last FM call used 32-bit keys
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
@@ -1523,15 +1525,25 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     // restarts 8 wavefronts took 1.28 s against 1.40 s with 16, the same
     // 16 resident); fm_waves bounds the count
     if (sg::fm_lds_bytes(nmax, 1) + stage > kLdsBudget) stage = 0;  // too large to stage: read from memory
-    int waves = 0, resident = -1;
-    for (int w = 16; w >= 1; --w) {
-        if (H->fm_waves && w > H->fm_waves) continue;
-        const size_t lds = sg::fm_lds_bytes(nmax, w) + stage;
-        if (lds > kLdsBudget) continue;
-        const int r = w * sg::fm_max_blocks_per_cu(w, lds, tri, key32);
-        if (r > resident || (r == resident && w % 4 == 0)) {
-            resident = r;
-            waves = w;
+    const std::array<int64_t, 5> fkey{{nmax, (int64_t)stage, tri ? 1 : 0, key32 ? 1 : 0, H->fm_waves}};
+    int waves = 0;
+    if (H->fm_key == fkey) {
+        waves = H->fm_waves_cached;
+    } else {
+        int resident = -1;
+        for (int w = 16; w >= 1; --w) {
+            if (H->fm_waves && w > H->fm_waves) continue;
+            const size_t lds = sg::fm_lds_bytes(nmax, w) + stage;
+            if (lds > kLdsBudget) continue;
+            const int r = w * sg::fm_max_blocks_per_cu(w, lds, tri, key32);
+            if (r > resident || (r == resident && w % 4 == 0)) {
+                resident = r;
+                waves = w;
+            }
+        }
+        if (waves > 0) {
+            H->fm_key = fkey;
+            H->fm_waves_cached = waves;
         }
     }
     if (waves == 0) return fail(SG_EINVAL, "rule SG_RULE_FM: no workgroup size fits LDS (fm_waves %d)", H->fm_waves);
