@@ -153,7 +153,6 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
     int8_t* lds = reinterpret_cast<int8_t*>(lds64);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ int s_item;
-    __shared__ int s_flips;
     // ---- large items: the whole workgroup on one replica
     for (;;) {
         if (tid == 0) s_item = (int)atomicAdd(&counters[0], 1u);
@@ -170,7 +169,6 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
         if (frozen) continue;
         const uint32_t base = (uint32_t)st0->sweeps;
         for (int k = tid; k < I.n; k += kBatThreads) lds[k] = gsp[k];
-        if (tid == 0) s_flips = 0;
         __syncthreads();
         long long dE = 0, e6 = 0;
         int nflip = 0, performed = 0, lastflip = 0;
@@ -180,20 +178,14 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
             for (int c = 0; c < Q.C; ++c) {
                 queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], lds, wave, kBatWaves,
                                  lane, base + t, seed, (uint32_t)it.r, dE, my, e6);
-                __syncthreads();
+                if (c + 1 < Q.C) __syncthreads();
             }
             nflip += my;
             performed = t + 1;
-            int wsum = my;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
-            if (lane == 0 && wsum) atomicAdd(&s_flips, wsum);
-            __syncthreads();
-            const int tot = s_flips;
-            __syncthreads();
-            if (tid == 0) s_flips = 0;
+            // the last colour's barrier also tells whether the sweep flipped anything
+            const bool tot = __syncthreads_or(my != 0);
             if (tot) lastflip = t + 1;
-            if (until_conv && tot == 0) break;
+            if (until_conv && !tot) break;
         }
         for (int k = tid; k < I.n; k += kBatThreads) gsp[k] = lds[k];
         // fold the workgroup's dE, energy sum and flips
