@@ -370,6 +370,18 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
  * per-phase launches, and how many launches that span holds). */
 sg_status sg_query(sg_handle h, const char* key, int64_t* value);
 
+/* The device generator behind every random start and tie decision, exposed
+ * so that it can be checked against published values: word 0 of
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11; ten rounds, key = seed:
+ * low word, high word) for `count` counters.
+ *   dev_ctr     device memory, 4 x count uint32: counter words 0..3 of each
+ *   dev_out     device memory, count uint32 (written)
+ *   hip_stream  hipStream_t the kernel runs on (NULL = default stream); the
+ *               call returns after the stream has finished it
+ * Both buffers are caller-owned and 4-byte aligned.  Errors: SG_EINVAL (bad
+ * count, null or misaligned pointer), SG_EDEVICE. */
+sg_status sg_philox_word0(const void* dev_ctr, void* dev_out, int64_t count, uint64_t seed, void* hip_stream);
+
 /* Release the handle (not the caller's device memory).  NULL is allowed. */
 sg_status sg_free(sg_handle h);
 

@@ -11,11 +11,10 @@ Sec. IV/Fig. 3.  The colour-ordered schedule, tie rule and counter-based RNG
 are this project's readings (see the C file's header).
 
 Pins (what checks this oracle against something other than itself) live in
-``tests/test_oracle_pins.py``.  The exact Philox bit stream has no published
-known-answer vector available here: it is pinned only by agreement with the
-independent device implementation and by frequency tests ("parity unpinned"
-for the raw stream; every result that depends on it is still pinned by the
-invariants).
+``tests/test_oracle_pins.py``, ``tests/test_oracle_fm.py``,
+``tests/test_factoring.py`` and ``tests/test_oracle_philox.py``; the last pins
+the Philox4x32-10 generator to its published known-answer vectors and to the
+independent engine of rocRAND's source header.
 """
 from __future__ import annotations
 

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Optional, Sequence
 
 import numpy as np
@@ -100,6 +101,7 @@ SIGNATURES = [
     ("sg_best", ctypes.c_int32, [_P, _P, _P]),
     ("sg_tune", ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
     ("sg_query", ctypes.c_int32, [_P, ctypes.c_char_p, _P]),
+    ("sg_philox_word0", ctypes.c_int32, [_P, _P, ctypes.c_int64, ctypes.c_uint64, _P]),
     ("sg_free", ctypes.c_int32, [_P]),
     ("sg_last_error", ctypes.c_char_p, []),
     ("sg_version", ctypes.c_char_p, []),
@@ -321,6 +323,12 @@ class Handle:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
+        # A handle still alive at interpreter shutdown is left to the process
+        # exit: by then the HIP runtime, and any profiler attached to it, may
+        # already be finalised, so sg_free's event and stream destruction
+        # would call into a torn-down runtime.  Call free() explicitly.
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -371,6 +379,22 @@ def load_dense(instances) -> Handle:
     if not isinstance(instances, (list, tuple)):
         instances = [instances]
     return Handle(instances, dense=True)
+
+
+def philox_word0(ctr, seed: int):
+    """Word 0 of Philox4x32-10 computed on the GPU for an (N, 4) uint32 torch
+    device tensor of counters under key ``seed``; returns an (N,) tensor."""
+    import torch
+    if ctr.dtype != torch.int32 and ctr.dtype != torch.uint32:
+        raise TypeError("counters must be a 32-bit integer tensor")
+    ctr = ctr.contiguous()
+    if ctr.dim() != 2 or ctr.shape[1] != 4 or not ctr.is_cuda:
+        raise ValueError("counters must be an (N, 4) device tensor")
+    out = torch.empty(ctr.shape[0], dtype=ctr.dtype, device=ctr.device)
+    sp = torch.cuda.current_stream(ctr.device).cuda_stream
+    _check(lib().sg_philox_word0(ctypes.c_void_p(ctr.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctr.shape[0],
+                                 seed & 0xFFFFFFFFFFFFFFFF, ctypes.c_void_p(sp)))
+    return out
 
 
 def run_sweeps(handle: Handle, **kw) -> dict:

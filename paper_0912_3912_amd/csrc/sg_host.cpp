@@ -2299,6 +2299,17 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     return SG_OK;
 }
 
+sg_status sg_philox_word0(const void* dev_ctr, void* dev_out, int64_t count, uint64_t seed, void* hip_stream)
+{
+    if (count < 0) return fail(SG_EINVAL, "count must be >= 0");
+    if (count > 0 && (!dev_ctr || !dev_out)) return fail(SG_EINVAL, "null device pointer");
+    if (((uintptr_t)dev_ctr & 3) || ((uintptr_t)dev_out & 3)) return fail(SG_EINVAL, "pointers must be 4-byte aligned");
+    hipStream_t st = (hipStream_t)hip_stream;
+    SG_HIP(sg::launch_philox_word0((const uint32_t*)dev_ctr, (uint32_t*)dev_out, count, seed, st), "philox kernel");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    return SG_OK;
+}
+
 sg_status sg_free(sg_handle H)
 {
     if (!H) return SG_OK;

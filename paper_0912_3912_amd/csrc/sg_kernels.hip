@@ -347,6 +347,16 @@ __global__ void k_any_active(const RepState* __restrict__ rs, int R, int T, uint
     if (r < R && !rs[r].converged && rs[r].lastflip >= T) *flag = 1u;
 }
 
+// Word 0 of Philox4x32-10 for count counters (4 words each), key = seed: the
+// generator behind every start and tie decision, exposed for checking.
+__global__ void k_philox_word0(const uint32_t* __restrict__ ctr, uint32_t* __restrict__ out, int64_t count,
+                               uint64_t seed)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = philox_word0(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], (uint32_t)seed,
+                              (uint32_t)(seed >> 32));
+}
+
 // Multi-start result per instance: lowest tracked energy, lowest restart on ties.
 __global__ void k_best(const RepState* __restrict__ rs, const int64_t* __restrict__ rep_base,
                        const int32_t* __restrict__ restarts, int ninst, int64_t* __restrict__ Eb,
@@ -459,6 +469,14 @@ hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T
 hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, hipStream_t st)
 {
     hipLaunchKernelGGL(k_any_active, dim3(grid1(R, 256, 1u << 30)), dim3(256), 0, st, rs, R, T, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_word0(const uint32_t* ctr, uint32_t* out, int64_t count, uint64_t seed, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_word0, dim3(grid1((uint64_t)count, 256, 8192)), dim3(256), 0, st, ctr, out, count,
+                       seed);
     return hipGetLastError();
 }
 

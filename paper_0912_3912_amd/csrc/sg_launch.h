@@ -27,6 +27,8 @@ hipError_t launch_bump(int32_t* t_base, int d, hipStream_t st);
 hipError_t launch_end(RepState* rs, int R, const int64_t* acc, int nslots, int T, int until_conv, int64_t n,
                       CallStats* cs, hipStream_t st, bool absolute = false);
 hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, hipStream_t st);
+// Word 0 of Philox4x32-10 of count counters (4 uint32 each) under key seed.
+hipError_t launch_philox_word0(const uint32_t* ctr, uint32_t* out, int64_t count, uint64_t seed, hipStream_t st);
 hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_t* restarts, int ninst,
                        int64_t* Eb, int32_t* rb, hipStream_t st);
 

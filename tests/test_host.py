@@ -25,7 +25,7 @@ def sg():
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "sg.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sg_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported(sg):
