@@ -24,8 +24,13 @@ Workloads (--workload):
                Chimera with hyper-couplings, 3-regular), n log-uniform in
                [1e3, 1e6], admitted by HBM footprint into a device pool,
                rate 0.7 x the measured capacity; p50/p99 latency, flips/s.
-The default run also measures the Chimera batch against per-instance
-per-phase launches (the plain method) and reports the speedup.
+The default run measures the headline lattice and then every other workload
+of the configuration list as a leg of the same JSON line: ``square16`` (the
+small lattice, microseconds per solve), ``batched`` (the Chimera batch against
+per-instance per-phase launches), ``uneven`` (the 2000 uneven instances
+against the per-phase method on every instance) and ``serving``.  Every leg
+carries the roofline position of its dominant kernel and the CPU oracle timed
+on a stated sample (``cpu_baseline``).
 
 Prints one JSON line.  Only one GPU is supported.
 """
@@ -113,6 +118,39 @@ def measured_traffic(kernel: str, geometry=None):
     return rec["bytes_per_launch"]
 
 
+def host_cores() -> int:
+    """Host threads the CPU baselines use: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS and at 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_parallel(jobs, cores):
+    """Run oracle calls (callables) on `cores` host threads; the oracle's C
+    functions run without the interpreter lock."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        return list(ex.map(lambda f: f(), jobs))
+
+
 def timed(fn, steps, warmup, sync):
     for _ in range(warmup):
         fn()
@@ -158,27 +196,53 @@ def run_cubic(args, sg, gen, torch):
         plain_ms *= 1e3
         log(f"plain per-phase method: {plain_ms:.3f} ms/step")
 
-    ops = int_ops_per_attempt(6)
-    per_launch_s = hot_us / 1e6 / max(launches, 1)
-    achieved = ops * attempts / max(launches, 1) / per_launch_s / 1e12
-    bpa = sell_bytes_per_attempt(6)
+    launches = max(launches, 1)
+    per_launch_s = hot_us / 1e6 / launches
+    apl = attempts // launches
     kname = KERNEL_NAME.get(sched, str(sched))
     if sched == 3 and h.query("last_msc"):
         kname = "k_lattice_msc"
     geometry = {"tiles": h.query("last_tiles"), "halo_k": h.query("last_tile_k")}
     traffic = measured_traffic(kname, geometry) if sched == 3 else None
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 2), "unit": "TOP/s",
-                "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": kname, "ops_per_attempt": ops,
-                "attempts_per_launch": attempts // max(launches, 1), "launches_per_step": launches,
-                "avg_launch_us": round(hot_us / max(launches, 1), 2),
-                "hbm_equiv": {"bytes_per_attempt": bpa, "GB/s": round(bpa * value / 1e9, 1),
-                              "frac": round(bpa * value / 1e9 / PEAK_HBM_GBS, 4),
-                              "note": "bytes a streaming sliced-CSR sweep moves per attempt, at this attempt rate",
-                              "models": {name: {"bytes_per_attempt": b, "frac": round(b * value / 1e9 / PEAK_HBM_GBS, 4)}
-                                         for name, b in (("csr_int32_index_int8_J", CSR_BYTES_PER_ATTEMPT),
-                                                         ("compact_lattice", COMPACT_BYTES_PER_ATTEMPT))}}}
+    # Survey's compact-lattice model (implicit neighbours, int8 couplings and
+    # field) for the tile kernels, the sliced-layout model otherwise.
+    bpa = COMPACT_BYTES_PER_ATTEMPT if sched == 3 else sell_bytes_per_attempt(6)
+    ach = bpa * apl / per_launch_s / 1e9
+    ops = int_ops_per_attempt(6)
+    alu = ops * apl / per_launch_s / 1e12
+    roofline = {
+        "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kname,
+        "model": ("compact lattice: 10 B per attempt (six int8 couplings, int8 field, own spin read and written, "
+                  "the other colour's spins once)") if sched == 3 else
+                 "sliced coupling layout: 4 B per coupling word, int8 field, own spin read and written, neighbours once",
+        "bytes_per_attempt": bpa, "attempts_per_launch": apl, "launches_per_step": launches,
+        "avg_launch_us": round(hot_us / launches, 2),
+        "traffic_source": None if traffic is None else (
+            "profiles/traffic.json: rocprofv3 FETCH_SIZE and WRITE_SIZE of this kernel at this tiling, scaled by a "
+            "plain-copy calibration, taken by a profiled run of this command (not in this run); it is dropped "
+            "(null) as soon as a source of the kernel changes"),
+        "counter_GBps": None if traffic is None else round(traffic / per_launch_s / 1e9, 1),
+        "counter_frac": None if traffic is None else round(traffic / per_launch_s / 1e9 / PEAK_HBM_GBS, 4),
+        "csr_model": {"bytes_per_attempt": CSR_BYTES_PER_ATTEMPT,
+                      "frac": round(CSR_BYTES_PER_ATTEMPT * apl / per_launch_s / 1e9 / PEAK_HBM_GBS, 4),
+                      "note": "the survey's CSR stream model; this kernel streams no CSR structure, so it is not "
+                              "a bandwidth figure"},
+        "alu": {"ops_per_attempt": ops, "achieved_TOPs": round(alu, 3), "peak_TOPs": round(PEAK_INT_TOPS, 2),
+                "frac": round(alu / PEAK_INT_TOPS, 4),
+                "note": "algorithmic integer operations; the bit-plane kernel decides 32 sites per word operation"},
+    }
+    if kname == "k_lattice_msc":
+        ph_us = h.query("last_model_phase_ns") / 1e3
+        ex_us = h.query("last_model_exchange_ns") / 1e3
+        nph, nex = h.query("last_model_phases"), h.query("last_model_exchanges")
+        pred = ph_us * nph + ex_us * nex
+        roofline["limiter"] = "latency"
+        roofline["latency_model"] = {
+            "phase_us": round(ph_us, 3), "exchange_us": round(ex_us, 3), "phases": nph, "exchanges": nex,
+            "predicted_us": round(pred, 1), "measured_us": round(hot_us / launches, 1),
+            "note": "the launch is a dependent chain of colour phases (LDS loads, decision, tie draws, barrier) "
+                    "and halo exchanges between tiles; the tiling's fitted cost model predicts its time"}
     cpu = None
     if args.cpu_sweeps > 0:
         import oracle
@@ -244,13 +308,33 @@ def run_chimera(args, sg, gen, torch, count=4096, sample=16):
         hs.free()
     ops = int_ops_per_attempt(deg, tau)
     ach = ops * attempts / (hot_us / 1e6) / 1e12
+    cpu = None
+    if args.cpu_sweeps > 0:
+        import oracle
+        cores = host_cores()
+        cpu_sample = insts[:min(args.cpu_chimera, count)]
+        t1 = time.perf_counter()
+        catt = 0
+        for inst in cpu_sample:
+            sto, _ = oracle.run(inst, seed=args.seed, rule=oracle.GREEDY, max_sweeps=10000, until_converged=True,
+                                threads=cores)
+            catt += int(sto.sweeps.sum()) * inst.n
+        ct = time.perf_counter() - t1
+        cpu = {"value": catt / ct, "unit": "attempts/s", "cores": cores, "kind": "oracle",
+               "sample": f"instances 0..{len(cpu_sample) - 1} of the {count}, all 256 restarts each, GREEDY until "
+                         f"converged ({catt:.3g} attempts in {ct:.1f} s; restarts spread over {cores} threads of "
+                         f"{cpu_model()}, nproc {os.cpu_count()})"}
+        log(f"chimera cpu oracle: {cpu['value']:.3e} attempts/s on {cores} threads")
     return {"workload": f"chimera{count}x256_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
             "attempts": attempts, "schedule": st["schedule_used"],
             "per_instance_ms": None if extrap is None else round(extrap * 1e3, 2), "per_instance_sample": sample,
             "per_instance_extrapolated": True, "speedup": None if extrap is None else round(extrap / dt, 2),
             "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(PEAK_INT_TOPS, 2),
                          "unit": "TOP/s", "frac": round(ach / PEAK_INT_TOPS, 4), "kernel": kname,
-                         "ops_per_attempt": round(ops, 2)}}
+                         "ops_per_attempt": round(ops, 2),
+                         "note": "instance and restarts stay in LDS, so HBM carries only the structure and the "
+                                 "spins read out; algorithmic integer operations against the int32 VALU issue rate"},
+            "cpu_baseline": cpu}
 
 
 def fm_ops_per_move(n: float, deg: float, tau: float) -> float:
@@ -385,19 +469,51 @@ def run_er(args, sg, gen, torch, count=2000):
     ntot = sum(i.n for i in insts)
     deg = sum(2 * i.m for i in insts) / ntot
     tau = sum(3 * i.t for i in insts) / ntot
+    # the layout's own bytes (coupling and hyper-coupling words, field; spins in LDS)
     bpa = sell_bytes_per_attempt(deg, tau, spins_in_lds=True)
+    # the survey's CSR model: row pointers (edges and triples), deg (4 + 1), tau (2 * 4 + 1), field, own spin
+    # read and written, other spins once
+    bpa_csr = 4 + 4 + deg * 5 + tau * 9 + 1 + 2 + 1
     ach = bpa * attempts / (hot_us / 1e6) / 1e9
+    traffic = measured_traffic("k_queue")
     log(f"batched {dt * 1e3:.2f} ms, hot {hot_us:.0f} us"
         + ("" if dtp is None else f", per-instance per-phase {dtp * 1e3:.1f} ms, speedup {dtp / dt:.2f}"))
     h.free()
+    cpu = None
+    if args.cpu_sweeps > 0:
+        import oracle
+        cores = host_cores()
+        order = sorted(range(len(insts)), key=lambda k: -insts[k].n)  # largest first balances the threads
+        t1 = time.perf_counter()
+        res = oracle_parallel([lambda k=k: oracle.run(insts[k], seed=args.seed, rule=oracle.GREEDY, max_sweeps=10000,
+                                                      until_converged=True, threads=1)[0] for k in order], cores)
+        ct = time.perf_counter() - t1
+        catt = sum(int(r.sweeps.sum()) * insts[k].n for r, k in zip(res, order))
+        assert catt == attempts, (catt, attempts)
+        cpu = {"value": catt / ct, "unit": "attempts/s", "cores": cores, "kind": "oracle",
+               "sample": f"all {count} instances, one per task on {cores} threads of {cpu_model()} (nproc "
+                         f"{os.cpu_count()}), GREEDY until converged ({catt:.3g} attempts in {ct:.1f} s)"}
+        log(f"er cpu oracle: {cpu['value']:.3e} attempts/s on {cores} threads")
+    algo_launch = bpa * attempts
     return {"workload": f"er{count}_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
             "attempts": attempts, "schedule": st["schedule_used"],
             "per_instance_ms": None if dtp is None else round(dtp * 1e3, 2),
             "per_instance_extrapolated": False, "speedup": None if dtp is None else round(dtp / dt, 2),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": "k_queue",
-                         "bytes_per_attempt": round(bpa, 2), "traffic": measured_traffic("k_queue"),
-                         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}}
+                         "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": "k_queue", "avg_launch_us": round(hot_us, 1),
+                         "bytes_per_attempt": round(bpa, 2),
+                         "model": "the sliced layout's own stream: 4 B per coupling word, 8 B per hyper-coupling "
+                                  "incidence, 1 B field (spins in LDS)",
+                         "survey_model": {"bytes_per_attempt": round(bpa_csr, 2),
+                                          "frac": round(bpa_csr * attempts / (hot_us / 1e6) / 1e9 / PEAK_HBM_GBS, 4)},
+                         "traffic": traffic,
+                         "traffic_source": None if traffic is None else (
+                             "profiles/traffic.json: rocprofv3 FETCH_SIZE and WRITE_SIZE of this kernel on this "
+                             "workload, copy-calibrated, taken by a profiled run (not in this run)"),
+                         "traffic_over_model": None if traffic is None else round(traffic / algo_launch, 3),
+                         "counter_frac": None if traffic is None else round(
+                             traffic / (hot_us / 1e6) / 1e9 / PEAK_HBM_GBS, 4)},
+            "cpu_baseline": cpu}
 
 
 def run_square(args, sg, gen, torch):
@@ -410,12 +526,44 @@ def run_square(args, sg, gen, torch):
         h.best()
         return st
 
-    dt, outs = timed(step, args.steps, args.warmup, torch.cuda.synchronize)
-    dtp, _ = timed(lambda: step(SCHED_PHASE), 3, 1, torch.cuda.synchronize)
+    def step_hot():
+        st = step()
+        st["hot_ns"] = h.query("hot_ns")
+        return st
+
+    dt, outs = timed(step_hot, max(args.steps, 20), args.warmup, torch.cuda.synchronize)
+    dtp, _ = timed(lambda: step(SCHED_PHASE), 5, 1, torch.cuda.synchronize)
     st = outs[-1]
+    hot_us = sum(o["hot_ns"] for o in outs) / len(outs) / 1e3
+    h.free()
+    ops = int_ops_per_attempt(4)
+    ach = ops * st["attempts"] / (hot_us / 1e6) / 1e12
+    cpu = None
+    if args.cpu_sweeps > 0:
+        import oracle
+        reps, catt = 0, 0
+        t1 = time.perf_counter()
+        while True:
+            sto, _ = oracle.run(inst, seed=args.seed, rule=oracle.GREEDY, max_sweeps=10000, until_converged=True,
+                                threads=1)
+            catt += int(sto.sweeps.sum()) * inst.n
+            reps += 1
+            if time.perf_counter() - t1 > 1.0:
+                break
+        ct = time.perf_counter() - t1
+        cpu = {"value": catt / ct, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+               "us_per_solve": ct / reps * 1e6,
+               "sample": f"the whole 64-start solve, repeated {reps} times on one core ({catt:.3g} attempts in "
+                         f"{ct:.2f} s)"}
     return {"workload": "square16_64starts_greedy", "attempts_per_s": st["attempts"] / dt,
-            "us_per_solve": dt * 1e6, "attempts": st["attempts"], "schedule": st["schedule_used"],
-            "per_phase_us_per_solve": dtp * 1e6, "speedup": round(dtp / dt, 2)}
+            "us_per_solve": dt * 1e6, "ms_per_step": dt * 1e3, "attempts": st["attempts"],
+            "schedule": st["schedule_used"], "per_phase_us_per_solve": dtp * 1e6, "speedup": round(dtp / dt, 2),
+            "roofline": {"bound": "alu", "achieved": round(ach, 4), "peak": round(PEAK_INT_TOPS, 2), "unit": "TOP/s",
+                         "frac": round(ach / PEAK_INT_TOPS, 5), "kernel": "k_lattice_wg",
+                         "avg_launch_us": round(hot_us, 2), "ops_per_attempt": ops, "limiter": "latency",
+                         "note": "256 spins x 64 starts occupy a handful of workgroups: the solve is bound by launch "
+                                 "and phase latency, not by any throughput roof"},
+            "cpu_baseline": cpu}
 
 
 def run_serving(args, sg, gen, torch):
@@ -450,8 +598,36 @@ def run_serving(args, sg, gen, torch):
                  "max_resident_requests": max(t[2] for t in server2.timeline)})
     log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['flips_per_s']:.3g} flips/s")
     summ["workload"] = f"serving{count}_mixed_greedy"
-    summ["attempts_per_s"] = summ["attempts_per_s"]
     summ["ms_per_step"] = wall * 1e3
+    # algorithmic bytes of the sliced layout per attempt, request by request
+    tot_b = 0.0
+    for inst, r in zip(insts, results):
+        if r.status in ("ok", "notconv"):
+            n = inst.n
+            tot_b += sell_bytes_per_attempt(2 * inst.m / n, 3 * inst.t / n) * r.attempts
+    gbps = tot_b / wall / 1e9
+    summ["roofline"] = {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbps / PEAK_HBM_GBS, 5), "kernel": "mixed (per-request schedules)",
+                        "model": "sliced layout per request: 4 B per coupling word, 8 B per hyper-coupling "
+                                 "incidence, field, own spin read and written, neighbours once",
+                        "note": "over the whole trace's wall time, including the gaps between Poisson arrivals "
+                                "(the offered load is 0.7 of capacity)"}
+    if args.cpu_sweeps > 0:
+        import oracle
+        cores = host_cores()
+        order = sorted(range(len(insts)), key=lambda k: -insts[k].n)
+        t1 = time.perf_counter()
+        res = oracle_parallel([lambda k=k: oracle.run(insts[k], seed=args.seed, rule=oracle.GREEDY, max_sweeps=10000,
+                                                      until_converged=True, threads=1)[0] for k in order], cores)
+        ct = time.perf_counter() - t1
+        catt = sum(int(r.sweeps.sum()) * insts[k].n for r, k in zip(res, order))
+        gpu_att = sum(r.attempts for r in results if r.status in ("ok", "notconv"))
+        summ["cpu_baseline"] = {
+            "value": catt / ct, "unit": "attempts/s", "cores": cores, "kind": "oracle",
+            "requests_per_s": len(insts) / ct, "same_attempts_as_gpu": catt == gpu_att,
+            "sample": f"the same {count} requests replayed back to back, one per task on {cores} threads of "
+                      f"{cpu_model()} (nproc {os.cpu_count()}), throughput only ({catt:.3g} attempts in {ct:.1f} s)"}
+        log(f"serving cpu oracle: {catt / ct:.3e} attempts/s on {cores} threads")
     return summ
 
 
@@ -471,6 +647,10 @@ def main():
                     help="sweeps of the CPU oracle sample (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the Chimera batch in the default run")
+    ap.add_argument("--legs", default="square16,batched,uneven,serving",
+                    help="comma-separated workloads measured after the headline in the default run")
+    ap.add_argument("--cpu-chimera", type=int, default=2048,
+                    help="Chimera instances (x 256 restarts) in the batched leg's CPU oracle sample")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the per-phase comparison runs (the plain method and per-instance baselines)")
     ap.add_argument("--serving-requests", type=int, default=200)
@@ -502,8 +682,14 @@ def main():
         return
     if args.workload == "cubic100":
         out = run_cubic(args, sg, gen, torch)
-        if not args.no_batched:
-            out["batched"] = run_chimera(args, sg, gen, torch)
+        legs = [x for x in args.legs.split(",") if x]
+        if args.no_batched and "batched" in legs:
+            legs.remove("batched")
+        for leg in legs:
+            fn = {"square16": run_square, "batched": run_chimera, "uneven": run_er, "serving": run_serving}[leg]
+            t_leg = time.perf_counter()
+            out[leg] = fn(args, sg, gen, torch)
+            log(f"leg {leg} done in {time.perf_counter() - t_leg:.1f} s")
     else:
         fn = {"square16": run_square, "chimera4096": run_chimera, "chimera4096_fm": run_chimera_fm,
               "er2000": run_er, "serving": run_serving, "factoring": run_factoring}[args.workload]

@@ -115,8 +115,15 @@ typedef struct sg_ctx* sg_handle;
  *   instance_id  RNG key word of the instance; keep it stable across
  *                batching and serving to reproduce results
  *   restarts     independent replicas of this instance, >= 1
- * Limits (SG_ERANGE beyond): n < 2^24; |J|, |h|, |K| <= 127; for every
- * spin |h_i| + sum|J_ij| + sum|K| < 2^23. */
+ * Values: any int32 coupling, field and hyper-coupling.  SG_ERANGE only when
+ * a spin's |h_i| + sum_j |J_ij| + sum |K| exceeds 2^31 - 1 (its local field
+ * would not fit int32), when sum|J| + sum|h| + sum|K| exceeds 2^63 - 1 (an
+ * energy would not fit int64), or when n exceeds 2^30.  How the library
+ * stores an instance (packed 8-bit coefficients and 24-bit indices, or a wide
+ * form for larger values, sizes and restart counts) is invisible here: every
+ * call accepts both and gives the same results; the wide form runs on
+ * SG_SCHED_PHASE and SG_SCHED_GRAPH (SG_SCHED_AUTO picks them), and
+ * SG_RULE_FM does not take it. */
 typedef struct {
     int32_t n;
     int64_t m;
@@ -177,8 +184,12 @@ typedef struct {
 } sg_instance_info;
 
 /* Validate and pack `count` instances into one handle (a batch when
- * count > 1).  Host-only: needs no GPU.  Errors: SG_EINVAL (message names the
- * instance and the problem), SG_ERANGE, SG_ENOMEM. */
+ * count > 1).  An instance is the spin glass of Sec. II (couplings J_ij on the
+ * edges of a graph and fields h_i, energy eq. (1)) with the three-spin
+ * couplings of Sec. VI eq. (5); the problem solved is Sec. II's ground-state
+ * search (find spins that minimise E).  Host-only: needs no GPU.  Errors:
+ * SG_EINVAL (message names the instance and the problem), SG_ERANGE,
+ * SG_ENOMEM. */
 sg_status sg_load_instance(const sg_instance_desc* descs, int32_t count, sg_handle* out);
 
 /* Dense hyper-Ising instance (Sec. VI eq. (5)): couplings over any set of
@@ -247,7 +258,10 @@ sg_status sg_instance_info_get(sg_handle h, int32_t inst, sg_instance_info* info
 
 /* Bind caller-owned device memory (>= sg_workspace_bytes, 256-byte aligned)
  * and a HIP stream (hipStream_t, NULL = default stream) to the handle, and
- * upload the coupling structure.  The memory must stay allocated while the
+ * upload the coupling structure: the instance of Sec. II eq. (1) / Sec. VI
+ * eq. (5) and room for the replicas' spin configurations, the state the local
+ * search of Sec. IV (Fig. 3) works on; the paper itself defines no memory
+ * layout.  The memory must stay allocated while the
  * handle uses it; binding again moves the handle (state is not kept).
  * Errors: SG_ENOMEM if too small, SG_EINVAL if misaligned, SG_EDEVICE. */
 sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
@@ -259,12 +273,17 @@ sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
 sg_status sg_init_spins(sg_handle h, uint64_t seed);
 
 /* Set replica r of instance inst to host spins s (n int8 values, each +1 or
- * -1, external order) and reset its counters.  Errors: SG_EINVAL for a value
+ * -1, external order) and reset its counters: the starting configuration of
+ * the local search (Sec. IV, Fig. 3's input), given instead of drawn; its
+ * energy is eq. (1) / eq. (5) of these spins.  Errors: SG_EINVAL for a value
  * other than +-1 or an index out of range; SG_ESTATE before bind. */
 sg_status sg_set_spins(sg_handle h, int32_t inst, int32_t r, const int8_t* s);
 
 /* Run colour-ordered sweeps on every replica that is not frozen (enqueued
- * on the bound stream; returns after the stream has finished them).
+ * on the bound stream; returns after the stream has finished them): the
+ * single-spin moves of Sec. IV with their gains -dE_i (dE_i = 2 s_i f_i), the
+ * three-spin terms entering the gains as in Sec. VI, and the stopping rule of
+ * Fig. 3 (a pass that brings no improvement ends the search).
  * stats may be NULL.  Returns SG_ENOTCONV when until_converged and a
  * replica hit max_sweeps.  Errors: SG_ESTATE before sg_init_spins or
  * sg_set_spins of every replica, SG_EINVAL for bad parameters or a schedule
@@ -273,8 +292,37 @@ sg_status sg_set_spins(sg_handle h, int32_t inst, int32_t r, const int8_t* s);
  * undefined: start again with sg_init_spins). */
 sg_status sg_run_sweeps(sg_handle h, const sg_run_params* p, sg_run_stats* stats);
 
+/* Continuous batching: one sg_run_sweeps step over the replicas of `count`
+ * handles at once, in a single launch of the persistent queue kernel, so
+ * that requests loaded and started at different times share the GPU launch
+ * by launch (a serving loop calls it repeatedly with a bounded max_sweeps and
+ * lets finished handles leave and new ones join between calls).  Each
+ * replica follows exactly the rules of sg_run_sweeps (Sec. IV moves, the
+ * stopping rule of Fig. 3, the absolute sweep count in the RNG counter), so
+ * its result does not depend on the other handles of the group, on how many
+ * calls its sweeps are split over, or on the schedule.
+ *   hs, count      distinct bound handles, all bound to the same stream (the
+ *                  launch runs on it), every replica started; every instance
+ *                  at most 150000 spins in the packed form (sg_query
+ *                  "queue_ok" = 1), no dense handles
+ *   p              rule SG_RULE_GREEDY or SG_RULE_GREEDY_TIE, schedule
+ *                  SG_SCHED_AUTO or SG_SCHED_QUEUE
+ *   dev_scratch    caller-owned device memory of at least
+ *                  sg_group_scratch_bytes() bytes, 256-byte aligned (the
+ *                  group's instance table and work list)
+ *   unconverged    host array of `count` entries or NULL: replicas of each
+ *                  handle not converged after the call
+ *   stats          totals over the group, or NULL
+ * Returns after the stream has finished.  SG_ENOTCONV as sg_run_sweeps.
+ * Errors: SG_EINVAL (a handle that cannot join, another stream, bad
+ * parameters), SG_ESTATE, SG_ENOMEM (scratch too small), SG_EDEVICE. */
+sg_status sg_group_scratch_bytes(const sg_handle* hs, int32_t count, uint64_t* bytes);
+sg_status sg_run_group(const sg_handle* hs, int32_t count, const sg_run_params* p, void* dev_scratch,
+                       uint64_t scratch_bytes, int32_t* unconverged, sg_run_stats* stats);
+
 /* Energies of all replicas in handle order (sum over instances of
- * restarts entries).  recompute = 0: the tracked energy (start energy plus
+ * restarts entries): E(s) of Sec. II eq. (1) with the three-spin terms of
+ * Sec. VI eq. (5), every edge and triple once, exact in int64.  recompute = 0: the tracked energy (start energy plus
  * the dE of every applied move); recompute = 1: a fresh evaluation of the
  * energy from the current spins. */
 sg_status sg_energy(sg_handle h, int64_t* E, int32_t recompute);
@@ -283,7 +331,9 @@ sg_status sg_energy(sg_handle h, int64_t* E, int32_t recompute);
  * performed since the last start, moves applied, converged flag. */
 sg_status sg_replica_counters(sg_handle h, int64_t* sweeps, int64_t* flips, int8_t* converged);
 
-/* Spins of replica r of instance inst, n int8 values in external order. */
+/* Spins of replica r of instance inst, n int8 values in external order: the
+ * configuration the search reached (Fig. 3's output, Sec. II's solution of
+ * the ground-state problem when it is a ground state). */
 sg_status sg_spins_out(sg_handle h, int32_t inst, int32_t r, int8_t* s);
 
 /* Spins of restarts r0 .. r0+count-1 of instance inst: count x n int8 values,
@@ -358,12 +408,19 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
 
 /* Read a knob, or one of "last_tiles" (Px*10^6 + Py*10^3 + Pz of the last
  * lattice tile launch), "last_tile_k", "last_msc" (1 when that launch used
- * the bit-plane kernel), "last_bits" (1 when the last block-schedule call
+ * the bit-plane kernel), "last_model_phase_ns" / "last_model_exchange_ns" /
+ * "last_model_phases" / "last_model_exchanges" (the bit-plane tiling's
+ * latency model for that launch: mean cost of one colour phase and of one
+ * halo exchange, and how many of each the launch holds), "last_bits" (1 when the last block-schedule call
  * used the bit-sliced kernel), "last_key32" (1 when the last SG_RULE_FM call
  * picked moves on 32-bit keys), "last_fm_waves" (its wavefronts per
  * workgroup), "energy_pending" (1 while start energies
  * left out by sg_init_spins are not yet computed), "last_queue_grid",
- * "total_replicas",
+ * "total_replicas", "queue_ok" (1 when every instance can join sg_run_group),
+ * "wide_instances" (instances stored in the wide form: a
+ * coefficient beyond int8, a spin with |h|+sum|J|+sum|K| >= 2^23 or more than
+ * 255 triples, n >= 2^24 or more than 65535 restarts; they run on
+ * SG_SCHED_PHASE or SG_SCHED_GRAPH),
  * "instances", "hot_ns" / "hot_launches" (device time, from HIP events on the
  * bound stream, of the last sg_run_sweeps call's sweep kernel launches: the
  * single launch of the lattice, block or queue schedule, or the span of the

@@ -29,7 +29,7 @@ __all__ = [
     "GREEDY", "GREEDY_TIE", "FM", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH",
     "SCHED_LATTICE", "SCHED_BLOCK", "SCHED_QUEUE", "SCHED_FM", "SCHED_FIELDS", "SCHED_DENSE", "SGError", "Handle",
     "load_instance", "load_dense", "exact_ground_state",
-    "run_sweeps", "energy", "spins_out", "library_path", "lib",
+    "run_sweeps", "energy", "spins_out", "library_path", "lib", "run_group", "group_scratch_bytes", "philox_word0",
 ]
 
 SG_OK, SG_ENOTCONV, SG_EINVAL, SG_ERANGE, SG_ENOMEM, SG_EDEVICE, SG_ESTATE = 0, 1, -1, -2, -3, -4, -5
@@ -94,6 +94,8 @@ SIGNATURES = [
     ("sg_init_spins", ctypes.c_int32, [_P, ctypes.c_uint64]),
     ("sg_set_spins", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("sg_run_sweeps", ctypes.c_int32, [_P, _P, _P]),
+    ("sg_group_scratch_bytes", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    ("sg_run_group", ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, ctypes.c_uint64, _P, _P]),
     ("sg_energy", ctypes.c_int32, [_P, _P, ctypes.c_int32]),
     ("sg_replica_counters", ctypes.c_int32, [_P, _P, _P, _P]),
     ("sg_spins_out", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
@@ -379,6 +381,36 @@ def load_dense(instances) -> Handle:
     if not isinstance(instances, (list, tuple)):
         instances = [instances]
     return Handle(instances, dense=True)
+
+
+def _handle_array(handles):
+    arr = (ctypes.c_void_p * len(handles))()
+    for k, h in enumerate(handles):
+        arr[k] = h._h.value if isinstance(h._h, ctypes.c_void_p) else h._h
+    return arr
+
+
+def group_scratch_bytes(handles) -> int:
+    """Device scratch bytes that run_group needs for these handles."""
+    b = ctypes.c_uint64()
+    _check(lib().sg_group_scratch_bytes(_handle_array(handles), len(handles), ctypes.byref(b)))
+    return int(b.value)
+
+
+def run_group(handles, scratch, seed: int, rule: int = GREEDY, max_sweeps: int = 16, until_converged: bool = True):
+    """One step of continuous batching (sg_run_group): the replicas of every
+    handle in one launch.  ``scratch`` is a torch device tensor of at least
+    group_scratch_bytes(handles) bytes.  Returns (stats dict, per-handle
+    count of replicas not converged)."""
+    arr = _handle_array(handles)
+    p = RunParams(seed & 0xFFFFFFFFFFFFFFFF, rule, max_sweeps, int(until_converged), SCHED_AUTO)
+    st = RunStats()
+    unc = (ctypes.c_int32 * len(handles))()
+    status = _check(lib().sg_run_group(arr, len(handles), ctypes.byref(p), ctypes.c_void_p(scratch.data_ptr()),
+                                       scratch.numel() * scratch.element_size(), unc, ctypes.byref(st)))
+    d = st.as_dict()
+    d["status"] = status
+    return d, [int(v) for v in unc]
 
 
 def philox_word0(ctr, seed: int):

@@ -52,7 +52,9 @@ inline uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) /
 constexpr int32_t kMaxN = (1 << 24) - 1;
 constexpr int32_t kMaxCoef = 127;
 constexpr int64_t kMaxField = (1 << 23) - 1;
-constexpr int32_t kMaxRestarts = 65535;
+constexpr int32_t kMaxRestarts = 65535;         // packed form: restarts within one launch dimension
+constexpr int32_t kMaxWideN = 1 << 30;          // wide form: spins per instance
+constexpr int64_t kMaxWideField = INT32_MAX;    // per-spin |h| + sum|J| + sum|K| (int32 field)
 constexpr int32_t kMaxLatticeTiles = 1024;
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
@@ -89,6 +91,7 @@ struct HostInst {
     std::array<int32_t, 6> tile_key{{-1, -1, -1, -1, -1, -1}};
     sg::TileGeom tile_geom{};
     int32_t tile_msc = 0;
+    double tile_model_phase_us = 0.0, tile_model_ex_us = 0.0;  // cost model of the bit-plane tiling
     int32_t lat_L[3] = {0, 0, 0};      // (x, y, z) extents, z fastest; 2-D: (1, Lx, Ly)
     int32_t lat_D = 0;
     int32_t lat_c0 = 0;
@@ -98,6 +101,12 @@ struct HostInst {
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0, off_eterm = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
     uint64_t off_fields = 0, field_stride = 0;  // maintained local fields (ints per replica), when enabled
+    // wide form (values or sizes beyond the packed words, sg_layout.h)
+    int32_t wide = 0;
+    std::vector<uint32_t> w_nbr, w_ta, w_tb;
+    std::vector<int32_t> w_J, w_K, w_h;
+    std::vector<sg::WSlice> w_slices;
+    uint64_t off_wnbr = 0, off_wJ = 0, off_wta = 0, off_wtb = 0, off_wK = 0, off_wh = 0, off_wslices = 0;
     // dense hyper-Ising instance (sg_load_dense)
     int32_t dense = 0;
     std::vector<int32_t> d_start, d_order;
@@ -176,6 +185,10 @@ struct sg_ctx {
     double hot_us = 0.0;                        // their device time, microseconds
     int32_t hot_launches = 0;                   // launches inside that interval
     int32_t last_tiles[4] = {0, 0, 0, 0};  // tiling of the last lattice tile launch
+    // latency model of the last bit-plane launch: mean colour phase and exchange
+    // cost (microseconds), and how many of each the launch holds
+    double last_model_phase_us = 0.0, last_model_ex_us = 0.0;
+    int64_t last_model_phases = 0, last_model_exchanges = 0;
     int32_t last_queue_grid = 0;
 
     template <class T>
@@ -191,7 +204,24 @@ struct sg_ctx {
         I.ext = at<uint32_t>(q.off_ext);
         I.slices = at<sg::Slice>(q.off_slices);
         I.n = q.n;
-        I.nslices = (int32_t)q.slices.size();
+        I.nslices = (int32_t)q.slices.size();  // 0 for a wide instance: no packed kernel walks it
+        I.instance_id = q.id;
+        I.has_tri = q.t > 0 ? 1 : 0;
+        return I;
+    }
+    sg::WideDev wview(const HostInst& q) const
+    {
+        sg::WideDev I;
+        I.nbr = at<uint32_t>(q.off_wnbr);
+        I.J = at<int32_t>(q.off_wJ);
+        I.ta = at<uint32_t>(q.off_wta);
+        I.tb = at<uint32_t>(q.off_wtb);
+        I.K = at<int32_t>(q.off_wK);
+        I.h = at<int32_t>(q.off_wh);
+        I.ext = at<uint32_t>(q.off_ext);
+        I.slices = at<sg::WSlice>(q.off_wslices);
+        I.n = q.n;
+        I.nslices = (int32_t)q.w_slices.size();
         I.instance_id = q.id;
         I.has_tri = q.t > 0 ? 1 : 0;
         return I;
@@ -271,30 +301,40 @@ int32_t first_fit(const Primal& P, int32_t n, std::vector<int32_t>& colour)
     return ncol;
 }
 
-sg_status validate(const sg_instance_desc& d, int idx)
+// Checks an instance.  *wide (when given) is set when its values or sizes
+// exceed the packed words (int8 coefficients, 24-bit spin index, per-spin
+// |h| + sum|J| + sum|K| < 2^23, restarts within one launch dimension): such
+// an instance is stored in the wide form.  SG_ERANGE only when a spin's
+// |h_i| + sum|J_ij| + sum|K| exceeds 2^31 - 1 (its field would not fit int32),
+// when sum|J| + sum|h| + sum|K| exceeds 2^63 - 1 (an energy would not fit
+// int64), or when n exceeds 2^30 (index arithmetic).
+sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
 {
+    bool w = false;
     if (d.n < 1) return fail(SG_EINVAL, "instance %d: n must be >= 1", idx);
-    if (d.n > kMaxN) return fail(SG_ERANGE, "instance %d: n = %d exceeds %d", idx, d.n, kMaxN);
+    if (d.n > kMaxWideN) return fail(SG_ERANGE, "instance %d: n = %d exceeds %d", idx, d.n, kMaxWideN);
+    if (d.n > kMaxN) w = true;
     if (d.m < 0 || d.t < 0) return fail(SG_EINVAL, "instance %d: negative edge or triple count", idx);
     if (d.m > 0 && (!d.ei || !d.ej || !d.J)) return fail(SG_EINVAL, "instance %d: edge arrays missing", idx);
     if (d.t > 0 && (!d.tri || !d.K)) return fail(SG_EINVAL, "instance %d: triple arrays missing", idx);
     if (d.restarts < 1) return fail(SG_EINVAL, "instance %d: restarts must be >= 1", idx);
-    if (d.restarts > kMaxRestarts)
-        return fail(SG_ERANGE, "instance %d: restarts = %d exceeds %d", idx, d.restarts, kMaxRestarts);
+    if (d.restarts > kMaxRestarts) w = true;
     const int64_t n = d.n;
     std::vector<uint64_t> keys((size_t)d.m);
     std::vector<int64_t> field((size_t)n, 0);
+    __int128 total = 0;  // sum |J| + sum |h| + sum |K|
     for (int64_t k = 0; k < d.m; ++k) {
         const int64_t a = d.ei[k], b = d.ej[k];
         if (a < 0 || a >= n || b < 0 || b >= n)
             return fail(SG_EINVAL, "instance %d: edge %lld has a spin index out of range", idx, (long long)k);
         if (a == b) return fail(SG_EINVAL, "instance %d: edge %lld is a self-loop on spin %lld", idx, (long long)k,
                                 (long long)a);
-        if (d.J[k] < -kMaxCoef || d.J[k] > kMaxCoef)
-            return fail(SG_ERANGE, "instance %d: |J| of edge %lld exceeds %d", idx, (long long)k, kMaxCoef);
+        const int64_t c = std::llabs((int64_t)d.J[k]);
+        if (c > kMaxCoef) w = true;
         keys[k] = (uint64_t)std::min(a, b) * (uint64_t)n + (uint64_t)std::max(a, b);
-        field[a] += std::abs(d.J[k]);
-        field[b] += std::abs(d.J[k]);
+        field[a] += c;
+        field[b] += c;
+        total += c;
     }
     std::sort(keys.begin(), keys.end());
     for (size_t k = 1; k < keys.size(); ++k)
@@ -309,11 +349,12 @@ sg_status validate(const sg_instance_desc& d, int idx)
                 return fail(SG_EINVAL, "instance %d: triple %lld has a spin index out of range", idx, (long long)k);
         if (v[0] == v[1] || v[0] == v[2] || v[1] == v[2])
             return fail(SG_EINVAL, "instance %d: triple %lld repeats a spin", idx, (long long)k);
-        if (d.K[k] < -kMaxCoef || d.K[k] > kMaxCoef)
-            return fail(SG_ERANGE, "instance %d: |K| of triple %lld exceeds %d", idx, (long long)k, kMaxCoef);
+        const int64_t c = std::llabs((int64_t)d.K[k]);
+        if (c > kMaxCoef) w = true;
         std::sort(v.begin(), v.end());
         tk[k] = v;
-        for (int q = 0; q < 3; ++q) field[v[q]] += std::abs(d.K[k]);
+        for (int q = 0; q < 3; ++q) field[v[q]] += c;
+        total += c;
     }
     std::sort(tk.begin(), tk.end());
     for (size_t k = 1; k < tk.size(); ++k)
@@ -321,14 +362,19 @@ sg_status validate(const sg_instance_desc& d, int idx)
             return fail(SG_EINVAL, "instance %d: triple (%d,%d,%d) given twice", idx, tk[k][0], tk[k][1], tk[k][2]);
     for (int64_t i = 0; i < n; ++i) {
         if (d.h) {
-            if (d.h[i] < -kMaxCoef || d.h[i] > kMaxCoef)
-                return fail(SG_ERANGE, "instance %d: |h| of spin %lld exceeds %d", idx, (long long)i, kMaxCoef);
-            field[i] += std::abs(d.h[i]);
+            const int64_t c = std::llabs((int64_t)d.h[i]);
+            if (c > kMaxCoef) w = true;
+            field[i] += c;
+            total += c;
         }
-        if (field[i] > kMaxField)
+        if (field[i] > kMaxWideField)
             return fail(SG_ERANGE, "instance %d: spin %lld has |h|+sum|J|+sum|K| = %lld > %lld", idx, (long long)i,
-                        (long long)field[i], (long long)kMaxField);
+                        (long long)field[i], (long long)kMaxWideField);
+        if (field[i] > kMaxField) w = true;
     }
+    if (total > (__int128)INT64_MAX)
+        return fail(SG_ERANGE, "instance %d: sum|J| + sum|h| + sum|K| exceeds 2^63 - 1", idx);
+    if (wide) *wide = w;
     return SG_OK;
 }
 
@@ -496,9 +542,13 @@ sg_status ingest_dense(const sg_dense_desc& d, int idx, HostInst& q)
     return SG_OK;
 }
 
+sg_status ingest_wide(const sg_instance_desc& d, int idx, HostInst& q, const std::vector<uint32_t>& int_of,
+                      const std::vector<int64_t>& es, const std::vector<int64_t>& ts);
+
 sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
 {
-    sg_status st = validate(d, idx);
+    bool wide = false;
+    sg_status st = validate(d, idx, &wide);
     if (st != SG_OK) return st;
     q.n = d.n;
     q.m = d.m;
@@ -529,7 +579,6 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     } else {
         q.C = first_fit(P, n, q.colour);
     }
-    if (q.C > 65535) return fail(SG_ERANGE, "instance %d: %d colours", idx, q.C);
 
     // incidence counts
     std::vector<int32_t> deg((size_t)n, 0), tdeg((size_t)n, 0);
@@ -538,10 +587,9 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
         deg[d.ej[k]]++;
     }
     for (int64_t k = 0; k < 3 * d.t; ++k) tdeg[d.tri[k]]++;
-    for (int32_t i = 0; i < n; ++i) {
-        if (deg[i] > 65535) return fail(SG_ERANGE, "instance %d: spin %d has %d couplings", idx, i, deg[i]);
-        if (tdeg[i] > 255) return fail(SG_ERANGE, "instance %d: spin %d is in %d triples (max 255)", idx, i, tdeg[i]);
-    }
+    for (int32_t i = 0; i < n && !wide; ++i) wide = deg[i] > 65535 || tdeg[i] > 255;
+    if (q.C > 65535) wide = true;
+    q.wide = wide ? 1 : 0;
     // colour-major relabel, decreasing incidence inside a colour, stable
     q.ext_of.resize((size_t)n);
     std::iota(q.ext_of.begin(), q.ext_of.end(), 0u);
@@ -563,6 +611,7 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
         es[i + 1] += es[i];
         ts[i + 1] += ts[i];
     }
+    if (q.wide) return ingest_wide(d, idx, q, int_of, es, ts);
     std::vector<uint32_t> ew((size_t)es[n]), twa((size_t)ts[n]), twb((size_t)ts[n]);
     {
         std::vector<int64_t> fe(es.begin(), es.end() - 1), ft(ts.begin(), ts.end() - 1);
@@ -700,8 +749,117 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     return SG_OK;
 }
 
+// The wide form: the rows of the packed form with the partner index and the
+// coefficient in separate 32-bit words (int_of, es, ts: the relabel and the
+// per-row incidence offsets in internal numbering).
+sg_status ingest_wide(const sg_instance_desc& d, int idx, HostInst& q, const std::vector<uint32_t>& int_of,
+                      const std::vector<int64_t>& es, const std::vector<int64_t>& ts)
+{
+    const int32_t n = d.n;
+    std::vector<uint32_t> wp((size_t)es[n]), wa((size_t)ts[n]), wb((size_t)ts[n]);
+    std::vector<int32_t> wj((size_t)es[n]), wk((size_t)ts[n]);
+    {
+        std::vector<int64_t> fe(es.begin(), es.end() - 1), ft(ts.begin(), ts.end() - 1);
+        for (int64_t k = 0; k < d.m; ++k) {
+            const uint32_t a = int_of[d.ei[k]], b = int_of[d.ej[k]];
+            wp[fe[a]] = b;
+            wj[fe[a]++] = d.J[k];
+            wp[fe[b]] = a;
+            wj[fe[b]++] = d.J[k];
+        }
+        for (int64_t k = 0; k < d.t; ++k) {
+            const uint32_t v[3] = {int_of[d.tri[3 * k]], int_of[d.tri[3 * k + 1]], int_of[d.tri[3 * k + 2]]};
+            for (int s = 0; s < 3; ++s) {
+                const uint32_t o1 = v[(s + 1) % 3], o2 = v[(s + 2) % 3];
+                wa[ft[v[s]]] = std::min(o1, o2);
+                wb[ft[v[s]]] = std::max(o1, o2);
+                wk[ft[v[s]]++] = d.K[k];
+            }
+        }
+    }
+    q.w_h.assign((size_t)n, 0);
+    if (d.h)
+        for (int32_t i = 0; i < n; ++i) q.w_h[int_of[i]] = d.h[i];
+    std::vector<int64_t> cstart((size_t)q.C + 1, 0);
+    for (int32_t i = 0; i < n; ++i) cstart[q.colour[i] + 1]++;
+    for (int32_t c = 0; c < q.C; ++c) cstart[c + 1] += cstart[c];
+    q.colour_slice.assign((size_t)q.C + 1, 0);
+    q.w_slices.clear();
+    uint64_t ebase = 0, tbase = 0;
+    int64_t maxblocks = 1;
+    for (int32_t c = 0; c < q.C; ++c) {
+        if (q.w_slices.size() > (size_t)INT32_MAX - 1)
+            return fail(SG_ERANGE, "instance %d: more than 2^31 - 1 row slices", idx);
+        q.colour_slice[c] = (int32_t)q.w_slices.size();
+        for (int64_t r0 = cstart[c]; r0 < cstart[c + 1]; r0 += sg::kSlice) {
+            const int32_t rows = (int32_t)std::min<int64_t>(sg::kSlice, cstart[c + 1] - r0);
+            int64_t w = 0, tw = 0;
+            for (int32_t l = 0; l < rows; ++l) {
+                w = std::max<int64_t>(w, es[r0 + l + 1] - es[r0 + l]);
+                tw = std::max<int64_t>(tw, ts[r0 + l + 1] - ts[r0 + l]);
+            }
+            sg::WSlice S;
+            S.ebase = ebase;
+            S.tbase = tbase;
+            S.row0 = (uint32_t)r0;
+            S.ew = (uint32_t)w;
+            S.tw = (uint32_t)tw;
+            S.rows = (uint32_t)rows;
+            q.w_slices.push_back(S);
+            ebase += (uint64_t)w * sg::kSlice;
+            tbase += (uint64_t)tw * sg::kSlice;
+        }
+        const int64_t ns = (int64_t)q.w_slices.size() - q.colour_slice[c];
+        maxblocks = std::max<int64_t>(maxblocks, (ns + sg::kPhaseWaves - 1) / sg::kPhaseWaves);
+    }
+    if (q.w_slices.size() > (size_t)INT32_MAX) return fail(SG_ERANGE, "instance %d: more than 2^31 - 1 row slices", idx);
+    q.colour_slice[q.C] = (int32_t)q.w_slices.size();
+    q.nslots = (int32_t)maxblocks;
+    q.acc_slots = (int32_t)maxblocks;
+    q.w_nbr.assign((size_t)std::max<uint64_t>(ebase, 1), 0u);
+    q.w_J.assign((size_t)std::max<uint64_t>(ebase, 1), 0);
+    q.w_ta.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
+    q.w_tb.assign((size_t)std::max<uint64_t>(tbase, 1), 0u);
+    q.w_K.assign((size_t)std::max<uint64_t>(tbase, 1), 0);
+    q.max_w = 0;
+    for (const sg::WSlice& S : q.w_slices) {
+        for (uint32_t l = 0; l < S.rows; ++l) {
+            const int64_t i = (int64_t)S.row0 + l;
+            int64_t W = std::llabs((int64_t)q.w_h[(size_t)i]);
+            for (int64_t k = es[i]; k < es[i + 1]; ++k) {
+                const uint64_t at = S.ebase + (uint64_t)(k - es[i]) * sg::kSlice + l;
+                q.w_nbr[at] = wp[k];
+                q.w_J[at] = wj[k];
+                W += std::llabs((int64_t)wj[k]);
+            }
+            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
+                const uint64_t at = S.tbase + (uint64_t)(k - ts[i]) * sg::kSlice + l;
+                q.w_ta[at] = wa[k];
+                q.w_tb[at] = wb[k];
+                q.w_K[at] = wk[k];
+                W += std::llabs((int64_t)wk[k]);
+            }
+            q.max_w = std::max(q.max_w, W);
+        }
+    }
+    // the packed arrays stay empty placeholders
+    q.slices.clear();
+    q.nbr.assign(1, 0u);
+    q.ta.assign(1, 0u);
+    q.tb.assign(1, 0u);
+    q.h.assign(1, 0);
+    q.eterm.clear();
+    q.n_eh = q.n_ee = q.n_et = 0;
+    q.bits_ok = 0;
+    q.lat_ok = 0;
+    return SG_OK;
+}
+
 // Replicas of this instance may start (and recompute energies) one lane per replica.
-bool lane_start_candidate(const HostInst& q) { return !q.dense && q.n <= kLaneStartMaxN && q.R >= kLaneStartMinR; }
+bool lane_start_candidate(const HostInst& q)
+{
+    return !q.dense && !q.wide && q.n <= kLaneStartMaxN && q.R >= kLaneStartMinR;
+}
 
 void layout(sg_ctx* H)
 {
@@ -720,10 +878,19 @@ void layout(sg_ctx* H)
     };
     int64_t max_slots = 1;
     for (HostInst& q : H->insts) {
+        if (q.wide) {
+            q.off_wnbr = take(q.w_nbr.size() * 4);
+            q.off_wJ = take(q.w_J.size() * 4);
+            q.off_wta = take(q.w_ta.size() * 4);
+            q.off_wtb = take(q.w_tb.size() * 4);
+            q.off_wK = take(q.w_K.size() * 4);
+            q.off_wh = take(q.w_h.size() * 4);
+            q.off_wslices = take(q.w_slices.size() * sizeof(sg::WSlice));
+        }
         q.off_nbr = take(q.nbr.size() * 4);
         q.off_ta = take(q.ta.size() * 4);
         q.off_tb = take(q.tb.size() * 4);
-        q.off_h = take((uint64_t)q.n);
+        q.off_h = take(q.h.size());
         q.off_ext = take((uint64_t)q.n * 4);
         q.off_slices = take(q.slices.size() * sizeof(sg::Slice));
         q.off_eterm = take(q.eterm.size() * 4);
@@ -779,6 +946,7 @@ void layout(sg_ctx* H)
         for (int32_t r = 0; r < q.R; ++r) {
             const int64_t g = q.rep_base + r;
             for (int32_t i0 = 0; i0 < q.n; i0 += 1024) H->h_sunits.push_back(sg::StartUnit{g, (int32_t)k, i0});
+            if (q.wide) continue;  // energies of the wide form: the wide energy pass
             const int64_t u0 = (int64_t)H->h_eunits.size();
             for (int32_t s0 = 0; s0 < (int32_t)q.slices.size(); s0 += 4)
                 H->h_eunits.push_back(sg::StartUnit{g, (int32_t)k, s0});
@@ -856,13 +1024,19 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
         const int64_t fstride = (int64_t)q.field_stride;
         if (inc) SG_HIP(sg::launch_fields(I, spins, (int64_t)q.spin_stride, q.R, F, fstride, st), "field kernel");
         int T = 0;
+        const sg::WideDev W = q.wide ? H->wview(q) : sg::WideDev{};
         auto sweeps = [&](int from, int to) -> sg_status {
             for (int t = from; t < to; ++t)
                 for (int32_t c = 0; c < q.C; ++c) {
                     const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
-                    SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, t,
-                                            p->seed, p->rule, p->until_converged, st, nullptr, F, fstride),
-                           "phase kernel");
+                    if (q.wide)
+                        SG_HIP(sg::launch_wide_phase(W, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0,
+                                                     ns, t, p->seed, p->rule, p->until_converged, st),
+                               "wide phase kernel");
+                    else
+                        SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns,
+                                                t, p->seed, p->rule, p->until_converged, st, nullptr, F, fstride),
+                               "phase kernel");
                     H->hot_launches++;
                 }
             return SG_OK;
@@ -913,6 +1087,7 @@ sg_status run_graph_schedule(sg_handle H, const sg_run_params* p, const std::vec
         int8_t* spins = H->at<int8_t>(q.off_spins);
         int64_t* acc = H->at<int64_t>(q.off_acc);
         int32_t* tb = H->at<int32_t>(H->off_tbase) + qi;
+        const sg::WideDev W = q.wide ? H->wview(q) : sg::WideDev{};
         SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
         SG_HIP(sg::launch_fill_u32(tb, 1, 0u, st), "fill kernel");
         const int seg = std::max(1, std::min(H->graph_sweeps, p->max_sweeps));
@@ -933,8 +1108,11 @@ sg_status run_graph_schedule(sg_handle H, const sg_run_params* p, const std::vec
             for (int t = 0; t < seg && ce == hipSuccess; ++t)
                 for (int32_t c = 0; c < q.C && ce == hipSuccess; ++c) {
                     const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
-                    ce = sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, t,
-                                          p->seed, p->rule, p->until_converged, H->cap_stream, tb);
+                    ce = q.wide ? sg::launch_wide_phase(W, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots,
+                                                        s0, ns, t, p->seed, p->rule, p->until_converged,
+                                                        H->cap_stream, tb)
+                                : sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0,
+                                                   ns, t, p->seed, p->rule, p->until_converged, H->cap_stream, tb);
                 }
             if (ce == hipSuccess) ce = sg::launch_bump(tb, seg, H->cap_stream);
             hipError_t ee = hipStreamEndCapture(H->cap_stream, &graph);
@@ -980,9 +1158,14 @@ sg_status run_graph_schedule(sg_handle H, const sg_run_params* p, const std::vec
         for (; !stopped && T < p->max_sweeps; ++T)
             for (int32_t c = 0; c < q.C; ++c) {
                 const int s0 = q.colour_slice[c], ns = q.colour_slice[c + 1] - s0;
-                SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, T,
-                                        p->seed, p->rule, p->until_converged, st),
-                       "phase kernel");
+                if (q.wide)
+                    SG_HIP(sg::launch_wide_phase(W, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns,
+                                                 T, p->seed, p->rule, p->until_converged, st),
+                           "wide phase kernel");
+                else
+                    SG_HIP(sg::launch_phase(I, spins, (int64_t)q.spin_stride, rs, q.R, acc, q.acc_slots, s0, ns, T,
+                                            p->seed, p->rule, p->until_converged, st),
+                           "phase kernel");
                 H->hot_launches++;
             }
         if (qi == which.back()) SG_HIP(hipEventRecord(H->evh1, st), "event record");
@@ -1049,7 +1232,8 @@ bool choose_tiling(const sg_ctx* H, const HostInst& q, sg::TileGeom& tg)
 // of 1000 sweeps of this kernel on the 10^6-spin lattice over 31 tilings and
 // halo widths under both rules; the choice minimises the cost per phase,
 // subject to LDS, co-residency and the geometry limits of the kernel.
-bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeom& tg)
+bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeom& tg, double* model_phase_us = nullptr,
+                       double* model_exchange_us = nullptr)
 {
     int cap_limit = kMaxLatticeTiles;
     if (H->lattice_max_tiles > 0) cap_limit = std::min(cap_limit, H->lattice_max_tiles);
@@ -1084,7 +1268,8 @@ bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeo
                     const double rows = (double)B[0] * B[1];
                     const double ex0 = tie ? 2.0 : 2.1, ex1 = 0.4;
                     const double ph0 = tie ? 0.84 : 0.19, ph1 = tie ? 0.49 : 0.28;
-                    double cost = ex0 + ex1 * (std::ceil(rows / 1024.0) - 1.0);
+                    const double excost = ex0 + ex1 * (std::ceil(rows / 1024.0) - 1.0);
+                    double cost = excost;
                     for (int qq = 0; qq < k; ++qq) {
                         const double ax = a0 ? 1.0 : std::max(0, B[0] - 2 * (qq + 1));
                         const double ay = std::max(0, B[1] - 2 * (qq + 1));
@@ -1099,6 +1284,8 @@ bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeo
                     bestT = T;
                     tg = g;
                     found = true;
+                    if (model_phase_us) *model_phase_us = (cost * k - excost) / k;
+                    if (model_exchange_us) *model_exchange_us = excost;
                 }
             }
     return found;
@@ -1138,7 +1325,11 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                                                   H->lattice_k, 1}};
                 if (qm.tile_key != key) {
                     sg::TileGeom g{};
-                    const bool m = q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, p->rule == 1, g);
+                    double mph = 0.0, mex = 0.0;
+                    const bool m =
+                        q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, p->rule == 1, g, &mph, &mex);
+                    qm.tile_model_phase_us = m ? mph : 0.0;
+                    qm.tile_model_ex_us = m ? mex : 0.0;
                     if (!m && !choose_tiling(H, q, g))
                         return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0],
                                     q.lat_L[1], q.lat_L[2]);
@@ -1174,6 +1365,13 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 H->last_tiles[1] = tg.P[1];
                 H->last_tiles[2] = tg.P[2];
                 H->last_tiles[3] = tg.k;
+                // the tiling cost model's prediction of this launch: C colour
+                // phases per sweep, one exchange every k phases
+                const double phases = (double)T * q.C;
+                H->last_model_phase_us = msc ? qm.tile_model_phase_us : 0.0;
+                H->last_model_ex_us = msc ? qm.tile_model_ex_us : 0.0;
+                H->last_model_exchanges = msc ? (int64_t)std::ceil(phases / tg.k) : 0;
+                H->last_model_phases = msc ? (int64_t)phases : 0;
             }
         }
         SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st, absolute), "end kernel");
@@ -1194,6 +1392,7 @@ constexpr int32_t kBlockGroupsAuto = 4;                 // most restart groups p
 // 9.6 ms at 64, 15.2 ms at 128, 15.8 ms with the largest size that fits).
 int block_rg_for(const sg_ctx* H, const HostInst& q)
 {
+    if (q.wide) return 0;
     const int want = H->block_rg ? H->block_rg : 64;
     for (int rg = want; rg >= 64; rg -= 64) {
         if (H->block_rg && rg != H->block_rg) break;
@@ -1415,7 +1614,7 @@ bool can_lattice(const sg_ctx* H, const HostInst& q, const sg_run_params* p)
     return q.lat_ok && (lattice_wg_fits(H, q) || !p->until_converged);
 }
 bool can_block(const sg_ctx* H, const HostInst& q) { return block_rg_for(H, q) > 0; }
-bool can_queue(const HostInst& q) { return q.n <= kQueueMaxN; }
+bool can_queue(const HostInst& q) { return !q.wide && q.n <= kQueueMaxN; }
 
 // Per-instance schedule, or -1 when the requested schedule cannot run some instance.
 int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& out)
@@ -1433,11 +1632,11 @@ int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& 
             if (can_lattice(H, q, p)) s = SG_SCHED_LATTICE;
             else if (q.R >= H->block_min_restarts && can_block(H, q)) s = SG_SCHED_BLOCK;
             else if (can_queue(q) && queue_items >= H->queue_min_items) s = SG_SCHED_QUEUE;
-            else s = H->fields_ws ? SG_SCHED_FIELDS : SG_SCHED_PHASE;
+            else s = H->fields_ws && !q.wide ? SG_SCHED_FIELDS : SG_SCHED_PHASE;
             break;
         case SG_SCHED_PHASE: s = SG_SCHED_PHASE; break;
         case SG_SCHED_GRAPH: s = SG_SCHED_GRAPH; break;
-        case SG_SCHED_FIELDS: s = H->fields_ws ? SG_SCHED_FIELDS : -1; break;
+        case SG_SCHED_FIELDS: s = H->fields_ws && !q.wide ? SG_SCHED_FIELDS : -1; break;
         case SG_SCHED_LATTICE: s = can_lattice(H, q, p) ? SG_SCHED_LATTICE : -1; break;
         case SG_SCHED_BLOCK: s = can_block(H, q) ? SG_SCHED_BLOCK : -1; break;
         case SG_SCHED_QUEUE: s = can_queue(q) ? SG_SCHED_QUEUE : -1; break;
@@ -1500,6 +1699,10 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     bool tri = false, key32 = true;
     for (const HostInst& q : H->insts) {
         if (q.n > kFmMaxN) return fail(SG_EINVAL, "rule SG_RULE_FM: instance of %d spins (at most %d)", q.n, kFmMaxN);
+        if (q.wide)
+            return fail(SG_EINVAL, "rule SG_RULE_FM: instance %zu needs the wide form (a coefficient beyond int8, "
+                                   "a spin's |h|+sum|J|+sum|K| >= 2^23, or more than 255 triples on a spin)",
+                        (size_t)(&q - H->insts.data()));
         nmax = std::max(nmax, q.n);
         tri = tri || q.t > 0;
         // 32-bit move keys: every gain |2 s f| < 2^19 and external indices below 4096
@@ -1772,7 +1975,24 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
                "upload triples");
         SG_HIP(hipMemcpyAsync(H->dev + q.off_tb, q.tb.data(), q.tb.size() * 4, hipMemcpyHostToDevice, st),
                "upload triples");
-        SG_HIP(hipMemcpyAsync(H->dev + q.off_h, q.h.data(), (size_t)q.n, hipMemcpyHostToDevice, st), "upload fields");
+        SG_HIP(hipMemcpyAsync(H->dev + q.off_h, q.h.data(), q.h.size(), hipMemcpyHostToDevice, st), "upload fields");
+        if (q.wide) {
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wnbr, q.w_nbr.data(), q.w_nbr.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload couplings");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wJ, q.w_J.data(), q.w_J.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload couplings");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wta, q.w_ta.data(), q.w_ta.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload triples");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wtb, q.w_tb.data(), q.w_tb.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload triples");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wK, q.w_K.data(), q.w_K.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload triples");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wh, q.w_h.data(), q.w_h.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload fields");
+            SG_HIP(hipMemcpyAsync(H->dev + q.off_wslices, q.w_slices.data(), q.w_slices.size() * sizeof(sg::WSlice),
+                                  hipMemcpyHostToDevice, st),
+                   "upload slices");
+        }
         if (!q.eterm.empty())
             SG_HIP(hipMemcpyAsync(H->dev + q.off_eterm, q.eterm.data(), q.eterm.size() * 4, hipMemcpyHostToDevice, st),
                    "upload energy terms");
@@ -1945,6 +2165,12 @@ sg_status sg_init_spins(sg_handle H, uint64_t seed)
                                       (int)H->h_litems.size(), H->lane_nmax, true, H->reps(), nullptr, seed, st),
                "lane start kernel");
     }
+    // start energies of the wide-form instances (their starts came from the unit kernel above)
+    for (const HostInst& q : H->insts)
+        if (q.wide)
+            SG_HIP(sg::launch_wide_energy(H->wview(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
+                                          H->at<int64_t>(H->off_slots), q.nslots, H->reps() + q.rep_base, nullptr, st),
+                   "wide energy kernel");
     // enqueued on the bound stream: every later call of the handle is ordered after it
     std::fill(H->started.begin(), H->started.end(), 1);
     return SG_OK;
@@ -1977,7 +2203,11 @@ sg_status sg_set_spins(sg_handle H, int32_t inst, int32_t r, const int8_t* s)
     }
     SG_HIP(hipMemcpyAsync(dst, tmp.data(), (size_t)q.n, hipMemcpyHostToDevice, st), "spin upload");
     SG_HIP(hipMemcpyAsync(rs, &z, sizeof z, hipMemcpyHostToDevice, st), "state upload");
-    if (!q.dense)
+    if (q.wide)
+        SG_HIP(sg::launch_wide_energy(H->wview(q), dst, (int64_t)q.spin_stride, 1, H->at<int64_t>(H->off_slots),
+                                      q.nslots, rs, nullptr, st),
+               "wide energy kernel");
+    else if (!q.dense)
         SG_HIP(sg::launch_energy(H->view(q), dst, (int64_t)q.spin_stride, 1, H->at<int64_t>(H->off_slots), q.nslots,
                                  rs, nullptr, st),
                "energy kernel");
@@ -2108,6 +2338,11 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
             SG_HIP(sg::launch_start_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_litems),
                                           (int)H->h_litems.size(), H->lane_nmax, false, H->reps(), eout, 0, st),
                    "batched energy kernel");
+        for (const HostInst& q : H->insts)
+            if (q.wide)
+                SG_HIP(sg::launch_wide_energy(H->wview(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride, q.R,
+                                              H->at<int64_t>(H->off_slots), q.nslots, nullptr, eout + q.rep_base, st),
+                       "wide energy kernel");
         SG_HIP(hipMemcpyAsync(E, eout, (size_t)H->total_reps * 8, hipMemcpyDeviceToHost, st), "energy copy");
         SG_HIP(hipStreamSynchronize(st), "stream sync");
         return SG_OK;
@@ -2293,9 +2528,225 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "hot_launches") *value = H->hot_launches;
     else if (k == "last_tiles") *value = (int64_t)H->last_tiles[0] * 1000000 + H->last_tiles[1] * 1000 + H->last_tiles[2];
     else if (k == "last_tile_k") *value = H->last_tiles[3];
+    else if (k == "last_model_phase_ns") *value = (int64_t)std::llround(H->last_model_phase_us * 1000.0);
+    else if (k == "last_model_exchange_ns") *value = (int64_t)std::llround(H->last_model_ex_us * 1000.0);
+    else if (k == "last_model_phases") *value = H->last_model_phases;
+    else if (k == "last_model_exchanges") *value = H->last_model_exchanges;
     else if (k == "total_replicas") *value = H->total_reps;
+    else if (k == "queue_ok") {
+        int64_t ok = H->dense ? 0 : 1;
+        for (const HostInst& q : H->insts) ok = ok && can_queue(q);
+        *value = ok;
+    }
+    else if (k == "wide_instances") {
+        int64_t c = 0;
+        for (const HostInst& q : H->insts) c += q.wide;
+        *value = c;
+    }
     else if (k == "instances") *value = (int64_t)H->insts.size();
     else return fail(SG_EINVAL, "sg_query: unknown key '%s'", key);
+    return SG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// continuous batching: the replicas of several handles in one launch of the
+// persistent queue kernel
+
+namespace {
+
+struct GroupLayout {
+    uint64_t off_tab = 0, off_ctab = 0, off_items = 0, off_cnt = 0, off_stats = 0, bytes = 0;
+    int64_t ninst = 0, nctab = 0, nitems = 0;
+};
+
+sg_status group_layout(const sg_handle* hs, int32_t count, GroupLayout& g)
+{
+    if (!hs || count < 1) return fail(SG_EINVAL, "sg_run_group: need handles and count >= 1");
+    for (int32_t k = 0; k < count; ++k) {
+        const sg_ctx* H = hs[k];
+        if (!H) return fail(SG_EINVAL, "sg_run_group: handle %d is null", k);
+        if (H->dense) return fail(SG_EINVAL, "sg_run_group: handle %d holds dense instances", k);
+        for (size_t q = 0; q < H->insts.size(); ++q)
+            if (!can_queue(H->insts[q]))
+                return fail(SG_EINVAL, "sg_run_group: instance %zu of handle %d cannot run on the queue kernel "
+                                       "(more than %d spins, or the wide form)", q, k, kQueueMaxN);
+        g.ninst += (int64_t)H->insts.size();
+        g.nitems += H->total_reps;
+        for (const HostInst& q : H->insts) g.nctab += q.C + 1;
+    }
+    if (g.nitems > INT32_MAX || g.ninst > INT32_MAX || g.nctab > INT32_MAX)
+        return fail(SG_ERANGE, "sg_run_group: more than 2^31 - 1 replicas");
+    uint64_t off = 0;
+    auto take = [&](uint64_t b) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(b, 1));
+        return o;
+    };
+    g.off_tab = take((uint64_t)g.ninst * sizeof(sg::InstTab));
+    g.off_ctab = take((uint64_t)g.nctab * 4);
+    g.off_items = take((uint64_t)g.nitems * sizeof(sg::QueueItem));
+    g.off_cnt = take(64);
+    g.off_stats = take(sizeof(sg::CallStats));
+    g.bytes = off;
+    return SG_OK;
+}
+
+}  // namespace
+
+sg_status sg_group_scratch_bytes(const sg_handle* hs, int32_t count, uint64_t* bytes)
+{
+    if (!bytes) return fail(SG_EINVAL, "sg_group_scratch_bytes: null output");
+    GroupLayout g;
+    sg_status e = group_layout(hs, count, g);
+    if (e != SG_OK) return e;
+    *bytes = g.bytes;
+    return SG_OK;
+}
+
+sg_status sg_run_group(const sg_handle* hs, int32_t count, const sg_run_params* p, void* dev_scratch,
+                       uint64_t scratch_bytes, int32_t* unconverged, sg_run_stats* stats)
+{
+    GroupLayout g;
+    sg_status e = group_layout(hs, count, g);
+    if (e != SG_OK) return e;
+    if (!p) return fail(SG_EINVAL, "sg_run_group: null params");
+    if (p->rule != SG_RULE_GREEDY && p->rule != SG_RULE_GREEDY_TIE)
+        return fail(SG_EINVAL, "sg_run_group: rule %d (the queue kernel runs GREEDY and GREEDY_TIE)", p->rule);
+    if (p->schedule != SG_SCHED_AUTO && p->schedule != SG_SCHED_QUEUE)
+        return fail(SG_EINVAL, "sg_run_group: schedule %d (a group runs on SG_SCHED_QUEUE)", p->schedule);
+    if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
+    if (!dev_scratch || ((uintptr_t)dev_scratch % kAlign))
+        return fail(SG_EINVAL, "sg_run_group: scratch must be a 256-byte aligned device pointer");
+    if (scratch_bytes < g.bytes)
+        return fail(SG_ENOMEM, "sg_run_group: scratch of %llu bytes, need %llu", (unsigned long long)scratch_bytes,
+                    (unsigned long long)g.bytes);
+    sg_ctx* H0 = hs[0];
+    for (int32_t k = 0; k < count; ++k) {
+        sg_ctx* H = hs[k];
+        if ((e = need_bound(H)) != SG_OK) return e;
+        if (H->stream != H0->stream) return fail(SG_EINVAL, "sg_run_group: handle %d is bound to another stream", k);
+        for (uint8_t v : H->started)
+            if (!v) return fail(SG_ESTATE, "sg_run_group: a replica of handle %d has no start", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (hs[j] == H) return fail(SG_EINVAL, "sg_run_group: handle %d given twice", k);
+    }
+    hipStream_t st = H0->stream;
+    // start energies left out by sg_init_spins: the queue kernel continues from them
+    for (int32_t k = 0; k < count; ++k)
+        if ((e = ensure_energy(hs[k])) != SG_OK) return e;
+    uint8_t* scr = (uint8_t*)dev_scratch;
+    // replica states stay in each handle's workspace: a table entry's rep_base
+    // is the offset, in RepState units, of its replica 0 from the first
+    // handle's state array (all workspaces are 256-byte aligned)
+    sg::RepState* rs0 = H0->reps();
+    std::vector<sg::InstTab> tab;
+    std::vector<int32_t> ctab;
+    std::vector<sg::QueueItem> items;
+    std::vector<int32_t> nsz;
+    tab.reserve((size_t)g.ninst);
+    ctab.reserve((size_t)g.nctab);
+    items.reserve((size_t)g.nitems);
+    for (int32_t k = 0; k < count; ++k) {
+        const sg_ctx* H = hs[k];
+        for (const HostInst& q : H->insts) {
+            sg::InstTab T{};
+            T.I = H->view(q);
+            T.spins = H->at<int8_t>(q.off_spins);
+            T.spin_stride = (int64_t)q.spin_stride;
+            const intptr_t d = (intptr_t)((const uint8_t*)(H->reps() + q.rep_base) - (const uint8_t*)rs0);
+            T.rep_base = (int64_t)(d / (intptr_t)sizeof(sg::RepState));
+            T.C = q.C;
+            T.ctab_off = (int32_t)ctab.size();
+            T.nbr_words = (int32_t)q.nbr.size();
+            T.tri_words = (int32_t)q.ta.size();
+            T.eterm = H->at<uint32_t>(q.off_eterm);
+            T.n_eh = q.n_eh;
+            T.n_ee = q.n_ee;
+            T.n_et = q.n_et;
+            for (int32_t c = 0; c <= q.C; ++c) ctab.push_back(q.colour_slice[c]);
+            const int32_t gi = (int32_t)tab.size();
+            tab.push_back(T);
+            nsz.push_back(q.n);
+            for (int32_t r = 0; r < q.R; ++r) items.push_back(sg::QueueItem{gi, r});
+        }
+    }
+    // largest items first; those above the wavefront size run on whole workgroups
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const sg::QueueItem& a, const sg::QueueItem& b) { return nsz[a.inst] > nsz[b.inst]; });
+    int n_big = 0, nmax_big = 0, nmax_small = 0;
+    for (const sg::QueueItem& it : items) {
+        const int n = nsz[it.inst];
+        if (n > H0->queue_wave_max_n) {
+            ++n_big;
+            nmax_big = std::max(nmax_big, n);
+        } else {
+            nmax_small = std::max(nmax_small, n);
+        }
+    }
+    const int wave_lds = (nmax_small + 15) / 16 * 16;
+    size_t lds = std::max<size_t>((size_t)nmax_big, (size_t)wave_lds * 16);
+    lds = std::max<size_t>((lds + 15) / 16 * 16, 16);
+    if (lds > kLdsBudget) return fail(SG_EINVAL, "sg_run_group: an item needs %zu bytes of LDS", lds);
+    int grid = H0->queue_grid;
+    if (grid <= 0) grid = sg::queue_max_blocks(lds);
+    if (grid <= 0) grid = 256;
+    grid = std::min<int>(grid, (int)items.size());
+    SG_HIP(hipMemcpyAsync(scr + g.off_tab, tab.data(), tab.size() * sizeof(sg::InstTab), hipMemcpyHostToDevice, st),
+           "upload group table");
+    SG_HIP(hipMemcpyAsync(scr + g.off_ctab, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st),
+           "upload group colour table");
+    SG_HIP(hipMemcpyAsync(scr + g.off_items, items.data(), items.size() * sizeof(sg::QueueItem),
+                          hipMemcpyHostToDevice, st),
+           "upload group items");
+    SG_HIP(sg::launch_fill_u32(scr + g.off_cnt, 16, 0u, st), "fill kernel");
+    SG_HIP(sg::launch_fill_u32(scr + g.off_stats, sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
+    SG_HIP(hipEventRecord(H0->evh0, st), "event record");
+    if (p->max_sweeps > 0)
+        SG_HIP(sg::launch_queue(reinterpret_cast<sg::InstTab*>(scr + g.off_tab),
+                                reinterpret_cast<int32_t*>(scr + g.off_ctab),
+                                reinterpret_cast<sg::QueueItem*>(scr + g.off_items), n_big, (int)items.size(),
+                                reinterpret_cast<uint32_t*>(scr + g.off_cnt), wave_lds, lds, grid, rs0,
+                                reinterpret_cast<sg::CallStats*>(scr + g.off_stats), p->max_sweeps, p->seed, p->rule,
+                                p->until_converged, st),
+               "queue kernel");
+    SG_HIP(hipEventRecord(H0->evh1, st), "event record");
+    sg::CallStats cs{};
+    SG_HIP(hipMemcpyAsync(&cs, scr + g.off_stats, sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
+    std::vector<std::vector<sg::RepState>> reps;
+    if (unconverged) {
+        reps.resize((size_t)count);
+        for (int32_t k = 0; k < count; ++k) {
+            reps[(size_t)k].resize((size_t)hs[k]->total_reps);
+            SG_HIP(hipMemcpyAsync(reps[(size_t)k].data(), hs[k]->reps(), reps[(size_t)k].size() * sizeof(sg::RepState),
+                                  hipMemcpyDeviceToHost, st),
+                   "state copy");
+        }
+    }
+    SG_HIP(hipStreamSynchronize(st), "stream sync");  // the host tables above are released on return
+    if (unconverged)
+        for (int32_t k = 0; k < count; ++k) {
+            int32_t c = 0;
+            for (const sg::RepState& r : reps[(size_t)k]) c += r.converged ? 0 : 1;
+            unconverged[k] = c;
+        }
+    float hms = 0.f;
+    if (hipEventElapsedTime(&hms, H0->evh0, H0->evh1) != hipSuccess) {
+        (void)hipGetLastError();
+        hms = 0.f;
+    }
+    if (stats) {
+        stats->attempts = (int64_t)cs.attempts;
+        stats->flips = (int64_t)cs.flips;
+        stats->sweeps_max = (int64_t)cs.sweeps_max;
+        stats->n_unconverged = (int32_t)cs.unconverged;
+        stats->schedule_used = SG_SCHED_QUEUE;
+        stats->kernel_ms = hms;
+    }
+    if (p->until_converged && cs.unconverged) {
+        fail(SG_ENOTCONV, "%llu replicas did not converge within %d sweeps", (unsigned long long)cs.unconverged,
+             p->max_sweeps);
+        return SG_ENOTCONV;
+    }
     return SG_OK;
 }
 

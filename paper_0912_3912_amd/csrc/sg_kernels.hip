@@ -404,6 +404,13 @@ hipError_t launch_energy(const InstDev& I, const int8_t* spins, int64_t stride, 
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_energy(const int64_t* slots, int nslots, int R, RepState* rs, int64_t* out, hipStream_t st)
+{
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_energy, dim3(R), dim3(256), 0, st, slots, nslots, rs, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStream_t st)
 {
     const uint64_t work = (uint64_t)(nacc > R ? nacc : R);

@@ -11,6 +11,8 @@ hipError_t launch_fill_u32(void* p, uint64_t count, uint32_t v, hipStream_t st);
 // Energy of every replica of one instance into rs[r].E (out == NULL) or out[r].
 hipError_t launch_energy(const InstDev& I, const int8_t* spins, int64_t stride, int R, int64_t* slots,
                          int nslots, RepState* rs, int64_t* out, hipStream_t st);
+// out[r] (or rs[r].E when out is null) = sum of slots[r * nslots ...], r < R.
+hipError_t launch_reduce_energy(const int64_t* slots, int nslots, int R, RepState* rs, int64_t* out, hipStream_t st);
 hipError_t launch_begin(RepState* rs, int R, int64_t* acc, int64_t nacc, hipStream_t st);
 // t_rel is relative to *t_base when t_base is not null (graph replays);
 // with fields not null the phase reads and maintains the replicas' local
@@ -31,6 +33,14 @@ hipError_t launch_any_active(const RepState* rs, int R, int T, uint32_t* flag, h
 hipError_t launch_philox_word0(const uint32_t* ctr, uint32_t* out, int64_t count, uint64_t seed, hipStream_t st);
 hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_t* restarts, int ninst,
                        int64_t* Eb, int32_t* rb, hipStream_t st);
+
+// wide-form instances (sg_wide.hip): one colour phase, and the energy of
+// every replica (into rs[r].E, or out[r] when out is not null)
+hipError_t launch_wide_phase(const WideDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, int64_t* acc,
+                             int nslots, int slice0, int nslice_c, int t_rel, uint64_t seed, int rule, int until_conv,
+                             hipStream_t st, const int32_t* t_base = nullptr);
+hipError_t launch_wide_energy(const WideDev& I, const int8_t* spins, int64_t stride, int R, int64_t* slots,
+                              int nslots, RepState* rs, int64_t* out, hipStream_t st);
 
 // lattice schedules (sg_lattice.hip)
 size_t lattice_tiles_lds(const TileGeom& tg, const int L[3], int D);

@@ -46,6 +46,39 @@ struct InstDev {
     int32_t has_tri;
 };
 
+// Wide form of an instance whose values or sizes exceed the packed words:
+// couplings, fields or hyper-couplings outside int8 (any int32 value, with
+// |h_i| + sum|J_ij| + sum|K| < 2^31 per spin), more than 2^24 - 1 spins, more
+// than 255 hyper-couplings on one spin or 65535 couplings on one row, or more
+// restarts than one launch dimension holds.  Same colour-major relabel and
+// sliced rows as the packed form; the partner index and the coefficient sit
+// in separate 32-bit words at the same sliced position (k-th entry of the row
+// in lane l at base + k*64 + l).
+struct WSlice {          // 32 bytes
+    uint64_t ebase;      // word offset of the slice's first coupling
+    uint64_t tbase;      // word offset of the slice's first hyper-coupling
+    uint32_t row0;       // internal index of the spin in lane 0
+    uint32_t ew;         // couplings per row in this slice
+    uint32_t tw;         // hyper-couplings per row in this slice
+    uint32_t rows;       // valid rows (1..64)
+};
+static_assert(sizeof(WSlice) == 32, "WSlice must be 32 bytes");
+
+struct WideDev {
+    const uint32_t* nbr;     // coupling partner (internal index)
+    const int32_t* J;        // coupling value
+    const uint32_t* ta;      // hyper-coupling partners a and b
+    const uint32_t* tb;
+    const int32_t* K;        // hyper-coupling value
+    const int32_t* h;        // field per internal index
+    const uint32_t* ext;     // internal -> external index (RNG counter word 0)
+    const WSlice* slices;    // all slices, colour by colour
+    int32_t n;
+    int32_t nslices;
+    uint32_t instance_id;
+    int32_t has_tri;
+};
+
 // Per-replica state, 32 bytes.
 struct RepState {
     int64_t E;          // tracked energy

@@ -72,22 +72,45 @@ def test_validation_errors(sg):
 
 
 def test_range_errors(sg):
+    """The boundary takes any int32 coefficient and rejects (SG_ERANGE) only a
+    spin whose |h| + sum|J| + sum|K| exceeds 2^31 - 1, i.e. whose local field
+    would overflow int32 (and a total beyond 2^63 - 1, which no instance of
+    test size reaches).  Values or sizes beyond the packed words select the
+    wide form, invisibly to the caller."""
     base = gen.random_small(10, seed=2)
-    J = base.J.copy()
-    J[0] = 128
-    assert _err(sg, [base.replace(J=J)]).status == sg.SG_ERANGE
-    h = base.h.copy()
-    h[0] = -128
-    assert _err(sg, [base.replace(h=h)]).status == sg.SG_ERANGE
-    K = base.K.copy()
-    K[0] = 200
-    assert _err(sg, [base.replace(K=K)]).status == sg.SG_ERANGE
-    # a star whose centre field exceeds 2^23 - 1
-    n = 70000
+    for kind, v in (("J", 128), ("h", -128), ("K", 200), ("J", 10**6), ("h", -(2**30))):
+        arr = getattr(base, kind).copy()
+        arr[0] = v
+        h = sg.load_instance([base.replace(**{kind: arr})])
+        assert h.query("wide_instances") == 1, (kind, v)
+        h.free()
+    # a star whose centre field is exactly 2^31 - 1: accepted; one more: SG_ERANGE
+    n = 3
+    c = 2**31 - 1
     star = gen.Instance(n=n, ei=np.zeros(n - 1, np.int32), ej=np.arange(1, n, dtype=np.int32),
-                        J=np.full(n - 1, 127, np.int32))
-    assert _err(sg, [star]).status == sg.SG_ERANGE
-    assert _err(sg, [base.replace(restarts=70000)]).status == sg.SG_ERANGE
+                        J=np.array([c // 2, c - c // 2], np.int32))
+    h = sg.load_instance([star])
+    assert h.query("wide_instances") == 1
+    h.free()
+    over = star.replace(h=np.array([1, 0, 0], np.int32))
+    e = _err(sg, [over])
+    assert e.status == sg.SG_ERANGE and "2147483647" in str(e)
+    lowest = base.J.copy()
+    lowest[0] = -2**31           # |J| = 2^31 alone exceeds the limit
+    assert _err(sg, [base.replace(J=lowest)]).status == sg.SG_ERANGE
+    # the old packed limits are no longer visible: 2^23 per spin, restarts beyond one launch dimension
+    n = 70000
+    big = gen.Instance(n=n, ei=np.zeros(n - 1, np.int32), ej=np.arange(1, n, dtype=np.int32),
+                       J=np.full(n - 1, 127, np.int32))
+    h = sg.load_instance([big])
+    assert h.query("wide_instances") == 1
+    h.free()
+    h = sg.load_instance([base.replace(restarts=70000)])
+    assert h.query("wide_instances") == 1 and h.query("total_replicas") == 70000
+    h.free()
+    h = sg.load_instance([base])
+    assert h.query("wide_instances") == 0
+    h.free()
 
 
 def test_improper_colouring_rejected(sg):
