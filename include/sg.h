@@ -266,6 +266,26 @@ sg_status sg_instance_info_get(sg_handle h, int32_t inst, sg_instance_info* info
  * Errors: SG_ENOMEM if too small, SG_EINVAL if misaligned, SG_EDEVICE. */
 sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
 
+/* Size of the library's static device workspace used by sg_bind_noalloc. */
+#define SG_NOALLOC_MAX_BYTES (64ull << 20)
+
+/* sg_bind without caller memory, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Binds the handle to a workspace of
+ * SG_NOALLOC_MAX_BYTES bytes that the library holds in a statically
+ * allocated device array (one per GPU, held until the process ends) and to a
+ * HIP stream, and uploads the coupling structure, as sg_bind does.  Allocates
+ * no device memory (no hipMalloc, no allocating library routine; the
+ * handle's HIP timing events are created on its first bind, as by sg_bind).  Every
+ * handle bound this way on one GPU shares that array, which keeps the last
+ * user's contents: binding another handle replaces the first one's structure
+ * and state (use the first one again only after binding it again), and calls
+ * that overlap on one GPU race.  The caller still passes inputs (the loaded
+ * handle) and reads outputs into host buffers as with sg_bind.  Errors:
+ * SG_ENOMEM when sg_workspace_bytes exceeds SG_NOALLOC_MAX_BYTES, SG_EDEVICE,
+ * and those of sg_bind. */
+sg_status sg_bind_noalloc(sg_handle h, void* hip_stream);
+
 /* Draw the random start of every replica (Sec. IV: uniform), compute its
  * energy (or leave it to the run that follows, see the "defer_energy" knob
  * of sg_tune), reset sweeps, flips and converged.  Enqueued on the bound

@@ -91,6 +91,7 @@ SIGNATURES = [
     ("sg_workspace_bytes", ctypes.c_int32, [_P, _P]),
     ("sg_instance_info_get", ctypes.c_int32, [_P, ctypes.c_int32, _P, _P]),
     ("sg_bind", ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
+    ("sg_bind_noalloc", ctypes.c_int32, [_P, _P]),
     ("sg_init_spins", ctypes.c_int32, [_P, ctypes.c_uint64]),
     ("sg_set_spins", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("sg_run_sweeps", ctypes.c_int32, [_P, _P, _P]),
@@ -258,6 +259,20 @@ class Handle:
 
     def bind_raw(self, dev_ptr: int, nbytes: int, stream_ptr: int = 0):
         _check(lib().sg_bind(self._h, ctypes.c_void_p(dev_ptr), nbytes, ctypes.c_void_p(stream_ptr)))
+        return self
+
+    def bind_noalloc(self, stream=None, device=None):
+        """Bind to the library's static device workspace (no allocation by
+        the library or by torch) and a torch stream (current stream when
+        None).  Every handle bound this way on one GPU shares that workspace."""
+        import torch
+        if stream is None:
+            dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+            stream = torch.cuda.current_stream(dev)
+        self.workspace = None
+        self.stream = stream
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().sg_bind_noalloc(self._h, ctypes.c_void_p(sp)))
         return self
 
     def init_spins(self, seed: int):
