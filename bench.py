@@ -451,6 +451,12 @@ def run_er(args, sg, gen, torch, count=2000):
     h = sg.load_instance(insts).bind()
     log(f"er{count}: ingest {time.perf_counter() - t0:.1f} s, workspace {h.workspace_bytes() / 1e6:.0f} MB")
 
+    from paper_0912_3912_amd import autotune
+    tune = autotune.autotune(h, seed=args.seed, rule=GREEDY, max_sweeps=10000, until_converged=True)
+    log(f"er{count}: autotuned {tune['setting']} in {tune['calibration_ms']:.0f} ms "
+        f"({len(tune['measured'])} candidates: " + ", ".join(f"{m['setting']} {m['ms']:.2f} ms" for m in tune["measured"])
+        + ")")
+
     def step(schedule=SCHED_AUTO):
         h.init_spins(args.seed)
         st = h.run_sweeps(seed=args.seed, rule=GREEDY, max_sweeps=10000, until_converged=True, schedule=schedule)
@@ -497,6 +503,10 @@ def run_er(args, sg, gen, torch, count=2000):
     algo_launch = bpa * attempts
     return {"workload": f"er{count}_greedy", "attempts_per_s": attempts / dt, "ms_per_step": dt * 1e3,
             "attempts": attempts, "schedule": st["schedule_used"],
+            "autotune": {"key": tune["key"], "setting": tune["setting"],
+                         "calibration_ms": round(tune["calibration_ms"], 1),
+                         "candidates_ms": {json.dumps(m["setting"], sort_keys=True): round(m["ms"], 3)
+                                           for m in tune["measured"]}},
             "per_instance_ms": None if dtp is None else round(dtp * 1e3, 2),
             "per_instance_extrapolated": False, "speedup": None if dtp is None else round(dtp / dt, 2),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -412,11 +412,19 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *                        handle has at least this many queue items (32)
  *   "graph_sweeps"       sweeps per captured HIP graph of SG_SCHED_GRAPH
  *                        (1..1024, default 32)
+ *   "auto_graph"         1: SG_SCHED_AUTO records the per-phase launches of the
+ *                        instances it would run on SG_SCHED_PHASE in HIP graphs
+ *                        (SG_SCHED_GRAPH); 0: plain launches (default 0; the
+ *                        autotuner of the Python package sets it where
+ *                        graphs measure faster)
  *   "lattice_msc"        1: tile lattices whose bonds are all +-1 and whose
  *                        fields satisfy |h| <= 2 with the bit-plane kernel
  *                        (32 sites of a colour per lane word); 0: byte kernel
  *   "msc_k"              halo width of the bit-plane kernel (0 = chosen by
  *                        its cost model, else 1..62)
+ *   "lattice_conv_chunk" most sweeps of one bit-plane launch under
+ *                        until_converged (1..16384, default 16384); a call
+ *                        that needs more runs several launches
  *   "fields"             1: the workspace also holds each replica's local
  *                        fields (4 bytes per spin per replica) and
  *                        SG_SCHED_FIELDS becomes available (SG_SCHED_AUTO

@@ -56,6 +56,7 @@ constexpr int32_t kMaxRestarts = 65535;         // packed form: restarts within 
 constexpr int32_t kMaxWideN = 1 << 30;          // wide form: spins per instance
 constexpr int64_t kMaxWideField = INT32_MAX;    // per-spin |h| + sum|J| + sum|K| (int32 field)
 constexpr int32_t kMaxLatticeTiles = 1024;
+constexpr int32_t kConvChunk = 16384;  // sweeps per bit-plane launch under the stopping rule (counter slots)
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
 constexpr int32_t kLaneStartMaxN = 2048;       // lane-per-replica start/energy: instances up to this size ...
@@ -88,15 +89,17 @@ struct HostInst {
     int32_t bits_ok = 0;               // at most 2048 spins, every |coefficient| <= 15 and per spin
                                        // sum |c| <= 255 (bit-sliced block kernel)
     // last tiling decision and the settings it was made for (rule, knobs)
-    std::array<int32_t, 6> tile_key{{-1, -1, -1, -1, -1, -1}};
-    sg::TileGeom tile_geom{};
-    int32_t tile_msc = 0;
-    double tile_model_phase_us = 0.0, tile_model_ex_us = 0.0;  // cost model of the bit-plane tiling
+    mutable std::array<int32_t, 6> tile_key{{-1, -1, -1, -1, -1, -1}};
+    mutable sg::TileGeom tile_geom{};
+    mutable int32_t tile_msc = 0;
+    mutable int32_t tile_found = 0;
+    mutable double tile_model_phase_us = 0.0, tile_model_ex_us = 0.0;  // cost model of the bit-plane tiling
     int32_t lat_L[3] = {0, 0, 0};      // (x, y, z) extents, z fastest; 2-D: (1, Lx, Ly)
     int32_t lat_D = 0;
     int32_t lat_c0 = 0;
     std::vector<uint64_t> lat_rec;     // per-site coupling record
     uint64_t off_lat_rec = 0, off_lat_g = 0, lat_g_bytes = 0;
+    uint64_t off_lat_cnt = 0;          // per-sweep tile counters of the bit-plane kernel's stopping rule
     // workspace offsets (bytes)
     uint64_t off_nbr = 0, off_ta = 0, off_tb = 0, off_h = 0, off_ext = 0, off_slices = 0, off_eterm = 0;
     uint64_t off_spins = 0, spin_stride = 0, off_acc = 0;
@@ -143,6 +146,8 @@ struct sg_ctx {
     int32_t queue_grid = 0;            // persistent queue grid (0 = co-resident capacity)
     int32_t queue_min_items = 32;      // AUTO uses the queue schedule from this many items
     int32_t graph_sweeps = 32;         // sweeps per captured graph (SG_SCHED_GRAPH)
+    int32_t auto_graph = 0;            // SG_SCHED_AUTO records per-phase launches in graphs (SG_SCHED_GRAPH)
+    int32_t conv_chunk = kConvChunk;   // sweeps per bit-plane launch under the stopping rule
     int32_t lattice_msc = 1;           // use the bit-plane tile kernel where it applies
     int32_t msc_k = 0;                 // its halo width (0 = chosen by the cost model)
     int32_t last_msc = 0;              // the last tile launch used the bit-plane kernel
@@ -913,6 +918,7 @@ void layout(sg_ctx* H)
             // every tile (z extent >= 4 sites)
             q.lat_g_bytes = ((uint64_t)q.n / 4 + 4096) * 8 * 2 * q.R;
             q.off_lat_g = take(q.lat_g_bytes);
+            q.off_lat_cnt = take((uint64_t)q.R * kConvChunk * 8);
 
         }
         max_slots = std::max<int64_t>(max_slots, (int64_t)q.R * q.nslots);
@@ -1291,6 +1297,30 @@ bool choose_tiling_msc(const sg_ctx* H, const HostInst& q, bool tie, sg::TileGeo
     return found;
 }
 
+// The tiling of a lattice instance for the tile kernels (the bit-plane kernel
+// when it applies and fits, else the byte kernel); it depends only on the
+// instance, the rule and the knobs, so it is searched once per setting.
+// False when no tiling fits.
+bool lattice_tiling(const sg_ctx* H, const HostInst& q, int rule, sg::TileGeom& tg, bool& msc)
+{
+    const std::array<int32_t, 6> key{{rule, H->lattice_msc, H->msc_k, H->lattice_max_tiles, H->lattice_k, 1}};
+    if (q.tile_key != key) {
+        sg::TileGeom g{};
+        double mph = 0.0, mex = 0.0;
+        const bool m = q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, rule == 1, g, &mph, &mex);
+        const bool found = m || choose_tiling(H, q, g);
+        q.tile_key = key;
+        q.tile_geom = g;
+        q.tile_msc = m ? 1 : 0;
+        q.tile_found = found ? 1 : 0;
+        q.tile_model_phase_us = m ? mph : 0.0;
+        q.tile_model_ex_us = m ? mex : 0.0;
+    }
+    tg = q.tile_geom;
+    msc = q.tile_msc != 0;
+    return q.tile_found != 0;
+}
+
 sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::vector<int>& which)
 {
     hipStream_t st = H->stream;
@@ -1308,6 +1338,7 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
         const sg::LatticeDev Lt = H->lat_view(q);
         SG_HIP(sg::launch_begin(rs, q.R, acc, (int64_t)q.R * q.acc_slots * 2, st), "begin kernel");
         const int T = p->max_sweeps;
+        int T_done = T;         // sweeps launched (fewer when the tile chunks stop early)
         bool absolute = false;  // the bit-plane kernel leaves final energies, not changes
         if (T > 0) {
             if (lattice_wg_fits(H, q)) {
@@ -1318,49 +1349,62 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
                 H->hot_launches = 1;
             } else {
-                // the tiling depends only on the instance, the rule and the knobs:
-                // search once per setting
-                HostInst& qm = H->insts[qi];
-                const std::array<int32_t, 6> key{{p->rule, H->lattice_msc, H->msc_k, H->lattice_max_tiles,
-                                                  H->lattice_k, 1}};
-                if (qm.tile_key != key) {
-                    sg::TileGeom g{};
-                    double mph = 0.0, mex = 0.0;
-                    const bool m =
-                        q.lat_msc && H->lattice_msc && choose_tiling_msc(H, q, p->rule == 1, g, &mph, &mex);
-                    qm.tile_model_phase_us = m ? mph : 0.0;
-                    qm.tile_model_ex_us = m ? mex : 0.0;
-                    if (!m && !choose_tiling(H, q, g))
-                        return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0],
-                                    q.lat_L[1], q.lat_L[2]);
-                    qm.tile_key = key;
-                    qm.tile_geom = g;
-                    qm.tile_msc = m ? 1 : 0;
-                }
-                const sg::TileGeom tg = qm.tile_geom;
-                const bool msc = qm.tile_msc != 0;
+                sg::TileGeom tg{};
+                bool msc = false;
+                if (!lattice_tiling(H, q, p->rule, tg, msc))
+                    return fail(SG_EINVAL, "lattice schedule: no tiling of %dx%dx%d fits", q.lat_L[0], q.lat_L[1],
+                                q.lat_L[2]);
+                const HostInst& qm = q;
+                if (p->until_converged && !(msc && p->rule == SG_RULE_GREEDY))
+                    return fail(SG_EINVAL, "lattice schedule: the stopping rule on a lattice of %d spins needs the "
+                                           "bit-plane tile kernel under GREEDY", q.n);
                 // exchange words (8 bytes: epoch tag and bits): at most n / (smallest z
                 // extent) + one row per tile, per copy
                 const int64_t words = sg::lattice_tiles_words(tg, q.lat_L) * q.R;
                 if ((uint64_t)words * 16 > q.lat_g_bytes)
                     return fail(SG_ERANGE, "lattice tile exchange needs %lld bytes", (long long)(words * 16));
-                // tags of this launch's epochs start at 1: clear the tags of earlier launches
+                // tags of a launch's epochs start at 1: clear the tags of earlier launches
                 uint64_t* G0 = H->at<uint64_t>(q.off_lat_g);
-                SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(G0), (uint64_t)words * 4, 0u, st), "fill kernel");
+                uint64_t* cnt = H->at<uint64_t>(q.off_lat_cnt);
                 SG_HIP(hipEventRecord(H->evh0, st), "event record");
-                if (msc)
-                    SG_HIP(sg::launch_lattice_msc(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err, rs,
-                                                  q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
-                           "lattice bit-plane kernel");
-                else
-                    SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err, rs,
-                                                    q.R, acc, q.acc_slots, T, p->seed, p->rule, st),
-                           "lattice tile kernel");
+                H->hot_launches = 0;
+                int launched = 0;  // sweeps launched in this call
+                while (launched < T) {
+                    // under the stopping rule the sweeps go in chunks of at most
+                    // kConvChunk (one counter slot per sweep and replica), and a
+                    // chunk ends early once every replica's tiles have seen a sweep
+                    // without a flip
+                    const int Tc = p->until_converged ? std::min(T - launched, H->conv_chunk) : T;
+                    SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(G0), (uint64_t)words * 4, 0u, st),
+                           "fill kernel");
+                    if (p->until_converged)
+                        SG_HIP(sg::launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), (uint64_t)q.R * Tc * 2, 0u, st),
+                               "fill kernel");
+                    if (msc)
+                        SG_HIP(sg::launch_lattice_msc(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err, rs,
+                                                      q.R, acc, q.acc_slots, Tc, p->seed, p->rule, st,
+                                                      p->until_converged ? cnt : nullptr, launched),
+                               "lattice bit-plane kernel");
+                    else
+                        SG_HIP(sg::launch_lattice_tiles(Lt, tg, spins, (int64_t)q.spin_stride, G0, G0 + words, err,
+                                                        rs, q.R, acc, q.acc_slots, Tc, p->seed, p->rule, st),
+                               "lattice tile kernel");
+                    H->hot_launches++;
+                    launched += Tc;
+                    if (!p->until_converged || launched >= T) break;
+                    uint32_t* flag = H->at<uint32_t>(H->off_flag);
+                    uint32_t hflag = 0;
+                    SG_HIP(sg::launch_fill_u32(flag, 1, 0u, st), "fill kernel");
+                    SG_HIP(sg::launch_any_active(rs, q.R, launched, flag, st), "activity kernel");
+                    SG_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
+                    SG_HIP(hipStreamSynchronize(st), "stream sync");
+                    if (!hflag) break;
+                }
+                T_done = launched;
                 H->last_msc = msc ? 1 : 0;
                 absolute = msc;
                 if (msc) H->e_written[(size_t)qi] = 1;
                 SG_HIP(hipEventRecord(H->evh1, st), "event record");
-                H->hot_launches = 1;
                 H->last_tiles[0] = tg.P[0];
                 H->last_tiles[1] = tg.P[1];
                 H->last_tiles[2] = tg.P[2];
@@ -1374,7 +1418,8 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                 H->last_model_phases = msc ? (int64_t)phases : 0;
             }
         }
-        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T, p->until_converged, q.n, cs, st, absolute), "end kernel");
+        SG_HIP(sg::launch_end(rs, q.R, acc, q.acc_slots, T_done, p->until_converged, q.n, cs, st, absolute),
+               "end kernel");
     }
     return SG_OK;
 }
@@ -1611,7 +1656,14 @@ sg_status run_queue_schedule(sg_handle H, const sg_run_params* p, const std::vec
 
 bool can_lattice(const sg_ctx* H, const HostInst& q, const sg_run_params* p)
 {
-    return q.lat_ok && (lattice_wg_fits(H, q) || !p->until_converged);
+    if (!q.lat_ok) return false;
+    if (lattice_wg_fits(H, q) || !p->until_converged) return true;
+    // the stopping rule on the tile kernels: the bit-plane kernel under GREEDY,
+    // where a sweep without a flip is a fixed point (later sweeps change nothing)
+    if (p->rule != SG_RULE_GREEDY) return false;
+    sg::TileGeom tg{};
+    bool msc = false;
+    return lattice_tiling(H, q, p->rule, tg, msc) && msc;
 }
 bool can_block(const sg_ctx* H, const HostInst& q) { return block_rg_for(H, q) > 0; }
 bool can_queue(const HostInst& q) { return !q.wide && q.n <= kQueueMaxN; }
@@ -1632,7 +1684,8 @@ int assign_schedules(const sg_ctx* H, const sg_run_params* p, std::vector<int>& 
             if (can_lattice(H, q, p)) s = SG_SCHED_LATTICE;
             else if (q.R >= H->block_min_restarts && can_block(H, q)) s = SG_SCHED_BLOCK;
             else if (can_queue(q) && queue_items >= H->queue_min_items) s = SG_SCHED_QUEUE;
-            else s = H->fields_ws && !q.wide ? SG_SCHED_FIELDS : SG_SCHED_PHASE;
+            else if (H->fields_ws && !q.wide) s = SG_SCHED_FIELDS;
+            else s = H->auto_graph ? SG_SCHED_GRAPH : SG_SCHED_PHASE;
             break;
         case SG_SCHED_PHASE: s = SG_SCHED_PHASE; break;
         case SG_SCHED_GRAPH: s = SG_SCHED_GRAPH; break;
@@ -2487,6 +2540,12 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "graph_sweeps") {
         if (value < 1 || value > 1024) return fail(SG_EINVAL, "graph_sweeps must be in [1,1024]");
         H->graph_sweeps = (int32_t)value;
+    } else if (k == "lattice_conv_chunk") {
+        if (value < 1 || value > kConvChunk) return fail(SG_EINVAL, "lattice_conv_chunk must be in [1,%d]", kConvChunk);
+        H->conv_chunk = (int32_t)value;
+    } else if (k == "auto_graph") {
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "auto_graph must be 0 or 1");
+        H->auto_graph = (int32_t)value;
     } else if (k == "queue_min_items") {
         if (value < 1) return fail(SG_EINVAL, "queue_min_items must be >= 1");
         H->queue_min_items = (int32_t)std::min<int64_t>(value, INT32_MAX);
@@ -2518,6 +2577,8 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "queue_grid") *value = H->queue_grid;
     else if (k == "queue_min_items") *value = H->queue_min_items;
     else if (k == "graph_sweeps") *value = H->graph_sweeps;
+    else if (k == "auto_graph") *value = H->auto_graph;
+    else if (k == "lattice_conv_chunk") *value = H->conv_chunk;
     else if (k == "fields") *value = H->fields_ws;
     else if (k == "lattice_msc") *value = H->lattice_msc;
     else if (k == "msc_k") *value = H->msc_k;

@@ -55,9 +55,13 @@ int64_t lattice_tiles_words(const TileGeom& tg, const int L[3]);
 size_t lattice_msc_lds(const TileGeom& tg, const int L[3], int D);
 bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D);
 int lattice_msc_max_blocks(const TileGeom& tg, const int L[3], int D);
+// With scnt (per-sweep tile counters, R x T words, zero on entry) the launch
+// runs GREEDY under the stopping rule and a settle kernel then sets each
+// replica's lastflip to done + its first sweep without a flip (or done + T).
 hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint64_t* G0,
                               uint64_t* G1, uint32_t* err, RepState* rs, int R, int64_t* acc,
-                              int nslots, int T, uint64_t seed, int rule, hipStream_t st);
+                              int nslots, int T, uint64_t seed, int rule, hipStream_t st, uint64_t* scnt = nullptr,
+                              int done = 0);
 // The paper's pass-based search, one wavefront per replica item.
 size_t fm_lds_bytes(int nmax, int waves);
 // Workgroups of `waves` wavefronts of the pass kernel with this much LDS

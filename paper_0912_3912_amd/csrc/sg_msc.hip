@@ -33,6 +33,20 @@
 // satisfied) and -s h, so each bond and field of the lattice is counted once
 // (Sec. II eq. (1)); the replica's energy is the sum over its tiles.
 //
+// Stopping rule (CONV, GREEDY only): after each sweep every tile adds one
+// arrival and whether its interior flipped anything to that sweep's counter.
+// Under GREEDY a sweep without a flip anywhere is a fixed point, so sweeps run
+// after it change no spin: a tile keeps sweeping until it knows.  Once the
+// counter of sweep s shows every tile arrived and none flipped, the tiles stop
+// after exchange S - 1, S = e(s) + d + 2, where e(s) is the epoch holding the
+// sweep's last phase and d the largest tile distance (Chebyshev, on the torus
+// of tiles).  Every tile reads the counters after each exchange; a tile that
+// finished exchange e has received words that depend on every tile within
+// distance dd having finished exchange e - dd, so by exchange e(s) + d every
+// tile has seen the completed counter and all stop after the same exchange.
+// The replica's sweep count (the first sweep without a flip, plus one) is
+// settled from the counters after the launch.
+//
 // Neighbours: the +-x and +-y neighbours of a colour-c site are the same bit
 // of the other colour's word in the neighbouring rows (their offset is the
 // same); its -z and +z neighbours are, in the same row's other-colour word,
@@ -40,6 +54,8 @@
 // the -d neighbour, read from that neighbour's plane the same way.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "sg_device.h"
 #include "sg_launch.h"
@@ -122,13 +138,14 @@ __device__ __forceinline__ uint32_t u_eq(uint32_t u0, uint32_t u1, uint32_t u2)
     return ((t & 4) ? u2 : ~u2) & ((t & 2) ? u1 : ~u1) & ((t & 1) ? u0 : ~u0);
 }
 
-template <int D, bool TIE>
+template <int D, bool TIE, bool CONV>
 __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, TileGeom tg, int8_t* __restrict__ canon,
                                                              int64_t stride, uint64_t* __restrict__ G0,
                                                              uint64_t* __restrict__ G1, uint32_t* __restrict__ err, RepState* __restrict__ rs,
                                                              int64_t* __restrict__ acc, int nslots, int T,
-                                                             uint64_t seed)
+                                                             uint64_t seed, uint64_t* __restrict__ scnt, int drift)
 {
+    static_assert(!(CONV && TIE), "the stopping rule runs on the tile kernel under GREEDY only");
     constexpr int NPL = msc_planes(D);
     constexpr int T0 = D + 1;  // flip threshold on U for g in {0, 1}
     extern __shared__ uint32_t lds32[];
@@ -239,6 +256,15 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
     const int P_total = 2 * T;
     int nflip = 0;
     bool failed = false;
+    // stopping rule: this replica's per-sweep counters, the next sweep to
+    // read, and the epoch before which every tile of the replica stops
+    uint64_t* const sc = CONV ? scnt + (int64_t)r * T : nullptr;
+    __shared__ int s_next, s_stop;
+    uint32_t fsw = 0;  // interior flips of this thread in the current sweep
+    if (CONV && tid == 0) {
+        s_next = 0;
+        s_stop = 0x7FFFFFFF;
+    }
 
     for (int e = 0; e * k < P_total; ++e) {
         const int nq = min(k, P_total - e * k);
@@ -310,6 +336,7 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                 const uint32_t I = inner_row ? (zo ? im1 : im0) : 0u;
                 const uint32_t FI = F & I;
                 nflip += __popc(FI);
+                if constexpr (CONV) fsw |= FI;
                 const uint32_t ns = s ^ F;
                 if constexpr (TIE) {
                     const uint32_t odd = (hp | hn) & ~ha;
@@ -375,7 +402,25 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
                     if (ns != s) wc[2 * kPlS] = ns;
                 }
             }
-            __syncthreads();
+            if constexpr (CONV) {
+                if (c == 1) {
+                    // the sweep's last colour: report arrival and whether the interior flipped
+                    const int any = __syncthreads_or(fsw != 0u);
+                    fsw = 0;
+                    if (tid == 0) {
+                        // the returned value is used (a counter never reaches its top
+                        // bit), so the add has completed before this tile's later
+                        // stores, its next exchange words, are issued
+                        const unsigned long long old =
+                            atomicAdd((unsigned long long*)(sc + (p >> 1)), (1ull << 32) | (any ? 1ull : 0ull));
+                        if (old >> 63) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                } else {
+                    __syncthreads();
+                }
+            } else {
+                __syncthreads();
+            }
         }
         // ---- exchange: publish the interior z-rows, then read the box back.
         // Every word travels with the epoch's tag in one 8-byte agent-scope
@@ -440,6 +485,30 @@ __global__ __launch_bounds__(kMscThreads) void k_lattice_msc(LatticeDev Lt, Tile
         }
         failed = __syncthreads_or(failed);
         if (failed) break;
+        if constexpr (CONV) {
+            // after this exchange's reads: the counters of sweeps s_next .. s_next + 63
+            if (wave == 0 && s_stop == 0x7FFFFFFF) {
+                const int s0 = s_next;
+                const int sw = s0 + lane;
+                const bool inb = sw < T;
+                const uint64_t v = inb ? __hip_atomic_load(sc + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+                const bool complete = inb && (uint32_t)(v >> 32) >= (uint32_t)ntiles;
+                const uint64_t cm = __ballot(complete);
+                const uint64_t zm = __ballot(complete && (uint32_t)v == 0u);
+                const int pre = cm == ~0ull ? 64 : __builtin_ctzll(~cm);  // completed prefix
+                const uint64_t zp = pre == 64 ? zm : (zm & ((1ull << pre) - 1ull));
+                if (lane == 0) {
+                    if (zp) {
+                        const int sstar = s0 + __builtin_ctzll(zp);
+                        s_stop = (2 * sstar + 1) / k + drift + 2;
+                    } else {
+                        s_next = s0 + pre;
+                    }
+                }
+            }
+            __syncthreads();
+            if (e + 1 >= s_stop) break;
+        }
     }
     // write the interior back in internal order (one wavefront per row, lane = z)
     if (!failed) {
@@ -545,34 +614,68 @@ bool lattice_msc_geometry_ok(const TileGeom& tg, const int L[3], int D)
     return true;
 }
 
-template <int D, bool TIE>
-static const void* msc_kernel() { return (const void*)k_lattice_msc<D, TIE>; }
+template <int D, bool TIE, bool CONV>
+static const void* msc_kernel() { return (const void*)k_lattice_msc<D, TIE, CONV>; }
 
-static const void* pick_msc_kernel(int D, bool tie)
+static const void* pick_msc_kernel(int D, bool tie, bool conv)
 {
-    return D == 3 ? (tie ? msc_kernel<3, true>() : msc_kernel<3, false>())
-                  : (tie ? msc_kernel<2, true>() : msc_kernel<2, false>());
+    if (conv) return D == 3 ? msc_kernel<3, false, true>() : msc_kernel<2, false, true>();
+    return D == 3 ? (tie ? msc_kernel<3, true, false>() : msc_kernel<3, false, false>())
+                  : (tie ? msc_kernel<2, true, false>() : msc_kernel<2, false, false>());
+}
+
+// The replica's sweep count under the stopping rule, from the counters of
+// its tiles (after the launch): lastflip = done + the first sweep that every
+// tile reached without a flip, or done + T when there is none.  A replica
+// whose lastflip is below done converged in an earlier chunk and is left.
+__global__ void k_msc_settle(RepState* __restrict__ rs, int R, const uint64_t* __restrict__ scnt, int T, int done,
+                             int ntiles)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    RepState* st = rs + r;
+    if (st->converged || st->lastflip < done) return;
+    const uint64_t* sc = scnt + (int64_t)r * T;
+    int first = T;
+    for (int s = 0; s < T; ++s) {
+        const uint64_t v = sc[s];
+        if ((uint32_t)(v >> 32) < (uint32_t)ntiles) break;
+        if ((uint32_t)v == 0u) {
+            first = s;
+            break;
+        }
+    }
+    st->lastflip = done + first;
 }
 
 hipError_t launch_lattice_msc(const LatticeDev& Lt, const TileGeom& tg, int8_t* canon, int64_t stride, uint64_t* G0,
                               uint64_t* G1, uint32_t* err, RepState* rs, int R, int64_t* acc,
-                              int nslots, int T, uint64_t seed, int rule, hipStream_t st)
+                              int nslots, int T, uint64_t seed, int rule, hipStream_t st, uint64_t* scnt, int done)
 {
     if (!lattice_msc_geometry_ok(tg, Lt.L, Lt.D)) return hipErrorInvalidValue;
-    const void* kern = pick_msc_kernel(Lt.D, rule == 1);
+    const bool conv = scnt != nullptr;
+    if (conv && rule == 1) return hipErrorInvalidValue;
+    const void* kern = pick_msc_kernel(Lt.D, rule == 1, conv);
     const size_t lds = lattice_msc_lds(tg, Lt.L, Lt.D);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int ntiles = tg.P[0] * tg.P[1] * tg.P[2];
+    // the largest distance between two tiles on the torus of tiles (Chebyshev)
+    int drift = 0;
+    for (int a = 0; a < 3; ++a) drift = std::max(drift, tg.P[a] / 2);
     LatticeDev a0 = Lt;
     TileGeom a1 = tg;
-    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &err, &rs, &acc, &nslots, &T, &seed};
-    return hipLaunchCooperativeKernel(kern, dim3(ntiles * R), dim3(kMscThreads), args, (unsigned)lds, st);
+    void* args[] = {&a0, &a1, &canon, &stride, &G0, &G1, &err, &rs, &acc, &nslots, &T, &seed, &scnt, &drift};
+    e = hipLaunchCooperativeKernel(kern, dim3(ntiles * R), dim3(kMscThreads), args, (unsigned)lds, st);
+    if (e != hipSuccess || !conv) return e;
+    hipLaunchKernelGGL(k_msc_settle, dim3((R + 63) / 64), dim3(64), 0, st, rs, R, (const uint64_t*)scnt, T, done,
+                       ntiles);
+    return hipGetLastError();
 }
 
 int lattice_msc_max_blocks(const TileGeom& tg, const int L[3], int D)
 {
-    const void* kern = pick_msc_kernel(D, true);
+    const void* kern = pick_msc_kernel(D, true, false);
     const size_t lds = lattice_msc_lds(tg, L, D);
     int per_cu = 0, dev = 0, cus = 0;
     if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||

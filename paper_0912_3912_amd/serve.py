@@ -447,7 +447,9 @@ class Server:
             res.started = self.now()
             h.init_spins(req.seed)
             info = h.info(0)
-            coop = info["lattice"] and not req.until_converged and info["n"] > h.query("lattice_wg_max_n")
+            # a lattice beyond one workgroup runs on the co-resident tile launch
+            # (fixed budgets, and GREEDY until converged on the bit-plane kernel)
+            coop = info["lattice"] and info["n"] > h.query("lattice_wg_max_n")
             if coop:
                 with self.coop_lock:
                     stats = h.run_sweeps(seed=req.seed, rule=req.rule, max_sweeps=req.max_sweeps,

@@ -182,17 +182,50 @@ def test_msc_not_used_when_ineligible(gpu):
     assert h.query("last_msc") == 0
 
 
-def test_tile_mode_refuses_until_converged(gpu):
+def test_tile_mode_stopping_rule_availability(gpu):
+    """The stopping rule runs on the tile kernels only as the bit-plane kernel
+    under GREEDY (where a sweep without a flip is a fixed point): GREEDY_TIE
+    and the byte kernel refuse it on the tile schedule, and SG_SCHED_AUTO
+    then falls back to a schedule that supports it."""
     import paper_0912_3912_amd as sg
     inst = gen.lattice((16, 16, 16), seed=8, h_range=(-2, 2))
     h = sg.load_instance([inst], lattice_dims=[(16, 16, 16)]).tune("lattice_wg_max_n", 0).bind()
     h.init_spins(1)
     with pytest.raises(sg.SGError) as e:
-        h.run_sweeps(seed=1, until_converged=True, schedule=SCHED_LATTICE)
+        h.run_sweeps(seed=1, rule=TIE, until_converged=True, schedule=SCHED_LATTICE)
     assert e.value.status == sg.SG_EINVAL
-    # AUTO falls back to a schedule that supports the stopping rule
-    st = h.run_sweeps(seed=1, until_converged=True)
+    h.tune("lattice_msc", 0)
+    with pytest.raises(sg.SGError) as e:
+        h.run_sweeps(seed=1, rule=GREEDY, until_converged=True, schedule=SCHED_LATTICE)
+    assert e.value.status == sg.SG_EINVAL
+    st = h.run_sweeps(seed=1, rule=GREEDY, until_converged=True)
     assert st["schedule_used"] != SCHED_LATTICE
+    h.tune("lattice_msc", 1)
+    h.init_spins(1)
+    st = h.run_sweeps(seed=1, rule=GREEDY, until_converged=True)
+    assert st["schedule_used"] == SCHED_LATTICE and h.query("last_msc") == 1
+
+
+@pytest.mark.parametrize("dims,R,chunk", [((100, 100, 100), 1, 0), ((64, 64, 64), 3, 0), ((512, 512), 2, 0),
+                                          ((40, 48, 56), 2, 3), ((32, 32, 32), 4, 1)])
+def test_msc_greedy_until_converged(gpu, dims, R, chunk):
+    """GREEDY until converged on the bit-plane tile kernel: tiles keep sweeping
+    until every tile has reported a sweep without a flip, stop together, and
+    the replica's sweep count is the first such sweep plus one.  Small chunks
+    split a run into several launches; capped and resumed calls too."""
+    inst = gen.lattice(dims, seed=len(dims) * 7 + R, h_range=(-2, 2) if len(dims) == 3 else None, restarts=R,
+                       instance_id=40 + R)
+    tune = {"lattice_wg_max_n": 0}
+    if chunk:
+        tune["lattice_conv_chunk"] = chunk
+    h, st = _run([inst], [dims], 5, GREEDY, 10000, True, tune=tune)
+    assert h.query("last_msc") == 1 and st[0]["n_unconverged"] == 0
+    log(f"  tiles={h.query('last_tiles')} k={h.query('last_tile_k')} sweeps_max={st[0]['sweeps_max']} "
+        f"launches={h.query('hot_launches')} kernel_ms={st[0]['kernel_ms']:.3f}")
+    h.free()
+    h, st = _run([inst], [dims], 6, GREEDY, 0, True, tune=tune, runs=[2, 1, 0, 10000])
+    assert st[0]["status"] == 1 and st[-1]["status"] == 0  # the capped call reports SG_ENOTCONV
+    h.free()
 
 
 def test_mixed_lattice_batch(gpu):
