@@ -592,21 +592,41 @@ def run_serving(args, sg, gen, torch):
     t1 = time.perf_counter()
     server.run_trace(cal, [0.0] * ncal)
     cap = ncal / (time.perf_counter() - t1)
-    lam = 0.7 * cap
-    log(f"capacity {cap:.1f} req/s -> arrival rate {lam:.1f} req/s")
-    server2 = Server(budget_bytes=budget, slots=args.serving_slots, ingest_workers=args.serving_ingest)
     server.close()
+    burst = {"requests": ncal, "shared_launches": server.shared_launches,
+             "max_requests_per_shared_launch": max(server.shared_batch_sizes, default=0),
+             "mean_requests_per_shared_launch": float(np.mean(server.shared_batch_sizes))
+             if server.shared_batch_sizes else 0.0}
     del server
+    # the same burst with every request on its own handle and stream (no shared launches)
+    solo = Server(budget_bytes=budget, slots=args.serving_slots, ingest_workers=args.serving_ingest, shared=False)
+    cal = [Request(rid=2_000_000 + k, instance=insts[k], seed=args.seed) for k in range(ncal)]
+    t1 = time.perf_counter()
+    solo.run_trace(cal, [0.0] * ncal)
+    cap_solo = ncal / (time.perf_counter() - t1)
+    solo.close()
+    del solo
+    lam = 0.7 * cap
+    log(f"capacity {cap:.1f} req/s (every request solo: {cap_solo:.1f} req/s) -> arrival rate {lam:.1f} req/s")
+    server2 = Server(budget_bytes=budget, slots=args.serving_slots, ingest_workers=args.serving_ingest)
     requests = [Request(rid=k, instance=inst, seed=args.seed) for k, inst in enumerate(insts)]
     t2 = time.perf_counter()
     results = server2.run_trace(requests, gaps, time_scale=1.0 / lam)
     wall = time.perf_counter() - t2
     server2.close()
     summ = summarize(results, wall)
-    summ.update({"capacity_req_per_s": cap, "arrival_rate_req_per_s": lam, "budget_bytes": budget,
+    summ.update({"capacity_req_per_s": cap, "capacity_all_solo_req_per_s": cap_solo, "burst": burst,
+                 "arrival_rate_req_per_s": lam, "budget_bytes": budget,
                  "slots": args.serving_slots, "peak_resident_bytes": server2.pool.peak,
-                 "max_resident_requests": max(t[2] for t in server2.timeline)})
-    log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['flips_per_s']:.3g} flips/s")
+                 "max_resident_requests": max(t[2] for t in server2.timeline),
+                 "shared_launches": server2.shared_launches,
+                 "max_requests_per_shared_launch": max(server2.shared_batch_sizes, default=0),
+                 "mean_requests_per_shared_launch": float(np.mean(server2.shared_batch_sizes))
+                 if server2.shared_batch_sizes else 0.0})
+    log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms (ingest p50 {summ['ingest_p50_ms']:.1f} "
+        f"p99 {summ['ingest_p99_ms']:.1f}, waiting p99 {summ['admission_wait_p99_ms']:.1f}, device p50 "
+        f"{summ['device_p50_ms']:.1f} p99 {summ['device_p99_ms']:.1f} ms), {summ['flips_per_s']:.3g} flips/s, "
+        f"{summ['shared_launches']} shared launches of up to {summ['max_requests_per_shared_launch']} requests")
     summ["workload"] = f"serving{count}_mixed_greedy"
     summ["ms_per_step"] = wall * 1e3
     # algorithmic bytes of the sliced layout per attempt, request by request
@@ -666,7 +686,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-budget-mb", type=int, default=4096)
     ap.add_argument("--serving-slots", type=int, default=4)
-    ap.add_argument("--serving-ingest", type=int, default=8)
+    ap.add_argument("--serving-ingest", type=int, default=12)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device 3 times (counter calibration) and exit")
     args = ap.parse_args()

@@ -325,8 +325,8 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
     if (d.restarts < 1) return fail(SG_EINVAL, "instance %d: restarts must be >= 1", idx);
     if (d.restarts > kMaxRestarts) w = true;
     const int64_t n = d.n;
-    std::vector<uint64_t> keys((size_t)d.m);
     std::vector<int64_t> field((size_t)n, 0);
+    std::vector<int64_t> bstart((size_t)n + 1, 0);  // edges bucketed by their smaller endpoint
     __int128 total = 0;  // sum |J| + sum |h| + sum |K|
     for (int64_t k = 0; k < d.m; ++k) {
         const int64_t a = d.ei[k], b = d.ej[k];
@@ -336,16 +336,30 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
                                 (long long)a);
         const int64_t c = std::llabs((int64_t)d.J[k]);
         if (c > kMaxCoef) w = true;
-        keys[k] = (uint64_t)std::min(a, b) * (uint64_t)n + (uint64_t)std::max(a, b);
+        bstart[(size_t)std::min(a, b) + 1]++;
         field[a] += c;
         field[b] += c;
         total += c;
     }
-    std::sort(keys.begin(), keys.end());
-    for (size_t k = 1; k < keys.size(); ++k)
-        if (keys[k] == keys[k - 1])
-            return fail(SG_EINVAL, "instance %d: edge (%llu,%llu) given twice", idx,
-                        (unsigned long long)(keys[k] / n), (unsigned long long)(keys[k] % n));
+    {
+        // duplicate pairs: a counting sort by the smaller endpoint, then each
+        // bucket's larger endpoints sorted (buckets are short)
+        for (int64_t i = 0; i < n; ++i) bstart[(size_t)i + 1] += bstart[(size_t)i];
+        std::vector<int32_t> other((size_t)d.m);
+        std::vector<int64_t> at(bstart.begin(), bstart.end() - 1);
+        for (int64_t k = 0; k < d.m; ++k) {
+            const int32_t a = d.ei[k], b = d.ej[k];
+            other[(size_t)at[(size_t)std::min(a, b)]++] = std::max(a, b);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            auto lo = other.begin() + bstart[(size_t)i], hi = other.begin() + bstart[(size_t)i + 1];
+            if (hi - lo < 2) continue;
+            std::sort(lo, hi);
+            for (auto it = lo + 1; it < hi; ++it)
+                if (*it == *(it - 1))
+                    return fail(SG_EINVAL, "instance %d: edge (%lld,%d) given twice", idx, (long long)i, *it);
+        }
+    }
     std::vector<std::array<int32_t, 3>> tk((size_t)d.t);
     for (int64_t k = 0; k < d.t; ++k) {
         std::array<int32_t, 3> v = {d.tri[3 * k], d.tri[3 * k + 1], d.tri[3 * k + 2]};

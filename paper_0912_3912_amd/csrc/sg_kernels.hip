@@ -357,23 +357,40 @@ __global__ void k_philox_word0(const uint32_t* __restrict__ ctr, uint32_t* __res
                               (uint32_t)(seed >> 32));
 }
 
-// Multi-start result per instance: lowest tracked energy, lowest restart on ties.
+// Multi-start result per instance: lowest tracked energy, lowest restart on
+// ties.  One wavefront per instance: lanes take restarts lane, lane + 64, ...,
+// then a butterfly keeps the lexicographically smallest (energy, restart).
 __global__ void k_best(const RepState* __restrict__ rs, const int64_t* __restrict__ rep_base,
                        const int32_t* __restrict__ restarts, int ninst, int64_t* __restrict__ Eb,
                        int32_t* __restrict__ rb)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= ninst) return;
+    const int q = blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= ninst) return;  // uniform over the wavefront
     const RepState* p = rs + rep_base[q];
-    int best = 0;
-    int64_t e = p[0].E;
-    for (int r = 1; r < restarts[q]; ++r)
-        if (p[r].E < e) {
-            e = p[r].E;
+    const int R = restarts[q];
+    long long e = 0x7FFFFFFFFFFFFFFFll;
+    int best = 0x7FFFFFFF;
+    for (int r = lane; r < R; r += 64) {
+        const long long v = p[r].E;
+        if (v < e) {  // restarts rise along a lane: the first of equal energies is kept
+            e = v;
             best = r;
         }
-    Eb[q] = e;
-    rb[q] = best;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long e2 = __shfl_xor(e, o, 64);
+        const int b2 = __shfl_xor(best, o, 64);
+        if (e2 < e || (e2 == e && b2 < best)) {
+            e = e2;
+            best = b2;
+        }
+    }
+    if (lane == 0) {
+        Eb[q] = e;
+        rb[q] = best;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -490,8 +507,8 @@ hipError_t launch_philox_word0(const uint32_t* ctr, uint32_t* out, int64_t count
 hipError_t launch_best(const RepState* rs, const int64_t* rep_base, const int32_t* restarts, int ninst,
                        int64_t* Eb, int32_t* rb, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_best, dim3(grid1(ninst, 256, 1u << 30)), dim3(256), 0, st, rs, rep_base, restarts,
-                       ninst, Eb, rb);
+    hipLaunchKernelGGL(k_best, dim3(grid1((uint64_t)ninst * 64, 256, 1u << 30)), dim3(256), 0, st, rs, rep_base,
+                       restarts, ninst, Eb, rb);
     return hipGetLastError();
 }
 

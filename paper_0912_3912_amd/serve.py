@@ -104,6 +104,7 @@ class Result:
     footprint: int = 0
     slot: int = -1
     arrival: float = 0.0
+    ingested: float = 0.0         # host ingest finished (validated, coloured, packed)
     admitted: float = 0.0
     started: float = 0.0
     done: float = 0.0
@@ -191,6 +192,7 @@ class Server:
         self.timeline: List[tuple] = []  # (time, bytes resident, requests resident)
         self.cancelled = set()
         self.admitted = set()
+        self.ingest_done: Dict[int, float] = {}
         self.tick_sweeps = max(1, int(tick_sweeps))
         self.shared_enabled = bool(shared)
         self.paused = False
@@ -314,6 +316,7 @@ class Server:
             fp = h.workspace_bytes()
             shared = (self.shared_enabled and req.until_converged and req.rule == self.sg.GREEDY
                       and h.query("queue_ok") == 1)
+            self.ingest_done[req.rid] = self.now()
         except Exception as e:  # invalid instance
             with self.lock:
                 self._finish_unadmitted(req.rid, f"error: {e}")
@@ -369,7 +372,8 @@ class Server:
     def _join(self, rid: int, off: int, h):
         req = self.requests[rid]
         fp = h.workspace_bytes()
-        res = Result(rid=rid, status="ok", footprint=fp, slot=-1, arrival=req.arrival, admitted=self.now())
+        res = Result(rid=rid, status="ok", footprint=fp, slot=-1, arrival=req.arrival, admitted=self.now(),
+                     ingested=self.ingest_done.get(rid, req.arrival))
         try:
             h.bind_raw(self.mem.data_ptr() + off, fp, self.group_stream.cuda_stream)
             h.init_spins(req.seed)
@@ -439,7 +443,8 @@ class Server:
         with self.lock:
             h = self.handles.pop(rid)
         fp = h.workspace_bytes()
-        res = Result(rid=rid, status="ok", footprint=fp, slot=slot, arrival=req.arrival, admitted=self.now())
+        res = Result(rid=rid, status="ok", footprint=fp, slot=slot, arrival=req.arrival, admitted=self.now(),
+                     ingested=self.ingest_done.get(rid, req.arrival))
         try:
             st = self.streams[slot]
             base = self.mem.data_ptr() + off
@@ -475,12 +480,26 @@ class Server:
 
 
 def summarize(results: List[Result], wall: float) -> dict:
+    """Latency (arrival to result on the host) percentiles and throughput,
+    with the latency split into host ingest (arrival to packed), waiting for
+    admission (packed to admitted) and the run on the device (admitted to
+    result, including the start and the readout)."""
     ok = [r for r in results if r.status in ("ok", "notconv")]
     lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    ing = np.array([r.ingested - r.arrival for r in ok]) if ok else np.zeros(1)
+    wai = np.array([r.admitted - r.ingested for r in ok]) if ok else np.zeros(1)
+    run = np.array([r.done - r.admitted for r in ok]) if ok else np.zeros(1)
     att = sum(r.attempts for r in ok)
     fl = sum(r.flips for r in ok)
+
+    def pct(a, q):
+        return float(np.percentile(a, q) * 1e3)
+
     return {"requests": len(results), "completed": len(ok),
             "rejected": sum(r.status == "rejected" for r in results),
-            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "wall_s": wall, "attempts_per_s": att / wall,
-            "flips_per_s": fl / wall, "requests_per_s": len(ok) / wall}
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean() * 1e3),
+            "ingest_p50_ms": pct(ing, 50), "ingest_p99_ms": pct(ing, 99),
+            "admission_wait_p50_ms": pct(wai, 50), "admission_wait_p99_ms": pct(wai, 99),
+            "device_p50_ms": pct(run, 50), "device_p99_ms": pct(run, 99),
+            "shared_requests": sum(r.slot < 0 for r in ok), "solo_requests": sum(r.slot >= 0 for r in ok),
+            "wall_s": wall, "attempts_per_s": att / wall, "flips_per_s": fl / wall, "requests_per_s": len(ok) / wall}

@@ -23,11 +23,11 @@ pytestmark = pytest.mark.gpu
 GREEDY, TIE = 0, 1
 
 
-def _alone(inst, seed):
+def _alone(inst, seed, rule=GREEDY, max_sweeps=10000, until_converged=True):
     import paper_0912_3912_amd as sg
     h = sg.load_instance([inst]).bind()
     h.init_spins(seed)
-    st = h.run_sweeps(seed=seed)
+    st = h.run_sweeps(seed=seed, rule=rule, max_sweeps=max_sweeps, until_converged=until_converged)
     E, r = h.best()
     s = h.spins_out(0, int(r[0]))
     h.free()
@@ -163,9 +163,13 @@ def test_serving_full_range_equals_alone_and_oracle(gpu):
         f"budget {budget} B")
     server = Server(budget_bytes=budget, slots=2, ingest_workers=4, keep_spins=True, tick_sweeps=4)
     reqs = [Request(rid=k, instance=inst, seed=11) for k, inst in enumerate(insts)]
+    # a 10^6-spin lattice under a fixed GREEDY_TIE budget (the co-resident tile launch) among the others
+    tie = dict(rule=TIE, max_sweeps=200, until_converged=False)
+    reqs[-2] = Request(rid=len(insts) - 2, instance=insts[-2], seed=11, **tie)
     results = server.run_trace(reqs, gaps, time_scale=0.002)
     server.close()
     assert all(r.status == "ok" for r in results), [r.status for r in results]
+    assert results[-2].slot >= 0  # the fixed-budget lattice ran solo, beside the shared launches
     assert server.pool.peak <= server.pool.size
     assert max(t[2] for t in server.timeline) >= 2, "no two requests were ever resident together"
     assert server.shared_launches > 0 and max(server.shared_batch_sizes) >= 2, "no launch was shared"
@@ -173,12 +177,13 @@ def test_serving_full_range_equals_alone_and_oracle(gpu):
         f"{sum(r.slot >= 0 for r in results)} solo requests")
     iv = sorted((r.started, r.done) for r in results)
     assert any(b[0] < a[1] for a, b in zip(iv, iv[1:]))
-    for inst, res in zip(insts, results):
-        E, r, s, st = _alone(inst, 11)
+    for req, inst, res in zip(reqs, insts, results):
+        kw = dict(rule=req.rule, max_sweeps=req.max_sweeps, until_converged=req.until_converged)
+        E, r, s, st = _alone(inst, 11, **kw)
         assert (res.energy, res.best_restart) == (E, r), inst.name
         assert np.array_equal(res.spins, s), inst.name
         assert res.flips == st["flips"] and res.attempts == st["attempts"], inst.name
-        ref, _ = oracle.run(inst, seed=11, threads=1)
+        ref, _ = oracle.run(inst, seed=11, threads=1, **kw)
         assert res.energy == int(ref.energy.min()), inst.name
         assert np.array_equal(res.spins, ref.spins[int(np.argmin(ref.energy))]), inst.name
 
