@@ -54,6 +54,7 @@ class Instance:
     instance_id: int = 0
     restarts: int = 1
     name: str = ""
+    dims: Optional[tuple] = None      # lattice hint (periodic extents) passed to the solver, or None
 
     def __post_init__(self):
         self.ei = np.ascontiguousarray(self.ei, dtype=np.int32)
@@ -98,7 +99,7 @@ def _pm1(rng, size) -> np.ndarray:
 
 def lattice(dims: Sequence[int], periodic=True, seed=0, j_values=(-1, 1),
             h_range: Optional[tuple] = None, checkerboard=True,
-            instance_id=0, restarts=1, name="") -> Instance:
+            instance_id=0, restarts=1, name="", hint=False) -> Instance:
     """d-dimensional hypercubic lattice, row-major site index (last axis fastest).
 
     Every site has one bond in the + direction of each axis; with ``periodic``
@@ -139,7 +140,8 @@ def lattice(dims: Sequence[int], periodic=True, seed=0, j_values=(-1, 1),
         colour = (coords.sum(axis=0) % 2).astype(np.int32)
     return Instance(n=n, ei=ei, ej=ej, J=J, h=h, colour=colour,
                     instance_id=instance_id, restarts=restarts,
-                    name=name or "lattice" + "x".join(map(str, dims)))
+                    name=name or "lattice" + "x".join(map(str, dims)),
+                    dims=tuple(dims) if hint and periodic else None)
 
 
 @functools.lru_cache(maxsize=16)
@@ -437,13 +439,14 @@ def cfg4_uneven_batch(count=2000, seed=4, sizes=None) -> List[Instance]:
 
 def serving_instance(family: str, n_target: int, seed, instance_id: int) -> Instance:
     """One request of the mixed serving workload (families: 'sq2', 'cub3',
-    'chimera', 'reg3'), sized near ``n_target`` spins."""
+    'chimera', 'reg3'), sized near ``n_target`` spins.  Lattice requests carry
+    their periodic extents as the solver's lattice hint."""
     if family == "sq2":
         L = max(4, int(round(math.sqrt(n_target) / 2)) * 2)
-        return lattice((L, L), seed=seed, instance_id=instance_id, name=f"sq{L}")
+        return lattice((L, L), seed=seed, instance_id=instance_id, name=f"sq{L}", hint=True)
     if family == "cub3":
         L = max(4, int(round(n_target ** (1 / 3) / 2)) * 2)
-        return lattice((L, L, L), seed=seed, instance_id=instance_id, name=f"cub{L}")
+        return lattice((L, L, L), seed=seed, instance_id=instance_id, name=f"cub{L}", hint=True)
     if family == "chimera":
         G = max(2, int(round(math.sqrt(n_target / 8))))
         return chimera(G, G, seed=seed, instance_id=instance_id, name=f"chim{G}")

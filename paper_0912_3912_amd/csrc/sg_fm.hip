@@ -222,18 +222,35 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                     if constexpr (K32) return fm_key32(gn, e);
                     else return fm_key(gn, e);
                 };
+                // this lane's best unlocked key: its spins lane, lane + 64, ... in
+                // groups of eight, every load of a group issued before any is used
+                // (one LDS round trip per group instead of one per spin)
+                auto scan = [&](uint64_t lk, Key& bk, int& bi) {
+                    bk = 0;
+                    bi = -1;
+                    for (int k0 = 0; k0 < G; k0 += 8) {
+                        Key kk[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int k = k0 + u;
+                            const int ii = lane + 64 * k;
+                            const bool ok = k < G && ii < n && !((lk >> (k & 63)) & 1ull);
+                            const int is = ok ? ii : 0;
+                            const int gv = gain[is];
+                            const int ev = ext[is];
+                            kk[u] = ok ? make_key(gv, ev) : Key(0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (kk[u] > bk) {
+                                bk = kk[u];
+                                bi = lane + 64 * (k0 + u);
+                            }
+                    }
+                };
                 Key best = 0;
                 int besti = -1;
-                for (int k = 0; k < G; ++k) {
-                    const int i = lane + 64 * k;
-                    if (i < n) {
-                        const Key key = make_key(gain[i], ext[i]);
-                        if (key > best) {
-                            best = key;
-                            besti = i;
-                        }
-                    }
-                }
+                scan(0ull, best, besti);
                 long long E = Estar, Elow = Estar;
                 int best_len = 0;
                 for (int step = 0; step < n; ++step) {
@@ -292,20 +309,7 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
                     }
                     wave_lds_order();
                     if (lane < 2) dirty[lane] = 0u;
-                    if (rescan) {
-                        best = 0;
-                        besti = -1;
-                        for (int k = 0; k < G; ++k) {
-                            const int ii = lane + 64 * k;
-                            if (ii < n && !((locked >> k) & 1ull)) {
-                                const Key key = make_key(gain[ii], ext[ii]);
-                                if (key > best) {
-                                    best = key;
-                                    besti = ii;
-                                }
-                            }
-                        }
-                    }
+                    if (rescan) scan(locked, best, besti);
                     E -= g;
                     if (E < Elow) {
                         Elow = E;

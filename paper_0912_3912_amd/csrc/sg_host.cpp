@@ -14,6 +14,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sg.h"
@@ -48,6 +49,27 @@ sg_status hip_fail(hipError_t e, const char* what)
 
 constexpr uint64_t kAlign = 256;
 inline uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// f(lo, hi) over [0, count) in contiguous ranges on up to four host threads
+// (one below 2^16 items): the per-row loops of a large instance's ingest.
+template <class F>
+void parallel_ranges(int64_t count, F&& f)
+{
+    unsigned T = std::thread::hardware_concurrency();
+    T = std::min(T ? T : 1u, 4u);
+    if (count < 65536 || T <= 1) {
+        f((int64_t)0, count);
+        return;
+    }
+    const int64_t step = (count + T - 1) / T;
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < T; ++t) {
+        const int64_t lo = std::min<int64_t>(count, (int64_t)t * step), hi = std::min<int64_t>(count, lo + step);
+        if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    f((int64_t)0, std::min<int64_t>(count, step));
+    for (std::thread& x : th) x.join();
+}
 
 constexpr int32_t kMaxN = (1 << 24) - 1;
 constexpr int32_t kMaxCoef = 127;
@@ -351,14 +373,26 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
             const int32_t a = d.ei[k], b = d.ej[k];
             other[(size_t)at[(size_t)std::min(a, b)]++] = std::max(a, b);
         }
-        for (int64_t i = 0; i < n; ++i) {
-            auto lo = other.begin() + bstart[(size_t)i], hi = other.begin() + bstart[(size_t)i + 1];
-            if (hi - lo < 2) continue;
-            std::sort(lo, hi);
-            for (auto it = lo + 1; it < hi; ++it)
-                if (*it == *(it - 1))
-                    return fail(SG_EINVAL, "instance %d: edge (%lld,%d) given twice", idx, (long long)i, *it);
-        }
+        std::vector<int64_t> dup_row(4, -1);
+        std::vector<int32_t> dup_col(4, 0);
+        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+            const size_t slot = (size_t)(r0 * 4 / std::max<int64_t>(n, 1));
+            for (int64_t i = r0; i < r1; ++i) {
+                auto lo = other.begin() + bstart[(size_t)i], hi = other.begin() + bstart[(size_t)i + 1];
+                if (hi - lo < 2) continue;
+                std::sort(lo, hi);
+                for (auto it = lo + 1; it < hi; ++it)
+                    if (*it == *(it - 1)) {
+                        dup_row[slot] = i;
+                        dup_col[slot] = *it;
+                        return;
+                    }
+            }
+        });
+        for (size_t t = 0; t < dup_row.size(); ++t)
+            if (dup_row[t] >= 0)
+                return fail(SG_EINVAL, "instance %d: edge (%lld,%d) given twice", idx, (long long)dup_row[t],
+                            dup_col[t]);
     }
     std::vector<std::array<int32_t, 3>> tk((size_t)d.t);
     for (int64_t k = 0; k < d.t; ++k) {
@@ -408,21 +442,34 @@ sg_status check_lattice(const sg_instance_desc& d, int idx)
     if (d.m != (int64_t)dim * d.n)
         return fail(SG_EINVAL, "instance %d: a periodic %d-D lattice has %lld bonds, got %lld", idx, dim,
                     (long long)dim * d.n, (long long)d.m);
-    for (int64_t k = 0; k < d.m; ++k) {
-        int64_t a = d.ei[k], b = d.ej[k];
-        int64_t ca[3] = {a / (L[1] * L[2]), (a / L[2]) % L[1], a % L[2]};
-        int64_t cb[3] = {b / (L[1] * L[2]), (b / L[2]) % L[1], b % L[2]};
-        int diff = 0, ok = 1;
-        for (int q = 0; q < 3; ++q) {
-            if (ca[q] == cb[q]) continue;
-            ++diff;
-            const int64_t dd = (cb[q] - ca[q] + L[q]) % L[q];
-            if (dd != 1 && dd != L[q] - 1) ok = 0;
+    // every edge joins two sites that differ by one step along one axis (in
+    // 32-bit arithmetic: n < 2^31), checked over a few host threads
+    const int32_t L1 = (int32_t)L[1], L2 = (int32_t)L[2], L12 = (int32_t)(L[1] * L[2]);
+    const int32_t Lq[3] = {(int32_t)L[0], L1, L2};
+    std::vector<int64_t> bad(4, -1);
+    parallel_ranges(d.m, [&](int64_t k0, int64_t k1) {
+        const size_t slot = (size_t)(k0 * 4 / std::max<int64_t>(d.m, 1));
+        for (int64_t k = k0; k < k1; ++k) {
+            const int32_t a = d.ei[k], b = d.ej[k];
+            const int32_t ca[3] = {a / L12, (a / L2) % L1, a % L2};
+            const int32_t cb[3] = {b / L12, (b / L2) % L1, b % L2};
+            int diff = 0, ok = 1;
+            for (int q = 0; q < 3; ++q) {
+                if (ca[q] == cb[q]) continue;
+                ++diff;
+                const int32_t dd = (cb[q] - ca[q] + Lq[q]) % Lq[q];
+                if (dd != 1 && dd != Lq[q] - 1) ok = 0;
+            }
+            if (diff != 1 || !ok) {
+                bad[slot] = k;
+                return;
+            }
         }
-        if (diff != 1 || !ok)
-            return fail(SG_EINVAL, "instance %d: edge %lld (%lld,%lld) is not a lattice bond", idx, (long long)k,
-                        (long long)a, (long long)b);
-    }
+    });
+    for (int64_t k : bad)
+        if (k >= 0)
+            return fail(SG_EINVAL, "instance %d: edge %lld (%d,%d) is not a lattice bond", idx, (long long)k, d.ei[k],
+                        d.ej[k]);
     return SG_OK;
 }
 
@@ -612,11 +659,27 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     // colour-major relabel, decreasing incidence inside a colour, stable
     q.ext_of.resize((size_t)n);
     std::iota(q.ext_of.begin(), q.ext_of.end(), 0u);
-    std::stable_sort(q.ext_of.begin(), q.ext_of.end(), [&](uint32_t a, uint32_t b) {
-        if (q.colour[a] != q.colour[b]) return q.colour[a] < q.colour[b];
-        if (deg[a] != deg[b]) return deg[a] > deg[b];
-        return tdeg[a] > tdeg[b];
-    });
+    {
+        // order (colour ascending, couplings descending, triples descending,
+        // index ascending) by three stable counting sorts, least significant
+        // key first
+        std::vector<uint32_t> tmp((size_t)n);
+        auto pass = [&](auto key, int64_t kmax) {
+            std::vector<int64_t> cnt((size_t)kmax + 2, 0);
+            for (int32_t k = 0; k < n; ++k) cnt[(size_t)key(q.ext_of[k]) + 1]++;
+            for (int64_t v = 0; v <= kmax; ++v) cnt[(size_t)v + 1] += cnt[(size_t)v];
+            for (int32_t k = 0; k < n; ++k) tmp[(size_t)cnt[(size_t)key(q.ext_of[k])]++] = q.ext_of[k];
+            q.ext_of.swap(tmp);
+        };
+        int64_t dmax = 0, tmax = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            dmax = std::max<int64_t>(dmax, deg[i]);
+            tmax = std::max<int64_t>(tmax, tdeg[i]);
+        }
+        pass([&](uint32_t i) { return tmax - tdeg[i]; }, tmax);
+        pass([&](uint32_t i) { return dmax - deg[i]; }, dmax);
+        pass([&](uint32_t i) { return (int64_t)q.colour[i]; }, (int64_t)q.C - 1);
+    }
     std::vector<uint32_t> int_of((size_t)n);
     for (int32_t i = 0; i < n; ++i) int_of[q.ext_of[i]] = (uint32_t)i;
 
@@ -649,17 +712,21 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
                 twb[ft[v[s]]++] = std::max(o1, o2);
             }
         }
-        for (int32_t i = 0; i < n; ++i) {
-            std::sort(ew.begin() + es[i], ew.begin() + es[i + 1]);
-            // order triple entries of a row by partner (pairs sorted together)
+        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
             std::vector<std::pair<uint32_t, uint32_t>> tmp;
-            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) tmp.emplace_back(twa[k], twb[k]);
-            std::sort(tmp.begin(), tmp.end());
-            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
-                twa[k] = tmp[k - ts[i]].first;
-                twb[k] = tmp[k - ts[i]].second;
+            for (int64_t i = r0; i < r1; ++i) {
+                std::sort(ew.begin() + es[i], ew.begin() + es[i + 1]);
+                // order triple entries of a row by partner (pairs sorted together)
+                if (ts[i + 1] - ts[i] < 2) continue;
+                tmp.clear();
+                for (int64_t k = ts[i]; k < ts[i + 1]; ++k) tmp.emplace_back(twa[k], twb[k]);
+                std::sort(tmp.begin(), tmp.end());
+                for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
+                    twa[k] = tmp[k - ts[i]].first;
+                    twb[k] = tmp[k - ts[i]].second;
+                }
             }
-        }
+        });
     }
     // fields
     q.h.assign((size_t)n, 0);
@@ -754,16 +821,19 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
                 }
             }
     }
-    for (const sg::Slice& S : q.slices) {
-        for (int32_t l = 0; l < S.rows; ++l) {
-            const int32_t i = (int32_t)S.row0 + l;
-            for (int64_t k = es[i]; k < es[i + 1]; ++k) q.nbr[S.ebase + (k - es[i]) * sg::kSlice + l] = ew[k];
-            for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
-                q.ta[S.tbase + (k - ts[i]) * sg::kSlice + l] = twa[k];
-                q.tb[S.tbase + (k - ts[i]) * sg::kSlice + l] = twb[k];
+    parallel_ranges((int64_t)q.slices.size(), [&](int64_t s0, int64_t s1) {
+        for (int64_t si = s0; si < s1; ++si) {
+            const sg::Slice& S = q.slices[(size_t)si];
+            for (int32_t l = 0; l < S.rows; ++l) {
+                const int32_t i = (int32_t)S.row0 + l;
+                for (int64_t k = es[i]; k < es[i + 1]; ++k) q.nbr[S.ebase + (k - es[i]) * sg::kSlice + l] = ew[k];
+                for (int64_t k = ts[i]; k < ts[i + 1]; ++k) {
+                    q.ta[S.tbase + (k - ts[i]) * sg::kSlice + l] = twa[k];
+                    q.tb[S.tbase + (k - ts[i]) * sg::kSlice + l] = twb[k];
+                }
             }
         }
-    }
+    });
     if (q.lattice && q.t == 0) build_lattice(d, q, int_of);
     return SG_OK;
 }
