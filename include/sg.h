@@ -402,6 +402,19 @@ sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
  *   "fm_key32"           1: SG_RULE_FM picks moves on 32-bit keys when every
  *                        gain is below 2^19 in magnitude; 0: 64-bit keys
  *                        (default 1)
+ *   "fm_lanes"           1: SG_RULE_FM runs one replica per lane for every
+ *                        instance of at most 1024 spins whose per-spin sum
+ *                        |h|+sum|J|+sum|K| is at most 127 (the others one
+ *                        replica per wavefront); 0: one replica per wavefront
+ *                        throughout (default 1; results are the same).  The
+ *                        per-spin term lists of those instances are part of
+ *                        the workspace (about 4 words per spin and 1 per
+ *                        coupling incidence); 0 set before sg_bind leaves
+ *                        them out, and 1 after such a bind is SG_EINVAL
+ *   "fm_lane_restarts"   restarts handed to one wavefront of the lane kernel,
+ *                        which refills its lanes from them as replicas finish
+ *                        (0 = the largest multiple of 64 that still gives
+ *                        every resident wavefront one; else a multiple of 64)
  *   "block_min_restarts" SG_SCHED_AUTO uses the block schedule for instances
  *                        with at least this many restarts (default 32)
  *   "queue_wave_max_n"   queue items with at most this many spins run one per
@@ -442,7 +455,9 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
  * halo exchange, and how many of each the launch holds), "last_bits" (1 when the last block-schedule call
  * used the bit-sliced kernel), "last_key32" (1 when the last SG_RULE_FM call
  * picked moves on 32-bit keys), "last_fm_waves" (its wavefronts per
- * workgroup), "energy_pending" (1 while start energies
+ * workgroup, 0 when every replica ran one per lane), "last_fm_lanes" (its
+ * replicas run one per lane), "last_fm_lane_nr" (its restarts per lane-kernel
+ * wavefront), "energy_pending" (1 while start energies
  * left out by sg_init_spins are not yet computed), "last_queue_grid",
  * "total_replicas", "queue_ok" (1 when every instance can join sg_run_group),
  * "wide_instances" (instances stored in the wide form: a

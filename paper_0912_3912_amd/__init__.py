@@ -23,6 +23,8 @@ import os
 import sys
 from typing import Optional, Sequence
 
+_finalizing = sys.is_finalizing  # kept: module globals may be cleared at shutdown
+
 import numpy as np
 
 __all__ = [
@@ -344,7 +346,7 @@ class Handle:
         # exit: by then the HIP runtime, and any profiler attached to it, may
         # already be finalised, so sg_free's event and stream destruction
         # would call into a torn-down runtime.  Call free() explicitly.
-        if sys.is_finalizing():
+        if _finalizing is None or _finalizing():
             return
         try:
             self.free()

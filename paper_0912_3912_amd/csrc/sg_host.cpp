@@ -81,6 +81,8 @@ constexpr int32_t kMaxLatticeTiles = 1024;
 constexpr int32_t kConvChunk = 16384;  // sweeps per bit-plane launch under the stopping rule (counter slots)
 constexpr size_t kLatLdsBudget = 160 * 1024 - 4 * 1024;  // dynamic LDS of the tile kernels
 constexpr int32_t kFmMaxN = 4096;          // largest instance of the pass-based search (LDS per wavefront)
+constexpr int32_t kFmlMaxN = 1024;         // one replica per lane: instances up to this size ...
+constexpr int64_t kFmlMaxW = 127;          // ... whose per-spin sum of |coefficients| fits a byte gain
 constexpr int32_t kLaneStartMaxN = 2048;       // lane-per-replica start/energy: instances up to this size ...
 constexpr int32_t kLaneStartMinR = 32;         // ... with at least this many restarts, ...
 constexpr int64_t kLaneStartMinTotal = 16384;  // ... when such replicas fill the chip (64 per wavefront)  // instances below this size start and evaluate in batched launches
@@ -108,6 +110,8 @@ struct HostInst {
     int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
     int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
     int64_t max_w = 0;                 // largest sum of |coefficients| over one spin's terms
+    uint64_t fml_off = UINT64_MAX;     // word offset of its per-spin term rows (lane pass kernel), or none
+    int32_t fml_d4 = 0, fml_t4 = 0;    // groups of four coupling / hyper-coupling words per row
     int32_t bits_ok = 0;               // at most 2048 spins, every |coefficient| <= 15 and per spin
                                        // sum |c| <= 255 (bit-sliced block kernel)
     // last tiling decision and the settings it was made for (rule, knobs)
@@ -162,6 +166,16 @@ struct sg_ctx {
     int32_t last_fm_waves = 0;         // what the last FM call used
     std::array<int64_t, 5> fm_key{{-1, -1, -1, -1, -1}};  // setting of the cached FM workgroup size
     int32_t fm_waves_cached = 0;
+    int32_t fml_ws = 1;                // workspace holds the per-spin term lists of the lane pass kernel
+    int32_t fm_lanes = 1;              // FM runs one replica per lane where the instance allows
+    int32_t fm_lane_restarts = 0;      // restarts per lane-kernel item (0 = chosen to fill the device)
+    int32_t fm_lane_waves = 0;         // wavefronts per lane-kernel workgroup sharing an item (0 = 1)
+    int32_t last_fm_lanes = 0;         // replicas of the last FM call run one per lane
+    int32_t last_fm_lane_nr = 0;       // restarts per item of that call
+    std::vector<uint32_t> h_fml;       // term lists of every qualifying instance
+    uint64_t off_fml = 0, off_fmitems = 0;
+    int64_t fm_item_cap = 0;
+    std::vector<sg::BlockItem> h_fmitems;
     int32_t defer_energy = 1;          // a drawn start whose run computes final energies gets its energy later
     int32_t last_key32 = 0;            // the last FM call used 32-bit keys
     int32_t queue_wave_max_n = 512;    // queue items up to this size run one per wavefront (fastest measured)
@@ -950,6 +964,90 @@ bool lane_start_candidate(const HostInst& q)
     return !q.dense && !q.wide && q.n <= kLaneStartMaxN && q.R >= kLaneStartMinR;
 }
 
+// The pass kernel with one replica per lane takes instances of at most 1024
+// spins (tags of the move order fit a byte) whose every half-gain -s_i f_i
+// fits a byte, with at most 16 couplings and 6 hyper-couplings on a spin
+// (its rows of fixed width).
+void fml_counts(const HostInst& q, int32_t& dmax, int32_t& tmax)
+{
+    dmax = tmax = 0;
+    for (const sg::Slice& S : q.slices)
+        for (uint32_t l = 0; l < S.rows; ++l) {
+            int32_t c = 0, t = 0;
+            for (uint32_t k = 0; k < S.ew; ++k) c += (q.nbr[S.ebase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
+            for (uint32_t k = 0; k < S.tw; ++k) t += (q.ta[S.tbase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
+            dmax = std::max(dmax, c);
+            tmax = std::max(tmax, t);
+        }
+}
+
+bool fml_candidate(const HostInst& q)
+{
+    if (q.dense || q.wide || q.n > kFmlMaxN || q.max_w > kFmlMaxW) return false;
+    int32_t d, t;
+    fml_counts(q, d, t);
+    return d <= 16 && t <= 6;
+}
+
+// byte offset of spin j in the lane-interleaved gain words of the lane kernel
+inline uint32_t fml_fb(uint32_t j) { return (j >> 2) << 8 | (j & 3u); }
+
+// Appends the term rows of one instance in external order (layout in
+// sg::InstTab::fml): per spin e a word h_e & 255 | couplings << 8 |
+// hyper-couplings << 16, then per spin d4 groups of four coupling words
+// fb(j) << 16 | (j & 31) << 11 | J & 255, then per spin t4 groups of four
+// words holding two hyper-couplings as the pair (fb(a) << 16 | fb(b),
+// (a & 31) << 24 | (b & 31) << 16 | K & 255); partners as external indices.
+// Unused entries name spin e itself with coefficient 0 (the sliced layout's
+// zero padding is left out).
+void build_fml(const HostInst& q, std::vector<uint32_t>& out, int32_t& d4, int32_t& t4)
+{
+    const int32_t n = q.n;
+    int32_t dmax, tmax;
+    fml_counts(q, dmax, tmax);
+    d4 = (dmax + 3) / 4;
+    d4 = d4 <= 1 ? 1 : (d4 == 2 ? 2 : 4);  // the lane kernel is built for widths 1, 2 and 4
+    t4 = (tmax + 1) / 2;
+    const size_t hn = ((size_t)n + 3) & ~(size_t)3;
+    const size_t base = out.size();
+    out.resize(base + hn + (size_t)n * 4 * (size_t)(d4 + t4), 0u);
+    uint32_t* w = out.data() + base;
+    uint32_t* cw = w + hn;
+    uint32_t* tw = cw + (size_t)n * 4 * (size_t)d4;
+    for (const sg::Slice& S : q.slices)
+        for (uint32_t l = 0; l < S.rows; ++l) {
+            const uint32_t i = S.row0 + l, e = q.ext_of[i];
+            const uint32_t self_c = fml_fb(e) << 16 | (e & 31u) << 11;
+            uint32_t* cr = cw + (size_t)e * 4 * (size_t)d4;
+            uint32_t* ce = cr + 4 * (size_t)d4;
+            uint32_t nc = 0, nt = 0;
+            for (uint32_t k = 0; k < S.ew; ++k) {
+                const uint32_t x = q.nbr[S.ebase + (size_t)k * sg::kSlice + l];
+                if (!(x & 0xFFu)) continue;
+                const uint32_t j = q.ext_of[x >> 8];
+                *cr++ = fml_fb(j) << 16 | (j & 31u) << 11 | (x & 0xFFu);
+                ++nc;
+            }
+            while (cr < ce) *cr++ = self_c;
+            uint32_t* tr = tw + (size_t)e * 4 * (size_t)t4;
+            uint32_t* te = tr + 4 * (size_t)t4;
+            for (uint32_t k = 0; k < S.tw; ++k) {
+                const size_t at = S.tbase + (size_t)k * sg::kSlice + l;
+                const uint32_t x = q.ta[at];
+                if (!(x & 0xFFu)) continue;
+                const uint32_t a = q.ext_of[x >> 8], b = q.ext_of[q.tb[at]];
+                *tr++ = fml_fb(a) << 16 | fml_fb(b);
+                *tr++ = (a & 31u) << 24 | (b & 31u) << 16 | (x & 0xFFu);
+                ++nt;
+            }
+            while (tr < te) {
+                *tr++ = fml_fb(e) << 16 | fml_fb(e);
+                *tr++ = (e & 31u) << 24 | (e & 31u) << 16;
+            }
+            w[e] = ((uint32_t)(int32_t)q.h[i] & 0xFFu) | nc << 8 | nt << 16;
+        }
+}
+
 void layout(sg_ctx* H)
 {
     // the lane path keeps one wavefront per 64 replicas busy with a whole
@@ -1020,6 +1118,17 @@ void layout(sg_ctx* H)
         H->n_block_item_cap += (q.R + 63) / 64;
         H->ctab_len += q.C + 1;
     }
+    H->h_fml.clear();
+    H->fm_item_cap = 0;
+    for (HostInst& q : H->insts) {
+        q.fml_off = UINT64_MAX;
+        if (!H->fml_ws || !fml_candidate(q)) continue;
+        q.fml_off = H->h_fml.size();
+        build_fml(q, H->h_fml, q.fml_d4, q.fml_t4);
+        H->fm_item_cap += (q.R + 63) / 64;
+    }
+    H->off_fml = take(H->h_fml.size() * 4);
+    H->off_fmitems = take((uint64_t)H->fm_item_cap * sizeof(sg::BlockItem));
     H->off_tab = take(ni * sizeof(sg::InstTab));
     H->off_ctab = take((uint64_t)H->ctab_len * 4);
     H->off_bitems = take((uint64_t)H->n_block_item_cap * sizeof(sg::BlockItem));
@@ -1832,31 +1941,91 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
 {
     if (p->schedule != SG_SCHED_AUTO && p->schedule != SG_SCHED_FM)
         return fail(SG_EINVAL, "rule SG_RULE_FM runs under SG_SCHED_AUTO or SG_SCHED_FM only");
-    int nmax = 1;
+    int nmax = 1, lnmax = 1;
     bool tri = false, key32 = true;
+    int64_t lane_reps = 0, wave_reps = 0;
+    auto on_lanes = [&](const HostInst& q) { return H->fm_lanes && q.fml_off != UINT64_MAX; };
     for (const HostInst& q : H->insts) {
         if (q.n > kFmMaxN) return fail(SG_EINVAL, "rule SG_RULE_FM: instance of %d spins (at most %d)", q.n, kFmMaxN);
         if (q.wide)
             return fail(SG_EINVAL, "rule SG_RULE_FM: instance %zu needs the wide form (a coefficient beyond int8, "
                                    "a spin's |h|+sum|J|+sum|K| >= 2^23, or more than 255 triples on a spin)",
                         (size_t)(&q - H->insts.data()));
+        if (on_lanes(q)) {
+            lnmax = std::max(lnmax, q.n);
+            lane_reps += q.R;
+            continue;
+        }
+        wave_reps += q.R;
         nmax = std::max(nmax, q.n);
         tri = tri || q.t > 0;
         // 32-bit move keys: every gain |2 s f| < 2^19 and external indices below 4096
         key32 = key32 && 2 * q.max_w < (int64_t)1 << 19 && q.n <= 4096 && H->fm_key32;
     }
-    H->last_key32 = key32 ? 1 : 0;
+    H->last_key32 = wave_reps && key32 ? 1 : 0;
+    H->last_fm_lanes = (int32_t)std::min<int64_t>(lane_reps, INT32_MAX);
     hipStream_t st = H->stream;
     H->h_qitems.clear();
     for (size_t k = 0; k < H->insts.size(); ++k)
-        for (int32_t r = 0; r < H->insts[k].R; ++r) H->h_qitems.push_back(sg::QueueItem{(int32_t)k, r});
+        if (!on_lanes(H->insts[k]))
+            for (int32_t r = 0; r < H->insts[k].R; ++r) H->h_qitems.push_back(sg::QueueItem{(int32_t)k, r});
     std::stable_sort(H->h_qitems.begin(), H->h_qitems.end(), [&](const sg::QueueItem& a, const sg::QueueItem& b) {
         return H->insts[a.inst].n > H->insts[b.inst].n;
     });
-    // the wavefronts' slices, plus room to stage one instance's structure
+    // lane kernel items: restarts [r0, r0 + nr) of one instance per wavefront,
+    // nr the largest multiple of 64 that still gives every resident wavefront
+    // an item (a wavefront refills its lanes from its own item as replicas
+    // finish, so longer items lose less to the replicas' uneven pass counts)
+    H->h_fmitems.clear();
+    int32_t nr = 64, lw = 1;
+    if (lane_reps) {
+        // a workgroup of W wavefronts shares its item: restarts in multiples of 64 W
+        lw = std::max(1, sg::fml_waves_per_block(lnmax, H->fm_lane_waves));
+        const int32_t unit = 64 * lw;
+        int32_t d4 = 1, t4 = 0;
+        for (const HostInst& q : H->insts)
+            if (on_lanes(q)) {
+                d4 = q.fml_d4;
+                t4 = q.fml_t4;
+                break;
+            }
+        const int64_t resident = std::max(1, sg::fml_resident_blocks(lnmax, lw, d4, t4));
+        int32_t rmax = unit;
+        for (const HostInst& q : H->insts)
+            if (on_lanes(q)) rmax = std::max(rmax, (q.R + unit - 1) / unit * unit);
+        if (H->fm_lane_restarts) {
+            nr = H->fm_lane_restarts;
+        } else {
+            for (int32_t c = rmax; c >= unit; c -= unit) {
+                int64_t items = 0;
+                for (const HostInst& q : H->insts)
+                    if (on_lanes(q)) items += (q.R + c - 1) / c;
+                if (items >= resident || c == unit) {
+                    nr = c;
+                    break;
+                }
+            }
+        }
+        for (size_t k = 0; k < H->insts.size(); ++k) {
+            const HostInst& q = H->insts[k];
+            if (!on_lanes(q)) continue;
+            for (int32_t r0 = 0; r0 < q.R; r0 += nr)
+                H->h_fmitems.push_back(sg::BlockItem{(int32_t)k, r0, std::min(nr, q.R - r0), 0});
+        }
+        // one launch per pair of row widths, the largest items first in each
+        auto combo = [&](const sg::BlockItem& a) { return H->insts[a.inst].fml_d4 * 10 + H->insts[a.inst].fml_t4; };
+        std::stable_sort(H->h_fmitems.begin(), H->h_fmitems.end(), [&](const sg::BlockItem& a, const sg::BlockItem& b) {
+            if (combo(a) != combo(b)) return combo(a) < combo(b);
+            return (int64_t)H->insts[a.inst].n * a.nr > (int64_t)H->insts[b.inst].n * b.nr;
+        });
+    }
+    H->last_fm_lane_nr = lane_reps ? nr : 0;
+    // the wavefront-per-replica kernel: the wavefronts' slices, plus room to
+    // stage one instance's structure
     size_t stage = 0;
     for (const HostInst& q : H->insts)
-        stage = std::max(stage, q.slices.size() * sizeof(sg::Slice) + q.nbr.size() * 4 + (tri ? q.ta.size() * 8 : 0));
+        if (!on_lanes(q))
+            stage = std::max(stage, q.slices.size() * sizeof(sg::Slice) + q.nbr.size() * 4 + (tri ? q.ta.size() * 8 : 0));
     stage = (stage + 15) / 16 * 16;
     // wavefronts per workgroup: the most resident wavefronts per compute unit
     // (several smaller workgroups can share one), staging the instance where
@@ -1867,7 +2036,9 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     if (sg::fm_lds_bytes(nmax, 1) + stage > kLdsBudget) stage = 0;  // too large to stage: read from memory
     const std::array<int64_t, 5> fkey{{nmax, (int64_t)stage, tri ? 1 : 0, key32 ? 1 : 0, H->fm_waves}};
     int waves = 0;
-    if (H->fm_key == fkey) {
+    if (!wave_reps) {
+        waves = 1;
+    } else if (H->fm_key == fkey) {
         waves = H->fm_waves_cached;
     } else {
         int resident = -1;
@@ -1887,17 +2058,38 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
         }
     }
     if (waves == 0) return fail(SG_EINVAL, "rule SG_RULE_FM: no workgroup size fits LDS (fm_waves %d)", H->fm_waves);
-    H->last_fm_waves = waves;
+    H->last_fm_waves = wave_reps ? waves : 0;
     sg::QueueItem* dit = H->at<sg::QueueItem>(H->off_qitems);
     uint32_t* err = H->at<uint32_t>(H->off_err);
     SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
     SG_HIP(sg::launch_fill_u32(err, 1, 0u, st), "fill kernel");
-    SG_HIP(hipMemcpyAsync(dit, H->h_qitems.data(), H->h_qitems.size() * sizeof(sg::QueueItem), hipMemcpyHostToDevice,
-                          st),
-           "upload items");
+    if (!H->h_qitems.empty())
+        SG_HIP(hipMemcpyAsync(dit, H->h_qitems.data(), H->h_qitems.size() * sizeof(sg::QueueItem),
+                              hipMemcpyHostToDevice, st),
+               "upload items");
+    if (!H->h_fmitems.empty())
+        SG_HIP(hipMemcpyAsync(H->dev + H->off_fmitems, H->h_fmitems.data(), H->h_fmitems.size() * sizeof(sg::BlockItem),
+                              hipMemcpyHostToDevice, st),
+               "upload lane items");
     SG_HIP(hipEventRecord(H->ev0, st), "event record");
     SG_HIP(hipEventRecord(H->evh0, st), "event record");
+    int lane_launches = 0;
     if (p->max_sweeps > 0)
+        for (size_t a = 0; a < H->h_fmitems.size();) {
+            const HostInst& q0 = H->insts[H->h_fmitems[a].inst];
+            size_t b = a;
+            int cn = 1;
+            while (b < H->h_fmitems.size() && H->insts[H->h_fmitems[b].inst].fml_d4 == q0.fml_d4 &&
+                   H->insts[H->h_fmitems[b].inst].fml_t4 == q0.fml_t4)
+                cn = std::max(cn, H->insts[H->h_fmitems[b++].inst].n);
+            SG_HIP(sg::launch_fm_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_fmitems) + a,
+                                       (int)(b - a), cn, lw, q0.fml_d4, q0.fml_t4, H->reps(),
+                                       H->at<sg::CallStats>(H->off_stats), err, p->max_sweeps, p->until_converged, st),
+                   "lane pass kernel");
+            ++lane_launches;
+            a = b;
+        }
+    if (p->max_sweeps > 0 && !H->h_qitems.empty())
         SG_HIP(sg::launch_fm(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab), dit,
                              (int)H->h_qitems.size(), nmax, waves, (int)stage, tri, key32, H->reps(),
                              H->at<sg::CallStats>(H->off_stats),
@@ -1905,7 +2097,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
                "pass kernel");
     SG_HIP(hipEventRecord(H->evh1, st), "event record");
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
-    H->hot_launches = p->max_sweeps > 0 ? 1 : 0;
+    H->hot_launches = p->max_sweeps > 0 ? lane_launches + (int)!H->h_qitems.empty() : 0;
     sg::CallStats cs;
     uint32_t herr = 0;
     SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
@@ -2213,11 +2405,17 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             T.n_ee = q.n_ee;
             T.n_et = q.n_et;
             T.eterm_pad = 0;
+            T.fml = q.fml_off == UINT64_MAX ? nullptr : H->at<uint32_t>(H->off_fml) + q.fml_off;
+            T.fml_d4 = q.fml_d4;
+            T.fml_t4 = q.fml_t4;
             for (int32_t c = 0; c <= q.C; ++c) ctab.push_back(q.colour_slice[c]);
         }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_tab, tab.data(), tab.size() * sizeof(sg::InstTab), hipMemcpyHostToDevice,
                               st),
                "upload instance table");
+        if (!H->h_fml.empty())
+            SG_HIP(hipMemcpyAsync(H->dev + H->off_fml, H->h_fml.data(), H->h_fml.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload term lists");
         SG_HIP(hipMemcpyAsync(H->dev + H->off_ctab, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st),
                "upload colour table");
         std::vector<int32_t> rep_inst((size_t)H->total_reps);
@@ -2584,6 +2782,23 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
     } else if (k == "fm_key32") {
         if (value != 0 && value != 1) return fail(SG_EINVAL, "fm_key32 must be 0 or 1");
         H->fm_key32 = (int32_t)value;
+    } else if (k == "fm_lanes") {
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "fm_lanes must be 0 or 1");
+        if (!H->bound) {
+            // before sg_bind the term lists follow the knob (0 leaves them out of the workspace)
+            H->fml_ws = (int32_t)value;
+            layout(H);
+        } else if (value && !H->fml_ws) {
+            return fail(SG_EINVAL, "fm_lanes: the workspace was laid out without the term lists (set it before sg_bind)");
+        }
+        H->fm_lanes = (int32_t)value;
+    } else if (k == "fm_lane_waves") {
+        if (value < 0 || value > 4) return fail(SG_EINVAL, "fm_lane_waves must be in [0,4]");
+        H->fm_lane_waves = (int32_t)value;
+    } else if (k == "fm_lane_restarts") {
+        if (value < 0 || value > (1 << 20) || value % 64)
+            return fail(SG_EINVAL, "fm_lane_restarts must be 0 or a multiple of 64 up to 2^20");
+        H->fm_lane_restarts = (int32_t)value;
     } else if (k == "defer_energy") {
         if (value != 0 && value != 1) return fail(SG_EINVAL, "defer_energy must be 0 or 1");
         H->defer_energy = (int32_t)value;
@@ -2654,6 +2869,11 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "defer_energy") *value = H->defer_energy;
     else if (k == "energy_pending") *value = H->e_pending ? 1 : 0;
     else if (k == "fm_key32") *value = H->fm_key32;
+    else if (k == "fm_lanes") *value = H->fm_lanes;
+    else if (k == "fm_lane_restarts") *value = H->fm_lane_restarts;
+    else if (k == "fm_lane_waves") *value = H->fm_lane_waves;
+    else if (k == "last_fm_lanes") *value = H->last_fm_lanes;
+    else if (k == "last_fm_lane_nr") *value = H->last_fm_lane_nr;
     else if (k == "last_key32") *value = H->last_key32;
     else if (k == "bits_groups") *value = H->bits_groups;
     else if (k == "block_min_restarts") *value = H->block_min_restarts;

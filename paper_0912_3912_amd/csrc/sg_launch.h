@@ -72,6 +72,20 @@ int fm_max_blocks_per_cu(int waves, size_t lds, bool tri, bool key32);
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
                      int stage_cap, bool tri, bool key32, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
                      int until_conv, hipStream_t st);
+// The pass-based search with one replica per lane (instances of at most 1024
+// spins whose per-spin sum of |coefficients| is at most 127, with the
+// per-spin term rows InstTab::fml): workgroup k runs restarts [r0, r0 + nr)
+// of item k's instance on its wavefronts, handing them out through the
+// item's pad word, which must be zero at launch, on W wavefronts per
+// workgroup.  fml_waves_per_block: the wavefronts of one workgroup for
+// instances of up to nmax spins, want (0: one) bounded by four and the LDS
+// (0: too large); fml_resident_blocks: such workgroups resident on the device.
+// Every instance of one launch has rows of the widths d4 (1, 2 or 4) and t4
+// (0..3) (InstTab::fml_d4, fml_t4).
+int fml_waves_per_block(int nmax, int want);
+int fml_resident_blocks(int nmax, int W, int d4, int t4);
+hipError_t launch_fm_lanes(const InstTab* tab, BlockItem* items, int nitems, int nmax, int W, int d4, int t4,
+                           RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv, hipStream_t st);
 // Dense hyper-Ising instances: one lane per replica; items are (instance,
 // first restart, count <= 64).  rule 0/1: colour sweeps; 2: pass-based search.
 hipError_t launch_dense_init(const DenseTab* tabs, const BlockItem* items, int nitems, RepState* rs, uint64_t seed,

@@ -25,13 +25,15 @@ def _oracle(insts, seed, max_passes, uc, runs=None, threads=0):
     return out
 
 
-def _check(insts, seed, max_passes=1000, uc=True, runs=None, key32=1, waves=0):
+def _check(insts, seed, max_passes=1000, uc=True, runs=None, key32=1, waves=0, lanes=1, lane_restarts=0):
     import paper_0912_3912_amd as sg
     log(f"fm case: {[i.name for i in insts][:4]} seed={seed} passes={runs or max_passes} uc={uc} key32={key32} "
-        f"waves={waves}")
+        f"waves={waves} lanes={lanes} lane_restarts={lane_restarts}")
     h = sg.load_instance(list(insts))
     h.tune("fm_key32", key32)
     h.tune("fm_waves", waves)
+    h.tune("fm_lanes", lanes)
+    h.tune("fm_lane_restarts", lane_restarts)
     h.bind()
     h.init_spins(seed)
     stats = [h.run_sweeps(seed=seed, rule=FM, max_sweeps=mp, until_converged=uc) for mp in (runs or [max_passes])]
@@ -44,19 +46,71 @@ def _check(insts, seed, max_passes=1000, uc=True, runs=None, key32=1, waves=0):
     return h
 
 
+@pytest.mark.parametrize("lanes", [1, 0])
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 129, 700])
-def test_ragged_random_with_triples(gpu, n):
+def test_ragged_random_with_triples(gpu, n, lanes):
     inst = gen.random_small(n, seed=n, p_edge=min(1.0, 8.0 / max(n, 1)), n_triples=n // 2, j_range=(-15, 15),
                             h_range=(-7, 7), k_range=(-7, 7)).replace(restarts=4, instance_id=n)
-    _check([inst], seed=n + 3)
+    _check([inst], seed=n + 3, lanes=lanes)
+
+
+def _small_coef(n, restarts, seed=None):
+    """Random instance whose per-spin sum of |coefficients| stays within one
+    byte (the lane kernel's range)."""
+    seed = n if seed is None else seed
+    return gen.random_small(n, seed=seed, p_edge=min(1.0, 6.0 / max(n, 1)), n_triples=n // 3, j_range=(-5, 5),
+                            h_range=(-3, 3), k_range=(-3, 3)).replace(restarts=restarts, instance_id=n + 1000,
+                                                                       name=f"lo{n}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 33, 64, 129, 256, 257, 511, 513, 700, 1000, 1024])
+def test_lane_kernel_ragged(gpu, n):
+    """One replica per lane: sizes around the 32-spin groups, the 4-spin gain
+    words and the move-tag widths (n <= 256, 512, 1024), 70 restarts (a
+    second wavefront item, partly filled)."""
+    inst = _small_coef(n, 70)
+    h = _check([inst], seed=n + 5)
+    assert h.query("last_fm_lanes") == 70 and h.query("last_fm_waves") == 0
+
+
+@pytest.mark.parametrize("nr", [64, 128, 256])
+def test_lane_kernel_refill(gpu, nr):
+    """A wavefront refills its lanes from its item's restarts as replicas
+    finish: items of 64, 128 and 256 restarts give the oracle's results."""
+    insts = [gen.chimera(8, 8, seed=s, instance_id=s, restarts=200) for s in range(2)] + [_small_coef(300, 90)]
+    h = _check(insts, seed=4, lane_restarts=nr)
+    assert h.query("last_fm_lane_nr") == nr and h.query("last_fm_lanes") == 490
+
+
+def test_lane_kernel_lattice_regular_resume(gpu):
+    insts = [gen.lattice((20, 20), seed=2, restarts=65), gen.lattice((32, 32), seed=3, restarts=9),
+             gen.random_regular3(1000, seed=4, instance_id=9).replace(restarts=5)]
+    _check(insts, seed=5, uc=True, runs=[1, 2, 0, 1000])
+    h = _check(insts, seed=6, max_passes=3, uc=False)
+    assert h.query("last_fm_lanes") == 79
+
+
+def test_lane_and_wave_kernels_in_one_call(gpu):
+    """Instances within the lane kernel's range next to ones beyond it (more
+    than 1024 spins, or a per-spin sum of |coefficients| above 127) in one
+    call: both kernels run, every replica matches the oracle."""
+    big = gen.erdos_renyi_triples(3000, seed=8)
+    wide = gen.random_small(200, seed=3, p_edge=0.2, n_triples=0, j_range=(-15, 15), instance_id=44).replace(
+        restarts=3)
+    insts = [gen.chimera(6, 6, seed=1, instance_id=1, restarts=80), big, wide, _small_coef(100, 3)]
+    h = _check(insts, seed=9)
+    assert h.query("last_fm_lanes") == 83 and h.query("last_fm_waves") > 0
 
 
 @pytest.mark.parametrize("key32", [1, 0])
 def test_chimera_with_triples(gpu, key32):
     """Moves chosen on 32-bit keys (the default where the gains allow) and on
-    64-bit keys give the same passes."""
-    h = _check([gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)], seed=11, key32=key32)
+    64-bit keys give the same passes (one replica per wavefront), and so does
+    one replica per lane."""
+    h = _check([gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)], seed=11, key32=key32, lanes=0)
     assert h.query("last_key32") == key32
+    h = _check([gen.chimera(8, 8, seed=3, instance_id=17, restarts=6)], seed=11, key32=key32)
+    assert h.query("last_fm_lanes") == 6
 
 
 def test_large_coefficients_use_wide_keys(gpu):
@@ -81,12 +135,12 @@ def test_fixed_pass_budget_and_resume(gpu):
 
 @pytest.mark.parametrize("waves", [0, 1, 3, 8, 16])
 def test_mixed_batch(gpu, waves):
-    """Mixed sizes in one call, for several workgroup sizes (0: chosen by
-    occupancy): blocks that stage one instance and blocks that read several
-    from memory."""
+    """Mixed sizes in one call, one replica per wavefront, for several
+    workgroup sizes (0: chosen by occupancy): blocks that stage one instance
+    and blocks that read several from memory."""
     insts = [gen.chimera(6, 6, seed=s, instance_id=s, restarts=3) for s in range(3)]
     insts += [gen.random_small(40, seed=1, instance_id=77).replace(restarts=2), gen.erdos_renyi_triples(3000, seed=8)]
-    _check(insts, seed=9, waves=waves)
+    _check(insts, seed=9, waves=waves, lanes=0)
 
 
 def test_errors(gpu):
@@ -114,6 +168,7 @@ def test_chimera_batch_full_size(gpu):
     h.init_spins(7)
     st = h.run_sweeps(seed=7, rule=FM, max_sweeps=1000, until_converged=True)
     log(f"fm chimera4096x256: {st['kernel_ms']:.1f} ms, passes max {st['sweeps_max']}, attempts {st['attempts']}")
+    assert h.query("last_fm_lanes") == 4096 * 256
     E = h.energy()
     assert np.array_equal(E, h.energy(recompute=True))
     sw, fl, cv = h.counters()
