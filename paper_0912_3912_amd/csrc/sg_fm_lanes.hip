@@ -53,13 +53,13 @@ constexpr int kFmlMaxN = 1024;
 typedef unsigned short fml_u16x2 __attribute__((ext_vector_type(2)));
 // device-memory views (the pointers come from the instance table, so the
 // compiler would otherwise address them as generic memory)
-typedef uint32_t fml_v4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const fml_v4 fml_g4;
+typedef uint32_t fml_v2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const fml_v2 fml_g2;
 typedef __attribute__((address_space(1))) const uint32_t fml_g32;
 typedef __attribute__((address_space(1))) int8_t fml_gi8;
 typedef __attribute__((address_space(1))) uint32_t fml_gu32;
 // read-only views for loads at wavefront-uniform addresses (scalar loads)
-typedef __attribute__((address_space(4))) const fml_v4 fml_k4;
+typedef __attribute__((address_space(4))) const fml_v2 fml_k2;
 typedef __attribute__((address_space(4))) const uint32_t fml_k32;
 
 // LDS of one wavefront: gain words for whole groups (8 per group), spin
@@ -107,14 +107,15 @@ __device__ __forceinline__ uint32_t fml_group_key(const uint32_t* gw, int g, int
     return (k16 >> 8) << 16 | (0xFFFFu - fb);
 }
 
-// Row layout (InstTab::fml): n field words (padded to a multiple of four),
-// then d4 groups of four coupling words per spin, each fb(j) << 16 |
-// (j & 31) << 11 | J & 255, then t4 groups of four words per spin holding two
-// hyper-couplings each as the pair (fb(a) << 16 | fb(b), (a & 31) << 24 |
-// (b & 31) << 16 | K & 255); unused entries are zero (coefficient 0).
-// D4 (1, 2 or 4) and T4 (0..3) are the row widths of every instance of a
-// launch: fixed at compile time, so that a row's loads are issued together.
-template <int D4, int T4>
+// Row layout (InstTab::fml): per spin a word h & 255 | couplings << 8 |
+// hyper-couplings << 16 (padded to an even count), then DC coupling words
+// per spin, each fb(j) << 16 | (j & 31) << 11 | J & 255, then TT pairs of
+// words per spin, one hyper-coupling each: (fb(a) << 16 | fb(b), (a & 31) <<
+// 24 | (b & 31) << 16 | K & 255).  Unused entries name the spin itself with
+// coefficient 0.  DC (4, 6, 8 or 16) and TT (0, 2, 4 or 6) are the row widths
+// of every instance of a launch: fixed at compile time, so that a row's loads
+// are issued together.
+template <int DC, int TT>
 __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ tab, BlockItem* __restrict__ items,
                                                   int wave_words, RepState* __restrict__ rs,
                                                   CallStats* __restrict__ cs, uint32_t* __restrict__ err,
@@ -134,12 +135,14 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
     uint8_t* gl8 = reinterpret_cast<uint8_t*>(gw + lane);  // this lane's gain byte of spin j at gl8[fb(j)]
     uint32_t* sl = sw + lane;                              // this lane's spin word k at sl[k * 64]
     uint32_t* bl = bw + lane;                              // this lane's group key g at bl[g * 64]
-    fml_g4* cw4 = (fml_g4*)(Q.fml + ((n + 3) & ~3));
-    fml_g4* tw4 = cw4 + (size_t)n * D4;
+    constexpr int TTa = TT > 0 ? TT : 1;
+    fml_g32* hg = (fml_g32*)Q.fml;
+    fml_g2* cw2 = (fml_g2*)(Q.fml + ((n + 1) & ~1));
+    fml_g2* tw2 = cw2 + (size_t)n * (DC / 2);
     fml_k32* ext = (fml_k32*)Q.I.ext;
     fml_k32* hk = (fml_k32*)Q.fml;
-    fml_k4* ck4 = (fml_k4*)(Q.fml + ((n + 3) & ~3));
-    fml_k4* tk4 = ck4 + (size_t)n * D4;
+    fml_k2* ck2 = (fml_k2*)(Q.fml + ((n + 1) & ~1));
+    fml_k2* tk2 = ck2 + (size_t)n * (DC / 2);
 
     auto sgn = [&](int j) { return ((sl[(j >> 5) * 64] >> (j & 31)) & 1u) ? -1 : 1; };
 
@@ -215,15 +218,15 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
                     const int e0 = g * 32 + d * 4;
                     // the four spins' rows, every load issued before any is used
                     int hq[4];
-                    fml_v4 cr[4][D4], tr[4][T4 > 0 ? T4 : 1];
+                    fml_v2 cr[4][DC / 2], tr[4][TTa];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int e = e0 + u < n ? e0 + u : n - 1;
                         hq[u] = (int)hk[e];
 #pragma unroll
-                        for (int c = 0; c < D4; ++c) cr[u][c] = ck4[(size_t)e * D4 + c];
+                        for (int c = 0; c < DC / 2; ++c) cr[u][c] = ck2[(size_t)e * (DC / 2) + c];
 #pragma unroll
-                        for (int c = 0; c < T4; ++c) tr[u][c] = tk4[(size_t)e * T4 + c];
+                        for (int c = 0; c < TT; ++c) tr[u][c] = tk2[(size_t)e * TT + c];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -233,22 +236,19 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
                             const int nc = (hq[u] >> 8) & 0xFF, nt = hq[u] >> 16;
                             int f = (int)(int8_t)(hq[u] & 0xFF);
 #pragma unroll
-                            for (int c = 0; c < D4; ++c) {
-                                const uint32_t wq[4] = {cr[u][c].x, cr[u][c].y, cr[u][c].z, cr[u][c].w};
+                            for (int c = 0; c < DC / 2; ++c) {
+                                const uint32_t wq[2] = {cr[u][c].x, cr[u][c].y};
 #pragma unroll
-                                for (int k = 0; k < 4; ++k)
-                                    if (4 * c + k < nc)
+                                for (int k = 0; k < 2; ++k)
+                                    if (2 * c + k < nc)
                                         f += (int)(int8_t)(wq[k] & 0xFFu) * sr(wq[k] >> 27, (wq[k] >> 11) & 31u);
                             }
 #pragma unroll
-                            for (int c = 0; c < T4; ++c) {
-                                const uint32_t wq[4] = {tr[u][c].x, tr[u][c].y, tr[u][c].z, tr[u][c].w};
-#pragma unroll
-                                for (int k = 0; k < 2; ++k)
-                                    if (2 * c + k < nt)
-                                        f += (int)(int8_t)(wq[2 * k + 1] & 0xFFu) *
-                                             sr(wq[2 * k] >> 27, (wq[2 * k + 1] >> 24) & 31u) *
-                                             sr((wq[2 * k] & 0xFFFFu) >> 11, (wq[2 * k + 1] >> 16) & 31u);
+                            for (int c = 0; c < TT; ++c) {
+                                const uint32_t w0 = tr[u][c].x, w1 = tr[u][c].y;
+                                if (c < nt)
+                                    f += (int)(int8_t)(w1 & 0xFFu) * sr(w0 >> 27, (w1 >> 24) & 31u) *
+                                         sr((w0 & 0xFFFFu) >> 11, (w1 >> 16) & 31u);
                             }
                             const uint32_t vb = (uint32_t)(128 - sr((uint32_t)e >> 5, (uint32_t)e & 31u) * f);
                             word |= vb << (8 * u);
@@ -262,20 +262,20 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
             }
         }
 
-        // the n moves of the pass
+        // the n moves of the pass; top is the largest group key
         long long E = Estar, Elow = Estar;
         int blen = 0;
         uint64_t ring = 0, saved = 0;
+        uint32_t top = 0;
+        for (int g0 = 0; g0 < Gp; g0 += 8) {
+            uint32_t b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b[u] = bl[(g0 + u) * 64];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) top = b[u] > top ? b[u] : top;
+        }
         for (int step = 0; step < n; ++step) {
             if (!act || bad) continue;
-            uint32_t top = 0;
-            for (int g0 = 0; g0 < Gp; g0 += 8) {
-                uint32_t b[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) b[u] = bl[(g0 + u) * 64];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) top = b[u] > top ? b[u] : top;
-            }
             const int vb = (int)(top >> 16);
             if (vb == 0) {  // no unlocked spin left before n moves: internal error, stop this replica
                 bad = true;
@@ -284,13 +284,14 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
             const uint32_t fe = 0xFFFFu - (top & 0xFFFFu);
             const int e = fml_spin_of(fe);
             // the spin's rows: loads issued before anything waits on them
-            fml_g4* crow = cw4 + (size_t)e * D4;
-            fml_g4* trow = tw4 + (size_t)e * T4;
-            fml_v4 cq[D4], tq[T4 > 0 ? T4 : 1];
+            fml_g2* crow = cw2 + (size_t)e * (DC / 2);
+            fml_g2* trow = tw2 + (size_t)e * TT;
+            fml_v2 cq[DC / 2], tq[TTa];
+            const uint32_t hw = TT > 0 ? hg[e] : 0u;
 #pragma unroll
-            for (int c = 0; c < D4; ++c) cq[c] = crow[c];
+            for (int c = 0; c < DC / 2; ++c) cq[c] = crow[c];
 #pragma unroll
-            for (int c = 0; c < T4; ++c) tq[c] = trow[c];
+            for (int c = 0; c < TT; ++c) tq[c] = trow[c];
             gs[e] = (int8_t)(step >> sh);  // the move's tag
             gl8[fe] = 0;                   // locked
             uint32_t* sp = &sl[(fe >> 11) * 64];
@@ -305,30 +306,32 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
             // every read of the partners' state issued together (an unused
             // entry names spin e itself, now locked, with coefficient 0: it
             // changes nothing), then every change computed, then written
-            uint32_t gbv[4 * D4], spv[4 * D4], kv[4 * D4];
-            uint32_t sa[2 * (T4 > 0 ? T4 : 1)], sb[2 * (T4 > 0 ? T4 : 1)];
-            uint32_t la[2 * (T4 > 0 ? T4 : 1)], lb[2 * (T4 > 0 ? T4 : 1)];
+            uint32_t gbv[DC], spv[DC], kv[DC];
+            uint32_t sa[TTa], sb[TTa], la[TTa], lb[TTa];
 #pragma unroll
-            for (int c = 0; c < D4; ++c) {
-                const uint32_t wq[4] = {cq[c].x, cq[c].y, cq[c].z, cq[c].w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t fb = wq[k] >> 16;
-                    gbv[4 * c + k] = gl8[fb];
-                    spv[4 * c + k] = sl[(fb >> 11) * 64];
-                    kv[4 * c + k] = bl[(fb >> 11) * 64];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < T4; ++c) {
-                const uint32_t wq[4] = {tq[c].x, tq[c].y, tq[c].z, tq[c].w};
+            for (int c = 0; c < DC / 2; ++c) {
+                const uint32_t wq[2] = {cq[c].x, cq[c].y};
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const uint32_t fa = wq[2 * k] >> 16, fbb = wq[2 * k] & 0xFFFFu;
-                    sa[2 * c + k] = sl[(fa >> 11) * 64];
-                    sb[2 * c + k] = sl[(fbb >> 11) * 64];
-                    la[2 * c + k] = gl8[fa];
-                    lb[2 * c + k] = gl8[fbb];
+                    const uint32_t fb = wq[k] >> 16;
+                    gbv[2 * c + k] = gl8[fb];
+                    spv[2 * c + k] = sl[(fb >> 11) * 64];
+                    kv[2 * c + k] = bl[(fb >> 11) * 64];
+                }
+            }
+            // hyper-coupling slots that some lane uses (the rest are skipped)
+            int tmax = 0;
+#pragma unroll
+            for (int c = 0; c < TT; ++c)
+                if (__ballot((int)(hw >> 16) > c)) tmax = c + 1;
+#pragma unroll
+            for (int c = 0; c < TT; ++c) {
+                if (c < tmax) {
+                    const uint32_t fa = tq[c].x >> 16, fbb = tq[c].x & 0xFFFFu;
+                    sa[c] = sl[(fa >> 11) * 64];
+                    sb[c] = sl[(fbb >> 11) * 64];
+                    la[c] = gl8[fa];
+                    lb[c] = gl8[fbb];
                 }
             }
             const int s_old = ((sword >> (e & 31)) & 1u) ? -1 : 1;
@@ -339,16 +342,16 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
             // lowered one that was the group's largest before this move asks
             // for a rescan
 #pragma unroll
-            for (int c = 0; c < D4; ++c) {
-                const uint32_t wq[4] = {cq[c].x, cq[c].y, cq[c].z, cq[c].w};
+            for (int c = 0; c < DC / 2; ++c) {
+                const uint32_t wq[2] = {cq[c].x, cq[c].y};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t w = wq[k], fb = w >> 16, b = gbv[4 * c + k];
+                for (int k = 0; k < 2; ++k) {
+                    const uint32_t w = wq[k], fb = w >> 16, b = gbv[2 * c + k];
                     const int dj = (int)(int8_t)(w & 0xFFu) * m2;
-                    const int dv = ((spv[4 * c + k] >> ((w >> 11) & 31u)) & 1u) ? -dj : dj;
+                    const int dv = ((spv[2 * c + k] >> ((w >> 11) & 31u)) & 1u) ? -dj : dj;
                     const uint32_t nb = b ? (uint32_t)((int)b + dv) : 0u;  // a locked partner keeps 0
                     const uint32_t lo = 0xFFFFu - fb;
-                    dirty |= (nb < b && kv[4 * c + k] == (b << 16 | lo)) ? 1u << (fb >> 11) : 0u;
+                    dirty |= (nb < b && kv[2 * c + k] == (b << 16 | lo)) ? 1u << (fb >> 11) : 0u;
                     gl8[fb] = (uint8_t)nb;
                     atomicMax(&bl[(fb >> 11) * 64], nb << 16 | lo);
                 }
@@ -359,21 +362,31 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
             // the whole word carry nothing into a neighbouring byte at the
             // end); their groups are rescanned
 #pragma unroll
-            for (int c = 0; c < T4; ++c) {
-                const uint32_t wq[4] = {tq[c].x, tq[c].y, tq[c].z, tq[c].w};
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const uint32_t w0 = wq[2 * k], w1 = wq[2 * k + 1];
+            for (int c = 0; c < TT; ++c) {
+                if (c < tmax) {
+                    const uint32_t w0 = tq[c].x, w1 = tq[c].y;
                     const uint32_t fa = w0 >> 16, fbb = w0 & 0xFFFFu;
-                    const bool na = (sa[2 * c + k] >> ((w1 >> 24) & 31u)) & 1u;
-                    const bool nbn = (sb[2 * c + k] >> ((w1 >> 16) & 31u)) & 1u;
+                    const bool na = (sa[c] >> ((w1 >> 24) & 31u)) & 1u;
+                    const bool nbn = (sb[c] >> ((w1 >> 16) & 31u)) & 1u;
                     const int dv = (int)(int8_t)(w1 & 0xFFu) * m2 * (na != nbn ? -1 : 1);
                     atomicAdd(reinterpret_cast<uint32_t*>(gl8 + (fa & ~3u)),
-                              la[2 * c + k] ? (uint32_t)dv << (8 * (fa & 3u)) : 0u);
+                              la[c] ? (uint32_t)dv << (8 * (fa & 3u)) : 0u);
                     atomicAdd(reinterpret_cast<uint32_t*>(gl8 + (fbb & ~3u)),
-                              lb[2 * c + k] ? (uint32_t)dv << (8 * (fbb & 3u)) : 0u);
+                              lb[c] ? (uint32_t)dv << (8 * (fbb & 3u)) : 0u);
                     dirty |= 1u << (fa >> 11) | 1u << (fbb >> 11);
                 }
+            }
+            // the next move's key: the touched groups' keys are set aside (zero),
+            // every key is read in the same round trip as the rescan's gain
+            // words, and the rescanned keys join the maximum
+            for (uint32_t z = dirty; z; z &= z - 1u) bl[__builtin_ctz(z) * 64] = 0u;
+            top = 0;
+            for (int g0 = 0; g0 < Gp; g0 += 8) {
+                uint32_t b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) b[u] = bl[(g0 + u) * 64];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) top = b[u] > top ? b[u] : top;
             }
             // rescan the touched groups, two at a time
             while (dirty) {
@@ -385,6 +398,8 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
                 const uint32_t k2 = fml_group_key(gw, g2, lane);
                 bl[g1 * 64] = k1;
                 bl[g2 * 64] = k2;
+                top = k1 > top ? k1 : top;
+                top = k2 > top ? k2 : top;
             }
         }
 
@@ -479,36 +494,40 @@ int fml_waves_per_block(int nmax, int want)
     return k > 4 ? 4 : k;
 }
 
-template <int D4, int T4>
+template <int DC, int TT>
 static const void* fml_kernel()
 {
-    return (const void*)k_fm_lanes<D4, T4>;
+    return (const void*)k_fm_lanes<DC, TT>;
 }
 
-// the instantiation for row widths (d4, t4): d4 in {1, 2, 4}, t4 in 0..3
-static const void* fml_pick(int d4, int t4)
+// the instantiation for row widths (dc, tt): dc in {4, 6, 8, 16}, tt in {0, 2, 4, 6}
+static const void* fml_pick(int dc, int tt)
 {
-    switch (d4 * 10 + t4) {
-    case 10: return fml_kernel<1, 0>();
-    case 11: return fml_kernel<1, 1>();
-    case 12: return fml_kernel<1, 2>();
-    case 13: return fml_kernel<1, 3>();
-    case 20: return fml_kernel<2, 0>();
-    case 21: return fml_kernel<2, 1>();
-    case 22: return fml_kernel<2, 2>();
-    case 23: return fml_kernel<2, 3>();
+    switch (dc * 10 + tt) {
     case 40: return fml_kernel<4, 0>();
-    case 41: return fml_kernel<4, 1>();
     case 42: return fml_kernel<4, 2>();
-    case 43: return fml_kernel<4, 3>();
+    case 44: return fml_kernel<4, 4>();
+    case 46: return fml_kernel<4, 6>();
+    case 60: return fml_kernel<6, 0>();
+    case 62: return fml_kernel<6, 2>();
+    case 64: return fml_kernel<6, 4>();
+    case 66: return fml_kernel<6, 6>();
+    case 80: return fml_kernel<8, 0>();
+    case 82: return fml_kernel<8, 2>();
+    case 84: return fml_kernel<8, 4>();
+    case 86: return fml_kernel<8, 6>();
+    case 160: return fml_kernel<16, 0>();
+    case 162: return fml_kernel<16, 2>();
+    case 164: return fml_kernel<16, 4>();
+    case 166: return fml_kernel<16, 6>();
     default: return nullptr;
     }
 }
 
-int fml_resident_blocks(int nmax, int W, int d4, int t4)
+int fml_resident_blocks(int nmax, int W, int dc, int tt)
 {
     if (W <= 0) return 0;
-    const void* kern = fml_pick(d4, t4);
+    const void* kern = fml_pick(dc, tt);
     if (!kern) return 0;
     const size_t lds = fml_wave_lds_bytes(nmax) * (size_t)W;
     int per_cu = 0, dev = 0, cus = 0;
@@ -522,11 +541,11 @@ int fml_resident_blocks(int nmax, int W, int d4, int t4)
     return per_cu * cus;
 }
 
-hipError_t launch_fm_lanes(const InstTab* tab, BlockItem* items, int nitems, int nmax, int W, int d4, int t4,
+hipError_t launch_fm_lanes(const InstTab* tab, BlockItem* items, int nitems, int nmax, int W, int dc, int tt,
                            RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    const void* kern = fml_pick(d4, t4);
+    const void* kern = fml_pick(dc, tt);
     if (!kern || nmax < 1 || nmax > kFmlMaxN || W < 1 || W > 4 || fml_wave_lds_bytes(nmax) * (size_t)W > 160 * 1024)
         return hipErrorInvalidValue;
     const size_t wave_bytes = fml_wave_lds_bytes(nmax);

@@ -111,7 +111,7 @@ struct HostInst {
     int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
     int64_t max_w = 0;                 // largest sum of |coefficients| over one spin's terms
     uint64_t fml_off = UINT64_MAX;     // word offset of its per-spin term rows (lane pass kernel), or none
-    int32_t fml_d4 = 0, fml_t4 = 0;    // groups of four coupling / hyper-coupling words per row
+    int32_t fml_dc = 0, fml_tt = 0;    // coupling words / hyper-couplings per row
     int32_t bits_ok = 0;               // at most 2048 spins, every |coefficient| <= 15 and per spin
                                        // sum |c| <= 255 (bit-sliced block kernel)
     // last tiling decision and the settings it was made for (rule, knobs)
@@ -992,34 +992,30 @@ bool fml_candidate(const HostInst& q)
 // byte offset of spin j in the lane-interleaved gain words of the lane kernel
 inline uint32_t fml_fb(uint32_t j) { return (j >> 2) << 8 | (j & 3u); }
 
-// Appends the term rows of one instance in external order (layout in
-// sg::InstTab::fml): per spin e a word h_e & 255 | couplings << 8 |
-// hyper-couplings << 16, then per spin d4 groups of four coupling words
-// fb(j) << 16 | (j & 31) << 11 | J & 255, then per spin t4 groups of four
-// words holding two hyper-couplings as the pair (fb(a) << 16 | fb(b),
-// (a & 31) << 24 | (b & 31) << 16 | K & 255); partners as external indices.
-// Unused entries name spin e itself with coefficient 0 (the sliced layout's
-// zero padding is left out).
-void build_fml(const HostInst& q, std::vector<uint32_t>& out, int32_t& d4, int32_t& t4)
+// Appends the term rows of one instance in external order: per spin e a word
+// h_e & 255 | couplings << 8 | hyper-couplings << 16 (padded to an even
+// count), then per spin dc coupling words fb(j) << 16 | (j & 31) << 11 |
+// J & 255, then per spin tt pairs of words, one hyper-coupling each:
+// (fb(a) << 16 | fb(b), (a & 31) << 24 | (b & 31) << 16 | K & 255); partners
+// as external indices.  Unused entries name spin e itself with coefficient 0
+// (the sliced layout's zero padding is left out).  dc (4, 6, 8 or 16) and tt
+// (0, 2, 4 or 6) are widths the lane kernel is built for, shared by every
+// instance of the handle so that one launch runs them all.
+void build_fml(const HostInst& q, std::vector<uint32_t>& out, int32_t dc, int32_t tt)
 {
     const int32_t n = q.n;
-    int32_t dmax, tmax;
-    fml_counts(q, dmax, tmax);
-    d4 = (dmax + 3) / 4;
-    d4 = d4 <= 1 ? 1 : (d4 == 2 ? 2 : 4);  // the lane kernel is built for widths 1, 2 and 4
-    t4 = (tmax + 1) / 2;
-    const size_t hn = ((size_t)n + 3) & ~(size_t)3;
+    const size_t hn = ((size_t)n + 1) & ~(size_t)1;
     const size_t base = out.size();
-    out.resize(base + hn + (size_t)n * 4 * (size_t)(d4 + t4), 0u);
+    out.resize(base + hn + (size_t)n * (size_t)(dc + 2 * tt), 0u);
     uint32_t* w = out.data() + base;
     uint32_t* cw = w + hn;
-    uint32_t* tw = cw + (size_t)n * 4 * (size_t)d4;
+    uint32_t* tw = cw + (size_t)n * (size_t)dc;
     for (const sg::Slice& S : q.slices)
         for (uint32_t l = 0; l < S.rows; ++l) {
             const uint32_t i = S.row0 + l, e = q.ext_of[i];
             const uint32_t self_c = fml_fb(e) << 16 | (e & 31u) << 11;
-            uint32_t* cr = cw + (size_t)e * 4 * (size_t)d4;
-            uint32_t* ce = cr + 4 * (size_t)d4;
+            uint32_t* cr = cw + (size_t)e * (size_t)dc;
+            uint32_t* ce = cr + dc;
             uint32_t nc = 0, nt = 0;
             for (uint32_t k = 0; k < S.ew; ++k) {
                 const uint32_t x = q.nbr[S.ebase + (size_t)k * sg::kSlice + l];
@@ -1029,8 +1025,8 @@ void build_fml(const HostInst& q, std::vector<uint32_t>& out, int32_t& d4, int32
                 ++nc;
             }
             while (cr < ce) *cr++ = self_c;
-            uint32_t* tr = tw + (size_t)e * 4 * (size_t)t4;
-            uint32_t* te = tr + 4 * (size_t)t4;
+            uint32_t* tr = tw + (size_t)e * 2 * (size_t)tt;
+            uint32_t* te = tr + 2 * (size_t)tt;
             for (uint32_t k = 0; k < S.tw; ++k) {
                 const size_t at = S.tbase + (size_t)k * sg::kSlice + l;
                 const uint32_t x = q.ta[at];
@@ -1120,11 +1116,24 @@ void layout(sg_ctx* H)
     }
     H->h_fml.clear();
     H->fm_item_cap = 0;
+    int32_t fdmax = 0, ftmax = 0;
     for (HostInst& q : H->insts) {
         q.fml_off = UINT64_MAX;
         if (!H->fml_ws || !fml_candidate(q)) continue;
+        q.fml_off = 0;
+        int32_t d, t;
+        fml_counts(q, d, t);
+        fdmax = std::max(fdmax, d);
+        ftmax = std::max(ftmax, t);
+    }
+    const int32_t fdc = fdmax <= 4 ? 4 : fdmax <= 6 ? 6 : fdmax <= 8 ? 8 : 16;
+    const int32_t ftt = ftmax == 0 ? 0 : ftmax <= 2 ? 2 : ftmax <= 4 ? 4 : 6;
+    for (HostInst& q : H->insts) {
+        if (q.fml_off == UINT64_MAX) continue;
         q.fml_off = H->h_fml.size();
-        build_fml(q, H->h_fml, q.fml_d4, q.fml_t4);
+        q.fml_dc = fdc;
+        q.fml_tt = ftt;
+        build_fml(q, H->h_fml, fdc, ftt);
         H->fm_item_cap += (q.R + 63) / 64;
     }
     H->off_fml = take(H->h_fml.size() * 4);
@@ -1982,14 +1991,14 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
         // a workgroup of W wavefronts shares its item: restarts in multiples of 64 W
         lw = std::max(1, sg::fml_waves_per_block(lnmax, H->fm_lane_waves));
         const int32_t unit = 64 * lw;
-        int32_t d4 = 1, t4 = 0;
+        int32_t dc = 4, tt = 0;
         for (const HostInst& q : H->insts)
             if (on_lanes(q)) {
-                d4 = q.fml_d4;
-                t4 = q.fml_t4;
+                dc = q.fml_dc;
+                tt = q.fml_tt;
                 break;
             }
-        const int64_t resident = std::max(1, sg::fml_resident_blocks(lnmax, lw, d4, t4));
+        const int64_t resident = std::max(1, sg::fml_resident_blocks(lnmax, lw, dc, tt));
         int32_t rmax = unit;
         for (const HostInst& q : H->insts)
             if (on_lanes(q)) rmax = std::max(rmax, (q.R + unit - 1) / unit * unit);
@@ -2013,7 +2022,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
                 H->h_fmitems.push_back(sg::BlockItem{(int32_t)k, r0, std::min(nr, q.R - r0), 0});
         }
         // one launch per pair of row widths, the largest items first in each
-        auto combo = [&](const sg::BlockItem& a) { return H->insts[a.inst].fml_d4 * 10 + H->insts[a.inst].fml_t4; };
+        auto combo = [&](const sg::BlockItem& a) { return H->insts[a.inst].fml_dc * 100 + H->insts[a.inst].fml_tt; };
         std::stable_sort(H->h_fmitems.begin(), H->h_fmitems.end(), [&](const sg::BlockItem& a, const sg::BlockItem& b) {
             if (combo(a) != combo(b)) return combo(a) < combo(b);
             return (int64_t)H->insts[a.inst].n * a.nr > (int64_t)H->insts[b.inst].n * b.nr;
@@ -2079,11 +2088,11 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
             const HostInst& q0 = H->insts[H->h_fmitems[a].inst];
             size_t b = a;
             int cn = 1;
-            while (b < H->h_fmitems.size() && H->insts[H->h_fmitems[b].inst].fml_d4 == q0.fml_d4 &&
-                   H->insts[H->h_fmitems[b].inst].fml_t4 == q0.fml_t4)
+            while (b < H->h_fmitems.size() && H->insts[H->h_fmitems[b].inst].fml_dc == q0.fml_dc &&
+                   H->insts[H->h_fmitems[b].inst].fml_tt == q0.fml_tt)
                 cn = std::max(cn, H->insts[H->h_fmitems[b++].inst].n);
             SG_HIP(sg::launch_fm_lanes(H->at<sg::InstTab>(H->off_tab), H->at<sg::BlockItem>(H->off_fmitems) + a,
-                                       (int)(b - a), cn, lw, q0.fml_d4, q0.fml_t4, H->reps(),
+                                       (int)(b - a), cn, lw, q0.fml_dc, q0.fml_tt, H->reps(),
                                        H->at<sg::CallStats>(H->off_stats), err, p->max_sweeps, p->until_converged, st),
                    "lane pass kernel");
             ++lane_launches;
@@ -2406,8 +2415,8 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
             T.n_et = q.n_et;
             T.eterm_pad = 0;
             T.fml = q.fml_off == UINT64_MAX ? nullptr : H->at<uint32_t>(H->off_fml) + q.fml_off;
-            T.fml_d4 = q.fml_d4;
-            T.fml_t4 = q.fml_t4;
+            T.fml_dc = q.fml_dc;
+            T.fml_tt = q.fml_tt;
             for (int32_t c = 0; c <= q.C; ++c) ctab.push_back(q.colour_slice[c]);
         }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_tab, tab.data(), tab.size() * sizeof(sg::InstTab), hipMemcpyHostToDevice,

@@ -80,11 +80,12 @@ hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* i
 // workgroup.  fml_waves_per_block: the wavefronts of one workgroup for
 // instances of up to nmax spins, want (0: one) bounded by four and the LDS
 // (0: too large); fml_resident_blocks: such workgroups resident on the device.
-// Every instance of one launch has rows of the widths d4 (1, 2 or 4) and t4
-// (0..3) (InstTab::fml_d4, fml_t4).
+// Every instance of one launch has rows of the widths dc (4, 6, 8 or 16
+// coupling words) and tt (0, 2, 4 or 6 hyper-couplings) (InstTab::fml_dc,
+// fml_tt).
 int fml_waves_per_block(int nmax, int want);
-int fml_resident_blocks(int nmax, int W, int d4, int t4);
-hipError_t launch_fm_lanes(const InstTab* tab, BlockItem* items, int nitems, int nmax, int W, int d4, int t4,
+int fml_resident_blocks(int nmax, int W, int dc, int tt);
+hipError_t launch_fm_lanes(const InstTab* tab, BlockItem* items, int nitems, int nmax, int W, int dc, int tt,
                            RepState* rs, CallStats* cs, uint32_t* err, int max_passes, int until_conv, hipStream_t st);
 // Dense hyper-Ising instances: one lane per replica; items are (instance,
 // first restart, count <= 64).  rule 0/1: colour sweeps; 2: pass-based search.

@@ -131,13 +131,11 @@ struct InstTab {
     const uint32_t* eterm;
     int32_t n_eh, n_ee, n_et, eterm_pad;
     // Per-spin term rows in external order for the lane-per-replica pass
-    // kernel (null when the instance does not qualify): the fields (n int32
-    // words, padded to a multiple of four), then fml_d4 groups of four
-    // coupling words (partner << 8 | J & 255) per spin, then fml_t4 groups of
-    // four hyper-coupling words (a << 20 | b << 8 | K & 255) per spin;
-    // partners are external indices and unused entries are zero.
+    // kernel (null when the instance does not qualify; layout in
+    // sg_fm_lanes.hip): fml_dc coupling words and fml_tt hyper-couplings per
+    // spin.
     const uint32_t* fml;
-    int32_t fml_d4, fml_t4;
+    int32_t fml_dc, fml_tt;
 };
 
 struct BlockItem {           // k_block: restarts [r0, r0 + nr) of instance inst
