@@ -388,7 +388,15 @@ __global__ __launch_bounds__(256) void k_fm_lanes(const InstTab* __restrict__ ta
 #pragma unroll
                 for (int u = 0; u < 8; ++u) top = b[u] > top ? b[u] : top;
             }
-            // rescan the touched groups, two at a time
+            // rescan the touched groups: one when no lane has touched more,
+            // else two at a time
+            if (!__ballot(__popc(dirty) > 1)) {
+                const int g1 = __builtin_ctz(dirty);
+                const uint32_t k1 = fml_group_key(gw, g1, lane);
+                bl[g1 * 64] = k1;
+                top = k1 > top ? k1 : top;
+                dirty = 0;
+            }
             while (dirty) {
                 const int g1 = __builtin_ctz(dirty);
                 dirty &= dirty - 1u;

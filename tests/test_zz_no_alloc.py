@@ -51,9 +51,9 @@ CASES = [
     # (name, instance, seed, rule, max_sweeps, until_converged, lattice dims), by decreasing workspace
     ("cubic100 TIE 40 sweeps (tile kernel)", lambda: gen.cfg2_cubic100(), 7, 1, 40, False, [(100, 100, 100)]),
     ("square 16x16, 64 restarts", lambda: gen.cfg1_square16(), 7, 0, 10000, True, [(16, 16)]),
-    ("ER 3000 with triples, 4 restarts", lambda: gen.erdos_renyi_triples(3000, seed=2, restarts=4), 3, 0, 10000, True,
-     None),
     ("chimera 8x8, 256 restarts", lambda: gen.chimera(8, 8, seed=3, instance_id=9, restarts=256), 5, 0, 10000, True,
+     None),
+    ("ER 3000 with triples, 4 restarts", lambda: gen.erdos_renyi_triples(3000, seed=2, restarts=4), 3, 0, 10000, True,
      None),
 ]
 
