@@ -14,6 +14,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -50,13 +51,16 @@ sg_status hip_fail(hipError_t e, const char* what)
 constexpr uint64_t kAlign = 256;
 inline uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
 
-// f(lo, hi) over [0, count) in contiguous ranges on up to four host threads
-// (one below 2^16 items): the per-row loops of a large instance's ingest.
+// f(lo, hi) over [0, count) in contiguous ranges on up to kHostThreads host
+// threads (one below 2^16 items): the per-row loops of a large instance's
+// ingest.  A range starting at lo may keep per-range results in slot
+// lo * kHostThreads / count: distinct and increasing over the ranges.
+constexpr unsigned kHostThreads = 4;
 template <class F>
 void parallel_ranges(int64_t count, F&& f)
 {
     unsigned T = std::thread::hardware_concurrency();
-    T = std::min(T ? T : 1u, 4u);
+    T = std::min(T ? T : 1u, kHostThreads);
     if (count < 65536 || T <= 1) {
         f((int64_t)0, count);
         return;
@@ -306,16 +310,22 @@ Primal build_primal(const sg_instance_desc& d)
     for (int32_t i = 0; i < n; ++i) P.start[i + 1] += P.start[i];
     P.adj.resize((size_t)P.start[n]);
     std::vector<int64_t> fill(P.start.begin(), P.start.end() - 1);
-    for (int64_t k = 0; k < d.m; ++k) {
-        P.adj[fill[d.ei[k]]++] = d.ej[k];
-        P.adj[fill[d.ej[k]]++] = d.ei[k];
-    }
-    for (int64_t k = 0; k < d.t; ++k) {
-        const int32_t a = d.tri[3 * k], b = d.tri[3 * k + 1], c = d.tri[3 * k + 2];
-        P.adj[fill[a]++] = b; P.adj[fill[a]++] = c;
-        P.adj[fill[b]++] = a; P.adj[fill[b]++] = c;
-        P.adj[fill[c]++] = a; P.adj[fill[c]++] = b;
-    }
+    // each thread fills the rows of its range, scanning every term in input
+    // order (the same lists as one pass over the terms)
+    parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+        auto mine = [&](int32_t v) { return v >= r0 && v < r1; };
+        for (int64_t k = 0; k < d.m; ++k) {
+            const int32_t a = d.ei[k], b = d.ej[k];
+            if (mine(a)) P.adj[fill[a]++] = b;
+            if (mine(b)) P.adj[fill[b]++] = a;
+        }
+        for (int64_t k = 0; k < d.t; ++k) {
+            const int32_t a = d.tri[3 * k], b = d.tri[3 * k + 1], c = d.tri[3 * k + 2];
+            if (mine(a)) { P.adj[fill[a]++] = b; P.adj[fill[a]++] = c; }
+            if (mine(b)) { P.adj[fill[b]++] = a; P.adj[fill[b]++] = c; }
+            if (mine(c)) { P.adj[fill[c]++] = a; P.adj[fill[c]++] = b; }
+        }
+    });
     return P;
 }
 
@@ -364,18 +374,51 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
     std::vector<int64_t> field((size_t)n, 0);
     std::vector<int64_t> bstart((size_t)n + 1, 0);  // edges bucketed by their smaller endpoint
     __int128 total = 0;  // sum |J| + sum |h| + sum |K|
-    for (int64_t k = 0; k < d.m; ++k) {
-        const int64_t a = d.ei[k], b = d.ej[k];
-        if (a < 0 || a >= n || b < 0 || b >= n)
-            return fail(SG_EINVAL, "instance %d: edge %lld has a spin index out of range", idx, (long long)k);
-        if (a == b) return fail(SG_EINVAL, "instance %d: edge %lld is a self-loop on spin %lld", idx, (long long)k,
-                                (long long)a);
-        const int64_t c = std::llabs((int64_t)d.J[k]);
-        if (c > kMaxCoef) w = true;
-        bstart[(size_t)std::min(a, b) + 1]++;
-        field[a] += c;
-        field[b] += c;
-        total += c;
+    {
+        // indices, self-loops, coefficient sizes and the total, by ranges of edges
+        std::vector<int64_t> bad_at(kHostThreads, -1);
+        std::vector<__int128> part(kHostThreads, 0);
+        std::vector<char> big(kHostThreads, 0);
+        parallel_ranges(d.m, [&](int64_t k0, int64_t k1) {
+            const size_t slot = (size_t)(k0 * kHostThreads / std::max<int64_t>(d.m, 1));
+            __int128 sum = 0;
+            bool b8 = false;
+            for (int64_t k = k0; k < k1; ++k) {
+                const int64_t a = d.ei[k], b = d.ej[k];
+                if (a < 0 || a >= n || b < 0 || b >= n || a == b) {
+                    bad_at[slot] = k;
+                    return;
+                }
+                const int64_t c = std::llabs((int64_t)d.J[k]);
+                b8 = b8 || c > kMaxCoef;
+                sum += c;
+            }
+            part[slot] = sum;
+            big[slot] = b8;
+        });
+        for (size_t t = 0; t < bad_at.size(); ++t)
+            if (bad_at[t] >= 0) {
+                const int64_t k = bad_at[t], a = d.ei[k], b = d.ej[k];
+                if (a < 0 || a >= n || b < 0 || b >= n)
+                    return fail(SG_EINVAL, "instance %d: edge %lld has a spin index out of range", idx, (long long)k);
+                return fail(SG_EINVAL, "instance %d: edge %lld is a self-loop on spin %lld", idx, (long long)k,
+                            (long long)a);
+            }
+        for (size_t t = 0; t < part.size(); ++t) {
+            total += part[t];
+            w = w || big[t];
+        }
+        // per-spin sums and bucket sizes, by ranges of spins
+        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+            for (int64_t k = 0; k < d.m; ++k) {
+                const int64_t a = d.ei[k], b = d.ej[k];
+                const int64_t c = std::llabs((int64_t)d.J[k]);
+                if (a >= r0 && a < r1) field[a] += c;
+                if (b >= r0 && b < r1) field[b] += c;
+                const int64_t lo = std::min(a, b);
+                if (lo >= r0 && lo < r1) bstart[(size_t)lo + 1]++;
+            }
+        });
     }
     {
         // duplicate pairs: a counting sort by the smaller endpoint, then each
@@ -383,14 +426,16 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
         for (int64_t i = 0; i < n; ++i) bstart[(size_t)i + 1] += bstart[(size_t)i];
         std::vector<int32_t> other((size_t)d.m);
         std::vector<int64_t> at(bstart.begin(), bstart.end() - 1);
-        for (int64_t k = 0; k < d.m; ++k) {
-            const int32_t a = d.ei[k], b = d.ej[k];
-            other[(size_t)at[(size_t)std::min(a, b)]++] = std::max(a, b);
-        }
-        std::vector<int64_t> dup_row(4, -1);
-        std::vector<int32_t> dup_col(4, 0);
         parallel_ranges(n, [&](int64_t r0, int64_t r1) {
-            const size_t slot = (size_t)(r0 * 4 / std::max<int64_t>(n, 1));
+            for (int64_t k = 0; k < d.m; ++k) {
+                const int32_t a = d.ei[k], b = d.ej[k], lo = std::min(a, b);
+                if (lo >= r0 && lo < r1) other[(size_t)at[(size_t)lo]++] = std::max(a, b);
+            }
+        });
+        std::vector<int64_t> dup_row(kHostThreads, -1);
+        std::vector<int32_t> dup_col(kHostThreads, 0);
+        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+            const size_t slot = (size_t)(r0 * kHostThreads / std::max<int64_t>(n, 1));
             for (int64_t i = r0; i < r1; ++i) {
                 auto lo = other.begin() + bstart[(size_t)i], hi = other.begin() + bstart[(size_t)i + 1];
                 if (hi - lo < 2) continue;
@@ -460,9 +505,9 @@ sg_status check_lattice(const sg_instance_desc& d, int idx)
     // 32-bit arithmetic: n < 2^31), checked over a few host threads
     const int32_t L1 = (int32_t)L[1], L2 = (int32_t)L[2], L12 = (int32_t)(L[1] * L[2]);
     const int32_t Lq[3] = {(int32_t)L[0], L1, L2};
-    std::vector<int64_t> bad(4, -1);
+    std::vector<int64_t> bad(kHostThreads, -1);
     parallel_ranges(d.m, [&](int64_t k0, int64_t k1) {
-        const size_t slot = (size_t)(k0 * 4 / std::max<int64_t>(d.m, 1));
+        const size_t slot = (size_t)(k0 * kHostThreads / std::max<int64_t>(d.m, 1));
         for (int64_t k = k0; k < k1; ++k) {
             const int32_t a = d.ei[k], b = d.ej[k];
             const int32_t ca[3] = {a / L12, (a / L2) % L1, a % L2};
@@ -505,27 +550,60 @@ void build_lattice(const sg_instance_desc& d, HostInst& q, const std::vector<uin
     const int32_t n = d.n;
     const int32_t c0 = q.colour[0];
     if (c0 != 0 && c0 != 1) return;
-    for (int32_t g = 0; g < n; ++g) {
-        const int32_t x = g / (L[1] * L[2]), y = (g / L[2]) % L[1], z = g % L[2];
-        const int32_t col = (x + y + z + c0) & 1;
-        if (q.colour[g] != col) return;
-        if (int_of[g] != (uint32_t)(col * (n / 2) + g / 2)) return;
-    }
+    // site loops walk (x, y, z) incrementally from one division per range
+    const int32_t stride[3] = {L[1] * L[2], L[2], 1};
+    auto sites = [&](auto&& body) {
+        parallel_ranges(n, [&](int64_t g0, int64_t g1) {
+            int32_t c[3] = {(int32_t)g0 / stride[0], ((int32_t)g0 / L[2]) % L[1], (int32_t)g0 % L[2]};
+            for (int64_t g = g0; g < g1; ++g) {
+                if (!body((int32_t)g, c)) return;
+                if (++c[2] == L[2]) {
+                    c[2] = 0;
+                    if (++c[1] == L[1]) {
+                        c[1] = 0;
+                        ++c[0];
+                    }
+                }
+            }
+        });
+    };
+    std::atomic<bool> ok{true};
+    sites([&](int32_t g, const int32_t* c) {
+        const int32_t col = (c[0] + c[1] + c[2] + c0) & 1;
+        if (q.colour[g] != col || int_of[g] != (uint32_t)(col * (n / 2) + g / 2)) ok = false;
+        return ok.load(std::memory_order_relaxed);
+    });
+    if (!ok) return;
+    // each bond's J by its lower site and axis (every (site, axis) pair is one
+    // bond, written once; the axis and direction follow from the index
+    // difference, which is unique for extents >= 3), then every site's record
+    // from its own and its lower neighbours' bonds
+    std::vector<int8_t> bondJ((size_t)n * 3, 0);
+    parallel_ranges(d.m, [&](int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k) {
+            const int32_t a = d.ei[k], b = d.ej[k];
+            int32_t lo = -1, ax = 0;
+            for (int x = 3 - dim; x < 3 && lo < 0; ++x) {
+                const int32_t st = stride[x], wrap = (L[x] - 1) * stride[x];
+                if (b - a == st || a - b == wrap) lo = a;        // b = a + e_x
+                else if (a - b == st || b - a == wrap) lo = b;   // a = b + e_x
+                ax = x;
+            }
+            bondJ[(size_t)lo * 3 + ax] = (int8_t)d.J[k];
+        }
+    });
     q.lat_rec.assign((size_t)n, 0);
-    for (int64_t k = 0; k < d.m; ++k) {
-        const int32_t a = d.ei[k], b = d.ej[k];
-        const int32_t ca[3] = {a / (L[1] * L[2]), (a / L[2]) % L[1], a % L[2]};
-        const int32_t cb[3] = {b / (L[1] * L[2]), (b / L[2]) % L[1], b % L[2]};
-        int ax = 0;
-        while (ax < 3 && ca[ax] == cb[ax]) ++ax;
-        const bool b_is_plus = cb[ax] == (ca[ax] + 1) % L[ax];
-        const int32_t lo = b_is_plus ? a : b, hi = b_is_plus ? b : a;  // hi = lo + e_ax
-        const uint64_t jv = (uint64_t)(uint8_t)(int8_t)d.J[k];
-        q.lat_rec[lo] |= jv << (8 * (2 * ax));
-        q.lat_rec[hi] |= jv << (8 * (2 * ax + 1));
-    }
-    if (d.h)
-        for (int32_t g = 0; g < n; ++g) q.lat_rec[g] |= (uint64_t)(uint8_t)(int8_t)d.h[g] << 48;
+    sites([&](int32_t g, const int32_t* c) {
+        uint64_t rc = 0;
+        for (int ax = 3 - dim; ax < 3; ++ax) {
+            const int32_t down = c[ax] == 0 ? g + (L[ax] - 1) * stride[ax] : g - stride[ax];
+            rc |= (uint64_t)(uint8_t)bondJ[(size_t)g * 3 + ax] << (8 * (2 * ax));
+            rc |= (uint64_t)(uint8_t)bondJ[(size_t)down * 3 + ax] << (8 * (2 * ax + 1));
+        }
+        if (d.h) rc |= (uint64_t)(uint8_t)(int8_t)d.h[g] << 48;
+        q.lat_rec[g] = rc;
+        return true;
+    });
     // bit-plane form: every bond of the lattice present with J = +-1, |h| <= 2
     q.lat_msc = 1;
     for (int32_t g = 0; g < n && q.lat_msc; ++g) {
@@ -711,22 +789,26 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
     std::vector<uint32_t> ew((size_t)es[n]), twa((size_t)ts[n]), twb((size_t)ts[n]);
     {
         std::vector<int64_t> fe(es.begin(), es.end() - 1), ft(ts.begin(), ts.end() - 1);
-        for (int64_t k = 0; k < d.m; ++k) {
-            const uint32_t a = int_of[d.ei[k]], b = int_of[d.ej[k]];
-            const uint32_t jb = (uint32_t)(uint8_t)(int8_t)d.J[k];
-            ew[fe[a]++] = (b << 8) | jb;
-            ew[fe[b]++] = (a << 8) | jb;
-        }
-        for (int64_t k = 0; k < d.t; ++k) {
-            const uint32_t v[3] = {int_of[d.tri[3 * k]], int_of[d.tri[3 * k + 1]], int_of[d.tri[3 * k + 2]]};
-            const uint32_t kb = (uint32_t)(uint8_t)(int8_t)d.K[k];
-            for (int s = 0; s < 3; ++s) {
-                const uint32_t o1 = v[(s + 1) % 3], o2 = v[(s + 2) % 3];
-                twa[ft[v[s]]] = (std::min(o1, o2) << 8) | kb;
-                twb[ft[v[s]]++] = std::max(o1, o2);
-            }
-        }
+        // each thread fills and sorts the rows of its range, scanning every
+        // term (rows in internal numbering)
         parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+            auto mine = [&](uint32_t v) { return (int64_t)v >= r0 && (int64_t)v < r1; };
+            for (int64_t k = 0; k < d.m; ++k) {
+                const uint32_t a = int_of[d.ei[k]], b = int_of[d.ej[k]];
+                const uint32_t jb = (uint32_t)(uint8_t)(int8_t)d.J[k];
+                if (mine(a)) ew[fe[a]++] = (b << 8) | jb;
+                if (mine(b)) ew[fe[b]++] = (a << 8) | jb;
+            }
+            for (int64_t k = 0; k < d.t; ++k) {
+                const uint32_t v[3] = {int_of[d.tri[3 * k]], int_of[d.tri[3 * k + 1]], int_of[d.tri[3 * k + 2]]};
+                const uint32_t kb = (uint32_t)(uint8_t)(int8_t)d.K[k];
+                for (int s = 0; s < 3; ++s) {
+                    if (!mine(v[s])) continue;
+                    const uint32_t o1 = v[(s + 1) % 3], o2 = v[(s + 2) % 3];
+                    twa[ft[v[s]]] = (std::min(o1, o2) << 8) | kb;
+                    twb[ft[v[s]]++] = std::max(o1, o2);
+                }
+            }
             std::vector<std::pair<uint32_t, uint32_t>> tmp;
             for (int64_t i = r0; i < r1; ++i) {
                 std::sort(ew.begin() + es[i], ew.begin() + es[i + 1]);
