@@ -28,7 +28,8 @@ The default run measures the headline lattice and then every other workload
 of the configuration list as a leg of the same JSON line: ``square16`` (the
 small lattice, microseconds per solve), ``batched`` (the Chimera batch against
 per-instance per-phase launches), ``uneven`` (the 2000 uneven instances
-against the per-phase method on every instance) and ``serving``.  Every leg
+against the per-phase method on every instance), ``serving`` and ``fm`` (the
+Chimera batch under the pass-based search).  Every leg
 carries the roofline position of its dominant kernel and the CPU oracle timed
 on a stated sample (``cpu_baseline``).
 
@@ -380,11 +381,12 @@ def run_chimera_fm(args, sg, gen, torch, count=4096):
         sample = [i.replace(restarts=16) for i in insts[:4]]
         t1 = time.perf_counter()
         cmoves = 0
+        cores = host_cores()
         for inst in sample:
-            sst, _ = oracle.fm(inst, seed=args.seed, threads=os.cpu_count() or 1)
+            sst, _ = oracle.fm(inst, seed=args.seed, threads=cores)
             cmoves += int(sst.sweeps.sum()) * inst.n
         ct = time.perf_counter() - t1
-        cpu = {"value": cmoves / ct, "unit": "moves/s", "cores": os.cpu_count() or 1, "kind": "oracle",
+        cpu = {"value": cmoves / ct, "unit": "moves/s", "cores": cores, "kind": "oracle",
                "sample": f"4 instances x 16 restarts of the batch ({cmoves:.3g} moves in {ct:.1f} s; the oracle "
                          f"evaluates every unlocked gain from the definition at each move)"}
     return {"workload": f"chimera{count}x256_fm", "attempts_per_s": moves / dt, "ms_per_step": dt * 1e3,
@@ -690,7 +692,7 @@ def main():
                     help="sweeps of the CPU oracle sample (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the Chimera batch in the default run")
-    ap.add_argument("--legs", default="square16,batched,uneven,serving",
+    ap.add_argument("--legs", default="square16,batched,uneven,serving,fm",
                     help="comma-separated workloads measured after the headline in the default run")
     ap.add_argument("--cpu-chimera", type=int, default=2048,
                     help="Chimera instances (x 256 restarts) in the batched leg's CPU oracle sample")
@@ -729,7 +731,8 @@ def main():
         if args.no_batched and "batched" in legs:
             legs.remove("batched")
         for leg in legs:
-            fn = {"square16": run_square, "batched": run_chimera, "uneven": run_er, "serving": run_serving}[leg]
+            fn = {"square16": run_square, "batched": run_chimera, "uneven": run_er, "serving": run_serving,
+                  "fm": run_chimera_fm}[leg]
             t_leg = time.perf_counter()
             out[leg] = fn(args, sg, gen, torch)
             log(f"leg {leg} done in {time.perf_counter() - t_leg:.1f} s")

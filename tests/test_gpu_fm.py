@@ -82,6 +82,22 @@ def test_lane_kernel_refill(gpu, nr):
     assert h.query("last_fm_lane_nr") == nr and h.query("last_fm_lanes") == 490
 
 
+@pytest.mark.parametrize("waves", [2, 4])
+def test_lane_kernel_shared_items(gpu, waves):
+    """Several wavefronts of a workgroup share one item's restarts (one
+    counter): the results are the oracle's."""
+    import paper_0912_3912_amd as sg
+    insts = [gen.chimera(8, 8, seed=s + 5, instance_id=s, restarts=300) for s in range(2)]
+    log(f"fm lane workgroups of {waves} wavefronts")
+    h = sg.load_instance(insts)
+    h.tune("fm_lane_waves", waves)
+    h.bind()
+    h.init_spins(8)
+    st = h.run_sweeps(seed=8, rule=FM, max_sweeps=1000, until_converged=True)
+    assert st["schedule_used"] == sg.SCHED_FM and h.query("last_fm_lanes") == 600
+    compare(h, insts, _oracle(insts, 8, 1000, True))
+
+
 def test_lane_kernel_lattice_regular_resume(gpu):
     insts = [gen.lattice((20, 20), seed=2, restarts=65), gen.lattice((32, 32), seed=3, restarts=9),
              gen.random_regular3(1000, seed=4, instance_id=9).replace(restarts=5)]
