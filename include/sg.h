@@ -121,9 +121,10 @@ typedef struct sg_ctx* sg_handle;
  * energy would not fit int64), or when n exceeds 2^30.  How the library
  * stores an instance (packed 8-bit coefficients and 24-bit indices, or a wide
  * form for larger values, sizes and restart counts) is invisible here: every
- * call accepts both and gives the same results; the wide form runs on
- * SG_SCHED_PHASE and SG_SCHED_GRAPH (SG_SCHED_AUTO picks them), and
- * SG_RULE_FM does not take it. */
+ * call accepts both and gives the same results; under GREEDY and
+ * GREEDY_TIE the wide form runs on SG_SCHED_PHASE and SG_SCHED_GRAPH
+ * (SG_SCHED_AUTO picks them), and SG_RULE_FM runs it one wavefront per
+ * replica. */
 typedef struct {
     int32_t n;
     int64_t m;

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sg_device.h"
 #include <type_traits>
 #include "sg_launch.h"
@@ -380,6 +382,193 @@ __global__ __launch_bounds__(kFmThreads) void k_fm(const InstTab* __restrict__ t
     }
 }
 
+// The pass kernel for one instance in the wide form (any int32 coupling,
+// field and hyper-coupling value with |h_i| + sum|J_ij| + sum|K| < 2^31 per
+// spin): one wavefront per replica r in [0, R), waves_per_block wavefronts
+// per workgroup.  The pass is that of k_fm.  Local fields fit int32, so each
+// spin's half-gain v_i = -s_i f_i does too (the gain -dE_i is 2 v_i, up to
+// 2^32 in magnitude); the wavefront keeps v in LDS and orders moves by the key
+// (v + 2^31) << 32 | ~ext, larger gain first, then lower external index.  A
+// flip of s_i changes a partner's half-gain by 2 J_ij s_i s_j, or by
+// 2 K s_i s_a s_b for a hyper-coupling; the adds wrap modulo 2^32 on the way,
+// and every half-gain they leave is again a value in range.
+template <bool TRI>
+__global__ __launch_bounds__(kFmThreads) void k_fm_wide(WideDev I, int8_t* __restrict__ spins, int64_t stride,
+                                                        RepState* __restrict__ rs, int R, int nmax,
+                                                        int waves_per_block, CallStats* __restrict__ cs,
+                                                        uint32_t* __restrict__ err, int max_passes, int until_conv)
+{
+    extern __shared__ uint8_t fm_lds[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = blockIdx.x * waves_per_block + wave;
+    long long att = 0, kept_all = 0, passes_done = 0;
+    int unconv = 0;
+    if (wave < waves_per_block && r < R && !rs[r].converged) {
+        RepState* st = rs + r;
+        const int n = I.n;
+        const size_t n4 = ((size_t)nmax + 3) & ~(size_t)3;
+        uint8_t* base = fm_lds + (size_t)wave * fm_wave_bytes(nmax);
+        uint32_t* half = reinterpret_cast<uint32_t*>(base);  // v_i as two's complement
+        int8_t* spin = reinterpret_cast<int8_t*>(base + 4 * n4);
+        uint16_t* moves = reinterpret_cast<uint16_t*>(base + 5 * n4);
+        uint16_t* slice_of = reinterpret_cast<uint16_t*>(base + 7 * n4);
+        uint16_t* ext = reinterpret_cast<uint16_t*>(base + 9 * n4);
+        uint32_t* dirty = reinterpret_cast<uint32_t*>(base + 11 * n4);
+        int8_t* gs = spins + stride * r;
+        const int G = (n + 63) >> 6;
+        for (int sl = 0; sl < I.nslices; ++sl) {
+            const WSlice S = I.slices[sl];
+            if ((uint32_t)lane < S.rows) slice_of[S.row0 + lane] = (uint16_t)sl;
+        }
+        for (int i = lane; i < n; i += 64) {
+            ext[i] = (uint16_t)I.ext[i];
+            spin[i] = gs[i];
+        }
+        if (lane < 2) dirty[lane] = 0u;
+        wave_lds_order();
+        auto key_of = [](uint32_t v, int e) -> uint64_t {
+            return ((uint64_t)(v ^ 0x80000000u) << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)e);
+        };
+        // this lane's best unlocked key over its spins lane, lane + 64, ...
+        auto scan = [&](uint64_t lk, uint64_t& bk, int& bi) {
+            bk = 0;
+            bi = -1;
+            for (int k0 = 0; k0 < G; k0 += 8) {
+                uint64_t kk[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k0 + u, ii = lane + 64 * k;
+                    const bool ok = k < G && ii < n && !((lk >> (k & 63)) & 1ull);
+                    const int is = ok ? ii : 0;
+                    kk[u] = ok ? key_of(half[is], ext[is]) : 0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (kk[u] > bk) {
+                        bk = kk[u];
+                        bi = lane + 64 * (k0 + u);
+                    }
+            }
+        };
+        long long Estar = st->E, kept = 0;
+        int passes = 0;
+        bool conv = false, bad = false;
+        for (int pass = 0; pass < max_passes && !bad; ++pass) {
+            // half-gains from the definition (every partial sum of a local
+            // field is bounded by the spin's limit, so int32 holds it)
+            for (int i = lane; i < n; i += 64) {
+                const WSlice S = I.slices[slice_of[i]];
+                const uint32_t l = (uint32_t)i - S.row0;
+                int32_t f = I.h[i];
+                for (uint32_t k = 0; k < S.ew; ++k) {
+                    const uint64_t o = S.ebase + (uint64_t)k * kSlice + l;
+                    f += I.J[o] * spin[I.nbr[o]];
+                }
+                if (TRI)
+                    for (uint32_t k = 0; k < S.tw; ++k) {
+                        const uint64_t o = S.tbase + (uint64_t)k * kSlice + l;
+                        f += I.K[o] * spin[I.ta[o]] * spin[I.tb[o]];
+                    }
+                half[i] = (uint32_t)(-spin[i] * f);
+            }
+            wave_lds_order();
+            uint64_t locked = 0, best = 0;
+            int besti = -1;
+            scan(0ull, best, besti);
+            long long E = Estar, Elow = Estar;
+            int best_len = 0;
+            for (int step = 0; step < n; ++step) {
+                const uint64_t top = wave_max_u64(best);
+                const int v = (int)((uint32_t)(top >> 32) ^ 0x80000000u);
+                const uint64_t own = __ballot(best == top);
+                const int owner = (int)__builtin_ctzll(own);
+                const int i = __builtin_amdgcn_readlane(besti, owner);
+                if (i < 0) {  // a cached key without its spin: internal error, stop this replica
+                    bad = true;
+                    break;
+                }
+                const int s_old = spin[i];
+                const WSlice S = I.slices[slice_of[i]];
+                const uint32_t l = (uint32_t)i - S.row0;
+                for (uint32_t k = lane; k < S.ew; k += 64) {
+                    const uint64_t o = S.ebase + (uint64_t)k * kSlice + l;
+                    const int32_t J = I.J[o];
+                    if (J) {
+                        const uint32_t j = I.nbr[o];
+                        atomicAdd(half + j, (uint32_t)J * (uint32_t)(2 * spin[j] * s_old));
+                        atomicOr(dirty + ((j & 63u) >> 5), 1u << (j & 31u));
+                    }
+                }
+                if (TRI)
+                    for (uint32_t k = lane; k < S.tw; k += 64) {
+                        const uint64_t o = S.tbase + (uint64_t)k * kSlice + l;
+                        const int32_t K = I.K[o];
+                        if (K) {
+                            const uint32_t a = I.ta[o], b = I.tb[o];
+                            const uint32_t d = (uint32_t)K * (uint32_t)(2 * spin[a] * spin[b] * s_old);
+                            atomicAdd(half + a, d);
+                            atomicAdd(half + b, d);
+                            atomicOr(dirty + ((a & 63u) >> 5), 1u << (a & 31u));
+                            atomicOr(dirty + ((b & 63u) >> 5), 1u << (b & 31u));
+                        }
+                    }
+                wave_lds_order();
+                const uint32_t dm = dirty[lane >> 5];
+                bool rescan = (dm >> (lane & 31)) & 1u;
+                if (lane == owner) {
+                    locked |= 1ull << (i >> 6);
+                    spin[i] = (int8_t)-s_old;
+                    moves[step] = (uint16_t)i;
+                    rescan = true;
+                }
+                wave_lds_order();
+                if (lane < 2) dirty[lane] = 0u;
+                if (rescan) scan(locked, best, besti);
+                E -= 2LL * v;
+                if (E < Elow) {
+                    Elow = E;
+                    best_len = step + 1;
+                }
+                wave_lds_order();
+            }
+            if (bad) break;
+            // undo the moves after the best prefix
+            for (int t = best_len + lane; t < n; t += 64) {
+                const int i = moves[t];
+                spin[i] = (int8_t)-spin[i];
+            }
+            wave_lds_order();
+            ++passes;
+            kept += best_len;
+            const bool improved = Elow < Estar;
+            Estar = Elow;
+            if (until_conv && !improved) {
+                conv = true;
+                break;
+            }
+        }
+        if (bad && lane == 0) atomicOr(err, 1u);
+        for (int i = lane; i < n && !bad; i += 64) gs[i] = spin[i];
+        if (lane == 0 && !bad) {
+            st->E = Estar;
+            st->sweeps += passes;
+            st->flips += kept;
+            if (conv) st->converged = 1;
+        }
+        att = (long long)passes * n;
+        kept_all = kept;
+        passes_done = passes;
+        unconv = (until_conv && !conv) ? 1 : 0;
+    }
+    // call totals: one atomic per wavefront that ran a replica
+    if (lane == 0 && (att || unconv)) {
+        atomicAdd(&cs->attempts, (unsigned long long)att);
+        atomicAdd(&cs->flips, (unsigned long long)kept_all);
+        atomicMax(&cs->sweeps_max, (unsigned long long)passes_done);
+        atomicAdd(&cs->unconverged, (unsigned long long)unconv);
+    }
+}
+
 size_t fm_lds_bytes(int nmax, int waves) { return fm_wave_bytes(nmax) * (size_t)waves; }
 
 template <bool TRI, bool K32>
@@ -414,6 +603,28 @@ int fm_max_blocks_per_cu(int waves, size_t lds, bool tri, bool key32)
 {
     if (tri) return key32 ? fm_blocks_per_cu<true, true>(waves, lds) : fm_blocks_per_cu<true, false>(waves, lds);
     return key32 ? fm_blocks_per_cu<false, true>(waves, lds) : fm_blocks_per_cu<false, false>(waves, lds);
+}
+
+hipError_t launch_fm_wide(const WideDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, CallStats* cs,
+                          uint32_t* err, int max_passes, int until_conv, hipStream_t st)
+{
+    if (R <= 0) return hipSuccess;
+    if (I.n < 1 || I.n > 4096) return hipErrorInvalidValue;
+    const size_t per = fm_wave_bytes(I.n);
+    const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, (size_t)(64 * 1024) / per));
+    const size_t lds = per * (size_t)waves;
+    const bool tri = I.has_tri != 0;
+    const void* kern = tri ? (const void*)k_fm_wide<true> : (const void*)k_fm_wide<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((R + waves - 1) / waves);
+    if (tri)
+        hipLaunchKernelGGL(k_fm_wide<true>, dim3(blocks), dim3(waves * 64), lds, st, I, spins, stride, rs, R, I.n,
+                           waves, cs, err, max_passes, until_conv);
+    else
+        hipLaunchKernelGGL(k_fm_wide<false>, dim3(blocks), dim3(waves * 64), lds, st, I, spins, stride, rs, R, I.n,
+                           waves, cs, err, max_passes, until_conv);
+    return hipGetLastError();
 }
 
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,

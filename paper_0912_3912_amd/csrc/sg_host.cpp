@@ -2038,10 +2038,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     auto on_lanes = [&](const HostInst& q) { return H->fm_lanes && q.fml_off != UINT64_MAX; };
     for (const HostInst& q : H->insts) {
         if (q.n > kFmMaxN) return fail(SG_EINVAL, "rule SG_RULE_FM: instance of %d spins (at most %d)", q.n, kFmMaxN);
-        if (q.wide)
-            return fail(SG_EINVAL, "rule SG_RULE_FM: instance %zu needs the wide form (a coefficient beyond int8, "
-                                   "a spin's |h|+sum|J|+sum|K| >= 2^23, or more than 255 triples on a spin)",
-                        (size_t)(&q - H->insts.data()));
+        if (q.wide) continue;  // a launch of its own below
         if (on_lanes(q)) {
             lnmax = std::max(lnmax, q.n);
             lane_reps += q.R;
@@ -2058,7 +2055,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     hipStream_t st = H->stream;
     H->h_qitems.clear();
     for (size_t k = 0; k < H->insts.size(); ++k)
-        if (!on_lanes(H->insts[k]))
+        if (!on_lanes(H->insts[k]) && !H->insts[k].wide)
             for (int32_t r = 0; r < H->insts[k].R; ++r) H->h_qitems.push_back(sg::QueueItem{(int32_t)k, r});
     std::stable_sort(H->h_qitems.begin(), H->h_qitems.end(), [&](const sg::QueueItem& a, const sg::QueueItem& b) {
         return H->insts[a.inst].n > H->insts[b.inst].n;
@@ -2115,7 +2112,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     // stage one instance's structure
     size_t stage = 0;
     for (const HostInst& q : H->insts)
-        if (!on_lanes(q))
+        if (!on_lanes(q) && !q.wide)
             stage = std::max(stage, q.slices.size() * sizeof(sg::Slice) + q.nbr.size() * 4 + (tri ? q.ta.size() * 8 : 0));
     stage = (stage + 15) / 16 * 16;
     // wavefronts per workgroup: the most resident wavefronts per compute unit
@@ -2186,9 +2183,19 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
                              H->at<sg::CallStats>(H->off_stats),
                              err, p->max_sweeps, p->until_converged, st),
                "pass kernel");
+    // instances in the wide form: one launch each, a wavefront per replica
+    int wide_launches = 0;
+    for (const HostInst& q : H->insts)
+        if (q.wide && p->max_sweeps > 0) {
+            SG_HIP(sg::launch_fm_wide(H->wview(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride,
+                                      H->reps() + q.rep_base, q.R, H->at<sg::CallStats>(H->off_stats), err,
+                                      p->max_sweeps, p->until_converged, st),
+                   "wide pass kernel");
+            ++wide_launches;
+        }
     SG_HIP(hipEventRecord(H->evh1, st), "event record");
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
-    H->hot_launches = p->max_sweeps > 0 ? lane_launches + (int)!H->h_qitems.empty() : 0;
+    H->hot_launches = p->max_sweeps > 0 ? lane_launches + (int)!H->h_qitems.empty() + wide_launches : 0;
     sg::CallStats cs;
     uint32_t herr = 0;
     SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");

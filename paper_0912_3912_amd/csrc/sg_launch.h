@@ -72,6 +72,11 @@ int fm_max_blocks_per_cu(int waves, size_t lds, bool tri, bool key32);
 hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* items, int nitems, int nmax, int waves,
                      int stage_cap, bool tri, bool key32, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
                      int until_conv, hipStream_t st);
+// The pass-based search on one instance in the wide form (at most 4096
+// spins), one wavefront per replica of [0, R); rs and spins are the
+// instance's own.
+hipError_t launch_fm_wide(const WideDev& I, int8_t* spins, int64_t stride, RepState* rs, int R, CallStats* cs,
+                          uint32_t* err, int max_passes, int until_conv, hipStream_t st);
 // The pass-based search with one replica per lane (instances of at most 1024
 // spins whose per-spin sum of |coefficients| is at most 127, with the
 // per-spin term rows InstTab::fml): workgroup k runs restarts [r0, r0 + nr)

@@ -135,8 +135,80 @@ def test_mixed_handle_and_set_spins(gpu):
     ref, _ = oracle.run(wide, seed=1, rule=GREEDY, max_sweeps=10000, until_converged=True, state=ref)
     compare(h, [wide], [ref])
     assert st["n_unconverged"] == 0
-    # the pass-based search stays on the packed form
-    with pytest.raises(sg.SGError) as e:
-        h.run_sweeps(seed=1, rule=sg.FM)
-    assert e.value.status == sg.SG_EINVAL
+    h.free()
+
+
+def _check_fm(insts, seed, max_passes=1000, uc=True, runs=None, threads=16):
+    """The pass-based search (Sec. IV, Fig. 3) on the GPU and in the oracle."""
+    import paper_0912_3912_amd as sg
+    log(f"wide fm case: {[i.name for i in insts][:3]} seed={seed} passes={runs or max_passes} uc={uc}")
+    h = sg.load_instance(list(insts)).bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=sg.FM, max_sweeps=mp, until_converged=uc) for mp in (runs or [max_passes])]
+    assert all(s["schedule_used"] == sg.SCHED_FM for s in stats)
+    states = []
+    for inst in insts:
+        st = None
+        for mp in (runs or [max_passes]):
+            st, _ = oracle.fm(inst, seed=seed, max_passes=mp, until_converged=uc, state=st, threads=threads)
+        states.append(st)
+    compare(h, insts, states)
+    if runs is None:
+        assert stats[0]["attempts"] == sum(int((st.sweeps * i.n).sum()) for i, st in zip(insts, states))
+        assert stats[0]["flips"] == sum(int(st.flips.sum()) for st in states)
+    return h, stats
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 300, 700, 4096])
+def test_fm_large_coefficients_ragged(gpu, n):
+    """The pass-based search on the wide form: sizes around the 64-spin lane
+    stride, couplings, fields and hyper-couplings up to 10^5."""
+    base = gen.random_small(n, seed=n + 40, p_edge=min(1.0, 8.0 / max(n, 1)), n_triples=n // 2)
+    inst = _recoef(base, seed=n, j_max=10**5, h_max=10**5).replace(restarts=5, instance_id=n + 7)
+    h, _ = _check_fm([inst], seed=n + 1)
+    big = max([int(np.abs(a).max()) for a in (inst.J, inst.h, inst.K) if a is not None and a.size] + [0])
+    assert h.query("wide_instances") == int(big > 127)
+    h.free()
+
+
+def test_fm_fields_near_the_int32_limit(gpu):
+    """Half-gains of the whole int32 range; move gains beyond it."""
+    base = gen.random_regular3(600, seed=3, instance_id=4)
+    lim = 2**31 - 1
+    inst = _recoef(base, seed=6, j_max=lim // 4, h_max=lim // 4).replace(restarts=6)
+    h, _ = _check_fm([inst], seed=8)
+    assert h.query("wide_instances") == 1
+    h.free()
+    h, _ = _check_fm([inst], seed=8, uc=False, runs=[2, 0, 3])
+    h.free()
+
+
+def test_fm_many_triples_per_spin(gpu):
+    rng = np.random.default_rng(12)
+    n = 40
+    tri = set()
+    while len(tri) < 4000:
+        tri.add(tuple(sorted(rng.choice(n, 3, replace=False).tolist())))
+    tri = np.array(sorted(tri), np.int32)
+    assert np.bincount(tri.reshape(-1), minlength=n).max() > 255
+    inst = gen.Instance(n=n, ei=np.zeros(0, np.int32), ej=np.zeros(0, np.int32), J=np.zeros(0, np.int32),
+                        h=rng.integers(-2, 3, n).astype(np.int32), tri=tri,
+                        K=rng.integers(-2, 3, tri.shape[0]).astype(np.int32), instance_id=14, restarts=9,
+                        name="fm_dense_triples")
+    h, _ = _check_fm([inst], seed=3)
+    assert h.query("wide_instances") == 1
+    h.free()
+
+
+def test_fm_packed_and_wide_in_one_call(gpu):
+    """Instances on the lane kernel, the wavefront kernel and the wide form in
+    one call."""
+    lanes = gen.chimera(4, 4, seed=2, instance_id=1, restarts=70)
+    waves = gen.random_small(200, seed=9, p_edge=0.04, n_triples=50, j_range=(-60, 60), h_range=(-9, 9),
+                             k_range=(-9, 9)).replace(restarts=5, instance_id=3)
+    wide = _recoef(gen.erdos_renyi_triples(500, seed=5), seed=3, j_max=5000, h_max=300).replace(instance_id=2,
+                                                                                               restarts=3)
+    h, st = _check_fm([lanes, waves, wide], seed=5)
+    assert h.query("wide_instances") == 1 and h.query("last_fm_lanes") == 70
+    assert st[0]["n_unconverged"] == 0
     h.free()
