@@ -263,7 +263,10 @@ sg_status sg_instance_info_get(sg_handle h, int32_t inst, sg_instance_info* info
  * eq. (5) and room for the replicas' spin configurations, the state the local
  * search of Sec. IV (Fig. 3) works on; the paper itself defines no memory
  * layout.  The memory must stay allocated while the
- * handle uses it; binding again moves the handle (state is not kept).
+ * handle uses it; binding again moves the handle (state is not kept).  The
+ * first sg_bind of a handle also allocates 64 KiB of pinned host memory
+ * (hipHostMalloc, released by sg_free), through which the later calls read
+ * their small results back without a synchronisation per copy.
  * Errors: SG_ENOMEM if too small, SG_EINVAL if misaligned, SG_EDEVICE. */
 sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
 
@@ -277,7 +280,9 @@ sg_status sg_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream);
  * allocated device array (one per GPU, held until the process ends) and to a
  * HIP stream, and uploads the coupling structure, as sg_bind does.  Allocates
  * no device memory (no hipMalloc, no allocating library routine; the
- * handle's HIP timing events are created on its first bind, as by sg_bind).  Every
+ * handle's HIP timing events are created on its first bind, as by sg_bind)
+ * and no pinned host memory: a handle first bound this way reads its results
+ * back through pageable copies, one synchronisation each.  Every
  * handle bound this way on one GPU shares that array, which keeps the last
  * user's contents: binding another handle replaces the first one's structure
  * and state (use the first one again only after binding it again), and calls
@@ -366,6 +371,17 @@ sg_status sg_spins_out_batch(sg_handle h, int32_t inst, int32_t r0, int32_t coun
  * tracked energy over its restarts, lowest restart index on ties.  E_best and
  * r_best have one entry per instance; either may be NULL. */
 sg_status sg_best(sg_handle h, int64_t* E_best, int32_t* r_best);
+
+/* A whole multi-start search in one call (Sec. IV: random starts, the local
+ * search, keep the best): sg_init_spins(h, p->seed), then sg_run_sweeps(h, p,
+ * stats), then sg_best(h, E_best, r_best), with the same results, replica
+ * states and statuses as those three calls.  When every instance is a
+ * lattice that one workgroup holds (at most lattice_wg_max_n spins, lattice
+ * hint given) and the run would take SG_SCHED_LATTICE, the start, the sweeps
+ * and the replica energies run as one kernel launch per instance and the call
+ * synchronises once; otherwise it makes the three calls.  Errors: those of
+ * the three calls (SG_ENOTCONV after every output is written). */
+sg_status sg_solve(sg_handle h, const sg_run_params* p, sg_run_stats* stats, int64_t* E_best, int32_t* r_best);
 
 /* Tuning knobs of the schedules; results never depend on them.
  *   "lattice_k"          colour phases between halo exchanges of the lattice

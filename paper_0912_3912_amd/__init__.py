@@ -104,6 +104,7 @@ SIGNATURES = [
     ("sg_spins_out", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("sg_spins_out_batch", ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]),
     ("sg_best", ctypes.c_int32, [_P, _P, _P]),
+    ("sg_solve", ctypes.c_int32, [_P, _P, _P, _P, _P]),
     ("sg_tune", ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
     ("sg_query", ctypes.c_int32, [_P, ctypes.c_char_p, _P]),
     ("sg_philox_word0", ctypes.c_int32, [_P, _P, ctypes.c_int64, ctypes.c_uint64, _P]),
@@ -326,6 +327,20 @@ class Handle:
         r = np.zeros(ni, np.int32)
         _check(lib().sg_best(self._h, _ptr(E), _ptr(r)))
         return E, r
+
+    def solve(self, seed: int, rule: int = GREEDY, max_sweeps: int = 10000, until_converged: bool = True,
+              schedule: int = SCHED_AUTO):
+        """init_spins(seed), run_sweeps(...), best() in one library call;
+        returns (stats, E_best, r_best)."""
+        p = RunParams(seed & 0xFFFFFFFFFFFFFFFF, rule, max_sweeps, int(until_converged), schedule)
+        st = RunStats()
+        ni = len(self.sizes)
+        E = np.zeros(ni, np.int64)
+        r = np.zeros(ni, np.int32)
+        status = _check(lib().sg_solve(self._h, ctypes.byref(p), ctypes.byref(st), _ptr(E), _ptr(r)))
+        d = st.as_dict()
+        d["status"] = status
+        return d, E, r
 
     def tune(self, key: str, value: int):
         _check(lib().sg_tune(self._h, key.encode(), int(value)))

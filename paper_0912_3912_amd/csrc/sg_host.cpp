@@ -155,7 +155,7 @@ struct sg_ctx {
     int64_t total_reps = 0;
     uint64_t bytes = 0;
     uint64_t off_reps = 0, off_stats = 0, off_flag = 0, off_eout = 0, off_slots = 0;
-    uint64_t off_best_E = 0, off_best_r = 0, off_rep_base = 0, off_restarts = 0, off_err = 0;
+    uint64_t off_best_E = 0, off_best_r = 0, off_rep_base = 0, off_restarts = 0, off_err = 0, off_solve = 0;
     // tuning knobs (sg_tune)
     int32_t lattice_k = 4;             // phases per halo exchange of the lattice tile schedule
     int32_t lattice_max_tiles = 0;     // 0 = as many as fit co-resident
@@ -227,6 +227,14 @@ struct sg_ctx {
     bool lat_err_check = false;  // the current call launched tile kernels: read their error flag at its end
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evh0 = nullptr, evh1 = nullptr;  // around the hot kernel(s) of the last schedule run
+    // pinned host memory for the small results a call reads back (sg_bind;
+    // none after sg_bind_noalloc, whose callers cannot allocate): a copy into
+    // pageable memory waits for the device, one into pinned memory does not,
+    // so the copies of one call share its single synchronisation
+    uint8_t* pin = nullptr;
+    // the call totals are zero: the last sg_solve in one launch per instance
+    // left them so (its last workgroup clears them), and no run has used them since
+    bool stats_zero = false;
     double hot_us = 0.0;                        // their device time, microseconds
     int32_t hot_launches = 0;                   // launches inside that interval
     int32_t last_tiles[4] = {0, 0, 0, 0};  // tiling of the last lattice tile launch
@@ -351,6 +359,43 @@ int32_t first_fit(const Primal& P, int32_t n, std::vector<int32_t>& colour)
     }
     return ncol;
 }
+
+// Device-to-host copies of one call.  A copy of at most kPinBytes in total
+// goes through the handle's pinned buffer and reaches its destination in
+// finish(), after the call's stream synchronisation; a larger one, or any
+// copy of a handle without the buffer, goes straight to its destination.
+constexpr size_t kPinBytes = 64 * 1024;
+
+class CopiesOut {
+  public:
+    explicit CopiesOut(const sg_ctx* H) : pin_(H->pin) {}
+    hipError_t copy(void* dst, const void* src, size_t bytes, hipStream_t st)
+    {
+        if (pin_ && used_ + bytes <= kPinBytes) {
+            const hipError_t e = hipMemcpyAsync(pin_ + used_, src, bytes, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) pend_.push_back({dst, used_, bytes});
+            used_ += (bytes + 15) & ~(size_t)15;
+            return e;
+        }
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+    }
+    // only after the stream has been synchronised
+    void finish()
+    {
+        for (const Pending& c : pend_) std::memcpy(c.dst, pin_ + c.off, c.bytes);
+        pend_.clear();
+        used_ = 0;
+    }
+
+  private:
+    struct Pending {
+        void* dst;
+        size_t off, bytes;
+    };
+    uint8_t* pin_;
+    size_t used_ = 0;
+    std::vector<Pending> pend_;
+};
 
 // Checks an instance.  *wide (when given) is set when its values or sizes
 // exceed the packed words (int8 coefficients, 24-bit spin index, per-spin
@@ -1270,6 +1315,7 @@ void layout(sg_ctx* H)
     H->off_ditems = take(H->h_ditems.size() * sizeof(sg::BlockItem));
     H->off_best_E = take(ni * 8);
     H->off_best_r = take(ni * 4);
+    H->off_solve = take(64 + ni * 12);  // sg_solve's results: call totals, best energies, best restarts
     H->off_rep_base = take(ni * 8);
     H->off_restarts = take(ni * 4);
     H->bytes = off;
@@ -1346,8 +1392,10 @@ sg_status run_phase_schedule(sg_handle H, const sg_run_params* p, const std::vec
                 if (T >= p->max_sweeps) break;
                 SG_HIP(sg::launch_fill_u32(flag, 1, 0u, st), "fill kernel");
                 SG_HIP(sg::launch_any_active(rs, q.R, T, flag, st), "activity kernel");
-                SG_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
+                CopiesOut out(H);
+                SG_HIP(out.copy(&hflag, flag, 4, st), "flag copy");
                 SG_HIP(hipStreamSynchronize(st), "stream sync");
+                out.finish();
                 if (!hflag) break;
                 seg = std::min(seg * 2, 64);
             }
@@ -1434,12 +1482,14 @@ sg_status run_graph_schedule(sg_handle H, const sg_run_params* p, const std::vec
                 uint32_t hflag = 0;
                 hipError_t e1 = sg::launch_fill_u32(flag, 1, 0u, st);
                 if (e1 == hipSuccess) e1 = sg::launch_any_active(rs, q.R, T, flag, st);
-                if (e1 == hipSuccess) e1 = hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, st);
+                CopiesOut out(H);
+                if (e1 == hipSuccess) e1 = out.copy(&hflag, flag, 4, st);
                 if (e1 == hipSuccess) e1 = hipStreamSynchronize(st);
                 if (e1 != hipSuccess) {
                     cleanup();
                     return hip_fail(e1, "activity check");
                 }
+                out.finish();
                 stopped = hflag == 0;
             }
         }
@@ -1680,8 +1730,10 @@ sg_status run_lattice_schedule(sg_handle H, const sg_run_params* p, const std::v
                     uint32_t hflag = 0;
                     SG_HIP(sg::launch_fill_u32(flag, 1, 0u, st), "fill kernel");
                     SG_HIP(sg::launch_any_active(rs, q.R, launched, flag, st), "activity kernel");
-                    SG_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, st), "flag copy");
+                    CopiesOut out(H);
+                    SG_HIP(out.copy(&hflag, flag, 4, st), "flag copy");
                     SG_HIP(hipStreamSynchronize(st), "stream sync");
+                    out.finish();
                     if (!hflag) break;
                 }
                 T_done = launched;
@@ -2198,9 +2250,11 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     H->hot_launches = p->max_sweeps > 0 ? lane_launches + (int)!H->h_qitems.empty() + wide_launches : 0;
     sg::CallStats cs;
     uint32_t herr = 0;
-    SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
-    SG_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st), "error flag copy");
+    CopiesOut out(H);
+    SG_HIP(out.copy(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, st), "stats copy");
+    SG_HIP(out.copy(&herr, err, 4, st), "error flag copy");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
+    out.finish();
     if (herr) return fail(SG_EDEVICE, "pass kernel: internal error (a selected move had no spin)");
     float ms = 0.f;
     SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
@@ -2224,6 +2278,15 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
 
 // Error reporting and validation for the library's other translation units.
 sg_status sg_internal_fail(sg_status code, const char* msg) { return fail(code, "%s", msg); }
+
+// sg_bind_noalloc's binding: no pinned host buffer is allocated (one from an
+// earlier binding is kept).
+sg_status bind_impl(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream, bool may_alloc);
+sg_status sg_internal_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream, bool may_alloc)
+{
+    return bind_impl(H, dev_ptr, bytes, hip_stream, may_alloc);
+}
+
 sg_status sg_internal_validate(const sg_instance_desc* d) { return validate(*d, 0); }
 
 // ---------------------------------------------------------------------------
@@ -2380,7 +2443,9 @@ sg_status sg_instance_info_get(sg_handle H, int32_t inst, sg_instance_info* info
     return SG_OK;
 }
 
-sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
+}  // extern "C"
+
+sg_status bind_impl(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream, bool may_alloc)
 {
     if (!H) return fail(SG_EINVAL, "null handle");
     if (!dev_ptr) return fail(SG_EINVAL, "sg_bind: null device pointer");
@@ -2391,6 +2456,7 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
     H->dev = (uint8_t*)dev_ptr;
     H->stream = (hipStream_t)hip_stream;
     H->bound = false;
+    H->stats_zero = false;
     std::fill(H->started.begin(), H->started.end(), 0);
     H->e_pending = false;
     H->e_deferred.assign(H->insts.size(), 0);
@@ -2547,8 +2613,16 @@ sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
     if (!H->evh0) SG_HIP(hipEventCreate(&H->evh0), "event create");
     if (!H->evh1) SG_HIP(hipEventCreate(&H->evh1), "event create");
     if (!H->ev1) SG_HIP(hipEventCreate(&H->ev1), "event create");
+    if (!H->pin && may_alloc) SG_HIP(hipHostMalloc((void**)&H->pin, kPinBytes, hipHostMallocDefault), "pinned buffer");
     H->bound = true;
     return SG_OK;
+}
+
+extern "C" {
+
+sg_status sg_bind(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream)
+{
+    return bind_impl(H, dev_ptr, bytes, hip_stream, true);
 }
 
 sg_status sg_init_spins(sg_handle H, uint64_t seed)
@@ -2659,6 +2733,7 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
     for (uint8_t v : H->started)
         if (!v) return fail(SG_ESTATE, "a replica has no start (call sg_init_spins or sg_set_spins)");
+    H->stats_zero = false;  // every run below leaves its totals there
     if (H->dense) return run_dense(H, p, stats);
     if (p->rule == SG_RULE_FM) {
         if ((e = ensure_energy(H)) != SG_OK) return e;
@@ -2697,11 +2772,12 @@ sg_status sg_run_sweeps(sg_handle H, const sg_run_params* p, sg_run_stats* stats
     }
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
     sg::CallStats cs;
-    SG_HIP(hipMemcpyAsync(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, hipMemcpyDeviceToHost, st), "stats copy");
     uint32_t herr = 0;
-    if (H->lat_err_check)
-        SG_HIP(hipMemcpyAsync(&herr, H->at<uint32_t>(H->off_err), 4, hipMemcpyDeviceToHost, st), "error flag copy");
+    CopiesOut out(H);
+    SG_HIP(out.copy(&cs, H->at<sg::CallStats>(H->off_stats), sizeof cs, st), "stats copy");
+    if (H->lat_err_check) SG_HIP(out.copy(&herr, H->at<uint32_t>(H->off_err), 4, st), "error flag copy");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
+    out.finish();
     if (herr)
         return fail(SG_EDEVICE, "lattice tile kernel: a neighbour wait timed out (replica state is undefined; "
                                 "start again with sg_init_spins)");
@@ -2781,9 +2857,10 @@ sg_status sg_energy(sg_handle H, int64_t* E, int32_t recompute)
         return SG_OK;
     }
     std::vector<sg::RepState> rs((size_t)H->total_reps);
-    SG_HIP(hipMemcpyAsync(rs.data(), H->reps(), rs.size() * sizeof(sg::RepState), hipMemcpyDeviceToHost, st),
-           "state copy");
+    CopiesOut out(H);
+    SG_HIP(out.copy(rs.data(), H->reps(), rs.size() * sizeof(sg::RepState), st), "state copy");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
+    out.finish();
     for (size_t k = 0; k < rs.size(); ++k) E[k] = rs[k].E;
     return SG_OK;
 }
@@ -2853,11 +2930,100 @@ sg_status sg_best(sg_handle H, int64_t* E_best, int32_t* r_best)
            "best kernel");
     std::vector<int64_t> eb((size_t)ni);
     std::vector<int32_t> rb((size_t)ni);
-    SG_HIP(hipMemcpyAsync(eb.data(), H->at<int64_t>(H->off_best_E), (size_t)ni * 8, hipMemcpyDeviceToHost, st), "copy");
-    SG_HIP(hipMemcpyAsync(rb.data(), H->at<int32_t>(H->off_best_r), (size_t)ni * 4, hipMemcpyDeviceToHost, st), "copy");
+    CopiesOut out(H);
+    SG_HIP(out.copy(eb.data(), H->at<int64_t>(H->off_best_E), (size_t)ni * 8, st), "copy");
+    SG_HIP(out.copy(rb.data(), H->at<int32_t>(H->off_best_r), (size_t)ni * 4, st), "copy");
     SG_HIP(hipStreamSynchronize(st), "stream sync");
+    out.finish();
     if (E_best) std::memcpy(E_best, eb.data(), (size_t)ni * 8);
     if (r_best) std::memcpy(r_best, rb.data(), (size_t)ni * 4);
+    return SG_OK;
+}
+
+sg_status sg_solve(sg_handle H, const sg_run_params* p, sg_run_stats* stats, int64_t* E_best, int32_t* r_best)
+{
+    sg_status e = need_bound(H);
+    if (e != SG_OK) return e;
+    if (!p) return fail(SG_EINVAL, "sg_solve: null params");
+    if (p->rule != SG_RULE_GREEDY && p->rule != SG_RULE_GREEDY_TIE && p->rule != SG_RULE_FM)
+        return fail(SG_EINVAL, "unknown rule %d", p->rule);
+    if (p->max_sweeps < 0) return fail(SG_EINVAL, "max_sweeps must be >= 0");
+    // one launch per instance when every instance is a lattice that the
+    // workgroup-per-replica kernel holds and the run would take that kernel
+    bool one = !H->dense && (p->rule == SG_RULE_GREEDY || p->rule == SG_RULE_GREEDY_TIE) && p->max_sweeps >= 0 &&
+               (p->schedule == SG_SCHED_AUTO || p->schedule == SG_SCHED_LATTICE) && !H->insts.empty();
+    for (const HostInst& q : H->insts) one = one && !q.wide && q.lat_ok && lattice_wg_fits(H, q);
+    if (one) {
+        std::vector<int> assign;
+        one = assign_schedules(H, p, assign) == SG_SCHED_LATTICE;
+    }
+    if (!one) {
+        if ((e = sg_init_spins(H, p->seed)) != SG_OK) return e;
+        const sg_status run = sg_run_sweeps(H, p, stats);
+        if (run < 0) return run;
+        if ((e = sg_best(H, E_best, r_best)) != SG_OK) return e;
+        return run;
+    }
+    hipStream_t st = H->stream;
+    const int ni = (int)H->insts.size();
+    sg::CallStats* cs = H->at<sg::CallStats>(H->off_stats);
+    // results of the call, written by the last workgroup of each launch: call
+    // totals (64 bytes), best energies, best restarts; read back in one copy
+    static_assert(sizeof(sg::CallStats) <= 64, "the call totals take the first 64 bytes of the results");
+    uint8_t* res = H->dev + H->off_solve;
+    const size_t res_bytes = 64 + (size_t)ni * 12;
+    if (!H->stats_zero)
+        SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_stats), sizeof(sg::CallStats) / 4, 0u, st), "fill kernel");
+    H->stats_zero = false;
+    SG_HIP(hipEventRecord(H->ev0, st), "event record");
+    unsigned long long done_end = 0;
+    for (int k = 0; k < ni; ++k) {
+        const HostInst& q = H->insts[(size_t)k];
+        done_end += (unsigned long long)q.R;
+        const sg::WgSolve sv{cs, reinterpret_cast<int64_t*>(res + 64) + k,
+                             reinterpret_cast<int32_t*>(res + 64 + (size_t)ni * 8) + k,
+                             k == ni - 1 ? reinterpret_cast<sg::CallStats*>(res) : nullptr, done_end};
+        SG_HIP(sg::launch_lattice_wg(H->lat_view(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride,
+                                     H->reps() + q.rep_base, q.R, nullptr, 0, p->max_sweeps, p->seed, p->rule,
+                                     p->until_converged, st, &sv),
+               "lattice workgroup kernel");
+    }
+    SG_HIP(hipEventRecord(H->ev1, st), "event record");
+    H->hot_launches = ni;
+    std::vector<uint8_t> hres(res_bytes);
+    CopiesOut out(H);
+    SG_HIP(out.copy(hres.data(), res, res_bytes, st), "result copy");
+    SG_HIP(hipStreamSynchronize(st), "stream sync");
+    out.finish();
+    H->stats_zero = true;
+    sg::CallStats c;
+    std::memcpy(&c, hres.data(), sizeof c);
+    std::vector<int64_t> eb((size_t)ni);
+    std::vector<int32_t> rb((size_t)ni);
+    std::memcpy(eb.data(), hres.data() + 64, (size_t)ni * 8);
+    std::memcpy(rb.data(), hres.data() + 64 + (size_t)ni * 8, (size_t)ni * 4);
+    // every replica has a start and an exact energy
+    std::fill(H->started.begin(), H->started.end(), 1);
+    H->e_pending = false;
+    H->e_deferred.assign(H->insts.size(), 0);
+    float ms = 0.f;
+    SG_HIP(hipEventElapsedTime(&ms, H->ev0, H->ev1), "event time");
+    H->hot_us = ms * 1000.0;  // only the solve's launches lie between the events
+    if (E_best) std::memcpy(E_best, eb.data(), (size_t)ni * 8);
+    if (r_best) std::memcpy(r_best, rb.data(), (size_t)ni * 4);
+    if (stats) {
+        stats->attempts = (int64_t)c.attempts;
+        stats->flips = (int64_t)c.flips;
+        stats->sweeps_max = (int64_t)c.sweeps_max;
+        stats->n_unconverged = (int32_t)c.unconverged;
+        stats->schedule_used = SG_SCHED_LATTICE;
+        stats->kernel_ms = ms;
+    }
+    if (p->until_converged && c.unconverged) {
+        fail(SG_ENOTCONV, "%llu replicas did not converge within %d sweeps", (unsigned long long)c.unconverged,
+             p->max_sweeps);
+        return SG_ENOTCONV;
+    }
     return SG_OK;
 }
 
@@ -3232,6 +3398,7 @@ sg_status sg_free(sg_handle H)
     if (H->evh0) (void)hipEventDestroy(H->evh0);
     if (H->evh1) (void)hipEventDestroy(H->evh1);
     if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
+    if (H->pin) (void)hipHostFree(H->pin);
     delete H;
     return SG_OK;
 }

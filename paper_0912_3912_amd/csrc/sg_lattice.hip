@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "sg_device.h"
 #include "sg_launch.h"
 #include "sg_layout.h"
@@ -375,26 +377,33 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_tiles(LatticeDev Lt, Ti
 template <int D, bool TIE>
 __global__ __launch_bounds__(kLatThreads) void k_lattice_wg(LatticeDev Lt, int8_t* __restrict__ canon, int64_t stride,
                                                             RepState* __restrict__ rs, int64_t* __restrict__ acc,
-                                                            int nslots, int T, uint64_t seed, int until_conv)
+                                                            int nslots, int T, uint64_t seed, int until_conv,
+                                                            WgSolve sv, int solve)
 {
     extern __shared__ uint64_t lds64[];
     int8_t* s = reinterpret_cast<int8_t*>(lds64);
     const int r = blockIdx.x;
     RepState* stp = rs + r;
-    if (stp->converged) return;
+    if (!solve && stp->converged) return;
     const int tid = threadIdx.x;
     const int L0 = Lt.L[0], L1 = Lt.L[1], L2 = Lt.L[2];
     const int n = Lt.n, half = n / 2;
     int8_t* cs = canon + (int64_t)r * stride;
-    // load: site g <- internal index
+    // load: site g <- internal index; a solve draws the random start instead
+    // (the start rule of every other start kernel: the Philox bit of (site,
+    // 0xFFFFFFFF, instance, restart), set meaning s = -1)
     for (int g = tid; g < n; g += kLatThreads) {
-        const int gz = g % L2, gy = (g / L2) % L1, gx = g / (L1 * L2);
-        s[g] = cs[((gx + gy + gz + Lt.c0) & 1) * half + (g >> 1)];
+        if (solve) {
+            s[g] = (int8_t)(rng_bit(seed, (uint32_t)g, 0xFFFFFFFFu, Lt.instance_id, (uint32_t)r) ? -1 : 1);
+        } else {
+            const int gz = g % L2, gy = (g / L2) % L1, gx = g / (L1 * L2);
+            s[g] = cs[((gx + gy + gz + Lt.c0) & 1) * half + (g >> 1)];
+        }
     }
     __shared__ int sweep_flips;
     if (tid == 0) sweep_flips = 0;
     __syncthreads();
-    const uint32_t base = (uint32_t)stp->sweeps;
+    const uint32_t base = solve ? 0u : (uint32_t)stp->sweeps;
     const uint32_t mL2 = fdiv_magic((uint32_t)L2), mL1 = fdiv_magic((uint32_t)L1);
     const int hz = L2 >> 1;  // sites of one colour per z row
     long long dE = 0, nflip = 0;
@@ -444,31 +453,128 @@ __global__ __launch_bounds__(kLatThreads) void k_lattice_wg(LatticeDev Lt, int8_
             lastflip = t + 1;
         }
     }
+    // a solve ends with the exact energy of the final spins (Sec. II eq. (1)):
+    // every site adds its field and its +x, +y, +z bonds, so each term counts once
+    long long Efin = 0;
     for (int g = tid; g < n; g += kLatThreads) {
         const int gz = g % L2, gy = (g / L2) % L1, gx = g / (L1 * L2);
         cs[((gx + gy + gz + Lt.c0) & 1) * half + (g >> 1)] = s[g];
+        if (solve) {
+            const uint64_t rc = Lt.rec[g];
+            const int yp = gy + 1 == L1 ? 0 : gy + 1, zp = gz + 1 == L2 ? 0 : gz + 1;
+            int f = jb(rc, 6) + jb(rc, 2) * s[(gx * L1 + yp) * L2 + gz] + jb(rc, 4) * s[(gx * L1 + gy) * L2 + zp];
+            if (D == 3) {
+                const int xp = gx + 1 == L0 ? 0 : gx + 1;
+                f += jb(rc, 0) * s[(xp * L1 + gy) * L2 + gz];
+            }
+            Efin -= (long long)(s[g] * f);
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         dE += __shfl_xor(dE, off, 64);
         nflip += __shfl_xor(nflip, off, 64);
+        Efin += __shfl_xor(Efin, off, 64);
     }
-    __shared__ long long pd[kLatWaves], pf[kLatWaves];
+    __shared__ long long pd[kLatWaves], pf[kLatWaves], pe[kLatWaves];
     if ((tid & 63) == 0) {
         pd[tid >> 6] = dE;
         pf[tid >> 6] = nflip;
+        pe[tid >> 6] = Efin;
     }
     __syncthreads();
     if (tid == 0) {
-        long long a = 0, b2 = 0;
+        long long a = 0, b2 = 0, e2 = 0;
         for (int w = 0; w < kLatWaves; ++w) {
             a += pd[w];
             b2 += pf[w];
+            e2 += pe[w];
         }
-        int64_t* ap = acc + 2 * ((int64_t)r * nslots);
-        ap[0] += a;
-        ap[1] += b2;
-        if (until_conv) stp->lastflip = lastflip;
+        if (solve) {
+            // the replica's state and the call totals as a start, this run
+            // and its end kernel leave them (sweeps: the first sweep without
+            // a flip counts)
+            int performed = T, conv = 0;
+            if (until_conv && lastflip < T) {
+                performed = lastflip + 1;
+                conv = 1;
+            }
+            RepState z;
+            z.E = e2;
+            z.flips = b2;
+            z.sweeps = performed;
+            z.lastflip = until_conv ? lastflip : 0;
+            z.converged = conv;
+            *stp = z;
+            CallStats* cs2 = sv.stats;
+            atomicAdd(&cs2->attempts, (unsigned long long)((long long)performed * n));
+            atomicAdd(&cs2->flips, (unsigned long long)b2);
+            atomicMax(&cs2->sweeps_max, (unsigned long long)performed);
+            if (until_conv && !conv) atomicAdd(&cs2->unconverged, 1ull);
+        } else {
+            int64_t* ap = acc + 2 * ((int64_t)r * nslots);
+            ap[0] += a;
+            ap[1] += b2;
+            if (until_conv) stp->lastflip = lastflip;
+        }
+    }
+    if (!solve) return;
+    // the workgroup that finishes last picks the best restart (lowest energy,
+    // lowest restart among equal energies) and copies the call totals out
+    __shared__ int is_last;
+    if (tid == 0) {
+        __threadfence();
+        is_last = atomicAdd(&sv.stats->done, 1ull) + 1 == sv.done_end;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    const int R = (int)gridDim.x;
+    long long bE = 0x7FFFFFFFFFFFFFFFll;
+    int bR = 0x7FFFFFFF;
+    for (int k = tid; k < R; k += kLatThreads) {  // restarts rise along a thread: the first of equal energies stays
+        const long long e = __hip_atomic_load(&rs[k].E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (e < bE) {
+            bE = e;
+            bR = k;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long e2 = __shfl_xor(bE, off, 64);
+        const int r2 = __shfl_xor(bR, off, 64);
+        if (e2 < bE || (e2 == bE && r2 < bR)) {
+            bE = e2;
+            bR = r2;
+        }
+    }
+    __shared__ long long wE[kLatWaves];
+    __shared__ int wR[kLatWaves];
+    if ((tid & 63) == 0) {
+        wE[tid >> 6] = bE;
+        wR[tid >> 6] = bR;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kLatWaves; ++w)
+            if (wE[w] < wE[0] || (wE[w] == wE[0] && wR[w] < wR[0])) {
+                wE[0] = wE[w];
+                wR[0] = wR[w];
+            }
+        *sv.best_E = wE[0];
+        *sv.best_r = wR[0];
+        if (sv.stats_out) {
+            CallStats c;
+            c.attempts = __hip_atomic_load(&sv.stats->attempts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c.flips = __hip_atomic_load(&sv.stats->flips, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c.sweeps_max = __hip_atomic_load(&sv.stats->sweeps_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c.unconverged = __hip_atomic_load(&sv.stats->unconverged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c.done = sv.done_end;
+            *sv.stats_out = c;
+            // every workgroup of the solve has counted: the totals start the
+            // next solve at zero
+            *sv.stats = CallStats{0ull, 0ull, 0ull, 0ull, 0ull};
+        }
     }
 }
 
@@ -568,29 +674,41 @@ int lattice_tiles_max_blocks(const TileGeom& tg, const int L[3], int D)
 }
 
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
-                             int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st)
+                             int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st,
+                             const WgSolve* solve_p)
 {
+    const int solve = solve_p ? 1 : 0;
+    const WgSolve sv = solve_p ? *solve_p : WgSolve{};
+    // the LDS size is raised once per kernel variant (a call per launch costs
+    // as much host time as the launch of a small lattice itself)
+    static std::atomic<size_t> lds_set[4];
     const size_t lds = ((size_t)Lt.n + 7) / 8 * 8;
     const bool tie = rule == 1;
     const void* kern;
     if (Lt.D == 3) kern = tie ? (const void*)k_lattice_wg<3, true> : (const void*)k_lattice_wg<3, false>;
     else kern = tie ? (const void*)k_lattice_wg<2, true> : (const void*)k_lattice_wg<2, false>;
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    std::atomic<size_t>& set = lds_set[(Lt.D == 3 ? 2 : 0) + (tie ? 1 : 0)];
+    if (lds > set.load(std::memory_order_relaxed)) {
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        size_t cur = set.load(std::memory_order_relaxed);
+        while (lds > cur && !set.compare_exchange_weak(cur, lds)) {
+        }
+    }
     if (Lt.D == 3) {
         if (tie)
             hipLaunchKernelGGL((k_lattice_wg<3, true>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs, acc,
-                               nslots, T, seed, until_conv);
+                               nslots, T, seed, until_conv, sv, solve);
         else
             hipLaunchKernelGGL((k_lattice_wg<3, false>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs,
-                               acc, nslots, T, seed, until_conv);
+                               acc, nslots, T, seed, until_conv, sv, solve);
     } else {
         if (tie)
             hipLaunchKernelGGL((k_lattice_wg<2, true>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs, acc,
-                               nslots, T, seed, until_conv);
+                               nslots, T, seed, until_conv, sv, solve);
         else
             hipLaunchKernelGGL((k_lattice_wg<2, false>), dim3(R), dim3(kLatThreads), lds, st, Lt, canon, stride, rs,
-                               acc, nslots, T, seed, until_conv);
+                               acc, nslots, T, seed, until_conv, sv, solve);
     }
     return hipGetLastError();
 }

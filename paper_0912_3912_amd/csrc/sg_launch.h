@@ -99,8 +99,24 @@ hipError_t launch_dense_init(const DenseTab* tabs, const BlockItem* items, int n
 hipError_t launch_dense_energy(const DenseTab* tabs, const BlockItem* items, int nitems, int64_t* out, hipStream_t st);
 hipError_t launch_dense_run(const DenseTab* tabs, const BlockItem* items, int nitems, int nmax, RepState* rs,
                             CallStats* cs, int rule, int max_sweeps, int until_conv, uint64_t seed, hipStream_t st);
+// One workgroup per replica of a small lattice.  With a WgSolve the launch is
+// a whole solve: it draws each replica's start (seed also keys the start),
+// runs the sweeps from sweep 0, and leaves the replica state (exact final
+// energy, counters, converged) and the call totals in stats as a start, a run
+// and its end kernel would (acc is then unused).  The workgroup that finishes
+// last (stats->done reaching done_end, counted over the launches of one
+// solve) writes the instance's best restart to best_E / best_r and, when
+// stats_out is given, a copy of the call totals there.
+struct WgSolve {
+    CallStats* stats;
+    int64_t* best_E;
+    int32_t* best_r;
+    CallStats* stats_out;
+    unsigned long long done_end;
+};
 hipError_t launch_lattice_wg(const LatticeDev& Lt, int8_t* canon, int64_t stride, RepState* rs, int R, int64_t* acc,
-                             int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st);
+                             int nslots, int T, uint64_t seed, int rule, int until_conv, hipStream_t st,
+                             const WgSolve* solve = nullptr);
 
 // batched schedules (sg_batch.hip)
 size_t block_lds_bytes(int n, int nbr_words, int tri_words, int nslices, int C, int RG);

@@ -95,6 +95,7 @@ struct CallStats {
     unsigned long long flips;
     unsigned long long sweeps_max;
     unsigned long long unconverged;
+    unsigned long long done;  // workgroups finished (the one-launch solve of small lattices)
 };
 
 // Lattice (implicit neighbour) layout for the LDS tile schedules.  Sites are

@@ -18,6 +18,7 @@
 #include "sg.h"
 
 sg_status sg_internal_fail(sg_status code, const char* msg);
+sg_status sg_internal_bind(sg_handle h, void* dev_ptr, uint64_t bytes, void* hip_stream, bool may_alloc);
 
 namespace {
 
@@ -72,5 +73,5 @@ extern "C" sg_status sg_bind_noalloc(sg_handle h, void* hip_stream)
     void* p = nullptr;
     s = scratch_address(&p);
     if (s != SG_OK) return s;
-    return sg_bind(h, p, kNoAllocBytes, hip_stream);
+    return sg_internal_bind(h, p, kNoAllocBytes, hip_stream, false);
 }

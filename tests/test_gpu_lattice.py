@@ -249,3 +249,84 @@ def test_cubic100_byte_kernel(gpu):
     inst = gen.cfg2_cubic100()
     h, st = _run([inst], [(100, 100, 100)], 7, TIE, 200, False, tune={"lattice_msc": 0})
     assert h.query("last_msc") == 0
+
+
+def _solve_check(insts, dims, seed, rule, sweeps, uc, tune=None, schedule=-1, then=None, one_launch=True):
+    """sg_solve (start, run and best in one call) against the oracle, and
+    against the three calls it stands for on a second handle: spins, energies,
+    counters, call totals and the best restart agree bit for bit; ``then``
+    continues both handles with one more run (resume after a solve)."""
+    import paper_0912_3912_amd as sg
+    log(f"solve case: {[i.name for i in insts]} rule={rule} sweeps={sweeps} uc={uc} tune={tune} "
+        f"schedule={schedule} then={then}")
+    hs = []
+    for _ in range(2):
+        h = sg.load_instance(insts, lattice_dims=dims)
+        for k, v in (tune or {}).items():
+            h.tune(k, v)
+        hs.append(h.bind())
+    st, Eb, rb = hs[0].solve(seed, rule=rule, max_sweeps=sweeps, until_converged=uc, schedule=schedule)
+    if one_launch:
+        assert hs[0].query("hot_launches") == len(insts)
+    hs[1].init_spins(seed)
+    st2 = hs[1].run_sweeps(seed=seed, rule=rule, max_sweeps=sweeps, until_converged=uc, schedule=schedule)
+    Eb2, rb2 = hs[1].best()
+    for k in ("attempts", "flips", "sweeps_max", "n_unconverged", "schedule_used", "status"):
+        assert st[k] == st2[k], k
+    assert np.array_equal(Eb, Eb2) and np.array_equal(rb, rb2)
+    runs = [sweeps] + ([then] if then is not None else [])
+    if then is not None:
+        for h in hs:
+            h.run_sweeps(seed=seed, rule=rule, max_sweeps=then, until_converged=uc, schedule=schedule)
+    states = [oracle_run(i, seed, rule, sweeps, uc, runs) for i in insts]
+    for h in hs:
+        compare(h, insts, states)
+    if then is None:
+        for q, s in enumerate(states):
+            assert Eb[q] == s.energy.min() and rb[q] == int(np.argmin(s.energy))
+    # a second solve on each handle (after a solve, and after a run) starts
+    # afresh and gives the first one's results again
+    for h in hs:
+        st3, Eb3, rb3 = h.solve(seed, rule=rule, max_sweeps=sweeps, until_converged=uc, schedule=schedule)
+        for k in ("attempts", "flips", "sweeps_max", "n_unconverged", "status"):
+            assert st3[k] == st[k], k
+        assert np.array_equal(Eb3, Eb) and np.array_equal(rb3, rb)
+        h.free()
+    return st
+
+
+def test_solve_square16(gpu):
+    st = _solve_check([gen.cfg1_square16()], [(16, 16)], 7, GREEDY, 10000, True)
+    assert st["n_unconverged"] == 0 and st["schedule_used"] == SCHED_LATTICE
+
+
+@pytest.mark.parametrize("rule,sweeps,uc", [(GREEDY, 10000, True), (TIE, 40, False), (TIE, 40, True),
+                                            (GREEDY, 0, True), (TIE, 0, False), (GREEDY, 3, True)])
+def test_solve_cubic(gpu, rule, sweeps, uc):
+    """3-D lattice with fields; no sweeps (start and energy only); a cap the
+    stopping rule does not reach (SG_ENOTCONV with every output written)."""
+    inst = gen.lattice((12, 10, 8), seed=5, h_range=(-2, 2), restarts=5)
+    st = _solve_check([inst], [(12, 10, 8)], 3, rule, sweeps, uc)
+    if rule == GREEDY and sweeps == 3:
+        assert st["status"] == 1 and st["n_unconverged"] > 0
+
+
+def test_solve_two_lattices_and_resume(gpu):
+    a = gen.cfg1_square16().replace(instance_id=4)
+    b = gen.lattice((8, 8, 6), seed=2, h_range=(-3, 3), restarts=9).replace(instance_id=5)
+    _solve_check([a, b], [(16, 16), (8, 8, 6)], 11, TIE, 25, False, then=17)
+    _solve_check([a, b], [(16, 16), (8, 8, 6)], 11, GREEDY, 4, False, then=200)
+
+
+@pytest.mark.parametrize("case", ["graph", "phase", "tiles"])
+def test_solve_other_schedules(gpu, case):
+    """Handles that the one-launch form does not take make the three calls."""
+    if case == "graph":
+        inst = gen.random_small(300, seed=3, p_edge=0.02, n_triples=40).replace(restarts=6, instance_id=8)
+        _solve_check([inst], None, 5, GREEDY, 10000, True, one_launch=False)
+    elif case == "phase":
+        inst = gen.lattice((8, 8, 8), seed=4, h_range=(-2, 2), restarts=3)
+        _solve_check([inst], [(8, 8, 8)], 5, TIE, 20, False, schedule=0, one_launch=False)
+    else:
+        inst = gen.lattice((16, 16, 16), seed=6, h_range=(-2, 2), restarts=2)
+        _solve_check([inst], [(16, 16, 16)], 5, TIE, 30, False, tune={"lattice_wg_max_n": 0}, one_launch=False)
