@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <atomic>
@@ -299,58 +300,168 @@ namespace {
 // ---------------------------------------------------------------------------
 // ingest
 
-struct Primal {  // primal adjacency (edges plus triple pairs), for colouring
-    std::vector<int64_t> start;
-    std::vector<int32_t> adj;
+// A host array that keeps its memory from one use to the next and is left
+// uninitialised when it grows: the large temporaries of an ingest reuse the
+// pages of the same thread's previous ingest instead of faulting in fresh
+// ones, and the threads that fill a grown array touch its pages in parallel.
+template <class T>
+struct Scratch {
+    std::unique_ptr<T[]> p;
+    size_t cap = 0;
+    T* get(size_t count)
+    {
+        if (count > cap) {
+            p.reset(new T[count]);
+            cap = count;
+        }
+        return p.get();
+    }
 };
 
-Primal build_primal(const sg_instance_desc& d)
+// Every term of an instance at each of its spins, grouped by spin (external
+// index) in input order, edges before triples: entry q of spin i (start[i] <=
+// q < start[i + 1]) names the term's other spin a[q] and, for a triple, its
+// third spin b[q] (-1 for an edge), with the term's coefficient c[q].  This is
+// the primal adjacency the colouring reads, and the source of the per-spin
+// sums, the duplicate check and the incidence lists.
+struct IncTerm {
+    int32_t a, b, c;
+};
+struct Incidence {
+    const int64_t* start = nullptr;
+    const IncTerm* e = nullptr;
+};
+
+struct IncEntry {
+    int32_t row, a, b, c;
+};
+
+// One thread's ingest temporaries (the arrays behind Incidence among them:
+// valid until that thread's next ingest).
+struct IngestScratch {
+    Scratch<int64_t> start, es, ts;
+    Scratch<int32_t> deg, tdeg;
+    Scratch<IncTerm> terms;
+    Scratch<IncEntry> bucket;
+    Scratch<uint32_t> ew, twa, twb, tmp, int_of;
+};
+
+IngestScratch& ingest_scratch()
 {
-    Primal P;
-    const int32_t n = d.n;
-    P.start.assign((size_t)n + 1, 0);
-    for (int64_t k = 0; k < d.m; ++k) {
-        P.start[d.ei[k] + 1]++;
-        P.start[d.ej[k] + 1]++;
-    }
-    for (int64_t k = 0; k < d.t; ++k)
-        for (int q = 0; q < 3; ++q) P.start[d.tri[3 * k + q] + 1] += 2;
-    for (int32_t i = 0; i < n; ++i) P.start[i + 1] += P.start[i];
-    P.adj.resize((size_t)P.start[n]);
-    std::vector<int64_t> fill(P.start.begin(), P.start.end() - 1);
-    // each thread fills the rows of its range, scanning every term in input
-    // order (the same lists as one pass over the terms)
-    parallel_ranges(n, [&](int64_t r0, int64_t r1) {
-        auto mine = [&](int32_t v) { return v >= r0 && v < r1; };
-        for (int64_t k = 0; k < d.m; ++k) {
-            const int32_t a = d.ei[k], b = d.ej[k];
-            if (mine(a)) P.adj[fill[a]++] = b;
-            if (mine(b)) P.adj[fill[b]++] = a;
+    thread_local IngestScratch s;
+    return s;
+}
+
+// Builds the incidences of an instance whose spin indices are all in range,
+// on up to kHostThreads threads: each thread sorts the incidences of its
+// range of terms into buckets by range of spins, then each thread gathers
+// the bucket of its spins in term order (so the result does not depend on
+// the thread count).
+void build_incidence(const sg_instance_desc& d, Incidence& I)
+{
+    const int64_t n = d.n, m = d.m, t = d.t, terms = m + t;
+    unsigned T = std::thread::hardware_concurrency();
+    T = std::min(T ? T : 1u, kHostThreads);
+    if (terms < 65536) T = 1;
+    // range r holds the spins i with i * T / n == r: [lo(r), lo(r + 1))
+    auto dest = [&](int64_t row) { return (size_t)(row * (int64_t)T / n); };
+    auto lo = [&](int64_t r) { return (n * r + (int64_t)T - 1) / (int64_t)T; };
+    // the incidences of term k: (spin, other, third, coefficient)
+    auto visit = [&](int64_t k, auto&& out) {
+        if (k < m) {
+            const int32_t x = d.ei[k], y = d.ej[k];
+            out(x, y, -1, d.J[k]);
+            out(y, x, -1, d.J[k]);
+        } else {
+            const int64_t u = k - m;
+            const int32_t x = d.tri[3 * u], y = d.tri[3 * u + 1], z = d.tri[3 * u + 2];
+            out(x, y, z, d.K[u]);
+            out(y, x, z, d.K[u]);
+            out(z, x, y, d.K[u]);
         }
-        for (int64_t k = 0; k < d.t; ++k) {
-            const int32_t a = d.tri[3 * k], b = d.tri[3 * k + 1], c = d.tri[3 * k + 2];
-            if (mine(a)) { P.adj[fill[a]++] = b; P.adj[fill[a]++] = c; }
-            if (mine(b)) { P.adj[fill[b]++] = a; P.adj[fill[b]++] = c; }
-            if (mine(c)) { P.adj[fill[c]++] = a; P.adj[fill[c]++] = b; }
+    };
+    auto run = [&](auto&& body) {
+        std::vector<std::thread> th;
+        for (unsigned x = 1; x < T; ++x) th.emplace_back([&body, x] { body(x); });
+        body(0u);
+        for (std::thread& y : th) y.join();
+    };
+    auto chunk = [&](unsigned sidx, int64_t& k0, int64_t& k1) {
+        k0 = terms * sidx / T;
+        k1 = terms * (sidx + 1) / T;
+    };
+    std::vector<std::vector<int64_t>> at(T, std::vector<int64_t>(T, 0));
+    run([&](unsigned sidx) {
+        int64_t k0, k1;
+        chunk(sidx, k0, k1);
+        std::vector<int64_t>& c = at[sidx];
+        for (int64_t k = k0; k < k1; ++k) visit(k, [&](int32_t row, int32_t, int32_t, int32_t) { c[dest(row)]++; });
+    });
+    // bucket r (entries base[r] .. base[r + 1] - 1): the entries of term
+    // ranges 0, 1, ... in turn
+    IngestScratch& S = ingest_scratch();
+    std::vector<int64_t> base(T + 1, 0);
+    for (unsigned r = 0; r < T; ++r) {
+        int64_t size = 0;
+        for (unsigned x = 0; x < T; ++x) {
+            const int64_t c = at[x][r];
+            at[x][r] = base[r] + size;
+            size += c;
+        }
+        base[r + 1] = base[r] + size;
+    }
+    IncEntry* bucket = S.bucket.get(std::max<size_t>((size_t)base[T], 1));
+    run([&](unsigned sidx) {
+        int64_t k0, k1;
+        chunk(sidx, k0, k1);
+        std::vector<int64_t>& o = at[sidx];
+        for (int64_t k = k0; k < k1; ++k)
+            visit(k, [&](int32_t row, int32_t a, int32_t b, int32_t c) {
+                const size_t r = dest(row);
+                bucket[(size_t)o[r]++] = IncEntry{row, a, b, c};
+            });
+    });
+    // per range: its spins' counts, offsets (its entries start at base[r]),
+    // then its entries in bucket order
+    const size_t total = std::max<size_t>((size_t)base[T], 1);
+    int64_t* start = S.start.get((size_t)n + 1);
+    IncTerm* E = S.terms.get(total);
+    run([&](unsigned r) {
+        const int64_t r0 = lo(r), r1 = lo(r + 1);
+        for (int64_t i = r0; i < r1; ++i) start[i + 1] = 0;
+        if (r == 0) start[0] = 0;
+        for (int64_t k = base[r]; k < base[r + 1]; ++k) start[bucket[k].row + 1]++;
+        int64_t acc = base[r];
+        for (int64_t i = r0; i < r1; ++i) {
+            const int64_t c = start[i + 1];
+            start[i + 1] = acc;  // fill position of spin i, then its end
+            acc += c;
+        }
+        for (int64_t k = base[r]; k < base[r + 1]; ++k) {
+            const IncEntry& e = bucket[k];
+            E[start[e.row + 1]++] = IncTerm{e.a, e.b, e.c};
         }
     });
-    return P;
+    I.start = start;
+    I.e = E;
 }
 
 // First-fit: spin i takes the smallest colour unused by primal neighbours j < i.
-int32_t first_fit(const Primal& P, int32_t n, std::vector<int32_t>& colour)
+int32_t first_fit(const Incidence& P, int32_t n, std::vector<int32_t>& colour)
 {
     colour.assign((size_t)n, 0);
     std::vector<int32_t> seen;  // seen[c] == i + 1 when colour c is taken by a lower neighbour of i
     int32_t ncol = 0;
+    auto mark = [&](int32_t j, int32_t i) {
+        if (j < 0 || j >= i) return;
+        const int32_t c = colour[j];
+        if ((size_t)c >= seen.size()) seen.resize((size_t)c + 1, 0);
+        seen[c] = i + 1;
+    };
     for (int32_t i = 0; i < n; ++i) {
         for (int64_t q = P.start[i]; q < P.start[i + 1]; ++q) {
-            const int32_t j = P.adj[q];
-            if (j < i) {
-                const int32_t c = colour[j];
-                if ((size_t)c >= seen.size()) seen.resize((size_t)c + 1, 0);
-                seen[c] = i + 1;
-            }
+            mark(P.e[q].a, i);
+            mark(P.e[q].b, i);
         }
         int32_t c = 0;
         while ((size_t)c < seen.size() && seen[c] == i + 1) ++c;
@@ -404,7 +515,7 @@ class CopiesOut {
 // |h_i| + sum|J_ij| + sum|K| exceeds 2^31 - 1 (its field would not fit int32),
 // when sum|J| + sum|h| + sum|K| exceeds 2^63 - 1 (an energy would not fit
 // int64), or when n exceeds 2^30 (index arithmetic).
-sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
+sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr, Incidence* inc = nullptr)
 {
     bool w = false;
     if (d.n < 1) return fail(SG_EINVAL, "instance %d: n must be >= 1", idx);
@@ -416,8 +527,6 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
     if (d.restarts < 1) return fail(SG_EINVAL, "instance %d: restarts must be >= 1", idx);
     if (d.restarts > kMaxRestarts) w = true;
     const int64_t n = d.n;
-    std::vector<int64_t> field((size_t)n, 0);
-    std::vector<int64_t> bstart((size_t)n + 1, 0);  // edges bucketed by their smaller endpoint
     __int128 total = 0;  // sum |J| + sum |h| + sum |K|
     {
         // indices, self-loops, coefficient sizes and the total, by ranges of edges
@@ -453,81 +562,89 @@ sg_status validate(const sg_instance_desc& d, int idx, bool* wide = nullptr)
             total += part[t];
             w = w || big[t];
         }
-        // per-spin sums and bucket sizes, by ranges of spins
-        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
-            for (int64_t k = 0; k < d.m; ++k) {
-                const int64_t a = d.ei[k], b = d.ej[k];
-                const int64_t c = std::llabs((int64_t)d.J[k]);
-                if (a >= r0 && a < r1) field[a] += c;
-                if (b >= r0 && b < r1) field[b] += c;
-                const int64_t lo = std::min(a, b);
-                if (lo >= r0 && lo < r1) bstart[(size_t)lo + 1]++;
-            }
-        });
     }
     {
-        // duplicate pairs: a counting sort by the smaller endpoint, then each
-        // bucket's larger endpoints sorted (buckets are short)
-        for (int64_t i = 0; i < n; ++i) bstart[(size_t)i + 1] += bstart[(size_t)i];
-        std::vector<int32_t> other((size_t)d.m);
-        std::vector<int64_t> at(bstart.begin(), bstart.end() - 1);
-        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
-            for (int64_t k = 0; k < d.m; ++k) {
-                const int32_t a = d.ei[k], b = d.ej[k], lo = std::min(a, b);
-                if (lo >= r0 && lo < r1) other[(size_t)at[(size_t)lo]++] = std::max(a, b);
-            }
-        });
-        std::vector<int64_t> dup_row(kHostThreads, -1);
+        // triples: indices, repeated spins, sizes, duplicates
+        std::vector<std::array<int32_t, 3>> tk((size_t)d.t);
+        for (int64_t k = 0; k < d.t; ++k) {
+            std::array<int32_t, 3> v = {d.tri[3 * k], d.tri[3 * k + 1], d.tri[3 * k + 2]};
+            for (int q = 0; q < 3; ++q)
+                if (v[q] < 0 || v[q] >= n)
+                    return fail(SG_EINVAL, "instance %d: triple %lld has a spin index out of range", idx,
+                                (long long)k);
+            if (v[0] == v[1] || v[0] == v[2] || v[1] == v[2])
+                return fail(SG_EINVAL, "instance %d: triple %lld repeats a spin", idx, (long long)k);
+            const int64_t c = std::llabs((int64_t)d.K[k]);
+            if (c > kMaxCoef) w = true;
+            total += c;
+            std::sort(v.begin(), v.end());
+            tk[k] = v;
+        }
+        std::sort(tk.begin(), tk.end());
+        for (size_t k = 1; k < tk.size(); ++k)
+            if (tk[k] == tk[k - 1])
+                return fail(SG_EINVAL, "instance %d: triple (%d,%d,%d) given twice", idx, tk[k][0], tk[k][1],
+                            tk[k][2]);
+    }
+    // every index is in range: the terms at each spin
+    Incidence local;
+    Incidence& I = inc ? *inc : local;
+    build_incidence(d, I);  // this thread's scratch
+    {
+        // per spin: |h| + sum |coefficients| against the limits, and the
+        // spin's edges to larger spins checked for a pair given twice
+        std::vector<int64_t> dup_row(kHostThreads, -1), over_row(kHostThreads, -1), over_val(kHostThreads, 0);
         std::vector<int32_t> dup_col(kHostThreads, 0);
+        std::vector<__int128> hpart(kHostThreads, 0);
+        std::vector<char> big(kHostThreads, 0);
         parallel_ranges(n, [&](int64_t r0, int64_t r1) {
             const size_t slot = (size_t)(r0 * kHostThreads / std::max<int64_t>(n, 1));
+            std::vector<int32_t> up;
+            __int128 hs = 0;
+            bool wf = false;
             for (int64_t i = r0; i < r1; ++i) {
-                auto lo = other.begin() + bstart[(size_t)i], hi = other.begin() + bstart[(size_t)i + 1];
-                if (hi - lo < 2) continue;
-                std::sort(lo, hi);
-                for (auto it = lo + 1; it < hi; ++it)
-                    if (*it == *(it - 1)) {
-                        dup_row[slot] = i;
-                        dup_col[slot] = *it;
-                        return;
-                    }
+                int64_t f = 0;
+                up.clear();
+                for (int64_t q = I.start[(size_t)i]; q < I.start[(size_t)i + 1]; ++q) {
+                    f += std::llabs((int64_t)I.e[(size_t)q].c);
+                    if (I.e[(size_t)q].b < 0 && I.e[(size_t)q].a > i) up.push_back(I.e[(size_t)q].a);
+                }
+                if (d.h) {
+                    const int64_t c = std::llabs((int64_t)d.h[i]);
+                    wf = wf || c > kMaxCoef;
+                    f += c;
+                    hs += c;
+                }
+                wf = wf || f > kMaxField;
+                if (f > kMaxWideField && over_row[slot] < 0) {
+                    over_row[slot] = i;
+                    over_val[slot] = f;
+                }
+                if (up.size() > 1 && dup_row[slot] < 0) {
+                    std::sort(up.begin(), up.end());
+                    for (size_t k = 1; k < up.size(); ++k)
+                        if (up[k] == up[k - 1]) {
+                            dup_row[slot] = i;
+                            dup_col[slot] = up[k];
+                            break;
+                        }
+                }
             }
+            hpart[slot] = hs;
+            big[slot] = wf;
         });
         for (size_t t = 0; t < dup_row.size(); ++t)
             if (dup_row[t] >= 0)
                 return fail(SG_EINVAL, "instance %d: edge (%lld,%d) given twice", idx, (long long)dup_row[t],
                             dup_col[t]);
-    }
-    std::vector<std::array<int32_t, 3>> tk((size_t)d.t);
-    for (int64_t k = 0; k < d.t; ++k) {
-        std::array<int32_t, 3> v = {d.tri[3 * k], d.tri[3 * k + 1], d.tri[3 * k + 2]};
-        for (int q = 0; q < 3; ++q)
-            if (v[q] < 0 || v[q] >= n)
-                return fail(SG_EINVAL, "instance %d: triple %lld has a spin index out of range", idx, (long long)k);
-        if (v[0] == v[1] || v[0] == v[2] || v[1] == v[2])
-            return fail(SG_EINVAL, "instance %d: triple %lld repeats a spin", idx, (long long)k);
-        const int64_t c = std::llabs((int64_t)d.K[k]);
-        if (c > kMaxCoef) w = true;
-        std::sort(v.begin(), v.end());
-        tk[k] = v;
-        for (int q = 0; q < 3; ++q) field[v[q]] += c;
-        total += c;
-    }
-    std::sort(tk.begin(), tk.end());
-    for (size_t k = 1; k < tk.size(); ++k)
-        if (tk[k] == tk[k - 1])
-            return fail(SG_EINVAL, "instance %d: triple (%d,%d,%d) given twice", idx, tk[k][0], tk[k][1], tk[k][2]);
-    for (int64_t i = 0; i < n; ++i) {
-        if (d.h) {
-            const int64_t c = std::llabs((int64_t)d.h[i]);
-            if (c > kMaxCoef) w = true;
-            field[i] += c;
-            total += c;
+        for (size_t t = 0; t < over_row.size(); ++t)
+            if (over_row[t] >= 0)
+                return fail(SG_ERANGE, "instance %d: spin %lld has |h|+sum|J|+sum|K| = %lld > %lld", idx,
+                            (long long)over_row[t], (long long)over_val[t], (long long)kMaxWideField);
+        for (size_t t = 0; t < hpart.size(); ++t) {
+            total += hpart[t];
+            w = w || big[t];
         }
-        if (field[i] > kMaxWideField)
-            return fail(SG_ERANGE, "instance %d: spin %lld has |h|+sum|J|+sum|K| = %lld > %lld", idx, (long long)i,
-                        (long long)field[i], (long long)kMaxWideField);
-        if (field[i] > kMaxField) w = true;
     }
     if (total > (__int128)INT64_MAX)
         return fail(SG_ERANGE, "instance %d: sum|J| + sum|h| + sum|K| exceeds 2^63 - 1", idx);
@@ -581,7 +698,7 @@ sg_status check_lattice(const sg_instance_desc& d, int idx)
 // every extent is even, the colouring is the checkerboard and the
 // colour-major relabel put site g at internal index colour(g)*n/2 + g/2 (true
 // for the uniform-degree lattice); otherwise those schedules stay off.
-void build_lattice(const sg_instance_desc& d, HostInst& q, const std::vector<uint32_t>& int_of)
+void build_lattice(const sg_instance_desc& d, HostInst& q, const uint32_t* int_of)
 {
     const int dim = d.dims[2] ? 3 : 2;
     int32_t L[3];
@@ -745,13 +862,14 @@ sg_status ingest_dense(const sg_dense_desc& d, int idx, HostInst& q)
     return SG_OK;
 }
 
-sg_status ingest_wide(const sg_instance_desc& d, int idx, HostInst& q, const std::vector<uint32_t>& int_of,
-                      const std::vector<int64_t>& es, const std::vector<int64_t>& ts);
+sg_status ingest_wide(const sg_instance_desc& d, int idx, HostInst& q, const Incidence& P, const uint32_t* int_of,
+                      const int64_t* es, const int64_t* ts);
 
 sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
 {
     bool wide = false;
-    sg_status st = validate(d, idx, &wide);
+    Incidence P;
+    sg_status st = validate(d, idx, &wide, &P);
     if (st != SG_OK) return st;
     q.n = d.n;
     q.m = d.m;
@@ -765,7 +883,6 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
         for (int a = 0; a < 3; ++a) q.dims[a] = d.dims[a];
     }
     const int32_t n = d.n;
-    Primal P = build_primal(d);
     if (d.colour) {
         q.colour.assign(d.colour, d.colour + n);
         int32_t mx = -1;
@@ -775,21 +892,28 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
         }
         for (int32_t i = 0; i < n; ++i)
             for (int64_t k = P.start[i]; k < P.start[i + 1]; ++k)
-                if (q.colour[P.adj[k]] == q.colour[i])
-                    return fail(SG_EINVAL, "instance %d: colouring is not proper (spins %d and %d share colour %d)",
-                                idx, i, P.adj[k], q.colour[i]);
+                for (const int32_t j : {P.e[k].a, P.e[k].b})
+                    if (j >= 0 && q.colour[j] == q.colour[i])
+                        return fail(SG_EINVAL,
+                                    "instance %d: colouring is not proper (spins %d and %d share colour %d)", idx, i,
+                                    j, q.colour[i]);
         q.C = mx + 1;
     } else {
         q.C = first_fit(P, n, q.colour);
     }
 
-    // incidence counts
-    std::vector<int32_t> deg((size_t)n, 0), tdeg((size_t)n, 0);
-    for (int64_t k = 0; k < d.m; ++k) {
-        deg[d.ei[k]]++;
-        deg[d.ej[k]]++;
-    }
-    for (int64_t k = 0; k < 3 * d.t; ++k) tdeg[d.tri[k]]++;
+    // incidence counts (a spin's edges come before its triples)
+    IngestScratch& S = ingest_scratch();
+    int32_t* deg = S.deg.get((size_t)n);
+    int32_t* tdeg = S.tdeg.get((size_t)n);
+    parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+        for (int64_t i = r0; i < r1; ++i) {
+            int32_t ne = 0;
+            for (int64_t k = P.start[i]; k < P.start[i + 1] && P.e[k].b < 0; ++k) ++ne;
+            deg[i] = ne;
+            tdeg[i] = (int32_t)(P.start[i + 1] - P.start[i]) - ne;
+        }
+    });
     for (int32_t i = 0; i < n && !wide; ++i) wide = deg[i] > 65535 || tdeg[i] > 255;
     if (q.C > 65535) wide = true;
     q.wide = wide ? 1 : 0;
@@ -800,28 +924,36 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
         // order (colour ascending, couplings descending, triples descending,
         // index ascending) by three stable counting sorts, least significant
         // key first
-        std::vector<uint32_t> tmp((size_t)n);
-        auto pass = [&](auto key, int64_t kmax) {
+        uint32_t* cur = q.ext_of.data();
+        uint32_t* nxt = S.tmp.get((size_t)n);
+        auto pass = [&](auto key, int64_t kmax, bool constant) {
+            if (constant) return;  // one key value: the stable order stays
             std::vector<int64_t> cnt((size_t)kmax + 2, 0);
-            for (int32_t k = 0; k < n; ++k) cnt[(size_t)key(q.ext_of[k]) + 1]++;
+            for (int32_t k = 0; k < n; ++k) cnt[(size_t)key(cur[k]) + 1]++;
             for (int64_t v = 0; v <= kmax; ++v) cnt[(size_t)v + 1] += cnt[(size_t)v];
-            for (int32_t k = 0; k < n; ++k) tmp[(size_t)cnt[(size_t)key(q.ext_of[k])]++] = q.ext_of[k];
-            q.ext_of.swap(tmp);
+            for (int32_t k = 0; k < n; ++k) nxt[(size_t)cnt[(size_t)key(cur[k])]++] = cur[k];
+            std::swap(cur, nxt);
         };
-        int64_t dmax = 0, tmax = 0;
+        int64_t dmax = 0, tmax = 0, dmin = INT64_MAX, tmin = INT64_MAX;
         for (int32_t i = 0; i < n; ++i) {
             dmax = std::max<int64_t>(dmax, deg[i]);
             tmax = std::max<int64_t>(tmax, tdeg[i]);
+            dmin = std::min<int64_t>(dmin, deg[i]);
+            tmin = std::min<int64_t>(tmin, tdeg[i]);
         }
-        pass([&](uint32_t i) { return tmax - tdeg[i]; }, tmax);
-        pass([&](uint32_t i) { return dmax - deg[i]; }, dmax);
-        pass([&](uint32_t i) { return (int64_t)q.colour[i]; }, (int64_t)q.C - 1);
+        pass([&](uint32_t i) { return tmax - tdeg[i]; }, tmax, tmin == tmax);
+        pass([&](uint32_t i) { return dmax - deg[i]; }, dmax, dmin == dmax);
+        pass([&](uint32_t i) { return (int64_t)q.colour[i]; }, (int64_t)q.C - 1, q.C == 1);
+        if (cur != q.ext_of.data()) std::memcpy(q.ext_of.data(), cur, (size_t)n * 4);
     }
-    std::vector<uint32_t> int_of((size_t)n);
+    uint32_t* int_of = S.int_of.get((size_t)n);
     for (int32_t i = 0; i < n; ++i) int_of[q.ext_of[i]] = (uint32_t)i;
 
     // incidence lists in internal numbering
-    std::vector<int64_t> es((size_t)n + 1, 0), ts((size_t)n + 1, 0);
+    int64_t* es = S.es.get((size_t)n + 1);
+    int64_t* ts = S.ts.get((size_t)n + 1);
+    es[0] = 0;
+    ts[0] = 0;
     for (int32_t i = 0; i < n; ++i) {
         es[int_of[i] + 1] = deg[i];
         ts[int_of[i] + 1] = tdeg[i];
@@ -830,33 +962,34 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
         es[i + 1] += es[i];
         ts[i + 1] += ts[i];
     }
-    if (q.wide) return ingest_wide(d, idx, q, int_of, es, ts);
-    std::vector<uint32_t> ew((size_t)es[n]), twa((size_t)ts[n]), twb((size_t)ts[n]);
+    if (q.wide) return ingest_wide(d, idx, q, P, int_of, es, ts);
+    uint32_t* ew = S.ew.get(std::max<size_t>((size_t)es[n], 1));
+    uint32_t* twa = S.twa.get(std::max<size_t>((size_t)ts[n], 1));
+    uint32_t* twb = S.twb.get(std::max<size_t>((size_t)ts[n], 1));
     {
-        std::vector<int64_t> fe(es.begin(), es.end() - 1), ft(ts.begin(), ts.end() - 1);
-        // each thread fills and sorts the rows of its range, scanning every
-        // term (rows in internal numbering)
+        // each thread writes the rows of its spins (external range) in
+        // internal numbering, then sorts the internal rows of its range
         parallel_ranges(n, [&](int64_t r0, int64_t r1) {
-            auto mine = [&](uint32_t v) { return (int64_t)v >= r0 && (int64_t)v < r1; };
-            for (int64_t k = 0; k < d.m; ++k) {
-                const uint32_t a = int_of[d.ei[k]], b = int_of[d.ej[k]];
-                const uint32_t jb = (uint32_t)(uint8_t)(int8_t)d.J[k];
-                if (mine(a)) ew[fe[a]++] = (b << 8) | jb;
-                if (mine(b)) ew[fe[b]++] = (a << 8) | jb;
-            }
-            for (int64_t k = 0; k < d.t; ++k) {
-                const uint32_t v[3] = {int_of[d.tri[3 * k]], int_of[d.tri[3 * k + 1]], int_of[d.tri[3 * k + 2]]};
-                const uint32_t kb = (uint32_t)(uint8_t)(int8_t)d.K[k];
-                for (int s = 0; s < 3; ++s) {
-                    if (!mine(v[s])) continue;
-                    const uint32_t o1 = v[(s + 1) % 3], o2 = v[(s + 2) % 3];
-                    twa[ft[v[s]]] = (std::min(o1, o2) << 8) | kb;
-                    twb[ft[v[s]]++] = std::max(o1, o2);
+            for (int64_t x = r0; x < r1; ++x) {
+                const uint32_t ix = int_of[x];
+                int64_t fe = es[ix], ft = ts[ix];
+                for (int64_t k = P.start[x]; k < P.start[x + 1]; ++k) {
+                    const uint32_t cb = (uint32_t)(uint8_t)(int8_t)P.e[k].c;
+                    const uint32_t o1 = int_of[P.e[k].a];
+                    if (P.e[k].b < 0) {
+                        ew[fe++] = (o1 << 8) | cb;
+                    } else {
+                        const uint32_t o2 = int_of[P.e[k].b];
+                        twa[ft] = (std::min(o1, o2) << 8) | cb;
+                        twb[ft++] = std::max(o1, o2);
+                    }
                 }
             }
+        });
+        parallel_ranges(n, [&](int64_t r0, int64_t r1) {
             std::vector<std::pair<uint32_t, uint32_t>> tmp;
             for (int64_t i = r0; i < r1; ++i) {
-                std::sort(ew.begin() + es[i], ew.begin() + es[i + 1]);
+                std::sort(ew + es[i], ew + es[i + 1]);
                 // order triple entries of a row by partner (pairs sorted together)
                 if (ts[i + 1] - ts[i] < 2) continue;
                 tmp.clear();
@@ -982,31 +1115,31 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
 // The wide form: the rows of the packed form with the partner index and the
 // coefficient in separate 32-bit words (int_of, es, ts: the relabel and the
 // per-row incidence offsets in internal numbering).
-sg_status ingest_wide(const sg_instance_desc& d, int idx, HostInst& q, const std::vector<uint32_t>& int_of,
-                      const std::vector<int64_t>& es, const std::vector<int64_t>& ts)
+sg_status ingest_wide(const sg_instance_desc& d, int idx, HostInst& q, const Incidence& P, const uint32_t* int_of,
+                      const int64_t* es, const int64_t* ts)
 {
     const int32_t n = d.n;
     std::vector<uint32_t> wp((size_t)es[n]), wa((size_t)ts[n]), wb((size_t)ts[n]);
     std::vector<int32_t> wj((size_t)es[n]), wk((size_t)ts[n]);
-    {
-        std::vector<int64_t> fe(es.begin(), es.end() - 1), ft(ts.begin(), ts.end() - 1);
-        for (int64_t k = 0; k < d.m; ++k) {
-            const uint32_t a = int_of[d.ei[k]], b = int_of[d.ej[k]];
-            wp[fe[a]] = b;
-            wj[fe[a]++] = d.J[k];
-            wp[fe[b]] = a;
-            wj[fe[b]++] = d.J[k];
-        }
-        for (int64_t k = 0; k < d.t; ++k) {
-            const uint32_t v[3] = {int_of[d.tri[3 * k]], int_of[d.tri[3 * k + 1]], int_of[d.tri[3 * k + 2]]};
-            for (int s = 0; s < 3; ++s) {
-                const uint32_t o1 = v[(s + 1) % 3], o2 = v[(s + 2) % 3];
-                wa[ft[v[s]]] = std::min(o1, o2);
-                wb[ft[v[s]]] = std::max(o1, o2);
-                wk[ft[v[s]]++] = d.K[k];
+    // each spin's terms in input order, in internal numbering
+    parallel_ranges(n, [&](int64_t r0, int64_t r1) {
+        for (int64_t x = r0; x < r1; ++x) {
+            const uint32_t ix = int_of[x];
+            int64_t fe = es[ix], ft = ts[ix];
+            for (int64_t k = P.start[x]; k < P.start[x + 1]; ++k) {
+                const uint32_t o1 = int_of[P.e[k].a];
+                if (P.e[k].b < 0) {
+                    wp[fe] = o1;
+                    wj[fe++] = P.e[k].c;
+                } else {
+                    const uint32_t o2 = int_of[P.e[k].b];
+                    wa[ft] = std::min(o1, o2);
+                    wb[ft] = std::max(o1, o2);
+                    wk[ft++] = P.e[k].c;
+                }
             }
         }
-    }
+    });
     q.w_h.assign((size_t)n, 0);
     if (d.h)
         for (int32_t i = 0; i < n; ++i) q.w_h[int_of[i]] = d.h[i];
