@@ -755,29 +755,26 @@ void build_lattice(const sg_instance_desc& d, HostInst& q, const uint32_t* int_o
         }
     });
     q.lat_rec.assign((size_t)n, 0);
+    // with the records, whether the bit-plane form holds: every bond of the
+    // lattice present with J = +-1, |h| <= 2
+    std::atomic<bool> msc{true};
     sites([&](int32_t g, const int32_t* c) {
         uint64_t rc = 0;
+        bool ok1 = true;
         for (int ax = 3 - dim; ax < 3; ++ax) {
             const int32_t down = c[ax] == 0 ? g + (L[ax] - 1) * stride[ax] : g - stride[ax];
-            rc |= (uint64_t)(uint8_t)bondJ[(size_t)g * 3 + ax] << (8 * (2 * ax));
-            rc |= (uint64_t)(uint8_t)bondJ[(size_t)down * 3 + ax] << (8 * (2 * ax + 1));
+            const int up_j = bondJ[(size_t)g * 3 + ax], down_j = bondJ[(size_t)down * 3 + ax];
+            rc |= (uint64_t)(uint8_t)up_j << (8 * (2 * ax));
+            rc |= (uint64_t)(uint8_t)down_j << (8 * (2 * ax + 1));
+            ok1 = ok1 && (up_j == 1 || up_j == -1) && (down_j == 1 || down_j == -1);
         }
-        if (d.h) rc |= (uint64_t)(uint8_t)(int8_t)d.h[g] << 48;
+        const int hv = d.h ? (int)(int8_t)d.h[g] : 0;
+        rc |= (uint64_t)(uint8_t)(int8_t)hv << 48;
         q.lat_rec[g] = rc;
+        if (!ok1 || hv < -2 || hv > 2) msc.store(false, std::memory_order_relaxed);
         return true;
     });
-    // bit-plane form: every bond of the lattice present with J = +-1, |h| <= 2
-    q.lat_msc = 1;
-    for (int32_t g = 0; g < n && q.lat_msc; ++g) {
-        const uint64_t rc = q.lat_rec[g];
-        for (int ax = 3 - dim; ax < 3; ++ax)
-            for (int side = 0; side < 2; ++side) {
-                const int v = (int)(int8_t)(rc >> (8 * (2 * ax + side)));
-                if (v != 1 && v != -1) q.lat_msc = 0;
-            }
-        const int hv = (int)(int8_t)(rc >> 48);
-        if (hv < -2 || hv > 2) q.lat_msc = 0;
-    }
+    q.lat_msc = msc.load() ? 1 : 0;
     for (int a = 0; a < 3; ++a) q.lat_L[a] = L[a];
     q.lat_D = dim;
     q.lat_c0 = c0;
@@ -898,6 +895,26 @@ sg_status ingest(const sg_instance_desc& d, int idx, HostInst& q)
                                     "instance %d: colouring is not proper (spins %d and %d share colour %d)", idx, i,
                                     j, q.colour[i]);
         q.C = mx + 1;
+    } else if (q.lattice && d.t == 0 && d.dims[0] % 2 == 0 && d.dims[1] % 2 == 0 && d.dims[2] % 2 == 0) {
+        // a periodic lattice with even extents (each >= 4) is bipartite, and
+        // every site but the origin has a lower neighbour, so first-fit in
+        // index order gives the checkerboard: colour (x + y + z) mod 2
+        q.colour.resize((size_t)n);
+        const int32_t L1 = d.dims[2] ? d.dims[1] : d.dims[0], L2 = d.dims[2] ? d.dims[2] : d.dims[1];
+        parallel_ranges(n, [&](int64_t g0, int64_t g1) {
+            int32_t z = (int32_t)(g0 % L2), y = (int32_t)((g0 / L2) % L1), x = (int32_t)(g0 / ((int64_t)L1 * L2));
+            for (int64_t g = g0; g < g1; ++g) {
+                q.colour[(size_t)g] = (x + y + z) & 1;
+                if (++z == L2) {
+                    z = 0;
+                    if (++y == L1) {
+                        y = 0;
+                        ++x;
+                    }
+                }
+            }
+        });
+        q.C = 2;
     } else {
         q.C = first_fit(P, n, q.colour);
     }

@@ -138,6 +138,17 @@ def test_first_fit_matches_oracle(sg, inst):
     assert oracle.colouring_is_proper(inst, info["colour"])
 
 
+@pytest.mark.parametrize("dims", [(8, 6), (4, 10), (5, 7), (6, 4, 8), (4, 4, 4), (5, 6, 4), (10, 12, 14)])
+def test_first_fit_matches_oracle_with_lattice_hint(sg, dims):
+    """With the lattice hint, even extents take the checkerboard directly; it
+    must be the first-fit colouring in index order (odd extents run first-fit)."""
+    inst = gen.lattice(dims, seed=2, h_range=(-2, 2)).replace(colour=None)
+    info = sg.load_instance([inst], lattice_dims=[dims]).info(0)
+    ref = oracle.first_fit_colouring(inst)
+    assert np.array_equal(info["colour"], ref)
+    assert info["colours"] == int(ref.max()) + 1
+
+
 def test_given_colouring_is_kept(sg):
     inst = gen.lattice((8, 8), seed=1)
     col = 1 - inst.colour  # the other checkerboard
