@@ -287,7 +287,7 @@ def test_chimera_4096x256_full(gpu):
     log("oracle done")
     compare(h, insts, states)
     E, r = h.best()
-    for q in (0, 1, 4095):
+    for q in range(len(insts)):
         assert E[q] == states[q].energy.min() and r[q] == int(np.argmin(states[q].energy))
 
 
