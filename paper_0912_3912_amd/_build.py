@@ -48,25 +48,25 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libsg.so (always recompiles)."""
     os.makedirs(OBJDIR, exist_ok=True)
     tag = "%d" % os.getpid()
+    objs = [os.path.join(OBJDIR, src.replace(".", "_") + "." + tag + ".o") for src in SOURCES]
 
-    def compile_one(src: str) -> str:
-        obj = os.path.join(OBJDIR, src.replace(".", "_") + "." + tag + ".o")
+    def compile_one(src: str, obj: str) -> None:
         cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        return obj
 
-    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp" + tag
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
     try:
+        with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+            list(ex.map(compile_one, SOURCES, objs))
+        cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
     finally:
+        # this build's objects go whether it succeeded or not
         for o in objs:
             try:
                 os.remove(o)
