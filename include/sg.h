@@ -72,8 +72,11 @@ enum {
      * SP*.  until_converged: stop after the first pass that leaves the energy
      * unchanged (it counts).  flips counts the moves kept (the best prefix of
      * each pass); attempts = passes x n.  Deterministic (no RNG).  Instances
-     * up to 4096 spins (else SG_EINVAL); runs under SG_SCHED_AUTO or
-     * SG_SCHED_FM only. */
+     * of more than 4096 spins need the knob fm_slots (set before sg_bind:
+     * that many replicas run at once, each with ~8 bytes of device scratch per
+     * spin in the workspace), the packed form, at most 64 couplings and 64
+     * hyper-couplings per row of the sliced layout and at most 4096 colours
+     * (else SG_EINVAL); runs under SG_SCHED_AUTO or SG_SCHED_FM only. */
     SG_RULE_FM = 2
 };
 
@@ -419,6 +422,11 @@ sg_status sg_solve(sg_handle h, const sg_run_params* p, sg_run_stats* stats, int
  *   "fm_key32"           1: SG_RULE_FM picks moves on 32-bit keys when every
  *                        gain is below 2^19 in magnitude; 0: 64-bit keys
  *                        (default 1)
+ *   "fm_slots"           replicas of instances beyond 4096 spins that
+ *                        SG_RULE_FM runs at once (0 = none: such instances
+ *                        are rejected); sizes the workspace (before sg_bind)
+ *                        with ~8 bytes per spin of the largest such instance
+ *                        per slot; more slots hide more memory latency
  *   "fm_lanes"           1: SG_RULE_FM runs one replica per lane for every
  *                        instance of at most 1024 spins whose per-spin sum
  *                        |h|+sum|J|+sum|K| is at most 127 (the others one
@@ -474,7 +482,8 @@ sg_status sg_tune(sg_handle h, const char* key, int64_t value);
  * picked moves on 32-bit keys), "last_fm_waves" (its wavefronts per
  * workgroup, 0 when every replica ran one per lane), "last_fm_lanes" (its
  * replicas run one per lane), "last_fm_lane_nr" (its restarts per lane-kernel
- * wavefront), "energy_pending" (1 while start energies
+ * wavefront), "last_fm_big" (its replicas on the kernel for instances beyond
+ * 4096 spins), "energy_pending" (1 while start energies
  * left out by sg_init_spins are not yet computed), "last_queue_grid",
  * "total_replicas", "queue_ok" (1 when every instance can join sg_run_group),
  * "wide_instances" (instances stored in the wide form: a

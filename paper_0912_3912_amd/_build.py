@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libsg.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["sg_host.cpp", "sg_bnb.cpp", "sg_kernels.hip", "sg_lattice.hip", "sg_batch.hip", "sg_queue.hip",
-           "sg_msc.hip", "sg_fm.hip", "sg_fm_lanes.hip", "sg_dense.hip", "sg_bits.hip", "sg_wide.hip", "sg_noalloc.hip"]
+           "sg_msc.hip", "sg_fm.hip", "sg_fm_lanes.hip", "sg_fm_big.hip", "sg_dense.hip", "sg_bits.hip", "sg_wide.hip", "sg_noalloc.hip"]
 HEADERS = ["sg_layout.h", "sg_launch.h", "sg_device.h"]
 
 # Packed-FP32 instructions are disabled for all device code (the path is

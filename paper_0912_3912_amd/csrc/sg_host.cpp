@@ -113,6 +113,7 @@ struct HostInst {
     int64_t rep_base = 0;
     // lattice schedule (implicit neighbours)
     int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
+    uint64_t off_fmb_intof = UINT64_MAX;  // external -> internal map for the large-instance pass kernel
     int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
     int64_t max_w = 0;                 // largest sum of |coefficients| over one spin's terms
     uint64_t fml_off = UINT64_MAX;     // word offset of its per-spin term rows (lane pass kernel), or none
@@ -174,6 +175,15 @@ struct sg_ctx {
     int32_t fml_ws = 1;                // workspace holds the per-spin term lists of the lane pass kernel
     int32_t fm_lanes = 1;              // FM runs one replica per lane where the instance allows
     int32_t fm_lane_restarts = 0;      // restarts per lane-kernel item (0 = chosen to fill the device)
+    // the pass-based search on instances beyond a wavefront's LDS: replicas
+    // run at once (0: none; its scratch is part of the workspace), the largest
+    // such instance, its colours, and the workspace areas
+    int32_t fm_slots = 0;
+    int32_t fmb_nmax = 0, fmb_cmax = 0;
+    int64_t fmb_reps = 0, fmb_slot_spins = 0, fmb_slot_leaves = 0;
+    uint64_t off_fmb_half = 0, off_fmb_moves = 0, off_fmb_leaf = 0, off_fmb_ptr = 0, off_fmb_items = 0,
+             off_fmb_cnt = 0;
+    int32_t last_fm_big = 0;           // replicas of the last FM call run on that kernel
     int32_t fm_lane_waves = 0;         // wavefronts per lane-kernel workgroup sharing an item (0 = 1)
     int32_t last_fm_lanes = 0;         // replicas of the last FM call run one per lane
     int32_t last_fm_lane_nr = 0;       // restarts per item of that call
@@ -1258,6 +1268,17 @@ void fml_counts(const HostInst& q, int32_t& dmax, int32_t& tmax)
         }
 }
 
+// Instances the large-instance pass kernel takes: packed, beyond one
+// wavefront's LDS, every slice at most 64 couplings and 64 hyper-couplings
+// wide (a move's partners fit one wavefront), at most 4096 colours.
+bool fmb_candidate(const HostInst& q)
+{
+    if (q.dense || q.wide || q.n <= kFmMaxN || q.C > 4096) return false;
+    for (const sg::Slice& S : q.slices)
+        if (S.ew > 64 || S.tw > 64) return false;
+    return true;
+}
+
 bool fml_candidate(const HostInst& q)
 {
     if (q.dense || q.wide || q.n > kFmlMaxN || q.max_w > kFmlMaxW) return false;
@@ -1468,6 +1489,30 @@ void layout(sg_ctx* H)
     H->off_solve = take(64 + ni * 12);  // sg_solve's results: call totals, best energies, best restarts
     H->off_rep_base = take(ni * 8);
     H->off_restarts = take(ni * 4);
+    // the large-instance pass kernel (fm_slots replicas at once): per slot
+    // the half-gains, the move list and the leaf keys of the largest such
+    // instance; per instance its external -> internal map
+    H->fmb_nmax = H->fmb_cmax = 0;
+    H->fmb_reps = 0;
+    for (HostInst& q : H->insts) {
+        q.off_fmb_intof = UINT64_MAX;
+        if (H->fm_slots <= 0 || !fmb_candidate(q)) continue;
+        H->fmb_nmax = std::max(H->fmb_nmax, q.n);
+        H->fmb_cmax = std::max(H->fmb_cmax, q.C);
+        H->fmb_reps += q.R;
+        q.off_fmb_intof = take((uint64_t)q.n * 4);
+    }
+    if (H->fmb_nmax > 0) {
+        const int64_t slots = std::min<int64_t>(H->fm_slots, H->fmb_reps);
+        H->fmb_slot_spins = (H->fmb_nmax + 63) / 64 * 64;
+        H->fmb_slot_leaves = (H->fmb_nmax + 63) / 64;
+        H->off_fmb_half = take((uint64_t)slots * H->fmb_slot_spins * 4);
+        H->off_fmb_moves = take((uint64_t)slots * H->fmb_slot_spins * 4);
+        H->off_fmb_leaf = take((uint64_t)slots * H->fmb_slot_leaves * 8);
+        H->off_fmb_ptr = take(ni * 8);
+        H->off_fmb_items = take((uint64_t)H->fmb_reps * sizeof(sg::QueueItem));
+        H->off_fmb_cnt = take(64);
+    }
     H->bytes = off;
 }
 
@@ -2238,8 +2283,18 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     bool tri = false, key32 = true;
     int64_t lane_reps = 0, wave_reps = 0;
     auto on_lanes = [&](const HostInst& q) { return H->fm_lanes && q.fml_off != UINT64_MAX; };
+    int64_t big_reps = 0;
     for (const HostInst& q : H->insts) {
-        if (q.n > kFmMaxN) return fail(SG_EINVAL, "rule SG_RULE_FM: instance of %d spins (at most %d)", q.n, kFmMaxN);
+        if (q.n > kFmMaxN) {
+            if (q.off_fmb_intof == UINT64_MAX)
+                return fail(SG_EINVAL,
+                            "rule SG_RULE_FM: instance %zu has %d spins (more than %d): its pass kernel needs "
+                            "fm_slots > 0 set before sg_bind, the packed form, at most 64 couplings and 64 "
+                            "hyper-couplings per slice row and at most 4096 colours",
+                            (size_t)(&q - H->insts.data()), q.n, kFmMaxN);
+            big_reps += q.R;
+            continue;
+        }
         if (q.wide) continue;  // a launch of its own below
         if (on_lanes(q)) {
             lnmax = std::max(lnmax, q.n);
@@ -2257,7 +2312,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     hipStream_t st = H->stream;
     H->h_qitems.clear();
     for (size_t k = 0; k < H->insts.size(); ++k)
-        if (!on_lanes(H->insts[k]) && !H->insts[k].wide)
+        if (!on_lanes(H->insts[k]) && !H->insts[k].wide && H->insts[k].n <= kFmMaxN)
             for (int32_t r = 0; r < H->insts[k].R; ++r) H->h_qitems.push_back(sg::QueueItem{(int32_t)k, r});
     std::stable_sort(H->h_qitems.begin(), H->h_qitems.end(), [&](const sg::QueueItem& a, const sg::QueueItem& b) {
         return H->insts[a.inst].n > H->insts[b.inst].n;
@@ -2314,7 +2369,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     // stage one instance's structure
     size_t stage = 0;
     for (const HostInst& q : H->insts)
-        if (!on_lanes(q) && !q.wide)
+        if (!on_lanes(q) && !q.wide && q.n <= kFmMaxN)
             stage = std::max(stage, q.slices.size() * sizeof(sg::Slice) + q.nbr.size() * 4 + (tri ? q.ta.size() * 8 : 0));
     stage = (stage + 15) / 16 * 16;
     // wavefronts per workgroup: the most resident wavefronts per compute unit
@@ -2395,9 +2450,27 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
                    "wide pass kernel");
             ++wide_launches;
         }
+    // instances beyond a wavefront's LDS: one launch, a wavefront per slot
+    int big_launches = 0;
+    H->last_fm_big = 0;
+    if (big_reps && p->max_sweeps > 0) {
+        SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_fmb_cnt), 1, 0u, st), "fill kernel");
+        const int slots = (int)std::min<int64_t>(H->fm_slots, H->fmb_reps);
+        SG_HIP(sg::launch_fm_big(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab),
+                                 H->at<const uint32_t*>(H->off_fmb_ptr), H->at<sg::QueueItem>(H->off_fmb_items),
+                                 (int)H->fmb_reps, H->at<uint32_t>(H->off_fmb_cnt), H->at<int32_t>(H->off_fmb_half),
+                                 H->at<int32_t>(H->off_fmb_moves), H->at<uint64_t>(H->off_fmb_leaf),
+                                 H->fmb_slot_spins, H->fmb_slot_leaves, slots, (int)((H->fmb_slot_leaves + 63) / 64),
+                                 H->fmb_cmax, H->reps(), H->at<sg::CallStats>(H->off_stats), err, p->max_sweeps,
+                                 p->until_converged, st),
+               "large-instance pass kernel");
+        H->last_fm_big = (int32_t)std::min<int64_t>(big_reps, INT32_MAX);
+        big_launches = 1;
+    }
     SG_HIP(hipEventRecord(H->evh1, st), "event record");
     SG_HIP(hipEventRecord(H->ev1, st), "event record");
-    H->hot_launches = p->max_sweeps > 0 ? lane_launches + (int)!H->h_qitems.empty() + wide_launches : 0;
+    H->hot_launches =
+        p->max_sweeps > 0 ? lane_launches + (int)!H->h_qitems.empty() + wide_launches + big_launches : 0;
     sg::CallStats cs;
     uint32_t herr = 0;
     CopiesOut out(H);
@@ -2730,6 +2803,26 @@ sg_status bind_impl(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream
         if (!H->h_fml.empty())
             SG_HIP(hipMemcpyAsync(H->dev + H->off_fml, H->h_fml.data(), H->h_fml.size() * 4, hipMemcpyHostToDevice, st),
                    "upload term lists");
+        if (H->fmb_nmax > 0) {
+            // external -> internal maps, their device addresses, the replica items
+            std::vector<const uint32_t*> ptr(H->insts.size(), nullptr);
+            std::vector<sg::QueueItem> items;
+            for (size_t k = 0; k < H->insts.size(); ++k) {
+                const HostInst& q = H->insts[k];
+                if (q.off_fmb_intof == UINT64_MAX) continue;
+                std::vector<uint32_t> iof((size_t)q.n);
+                for (int32_t i = 0; i < q.n; ++i) iof[q.ext_of[(size_t)i]] = (uint32_t)i;
+                SG_HIP(hipMemcpy(H->dev + q.off_fmb_intof, iof.data(), iof.size() * 4, hipMemcpyHostToDevice),
+                       "upload index map");
+                ptr[k] = H->at<uint32_t>(q.off_fmb_intof);
+                for (int32_t r = 0; r < q.R; ++r) items.push_back(sg::QueueItem{(int32_t)k, r});
+            }
+            SG_HIP(hipMemcpy(H->dev + H->off_fmb_ptr, ptr.data(), ptr.size() * sizeof(ptr[0]), hipMemcpyHostToDevice),
+                   "upload index map table");
+            SG_HIP(hipMemcpy(H->dev + H->off_fmb_items, items.data(), items.size() * sizeof(sg::QueueItem),
+                             hipMemcpyHostToDevice),
+                   "upload pass items");
+        }
         SG_HIP(hipMemcpyAsync(H->dev + H->off_ctab, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st),
                "upload colour table");
         std::vector<int32_t> rep_inst((size_t)H->total_reps);
@@ -3206,6 +3299,11 @@ sg_status sg_tune(sg_handle H, const char* key, int64_t value)
             return fail(SG_EINVAL, "fm_lanes: the workspace was laid out without the term lists (set it before sg_bind)");
         }
         H->fm_lanes = (int32_t)value;
+    } else if (k == "fm_slots") {
+        if (value < 0 || value > 65536) return fail(SG_EINVAL, "fm_slots must be in [0,65536]");
+        if (H->bound) return fail(SG_EINVAL, "fm_slots sizes the workspace: set it before sg_bind");
+        H->fm_slots = (int32_t)value;
+        layout(H);
     } else if (k == "fm_lane_waves") {
         if (value < 0 || value > 4) return fail(SG_EINVAL, "fm_lane_waves must be in [0,4]");
         H->fm_lane_waves = (int32_t)value;
@@ -3286,6 +3384,8 @@ sg_status sg_query(sg_handle H, const char* key, int64_t* value)
     else if (k == "fm_lanes") *value = H->fm_lanes;
     else if (k == "fm_lane_restarts") *value = H->fm_lane_restarts;
     else if (k == "fm_lane_waves") *value = H->fm_lane_waves;
+    else if (k == "fm_slots") *value = H->fm_slots;
+    else if (k == "last_fm_big") *value = H->last_fm_big;
     else if (k == "last_fm_lanes") *value = H->last_fm_lanes;
     else if (k == "last_fm_lane_nr") *value = H->last_fm_lane_nr;
     else if (k == "last_key32") *value = H->last_key32;

@@ -159,14 +159,87 @@ def test_mixed_batch(gpu, waves):
     _check(insts, seed=9, waves=waves, lanes=0)
 
 
+def _check_big(insts, seed, slots, max_passes=1000, uc=True, runs=None):
+    """Instances of more than 4096 spins on the large-instance pass kernel
+    (fm_slots replicas at once), beside smaller ones, against the oracle."""
+    import paper_0912_3912_amd as sg
+    log(f"fm big case: {[i.name for i in insts][:4]} n={[i.n for i in insts][:4]} seed={seed} slots={slots} "
+        f"passes={runs or max_passes} uc={uc}")
+    h = sg.load_instance(list(insts))
+    h.tune("fm_slots", slots)
+    h.bind()
+    h.init_spins(seed)
+    stats = [h.run_sweeps(seed=seed, rule=FM, max_sweeps=mp, until_converged=uc) for mp in (runs or [max_passes])]
+    assert h.query("last_fm_big") == (sum(i.restarts for i in insts if i.n > 4096) if (runs or [max_passes])[-1] else 0)
+    states = _oracle(insts, seed, max_passes, uc, runs, threads=8)
+    compare(h, insts, states)
+    if runs is None:
+        assert stats[0]["attempts"] == sum(int((st.sweeps * i.n).sum()) for i, st in zip(insts, states))
+        assert stats[0]["flips"] == sum(int(st.flips.sum()) for st in states)
+    return h
+
+
+@pytest.mark.parametrize("slots", [1, 2, 8])
+def test_big_er_with_triples(gpu, slots):
+    """5000 spins with hyper-couplings, three restarts: one slot runs them in
+    turn, two share them, eight leave slots idle."""
+    inst = gen.erdos_renyi_triples(5000, seed=3).replace(restarts=3, instance_id=5)
+    _check_big([inst], 4, slots).free()
+
+
+@pytest.mark.parametrize("case", ["lattice80x80", "n4097", "n4160"])
+def test_big_lattices_and_boundaries(gpu, case):
+    """A 6400-spin 2-D lattice with fields; 4097 spins (a leaf group of one
+    spin, two upper entries); 4160 spins (65 leaves)."""
+    if case == "n4097":
+        inst = gen.random_small(4097, seed=9, p_edge=4.0 / 4097, n_triples=300, j_range=(-9, 9),
+                                h_range=(-5, 5), k_range=(-5, 5)).replace(restarts=2, instance_id=11, name="rs4097")
+    elif case == "n4160":
+        inst = gen.random_small(4160, seed=10, p_edge=5.0 / 4160, n_triples=0, j_range=(-20, 20),
+                                h_range=(-3, 3)).replace(restarts=2, instance_id=12, name="rs4160")
+    else:
+        inst = gen.lattice((80, 80), seed=2, h_range=(-2, 2), restarts=2, instance_id=13)
+    _check_big([inst], 6, 4).free()
+
+
+def test_big_chimera_mixed_with_small(gpu):
+    """A 5408-spin Chimera instance (26 x 26 cells, hyper-couplings in some
+    cells) beside instances on the lane kernel and the wavefront kernel."""
+    big = gen.chimera(26, 26, seed=4, instance_id=20, restarts=2)
+    lanes = gen.chimera(4, 4, seed=2, instance_id=21, restarts=64)
+    wave = gen.random_small(300, seed=5, p_edge=0.03, n_triples=30, j_range=(-60, 60), h_range=(-9, 9),
+                            k_range=(-9, 9)).replace(restarts=3, instance_id=22)
+    h = _check_big([big, lanes, wave], 2, 3)
+    assert h.query("last_fm_lanes") == 64
+    h.free()
+
+
+def test_big_fixed_passes_and_resume(gpu):
+    inst = gen.erdos_renyi_triples(4500, seed=8).replace(restarts=2, instance_id=30)
+    _check_big([inst], 9, 2, uc=False, runs=[2, 0, 3]).free()
+    _check_big([inst], 9, 2, uc=True, runs=[1, 1000]).free()
+
+
 def test_errors(gpu):
     import paper_0912_3912_amd as sg
     big = gen.erdos_renyi_triples(5000, seed=1)
     h = sg.load_instance([big]).bind()
     h.init_spins(1)
-    with pytest.raises(sg.SGError) as e:
+    with pytest.raises(sg.SGError) as e:  # no slots for the large-instance kernel
+        h.run_sweeps(seed=1, rule=FM)
+    assert e.value.status == sg.SG_EINVAL and "fm_slots" in str(e.value)
+    h.free()
+    wide = big.replace(J=(big.J * 1000).astype(np.int32))
+    h = sg.load_instance([wide])
+    h.tune("fm_slots", 4)
+    h.bind()
+    h.init_spins(1)
+    with pytest.raises(sg.SGError) as e:  # the wide form stays off that kernel
         h.run_sweeps(seed=1, rule=FM)
     assert e.value.status == sg.SG_EINVAL
+    with pytest.raises(sg.SGError):
+        h.tune("fm_slots", 8)  # sizes the workspace: before bind only
+    h.free()
     h2 = sg.load_instance([gen.chimera(2, 2, seed=1)]).bind()
     h2.init_spins(1)
     with pytest.raises(sg.SGError) as e:
