@@ -73,10 +73,10 @@ enum {
      * unchanged (it counts).  flips counts the moves kept (the best prefix of
      * each pass); attempts = passes x n.  Deterministic (no RNG).  Instances
      * of more than 4096 spins need the knob fm_slots (set before sg_bind:
-     * that many replicas run at once, each with ~8 bytes of device scratch per
-     * spin in the workspace), the packed form, at most 64 couplings and 64
-     * hyper-couplings per row of the sliced layout and at most 4096 colours
-     * (else SG_EINVAL); runs under SG_SCHED_AUTO or SG_SCHED_FM only. */
+     * that many replicas run at once, each with ~9 bytes of device scratch per
+     * spin in the workspace), the packed form, and at most 64 couplings and 64
+     * hyper-couplings per row of the sliced layout (else SG_EINVAL); runs
+     * under SG_SCHED_AUTO or SG_SCHED_FM only. */
     SG_RULE_FM = 2
 };
 
@@ -425,8 +425,9 @@ sg_status sg_solve(sg_handle h, const sg_run_params* p, sg_run_stats* stats, int
  *   "fm_slots"           replicas of instances beyond 4096 spins that
  *                        SG_RULE_FM runs at once (0 = none: such instances
  *                        are rejected); sizes the workspace (before sg_bind)
- *                        with ~8 bytes per spin of the largest such instance
- *                        per slot; more slots hide more memory latency
+ *                        with ~9 bytes per spin of the largest such instance
+ *                        per slot, plus each such instance's term rows in
+ *                        external order; more slots hide more memory latency
  *   "fm_lanes"           1: SG_RULE_FM runs one replica per lane for every
  *                        instance of at most 1024 spins whose per-spin sum
  *                        |h|+sum|J|+sum|K| is at most 127 (the others one

@@ -113,7 +113,8 @@ struct HostInst {
     int64_t rep_base = 0;
     // lattice schedule (implicit neighbours)
     int32_t lat_ok = 0;                // lattice hint accepted, even extents, checkerboard colouring
-    uint64_t off_fmb_intof = UINT64_MAX;  // external -> internal map for the large-instance pass kernel
+    uint64_t off_fmb_rows = UINT64_MAX;  // term rows in external order for the large-instance pass kernel
+    int32_t fmb_dc = 0, fmb_tt = 0;      // their coupling and hyper-coupling widths
     int32_t lat_msc = 0;               // every lattice bond is +-1 and |h| <= 2 (bit-plane kernel)
     int64_t max_w = 0;                 // largest sum of |coefficients| over one spin's terms
     uint64_t fml_off = UINT64_MAX;     // word offset of its per-spin term rows (lane pass kernel), or none
@@ -177,12 +178,12 @@ struct sg_ctx {
     int32_t fm_lane_restarts = 0;      // restarts per lane-kernel item (0 = chosen to fill the device)
     // the pass-based search on instances beyond a wavefront's LDS: replicas
     // run at once (0: none; its scratch is part of the workspace), the largest
-    // such instance, its colours, and the workspace areas
+    // such instance, and the workspace areas
     int32_t fm_slots = 0;
-    int32_t fmb_nmax = 0, fmb_cmax = 0;
+    int32_t fmb_nmax = 0;
     int64_t fmb_reps = 0, fmb_slot_spins = 0, fmb_slot_leaves = 0;
-    uint64_t off_fmb_half = 0, off_fmb_moves = 0, off_fmb_leaf = 0, off_fmb_ptr = 0, off_fmb_items = 0,
-             off_fmb_cnt = 0;
+    uint64_t off_fmb_half = 0, off_fmb_moves = 0, off_fmb_leaf = 0, off_fmb_spin = 0, off_fmb_ptr = 0,
+             off_fmb_items = 0, off_fmb_cnt = 0;
     int32_t last_fm_big = 0;           // replicas of the last FM call run on that kernel
     int32_t fm_lane_waves = 0;         // wavefronts per lane-kernel workgroup sharing an item (0 = 1)
     int32_t last_fm_lanes = 0;         // replicas of the last FM call run one per lane
@@ -1270,13 +1271,53 @@ void fml_counts(const HostInst& q, int32_t& dmax, int32_t& tmax)
 
 // Instances the large-instance pass kernel takes: packed, beyond one
 // wavefront's LDS, every slice at most 64 couplings and 64 hyper-couplings
-// wide (a move's partners fit one wavefront), at most 4096 colours.
-bool fmb_candidate(const HostInst& q)
+// wide (a move's partners fit one wavefront).  dc, tt: the widest row's
+// nonzero couplings and hyper-couplings.
+bool fmb_candidate(const HostInst& q, int32_t* dc = nullptr, int32_t* tt = nullptr)
 {
-    if (q.dense || q.wide || q.n <= kFmMaxN || q.C > 4096) return false;
-    for (const sg::Slice& S : q.slices)
+    if (q.dense || q.wide || q.n <= kFmMaxN) return false;
+    int32_t d = 0, t = 0;
+    for (const sg::Slice& S : q.slices) {
         if (S.ew > 64 || S.tw > 64) return false;
+        for (int32_t l = 0; l < S.rows; ++l) {
+            int32_t cd = 0, ct = 0;
+            for (int32_t k = 0; k < S.ew; ++k) cd += (q.nbr[S.ebase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
+            for (int32_t k = 0; k < S.tw; ++k) ct += (q.ta[S.tbase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
+            d = std::max(d, cd);
+            t = std::max(t, ct);
+        }
+    }
+    if (dc) *dc = d;
+    if (tt) *tt = t;
     return true;
+}
+
+// The large-instance pass kernel's rows (FmbRows): per spin in external order
+// its field word, its nonzero couplings and hyper-couplings with partners in
+// external order, zero-padded to q.fmb_dc and q.fmb_tt.
+void build_fmb_rows(const HostInst& q, std::vector<uint32_t>& out)
+{
+    const int32_t dc = q.fmb_dc, tt = q.fmb_tt, stride = 1 + dc + 2 * tt;
+    out.assign((size_t)q.n * stride, 0u);
+    for (const sg::Slice& S : q.slices)
+        for (int32_t l = 0; l < S.rows; ++l) {
+            const int32_t i = (int32_t)S.row0 + l;
+            uint32_t* row = out.data() + (size_t)q.ext_of[(size_t)i] * stride;
+            row[0] = (uint32_t)(uint8_t)q.h[(size_t)i];
+            int32_t c = 0, t = 0;
+            for (int32_t k = 0; k < S.ew; ++k) {
+                const uint32_t w = q.nbr[S.ebase + (size_t)k * sg::kSlice + l];
+                if (w & 0xFFu) row[1 + c++] = (q.ext_of[w >> 8] << 8) | (w & 0xFFu);
+            }
+            for (int32_t k = 0; k < S.tw; ++k) {
+                const uint32_t wa = q.ta[S.tbase + (size_t)k * sg::kSlice + l];
+                if (!(wa & 0xFFu)) continue;
+                const uint32_t b = q.tb[S.tbase + (size_t)k * sg::kSlice + l];
+                row[1 + dc + 2 * t] = (q.ext_of[wa >> 8] << 8) | (wa & 0xFFu);
+                row[2 + dc + 2 * t] = q.ext_of[b];
+                ++t;
+            }
+        }
 }
 
 bool fml_candidate(const HostInst& q)
@@ -1492,24 +1533,24 @@ void layout(sg_ctx* H)
     // the large-instance pass kernel (fm_slots replicas at once): per slot
     // the half-gains, the move list and the leaf keys of the largest such
     // instance; per instance its external -> internal map
-    H->fmb_nmax = H->fmb_cmax = 0;
+    H->fmb_nmax = 0;
     H->fmb_reps = 0;
     for (HostInst& q : H->insts) {
-        q.off_fmb_intof = UINT64_MAX;
-        if (H->fm_slots <= 0 || !fmb_candidate(q)) continue;
+        q.off_fmb_rows = UINT64_MAX;
+        if (H->fm_slots <= 0 || !fmb_candidate(q, &q.fmb_dc, &q.fmb_tt)) continue;
         H->fmb_nmax = std::max(H->fmb_nmax, q.n);
-        H->fmb_cmax = std::max(H->fmb_cmax, q.C);
         H->fmb_reps += q.R;
-        q.off_fmb_intof = take((uint64_t)q.n * 4);
+        q.off_fmb_rows = take((uint64_t)q.n * (1 + q.fmb_dc + 2 * q.fmb_tt) * 4);
     }
     if (H->fmb_nmax > 0) {
         const int64_t slots = std::min<int64_t>(H->fm_slots, H->fmb_reps);
-        H->fmb_slot_spins = (H->fmb_nmax + 63) / 64 * 64;
+        H->fmb_slot_spins = (H->fmb_nmax + 255) / 256 * 256;
         H->fmb_slot_leaves = (H->fmb_nmax + 63) / 64;
         H->off_fmb_half = take((uint64_t)slots * H->fmb_slot_spins * 4);
         H->off_fmb_moves = take((uint64_t)slots * H->fmb_slot_spins * 4);
+        H->off_fmb_spin = take((uint64_t)slots * H->fmb_slot_spins);
         H->off_fmb_leaf = take((uint64_t)slots * H->fmb_slot_leaves * 8);
-        H->off_fmb_ptr = take(ni * 8);
+        H->off_fmb_ptr = take(ni * sizeof(sg::FmbRows));
         H->off_fmb_items = take((uint64_t)H->fmb_reps * sizeof(sg::QueueItem));
         H->off_fmb_cnt = take(64);
     }
@@ -2286,11 +2327,11 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     int64_t big_reps = 0;
     for (const HostInst& q : H->insts) {
         if (q.n > kFmMaxN) {
-            if (q.off_fmb_intof == UINT64_MAX)
+            if (q.off_fmb_rows == UINT64_MAX)
                 return fail(SG_EINVAL,
                             "rule SG_RULE_FM: instance %zu has %d spins (more than %d): its pass kernel needs "
-                            "fm_slots > 0 set before sg_bind, the packed form, at most 64 couplings and 64 "
-                            "hyper-couplings per slice row and at most 4096 colours",
+                            "fm_slots > 0 set before sg_bind, the packed form, and at most 64 couplings and 64 "
+                            "hyper-couplings per slice row",
                             (size_t)(&q - H->insts.data()), q.n, kFmMaxN);
             big_reps += q.R;
             continue;
@@ -2456,13 +2497,13 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     if (big_reps && p->max_sweeps > 0) {
         SG_HIP(sg::launch_fill_u32(H->at<uint32_t>(H->off_fmb_cnt), 1, 0u, st), "fill kernel");
         const int slots = (int)std::min<int64_t>(H->fm_slots, H->fmb_reps);
-        SG_HIP(sg::launch_fm_big(H->at<sg::InstTab>(H->off_tab), H->at<int32_t>(H->off_ctab),
-                                 H->at<const uint32_t*>(H->off_fmb_ptr), H->at<sg::QueueItem>(H->off_fmb_items),
-                                 (int)H->fmb_reps, H->at<uint32_t>(H->off_fmb_cnt), H->at<int32_t>(H->off_fmb_half),
+        SG_HIP(sg::launch_fm_big(H->at<sg::InstTab>(H->off_tab), H->at<sg::FmbRows>(H->off_fmb_ptr),
+                                 H->at<sg::QueueItem>(H->off_fmb_items), (int)H->fmb_reps,
+                                 H->at<uint32_t>(H->off_fmb_cnt), H->at<int32_t>(H->off_fmb_half),
                                  H->at<int32_t>(H->off_fmb_moves), H->at<uint64_t>(H->off_fmb_leaf),
-                                 H->fmb_slot_spins, H->fmb_slot_leaves, slots, (int)((H->fmb_slot_leaves + 63) / 64),
-                                 H->fmb_cmax, H->reps(), H->at<sg::CallStats>(H->off_stats), err, p->max_sweeps,
-                                 p->until_converged, st),
+                                 H->at<int8_t>(H->off_fmb_spin), H->fmb_slot_spins, H->fmb_slot_leaves, slots,
+                                 (int)((H->fmb_slot_leaves + 63) / 64), H->reps(), H->at<sg::CallStats>(H->off_stats),
+                                 err, p->max_sweeps, p->until_converged, st),
                "large-instance pass kernel");
         H->last_fm_big = (int32_t)std::min<int64_t>(big_reps, INT32_MAX);
         big_launches = 1;
@@ -2804,21 +2845,22 @@ sg_status bind_impl(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream
             SG_HIP(hipMemcpyAsync(H->dev + H->off_fml, H->h_fml.data(), H->h_fml.size() * 4, hipMemcpyHostToDevice, st),
                    "upload term lists");
         if (H->fmb_nmax > 0) {
-            // external -> internal maps, their device addresses, the replica items
-            std::vector<const uint32_t*> ptr(H->insts.size(), nullptr);
+            // term rows in external order, their table, the replica items
+            std::vector<sg::FmbRows> ptr(H->insts.size(), sg::FmbRows{nullptr, 0, 0, 0, 0});
             std::vector<sg::QueueItem> items;
+            std::vector<uint32_t> rows;
             for (size_t k = 0; k < H->insts.size(); ++k) {
                 const HostInst& q = H->insts[k];
-                if (q.off_fmb_intof == UINT64_MAX) continue;
-                std::vector<uint32_t> iof((size_t)q.n);
-                for (int32_t i = 0; i < q.n; ++i) iof[q.ext_of[(size_t)i]] = (uint32_t)i;
-                SG_HIP(hipMemcpy(H->dev + q.off_fmb_intof, iof.data(), iof.size() * 4, hipMemcpyHostToDevice),
-                       "upload index map");
-                ptr[k] = H->at<uint32_t>(q.off_fmb_intof);
+                if (q.off_fmb_rows == UINT64_MAX) continue;
+                build_fmb_rows(q, rows);
+                SG_HIP(hipMemcpy(H->dev + q.off_fmb_rows, rows.data(), rows.size() * 4, hipMemcpyHostToDevice),
+                       "upload pass rows");
+                ptr[k] = sg::FmbRows{H->at<uint32_t>(q.off_fmb_rows), 1 + q.fmb_dc + 2 * q.fmb_tt, q.fmb_dc, q.fmb_tt, 0};
                 for (int32_t r = 0; r < q.R; ++r) items.push_back(sg::QueueItem{(int32_t)k, r});
             }
-            SG_HIP(hipMemcpy(H->dev + H->off_fmb_ptr, ptr.data(), ptr.size() * sizeof(ptr[0]), hipMemcpyHostToDevice),
-                   "upload index map table");
+            SG_HIP(hipMemcpy(H->dev + H->off_fmb_ptr, ptr.data(), ptr.size() * sizeof(sg::FmbRows),
+                             hipMemcpyHostToDevice),
+                   "upload pass row table");
             SG_HIP(hipMemcpy(H->dev + H->off_fmb_items, items.data(), items.size() * sizeof(sg::QueueItem),
                              hipMemcpyHostToDevice),
                    "upload pass items");

@@ -73,16 +73,14 @@ hipError_t launch_fm(const InstTab* tab, const int32_t* ctab, const QueueItem* i
                      int stage_cap, bool tri, bool key32, RepState* rs, CallStats* cs, uint32_t* err, int max_passes,
                      int until_conv, hipStream_t st);
 // The pass-based search on instances of more than 4096 spins (packed form,
-// slice rows of at most 64 couplings and 64 hyper-couplings, at most c_cap
-// colours): one wavefront per slot takes the items (replicas) from *counter,
-// zero at launch; per slot slot_spins half-gains and move entries and
-// slot_leaves leaf keys; int_of[instance] maps external to internal indices;
-// top_cap >= the largest instance's ceil(ceil(n / 64) / 64).
-size_t fm_big_lds_bytes(int top_cap, int c_cap);
-hipError_t launch_fm_big(const InstTab* tab, const int32_t* ctab, const uint32_t* const* int_of, const QueueItem* items,
-                         int nitems, uint32_t* counter, int32_t* half, int32_t* moves, uint64_t* leaf,
-                         int64_t slot_spins, int64_t slot_leaves, int slots, int top_cap, int c_cap, RepState* rs,
-                         CallStats* cs, uint32_t* err, int max_passes, int until_conv, hipStream_t st);
+// term rows FmbRows per instance): one wavefront per slot takes the items
+// (replicas) from *counter, zero at launch; per slot slot_spins half-gains,
+// move entries and spin bytes and slot_leaves leaf keys; top_cap >= the
+// largest instance's ceil(ceil(n / 64) / 64).
+hipError_t launch_fm_big(const InstTab* tab, const FmbRows* rows, const QueueItem* items, int nitems,
+                         uint32_t* counter, int32_t* half, int32_t* moves, uint64_t* leaf, int8_t* spins,
+                         int64_t slot_spins, int64_t slot_leaves, int slots, int top_cap, RepState* rs, CallStats* cs,
+                         uint32_t* err, int max_passes, int until_conv, hipStream_t st);
 // The pass-based search on one instance in the wide form (at most 4096
 // spins), one wavefront per replica of [0, R); rs and spins are the
 // instance's own.

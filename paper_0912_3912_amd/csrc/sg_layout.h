@@ -139,6 +139,16 @@ struct InstTab {
     int32_t fml_dc, fml_tt;
 };
 
+// Per-spin term rows in external order for the pass kernel of instances
+// beyond 4096 spins (sg_fm_big.hip): spin e's row is the stride words from
+// rows + e * stride: a word with its field (low byte, int8), dc coupling
+// words (partner << 8 | J & 255), tt hyper-coupling pairs (a << 8 | K & 255,
+// b), unused entries zero; dc, tt <= 64.
+struct FmbRows {
+    const uint32_t* rows;
+    int32_t stride, dc, tt, pad;
+};
+
 struct BlockItem {           // k_block: restarts [r0, r0 + nr) of instance inst
     int32_t inst;
     int32_t r0;
