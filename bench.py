@@ -16,6 +16,9 @@ Workloads (--workload):
   chimera4096_fm  the same batch under the paper's pass-based search
                (max-gain moves with locking and hill-climbing, best prefix
                kept, passes until no improvement); value = moves/s.
+  square1000_fm  one pass of that search on each of 512 restarts of a
+               1000x1000 +-J lattice (10^6 spins, beyond one wavefront's LDS:
+               the large-instance pass kernel, fm_slots = 512); value = moves/s.
   er2000       2000 Erdos-Renyi instances, n log-uniform in [100, 1e5], mean
                degree 6, n/2 triples, GREEDY until converged, one launch.
   factoring    Sec. VI: random starts of the factoring hypergraphs of
@@ -403,6 +406,31 @@ def run_chimera_fm(args, sg, gen, torch, count=4096):
             "cpu_baseline": cpu}
 
 
+def run_square_fm(args, sg, gen, torch, L=1000, restarts=512):
+    """One pass of the pass-based search on every restart of a 10^6-spin 2-D
+    lattice: instances beyond one wavefront's LDS run on the large-instance
+    pass kernel, one replica per slot (fm_slots = restarts)."""
+    inst = gen.lattice((L, L), seed=2).replace(restarts=restarts)
+    h = sg.load_instance([inst])
+    h.tune("fm_slots", restarts)
+    h.bind()
+    log(f"square{L}_fm: workspace {h.workspace_bytes() / 1e9:.2f} GB")
+    h.init_spins(args.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = h.run_sweeps(seed=args.seed, rule=sg.FM, max_sweeps=1, until_converged=False)
+    dt = time.perf_counter() - t0
+    hot_us = h.query("hot_ns") / 1e3
+    big = h.query("last_fm_big")
+    h.free()
+    log(f"square{L}_fm: one pass of {restarts} restarts in {dt:.3f} s (hot {hot_us / 1e3:.1f} ms), "
+        f"{st['attempts'] / dt:.3g} moves/s")
+    return {"workload": f"square{L}_fm_{restarts}restarts_1pass", "metric": "moves/s", "unit": "moves/s",
+            "attempts_per_s": st["attempts"] / dt, "ms_per_step": dt * 1e3, "attempts": st["attempts"],
+            "replicas_on_large_kernel": big, "avg_launch_us": round(hot_us, 1),
+            "us_per_move_per_replica": round(dt / (st["attempts"] / restarts) * 1e6, 3), "cpu_baseline": None}
+
+
 def run_factoring(args, sg, gen, torch, copies=16, restarts=65535):
     """Sec. VI factoring experiments: every random start of the factoring
     hypergraph runs the pass-based search to convergence; a start succeeds
@@ -694,8 +722,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cubic100",
-                    choices=["cubic100", "square16", "chimera4096", "chimera4096_fm", "er2000", "serving",
-                             "factoring"])
+                    choices=["cubic100", "square16", "chimera4096", "chimera4096_fm", "square1000_fm", "er2000",
+                             "serving", "factoring"])
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--L", type=int, default=100)
     ap.add_argument("--schedule", type=int, default=SCHED_AUTO)
@@ -750,7 +778,8 @@ def main():
             log(f"leg {leg} done in {time.perf_counter() - t_leg:.1f} s")
     else:
         fn = {"square16": run_square, "chimera4096": run_chimera, "chimera4096_fm": run_chimera_fm,
-              "er2000": run_er, "serving": run_serving, "factoring": run_factoring}[args.workload]
+              "square1000_fm": run_square_fm, "er2000": run_er, "serving": run_serving,
+              "factoring": run_factoring}[args.workload]
         r = fn(args, sg, gen, torch)
         out = {"metric": r.get("metric", f"spin-flip attempts/s ({r['workload']})"), "value": r["attempts_per_s"],
                "unit": r.get("unit", "attempts/s"), "n_gpus": 1, "steps": args.batch_steps, "warmup": 1,
