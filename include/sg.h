@@ -74,9 +74,8 @@ enum {
      * each pass); attempts = passes x n.  Deterministic (no RNG).  Instances
      * of more than 4096 spins need the knob fm_slots (set before sg_bind:
      * that many replicas run at once, each with ~9 bytes of device scratch per
-     * spin in the workspace), the packed form, and at most 64 couplings and 64
-     * hyper-couplings per row of the sliced layout (else SG_EINVAL); runs
-     * under SG_SCHED_AUTO or SG_SCHED_FM only. */
+     * spin in the workspace) and at most 2^24 - 1 spins (else SG_EINVAL);
+     * both forms; runs under SG_SCHED_AUTO or SG_SCHED_FM only. */
     SG_RULE_FM = 2
 };
 

@@ -7,8 +7,10 @@
 //
 // Everything here is in external order, so that the largest key names its
 // spin directly.  Per instance a row table (FmbRows): per spin a word with
-// its field, then dc coupling words (partner << 8 | J & 255) and tt
-// hyper-coupling pairs (a << 8 | K & 255, b), unused entries zero.  Per
+// its field, then dc couplings and tt hyper-couplings, unused entries zero:
+// in the packed form words partner << 8 | J & 255 and pairs (a << 8 | K &
+// 255, b), in the wide form (any int32 coefficient) pairs (partner, J) and
+// triples (a, b, K).  A move's terms are taken 64 at a time (a lane each).  Per
 // replica, in a slot of the scratch area (a wavefront takes replicas from a
 // shared counter and reuses its slot):
 //   half  int32 per spin: v_e = -s_e f_e, half the gain -dE_e of moving e;
@@ -116,17 +118,29 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
         int passes = 0;
         bool conv = false, bad = false;
         for (int pass = 0; pass < max_passes && !bad; ++pass) {
-            // half-gains from the definition, 64 spins at a time
+            // half-gains from the definition, 64 spins at a time (every
+            // partial sum of a field is bounded by the spin's sum of |c|,
+            // below 2^31)
             for (int e = lane; e < n; e += 64) {
                 const uint32_t* row = Rw.rows + (int64_t)e * stride;
-                int f = (int)(int8_t)(row[0] & 0xffu);
-                for (int q = 0; q < dc; ++q) {
-                    const uint32_t w = row[1 + q];
-                    f += (int)(int8_t)(w & 0xffu) * sx[w >> 8];
-                }
-                for (int q = 0; q < tt; ++q) {
-                    const uint32_t wa = row[1 + dc + 2 * q], b = row[2 + dc + 2 * q];
-                    f += (int)(int8_t)(wa & 0xffu) * sx[wa >> 8] * sx[b];
+                int f;
+                if (!Rw.wide) {
+                    f = (int)(int8_t)(row[0] & 0xffu);
+                    for (int q = 0; q < dc; ++q) {
+                        const uint32_t w = row[1 + q];
+                        f += (int)(int8_t)(w & 0xffu) * sx[w >> 8];
+                    }
+                    for (int q = 0; q < tt; ++q) {
+                        const uint32_t wa = row[1 + dc + 2 * q], b = row[2 + dc + 2 * q];
+                        f += (int)(int8_t)(wa & 0xffu) * sx[wa >> 8] * sx[b];
+                    }
+                } else {
+                    f = (int)row[0];
+                    for (int q = 0; q < dc; ++q) f += (int)row[2 + 2 * q] * sx[row[1 + 2 * q]];
+                    for (int q = 0; q < tt; ++q) {
+                        const uint32_t* t3 = row + 1 + 2 * dc + 3 * q;
+                        f += (int)t3[2] * sx[t3[0]] * sx[t3[1]];
+                    }
                 }
                 half[e] = -sx[e] * f;
             }
@@ -158,25 +172,8 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                     break;
                 }
                 const int v = (int)((uint32_t)(K >> 32) ^ 0x80000000u);
-                // the mover's row (lane q: coupling q, hyper-coupling q) and spin
                 const uint32_t* row = Rw.rows + (int64_t)me * stride;
-                const uint32_t w = lane < dc ? row[1 + lane] : 0u;
-                const uint32_t wa = lane < tt ? row[1 + dc + 2 * lane] : 0u;
-                const uint32_t wb = lane < tt ? row[2 + dc + 2 * lane] : 0u;
                 const int s_old = sx[me];
-                // partners: their spins and half-gains, then the changes
-                // (unused entries have a zero coefficient)
-                const int J = (int)(int8_t)(w & 0xffu), K3 = (int)(int8_t)(wa & 0xffu);
-                const int j = (int)(w >> 8), a = (int)(wa >> 8), b = (int)wb;
-                const int sj = J ? sx[j] : 0, sa = K3 ? sx[a] : 0, sb = K3 ? sx[b] : 0;
-                const int32_t hj = J ? half[j] : kLocked;
-                const int32_t ha = K3 ? half[a] : kLocked, hb = K3 ? half[b] : kLocked;
-                if (hj != kLocked) atomicAdd(&half[j], 2 * J * sj * s_old);
-                if (K3) {
-                    const int d = 2 * K3 * sa * sb * s_old;
-                    if (ha != kLocked) atomicAdd(&half[a], d);
-                    if (hb != kLocked) atomicAdd(&half[b], d);
-                }
                 if (lane == 0) {
                     half[me] = kLocked;
                     sx[me] = (int8_t)-s_old;
@@ -187,66 +184,105 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                     Elow = E;
                     best_len = step + 1;
                 }
-                big_order();
-                // the touched leaves (the mover's, then each distinct partner
-                // leaf), up to four per round: their half-gains and the leaf
-                // keys of their upper entries are read in one round trip, the
-                // new leaf keys replace their old values in those entries, and
-                // the entries' maxima are taken from registers
-                int pend[3] = {J ? j >> 6 : -1, K3 ? a >> 6 : -1, K3 ? b >> 6 : -1};
-                bool first = true;
-                for (;;) {
-                    int gl[4];
-                    int ng = 0;
-                    if (first) {
-                        gl[ng++] = (int)(me >> 6);
-                        first = false;
+                // the mover's terms, 64 at a time (lane: coupling q and
+                // hyper-coupling q); a partner's half-gain changes by
+                // 2 J s_j s_old or 2 K s_a s_b s_old, added modulo 2^32 (every
+                // value it ends at is in range)
+                const int nq = dc > tt ? dc : tt;
+                for (int q0 = 0; q0 == 0 || q0 < nq; q0 += 64) {
+                    const int q = q0 + lane;
+                    int j = 0, a = 0, b = 0;
+                    int32_t J = 0, K3 = 0;
+                    if (!Rw.wide) {
+                        const uint32_t w = q < dc ? row[1 + q] : 0u;
+                        const uint32_t wa = q < tt ? row[1 + dc + 2 * q] : 0u;
+                        j = (int)(w >> 8);
+                        J = (int)(int8_t)(w & 0xffu);
+                        a = (int)(wa >> 8);
+                        b = q < tt ? (int)row[2 + dc + 2 * q] : 0;
+                        K3 = (int)(int8_t)(wa & 0xffu);
+                    } else {
+                        if (q < dc) {
+                            j = (int)row[1 + 2 * q];
+                            J = (int32_t)row[2 + 2 * q];
+                        }
+                        if (q < tt) {
+                            const uint32_t* t3 = row + 1 + 2 * dc + 3 * q;
+                            a = (int)t3[0];
+                            b = (int)t3[1];
+                            K3 = (int32_t)t3[2];
+                        }
                     }
-                    while (ng < 4) {
-                        // the lowest pending leaf of any lane, cleared wherever it is pending
-                        int cand = 0x7FFFFFFF;
-                        for (int u = 0; u < 3; ++u)
-                            if (pend[u] >= 0 && pend[u] < cand) cand = pend[u];
-                        int g = cand;
-                        for (int off = 32; off > 0; off >>= 1) g = min(g, __shfl_xor(g, off, 64));
-                        if (g == 0x7FFFFFFF) break;
-                        for (int u = 0; u < 3; ++u)
-                            if (pend[u] == g) pend[u] = -1;
-                        bool dup = false;
-                        for (int u = 0; u < ng; ++u) dup = dup || gl[u] == g;
-                        if (!dup) gl[ng++] = g;
+                    const int sj = J ? sx[j] : 0, sa = K3 ? sx[a] : 0, sb = K3 ? sx[b] : 0;
+                    const int32_t hj = J ? half[j] : kLocked;
+                    const int32_t ha = K3 ? half[a] : kLocked, hb = K3 ? half[b] : kLocked;
+                    if (hj != kLocked) atomicAdd(&half[j], (int32_t)((uint32_t)J * (uint32_t)(2 * sj * s_old)));
+                    if (K3) {
+                        const int32_t d = (int32_t)((uint32_t)K3 * (uint32_t)(2 * sa * sb * s_old));
+                        if (ha != kLocked) atomicAdd(&half[a], d);
+                        if (hb != kLocked) atomicAdd(&half[b], d);
                     }
-                    if (ng == 0) break;
-                    int32_t hv[4];
-                    uint32_t ev[4];
-                    uint64_t up[4];
+                    big_order();
+                    // the touched leaves (the mover's, then each distinct partner
+                    // leaf), up to four per round: their half-gains and the leaf
+                    // keys of their upper entries are read in one round trip, the
+                    // new leaf keys replace their old values in those entries, and
+                    // the entries' maxima are taken from registers
+                    int pend[3] = {J ? j >> 6 : -1, K3 ? a >> 6 : -1, K3 ? b >> 6 : -1};
+                    bool first = q0 == 0;
+                    for (;;) {
+                        int gl[4];
+                        int ng = 0;
+                        if (first) {
+                            gl[ng++] = (int)(me >> 6);
+                            first = false;
+                        }
+                        while (ng < 4) {
+                            // the lowest pending leaf of any lane, cleared wherever it is pending
+                            int cand = 0x7FFFFFFF;
+                            for (int u = 0; u < 3; ++u)
+                                if (pend[u] >= 0 && pend[u] < cand) cand = pend[u];
+                            int g = cand;
+                            for (int off = 32; off > 0; off >>= 1) g = min(g, __shfl_xor(g, off, 64));
+                            if (g == 0x7FFFFFFF) break;
+                            for (int u = 0; u < 3; ++u)
+                                if (pend[u] == g) pend[u] = -1;
+                            bool dup = false;
+                            for (int u = 0; u < ng; ++u) dup = dup || gl[u] == g;
+                            if (!dup) gl[ng++] = g;
+                        }
+                        if (ng == 0) break;
+                        int32_t hv[4];
+                        uint32_t ev[4];
+                        uint64_t up[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = u < ng ? gl[u] * 64 + lane : n;
-                        ev[u] = (uint32_t)e;
-                        hv[u] = e < n ? half[e] : kLocked;
-                        const int gg = u < ng ? (gl[u] >> 6) * 64 + lane : G1;
-                        up[u] = gg < G1 ? leaf[gg] : 0ull;
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = u < ng ? gl[u] * 64 + lane : n;
+                            ev[u] = (uint32_t)e;
+                            hv[u] = e < n ? half[e] : kLocked;
+                            const int gg = u < ng ? (gl[u] >> 6) * 64 + lane : G1;
+                            up[u] = gg < G1 ? leaf[gg] : 0ull;
+                        }
+                        uint64_t kk[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) kk[u] = big_wave_max(big_key(hv[u], ev[u]));
+                        // the new leaf keys into their entries' lanes, then each
+                        // entry's maximum (an entry read twice gives the same value)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (u >= ng) continue;
+                            if (lane == 0) leaf[gl[u]] = kk[u];
+#pragma unroll
+                            for (int x = 0; x < 4; ++x)
+                                if (x < ng && (gl[u] >> 6) == (gl[x] >> 6) && lane == (gl[u] & 63)) up[x] = kk[u];
+                        }
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) {
+                            const uint64_t m = big_wave_max(up[x]);
+                            if (x < ng && lane == 0) top[gl[x] >> 6] = m;
+                        }
+                        big_order();  // the leaf keys written before a later round reads them
                     }
-                    uint64_t kk[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) kk[u] = big_wave_max(big_key(hv[u], ev[u]));
-                    // the new leaf keys into their entries' lanes, then each
-                    // entry's maximum (an entry read twice gives the same value)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (u >= ng) continue;
-                        if (lane == 0) leaf[gl[u]] = kk[u];
-#pragma unroll
-                        for (int x = 0; x < 4; ++x)
-                            if (x < ng && (gl[u] >> 6) == (gl[x] >> 6) && lane == (gl[u] & 63)) up[x] = kk[u];
-                    }
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) {
-                        const uint64_t m = big_wave_max(up[x]);
-                        if (x < ng && lane == 0) top[gl[x] >> 6] = m;
-                    }
-                    big_order();  // the leaf keys written before a later round reads them
                 }
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");

@@ -1269,52 +1269,90 @@ void fml_counts(const HostInst& q, int32_t& dmax, int32_t& tmax)
         }
 }
 
-// Instances the large-instance pass kernel takes: packed, beyond one
-// wavefront's LDS, every slice at most 64 couplings and 64 hyper-couplings
-// wide (a move's partners fit one wavefront).  dc, tt: the widest row's
-// nonzero couplings and hyper-couplings.
+// Instances the large-instance pass kernel takes: beyond one wavefront's LDS
+// (more than kFmMaxN spins) and within its 2^24 - 1 (upper-level keys in
+// LDS).  dc, tt: the widest row's nonzero couplings and hyper-couplings.
+constexpr int32_t kFmBigMaxN = (1 << 24) - 1;
+
 bool fmb_candidate(const HostInst& q, int32_t* dc = nullptr, int32_t* tt = nullptr)
 {
-    if (q.dense || q.wide || q.n <= kFmMaxN) return false;
+    if (q.dense || q.n <= kFmMaxN || q.n > kFmBigMaxN) return false;
     int32_t d = 0, t = 0;
-    for (const sg::Slice& S : q.slices) {
-        if (S.ew > 64 || S.tw > 64) return false;
-        for (int32_t l = 0; l < S.rows; ++l) {
-            int32_t cd = 0, ct = 0;
-            for (int32_t k = 0; k < S.ew; ++k) cd += (q.nbr[S.ebase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
-            for (int32_t k = 0; k < S.tw; ++k) ct += (q.ta[S.tbase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
-            d = std::max(d, cd);
-            t = std::max(t, ct);
-        }
+    if (!q.wide) {
+        for (const sg::Slice& S : q.slices)
+            for (int32_t l = 0; l < S.rows; ++l) {
+                int32_t cd = 0, ct = 0;
+                for (int32_t k = 0; k < S.ew; ++k) cd += (q.nbr[S.ebase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
+                for (int32_t k = 0; k < S.tw; ++k) ct += (q.ta[S.tbase + (size_t)k * sg::kSlice + l] & 0xFFu) != 0;
+                d = std::max(d, cd);
+                t = std::max(t, ct);
+            }
+    } else {
+        for (const sg::WSlice& S : q.w_slices)
+            for (uint32_t l = 0; l < S.rows; ++l) {
+                int32_t cd = 0, ct = 0;
+                for (uint32_t k = 0; k < S.ew; ++k) cd += q.w_J[S.ebase + (size_t)k * sg::kSlice + l] != 0;
+                for (uint32_t k = 0; k < S.tw; ++k) ct += q.w_K[S.tbase + (size_t)k * sg::kSlice + l] != 0;
+                d = std::max(d, cd);
+                t = std::max(t, ct);
+            }
     }
     if (dc) *dc = d;
     if (tt) *tt = t;
     return true;
 }
 
+int32_t fmb_stride(const HostInst& q) { return q.wide ? 1 + 2 * q.fmb_dc + 3 * q.fmb_tt : 1 + q.fmb_dc + 2 * q.fmb_tt; }
+
 // The large-instance pass kernel's rows (FmbRows): per spin in external order
-// its field word, its nonzero couplings and hyper-couplings with partners in
+// its field, its nonzero couplings and hyper-couplings with partners in
 // external order, zero-padded to q.fmb_dc and q.fmb_tt.
 void build_fmb_rows(const HostInst& q, std::vector<uint32_t>& out)
 {
-    const int32_t dc = q.fmb_dc, tt = q.fmb_tt, stride = 1 + dc + 2 * tt;
+    const int32_t dc = q.fmb_dc, stride = fmb_stride(q);
     out.assign((size_t)q.n * stride, 0u);
-    for (const sg::Slice& S : q.slices)
-        for (int32_t l = 0; l < S.rows; ++l) {
-            const int32_t i = (int32_t)S.row0 + l;
-            uint32_t* row = out.data() + (size_t)q.ext_of[(size_t)i] * stride;
-            row[0] = (uint32_t)(uint8_t)q.h[(size_t)i];
-            int32_t c = 0, t = 0;
-            for (int32_t k = 0; k < S.ew; ++k) {
-                const uint32_t w = q.nbr[S.ebase + (size_t)k * sg::kSlice + l];
-                if (w & 0xFFu) row[1 + c++] = (q.ext_of[w >> 8] << 8) | (w & 0xFFu);
+    if (!q.wide) {
+        for (const sg::Slice& S : q.slices)
+            for (int32_t l = 0; l < S.rows; ++l) {
+                const int32_t i = (int32_t)S.row0 + l;
+                uint32_t* row = out.data() + (size_t)q.ext_of[(size_t)i] * stride;
+                row[0] = (uint32_t)(uint8_t)q.h[(size_t)i];
+                int32_t c = 0, t = 0;
+                for (int32_t k = 0; k < S.ew; ++k) {
+                    const uint32_t w = q.nbr[S.ebase + (size_t)k * sg::kSlice + l];
+                    if (w & 0xFFu) row[1 + c++] = (q.ext_of[w >> 8] << 8) | (w & 0xFFu);
+                }
+                for (int32_t k = 0; k < S.tw; ++k) {
+                    const uint32_t wa = q.ta[S.tbase + (size_t)k * sg::kSlice + l];
+                    if (!(wa & 0xFFu)) continue;
+                    const uint32_t b = q.tb[S.tbase + (size_t)k * sg::kSlice + l];
+                    row[1 + dc + 2 * t] = (q.ext_of[wa >> 8] << 8) | (wa & 0xFFu);
+                    row[2 + dc + 2 * t] = q.ext_of[b];
+                    ++t;
+                }
             }
-            for (int32_t k = 0; k < S.tw; ++k) {
-                const uint32_t wa = q.ta[S.tbase + (size_t)k * sg::kSlice + l];
-                if (!(wa & 0xFFu)) continue;
-                const uint32_t b = q.tb[S.tbase + (size_t)k * sg::kSlice + l];
-                row[1 + dc + 2 * t] = (q.ext_of[wa >> 8] << 8) | (wa & 0xFFu);
-                row[2 + dc + 2 * t] = q.ext_of[b];
+        return;
+    }
+    for (const sg::WSlice& S : q.w_slices)
+        for (uint32_t l = 0; l < S.rows; ++l) {
+            const uint32_t i = S.row0 + l;
+            uint32_t* row = out.data() + (size_t)q.ext_of[i] * stride;
+            row[0] = (uint32_t)q.w_h[i];
+            int32_t c = 0, t = 0;
+            for (uint32_t k = 0; k < S.ew; ++k) {
+                const uint64_t at = S.ebase + (uint64_t)k * sg::kSlice + l;
+                if (!q.w_J[at]) continue;
+                row[1 + 2 * c] = q.ext_of[q.w_nbr[at]];
+                row[2 + 2 * c] = (uint32_t)q.w_J[at];
+                ++c;
+            }
+            for (uint32_t k = 0; k < S.tw; ++k) {
+                const uint64_t at = S.tbase + (uint64_t)k * sg::kSlice + l;
+                if (!q.w_K[at]) continue;
+                uint32_t* t3 = row + 1 + 2 * dc + 3 * t;
+                t3[0] = q.ext_of[q.w_ta[at]];
+                t3[1] = q.ext_of[q.w_tb[at]];
+                t3[2] = (uint32_t)q.w_K[at];
                 ++t;
             }
         }
@@ -1540,7 +1578,7 @@ void layout(sg_ctx* H)
         if (H->fm_slots <= 0 || !fmb_candidate(q, &q.fmb_dc, &q.fmb_tt)) continue;
         H->fmb_nmax = std::max(H->fmb_nmax, q.n);
         H->fmb_reps += q.R;
-        q.off_fmb_rows = take((uint64_t)q.n * (1 + q.fmb_dc + 2 * q.fmb_tt) * 4);
+        q.off_fmb_rows = take((uint64_t)q.n * fmb_stride(q) * 4);
     }
     if (H->fmb_nmax > 0) {
         const int64_t slots = std::min<int64_t>(H->fm_slots, H->fmb_reps);
@@ -2330,9 +2368,8 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
             if (q.off_fmb_rows == UINT64_MAX)
                 return fail(SG_EINVAL,
                             "rule SG_RULE_FM: instance %zu has %d spins (more than %d): its pass kernel needs "
-                            "fm_slots > 0 set before sg_bind, the packed form, and at most 64 couplings and 64 "
-                            "hyper-couplings per slice row",
-                            (size_t)(&q - H->insts.data()), q.n, kFmMaxN);
+                            "fm_slots > 0 set before sg_bind and at most %d spins",
+                            (size_t)(&q - H->insts.data()), q.n, kFmMaxN, kFmBigMaxN);
             big_reps += q.R;
             continue;
         }
@@ -2484,7 +2521,7 @@ sg_status run_fm(sg_handle H, const sg_run_params* p, sg_run_stats* stats)
     // instances in the wide form: one launch each, a wavefront per replica
     int wide_launches = 0;
     for (const HostInst& q : H->insts)
-        if (q.wide && p->max_sweeps > 0) {
+        if (q.wide && q.n <= kFmMaxN && p->max_sweeps > 0) {
             SG_HIP(sg::launch_fm_wide(H->wview(q), H->at<int8_t>(q.off_spins), (int64_t)q.spin_stride,
                                       H->reps() + q.rep_base, q.R, H->at<sg::CallStats>(H->off_stats), err,
                                       p->max_sweeps, p->until_converged, st),
@@ -2855,7 +2892,7 @@ sg_status bind_impl(sg_handle H, void* dev_ptr, uint64_t bytes, void* hip_stream
                 build_fmb_rows(q, rows);
                 SG_HIP(hipMemcpy(H->dev + q.off_fmb_rows, rows.data(), rows.size() * 4, hipMemcpyHostToDevice),
                        "upload pass rows");
-                ptr[k] = sg::FmbRows{H->at<uint32_t>(q.off_fmb_rows), 1 + q.fmb_dc + 2 * q.fmb_tt, q.fmb_dc, q.fmb_tt, 0};
+                ptr[k] = sg::FmbRows{H->at<uint32_t>(q.off_fmb_rows), fmb_stride(q), q.fmb_dc, q.fmb_tt, q.wide};
                 for (int32_t r = 0; r < q.R; ++r) items.push_back(sg::QueueItem{(int32_t)k, r});
             }
             SG_HIP(hipMemcpy(H->dev + H->off_fmb_ptr, ptr.data(), ptr.size() * sizeof(sg::FmbRows),

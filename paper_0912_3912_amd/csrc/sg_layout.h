@@ -141,12 +141,13 @@ struct InstTab {
 
 // Per-spin term rows in external order for the pass kernel of instances
 // beyond 4096 spins (sg_fm_big.hip): spin e's row is the stride words from
-// rows + e * stride: a word with its field (low byte, int8), dc coupling
-// words (partner << 8 | J & 255), tt hyper-coupling pairs (a << 8 | K & 255,
-// b), unused entries zero; dc, tt <= 64.
+// rows + e * stride, unused entries zero.  Packed form (wide = 0): a word
+// with the field in its low byte (int8), dc coupling words (partner << 8 |
+// J & 255), tt hyper-coupling pairs (a << 8 | K & 255, b).  Wide form: the
+// field (int32), dc pairs (partner, J), tt triples (a, b, K).
 struct FmbRows {
     const uint32_t* rows;
-    int32_t stride, dc, tt, pad;
+    int32_t stride, dc, tt, wide;
 };
 
 struct BlockItem {           // k_block: restarts [r0, r0 + nr) of instance inst

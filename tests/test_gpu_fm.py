@@ -220,6 +220,48 @@ def test_big_fixed_passes_and_resume(gpu):
     _check_big([inst], 9, 2, uc=True, runs=[1, 1000]).free()
 
 
+def _hub(n, seed, scale=1):
+    """A sparse random instance whose spin 7 has 400 couplings and spin
+    n - 500 sits in 150 hyper-couplings, so that a move's terms take
+    several 64-term chunks."""
+    rng = np.random.default_rng(seed)
+    base = gen.random_small(n, seed=seed, p_edge=3.0 / n, n_triples=n // 10, j_range=(-9, 9), h_range=(-4, 4),
+                            k_range=(-6, 6))
+    nb = rng.choice(np.setdiff1d(np.arange(n), [7]), size=400, replace=False)
+    hub_j = rng.integers(1, 10, size=400) * rng.choice([-1, 1], size=400)
+    ei = np.concatenate([base.ei, np.full(400, 7)]).astype(base.ei.dtype)
+    ej = np.concatenate([base.ej, nb]).astype(base.ej.dtype)
+    J = np.concatenate([base.J, hub_j]).astype(np.int32) * scale
+    c = n - 500
+    pairs = rng.choice(np.setdiff1d(np.arange(n), [c]), size=(150, 2), replace=False)
+    tri = np.concatenate([base.tri, np.column_stack([np.full(150, c), pairs])]).astype(base.tri.dtype)
+    K = np.concatenate([base.K, rng.integers(1, 7, size=150) * rng.choice([-1, 1], size=150)]).astype(np.int32)
+    h = base.h.astype(np.int32) * scale
+    return gen.Instance(n, ei, ej, J, h, tri, (K * scale).astype(np.int32), restarts=2, instance_id=40 + scale,
+                        name=f"hub{n}x{scale}")
+
+
+@pytest.mark.parametrize("scale", [1, 1000])
+def test_big_hub_rows(gpu, scale):
+    """A spin with 400 couplings and one in 150 hyper-couplings: a move's
+    terms in several chunks; scale 1000 puts the instance in the wide form
+    (int32 coefficients)."""
+    inst = _hub(6000, seed=5, scale=scale)
+    h = _check_big([inst], 3, 2)
+    assert h.query("wide_instances") == (1 if scale > 1 else 0)
+    h.free()
+
+
+def test_big_wide_er(gpu):
+    """5000 spins with hyper-couplings and couplings of up to 9000 in
+    magnitude (wide form) on the large-instance pass kernel."""
+    big = gen.erdos_renyi_triples(5000, seed=1)
+    wide = big.replace(J=(big.J * 1000).astype(np.int32), restarts=3, instance_id=6)
+    h = _check_big([wide], 2, 2)
+    assert h.query("wide_instances") == 1
+    h.free()
+
+
 def test_errors(gpu):
     import paper_0912_3912_amd as sg
     big = gen.erdos_renyi_triples(5000, seed=1)
@@ -228,15 +270,6 @@ def test_errors(gpu):
     with pytest.raises(sg.SGError) as e:  # no slots for the large-instance kernel
         h.run_sweeps(seed=1, rule=FM)
     assert e.value.status == sg.SG_EINVAL and "fm_slots" in str(e.value)
-    h.free()
-    wide = big.replace(J=(big.J * 1000).astype(np.int32))
-    h = sg.load_instance([wide])
-    h.tune("fm_slots", 4)
-    h.bind()
-    h.init_spins(1)
-    with pytest.raises(sg.SGError) as e:  # the wide form stays off that kernel
-        h.run_sweeps(seed=1, rule=FM)
-    assert e.value.status == sg.SG_EINVAL
     with pytest.raises(sg.SGError):
         h.tune("fm_slots", 8)  # sizes the workspace: before bind only
     h.free()
