@@ -25,7 +25,10 @@
 // wave-wide maximum is the move.  A move locks and flips the spin, adds its
 // partners' half-gain changes (2 J s_e s_j for a coupling, 2 K s_e s_a s_b
 // for a hyper-coupling) and recomputes the leaves it touched and their
-// upper-level entries.
+// upper-level entries: the touched leaves are gathered whole, the changes
+// added in LDS and the results stored, so that a move costs two dependent
+// device-memory round trips (its row, then the gather) when it touches at
+// most four leaves.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -90,7 +93,9 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                                                uint32_t* __restrict__ err, int max_passes, int until_conv)
 {
     extern __shared__ uint64_t top[];
+    __shared__ int32_t dl[4 * 64];  // a round's half-gain changes per gathered leaf and lane
     const int lane = threadIdx.x;
+    for (int u = 0; u < 4; ++u) dl[u * 64 + lane] = 0;
     int32_t* half = half_all + (int64_t)blockIdx.x * slot_spins;
     int32_t* moves = moves_all + (int64_t)blockIdx.x * slot_spins;
     int8_t* sx = spin_all + (int64_t)blockIdx.x * slot_spins;
@@ -174,11 +179,7 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                 const int v = (int)((uint32_t)(K >> 32) ^ 0x80000000u);
                 const uint32_t* row = Rw.rows + (int64_t)me * stride;
                 const int s_old = sx[me];
-                if (lane == 0) {
-                    half[me] = kLocked;
-                    sx[me] = (int8_t)-s_old;
-                    moves[step] = (int)me;
-                }
+                const int gm = (int)(me >> 6);
                 E -= 2LL * v;
                 if (E < Elow) {
                     Elow = E;
@@ -213,45 +214,58 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                             K3 = (int32_t)t3[2];
                         }
                     }
-                    const int sj = J ? sx[j] : 0, sa = K3 ? sx[a] : 0, sb = K3 ? sx[b] : 0;
-                    const int32_t hj = J ? half[j] : kLocked;
-                    const int32_t ha = K3 ? half[a] : kLocked, hb = K3 ? half[b] : kLocked;
-                    if (hj != kLocked) atomicAdd(&half[j], (int32_t)((uint32_t)J * (uint32_t)(2 * sj * s_old)));
-                    if (K3) {
-                        const int32_t d = (int32_t)((uint32_t)K3 * (uint32_t)(2 * sa * sb * s_old));
-                        if (ha != kLocked) atomicAdd(&half[a], d);
-                        if (hb != kLocked) atomicAdd(&half[b], d);
-                    }
-                    big_order();
-                    // the touched leaves (the mover's, then each distinct partner
-                    // leaf), up to four per round: their half-gains and the leaf
-                    // keys of their upper entries are read in one round trip, the
-                    // new leaf keys replace their old values in those entries, and
-                    // the entries' maxima are taken from registers
+                    // the touched leaves (the mover's, then each distinct
+                    // partner leaf), up to four per round.  A round gathers
+                    // their half-gains and the leaf keys of their upper
+                    // entries in one round trip (the first round also the
+                    // partners' spins), adds the partners it takes through
+                    // the LDS table dl, stores the changed half-gains and
+                    // leaf keys and refreshes the upper entries from
+                    // registers.
                     int pend[3] = {J ? j >> 6 : -1, K3 ? a >> 6 : -1, K3 ? b >> 6 : -1};
-                    bool first = q0 == 0;
+                    bool first = q0 == 0, fresh = true;
+                    int32_t dJ = 0, dK = 0;
                     for (;;) {
                         int gl[4];
                         int ng = 0;
+                        bool take[3] = {false, false, false};
                         if (first) {
-                            gl[ng++] = (int)(me >> 6);
+                            gl[ng++] = gm;
                             first = false;
                         }
                         while (ng < 4) {
-                            // the lowest pending leaf of any lane, cleared wherever it is pending
-                            int cand = 0x7FFFFFFF;
+                            // the pending leaf of the first lane that has one,
+                            // taken wherever it is pending
+                            const uint64_t b0 = __ballot(pend[0] >= 0), b1 = __ballot(pend[1] >= 0),
+                                           b2 = __ballot(pend[2] >= 0);
+                            int g;
+                            if (b0)
+                                g = __builtin_amdgcn_readlane(pend[0], (int)__builtin_ctzll(b0));
+                            else if (b1)
+                                g = __builtin_amdgcn_readlane(pend[1], (int)__builtin_ctzll(b1));
+                            else if (b2)
+                                g = __builtin_amdgcn_readlane(pend[2], (int)__builtin_ctzll(b2));
+                            else
+                                break;
                             for (int u = 0; u < 3; ++u)
-                                if (pend[u] >= 0 && pend[u] < cand) cand = pend[u];
-                            int g = cand;
-                            for (int off = 32; off > 0; off >>= 1) g = min(g, __shfl_xor(g, off, 64));
-                            if (g == 0x7FFFFFFF) break;
-                            for (int u = 0; u < 3; ++u)
-                                if (pend[u] == g) pend[u] = -1;
+                                if (pend[u] == g) {
+                                    pend[u] = -1;
+                                    take[u] = true;
+                                }
                             bool dup = false;
                             for (int u = 0; u < ng; ++u) dup = dup || gl[u] == g;
                             if (!dup) gl[ng++] = g;
                         }
                         if (ng == 0) break;
+                        // earlier stores (the previous move's, an earlier
+                        // round's) are complete before the gather reads them
+                        big_order();
+                        if (fresh) {
+                            const int sj = J ? sx[j] : 0, sa = K3 ? sx[a] : 0, sb = K3 ? sx[b] : 0;
+                            dJ = (int32_t)((uint32_t)J * (uint32_t)(2 * sj * s_old));
+                            dK = (int32_t)((uint32_t)K3 * (uint32_t)(2 * sa * sb * s_old));
+                            fresh = false;
+                        }
                         int32_t hv[4];
                         uint32_t ev[4];
                         uint64_t up[4];
@@ -263,9 +277,32 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                             const int gg = u < ng ? (gl[u] >> 6) * 64 + lane : G1;
                             up[u] = gg < G1 ? leaf[gg] : 0ull;
                         }
+                        // this round's partners into their leaves' rows of dl
+                        // (same-wavefront LDS operations complete in order)
+                        const int pe[3] = {j, a, b};
+                        const int32_t pd[3] = {dJ, dK, dK};
+#pragma unroll
+                        for (int u = 0; u < 3; ++u) {
+                            if (!take[u]) continue;
+                            int x = 0;
+                            for (int y = 1; y < ng; ++y)
+                                if (gl[y] == (pe[u] >> 6)) x = y;
+                            atomicAdd(&dl[x * 64 + (pe[u] & 63)], pd[u]);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         uint64_t kk[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) kk[u] = big_wave_max(big_key(hv[u], ev[u]));
+                        for (int u = 0; u < 4; ++u) {
+                            int32_t nv = hv[u];
+                            if (u < ng) {
+                                const int32_t add = dl[u * 64 + lane];
+                                dl[u * 64 + lane] = 0;
+                                if (nv != kLocked) nv = (int32_t)((uint32_t)nv + (uint32_t)add);
+                                if (ev[u] == me) nv = kLocked;
+                                if (nv != hv[u]) half[ev[u]] = nv;
+                            }
+                            kk[u] = big_wave_max(big_key(nv, ev[u]));
+                        }
                         // the new leaf keys into their entries' lanes, then each
                         // entry's maximum (an entry read twice gives the same value)
 #pragma unroll
@@ -281,12 +318,15 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                             const uint64_t m = big_wave_max(up[x]);
                             if (x < ng && lane == 0) top[gl[x] >> 6] = m;
                         }
-                        big_order();  // the leaf keys written before a later round reads them
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     }
                 }
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                if (lane == 0) {
+                    sx[me] = (int8_t)-s_old;
+                    moves[step] = (int)me;
+                }
             }
+            big_order();  // the last moves' stores before the undo reads them
             if (bad) break;
             // undo the moves after the best prefix
             for (int t = best_len + lane; t < n; t += 64) {
