@@ -220,6 +220,41 @@ def test_big_fixed_passes_and_resume(gpu):
     _check_big([inst], 9, 2, uc=True, runs=[1, 1000]).free()
 
 
+def test_big_square1000_one_pass_properties(gpu):
+    """The 10^6-spin 2-D lattice of the one-pass workload, four restarts in
+    four slots: the oracle's pass costs O(n^2), so the result is checked
+    against what holds at any size.  The start is the oracle's; a pass moves
+    every spin once and keeps a prefix, so exactly the kept moves' spins
+    differ from the start; the tracked energy equals the recomputed one and
+    the oracle's energy of the read-back spins, and is not above the start's."""
+    import paper_0912_3912_amd as sg
+    inst = gen.lattice((1000, 1000), seed=2).replace(restarts=4)
+    log(f"fm big case: {inst.name} n={inst.n} seed=7 slots=4 passes=1")
+    start, _ = oracle.fm(inst, seed=7, max_passes=0, until_converged=False)
+    h = sg.load_instance([inst])
+    h.tune("fm_slots", 4)
+    h.bind()
+    h.init_spins(7)
+    assert np.array_equal(h.spins_out_batch(0), start.spins)
+    assert np.array_equal(h.energy(), start.energy)
+    st = h.run_sweeps(seed=7, rule=FM, max_sweeps=1, until_converged=False)
+    assert h.query("last_fm_big") == 4
+    assert st["attempts"] == 4 * inst.n
+    S = h.spins_out_batch(0)
+    E, Er = h.energy(), h.energy(recompute=True)
+    sw, fl, cv = h.counters()
+    assert np.array_equal(E, Er)
+    assert (sw == 1).all() and (cv == 0).all()
+    assert st["flips"] == int(fl.sum())
+    for r in range(4):
+        assert np.isin(S[r], (-1, 1)).all()
+        assert int((S[r] != start.spins[r]).sum()) == int(fl[r])
+        assert oracle.energy(inst, S[r]) == int(E[r])
+        assert E[r] <= start.energy[r]
+        assert 0 < fl[r] <= inst.n
+    h.free()
+
+
 def _hub(n, seed, scale=1):
     """A sparse random instance whose spin 7 has 400 couplings and spin
     n - 500 sits in 150 hyper-couplings, so that a move's terms take
