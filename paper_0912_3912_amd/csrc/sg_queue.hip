@@ -35,7 +35,13 @@ constexpr int kBatWaves = kBatThreads / 64;
 // wavefront keeps a whole slice's loads in flight (measured on 2000 uneven
 // instances: 3.26 ms, against 4.67 ms with four loads at a time and 3.78 ms
 // when loading the next slice while evaluating the current one with fewer
-// words each).
+// words each).  The slice descriptors are read with scalar loads one slice
+// ahead and the instance arrays addressed as device memory (2.78 ms; with
+// the descriptor read per lane before the words and generic loads, 3.25 ms).
+// Loading the next slice's words as well, with both buffers at full width,
+// measured 2.82-2.89 ms: the extra registers and copies cost what the hidden
+// latency saves, as the wavefronts of a compute unit already keep its vector
+// and LDS units about half busy.
 constexpr int kPreW = 16, kPreT = 8;
 
 struct SliceWords {
@@ -44,22 +50,55 @@ struct SliceWords {
     int h;
 };
 
+// Device-memory views of the instance arrays (the pointers come from the
+// instance table, so the compiler would otherwise address them as generic
+// memory, whose loads also hold up every LDS wait), and a read-only view of
+// the slice table for loads at wavefront-uniform addresses (scalar loads).
+typedef __attribute__((address_space(1))) const uint32_t q_g32;
+typedef __attribute__((address_space(1))) const int8_t q_gi8;
+typedef uint32_t q_v4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const q_v4 q_kslice;
+
+__device__ __forceinline__ q_v4 queue_slice_raw(const Slice* slices, int sl) { return *(q_kslice*)(slices + sl); }
+
+__device__ __forceinline__ Slice queue_unpack(q_v4 v)
+{
+    Slice S;
+    S.row0 = v.x;
+    S.ebase = v.y;
+    S.tbase = v.z;
+    S.ew = (uint16_t)(v.w & 0xFFFFu);
+    S.tw = (uint8_t)((v.w >> 16) & 0xFFu);
+    S.rows = (uint8_t)(v.w >> 24);
+    return S;
+}
+
+// A pointer the whole wavefront holds, in scalar registers.
+template <class T>
+__device__ __forceinline__ T* queue_uniform(T* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ void queue_load(const InstDev& I, const Slice& S, int lane, SliceWords& L)
 {
     const bool row = lane < S.rows;
-    const uint32_t* p = I.nbr + S.ebase + lane;
+    q_g32* p = (q_g32*)I.nbr + S.ebase + lane;
 #pragma unroll
     for (int k = 0; k < kPreW; ++k) L.w[k] = (row && k < S.ew) ? p[k * kSlice] : 0u;
     if (I.has_tri) {
-        const uint32_t* pa = I.ta + S.tbase + lane;
-        const uint32_t* pb = I.tb + S.tbase + lane;
+        q_g32* pa = (q_g32*)I.ta + S.tbase + lane;
+        q_g32* pb = (q_g32*)I.tb + S.tbase + lane;
 #pragma unroll
         for (int q = 0; q < kPreT; ++q) {
             L.a[q] = (row && q < S.tw) ? pa[q * kSlice] : 0u;
             L.b[q] = (row && q < S.tw) ? pb[q * kSlice] : 0u;
         }
     }
-    L.h = row ? (int)I.h[S.row0 + lane] : 0;
+    L.h = row ? (int)((q_gi8*)I.h)[S.row0 + lane] : 0;
 }
 
 // Energy from one sweep's fields: with f1 = h_i + (coupling part) and f the
@@ -78,7 +117,7 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
     for (int k = 0; k < kPreW; ++k)
         if (k < S.ew) f += bat_j(L.w[k]) * sp[L.w[k] >> 8];
     if (S.ew > kPreW) {
-        const uint32_t* p = I.nbr + S.ebase + lane;
+        q_g32* p = (q_g32*)I.nbr + S.ebase + lane;
         for (int k = kPreW; k < S.ew; ++k) {
             const uint32_t w1 = p[k * kSlice];
             f += bat_j(w1) * sp[w1 >> 8];
@@ -90,8 +129,8 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
         for (int q = 0; q < kPreT; ++q)
             if (q < S.tw) f += bat_j(L.a[q]) * sp[L.a[q] >> 8] * sp[L.b[q]];
         if (S.tw > kPreT) {
-            const uint32_t* pa = I.ta + S.tbase + lane;
-            const uint32_t* pb = I.tb + S.tbase + lane;
+            q_g32* pa = (q_g32*)I.ta + S.tbase + lane;
+            q_g32* pb = (q_g32*)I.tb + S.tbase + lane;
             for (int q = kPreT; q < S.tw; ++q) {
                 const uint32_t wa = pa[q * kSlice];
                 f += bat_j(wa) * sp[wa >> 8] * sp[pb[q * kSlice]];
@@ -102,7 +141,7 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
     e6 += si * (3 * L.h + f1 + 2 * f);
     const int d = 2 * si * f;
     bool flip = d < 0;
-    if (TIE && d == 0) flip = rng_bit(seed, I.ext[i], sweep, I.instance_id, r) != 0;
+    if (TIE && d == 0) flip = rng_bit(seed, ((q_g32*)I.ext)[i], sweep, I.instance_id, r) != 0;
     if (flip) {
         sp[i] = (int8_t)(-si);
         dE += d;
@@ -111,12 +150,29 @@ __device__ __forceinline__ void queue_eval(const InstDev& I, const Slice& S, con
 }
 
 template <bool TIE>
-__device__ __forceinline__ void queue_phase(const InstDev& I, const Slice* __restrict__ slices, int s_lo, int s_hi,
+__device__ __forceinline__ void queue_phase(const InstDev& I0, const Slice* __restrict__ slices0, int s_lo, int s_hi,
                                             int8_t* __restrict__ sp, int w, int nw, int lane, uint32_t sweep,
                                             uint64_t seed, uint32_t r, long long& dE, int& my, long long& e6)
 {
-    for (int sl = s_lo + w; sl < s_hi; sl += nw) {
-        const Slice S = slices[sl];
+    InstDev I = I0;
+    I.nbr = queue_uniform(I0.nbr);
+    I.ta = queue_uniform(I0.ta);
+    I.tb = queue_uniform(I0.tb);
+    I.h = queue_uniform(I0.h);
+    I.ext = queue_uniform(I0.ext);
+    const Slice* slices = queue_uniform(slices0);
+    // the next slice's descriptor is read while this slice's words are in
+    // flight, so a slice costs one memory latency, not two
+    int sl = __builtin_amdgcn_readfirstlane(s_lo + w);
+    q_v4 nx = {0u, 0u, 0u, 0u};
+    if (sl < s_hi) nx = queue_slice_raw(slices, sl);
+    for (; sl < s_hi; sl += nw) {
+        // the descriptor is first used here, one slice after its load was
+        // issued (the empty statement keeps the compiler from unpacking, and
+        // so waiting for, it right after the load)
+        asm volatile("" : "+s"(nx.x), "+s"(nx.y), "+s"(nx.z), "+s"(nx.w));
+        const Slice S = queue_unpack(nx);
+        if (sl + nw < s_hi) nx = queue_slice_raw(slices, sl + nw);
         SliceWords cur;
         queue_load(I, S, lane, cur);
         queue_eval<TIE>(I, S, cur, sp, lane, sweep, seed, r, dE, my, e6);
@@ -157,7 +213,7 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
     for (;;) {
         if (tid == 0) s_item = (int)atomicAdd(&counters[0], 1u);
         __syncthreads();
-        const int q = s_item;
+        const int q = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (q >= n_big) break;
         const QueueItem it = items[q];
@@ -222,10 +278,10 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
     for (;;) {
         if (tid == 0) s_item = n_big + (int)atomicAdd(&counters[1], (unsigned)kBatWaves);
         __syncthreads();
-        const int q0 = s_item;
+        const int q0 = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (q0 >= n_items) break;
-        const int q = q0 + wave;
+        const int q = __builtin_amdgcn_readfirstlane(q0 + wave);
         if (q < n_items) {
             const QueueItem it = items[q];
             const InstTab& Q = tab[it.inst];
