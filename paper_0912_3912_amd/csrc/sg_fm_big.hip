@@ -43,6 +43,10 @@ namespace {
 
 constexpr int32_t kLocked = INT32_MIN;
 
+// The row table as device memory (its pointer comes from a table in memory,
+// so the compiler would otherwise address it as generic memory).
+typedef __attribute__((address_space(1))) const uint32_t fmb_g32;
+
 template <int CTRL, int ROWS>
 __device__ __forceinline__ uint64_t big_max_step(uint64_t v)
 {
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
             // partial sum of a field is bounded by the spin's sum of |c|,
             // below 2^31)
             for (int e = lane; e < n; e += 64) {
-                const uint32_t* row = Rw.rows + (int64_t)e * stride;
+                fmb_g32* row = (fmb_g32*)Rw.rows + (int64_t)e * stride;
                 int f;
                 if (!Rw.wide) {
                     f = (int)(int8_t)(row[0] & 0xffu);
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                     f = (int)row[0];
                     for (int q = 0; q < dc; ++q) f += (int)row[2 + 2 * q] * sx[row[1 + 2 * q]];
                     for (int q = 0; q < tt; ++q) {
-                        const uint32_t* t3 = row + 1 + 2 * dc + 3 * q;
+                        fmb_g32* t3 = row + 1 + 2 * dc + 3 * q;
                         f += (int)t3[2] * sx[t3[0]] * sx[t3[1]];
                     }
                 }
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                     break;
                 }
                 const int v = (int)((uint32_t)(K >> 32) ^ 0x80000000u);
-                const uint32_t* row = Rw.rows + (int64_t)me * stride;
+                fmb_g32* row = (fmb_g32*)Rw.rows + (int64_t)me * stride;
                 const int s_old = sx[me];
                 const int gm = (int)(me >> 6);
                 E -= 2LL * v;
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                             J = (int32_t)row[2 + 2 * q];
                         }
                         if (q < tt) {
-                            const uint32_t* t3 = row + 1 + 2 * dc + 3 * q;
+                            fmb_g32* t3 = row + 1 + 2 * dc + 3 * q;
                             a = (int)t3[0];
                             b = (int)t3[1];
                             K3 = (int32_t)t3[2];
