@@ -307,8 +307,16 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                             }
                             kk[u] = big_wave_max(big_key(nv, ev[u]));
                         }
-                        // the new leaf keys into their entries' lanes, then each
-                        // entry's maximum (an entry read twice gives the same value)
+                        // the old keys of the gathered leaves (lane gl & 63 of their
+                        // entries' keys), then the new keys into those lanes
+                        uint64_t oldk[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int src = u < ng ? (gl[u] & 63) : 0;
+                            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)up[u], src);
+                            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(up[u] >> 32), src);
+                            oldk[u] = ((uint64_t)hi << 32) | lo;
+                        }
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             if (u >= ng) continue;
@@ -317,10 +325,31 @@ __global__ __launch_bounds__(64) void k_fm_big(const InstTab* __restrict__ tab, 
                             for (int x = 0; x < 4; ++x)
                                 if (x < ng && (gl[u] >> 6) == (gl[x] >> 6) && lane == (gl[u] & 63)) up[x] = kk[u];
                         }
+                        // each touched entry once: its new maximum is the larger of
+                        // its old one and the new keys, unless a leaf that held the
+                        // old maximum went down (keys are distinct but for 0, below
+                        // which none goes); then its 64 leaf keys are taken again
 #pragma unroll
                         for (int x = 0; x < 4; ++x) {
-                            const uint64_t m = big_wave_max(up[x]);
-                            if (x < ng && lane == 0) top[gl[x] >> 6] = m;
+                            if (x >= ng) continue;
+                            const int a = gl[x] >> 6;
+                            bool again = false;
+                            for (int y = 0; y < x; ++y) again = again || (gl[y] >> 6) == a;
+                            if (again) continue;
+                            const uint64_t t0 = top[a];
+                            const uint64_t told =
+                                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t0 >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t0);
+                            uint64_t m = told;
+                            bool down = false;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                if (u >= ng || (gl[u] >> 6) != a) continue;
+                                down = down || (oldk[u] == told && kk[u] < oldk[u]);
+                                m = kk[u] > m ? kk[u] : m;
+                            }
+                            if (down) m = big_wave_max(up[x]);
+                            if (lane == 0) top[a] = m;
                         }
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     }

@@ -287,11 +287,23 @@ def test_big_hub_rows(gpu, scale):
     h.free()
 
 
-def test_big_wide_er(gpu):
-    """5000 spins with hyper-couplings and couplings of up to 9000 in
-    magnitude (wide form) on the large-instance pass kernel."""
+@pytest.mark.parametrize("scale", [1000, 1 << 24])
+def test_big_wide_er(gpu, scale):
+    """5000 spins with hyper-couplings in the wide form on the large-instance
+    pass kernel: couplings scaled by 1000, or couplings and hyper-couplings by
+    2^24, so that a spin's sum of |coefficients| passes 2^25 and the leaf
+    maxima take full 64-bit keys."""
     big = gen.erdos_renyi_triples(5000, seed=1)
-    wide = big.replace(J=(big.J * 1000).astype(np.int32), restarts=3, instance_id=6)
+    J = (big.J.astype(np.int64) * scale).astype(np.int32)
+    K = (big.K.astype(np.int64) * (scale if scale > 1000 else 1)).astype(np.int32)
+    wide = big.replace(J=J, K=K, restarts=3, instance_id=6)
+    if scale > 1000:
+        W = np.zeros(big.n, np.int64)
+        np.add.at(W, big.ei, np.abs(J.astype(np.int64)))
+        np.add.at(W, big.ej, np.abs(J.astype(np.int64)))
+        for c in range(3):
+            np.add.at(W, big.tri[:, c], np.abs(K.astype(np.int64)))
+        assert (1 << 25) <= W.max() < (1 << 31)
     h = _check_big([wide], 2, 2)
     assert h.query("wide_instances") == 1
     h.free()
