@@ -209,7 +209,7 @@ def run_cubic(args, sg, gen, torch):
         kname = "k_lattice_msc"
     geometry = {"tiles": h.query("last_tiles"), "halo_k": h.query("last_tile_k")}
     traffic = measured_traffic(kname, geometry) if sched == 3 else None
-    # Survey's compact-lattice model (implicit neighbours, int8 couplings and
+    # The compact-lattice model (implicit neighbours, int8 couplings and
     # field) for the tile kernels, the sliced-layout model otherwise.
     bpa = COMPACT_BYTES_PER_ATTEMPT if sched == 3 else sell_bytes_per_attempt(6)
     ach = bpa * apl / per_launch_s / 1e9
@@ -231,7 +231,7 @@ def run_cubic(args, sg, gen, torch):
         "counter_frac": None if traffic is None else round(traffic / per_launch_s / 1e9 / PEAK_HBM_GBS, 4),
         "csr_model": {"bytes_per_attempt": CSR_BYTES_PER_ATTEMPT,
                       "frac": round(CSR_BYTES_PER_ATTEMPT * apl / per_launch_s / 1e9 / PEAK_HBM_GBS, 4),
-                      "note": "the survey's CSR stream model; this kernel streams no CSR structure, so it is not "
+                      "note": "the CSR stream model (row pointers, column indices and values per coupling); this kernel streams no CSR structure, so it is not "
                               "a bandwidth figure"},
         "alu": {"ops_per_attempt": ops, "achieved_TOPs": round(alu, 3), "peak_TOPs": round(PEAK_INT_TOPS, 2),
                 "frac": round(alu / PEAK_INT_TOPS, 4),
@@ -514,7 +514,7 @@ def run_er(args, sg, gen, torch, count=2000):
     tau = sum(3 * i.t for i in insts) / ntot
     # the layout's own bytes (coupling and hyper-coupling words, field; spins in LDS)
     bpa = sell_bytes_per_attempt(deg, tau, spins_in_lds=True)
-    # the survey's CSR model: row pointers (edges and triples), deg (4 + 1), tau (2 * 4 + 1), field, own spin
+    # the CSR stream model: row pointers (edges and triples), deg (4 + 1), tau (2 * 4 + 1), field, own spin
     # read and written, other spins once
     bpa_csr = 4 + 4 + deg * 5 + tau * 9 + 1 + 2 + 1
     ach = bpa * attempts / (hot_us / 1e6) / 1e9
@@ -551,7 +551,7 @@ def run_er(args, sg, gen, torch, count=2000):
                          "bytes_per_attempt": round(bpa, 2),
                          "model": "the sliced layout's own stream: 4 B per coupling word, 8 B per hyper-coupling "
                                   "incidence, 1 B field (spins in LDS)",
-                         "survey_model": {"bytes_per_attempt": round(bpa_csr, 2),
+                         "csr_model": {"bytes_per_attempt": round(bpa_csr, 2),
                                           "frac": round(bpa_csr * attempts / (hot_us / 1e6) / 1e9 / PEAK_HBM_GBS, 4)},
                          "traffic": traffic,
                          "traffic_source": None if traffic is None else (
