@@ -179,6 +179,46 @@ __device__ __forceinline__ void queue_phase(const InstDev& I0, const Slice* __re
     }
 }
 
+// A wavefront's first slice of a phase, loaded before the barrier that
+// opens the phase (couplings and fields are read-only).
+struct QueueCarry {
+    Slice S;
+    SliceWords W;
+    bool valid;
+};
+
+// One colour phase of a workgroup item: the wavefront's first slice comes
+// loaded in `cy`, the rest as in queue_phase.
+template <bool TIE>
+__device__ __forceinline__ void queue_phase_wg(const InstDev& I, const Slice* slices, int s_lo, int s_hi,
+                                               int8_t* __restrict__ sp, int w, int nw, int lane, uint32_t sweep,
+                                               uint64_t seed, uint32_t r, long long& dE, int& my, long long& e6,
+                                               const QueueCarry& cy)
+{
+    if (!cy.valid) return;
+    int sl = __builtin_amdgcn_readfirstlane(s_lo + w);
+    q_v4 nx = {0u, 0u, 0u, 0u};
+    if (sl + nw < s_hi) nx = queue_slice_raw(slices, sl + nw);
+    queue_eval<TIE>(I, cy.S, cy.W, sp, lane, sweep, seed, r, dE, my, e6);
+    for (sl += nw; sl < s_hi; sl += nw) {
+        asm volatile("" : "+s"(nx.x), "+s"(nx.y), "+s"(nx.z), "+s"(nx.w));
+        const Slice S = queue_unpack(nx);
+        if (sl + nw < s_hi) nx = queue_slice_raw(slices, sl + nw);
+        SliceWords cur;
+        queue_load(I, S, lane, cur);
+        queue_eval<TIE>(I, S, cur, sp, lane, sweep, seed, r, dE, my, e6);
+    }
+}
+
+// Workgroup barrier that orders LDS only: device-memory loads issued before
+// it (the next phase's first slice) stay in flight across it.
+__device__ __forceinline__ void queue_lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // e6: -6 E of the last sweep's fields, exact when that sweep flipped nothing.
 __device__ __forceinline__ void queue_finish(const InstTab& Q, int r, long long dE, long long e6, int nflip,
                                              int performed, int lastflip, int T, int until_conv,
@@ -208,7 +248,7 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
     extern __shared__ uint64_t lds64[];
     int8_t* lds = reinterpret_cast<int8_t*>(lds64);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ int s_item;
+    __shared__ int s_item, s_any[3];
     // ---- large items: the whole workgroup on one replica
     for (;;) {
         if (tid == 0) s_item = (int)atomicAdd(&counters[0], 1u);
@@ -225,21 +265,66 @@ __global__ __launch_bounds__(kBatThreads) void k_queue(const InstTab* __restrict
         if (frozen) continue;
         const uint32_t base = (uint32_t)st0->sweeps;
         for (int k = tid; k < I.n; k += kBatThreads) lds[k] = gsp[k];
+        if (tid < 3) s_any[tid] = 0;
         __syncthreads();
+        // the instance arrays and slice table in scalar registers
+        InstDev J = I;
+        J.nbr = queue_uniform(I.nbr);
+        J.ta = queue_uniform(I.ta);
+        J.tb = queue_uniform(I.tb);
+        J.h = queue_uniform(I.h);
+        J.ext = queue_uniform(I.ext);
+        const Slice* sls = queue_uniform(I.slices);
+        const int C = Q.C;
+        const int32_t* ct = ctab + Q.ctab_off;
+        // this wavefront's first slice of colour 0
+        QueueCarry cy;
+        {
+            const int sl0 = __builtin_amdgcn_readfirstlane(ct[0] + wave);
+            cy.valid = sl0 < ct[1];
+            if (cy.valid) {
+                cy.S = queue_unpack(queue_slice_raw(sls, sl0));
+                queue_load(J, cy.S, lane, cy.W);
+            }
+        }
         long long dE = 0, e6 = 0;
         int nflip = 0, performed = 0, lastflip = 0;
         for (int t = 0; t < T; ++t) {
             int my = 0;
             e6 = 0;
-            for (int c = 0; c < Q.C; ++c) {
-                queue_phase<TIE>(I, I.slices, ctab[Q.ctab_off + c], ctab[Q.ctab_off + c + 1], lds, wave, kBatWaves,
-                                 lane, base + t, seed, (uint32_t)it.r, dE, my, e6);
-                if (c + 1 < Q.C) __syncthreads();
+            for (int c = 0; c < C; ++c) {
+                // the descriptor of this wavefront's first slice of the next
+                // phase, read while this phase runs
+                const int cn = c + 1 < C ? c + 1 : 0;
+                const int sln = __builtin_amdgcn_readfirstlane(ct[cn] + wave);
+                const bool nval = sln < ct[cn + 1];
+                q_v4 nraw = {0u, 0u, 0u, 0u};
+                if (nval) nraw = queue_slice_raw(sls, sln);
+                queue_phase_wg<TIE>(J, sls, ct[c], ct[c + 1], lds, wave, kBatWaves, lane, base + t, seed,
+                                    (uint32_t)it.r, dE, my, e6, cy);
+                // that slice's words, in flight across the barrier
+                asm volatile("" : "+s"(nraw.x), "+s"(nraw.y), "+s"(nraw.z), "+s"(nraw.w));
+                cy.valid = nval;
+                if (nval) {
+                    cy.S = queue_unpack(nraw);
+                    queue_load(J, cy.S, lane, cy.W);
+                }
+                if (c + 1 < C) {
+                    queue_lds_barrier();
+                } else {
+                    // the sweep's last barrier also tells whether it flipped
+                    // anything: slot t % 3 is set before the barrier and read
+                    // after it; slot (t + 2) % 3 is cleared for sweep t + 2,
+                    // after every read of it (sweep t - 1) and a barrier before
+                    // any write of it
+                    if (__ballot(my != 0) != 0 && lane == 0) s_any[t % 3] = 1;
+                    queue_lds_barrier();
+                }
             }
             nflip += my;
             performed = t + 1;
-            // the last colour's barrier also tells whether the sweep flipped anything
-            const bool tot = __syncthreads_or(my != 0);
+            const bool tot = s_any[t % 3] != 0;
+            if (tid == 0) s_any[(t + 2) % 3] = 0;
             if (tot) lastflip = t + 1;
             if (until_conv && !tot) break;
         }
