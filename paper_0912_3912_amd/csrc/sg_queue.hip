@@ -37,7 +37,9 @@ constexpr int kBatWaves = kBatThreads / 64;
 // when loading the next slice while evaluating the current one with fewer
 // words each).  The slice descriptors are read with scalar loads one slice
 // ahead and the instance arrays addressed as device memory (2.78 ms; with
-// the descriptor read per lane before the words and generic loads, 3.25 ms).
+// the descriptor read per lane before the words and generic loads, 3.25 ms;
+// 2.70 ms once a workgroup item's next-phase first slices are loaded before
+// the phase barrier, queue_phase_wg).
 // Loading the next slice's words as well, with both buffers at full width,
 // measured 2.82-2.89 ms: the extra registers and copies cost what the hidden
 // latency saves, as the wavefronts of a compute unit already keep its vector
