@@ -232,6 +232,21 @@ def test_queue_rules_and_restarts(gpu, rule, uc):
     _run(insts, 8, rule, 20, uc, SCHED_QUEUE)
 
 
+@pytest.mark.parametrize("rule,uc", [(GREEDY, True), (TIE, False)])
+def test_queue_single_colour_items(gpu, rule, uc):
+    """Workgroup items with one colour class (fields only, no couplings),
+    beside items with several: a sweep is then a single phase, so its flip
+    flag is written with no phase barrier after the previous sweep's."""
+    rng = np.random.default_rng(5)
+    lone = []
+    for k, n in enumerate((2000, 5000)):
+        h = rng.integers(-3, 4, size=n).astype(np.int32)
+        e = np.zeros(0, np.int32)
+        lone.append(gen.Instance(n, e, e, e, h, restarts=2, instance_id=70 + k, name=f"fields{n}"))
+    insts = lone + [gen.erdos_renyi_triples(3000, seed=4, instance_id=80, restarts=2)]
+    _run(insts, 5, rule, 12, uc, SCHED_QUEUE, tune={"queue_wave_max_n": 256})
+
+
 def test_queue_resume(gpu):
     insts = [gen.erdos_renyi_triples(n, seed=n, instance_id=n) for n in (300, 5000, 10000)]
     _run(insts, 1, GREEDY, 0, True, SCHED_QUEUE, runs=[1, 2, 0, 100])
