@@ -68,7 +68,7 @@ def candidates(h, rule: int, until_converged: bool) -> List[dict]:
         out += [{"bits_groups": g} for g in (4, 16)]
         out += [{"block_bits": 0}]
     elif h.query("queue_ok") and ninst >= 2:
-        out += [{"queue_wave_max_n": w} for w in (128, 256, 1024, 2048)]
+        out += [{"queue_wave_max_n": w} for w in (128, 256, 512, 1024, 2048)]
         if ninst <= 64:
             # few instances: their per-phase launches, plain or recorded in graphs, instead of the queue
             out += [{"queue_min_items": 1 << 30}]
