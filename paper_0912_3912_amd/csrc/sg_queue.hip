@@ -41,9 +41,8 @@ constexpr int kBatWaves = kBatThreads / 64;
 // 2.70 ms once a workgroup item's next-phase first slices are loaded before
 // the phase barrier, queue_phase_wg).
 // Loading the next slice's words as well, with both buffers at full width,
-// measured 2.82-2.89 ms: the extra registers and copies cost what the hidden
-// latency saves, as the wavefronts of a compute unit already keep its vector
-// and LDS units about half busy.
+// measured 2.82-2.89 ms: the extra registers and copies cost more than the
+// latency they hide.
 constexpr int kPreW = 16, kPreT = 8;
 
 struct SliceWords {
